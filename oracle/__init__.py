@@ -1,0 +1,30 @@
+"""Oracle for dynamic random walk with restart -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct CPU implementations of what the HIP path
+computes.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline
+leg of ``bench.py`` may import this package; the product package never does,
+and the two share no code (only the seeded generators in ``synth`` feed both).
+
+Contents
+  * ``rwr_static``   static RWR of Eq. (1): CPI of Section 2.2 from c*e_s to
+                      1e-14 in FP64, then Theorem 4's dead-end normalisation
+                      (C, single-threaded; ``rwr_oracle.c``)
+  * ``cpi``          cumulative power iteration for any seed vector
+  * ``osp``          one OSP / OSP-T update, Section 3.1 / Algorithm 1
+  * ``rwr_dense``    the same static RWR by a dense LU solve of
+                      (I - (1-c) A~^T) r = c e_s (numpy / LAPACK), n <= ~2000
+  * ``apply_batch``  the graph G + Delta G of a batch, by plain set
+                      operations on edge keys (Section 3.4.1 for new nodes)
+"""
+
+from .core import (  # noqa: F401
+    OracleError,
+    apply_batch,
+    cpi,
+    dead_end_reachable,
+    lib,
+    osp,
+    rwr_dense,
+    rwr_static,
+    row_normalised_dense,
+)
