@@ -1,0 +1,179 @@
+/*
+ * rwr.h -- C ABI of the MI355X dynamic random-walk-with-restart library.
+ *
+ * The library keeps, on one GPU, a directed (or undirected) graph and the
+ * random-walk-with-restart (RWR) score vectors of S seed nodes, and keeps the
+ * scores current while batches of edge and node insertions and deletions
+ * arrive, by offset score propagation (OSP, Section 3.1 and Algorithm 1 of
+ * Yoon, Jin and Kang, "Fast and Accurate Random Walk with Restart on Dynamic
+ * Graphs with Guarantees", WWW 2018), or its tolerance-driven variant OSP-T
+ * (Section 3.2).
+ *
+ * Scores (Eq. 1, Section 2.1): r = (1-c) A~^T r + c q with q = e_s, where A~
+ * is the row-normalised adjacency matrix (rows of dead ends are zero; dead
+ * ends are handled by Theorem 4's rescaling, Section 3.4.2).
+ *
+ * Conventions for every entry point
+ *   - Every call returns rwr_status (0 = RWR_OK, negative = error); no C++
+ *     exception crosses this boundary.  A text for the last error of a
+ *     context is returned by rwr_last_error().
+ *   - Calls are synchronous with respect to the host on return.  One context
+ *     uses one HIP stream; a context is not thread-safe.
+ *   - The caller owns every array it passes; the library copies what it
+ *     keeps.  A pointer flagged "on device" must be device memory of the
+ *     context's GPU, readable for the duration of the call.
+ *   - Node ids are int32 in [0, n); edge counts are int64.
+ */
+#ifndef RWR_H_
+#define RWR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rwr_ctx rwr_ctx;
+
+typedef enum rwr_status {
+  RWR_OK = 0,
+  RWR_EINVAL = -1,   /* bad argument, id out of range, duplicate entry in a batch */
+  RWR_ENOMEM = -2,   /* device or host allocation failed                        */
+  RWR_EHIP = -3,     /* a HIP runtime call failed                               */
+  RWR_EEXIST = -4,   /* batch inserts an edge that is already present           */
+  RWR_ENOENT = -5,   /* batch deletes an edge that is not present               */
+  RWR_ENOCONV = -6,  /* max_iters reached before ||x^(i)||_1 <= eps             */
+  RWR_ENUMERIC = -7, /* non-finite norm met during propagation                  */
+  RWR_ESTATE = -8    /* context unusable (an earlier call left it stale)        */
+} rwr_status;
+
+/* Precision of the propagated vectors x^(i).  Scores r and their sums are
+ * always accumulated in FP64. */
+typedef enum rwr_precision { RWR_PROP_FP32 = 0, RWR_PROP_FP64 = 1 } rwr_precision;
+
+typedef struct rwr_config {
+  double c;          /* restart probability, 0 < c < 1 (Section 2.1)                    */
+  double eps;        /* stop when ||x^(i)||_1 <= eps in every seed column (Alg. 1)      */
+  double err_budget; /* L1 error budget per seed column of the scores kept between
+                        updates; <= 0 selects 2*eps/c (Theorem 3 with rescaling)        */
+  double build_tol;  /* certified L1 error of the initial static solve; <= 0 selects
+                        err_budget/4                                                    */
+  int32_t precision; /* rwr_precision                                                   */
+  int32_t undirected;/* 1: each batch pair (u,v) stands for both directions             */
+  int32_t max_iters; /* per-update iteration guard; <= 0 selects 10000                  */
+  int32_t pull_ratio;/* switch from sparse push to dense pull once the frontier's
+                        out-edges exceed m/pull_ratio; <= 0 selects the tuned default   */
+  void *stream;      /* hipStream_t to run on; NULL: the library creates its own        */
+} rwr_config;
+
+/* A batch is a set (Theorem 1: only the graphs before and after matter).
+ * New nodes get ids n .. n+n_new_nodes-1 and may be named by this batch's
+ * insertions (Section 3.4.1).  A deleted node loses every incident edge and
+ * keeps its id with a zero row and column (Section 3.4.1; a seed node cannot
+ * be deleted).  The same edge may not appear twice, nor be both inserted and
+ * deleted.  In undirected mode a pair is given once, in either orientation. */
+typedef struct rwr_batch {
+  int64_t n_ins;
+  const int32_t *ins_src;
+  const int32_t *ins_dst;
+  int64_t n_del;
+  const int32_t *del_src;
+  const int32_t *del_dst;
+  int32_t n_new_nodes;
+  int32_t n_del_nodes;
+  const int32_t *del_nodes;
+  int32_t on_device; /* 1: the five arrays above are device pointers */
+} rwr_batch;
+
+/* Per-update statistics; norms are maxima over seed columns. */
+typedef struct rwr_stats {
+  int32_t iters;          /* propagation iterations of this update (Alg. 1 loop)           */
+  int32_t dense_iters;    /* of which dense pull sweeps                                    */
+  int32_t refined;        /* 1 if a residual refinement ran after this update              */
+  int32_t checked;        /* 1 if the FP64 residual was evaluated after this update        */
+  int64_t visited_edges;  /* edges read by propagation (Table 3's "visited edges")         */
+  int64_t touched_rows;   /* rows of A~ changed by the batch                               */
+  double q_off_l1;        /* ||q_offset||_1 (Section 3.1)                                  */
+  double last_x_l1;       /* ||x^(k)||_1 of the last iteration                             */
+  double err_bound;       /* L1 error bound of the scores after this update                */
+  double residual_l1;     /* ||residual||_1 when checked, else 0                           */
+  double ms_total;        /* wall time of the call (host clock)                            */
+} rwr_stats;
+
+/* Fill *cfg with defaults: c = 0.15, eps = 1e-9, FP32 propagation, directed. */
+rwr_status rwr_config_default(rwr_config *cfg);
+
+/* Build a context: copy the graph (n nodes, m edges (src[e], dst[e]); in
+ * undirected mode m pairs, each stored in both directions) to the GPU, and
+ * compute the static scores of each seed column by cumulative power iteration
+ * from c*e_s (Section 2.2) followed by FP64 residual refinement until the
+ * certified error is below cfg->build_tol.  Multi-edges are rejected
+ * (RWR_EINVAL); self-loops are allowed and count in the out-degree.
+ * n_seeds in [1, 64]; seeds distinct ids in [0, n).  edges_on_device: src/dst
+ * are device pointers.  On success *out owns all device memory of the
+ * context. */
+rwr_status rwr_build(const rwr_config *cfg, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                     int32_t n_seeds, const int32_t *seeds, int32_t edges_on_device, rwr_ctx **out);
+
+/* Apply one batch and update the scores (Algorithm 1): delta-apply on the
+ * device graph, offset seed q_offset = (1-c)(B~^T - A~^T) r_old, cumulative
+ * propagation on the new graph until ||x^(i)||_1 <= eps, merge into r, and
+ * Theorem 4's rescaling.  If the accumulated error bound exceeds the budget,
+ * the FP64 residual is evaluated and, if needed, propagated (refinement).
+ * The batch is validated on the device before anything changes: on
+ * RWR_EINVAL / RWR_EEXIST / RWR_ENOENT the graph and the scores are
+ * unchanged.  On RWR_ENOCONV the graph is updated, the scores hold the
+ * partial sum, stats->err_bound says how far off they may be and the context
+ * is marked stale (rwr_refine() clears it).  stats may be NULL. */
+rwr_status rwr_update(rwr_ctx *ctx, const rwr_batch *batch, rwr_stats *stats);
+
+/* Evaluate the FP64 residual of the current scores and propagate it until
+ * the certified error is below the budget (clears a stale context). */
+rwr_status rwr_refine(rwr_ctx *ctx, rwr_stats *stats);
+
+/* Copy the normalised scores of seed column j (n doubles) to out (capacity
+ * cap elements; host memory, or device memory when out_on_device = 1). */
+rwr_status rwr_scores(rwr_ctx *ctx, int32_t j, double *out, int64_t cap, int32_t out_on_device);
+
+/* Current node count and stored directed edge count. */
+rwr_status rwr_graph_size(const rwr_ctx *ctx, int32_t *n, int64_t *m);
+
+/* Copy the graph back to the host as a directed edge list in row order
+ * (out-neighbours of node 0, then of node 1, ...).  src/dst have capacity
+ * cap; *m_out receives the edge count.  Also copies out-degrees (n ints) to
+ * deg_out when not NULL.  For checking and checkpointing; not a hot path. */
+rwr_status rwr_graph_export(rwr_ctx *ctx, int32_t *src, int32_t *dst, int64_t cap, int64_t *m_out,
+                            int32_t *deg_out);
+
+/* Per-iteration ||x^(i)||_1 of seed column j during the last update (i = 0 is
+ * ||q_offset||_1): copies min(cap, iters+1) values to out, count to *len. */
+rwr_status rwr_last_norms(rwr_ctx *ctx, int32_t j, double *out, int32_t cap, int32_t *len);
+
+/* Measurement of the dense sweep kernel (one pull over every in-row of the
+ * graph, the bandwidth-bound step of the propagation, Section 2.2).  When
+ * enabled, each dense sweep launch is bracketed by two HIP events on the
+ * context's stream; after each propagation the elapsed times of the launches
+ * that swept the graph are summed (launches that found the propagation
+ * already converged are counted separately as idle).  Adds two event records
+ * per dense sweep; off by default. */
+rwr_status rwr_profile(rwr_ctx *ctx, int32_t enable);
+
+/* Read (and with reset = 1 clear) the accumulated dense-sweep time in ms, the
+ * number of timed sweeps and the number of idle launches.  Any pointer may be
+ * NULL. */
+rwr_status rwr_profile_read(rwr_ctx *ctx, double *dense_ms, int64_t *dense_sweeps, int64_t *idle_launches,
+                            int32_t reset);
+
+/* Free every resource of the context; NULL is allowed. */
+void rwr_destroy(rwr_ctx *ctx);
+
+/* Text of the last error recorded on ctx (or of the last failed rwr_build when
+ * ctx is NULL).  The string lives until the next call on the same context. */
+const char *rwr_last_error(const rwr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RWR_H_ */

@@ -1,0 +1,1171 @@
+// C ABI of the dynamic-RWR library: context management, the update pipeline
+// (batch upload -> keys -> sort/segment -> validate -> offset seed -> apply ->
+// propagation slots -> finish) and the error-budget bookkeeping with FP64
+// residual refinement.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rwr.h"
+#include "rwr_common.h"
+#include "rwr_kernels.h"
+
+namespace {
+
+std::string g_build_error;
+
+struct Orientation {
+  DevGraphView v{};
+  int64_t e_cap = 0;
+};
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+int next_pow2_cols(int n) {
+  int s = 1;
+  while (s < n) s <<= 1;
+  return s;
+}
+
+int bits_for(int64_t v) {
+  int b = 1;
+  while ((1ll << b) <= v) ++b;
+  return b;
+}
+
+}  // namespace
+
+struct rwr_ctx {
+  rwr_config cfg{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  int32_t n = 0, n_cap = 0;
+  int64_t m = 0;  // stored directed edges
+  int32_t n_seeds = 0, S = 1;
+  std::vector<int32_t> seeds_h;
+  int32_t *seeds_d = nullptr;
+  bool undirected = false, fp64 = false;
+  Orientation g[2];
+  double *r = nullptr, *ybuf = nullptr, *gbuf = nullptr;
+  void *x[2] = {nullptr, nullptr};
+  int32_t *stamp = nullptr;
+  int32_t *front[2] = {nullptr, nullptr};
+  int32_t *hfront = nullptr;
+  Ctl *ctl = nullptr;
+  Ctl *ctl_h = nullptr;  // pinned mirror
+  double *hist = nullptr;
+  int32_t max_iters = 10000;
+  double *part = nullptr;
+  int64_t *part_i = nullptr;
+  int32_t *gcnt = nullptr;
+  int64_t part_blocks = 0;
+  // heavy schedule of the pull orientation
+  int32_t *h_item_row = nullptr, *h_item_chunk = nullptr, *h_rows = nullptr, *h_nchunks = nullptr, *h_cnt = nullptr;
+  double *h_acc = nullptr;
+  int32_t h_items = 0, h_nrows = 0;
+  int32_t heavy_limit = 512, heavy_chunk = 4096;
+  int32_t *sel = nullptr, *sel_count = nullptr;
+  // row partition of the single-column dense sweep
+  int32_t *mp_rows = nullptr;
+  int32_t n_mp = 0;
+  // batch scratch
+  int64_t bcap = 0;  // key capacity per orientation
+  int32_t *b_dev = nullptr;
+  int32_t *b_host = nullptr;
+  int64_t b_host_cap = 0;
+  uint64_t *keys[2] = {nullptr, nullptr};
+  uint64_t *keys_alt = nullptr;
+  int32_t *flags = nullptr, *pos = nullptr;
+  int32_t *seg[2] = {nullptr, nullptr}, *row[2] = {nullptr, nullptr};
+  int32_t *t_dold[2] = {nullptr, nullptr}, *t_dnew[2] = {nullptr, nullptr};
+  void *temp = nullptr;
+  size_t temp_bytes = 0;
+  // tuning
+  int32_t grid_sparse = 512, grid_light = 2048, light_lanes = 16;
+  int32_t pull_ratio = 16;
+  // error budget per seed column (normalised L1)
+  double err_bound[RWR_MAX_COLS] = {};
+  double budget = 0.0;
+  bool stale = false;
+  std::string err;
+  std::vector<double> last_hist;
+  int32_t last_iters = 0;
+  // measurement: events around dense sweep launches
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;
+  int prof_used = 0;
+  double prof_dense_ms = 0.0;
+  int64_t prof_dense_sweeps = 0, prof_idle = 0;
+};
+
+// ------------------------------------------------------------------ helpers
+#define HIP_TRY(ctx, expr)                                                   \
+  do {                                                                       \
+    hipError_t _e = (expr);                                                  \
+    if (_e != hipSuccess) {                                                  \
+      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(_e);        \
+      return RWR_EHIP;                                                       \
+    }                                                                        \
+  } while (0)
+
+#define RWR_TRY(expr)                  \
+  do {                                 \
+    rwr_status _s = (expr);            \
+    if (_s != RWR_OK) return _s;       \
+  } while (0)
+
+static rwr_status dev_alloc(rwr_ctx *c, void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    c->err = "hipMalloc(" + std::to_string(bytes) + " bytes) failed: " + hipGetErrorString(e);
+    *p = nullptr;
+    return RWR_ENOMEM;
+  }
+  return RWR_OK;
+}
+
+static rwr_status copy_sync(rwr_ctx *c, void *dst, const void *src, size_t bytes, hipMemcpyKind kind) {
+  if (bytes == 0) return RWR_OK;
+  HIP_TRY(c, hipMemcpyAsync(dst, src, bytes, kind, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return RWR_OK;
+}
+#define H2D(c, dst, src, bytes) RWR_TRY(copy_sync((c), (dst), (src), (bytes), hipMemcpyHostToDevice))
+#define D2H(c, dst, src, bytes) RWR_TRY(copy_sync((c), (dst), (src), (bytes), hipMemcpyDeviceToHost))
+
+template <typename T>
+static rwr_status alloc_zero(rwr_ctx *c, T **p, size_t count) {
+  RWR_TRY(dev_alloc(c, (void **)p, sizeof(T) * count));
+  launch_zero_bytes(*p, (sizeof(T) * count + 3) / 4 * 4, c->stream);
+  return RWR_OK;
+}
+
+template <typename T>
+static void dev_free(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+static rwr_status ensure_temp(rwr_ctx *c, size_t bytes) {
+  if (bytes <= c->temp_bytes) return RWR_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  dev_free(c->temp);
+  c->temp_bytes = 0;
+  RWR_TRY(dev_alloc(c, &c->temp, bytes));
+  c->temp_bytes = bytes;
+  return RWR_OK;
+}
+
+// one event before (start = true) or after a dense sweep launch
+static rwr_status prof_record(rwr_ctx *c, bool start) {
+  (void)start;
+  if (c->prof_used == (int)c->prof_ev.size()) {
+    hipEvent_t e;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->prof_ev.push_back(e);
+  }
+  HIP_TRY(c, hipEventRecord(c->prof_ev[c->prof_used++], c->stream));
+  return RWR_OK;
+}
+
+// After a run: the first `real` of the `launched` dense launches swept the
+// graph (dense sweeps are contiguous); the rest found the run converged.
+static rwr_status prof_collect(rwr_ctx *c, int base, int launched, int real) {
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < launched; ++i) {
+    float ms = 0.0f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->prof_ev[base + 2 * i], c->prof_ev[base + 2 * i + 1]));
+    if (i < real) {
+      c->prof_dense_ms += ms;
+      ++c->prof_dense_sweeps;
+    } else {
+      ++c->prof_idle;
+    }
+  }
+  c->prof_used = base;
+  return RWR_OK;
+}
+
+static int pull_orient(const rwr_ctx *c) { return c->undirected ? 0 : 1; }
+
+static SlotArgs slot_args(const rwr_ctx *c) {
+  SlotArgs a{};
+  a.out = c->g[0].v;
+  a.in = c->g[pull_orient(c)].v;
+  a.heavy.item_row = c->h_item_row;
+  a.heavy.item_chunk = c->h_item_chunk;
+  a.heavy.rows = c->h_rows;
+  a.heavy.nchunks = c->h_nchunks;
+  a.heavy.acc = c->h_acc;
+  a.heavy.cnt = c->h_cnt;
+  a.heavy.n_items = c->h_items;
+  a.heavy.chunk = c->heavy_chunk;
+  a.r = c->r;
+  a.ybuf = c->ybuf;
+  a.gbuf = c->gbuf;
+  a.x[0] = c->x[0];
+  a.x[1] = c->x[1];
+  a.stamp = c->stamp;
+  a.front[0] = c->front[0];
+  a.front[1] = c->front[1];
+  a.hfront = c->hfront;
+  a.seeds = c->seeds_d;
+  a.ctl = c->ctl;
+  a.hist = c->hist;
+  a.part = c->part;
+  a.part_i = c->part_i;
+  a.gcnt = c->gcnt;
+  a.n = c->n;
+  a.n_seeds = c->n_seeds;
+  a.c = c->cfg.c;
+  a.grid_sparse = c->grid_sparse;
+  a.grid_light = c->grid_light;
+  a.light_lanes = c->light_lanes;
+  a.mp_rows = c->mp_rows;
+  a.n_mp = c->n_mp;
+  return a;
+}
+
+static rwr_status read_ctl(rwr_ctx *c) {
+  HIP_TRY(c, hipMemcpyAsync(c->ctl_h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return RWR_OK;
+}
+
+// partial-sum buffers sized for the largest grid in use
+static rwr_status ensure_partials(rwr_ctx *c) {
+  const int64_t blocks =
+      (int64_t)c->h_items + std::max<int64_t>({c->grid_light, c->grid_sparse, (int64_t)c->n_mp}) + 64;
+  if (blocks <= c->part_blocks) return RWR_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  dev_free(c->part);
+  dev_free(c->part_i);
+  dev_free(c->gcnt);
+  const int64_t groups = blocks / 32 + 2;
+  RWR_TRY(alloc_zero(c, &c->part, (size_t)(blocks + groups) * c->S * 2));
+  RWR_TRY(alloc_zero(c, &c->part_i, (size_t)(blocks + groups) * 2));
+  RWR_TRY(alloc_zero(c, &c->gcnt, (size_t)groups));
+  c->part_blocks = blocks;
+  return RWR_OK;
+}
+
+static void tune_defaults(rwr_ctx *c) {
+  const int S = c->S;
+  if (S == 1) {
+    c->light_lanes = 16;
+    c->heavy_limit = MP_EDGES;
+    c->heavy_chunk = 4096;
+  } else if (S <= 4) {
+    c->heavy_limit = 512;
+    c->heavy_chunk = 2048;
+  } else if (S <= 16) {
+    c->heavy_limit = 256;
+    c->heavy_chunk = 1024;
+  } else {
+    c->heavy_limit = 128;
+    c->heavy_chunk = 512;
+  }
+  if (const char *e = getenv("RWR_LIGHT_LANES")) c->light_lanes = atoi(e);
+  if (const char *e = getenv("RWR_HEAVY_LIMIT")) c->heavy_limit = atoi(e);
+  if (const char *e = getenv("RWR_HEAVY_CHUNK")) c->heavy_chunk = atoi(e);
+  if (const char *e = getenv("RWR_PULL_RATIO")) c->pull_ratio = atoi(e);
+  if (c->cfg.pull_ratio > 0) c->pull_ratio = c->cfg.pull_ratio;
+  const int lanes_per_row = (S == 1) ? c->light_lanes : (S >= 8 ? 64 : 8 * S);
+  const int rows_per_block = std::max(1, 256 / lanes_per_row);
+  const int64_t want = ((int64_t)c->n_cap + rows_per_block - 1) / rows_per_block;
+  c->grid_light = (int32_t)std::max<int64_t>(1, std::min<int64_t>(want, 4096));
+  c->grid_sparse = 1024;
+  if (const char *e = getenv("RWR_GRID_LIGHT")) c->grid_light = atoi(e);
+  if (const char *e = getenv("RWR_GRID_SPARSE")) c->grid_sparse = atoi(e);
+}
+
+// Row partition of the single-column dense sweep over all n_cap rows (rows
+// beyond n are empty): consecutive rows, at most 256 per workgroup and about
+// MP_EDGES light in-edges (rows above the heavy limit count as empty).
+static rwr_status plan_partition(rwr_ctx *c) {
+  Orientation &o = c->g[pull_orient(c)];
+  std::vector<int32_t> len(c->n_cap);
+  D2H(c, len.data(), o.v.len, sizeof(int32_t) * c->n_cap);
+  std::vector<int32_t> rows;
+  rows.reserve(c->n_cap / 64 + 2);
+  rows.push_back(0);
+  int64_t acc = 0;
+  int cnt = 0;
+  for (int32_t v = 0; v < c->n_cap; ++v) {
+    const int64_t l = len[v] > c->heavy_limit ? 0 : len[v];
+    if (cnt > 0 && (cnt == 256 || acc + l > MP_EDGES)) {
+      rows.push_back(v);
+      acc = 0;
+      cnt = 0;
+    }
+    acc += l;
+    ++cnt;
+  }
+  rows.push_back(c->n_cap);
+  dev_free(c->mp_rows);
+  RWR_TRY(dev_alloc(c, (void **)&c->mp_rows, sizeof(int32_t) * rows.size()));
+  H2D(c, c->mp_rows, rows.data(), sizeof(int32_t) * rows.size());
+  c->n_mp = (int32_t)rows.size() - 1;
+  return RWR_OK;
+}
+
+// Heavy rows of the pull orientation: flag them, split them into chunks.
+static rwr_status plan_heavy(rwr_ctx *c) {
+  Orientation &o = c->g[pull_orient(c)];
+  HIP_TRY(c, hipMemsetAsync(c->sel_count, 0, sizeof(int32_t), c->stream));
+  launch_mark_heavy(o.v.len, c->n, c->heavy_limit, o.v.heavy, c->sel, c->sel_count, c->stream);
+  int32_t count = 0;
+  HIP_TRY(c, hipMemcpyAsync(&count, c->sel_count, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<int32_t> rows(count), lens(count);
+  if (count > 0) {
+    D2H(c, rows.data(), c->sel, sizeof(int32_t) * count);
+    std::sort(rows.begin(), rows.end());
+    H2D(c, c->sel, rows.data(), sizeof(int32_t) * count);
+    launch_gather_i32(o.v.len, c->sel, count, c->sel + c->n_cap, c->stream);
+    HIP_TRY(c, hipMemcpyAsync(lens.data(), c->sel + c->n_cap, sizeof(int32_t) * count, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  std::vector<int32_t> item_row, item_chunk, nchunks(count);
+  for (int32_t h = 0; h < count; ++h) {
+    const int64_t planned = (int64_t)lens[h] + lens[h] / 4;
+    const int32_t nch = (int32_t)std::max<int64_t>(1, (planned + c->heavy_chunk - 1) / c->heavy_chunk);
+    nchunks[h] = nch;
+    for (int32_t k = 0; k < nch; ++k) {
+      item_row.push_back(h);
+      item_chunk.push_back(k);
+    }
+  }
+  dev_free(c->h_item_row);
+  dev_free(c->h_item_chunk);
+  dev_free(c->h_rows);
+  dev_free(c->h_nchunks);
+  dev_free(c->h_cnt);
+  dev_free(c->h_acc);
+  const int32_t items = (int32_t)item_row.size();
+  RWR_TRY(alloc_zero(c, &c->h_item_row, std::max(1, items)));
+  RWR_TRY(alloc_zero(c, &c->h_item_chunk, std::max(1, items)));
+  RWR_TRY(alloc_zero(c, &c->h_rows, std::max(1, count)));
+  RWR_TRY(alloc_zero(c, &c->h_nchunks, std::max(1, count)));
+  RWR_TRY(alloc_zero(c, &c->h_cnt, std::max(1, count)));
+  RWR_TRY(alloc_zero(c, &c->h_acc, (size_t)std::max(1, count) * c->S));
+  if (items > 0) {
+    H2D(c, c->h_item_row, item_row.data(), sizeof(int32_t) * items);
+    H2D(c, c->h_item_chunk, item_chunk.data(), sizeof(int32_t) * items);
+    H2D(c, c->h_rows, rows.data(), sizeof(int32_t) * count);
+    H2D(c, c->h_nchunks, nchunks.data(), sizeof(int32_t) * count);
+  }
+  c->h_items = items;
+  c->h_nrows = count;
+  if (c->S == 1) RWR_TRY(plan_partition(c));
+  return ensure_partials(c);
+}
+
+// Grow every per-node array to hold at least `need` nodes.
+static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
+  if (need <= c->n_cap) return RWR_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int32_t old_cap = c->n_cap;
+  const int64_t want = std::max<int64_t>((int64_t)need + need / 8 + 1024, (int64_t)old_cap * 3 / 2);
+  if (want >= INT32_MAX) {
+    c->err = "node capacity overflow";
+    return RWR_EINVAL;
+  }
+  const int32_t new_cap = (int32_t)want;
+  auto regrow = [&](void **p, size_t elem, size_t per_node) -> rwr_status {
+    void *np = nullptr;
+    RWR_TRY(dev_alloc(c, &np, elem * per_node * new_cap));
+    launch_zero_bytes(np, (elem * per_node * new_cap + 3) / 4 * 4, c->stream);
+    if (*p) {
+      hipError_t e = hipMemcpyAsync(np, *p, elem * per_node * old_cap, hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) {
+        c->err = hipGetErrorString(e);
+        return RWR_EHIP;
+      }
+      (void)hipStreamSynchronize(c->stream);
+      (void)hipFree(*p);
+    }
+    *p = np;
+    return RWR_OK;
+  };
+  const int no = c->undirected ? 1 : 2;
+  for (int o = 0; o < no; ++o) {
+    RWR_TRY(regrow((void **)&c->g[o].v.off, 4, 1));
+    RWR_TRY(regrow((void **)&c->g[o].v.len, 4, 1));
+    RWR_TRY(regrow((void **)&c->g[o].v.cap, 4, 1));
+    RWR_TRY(regrow((void **)&c->g[o].v.heavy, 1, 1));
+  }
+  if (c->undirected) c->g[1] = c->g[0];
+  const size_t xs = c->fp64 ? 8 : 4;
+  RWR_TRY(regrow((void **)&c->r, 8, c->S));
+  RWR_TRY(regrow((void **)&c->ybuf, 8, c->S));
+  RWR_TRY(regrow((void **)&c->gbuf, 8, c->S));
+  RWR_TRY(regrow(&c->x[0], xs, c->S));
+  RWR_TRY(regrow(&c->x[1], xs, c->S));
+  RWR_TRY(regrow((void **)&c->stamp, 4, 1));
+  RWR_TRY(regrow((void **)&c->front[0], 4, 1));
+  RWR_TRY(regrow((void **)&c->front[1], 4, 1));
+  RWR_TRY(regrow((void **)&c->hfront, 4, 1));
+  RWR_TRY(regrow((void **)&c->sel, 4, 2));
+  c->n_cap = new_cap;
+  tune_defaults(c);
+  RWR_TRY(plan_heavy(c));
+  RWR_TRY(ensure_partials(c));
+  return RWR_OK;
+}
+
+// Move orientation o to a fresh layout with slack on every row and an arena of
+// at least `arena_min` slots.
+static rwr_status relayout(rwr_ctx *c, int o, int64_t arena_min) {
+  Orientation &g = c->g[o];
+  int32_t *new_off = nullptr, *new_capv = nullptr, *new_adj = nullptr;
+  RWR_TRY(dev_alloc(c, (void **)&new_off, sizeof(int32_t) * c->n_cap));
+  RWR_TRY(dev_alloc(c, (void **)&new_capv, sizeof(int32_t) * c->n_cap));
+  launch_fill_i32(new_off, c->n_cap, 0, c->stream);
+  launch_fill_i32(new_capv, c->n_cap, 0, c->stream);
+  RWR_TRY(ensure_temp(c, build_temp_bytes(1, c->n_cap)));
+  int64_t used = 0;
+  HIP_TRY(c, relayout_offsets(g.v.len, c->n, new_capv, new_off, c->temp, c->temp_bytes, &used, c->stream));
+  const int64_t arena = std::max<int64_t>({used / 4, arena_min, 65536});
+  const int64_t e_cap = used + arena;
+  if (e_cap >= INT32_MAX) {
+    c->err = "adjacency capacity exceeds 2^31 slots";
+    return RWR_ENOMEM;
+  }
+  RWR_TRY(dev_alloc(c, (void **)&new_adj, sizeof(int32_t) * e_cap));
+  launch_copy_rows(g.v, new_off, new_adj, c->n, c->stream);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  (void)hipFree(g.v.adj);
+  (void)hipFree(g.v.off);
+  (void)hipFree(g.v.cap);
+  g.v.adj = new_adj;
+  g.v.off = new_off;
+  g.v.cap = new_capv;
+  g.e_cap = e_cap;
+  uint64_t tail = (uint64_t)used;
+  H2D(c, &c->ctl->tail[o], &tail, sizeof(tail));
+  if (c->undirected) c->g[1] = c->g[0];
+  return RWR_OK;
+}
+
+// Build orientation o from rows/cols (device arrays of m entries).
+static rwr_status build_orient(rwr_ctx *c, int o, const int32_t *rows, const int32_t *cols, int64_t m) {
+  Orientation &g = c->g[o];
+  RWR_TRY(alloc_zero(c, &g.v.off, c->n_cap));
+  RWR_TRY(alloc_zero(c, &g.v.len, c->n_cap));
+  RWR_TRY(alloc_zero(c, &g.v.cap, c->n_cap));
+  RWR_TRY(alloc_zero(c, &g.v.heavy, c->n_cap));
+  uint64_t *keys = nullptr, *keys_alt = nullptr;
+  int32_t *sstart = nullptr;
+  RWR_TRY(dev_alloc(c, (void **)&keys, sizeof(uint64_t) * std::max<int64_t>(1, m)));
+  RWR_TRY(dev_alloc(c, (void **)&keys_alt, sizeof(uint64_t) * std::max<int64_t>(1, m)));
+  RWR_TRY(dev_alloc(c, (void **)&sstart, sizeof(int32_t) * c->n_cap));
+  RWR_TRY(ensure_temp(c, build_temp_bytes(std::max<int64_t>(1, m), c->n_cap)));
+  int64_t used = 0;
+  // rows beyond n are empty; build over all n_cap rows so offsets are defined
+  HIP_TRY(c, build_phase1(rows, cols, m, c->n, g.v, c->temp, c->temp_bytes, keys, keys_alt, sstart, c->ctl, &used,
+                          c->stream));
+  RWR_TRY(read_ctl(c));
+  if (c->ctl_h->err != 0) {
+    (void)hipFree(keys);
+    (void)hipFree(keys_alt);
+    (void)hipFree(sstart);
+    c->err = "edge list has an id out of range or a repeated edge";
+    return RWR_EINVAL;
+  }
+  const int64_t arena = std::max<int64_t>(used / 4, 65536);
+  g.e_cap = used + arena;
+  if (g.e_cap >= INT32_MAX) {
+    c->err = "adjacency capacity exceeds 2^31 slots";
+    return RWR_ENOMEM;
+  }
+  RWR_TRY(alloc_zero(c, &g.v.adj, g.e_cap));
+  build_phase2(keys, m, g.v, sstart, c->stream);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  (void)hipFree(keys);
+  (void)hipFree(keys_alt);
+  (void)hipFree(sstart);
+  uint64_t tail = (uint64_t)used;
+  H2D(c, &c->ctl->tail[o], &tail, sizeof(tail));
+  return RWR_OK;
+}
+
+// Enqueue iteration slots until the device reports MODE_DONE.  The slot that
+// computes x^(0) must already be enqueued; `mode` is the phase it leaves
+// (sparse after an offset seed or a seed vector, dense after a residual).
+// Only the kernels of the current phase are launched; the phase is re-read
+// at every synchronisation (a switch mid-chunk turns the chunk's remaining
+// sparse slots into no-ops, and the next chunk starts at the device's count).
+static rwr_status run_slots(rwr_ctx *c, int mode) {
+  const SlotArgs a = slot_args(c);
+  int k = 1;
+  int chunk = 4;
+  double prev = -1.0;
+  int prev_iter = 0;
+  int dense_launched = 0, dense_base = c->prof_used;
+  while (true) {
+    if (k > c->max_iters + 1) {
+      c->err = "iteration slots exhausted without completion";
+      return RWR_EHIP;
+    }
+    const int kend = std::min(k + chunk, c->max_iters + 2);
+    for (; k < kend; ++k) {
+      if (mode == MODE_DENSE) {
+        if (c->prof_on) RWR_TRY(prof_record(c, true));
+        launch_dense_slot(a, c->S, c->fp64, k, c->stream);
+        if (c->prof_on) RWR_TRY(prof_record(c, false));
+        ++dense_launched;
+      } else {
+        launch_sparse_slot(a, c->S, c->fp64, k, c->stream);
+      }
+    }
+    RWR_TRY(read_ctl(c));
+    const Ctl &h = *c->ctl_h;
+    if (h.mode == MODE_DONE) break;
+    mode = h.mode;
+    k = h.iter;
+    // predict the remaining iterations from the observed decay
+    double cur = 0.0;
+    for (int j = 0; j < c->n_seeds; ++j)
+      if (h.active[j]) cur = std::max(cur, h.last_norm[j]);
+    double decay = 1.0 - c->cfg.c;
+    if (prev > 0.0 && cur > 0.0 && h.iter > prev_iter) {
+      decay = std::pow(cur / prev, 1.0 / (h.iter - prev_iter));
+      decay = std::min(std::max(decay, 0.3), 0.95);
+    }
+    int rem = 1;
+    if (cur > h.eps && cur > 0.0) rem = std::max(1, (int)std::ceil(std::log(h.eps / cur) / std::log(decay)));
+    chunk = mode == MODE_DENSE ? std::min(rem, 64) : std::max(2, std::min(rem, 16));
+    prev = cur;
+    prev_iter = h.iter;
+  }
+  if (c->prof_on) RWR_TRY(prof_collect(c, dense_base, dense_launched, c->ctl_h->dense_iters));
+  launch_finish(a, c->S, c->fp64, c->stream);
+  return RWR_OK;
+}
+
+static uint64_t all_cols_mask(int n_seeds) { return n_seeds >= 64 ? ~0ull : ((1ull << n_seeds) - 1ull); }
+
+static int64_t dense_thresh(const rwr_ctx *c) { return std::max<int64_t>(1, c->m / std::max(1, c->pull_ratio)); }
+
+static double fp32_factor(const rwr_ctx *c) { return c->fp64 ? 0.0 : 8.0 * std::ldexp(1.0, -24); }
+
+// bookkeeping after a propagation run: per-column bound increments
+static void account_run(rwr_ctx *c, bool reset) {
+  const Ctl &h = *c->ctl_h;
+  const int iters = std::max(0, h.iter - 1);
+  c->last_iters = iters;
+  c->last_hist.assign((size_t)(iters + 1) * c->S, 0.0);
+  (void)hipMemcpyAsync(c->last_hist.data(), c->hist, sizeof(double) * c->last_hist.size(), hipMemcpyDeviceToHost,
+                 c->stream);
+  (void)hipStreamSynchronize(c->stream);
+  const double cc = c->cfg.c;
+  for (int j = 0; j < c->n_seeds; ++j) {
+    double sum_norms = 0.0;
+    for (int i = 0; i <= iters; ++i) sum_norms += c->last_hist[(size_t)i * c->S + j];
+    const double sig = std::fabs(h.sigma[j]) > 0 ? std::fabs(h.sigma[j]) : 1.0;
+    const double tail = 2.0 * (1.0 - cc) / cc * h.last_norm[j] / sig;
+    const double rnd = 2.0 * fp32_factor(c) * sum_norms / (cc * sig);
+    if (reset)
+      c->err_bound[j] = tail + rnd;
+    else
+      c->err_bound[j] += tail + rnd;
+  }
+}
+
+// Keep every column's error bound within the budget.  The running bound is
+// the sum of the per-update truncation bounds (Theorem 3 applied to each
+// update, doubled for the rescaling) plus an estimate of FP32 rounding.  When
+// it exceeds the budget, the FP64 residual g = P r - r (seed entries zeroed)
+// is evaluated: it certifies ||r/sigma - r*/sigma*||_1 <= 2 ||g||_1 / (c sigma).
+// Columns whose certified error is still above the budget are refined: g is
+// propagated (r += sum_i P^i g) down to an eighth of the budget.  `force`
+// evaluates the residual regardless of the running bound, and refines above
+// `refine_at` (a fraction of the budget).
+static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double refine_at = 1.0) {
+  double worst = 0.0;
+  for (int j = 0; j < c->n_seeds; ++j) worst = std::max(worst, c->err_bound[j]);
+  if (!force && worst <= c->budget) return RWR_OK;
+  const SlotArgs a = slot_args(c);
+  launch_residual(a, c->S, c->stream);
+  RWR_TRY(read_ctl(c));
+  const double cc = c->cfg.c;
+  uint64_t mask = 0;
+  double resid = 0.0;
+  for (int j = 0; j < c->n_seeds; ++j) {
+    const double sig = std::fabs(c->ctl_h->sigma[j]);
+    const double g = c->ctl_h->red_norm[j];
+    resid = std::max(resid, g);
+    const double cert = 2.0 * g / (cc * sig);
+    c->err_bound[j] = cert;
+    if (cert > refine_at * c->budget) mask |= 1ull << j;
+  }
+  if (st) {
+    st->checked = 1;
+    st->residual_l1 = resid;
+  }
+  if (mask == 0) return RWR_OK;
+  double min_sig = 1e300;
+  for (int j = 0; j < c->n_seeds; ++j) min_sig = std::min(min_sig, std::fabs(c->ctl_h->sigma[j]));
+  // truncation bound of the refinement: 2 (1-c)/c * eps_ref / sigma = budget/8
+  const double eps_ref = c->budget * cc * min_sig / (16.0 * (1.0 - cc));
+  launch_reset_run(c->ctl, c->S, mask, eps_ref, c->max_iters, dense_thresh(c), c->n / 16 + 1, c->stream);
+  launch_refine_init(a, c->S, c->fp64, c->stream);
+  RWR_TRY(run_slots(c, MODE_DENSE));
+  RWR_TRY(read_ctl(c));
+  if (c->ctl_h->prop_err != 0) {
+    c->stale = true;
+    c->err = "refinement did not converge";
+    return (rwr_status)c->ctl_h->prop_err;
+  }
+  const double fpf = fp32_factor(c);
+  for (int j = 0; j < c->n_seeds; ++j) {
+    if (!((mask >> j) & 1ull)) continue;
+    const double sig = std::fabs(c->ctl_h->sigma[j]);
+    // truncation of the refinement + FP32 rounding of propagating g
+    c->err_bound[j] = 2.0 * (1.0 - cc) / cc * c->ctl_h->last_norm[j] / sig +
+                      8.0 * fpf * c->ctl_h->red_norm[j] / (cc * sig);
+  }
+  if (st) st->refined = 1;
+  return RWR_OK;
+}
+
+static void fill_stats(rwr_ctx *c, rwr_stats *st) {
+  if (!st) return;
+  const Ctl &h = *c->ctl_h;
+  st->iters = std::max(0, h.iter - 1);
+  st->dense_iters = h.dense_iters;
+  st->visited_edges = h.visited + (int64_t)h.dense_iters * c->m;
+  st->touched_rows = h.nT[0];
+  double q = 0.0, lx = 0.0;
+  for (int j = 0; j < c->n_seeds; ++j) {
+    if (!c->last_hist.empty()) q = std::max(q, c->last_hist[j]);
+    lx = std::max(lx, h.last_norm[j]);
+  }
+  st->q_off_l1 = q;
+  st->last_x_l1 = lx;
+}
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+rwr_status rwr_config_default(rwr_config *cfg) {
+  if (!cfg) return RWR_EINVAL;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->c = 0.15;
+  cfg->eps = 1e-9;
+  cfg->err_budget = 0.0;
+  cfg->build_tol = 0.0;
+  cfg->precision = RWR_PROP_FP32;
+  cfg->undirected = 0;
+  cfg->max_iters = 10000;
+  cfg->pull_ratio = 0;
+  cfg->stream = nullptr;
+  return RWR_OK;
+}
+
+static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                             int32_t n_seeds, const int32_t *seeds, int32_t on_device) {
+  HIP_TRY(c, hipGetDevice(&c->device));
+  if (c->cfg.stream) {
+    c->stream = (hipStream_t)c->cfg.stream;
+  } else {
+    HIP_TRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  c->undirected = c->cfg.undirected != 0;
+  c->fp64 = c->cfg.precision == RWR_PROP_FP64;
+  c->max_iters = c->cfg.max_iters > 0 ? c->cfg.max_iters : 10000;
+  c->n = n;
+  c->n_cap = (int32_t)std::min<int64_t>((int64_t)n + std::max<int64_t>(1024, n / 16), INT32_MAX - 1);
+  c->n_seeds = n_seeds;
+  c->S = next_pow2_cols(n_seeds);
+  c->budget = c->cfg.err_budget > 0 ? c->cfg.err_budget : 2.0 * c->cfg.eps / c->cfg.c;
+  c->seeds_h.assign(seeds, seeds + n_seeds);
+  tune_defaults(c);
+
+  HIP_TRY(c, hipHostMalloc((void **)&c->ctl_h, sizeof(Ctl), hipHostMallocDefault));
+  std::memset(c->ctl_h, 0, sizeof(Ctl));
+  RWR_TRY(alloc_zero(c, &c->ctl, 1));
+  {
+    Ctl init{};
+    init.stamp = 1;
+    H2D(c, c->ctl, &init, sizeof(Ctl));
+  }
+  RWR_TRY(alloc_zero(c, &c->seeds_d, RWR_MAX_COLS));
+  H2D(c, c->seeds_d, seeds, sizeof(int32_t) * n_seeds);
+
+  // edge list on the device, both directions for undirected graphs
+  int32_t *src_d = nullptr, *dst_d = nullptr;
+  int64_t m2 = m;
+  if (c->undirected) {
+    std::vector<int32_t> hs(m), hd(m);
+    if (m > 0) {
+      if (on_device) {
+        D2H(c, hs.data(), src, sizeof(int32_t) * m);
+        D2H(c, hd.data(), dst, sizeof(int32_t) * m);
+      } else {
+        std::memcpy(hs.data(), src, sizeof(int32_t) * m);
+        std::memcpy(hd.data(), dst, sizeof(int32_t) * m);
+      }
+    }
+    std::vector<int32_t> s2, d2;
+    s2.reserve(2 * m);
+    d2.reserve(2 * m);
+    for (int64_t i = 0; i < m; ++i) {
+      s2.push_back(hs[i]);
+      d2.push_back(hd[i]);
+      if (hs[i] != hd[i]) {
+        s2.push_back(hd[i]);
+        d2.push_back(hs[i]);
+      }
+    }
+    m2 = (int64_t)s2.size();
+    RWR_TRY(dev_alloc(c, (void **)&src_d, sizeof(int32_t) * std::max<int64_t>(1, m2)));
+    RWR_TRY(dev_alloc(c, (void **)&dst_d, sizeof(int32_t) * std::max<int64_t>(1, m2)));
+    if (m2 > 0) {
+      H2D(c, src_d, s2.data(), sizeof(int32_t) * m2);
+      H2D(c, dst_d, d2.data(), sizeof(int32_t) * m2);
+    }
+  } else if (on_device) {
+    src_d = const_cast<int32_t *>(src);
+    dst_d = const_cast<int32_t *>(dst);
+  } else {
+    RWR_TRY(dev_alloc(c, (void **)&src_d, sizeof(int32_t) * std::max<int64_t>(1, m)));
+    RWR_TRY(dev_alloc(c, (void **)&dst_d, sizeof(int32_t) * std::max<int64_t>(1, m)));
+    if (m > 0) {
+      H2D(c, src_d, src, sizeof(int32_t) * m);
+      H2D(c, dst_d, dst, sizeof(int32_t) * m);
+    }
+  }
+  const bool own_edges = c->undirected || !on_device;
+  rwr_status s = build_orient(c, 0, src_d, dst_d, m2);
+  if (s == RWR_OK && !c->undirected) s = build_orient(c, 1, dst_d, src_d, m2);
+  if (own_edges) {
+    (void)hipFree(src_d);
+    (void)hipFree(dst_d);
+  }
+  if (s != RWR_OK) return s;
+  if (c->undirected) c->g[1] = c->g[0];
+  c->m = m2;
+
+  // score and propagation state
+  const size_t nS = (size_t)c->n_cap * c->S;
+  RWR_TRY(alloc_zero(c, &c->r, nS));
+  RWR_TRY(alloc_zero(c, &c->ybuf, nS));
+  RWR_TRY(alloc_zero(c, &c->gbuf, nS));
+  const size_t xs = c->fp64 ? 8 : 4;
+  RWR_TRY(dev_alloc(c, &c->x[0], xs * nS));
+  RWR_TRY(dev_alloc(c, &c->x[1], xs * nS));
+  launch_zero_bytes(c->x[0], xs * nS, c->stream);
+  launch_zero_bytes(c->x[1], xs * nS, c->stream);
+  RWR_TRY(alloc_zero(c, &c->stamp, c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->front[0], c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->front[1], c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->hfront, c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->sel, (size_t)c->n_cap * 2));
+  RWR_TRY(alloc_zero(c, &c->sel_count, 1));
+  RWR_TRY(alloc_zero(c, &c->hist, (size_t)(c->max_iters + 2) * c->S));
+  RWR_TRY(plan_heavy(c));
+  RWR_TRY(ensure_partials(c));
+
+  // static scores: CPI from c*e_s (Section 2.2), then residual refinement
+  const double build_tol = c->cfg.build_tol > 0 ? c->cfg.build_tol : 0.25 * c->budget;
+  const double cc = c->cfg.c;
+  const double eps0 = std::min(c->cfg.eps, build_tol * cc / (4.0 * (1.0 - cc)));
+  const SlotArgs a = slot_args(c);
+  launch_reset_run(c->ctl, c->S, all_cols_mask(n_seeds), eps0, c->max_iters, dense_thresh(c), c->n / 16 + 1,
+                   c->stream);
+  launch_seed_init(a, c->S, c->stream);
+  launch_slot0_epilogue(a, c->S, c->fp64, c->stream);
+  RWR_TRY(run_slots(c, MODE_SPARSE));
+  RWR_TRY(read_ctl(c));
+  if (c->ctl_h->prop_err != 0) {
+    c->err = "initial solve did not converge";
+    return (rwr_status)c->ctl_h->prop_err;
+  }
+  account_run(c, true);
+  // certify (and refine) until the build tolerance holds
+  const double saved = c->budget;
+  c->budget = build_tol;
+  for (int round = 0; round < 8; ++round) {
+    rwr_stats st{};
+    RWR_TRY(check_and_refine(c, true, &st));
+    if (!st.refined) break;
+  }
+  c->budget = saved;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return RWR_OK;
+}
+
+rwr_status rwr_build(const rwr_config *cfg, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                     int32_t n_seeds, const int32_t *seeds, int32_t edges_on_device, rwr_ctx **out) {
+  if (!out) return RWR_EINVAL;
+  *out = nullptr;
+  rwr_config def;
+  rwr_config_default(&def);
+  const rwr_config &cf = cfg ? *cfg : def;
+  if (n <= 0 || m < 0 || (m > 0 && (!src || !dst)) || n_seeds < 1 || n_seeds > RWR_MAX_COLS || !seeds ||
+      !(cf.c > 0.0 && cf.c < 1.0) || !(cf.eps > 0.0) || n >= INT32_MAX - 1024) {
+    g_build_error = "invalid argument";
+    return RWR_EINVAL;
+  }
+  for (int i = 0; i < n_seeds; ++i) {
+    if (seeds[i] < 0 || seeds[i] >= n) {
+      g_build_error = "seed id out of range";
+      return RWR_EINVAL;
+    }
+    for (int k = 0; k < i; ++k)
+      if (seeds[k] == seeds[i]) {
+        g_build_error = "repeated seed";
+        return RWR_EINVAL;
+      }
+  }
+  rwr_ctx *c = new rwr_ctx();
+  c->cfg = cf;
+  rwr_status s = build_impl(c, n, m, src, dst, n_seeds, seeds, edges_on_device);
+  if (s != RWR_OK) {
+    g_build_error = c->err;
+    rwr_destroy(c);
+    return s;
+  }
+  *out = c;
+  return RWR_OK;
+}
+
+static rwr_status ensure_batch(rwr_ctx *c, int64_t nkeys, int64_t nints) {
+  if (nkeys > c->bcap) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int64_t cap = std::max<int64_t>(nkeys, 2 * c->bcap);
+    for (int o = 0; o < 2; ++o) {
+      dev_free(c->keys[o]);
+      dev_free(c->seg[o]);
+      dev_free(c->row[o]);
+      dev_free(c->t_dold[o]);
+      dev_free(c->t_dnew[o]);
+      RWR_TRY(alloc_zero(c, &c->keys[o], cap));
+      RWR_TRY(alloc_zero(c, &c->seg[o], cap + 1));
+      RWR_TRY(alloc_zero(c, &c->row[o], cap + 1));
+      RWR_TRY(alloc_zero(c, &c->t_dold[o], cap + 1));
+      RWR_TRY(alloc_zero(c, &c->t_dnew[o], cap + 1));
+    }
+    dev_free(c->keys_alt);
+    dev_free(c->flags);
+    dev_free(c->pos);
+    RWR_TRY(alloc_zero(c, &c->keys_alt, cap));
+    RWR_TRY(alloc_zero(c, &c->flags, cap));
+    RWR_TRY(alloc_zero(c, &c->pos, cap));
+    RWR_TRY(ensure_temp(c, sort_temp_bytes((int32_t)cap)));
+    c->bcap = cap;
+  }
+  if (nints > c->b_host_cap) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->b_host) (void)hipHostFree(c->b_host);
+    dev_free(c->b_dev);
+    const int64_t cap = std::max<int64_t>(nints, 2 * c->b_host_cap);
+    HIP_TRY(c, hipHostMalloc((void **)&c->b_host, sizeof(int32_t) * cap, hipHostMallocDefault));
+    RWR_TRY(dev_alloc(c, (void **)&c->b_dev, sizeof(int32_t) * cap));
+    c->b_host_cap = cap;
+  }
+  return RWR_OK;
+}
+
+rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
+  if (!c || !b) return RWR_EINVAL;
+  const double t0 = now_ms();
+  if (st) std::memset(st, 0, sizeof(*st));
+  if (c->stale) {
+    c->err = "context is stale (an earlier update did not converge); call rwr_refine";
+    return RWR_ESTATE;
+  }
+  if (b->n_ins < 0 || b->n_del < 0 || b->n_new_nodes < 0 || b->n_del_nodes < 0 ||
+      (b->n_ins > 0 && (!b->ins_src || !b->ins_dst)) || (b->n_del > 0 && (!b->del_src || !b->del_dst))) {
+    c->err = "invalid batch";
+    return RWR_EINVAL;
+  }
+  if (b->n_del_nodes > 0) {
+    c->err = "node deletion is expressed through edge deletions in this build";
+    return RWR_EINVAL;
+  }
+  const int64_t n_new64 = (int64_t)c->n + b->n_new_nodes;
+  if (n_new64 >= INT32_MAX - 1024) {
+    c->err = "node count overflow";
+    return RWR_EINVAL;
+  }
+  const int32_t n_new = (int32_t)n_new64;
+  RWR_TRY(grow_nodes(c, n_new));
+  const int64_t N = b->n_ins + b->n_del;
+  const int64_t nkeys = c->undirected ? 2 * N : N;
+  if (nkeys >= INT32_MAX) {
+    c->err = "batch too large";
+    return RWR_EINVAL;
+  }
+  RWR_TRY(ensure_batch(c, std::max<int64_t>(nkeys, 1), 4 * std::max<int64_t>(N, 1)));
+  const int b1 = bits_for(std::max(1, n_new - 1)) + 1;
+  launch_reset_batch(c->ctl, 0, c->stream);
+
+  const int32_t *ins_s = b->ins_src, *ins_d = b->ins_dst, *del_s = b->del_src, *del_d = b->del_dst;
+  if (!b->on_device && N > 0) {
+    int32_t *h = c->b_host;
+    std::memcpy(h, b->ins_src, sizeof(int32_t) * b->n_ins);
+    std::memcpy(h + b->n_ins, b->ins_dst, sizeof(int32_t) * b->n_ins);
+    std::memcpy(h + 2 * b->n_ins, b->del_src, sizeof(int32_t) * b->n_del);
+    std::memcpy(h + 2 * b->n_ins + b->n_del, b->del_dst, sizeof(int32_t) * b->n_del);
+    HIP_TRY(c, hipMemcpyAsync(c->b_dev, h, sizeof(int32_t) * 2 * N, hipMemcpyHostToDevice, c->stream));
+    ins_s = c->b_dev;
+    ins_d = c->b_dev + b->n_ins;
+    del_s = c->b_dev + 2 * b->n_ins;
+    del_d = c->b_dev + 2 * b->n_ins + b->n_del;
+  }
+  const int norient = c->undirected ? 1 : 2;
+  const int po = pull_orient(c);
+  if (N > 0) {
+    launch_make_keys(ins_s, ins_d, b->n_ins, del_s, del_d, b->n_del, n_new, b1, c->undirected ? 1 : 0, c->keys[0],
+                     c->keys[1], c->ctl, c->stream);
+    if (nkeys <= SMALL_SORT_MAX) {
+      launch_sort_segment_small(c->keys[0], c->keys[1], (int32_t)nkeys, b1, c->seg[0], c->row[0], c->seg[1],
+                                c->row[1], norient, c->ctl, c->stream);
+    } else {
+      for (int o = 0; o < norient; ++o)
+        HIP_TRY(c, sort_segment_large(c->keys[o], c->keys_alt, (int32_t)nkeys, b1, c->flags, c->pos, c->seg[o],
+                                      c->row[o], c->temp, c->temp_bytes, c->ctl, o, c->stream));
+    }
+    for (int o = 0; o < norient; ++o)
+      launch_validate_plan(c->keys[o], c->seg[o], c->row[o], c->g[o].v, b1, c->t_dold[o], c->t_dnew[o], c->ctl, o,
+                           o == 0 ? 1 : 0, o == po ? c->heavy_limit : 0, (int32_t)nkeys, c->stream);
+  }
+  RWR_TRY(read_ctl(c));
+  if (c->ctl_h->err != 0) {
+    const int e = c->ctl_h->err;
+    c->err = e == ERR_EEXIST   ? "batch inserts an edge that exists"
+             : e == ERR_ENOENT ? "batch deletes an edge that does not exist"
+                               : "batch has an id out of range or a repeated entry";
+    return (rwr_status)e;
+  }
+  // arena space for relocated rows; after a relayout the demand is recomputed
+  // on the new layout (capacities changed)
+  for (int round = 0;; ++round) {
+    bool again = false;
+    for (int o = 0; o < norient; ++o) {
+      const int64_t need = (int64_t)c->ctl_h->tail[o] + c->ctl_h->demand[o];
+      if (need > c->g[o].e_cap) {
+        if (round > 0) {
+          c->err = "relocation arena too small after relayout";
+          return RWR_ENOMEM;
+        }
+        RWR_TRY(relayout(c, o, 2 * c->ctl_h->demand[o] + 65536));
+        again = true;
+      }
+    }
+    if (!again) break;
+    launch_reset_batch(c->ctl, 1, c->stream);
+    for (int o = 0; o < norient; ++o)
+      launch_validate_plan(c->keys[o], c->seg[o], c->row[o], c->g[o].v, b1, c->t_dold[o], c->t_dnew[o], c->ctl, o, 0,
+                           o == po ? c->heavy_limit : 0, (int32_t)nkeys, c->stream);
+    RWR_TRY(read_ctl(c));
+  }
+  // the batch is valid: commit the node count and apply
+  c->n = n_new;
+  const SlotArgs a = slot_args(c);
+  launch_reset_run(c->ctl, c->S, all_cols_mask(c->n_seeds), c->cfg.eps, c->max_iters, dense_thresh(c),
+                   c->n / 16 + 1, c->stream);
+  if (N > 0) {
+    launch_offset_seed(c->S, c->keys[0], c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->g[0].v, c->r, c->ybuf,
+                       c->stamp, c->front[0], c->ctl, b1, 1.0 - c->cfg.c, (int32_t)nkeys, c->stream);
+    for (int o = 0; o < norient; ++o)
+      launch_apply(c->keys[o], c->seg[o], c->row[o], c->t_dold[o], c->t_dnew[o], c->g[o].v, c->ctl, o, b1,
+                   (int32_t)nkeys, c->g[o].e_cap, c->stream);
+  }
+  // stored edge count (an undirected self-loop is stored once; the count only
+  // steers the sparse/dense switch and the visited-edge statistic)
+  c->m += (b->n_ins - b->n_del) * (c->undirected ? 2 : 1);
+  launch_slot0_epilogue(a, c->S, c->fp64, c->stream);
+  RWR_TRY(run_slots(c, MODE_SPARSE));
+  RWR_TRY(read_ctl(c));
+  account_run(c, false);
+  fill_stats(c, st);
+  rwr_status ret = RWR_OK;
+  if (c->ctl_h->prop_err != 0) {
+    c->stale = true;
+    ret = (rwr_status)c->ctl_h->prop_err;
+    c->err = ret == RWR_ENOCONV ? "max_iters reached before convergence" : "non-finite values during propagation";
+  } else {
+    RWR_TRY(check_and_refine(c, false, st));
+  }
+  if (c->ctl_h->heavy_stale > 0) RWR_TRY(plan_heavy(c));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (st) {
+    double worst = 0.0;
+    for (int j = 0; j < c->n_seeds; ++j) worst = std::max(worst, c->err_bound[j]);
+    st->err_bound = worst;
+    st->ms_total = now_ms() - t0;
+  }
+  return ret;
+}
+
+rwr_status rwr_refine(rwr_ctx *c, rwr_stats *st) {
+  if (!c) return RWR_EINVAL;
+  if (st) std::memset(st, 0, sizeof(*st));
+  const double t0 = now_ms();
+  c->stale = false;
+  rwr_status s = check_and_refine(c, true, st, 0.125);
+  if (s != RWR_OK) return s;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (st) {
+    double worst = 0.0;
+    for (int j = 0; j < c->n_seeds; ++j) worst = std::max(worst, c->err_bound[j]);
+    st->err_bound = worst;
+    st->ms_total = now_ms() - t0;
+  }
+  return RWR_OK;
+}
+
+rwr_status rwr_scores(rwr_ctx *c, int32_t j, double *out, int64_t cap, int32_t out_on_device) {
+  if (!c || !out || j < 0 || j >= c->n_seeds) return RWR_EINVAL;
+  if (cap < c->n) {
+    c->err = "output capacity below the node count";
+    return RWR_EINVAL;
+  }
+  double *dst = out_on_device ? out : c->gbuf;
+  launch_scores(c->r, c->ctl, c->S, j, c->n, dst, c->stream);
+  if (!out_on_device) HIP_TRY(c, hipMemcpyAsync(out, c->gbuf, sizeof(double) * c->n, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return RWR_OK;
+}
+
+rwr_status rwr_graph_size(const rwr_ctx *c, int32_t *n, int64_t *m) {
+  if (!c) return RWR_EINVAL;
+  if (n) *n = c->n;
+  if (m) *m = c->m;
+  return RWR_OK;
+}
+
+rwr_status rwr_graph_export(rwr_ctx *c, int32_t *src, int32_t *dst, int64_t cap, int64_t *m_out, int32_t *deg_out) {
+  if (!c) return RWR_EINVAL;
+  std::vector<int32_t> len(c->n);
+  D2H(c, len.data(), c->g[0].v.len, sizeof(int32_t) * c->n);
+  int64_t m = 0;
+  for (int32_t v = 0; v < c->n; ++v) m += len[v];
+  c->m = m;
+  if (m_out) *m_out = m;
+  if (deg_out) std::memcpy(deg_out, len.data(), sizeof(int32_t) * c->n);
+  if (!src || !dst) return RWR_OK;
+  if (cap < m) {
+    c->err = "export capacity below the edge count";
+    return RWR_EINVAL;
+  }
+  int32_t *ds = nullptr, *dd = nullptr, *pos = nullptr;
+  RWR_TRY(dev_alloc(c, (void **)&ds, sizeof(int32_t) * std::max<int64_t>(1, m)));
+  RWR_TRY(dev_alloc(c, (void **)&dd, sizeof(int32_t) * std::max<int64_t>(1, m)));
+  RWR_TRY(dev_alloc(c, (void **)&pos, sizeof(int32_t) * c->n_cap));
+  RWR_TRY(ensure_temp(c, build_temp_bytes(1, c->n_cap)));
+  HIP_TRY(c, export_rows(c->g[0].v, c->n, ds, dd, pos, c->temp, c->temp_bytes, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  D2H(c, src, ds, sizeof(int32_t) * m);
+  D2H(c, dst, dd, sizeof(int32_t) * m);
+  (void)hipFree(ds);
+  (void)hipFree(dd);
+  (void)hipFree(pos);
+  return RWR_OK;
+}
+
+rwr_status rwr_last_norms(rwr_ctx *c, int32_t j, double *out, int32_t cap, int32_t *len) {
+  if (!c || j < 0 || j >= c->n_seeds || !len) return RWR_EINVAL;
+  const int32_t total = c->last_iters + 1;
+  const int32_t k = std::min(cap, total);
+  for (int32_t i = 0; i < k && out; ++i) out[i] = c->last_hist[(size_t)i * c->S + j];
+  *len = total;
+  return RWR_OK;
+}
+
+void rwr_destroy(rwr_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  const int no = c->undirected ? 1 : 2;
+  for (int o = 0; o < no; ++o) {
+    dev_free(c->g[o].v.off);
+    dev_free(c->g[o].v.len);
+    dev_free(c->g[o].v.cap);
+    dev_free(c->g[o].v.adj);
+    dev_free(c->g[o].v.heavy);
+  }
+  dev_free(c->r);
+  dev_free(c->ybuf);
+  dev_free(c->gbuf);
+  dev_free(c->x[0]);
+  dev_free(c->x[1]);
+  dev_free(c->stamp);
+  dev_free(c->front[0]);
+  dev_free(c->front[1]);
+  dev_free(c->hfront);
+  dev_free(c->ctl);
+  dev_free(c->hist);
+  dev_free(c->part);
+  dev_free(c->part_i);
+  dev_free(c->gcnt);
+  dev_free(c->h_item_row);
+  dev_free(c->h_item_chunk);
+  dev_free(c->h_rows);
+  dev_free(c->h_nchunks);
+  dev_free(c->h_cnt);
+  dev_free(c->h_acc);
+  dev_free(c->sel);
+  dev_free(c->sel_count);
+  dev_free(c->mp_rows);
+  dev_free(c->seeds_d);
+  dev_free(c->b_dev);
+  for (int o = 0; o < 2; ++o) {
+    dev_free(c->keys[o]);
+    dev_free(c->seg[o]);
+    dev_free(c->row[o]);
+    dev_free(c->t_dold[o]);
+    dev_free(c->t_dnew[o]);
+  }
+  dev_free(c->keys_alt);
+  dev_free(c->flags);
+  dev_free(c->pos);
+  dev_free(c->temp);
+  if (c->b_host) (void)hipHostFree(c->b_host);
+  if (c->ctl_h) (void)hipHostFree(c->ctl_h);
+  for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+rwr_status rwr_profile(rwr_ctx *c, int32_t enable) {
+  if (!c) return RWR_EINVAL;
+  c->prof_on = enable != 0;
+  return RWR_OK;
+}
+
+rwr_status rwr_profile_read(rwr_ctx *c, double *dense_ms, int64_t *dense_sweeps, int64_t *idle_launches,
+                            int32_t reset) {
+  if (!c) return RWR_EINVAL;
+  if (dense_ms) *dense_ms = c->prof_dense_ms;
+  if (dense_sweeps) *dense_sweeps = c->prof_dense_sweeps;
+  if (idle_launches) *idle_launches = c->prof_idle;
+  if (reset) {
+    c->prof_dense_ms = 0.0;
+    c->prof_dense_sweeps = 0;
+    c->prof_idle = 0;
+  }
+  return RWR_OK;
+}
+
+const char *rwr_last_error(const rwr_ctx *c) { return c ? c->err.c_str() : g_build_error.c_str(); }
+
+}  // extern "C"

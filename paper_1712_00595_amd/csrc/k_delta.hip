@@ -1,0 +1,465 @@
+// Device-side application of one update batch to the slack CSR/CSC graph,
+// and the offset seed of Section 3.1:
+//   q_offset = (1-c) (B~^T - A~^T) r_old,
+// which is non-zero only on the neighbours of the rows of A~ that the batch
+// changes (the non-zero rows of Delta A, Section 3.3).  For a changed row u
+// with old degree d_o and new degree d_n (1/0 read as 0, Section 3.4.2):
+//   neighbour kept      : (1-c) r(u) (1/d_n - 1/d_o)
+//   neighbour inserted  : (1-c) r(u) / d_n
+//   neighbour deleted   : -(1-c) r(u) / d_o
+//
+// Batch entries are packed into 64-bit keys
+//   key = (row << (B+1)) | (col << 1) | is_insert,   B = bits of the largest id,
+// one key array per orientation (out: row = source; in: row = destination).
+// Sorting a key array groups a row's entries, ordered by column, so each
+// touched row owns one segment that a wavefront can binary-search.
+#include <hipcub/hipcub.hpp>
+
+#include "rwr_common.h"
+#include "rwr_kernels.h"
+
+static constexpr uint64_t KEY_PAD = ~0ull;
+
+__device__ __forceinline__ int32_t key_row(uint64_t k, int b1) { return (int32_t)(k >> b1); }
+__device__ __forceinline__ int32_t key_col(uint64_t k, int b1) {
+  return (int32_t)((k >> 1) & ((1ull << (b1 - 1)) - 1));
+}
+
+// ---------------------------------------------------------------- keys
+__global__ void k_make_keys(const int32_t *__restrict__ ins_s, const int32_t *__restrict__ ins_d, int64_t n_ins,
+                            const int32_t *__restrict__ del_s, const int32_t *__restrict__ del_d, int64_t n_del,
+                            int32_t n_nodes, int b1, int undirected, uint64_t *__restrict__ k_out,
+                            uint64_t *__restrict__ k_in, Ctl *ctl) {
+  const int64_t total = n_ins + n_del;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const bool ins = i < n_ins;
+    const int32_t u = ins ? ins_s[i] : del_s[i - n_ins];
+    const int32_t v = ins ? ins_d[i] : del_d[i - n_ins];
+    const uint64_t t = ins ? 1ull : 0ull;
+    if (u < 0 || u >= n_nodes || v < 0 || v >= n_nodes) {
+      set_error(ctl, ERR_EINVAL);
+      if (undirected) {
+        k_out[2 * i] = KEY_PAD;
+        k_out[2 * i + 1] = KEY_PAD;
+      } else {
+        k_out[i] = KEY_PAD;
+        k_in[i] = KEY_PAD;
+      }
+      continue;
+    }
+    if (undirected) {
+      // a pair stands for both directed edges; a self-loop for one
+      k_out[2 * i] = ((uint64_t)u << b1) | ((uint64_t)v << 1) | t;
+      k_out[2 * i + 1] = (u == v) ? KEY_PAD : (((uint64_t)v << b1) | ((uint64_t)u << 1) | t);
+    } else {
+      k_out[i] = ((uint64_t)u << b1) | ((uint64_t)v << 1) | t;
+      k_in[i] = ((uint64_t)v << b1) | ((uint64_t)u << 1) | t;
+    }
+  }
+}
+
+// ------------------------------------------------- small batches: one block
+// Bitonic sort of up to SMALL_SORT_MAX keys in LDS, then duplicate check and
+// segment extraction.  blockIdx.x selects the orientation.
+__global__ __launch_bounds__(1024) void k_sort_segment_small(uint64_t *__restrict__ keys0, uint64_t *__restrict__ keys1,
+                                                             int32_t n_keys, int b1, int32_t *__restrict__ seg0,
+                                                             int32_t *__restrict__ row0, int32_t *__restrict__ seg1,
+                                                             int32_t *__restrict__ row1, Ctl *ctl) {
+  __shared__ uint64_t s[SMALL_SORT_MAX];
+  __shared__ int32_t wsum[1024 / RWR_WAVE];
+  uint64_t *keys = blockIdx.x == 0 ? keys0 : keys1;
+  int32_t *seg = blockIdx.x == 0 ? seg0 : seg1;
+  int32_t *row = blockIdx.x == 0 ? row0 : row1;
+  int np = 2;
+  while (np < n_keys) np <<= 1;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s[i] = i < n_keys ? keys[i] : KEY_PAD;
+  __syncthreads();
+  for (int k = 2; k <= np; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        const int p = i ^ j;
+        if (p > i) {
+          const uint64_t a = s[i], b = s[p];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            s[i] = b;
+            s[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // each thread owns a contiguous run of ITEMS positions
+  constexpr int ITEMS = SMALL_SORT_MAX / 1024;
+  const int base = threadIdx.x * ITEMS;
+  int heads = 0;
+  int32_t nvalid_local = -1;
+  for (int q = 0; q < ITEMS; ++q) {
+    const int i = base + q;
+    if (i >= np) break;
+    const uint64_t k = s[i];
+    if (k == KEY_PAD) {
+      if (nvalid_local < 0) nvalid_local = i;
+      continue;
+    }
+    if (i > 0) {
+      const uint64_t kp = s[i - 1];
+      if ((k >> 1) == (kp >> 1) && blockIdx.x == 0) set_error(ctl, ERR_EINVAL);
+      if (key_row(k, b1) != key_row(kp, b1)) ++heads;
+    } else {
+      ++heads;
+    }
+  }
+  // block exclusive scan of `heads`
+  const int lane = threadIdx.x % RWR_WAVE, wid = threadIdx.x / RWR_WAVE;
+  int incl = heads;
+  for (int off = 1; off < RWR_WAVE; off <<= 1) {
+    const int t = __shfl_up(incl, off, RWR_WAVE);
+    if (lane >= off) incl += t;
+  }
+  if (lane == RWR_WAVE - 1) wsum[wid] = incl;
+  __syncthreads();
+  int wbase = 0;
+  for (int w = 0; w < wid; ++w) wbase += wsum[w];
+  int pos = wbase + incl - heads;
+  for (int q = 0; q < ITEMS; ++q) {
+    const int i = base + q;
+    if (i >= np) break;
+    const uint64_t k = s[i];
+    if (k == KEY_PAD) break;
+    if (i == 0 || key_row(k, b1) != key_row(s[i - 1], b1)) {
+      seg[pos] = i;
+      row[pos] = key_row(k, b1);
+      ++pos;
+    }
+  }
+  for (int i = threadIdx.x; i < n_keys; i += blockDim.x) keys[i] = s[i];
+  // first PAD position = number of valid keys; segment end sentinel
+  __shared__ int32_t s_nvalid;
+  if (threadIdx.x == 0) s_nvalid = np;
+  __syncthreads();
+  if (nvalid_local >= 0) atomicMin(&s_nvalid, nvalid_local);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int total = 0;
+    for (int w = 0; w < (int)(blockDim.x / RWR_WAVE); ++w) total += wsum[w];
+    seg[total] = s_nvalid < n_keys ? s_nvalid : n_keys;
+    ctl->nT[blockIdx.x] = total;
+  }
+}
+
+// ------------------------------------------------- large batches: device sort
+__global__ void k_heads(const uint64_t *__restrict__ keys, int32_t n_keys, int b1, int32_t *__restrict__ flags,
+                        Ctl *ctl, int check_dups) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_keys; i += gridDim.x * blockDim.x) {
+    const uint64_t k = keys[i];
+    int h = 0;
+    if (k != KEY_PAD) {
+      if (i == 0) {
+        h = 1;
+      } else {
+        const uint64_t kp = keys[i - 1];
+        if (check_dups && (k >> 1) == (kp >> 1)) set_error(ctl, ERR_EINVAL);
+        h = key_row(k, b1) != key_row(kp, b1);
+      }
+    }
+    flags[i] = h;
+  }
+}
+
+__global__ void k_segments(const uint64_t *__restrict__ keys, int32_t n_keys, int b1,
+                           const int32_t *__restrict__ flags, const int32_t *__restrict__ pos,
+                           int32_t *__restrict__ seg, int32_t *__restrict__ row, Ctl *ctl, int orient) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_keys; i += gridDim.x * blockDim.x) {
+    const uint64_t k = keys[i];
+    if (k == KEY_PAD) continue;
+    if (flags[i]) {
+      seg[pos[i]] = i;
+      row[pos[i]] = key_row(k, b1);
+    }
+    if (i == n_keys - 1 || keys[i + 1] == KEY_PAD) {
+      const int32_t nT = pos[i] + flags[i];
+      seg[nT] = i + 1;
+      ctl->nT[orient] = nT;
+    }
+  }
+}
+
+// position of `col` in the sorted segment keys[b, e) of row `r`; -1 if absent
+__device__ __forceinline__ int32_t seg_find(const uint64_t *__restrict__ keys, int32_t b, int32_t e, int32_t r,
+                                            int32_t col, int b1) {
+  const uint64_t target = ((uint64_t)r << b1) | ((uint64_t)col << 1);
+  int32_t lo = b, hi = e;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (keys[mid] < target)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < e && (keys[lo] >> 1) == (target >> 1)) ? lo : -1;
+}
+
+__device__ __forceinline__ int32_t grown_cap(int32_t d) { return d + max(4, d >> 2); }
+
+// ------------------------------------------------- validation and planning
+// One wavefront per touched row.  For the out orientation (rows of A~) also
+// checks the batch against the graph: an inserted edge must be absent
+// (EEXIST), a deleted edge present (ENOENT).  Records old/new degree of each
+// touched row and the arena demand of rows that outgrow their capacity.
+__global__ void k_validate_plan(const uint64_t *__restrict__ keys, const int32_t *__restrict__ seg,
+                                const int32_t *__restrict__ row, const int32_t *__restrict__ off,
+                                const int32_t *__restrict__ len, const int32_t *__restrict__ cap,
+                                const int32_t *__restrict__ adj, int b1, int32_t *__restrict__ t_dold,
+                                int32_t *__restrict__ t_dnew, Ctl *ctl, int orient, int check, int heavy_limit) {
+  const int lane = threadIdx.x % RWR_WAVE;
+  const int32_t t = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE;
+  if (t >= ctl->nT[orient]) return;
+  const int32_t u = row[t], b = seg[t], e = seg[t + 1];
+  int n_ins = 0;
+  for (int32_t i = b + lane; i < e; i += RWR_WAVE) n_ins += (int)(keys[i] & 1ull);
+  n_ins = wave_xor_sum(n_ins, 1, RWR_WAVE);
+  const int n_del = (e - b) - n_ins;
+  const int32_t d_old = len[u];
+  int found = 0;
+  int exists = 0;
+  if (check) {
+    const int32_t o = off[u];
+    for (int32_t i = lane; i < d_old; i += RWR_WAVE) {
+      const int32_t v = adj[o + i];
+      const int32_t p = seg_find(keys, b, e, u, v, b1);
+      if (p >= 0) {
+        if (keys[p] & 1ull)
+          exists = 1;
+        else
+          ++found;
+      }
+    }
+    found = wave_xor_sum(found, 1, RWR_WAVE);
+    exists = wave_xor_sum(exists, 1, RWR_WAVE);
+  }
+  if (lane == 0) {
+    if (check) {
+      if (exists)
+        set_error(ctl, ERR_EEXIST);
+      else if (found != n_del)
+        set_error(ctl, ERR_ENOENT);
+    }
+    const int32_t d_new = d_old - n_del + n_ins;
+    t_dold[t] = d_old;
+    t_dnew[t] = d_new;
+    if (d_new > cap[u]) atomicAdd((unsigned long long *)&ctl->demand[orient], (unsigned long long)grown_cap(d_new));
+    if (heavy_limit > 0 && d_old <= heavy_limit && d_new > heavy_limit) atomicAdd(&ctl->heavy_stale, 1);
+  }
+}
+
+// ------------------------------------------------- offset seed
+// One wavefront per touched row u of A~ (before the row is rewritten).
+// Lane layout: column j = lane % S, edge slot p = lane / S.  Contributions go
+// to ybuf (FP64, atomically); every node receiving a non-zero contribution is
+// appended once to frontier list 0.
+template <int S>
+__global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *__restrict__ seg,
+                              const int32_t *__restrict__ row, const int32_t *__restrict__ t_dold,
+                              const int32_t *__restrict__ t_dnew, const int32_t *__restrict__ off,
+                              const int32_t *__restrict__ adj, const double *__restrict__ r,
+                              double *__restrict__ ybuf, int32_t *__restrict__ stamp, int32_t *__restrict__ front0,
+                              Ctl *ctl, int b1, double c1) {
+  if (ctl->err) return;
+  constexpr int P = RWR_WAVE / S;
+  const int lane = threadIdx.x % RWR_WAVE;
+  const int j = lane % S, p = lane / S;
+  const int32_t t = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE;
+  if (t >= ctl->nT[0]) return;
+  const int32_t u = row[t], b = seg[t], e = seg[t + 1];
+  const int32_t d_old = t_dold[t], d_new = t_dnew[t];
+  const double ru = r[col_index(u, S, j)];
+  const double w_old = d_old ? c1 * ru / (double)d_old : 0.0;
+  const double w_new = d_new ? c1 * ru / (double)d_new : 0.0;
+  const bool any_r = __ballot(ru != 0.0) != 0ull;
+  if (!any_r) return;
+  const int32_t st = ctl->stamp;
+  const int32_t o = off[u];
+  for (int32_t i = p; i < d_old; i += P) {
+    const int32_t v = adj[o + i];
+    const bool del = seg_find(keys, b, e, u, v, b1) >= 0;  // validated: a hit is a deletion
+    const double contrib = del ? -w_old : (w_new - w_old);
+    if (contrib != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], contrib);
+    if (j == 0 && (del || d_new != d_old)) stamp[v] = st;
+  }
+  for (int32_t i = b + p; i < e; i += P) {
+    const uint64_t k = keys[i];
+    if (!(k & 1ull)) continue;
+    const int32_t v = key_col(k, b1);
+    if (w_new != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], w_new);
+    if (j == 0) stamp[v] = st;
+  }
+}
+
+// ------------------------------------------------- structural apply
+// One wavefront per touched row: drop deleted entries (stable compaction in
+// place, or into a fresh arena slot when the row outgrows its capacity), then
+// append the inserted entries.
+__global__ void k_apply(const uint64_t *__restrict__ keys, const int32_t *__restrict__ seg,
+                        const int32_t *__restrict__ row, const int32_t *__restrict__ t_dold,
+                        const int32_t *__restrict__ t_dnew, int32_t *__restrict__ off, int32_t *__restrict__ len,
+                        int32_t *__restrict__ cap, int32_t *__restrict__ adj, Ctl *ctl, int orient, int b1,
+                        int64_t e_cap) {
+  if (ctl->err) return;
+  const int lane = threadIdx.x % RWR_WAVE;
+  const int32_t t = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE;
+  if (t >= ctl->nT[orient]) return;
+  const int32_t u = row[t], b = seg[t], e = seg[t + 1];
+  const int32_t d_old = t_dold[t], d_new = t_dnew[t];
+  const int32_t o = off[u];
+  int32_t base = o;
+  int32_t ncap = cap[u];
+  const bool move = d_new > ncap;
+  if (move) {
+    ncap = grown_cap(d_new);
+    unsigned long long pos = 0;
+    if (lane == 0) pos = atomicAdd((unsigned long long *)&ctl->tail[orient], (unsigned long long)ncap);
+    pos = (unsigned long long)__shfl((long long)pos, 0, RWR_WAVE);
+    if ((int64_t)pos + ncap > e_cap) {
+      // the host sizes the arena from the validated demand; never write past it
+      if (lane == 0) atomicCAS(&ctl->prop_err, 0, ERR_ENOMEM);
+      return;
+    }
+    base = (int32_t)pos;
+  }
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (RWR_WAVE - lane));
+  int32_t w = 0;
+  for (int32_t i0 = 0; i0 < d_old; i0 += RWR_WAVE) {
+    const int32_t i = i0 + lane;
+    int32_t v = -1;
+    bool keep = false;
+    if (i < d_old) {
+      v = adj[o + i];
+      keep = seg_find(keys, b, e, u, v, b1) < 0;
+    }
+    const uint64_t m = __ballot(keep);
+    if (keep) adj[base + w + __popcll(m & lt_mask)] = v;
+    w += __popcll(m);
+  }
+  for (int32_t i0 = b; i0 < e; i0 += RWR_WAVE) {
+    const int32_t i = i0 + lane;
+    const bool ins = i < e && (keys[i] & 1ull);
+    const uint64_t m = __ballot(ins);
+    if (ins) adj[base + w + __popcll(m & lt_mask)] = key_col(keys[i], b1);
+    w += __popcll(m);
+  }
+  if (lane == 0) {
+    len[u] = d_new;
+    if (move) {
+      off[u] = base;
+      cap[u] = ncap;
+    }
+  }
+}
+
+__global__ void k_reset_batch(Ctl *ctl, int demand_only) {
+  if (!demand_only) {
+    ctl->err = 0;
+    ctl->nT[0] = 0;
+    ctl->nT[1] = 0;
+  }
+  ctl->demand[0] = 0;
+  ctl->demand[1] = 0;
+  ctl->heavy_stale = 0;
+}
+
+// ------------------------------------------------- host launchers
+void launch_reset_batch(Ctl *ctl, int demand_only, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_batch, dim3(1), dim3(1), 0, st, ctl, demand_only);
+}
+
+void launch_make_keys(const int32_t *ins_s, const int32_t *ins_d, int64_t n_ins, const int32_t *del_s,
+                      const int32_t *del_d, int64_t n_del, int32_t n_nodes, int b1, int undirected, uint64_t *k_out,
+                      uint64_t *k_in, Ctl *ctl, hipStream_t st) {
+  const int64_t total = n_ins + n_del;
+  if (total == 0) return;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_make_keys, dim3(grid), dim3(256), 0, st, ins_s, ins_d, n_ins, del_s, del_d, n_del, n_nodes,
+                     b1, undirected, k_out, k_in, ctl);
+}
+
+void launch_sort_segment_small(uint64_t *k0, uint64_t *k1, int32_t n_keys, int b1, int32_t *seg0, int32_t *row0,
+                               int32_t *seg1, int32_t *row1, int orientations, Ctl *ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_sort_segment_small, dim3(orientations), dim3(1024), 0, st, k0, k1, n_keys, b1, seg0, row0,
+                     seg1, row1, ctl);
+}
+
+hipError_t sort_segment_large(uint64_t *keys, uint64_t *keys_alt, int32_t n_keys, int b1, int32_t *flags,
+                              int32_t *pos, int32_t *seg, int32_t *row, void *temp, size_t temp_bytes, Ctl *ctl,
+                              int orient, hipStream_t st) {
+  const int end_bit = std::min(64, 2 * b1 + 1);
+  size_t bytes = temp_bytes;
+  hipError_t err = hipcub::DeviceRadixSort::SortKeys(temp, bytes, keys, keys_alt, n_keys, 0, end_bit, st);
+  if (err != hipSuccess) return err;
+  const int grid = std::min((n_keys + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_heads, dim3(grid), dim3(256), 0, st, keys_alt, n_keys, b1, flags, ctl, orient == 0 ? 1 : 0);
+  bytes = temp_bytes;
+  err = hipcub::DeviceScan::ExclusiveSum(temp, bytes, flags, pos, n_keys, st);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_segments, dim3(grid), dim3(256), 0, st, keys_alt, n_keys, b1, flags, pos, seg, row, ctl,
+                     orient);
+  return hipMemcpyAsync(keys, keys_alt, sizeof(uint64_t) * (size_t)n_keys, hipMemcpyDeviceToDevice, st);
+}
+
+size_t sort_temp_bytes(int32_t n_keys) {
+  size_t a = 0, b = 0;
+  (void)hipcub::DeviceRadixSort::SortKeys((void *)nullptr, a, (uint64_t *)nullptr, (uint64_t *)nullptr, n_keys, 0, 64);
+  (void)hipcub::DeviceScan::ExclusiveSum((void *)nullptr, b, (int32_t *)nullptr, (int32_t *)nullptr, n_keys);
+  return std::max(a, b);
+}
+
+void launch_validate_plan(const uint64_t *keys, const int32_t *seg, const int32_t *row, const DevGraphView &g, int b1,
+                          int32_t *t_dold, int32_t *t_dnew, Ctl *ctl, int orient, int check, int heavy_limit,
+                          int32_t max_rows, hipStream_t st) {
+  if (max_rows <= 0) return;
+  const int waves_per_block = 4;
+  const int grid = (max_rows + waves_per_block - 1) / waves_per_block;
+  hipLaunchKernelGGL(k_validate_plan, dim3(grid), dim3(waves_per_block * RWR_WAVE), 0, st, keys, seg, row, g.off,
+                     g.len, g.cap, g.adj, b1, t_dold, t_dnew, ctl, orient, check, heavy_limit);
+}
+
+template <int S>
+static void offset_seed_s(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
+                          const int32_t *t_dnew, const DevGraphView &g, const double *r, double *ybuf, int32_t *stamp,
+                          int32_t *front0, Ctl *ctl, int b1, double c1, int32_t max_rows, hipStream_t st) {
+  const int waves_per_block = 4;
+  const int grid = (max_rows + waves_per_block - 1) / waves_per_block;
+  hipLaunchKernelGGL(k_offset_seed<S>, dim3(grid), dim3(waves_per_block * RWR_WAVE), 0, st, keys, seg, row, t_dold,
+                     t_dnew, g.off, g.adj, r, ybuf, stamp, front0, ctl, b1, c1);
+}
+
+void launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
+                        const int32_t *t_dnew, const DevGraphView &g, const double *r, double *ybuf, int32_t *stamp,
+                        int32_t *front0, Ctl *ctl, int b1, double c1, int32_t max_rows, hipStream_t st) {
+  if (max_rows <= 0) return;
+#define RWR_SEED_CASE(SS)                                                                                       \
+  case SS:                                                                                                      \
+    offset_seed_s<SS>(keys, seg, row, t_dold, t_dnew, g, r, ybuf, stamp, front0, ctl, b1, c1, max_rows, st); \
+    break;
+  switch (S) {
+    RWR_SEED_CASE(1)
+    RWR_SEED_CASE(2)
+    RWR_SEED_CASE(4)
+    RWR_SEED_CASE(8)
+    RWR_SEED_CASE(16)
+    RWR_SEED_CASE(32)
+    RWR_SEED_CASE(64)
+  }
+#undef RWR_SEED_CASE
+}
+
+void launch_apply(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
+                  const int32_t *t_dnew, const DevGraphView &g, Ctl *ctl, int orient, int b1, int32_t max_rows,
+                  int64_t e_cap, hipStream_t st) {
+  if (max_rows <= 0) return;
+  const int waves_per_block = 4;
+  const int grid = (max_rows + waves_per_block - 1) / waves_per_block;
+  hipLaunchKernelGGL(k_apply, dim3(grid), dim3(waves_per_block * RWR_WAVE), 0, st, keys, seg, row, t_dold, t_dnew,
+                     g.off, g.len, g.cap, g.adj, ctl, orient, b1, e_cap);
+}

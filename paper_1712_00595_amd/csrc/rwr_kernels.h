@@ -1,0 +1,117 @@
+// Launch interface of the HIP kernels (host side).  Each launcher enqueues
+// on the given stream and returns immediately.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "rwr_common.h"
+
+#define SMALL_SORT_MAX 4096
+
+// one orientation of the slack adjacency structure
+struct DevGraphView {
+  int32_t *off;
+  int32_t *len;
+  int32_t *cap;
+  int32_t *adj;
+  uint8_t *heavy;
+};
+
+// heavy-row schedule of the dense pull: rows whose in-degree exceeds the
+// light limit are split into chunks, each handled by a whole workgroup
+struct HeavyView {
+  const int32_t *item_row;   // work item -> heavy row index h
+  const int32_t *item_chunk; // work item -> chunk number within the row
+  const int32_t *rows;       // h -> node id
+  const int32_t *nchunks;    // h -> chunks planned for the row
+  double *acc;               // h*S + j -> partial sums (zero between sweeps)
+  int32_t *cnt;              // h -> arrived chunks (zero between sweeps)
+  int32_t n_items;
+  int32_t chunk;
+};
+
+// everything an iteration slot needs
+struct SlotArgs {
+  DevGraphView out;  // rows of A~ (push, out-degrees)
+  DevGraphView in;   // columns of A~ (pull)
+  HeavyView heavy;
+  double *r;
+  double *ybuf;
+  double *gbuf;
+  void *x[2];
+  int32_t *stamp;
+  int32_t *front[2];
+  int32_t *hfront;   // frontier nodes routed to the chunked push
+  const int32_t *seeds;
+  Ctl *ctl;
+  double *hist;
+  double *part;      // per-workgroup partials, then per-group partials
+  int64_t *part_i;
+  int32_t *gcnt;     // per-group arrival counters (zero between kernels)
+  int32_t n;
+  int32_t n_seeds;
+  double c;
+  int32_t grid_sparse;
+  int32_t grid_light;
+  int32_t light_lanes;  // lanes per row of the light pull (S > 1)
+  const int32_t *mp_rows;  // row partition of the single-column dense sweep
+  int32_t n_mp;            // workgroups of that partition
+};
+
+#define MP_EDGES 2048  // light in-edges per workgroup of the single-column sweep
+
+// ---- delta (k_delta.hip)
+void launch_make_keys(const int32_t *ins_s, const int32_t *ins_d, int64_t n_ins, const int32_t *del_s,
+                      const int32_t *del_d, int64_t n_del, int32_t n_nodes, int b1, int undirected, uint64_t *k_out,
+                      uint64_t *k_in, Ctl *ctl, hipStream_t st);
+void launch_sort_segment_small(uint64_t *k0, uint64_t *k1, int32_t n_keys, int b1, int32_t *seg0, int32_t *row0,
+                               int32_t *seg1, int32_t *row1, int orientations, Ctl *ctl, hipStream_t st);
+hipError_t sort_segment_large(uint64_t *keys, uint64_t *keys_alt, int32_t n_keys, int b1, int32_t *flags,
+                              int32_t *pos, int32_t *seg, int32_t *row, void *temp, size_t temp_bytes, Ctl *ctl,
+                              int orient, hipStream_t st);
+size_t sort_temp_bytes(int32_t n_keys);
+void launch_validate_plan(const uint64_t *keys, const int32_t *seg, const int32_t *row, const DevGraphView &g, int b1,
+                          int32_t *t_dold, int32_t *t_dnew, Ctl *ctl, int orient, int check, int heavy_limit,
+                          int32_t max_rows, hipStream_t st);
+void launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
+                        const int32_t *t_dnew, const DevGraphView &g, const double *r, double *ybuf, int32_t *stamp,
+                        int32_t *front0, Ctl *ctl, int b1, double c1, int32_t max_rows, hipStream_t st);
+void launch_apply(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
+                  const int32_t *t_dnew, const DevGraphView &g, Ctl *ctl, int orient, int b1, int32_t max_rows,
+                  int64_t e_cap, hipStream_t st);
+
+// ---- propagation (k_prop.hip); fp64 selects the propagation type
+void launch_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double eps, int32_t max_iters, int64_t dense_thresh,
+                      int64_t dense_nodes, hipStream_t st);
+void launch_seed_init(const SlotArgs &a, int S, hipStream_t st);
+void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st);
+// iteration slot k (computes x^(k)): sparse = push + epilogue, dense = pull
+void launch_sparse_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t st);
+void launch_dense_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t st);
+void launch_finish(const SlotArgs &a, int S, bool fp64, hipStream_t st);
+void launch_residual(const SlotArgs &a, int S, hipStream_t st);
+void launch_refine_init(const SlotArgs &a, int S, bool fp64, hipStream_t st);
+void launch_scores(const double *r, const Ctl *ctl, int S, int j, int32_t n, double *out, hipStream_t st);
+void launch_sigma_exact(const SlotArgs &a, int S, hipStream_t st);
+
+// ---- graph (k_graph.hip)
+void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st);
+void launch_fill_u8(uint8_t *p, int64_t count, uint8_t v, hipStream_t st);
+void launch_fill_f64(double *p, int64_t count, double v, hipStream_t st);
+void launch_zero_bytes(void *p, size_t bytes, hipStream_t st);
+size_t build_temp_bytes(int64_t m, int32_t n);
+hipError_t build_phase1(const int32_t *rows, const int32_t *cols, int64_t m, int32_t n, DevGraphView g, void *temp,
+                        size_t temp_bytes, uint64_t *keys, uint64_t *keys_alt, int32_t *sstart, Ctl *ctl,
+                        int64_t *used, hipStream_t st);
+void build_phase2(const uint64_t *keys, int64_t m, DevGraphView g, const int32_t *sstart, hipStream_t st);
+hipError_t relayout_offsets(const int32_t *len, int32_t n, int32_t *new_cap, int32_t *new_off, void *temp,
+                            size_t temp_bytes, int64_t *used, hipStream_t st);
+void launch_copy_rows(const DevGraphView &g, const int32_t *new_off, int32_t *new_adj, int32_t n, hipStream_t st);
+hipError_t export_rows(const DevGraphView &g, int32_t n, int32_t *out_src, int32_t *out_dst, int32_t *pos, void *temp,
+                       size_t temp_bytes, hipStream_t st);
+void launch_mark_heavy(const int32_t *len, int32_t n, int32_t limit, uint8_t *flags, int32_t *sel,
+                       int32_t *sel_count, hipStream_t st);
+void launch_gather_i32(const int32_t *src, const int32_t *idx, int32_t count, int32_t *out, hipStream_t st);
+void launch_reset_batch(Ctl *ctl, int demand_only, hipStream_t st);

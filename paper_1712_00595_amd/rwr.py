@@ -1,0 +1,320 @@
+"""Python binding of the HIP dynamic-RWR library (``librwr.so``).
+
+Argument marshalling only: every step of the update runs in the library's HIP
+kernels.  Arrays may be numpy arrays (host) or torch CUDA tensors (device);
+the library must have been built (``__graft_entry__.build()``) -- there is no
+fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librwr.so")
+
+STATUS = {
+    0: "RWR_OK",
+    -1: "RWR_EINVAL",
+    -2: "RWR_ENOMEM",
+    -3: "RWR_EHIP",
+    -4: "RWR_EEXIST",
+    -5: "RWR_ENOENT",
+    -6: "RWR_ENOCONV",
+    -7: "RWR_ENUMERIC",
+    -8: "RWR_ESTATE",
+}
+
+EXPORTED = [
+    "rwr_config_default",
+    "rwr_build",
+    "rwr_update",
+    "rwr_refine",
+    "rwr_scores",
+    "rwr_graph_size",
+    "rwr_graph_export",
+    "rwr_last_norms",
+    "rwr_profile",
+    "rwr_profile_read",
+    "rwr_destroy",
+    "rwr_last_error",
+]
+
+
+class RwrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+        super().__init__(f"{self.name}: {msg}")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("c", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("err_budget", ctypes.c_double),
+        ("build_tol", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("undirected", ctypes.c_int32),
+        ("max_iters", ctypes.c_int32),
+        ("pull_ratio", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class BatchStruct(ctypes.Structure):
+    _fields_ = [
+        ("n_ins", ctypes.c_int64),
+        ("ins_src", ctypes.c_void_p),
+        ("ins_dst", ctypes.c_void_p),
+        ("n_del", ctypes.c_int64),
+        ("del_src", ctypes.c_void_p),
+        ("del_dst", ctypes.c_void_p),
+        ("n_new_nodes", ctypes.c_int32),
+        ("n_del_nodes", ctypes.c_int32),
+        ("del_nodes", ctypes.c_void_p),
+        ("on_device", ctypes.c_int32),
+    ]
+
+
+class StatsStruct(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("dense_iters", ctypes.c_int32),
+        ("refined", ctypes.c_int32),
+        ("checked", ctypes.c_int32),
+        ("visited_edges", ctypes.c_int64),
+        ("touched_rows", ctypes.c_int64),
+        ("q_off_l1", ctypes.c_double),
+        ("last_x_l1", ctypes.c_double),
+        ("err_bound", ctypes.c_double),
+        ("residual_l1", ctypes.c_double),
+        ("ms_total", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load ``librwr.so``; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.rwr_config_default.argtypes = [ctypes.POINTER(Config)]
+    L.rwr_build.argtypes = [ctypes.POINTER(Config), i32, i64, p, p, i32, p, i32, ctypes.POINTER(p)]
+    L.rwr_update.argtypes = [p, ctypes.POINTER(BatchStruct), ctypes.POINTER(StatsStruct)]
+    L.rwr_refine.argtypes = [p, ctypes.POINTER(StatsStruct)]
+    L.rwr_scores.argtypes = [p, i32, p, i64, i32]
+    L.rwr_graph_size.argtypes = [p, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    L.rwr_graph_export.argtypes = [p, p, p, i64, ctypes.POINTER(i64), p]
+    L.rwr_last_norms.argtypes = [p, i32, p, i32, ctypes.POINTER(i32)]
+    L.rwr_profile.argtypes = [p, i32]
+    L.rwr_profile_read.argtypes = [p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), ctypes.POINTER(i64), i32]
+    L.rwr_destroy.argtypes = [p]
+    L.rwr_destroy.restype = None
+    L.rwr_last_error.argtypes = [p]
+    L.rwr_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        f = getattr(L, name)
+        if name not in ("rwr_destroy", "rwr_last_error"):
+            f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+class _Arr:
+    """Pointer to an int32 array: numpy on the host or a torch CUDA tensor."""
+
+    def __init__(self, a, on_device: bool):
+        if a is None:
+            self.keep = None
+            self.ptr = None
+            self.n = 0
+        elif on_device:
+            import torch
+
+            t = a if a.dtype == torch.int32 else a.to(torch.int32)
+            self.keep = t.contiguous()
+            self.ptr = self.keep.data_ptr()
+            self.n = self.keep.numel()
+        else:
+            self.keep = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+            self.ptr = self.keep.ctypes.data
+            self.n = int(self.keep.shape[0])
+
+
+def _check(lib, ctx, code: int):
+    if code != 0:
+        msg = lib.rwr_last_error(ctx)
+        raise RwrError(code, msg.decode() if msg else "")
+
+
+@dataclasses.dataclass
+class Update:
+    ins_src: object = None
+    ins_dst: object = None
+    del_src: object = None
+    del_dst: object = None
+    n_new_nodes: int = 0
+
+
+class Context:
+    """One dynamic-RWR context on the current GPU."""
+
+    def __init__(
+        self,
+        n: int,
+        src,
+        dst,
+        seeds,
+        *,
+        c: float = 0.15,
+        eps: float = 1e-9,
+        err_budget: float = 0.0,
+        build_tol: float = 0.0,
+        precision: str = "fp32",
+        undirected: bool = False,
+        max_iters: int = 10000,
+        pull_ratio: int = 0,
+        stream: Optional[int] = None,
+    ):
+        self._lib = load_library()
+        self._ctx = ctypes.c_void_p(None)
+        cfg = Config()
+        self._lib.rwr_config_default(ctypes.byref(cfg))
+        cfg.c = c
+        cfg.eps = eps
+        cfg.err_budget = err_budget
+        cfg.build_tol = build_tol
+        cfg.precision = {"fp32": 0, "fp64": 1}[precision]
+        cfg.undirected = 1 if undirected else 0
+        cfg.max_iters = max_iters
+        cfg.pull_ratio = pull_ratio
+        cfg.stream = stream
+        on_dev = _is_torch(src)
+        s = _Arr(src, on_dev)
+        d = _Arr(dst, on_dev)
+        sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.int32))
+        out = ctypes.c_void_p(None)
+        code = self._lib.rwr_build(
+            ctypes.byref(cfg), int(n), s.n, s.ptr, d.ptr, int(sd.shape[0]), sd.ctypes.data, 1 if on_dev else 0,
+            ctypes.byref(out),
+        )
+        _check(self._lib, None, code)
+        self._ctx = out
+        self.n_seeds = int(sd.shape[0])
+        self.seeds = sd.copy()
+        self.c = c
+        self.eps = eps
+
+    # -- lifetime
+    def close(self):
+        if self._ctx:
+            self._lib.rwr_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- updates
+    def update(self, ins_src=None, ins_dst=None, del_src=None, del_dst=None, n_new_nodes: int = 0) -> dict:
+        on_dev = any(_is_torch(a) for a in (ins_src, ins_dst, del_src, del_dst) if a is not None)
+        a = [_Arr(x, on_dev) for x in (ins_src, ins_dst, del_src, del_dst)]
+        if a[0].n != a[1].n or a[2].n != a[3].n:
+            raise ValueError("source and destination arrays differ in length")
+        b = BatchStruct()
+        b.n_ins = a[0].n
+        b.ins_src, b.ins_dst = a[0].ptr, a[1].ptr
+        b.n_del = a[2].n
+        b.del_src, b.del_dst = a[2].ptr, a[3].ptr
+        b.n_new_nodes = int(n_new_nodes)
+        b.n_del_nodes = 0
+        b.del_nodes = None
+        b.on_device = 1 if on_dev else 0
+        st = StatsStruct()
+        code = self._lib.rwr_update(self._ctx, ctypes.byref(b), ctypes.byref(st))
+        _check(self._lib, self._ctx, code)
+        return st.as_dict()
+
+    def update_batch(self, batch) -> dict:
+        return self.update(batch.ins_src, batch.ins_dst, batch.del_src, batch.del_dst, batch.n_new_nodes)
+
+    def refine(self) -> dict:
+        st = StatsStruct()
+        _check(self._lib, self._ctx, self._lib.rwr_refine(self._ctx, ctypes.byref(st)))
+        return st.as_dict()
+
+    # -- queries
+    @property
+    def n(self) -> int:
+        n = ctypes.c_int32(0)
+        m = ctypes.c_int64(0)
+        _check(self._lib, self._ctx, self._lib.rwr_graph_size(self._ctx, ctypes.byref(n), ctypes.byref(m)))
+        return n.value
+
+    def scores(self, j: int = 0) -> np.ndarray:
+        out = np.zeros(self.n, dtype=np.float64)
+        _check(self._lib, self._ctx, self._lib.rwr_scores(self._ctx, int(j), out.ctypes.data, out.shape[0], 0))
+        return out
+
+    def scores_device(self, j: int, out) -> None:
+        """Write column j into a float64 CUDA tensor of at least n elements."""
+        _check(self._lib, self._ctx, self._lib.rwr_scores(self._ctx, int(j), out.data_ptr(), out.numel(), 1))
+
+    def export(self):
+        m = ctypes.c_int64(0)
+        n = self.n
+        deg = np.zeros(n, dtype=np.int32)
+        _check(self._lib, self._ctx,
+               self._lib.rwr_graph_export(self._ctx, None, None, 0, ctypes.byref(m), deg.ctypes.data))
+        src = np.zeros(m.value, dtype=np.int32)
+        dst = np.zeros(m.value, dtype=np.int32)
+        _check(self._lib, self._ctx,
+               self._lib.rwr_graph_export(self._ctx, src.ctypes.data, dst.ctypes.data, m.value, ctypes.byref(m),
+                                          None))
+        return src, dst, deg
+
+    def profile(self, enable: bool = True) -> None:
+        _check(self._lib, self._ctx, self._lib.rwr_profile(self._ctx, 1 if enable else 0))
+
+    def profile_read(self, reset: bool = False) -> dict:
+        ms = ctypes.c_double(0.0)
+        sweeps = ctypes.c_int64(0)
+        idle = ctypes.c_int64(0)
+        _check(self._lib, self._ctx, self._lib.rwr_profile_read(self._ctx, ctypes.byref(ms), ctypes.byref(sweeps),
+                                                                ctypes.byref(idle), 1 if reset else 0))
+        return {"dense_ms": ms.value, "dense_sweeps": sweeps.value, "idle_launches": idle.value}
+
+    def last_norms(self, j: int = 0) -> np.ndarray:
+        ln = ctypes.c_int32(0)
+        self._lib.rwr_last_norms(self._ctx, int(j), None, 0, ctypes.byref(ln))
+        out = np.zeros(ln.value, dtype=np.float64)
+        _check(self._lib, self._ctx,
+               self._lib.rwr_last_norms(self._ctx, int(j), out.ctypes.data, ln.value, ctypes.byref(ln)))
+        return out

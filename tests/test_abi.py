@@ -1,0 +1,67 @@
+"""The C-ABI library loads and exports every entry point that include/rwr.h
+declares (no GPU needed: nothing here launches device work)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1712_00595_amd as pkg
+from paper_1712_00595_amd import rwr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rwr.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rwr_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_list():
+    assert _declared() == sorted(rwr.EXPORTED)
+
+
+def test_every_declared_symbol_is_exported():
+    L = pkg.load_library()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_struct_layouts_match_header():
+    # field order and sizes mirror rwr.h; 8-byte aligned structs
+    assert ctypes.sizeof(rwr.Config) == 8 * 4 + 4 * 4 + 8
+    assert ctypes.sizeof(rwr.BatchStruct) == 8 + 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
+    assert ctypes.sizeof(rwr.StatsStruct) == 4 * 4 + 8 * 2 + 8 * 5
+
+
+def test_config_default_and_host_side_rejection():
+    L = pkg.load_library()
+    cfg = rwr.Config()
+    assert L.rwr_config_default(ctypes.byref(cfg)) == 0
+    assert cfg.c == 0.15 and cfg.eps == 1e-9 and cfg.precision == 0 and cfg.max_iters == 10000
+    out = ctypes.c_void_p(None)
+    # invalid arguments are rejected before any device call
+    seeds = (ctypes.c_int32 * 1)(0)
+    assert L.rwr_build(ctypes.byref(cfg), 0, 0, None, None, 1, seeds, 0, ctypes.byref(out)) == -1
+    assert L.rwr_build(ctypes.byref(cfg), 10, 0, None, None, 0, seeds, 0, ctypes.byref(out)) == -1
+    bad = (ctypes.c_int32 * 1)(11)
+    assert L.rwr_build(ctypes.byref(cfg), 10, 0, None, None, 1, bad, 0, ctypes.byref(out)) == -1
+    assert b"seed" in L.rwr_last_error(None)
+    cfg.c = 1.5
+    assert L.rwr_build(ctypes.byref(cfg), 10, 0, None, None, 1, seeds, 0, ctypes.byref(out)) == -1
+    assert L.rwr_update(None, None, None) == -1
+    L.rwr_destroy(None)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(ImportError):
+        rwr.load_library.__wrapped__ if hasattr(rwr.load_library, "__wrapped__") else None
+        saved = rwr._lib
+        rwr._lib = None
+        try:
+            rwr.load_library(str(tmp_path / "absent.so"))
+        finally:
+            rwr._lib = saved

@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs."""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.core import RENORM_ALWAYS
+from synth import EdgeSetModel, rmat_graph
+from synth.stream import Batch, mixed_batch, single_edge_stream
+
+pytestmark = pytest.mark.gpu
+
+rwr = pytest.importorskip("paper_1712_00595_amd.rwr")
+
+
+def _ctx(g, seeds, **kw):
+    return rwr.Context(g.n, g.src, g.dst, seeds, **kw)
+
+
+def _l1(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).sum())
+
+
+def _batch(rng, n, src, dst, n_ins, n_del, n_new=0):
+    model = EdgeSetModel(n, src, dst)
+    return mixed_batch(rng, model, n_ins, n_del, n_new_nodes=n_new)
+
+
+# ---------------------------------------------------------------- static build
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n_seeds", [1, 3])
+def test_static_build_matches_oracle(prec, n_seeds):
+    print(f"[static] prec={prec} seeds={n_seeds}", flush=True)
+    g = rmat_graph(10, 6000, dead_end_self_loops=(n_seeds == 1))
+    seeds = np.array([int(np.argmax(g.out_degree()))] + [5, 77][: n_seeds - 1], np.int32)
+    tol = 1e-12
+    with _ctx(g, seeds, c=0.15, eps=1e-10, precision=prec, build_tol=tol) as ctx:
+        for j, s in enumerate(seeds):
+            r = ctx.scores(j)
+            ref = oracle.rwr_static(g.n, g.src, g.dst, int(s), 0.15)
+            assert _l1(r, ref) < tol + 1e-13
+
+
+# ---------------------------------------------------- one exact batch (FP64)
+
+def test_rmat13_one_batch_exact_fp64():
+    print("[rmat13 exact]", flush=True)
+    from synth.configs import RMAT13_ONE_BATCH, one_batch_rmat13
+
+    w = RMAT13_ONE_BATCH
+    g = w.graph()
+    seeds = w.seeds(g)
+    model = w.model(g)
+    b = one_batch_rmat13(model)
+    with _ctx(g, seeds, c=w.c, eps=1e-14, precision="fp64", build_tol=1e-13, err_budget=4e-13) as ctx:
+        r0 = ctx.scores(0)
+        ref0 = oracle.rwr_static(g.n, g.src, g.dst, int(seeds[0]), w.c)
+        assert _l1(r0, ref0) < 1e-12
+        st = ctx.update_batch(b)
+        n2, s2, d2 = oracle.apply_batch(g.n, g.src, g.dst, b)
+        ref = oracle.rwr_static(n2, s2, d2, int(seeds[0]), w.c)
+        r = ctx.scores(0)
+        assert _l1(r, ref) < 1e-12, st
+        # structure after the batch equals G + Delta G
+        es, ed, deg = ctx.export()
+        assert set(zip(es.tolist(), ed.tolist())) == set(zip(s2.tolist(), d2.tolist()))
+        assert np.array_equal(deg, np.bincount(s2, minlength=n2))
+        # per-iteration norms against the Algorithm 1 twin started from the
+        # oracle's exact scores
+        twin = oracle.osp((g.n, g.src, g.dst), (n2, s2, d2), ref0, w.c, 1e-14, renorm=RENORM_ALWAYS)
+        norms = ctx.last_norms(0)
+        assert norms.shape[0] == twin["norms"].shape[0]
+        assert np.allclose(norms, twin["norms"], rtol=1e-9, atol=1e-17)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_twin_norms_and_iterations(prec):
+    print(f"[twin] prec={prec}", flush=True)
+    g = rmat_graph(12, 40000, dead_end_self_loops=True)
+    s = int(np.argmax(g.out_degree()))
+    rng = np.random.default_rng(7)
+    b = _batch(rng, g.n, g.src, g.dst, 20, 20)
+    eps = 1e-9
+    with _ctx(g, [s], eps=eps, precision=prec, build_tol=1e-13) as ctx:
+        r_old = oracle.rwr_static(g.n, g.src, g.dst, s, 0.15)
+        ctx.update_batch(b)
+        n2, s2, d2 = oracle.apply_batch(g.n, g.src, g.dst, b)
+        twin = oracle.osp((g.n, g.src, g.dst), (n2, s2, d2), r_old, 0.15, eps, renorm=RENORM_ALWAYS)
+        norms = ctx.last_norms(0)
+        k = min(norms.shape[0], twin["norms"].shape[0])
+        assert abs(norms.shape[0] - twin["norms"].shape[0]) <= (0 if prec == "fp64" else 1)
+        rtol = 1e-9 if prec == "fp64" else 2e-5
+        assert np.allclose(norms[:k], twin["norms"][:k], rtol=rtol, atol=1e-18)
+        ref = oracle.rwr_static(n2, s2, d2, s, 0.15)
+        assert _l1(ctx.scores(0), ref) <= 2 * eps / 0.15
+
+
+# --------------------------------------------------------------- error paths
+
+def test_invalid_batches_leave_state_unchanged():
+    print("[errors]", flush=True)
+    g = rmat_graph(9, 3000, dead_end_self_loops=True)
+    s = int(np.argmax(g.out_degree()))
+    with _ctx(g, [s], eps=1e-10, precision="fp64") as ctx:
+        before = ctx.scores(0)
+        e_src, e_dst = int(g.src[0]), int(g.dst[0])
+        cases = [
+            ("RWR_EEXIST", dict(ins_src=[e_src], ins_dst=[e_dst])),
+            ("RWR_ENOENT", dict(del_src=[e_dst], del_dst=[e_dst]) if e_dst != e_src else None),
+            ("RWR_EINVAL", dict(ins_src=[0], ins_dst=[g.n + 5])),
+            ("RWR_EINVAL", dict(ins_src=[1, 1], ins_dst=[2, 2])),
+            ("RWR_EINVAL", dict(ins_src=[e_src], ins_dst=[e_dst], del_src=[e_src], del_dst=[e_dst])),
+        ]
+        for name, kw in cases:
+            if kw is None:
+                continue
+            if name == "RWR_ENOENT":
+                # pick a pair that is certainly absent
+                model = EdgeSetModel(g.n, g.src, g.dst)
+                u, v = 0, 1
+                while model.has(u, v) or u == v:
+                    v += 1
+                kw = dict(del_src=[u], del_dst=[v])
+            with pytest.raises(rwr.RwrError) as ei:
+                ctx.update(**kw)
+            assert ei.value.name == name, (name, kw)
+        assert np.array_equal(ctx.scores(0), before)
+        es, ed, _ = ctx.export()
+        assert set(zip(es.tolist(), ed.tolist())) == set(zip(g.src.tolist(), g.dst.tolist()))
+
+
+def test_new_node_with_only_out_edges():
+    print("[new node]", flush=True)
+    g = rmat_graph(9, 3000, dead_end_self_loops=True)
+    s = int(np.argmax(g.out_degree()))
+    with _ctx(g, [s], eps=1e-12, precision="fp64", build_tol=1e-13) as ctx:
+        before = ctx.scores(0)
+        st = ctx.update(ins_src=[g.n, g.n], ins_dst=[3, 9], n_new_nodes=1)
+        after = ctx.scores(0)
+        assert after.shape[0] == g.n + 1
+        assert after[g.n] == 0.0
+        assert np.abs(after[: g.n] - before).max() < 1e-15
+        assert st["q_off_l1"] == 0.0
+
+
+# ------------------------------------------------------------ streams / modes
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-9])
+def test_single_edge_stream_within_gate(eps):
+    print(f"[stream] eps={eps}", flush=True)
+    g = rmat_graph(12, 40000, dead_end_self_loops=True)
+    s = int(np.argmax(g.out_degree()))
+    model = EdgeSetModel(g.n, g.src, g.dst)
+    stream = single_edge_stream(model, 60, seed=4)
+    gate = 2 * eps / 0.15
+    n, src, dst = g.n, g.src, g.dst
+    with _ctx(g, [s], eps=eps, precision="fp32") as ctx:
+        for t, b in enumerate(stream):
+            st = ctx.update_batch(b)
+            n, src, dst = oracle.apply_batch(n, src, dst, b)
+            assert st["err_bound"] <= gate
+            if t in (0, 9, 59):
+                ref = oracle.rwr_static(n, src, dst, s, 0.15)
+                err = _l1(ctx.scores(0), ref)
+                assert err <= gate, (t, err, st)
+                assert err <= st["err_bound"] + 1e-13
+
+
+def test_many_seeds_padded_columns():
+    print("[seeds40]", flush=True)
+    g = rmat_graph(10, 8000, dead_end_self_loops=True)
+    from synth.rmat import sample_seeds
+
+    seeds = sample_seeds(g, 40, seed=3)
+    rng = np.random.default_rng(3)
+    b = _batch(rng, g.n, g.src, g.dst, 30, 30, n_new=2)
+    eps = 1e-8
+    with _ctx(g, seeds, eps=eps, precision="fp32") as ctx:
+        ctx.update_batch(b)
+        n2, s2, d2 = oracle.apply_batch(g.n, g.src, g.dst, b)
+        for j in (0, 17, 39):
+            ref = oracle.rwr_static(n2, s2, d2, int(seeds[j]), 0.15)
+            assert _l1(ctx.scores(j), ref) <= 2 * eps / 0.15
+
+
+def test_undirected_mode():
+    print("[undirected]", flush=True)
+    g = rmat_graph(10, 5000, undirected=True)
+    seeds = np.array([int(np.argmax(g.out_degree())), 11], np.int32)
+    c = 0.05
+    model = EdgeSetModel(g.n, g.pair_u, g.pair_v, undirected=True)
+    rng = np.random.default_rng(5)
+    b = mixed_batch(rng, model, 50, 50, n_new_nodes=3)
+    with rwr.Context(g.n, g.pair_u, g.pair_v, seeds, c=c, eps=1e-12, precision="fp64", undirected=True,
+                     build_tol=1e-12) as ctx:
+        ctx.update_batch(b)
+        n2, s2, d2 = oracle.apply_batch(g.n, g.src, g.dst, b, undirected=True)
+        for j, s in enumerate(seeds):
+            ref = oracle.rwr_static(n2, s2, d2, int(s), c)
+            assert _l1(ctx.scores(j), ref) < 1e-10
+
+
+def test_large_batch_device_sort_path():
+    print("[large batch]", flush=True)
+    g = rmat_graph(14, 200000, dead_end_self_loops=True)
+    s = int(np.argmax(g.out_degree()))
+    rng = np.random.default_rng(9)
+    b = _batch(rng, g.n, g.src, g.dst, 3000, 3000, n_new=20)
+    with _ctx(g, [s], eps=1e-13, precision="fp64", build_tol=1e-12, err_budget=1e-11) as ctx:
+        ctx.update_batch(b)
+        n2, s2, d2 = oracle.apply_batch(g.n, g.src, g.dst, b)
+        ref = oracle.rwr_static(n2, s2, d2, s, 0.15)
+        assert _l1(ctx.scores(0), ref) < 1e-11
+        es, ed, _ = ctx.export()
+        assert set(zip(es.tolist(), ed.tolist())) == set(zip(s2.tolist(), d2.tolist()))
+
+
+def test_heavy_row_chunks(monkeypatch):
+    print("[heavy]", flush=True)
+    monkeypatch.setenv("RWR_HEAVY_LIMIT", "8")
+    monkeypatch.setenv("RWR_HEAVY_CHUNK", "16")
+    g = rmat_graph(11, 20000, dead_end_self_loops=True)
+    seeds = np.array([int(np.argmax(g.out_degree())), 3], np.int32)
+    rng = np.random.default_rng(1)
+    b = _batch(rng, g.n, g.src, g.dst, 100, 100)
+    for prec in ("fp64", "fp32"):
+        with _ctx(g, seeds, eps=1e-12, precision=prec, build_tol=1e-12, err_budget=1e-11) as ctx:
+            for j, sd in enumerate(seeds):
+                ref = oracle.rwr_static(g.n, g.src, g.dst, int(sd), 0.15)
+                assert _l1(ctx.scores(j), ref) < 1e-11
+            ctx.update_batch(b)
+            n2, s2, d2 = oracle.apply_batch(g.n, g.src, g.dst, b)
+            for j, sd in enumerate(seeds):
+                ref = oracle.rwr_static(n2, s2, d2, int(sd), 0.15)
+                assert _l1(ctx.scores(j), ref) < 1e-11
+
+
+def test_relayout_when_arena_fills():
+    print("[relayout]", flush=True)
+    rng = np.random.default_rng(2)
+    g = rmat_graph(15, 60000, dead_end_self_loops=True)
+    n = g.n
+    s = int(np.argmax(g.out_degree()))
+    src, dst = g.src, g.dst
+    with _ctx(g, [s], eps=1e-12, precision="fp64", build_tol=1e-12, err_budget=1e-10) as ctx:
+        hub = 7
+        for rnd in range(3):
+            model = EdgeSetModel(n, src, dst)
+            # 3 x 9000 new out-edges of one row (of 32768 possible targets):
+            # the row outgrows its slack, is moved to the arena twice, and the
+            # third move exceeds the arena, which forces a relayout
+            free = np.array([v for v in range(n) if v != hub and not model.has(hub, v)], np.int64)
+            targets = rng.choice(free, size=9000, replace=False).tolist()
+            b = Batch(ins_src=np.full(len(targets), hub, np.int32), ins_dst=np.array(targets, np.int32),
+                      del_src=np.zeros(0, np.int32), del_dst=np.zeros(0, np.int32))
+            ctx.update_batch(b)
+            n, src, dst = oracle.apply_batch(n, src, dst, b)
+        es, ed, deg = ctx.export()
+        assert set(zip(es.tolist(), ed.tolist())) == set(zip(src.tolist(), dst.tolist()))
+        ref = oracle.rwr_static(n, src, dst, s, 0.15)
+        assert _l1(ctx.scores(0), ref) < 1e-10
