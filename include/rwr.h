@@ -64,6 +64,9 @@ typedef struct rwr_config {
   int32_t max_iters; /* per-update iteration guard; <= 0 selects 10000                  */
   int32_t pull_ratio;/* switch from sparse push to dense pull once the frontier's
                         out-edges exceed m/pull_ratio; <= 0 selects the tuned default   */
+  int32_t reorder;   /* 1: number nodes internally by descending out-degree (ids at
+                        this interface are unchanged); 0: keep the caller's order      */
+  int32_t reserved;  /* must be 0                                                       */
   void *stream;      /* hipStream_t to run on; NULL: the library creates its own        */
 } rwr_config;
 
@@ -101,7 +104,8 @@ typedef struct rwr_stats {
   double ms_total;        /* wall time of the call (host clock)                            */
 } rwr_stats;
 
-/* Fill *cfg with defaults: c = 0.15, eps = 1e-9, FP32 propagation, directed. */
+/* Fill *cfg with defaults: c = 0.15, eps = 1e-9, FP32 propagation, directed,
+ * internal degree ordering on. */
 rwr_status rwr_config_default(rwr_config *cfg);
 
 /* Build a context: copy the graph (n nodes, m edges (src[e], dst[e]); in

@@ -54,7 +54,9 @@ struct rwr_ctx {
   int64_t m = 0;  // stored directed edges
   int32_t n_seeds = 0, S = 1;
   std::vector<int32_t> seeds_h;
-  int32_t *seeds_d = nullptr;
+  int32_t *seeds_d = nullptr;      // internal ids
+  int32_t *perm = nullptr;         // external id -> internal id
+  int32_t *inv = nullptr;          // internal id -> external id
   bool undirected = false, fp64 = false;
   Orientation g[2];
   double *r = nullptr, *ybuf = nullptr, *gbuf = nullptr;
@@ -421,6 +423,9 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
   RWR_TRY(regrow((void **)&c->front[1], 4, 1));
   RWR_TRY(regrow((void **)&c->hfront, 4, 1));
   RWR_TRY(regrow((void **)&c->sel, 4, 2));
+  RWR_TRY(regrow((void **)&c->perm, 4, 1));
+  RWR_TRY(regrow((void **)&c->inv, 4, 1));
+  launch_identity(c->perm, c->inv, old_cap, new_cap, c->stream);
   c->n_cap = new_cap;
   tune_defaults(c);
   RWR_TRY(plan_heavy(c));
@@ -674,6 +679,8 @@ rwr_status rwr_config_default(rwr_config *cfg) {
   cfg->undirected = 0;
   cfg->max_iters = 10000;
   cfg->pull_ratio = 0;
+  cfg->reorder = 1;
+  cfg->reserved = 0;
   cfg->stream = nullptr;
   return RWR_OK;
 }
@@ -707,7 +714,6 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
     H2D(c, c->ctl, &init, sizeof(Ctl));
   }
   RWR_TRY(alloc_zero(c, &c->seeds_d, RWR_MAX_COLS));
-  H2D(c, c->seeds_d, seeds, sizeof(int32_t) * n_seeds);
 
   // edge list on the device, both directions for undirected graphs
   int32_t *src_d = nullptr, *dst_d = nullptr;
@@ -753,11 +759,47 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
     }
   }
   const bool own_edges = c->undirected || !on_device;
-  rwr_status s = build_orient(c, 0, src_d, dst_d, m2);
-  if (s == RWR_OK && !c->undirected) s = build_orient(c, 1, dst_d, src_d, m2);
+  // internal numbering: descending out-degree, or the caller's order
+  RWR_TRY(alloc_zero(c, &c->perm, c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->inv, c->n_cap));
+  int32_t *msrc = nullptr, *mdst = nullptr;
+  RWR_TRY(dev_alloc(c, (void **)&msrc, sizeof(int32_t) * std::max<int64_t>(1, m2)));
+  RWR_TRY(dev_alloc(c, (void **)&mdst, sizeof(int32_t) * std::max<int64_t>(1, m2)));
+  if (c->cfg.reorder) {
+    uint64_t *k1 = nullptr, *k2 = nullptr;
+    int32_t *deg = nullptr;
+    RWR_TRY(dev_alloc(c, (void **)&k1, sizeof(uint64_t) * c->n_cap));
+    RWR_TRY(dev_alloc(c, (void **)&k2, sizeof(uint64_t) * c->n_cap));
+    RWR_TRY(dev_alloc(c, (void **)&deg, sizeof(int32_t) * c->n_cap));
+    RWR_TRY(ensure_temp(c, build_temp_bytes(std::max<int64_t>(m2, c->n_cap), c->n_cap)));
+    HIP_TRY(c, build_relabel(src_d, m2, n, c->n_cap, c->perm, c->inv, deg, k1, k2, c->temp, c->temp_bytes,
+                             c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(k1);
+    (void)hipFree(k2);
+    (void)hipFree(deg);
+  } else {
+    launch_identity(c->perm, c->inv, 0, c->n_cap, c->stream);
+  }
+  launch_map_ids(src_d, m2, n, c->perm, msrc, c->stream);
+  launch_map_ids(dst_d, m2, n, c->perm, mdst, c->stream);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (own_edges) {
     (void)hipFree(src_d);
     (void)hipFree(dst_d);
+  }
+  rwr_status s = build_orient(c, 0, msrc, mdst, m2);
+  if (s == RWR_OK && !c->undirected) s = build_orient(c, 1, mdst, msrc, m2);
+  (void)hipFree(msrc);
+  (void)hipFree(mdst);
+  {
+    // seeds in internal ids
+    int32_t *tmp = nullptr;
+    RWR_TRY(dev_alloc(c, (void **)&tmp, sizeof(int32_t) * RWR_MAX_COLS));
+    H2D(c, tmp, seeds, sizeof(int32_t) * n_seeds);
+    launch_map_ids(tmp, n_seeds, n, c->perm, c->seeds_d, c->stream);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(tmp);
   }
   if (s != RWR_OK) return s;
   if (c->undirected) c->g[1] = c->g[0];
@@ -934,8 +976,8 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   const int norient = c->undirected ? 1 : 2;
   const int po = pull_orient(c);
   if (N > 0) {
-    launch_make_keys(ins_s, ins_d, b->n_ins, del_s, del_d, b->n_del, n_new, b1, c->undirected ? 1 : 0, c->keys[0],
-                     c->keys[1], c->ctl, c->stream);
+    launch_make_keys(ins_s, ins_d, b->n_ins, del_s, del_d, b->n_del, n_new, b1, c->undirected ? 1 : 0, c->perm,
+                     c->keys[0], c->keys[1], c->ctl, c->stream);
     if (nkeys <= SMALL_SORT_MAX) {
       launch_sort_segment_small(c->keys[0], c->keys[1], (int32_t)nkeys, b1, c->seg[0], c->row[0], c->seg[1],
                                 c->row[1], norient, c->ctl, c->stream);
@@ -1041,7 +1083,7 @@ rwr_status rwr_scores(rwr_ctx *c, int32_t j, double *out, int64_t cap, int32_t o
     return RWR_EINVAL;
   }
   double *dst = out_on_device ? out : c->gbuf;
-  launch_scores(c->r, c->ctl, c->S, j, c->n, dst, c->stream);
+  launch_scores(c->r, c->ctl, c->perm, c->S, j, c->n, dst, c->stream);
   if (!out_on_device) HIP_TRY(c, hipMemcpyAsync(out, c->gbuf, sizeof(double) * c->n, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return RWR_OK;
@@ -1056,13 +1098,15 @@ rwr_status rwr_graph_size(const rwr_ctx *c, int32_t *n, int64_t *m) {
 
 rwr_status rwr_graph_export(rwr_ctx *c, int32_t *src, int32_t *dst, int64_t cap, int64_t *m_out, int32_t *deg_out) {
   if (!c) return RWR_EINVAL;
-  std::vector<int32_t> len(c->n);
+  std::vector<int32_t> len(c->n), perm(c->n);
   D2H(c, len.data(), c->g[0].v.len, sizeof(int32_t) * c->n);
+  D2H(c, perm.data(), c->perm, sizeof(int32_t) * c->n);
   int64_t m = 0;
   for (int32_t v = 0; v < c->n; ++v) m += len[v];
   c->m = m;
   if (m_out) *m_out = m;
-  if (deg_out) std::memcpy(deg_out, len.data(), sizeof(int32_t) * c->n);
+  if (deg_out)
+    for (int32_t v = 0; v < c->n; ++v) deg_out[v] = len[perm[v]];
   if (!src || !dst) return RWR_OK;
   if (cap < m) {
     c->err = "export capacity below the edge count";
@@ -1073,7 +1117,7 @@ rwr_status rwr_graph_export(rwr_ctx *c, int32_t *src, int32_t *dst, int64_t cap,
   RWR_TRY(dev_alloc(c, (void **)&dd, sizeof(int32_t) * std::max<int64_t>(1, m)));
   RWR_TRY(dev_alloc(c, (void **)&pos, sizeof(int32_t) * c->n_cap));
   RWR_TRY(ensure_temp(c, build_temp_bytes(1, c->n_cap)));
-  HIP_TRY(c, export_rows(c->g[0].v, c->n, ds, dd, pos, c->temp, c->temp_bytes, c->stream));
+  HIP_TRY(c, export_rows(c->g[0].v, c->n, c->inv, ds, dd, pos, c->temp, c->temp_bytes, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   D2H(c, src, ds, sizeof(int32_t) * m);
   D2H(c, dst, dd, sizeof(int32_t) * m);
@@ -1127,6 +1171,8 @@ void rwr_destroy(rwr_ctx *c) {
   dev_free(c->sel_count);
   dev_free(c->mp_rows);
   dev_free(c->seeds_d);
+  dev_free(c->perm);
+  dev_free(c->inv);
   dev_free(c->b_dev);
   for (int o = 0; o < 2; ++o) {
     dev_free(c->keys[o]);

@@ -28,15 +28,15 @@ __device__ __forceinline__ int32_t key_col(uint64_t k, int b1) {
 // ---------------------------------------------------------------- keys
 __global__ void k_make_keys(const int32_t *__restrict__ ins_s, const int32_t *__restrict__ ins_d, int64_t n_ins,
                             const int32_t *__restrict__ del_s, const int32_t *__restrict__ del_d, int64_t n_del,
-                            int32_t n_nodes, int b1, int undirected, uint64_t *__restrict__ k_out,
-                            uint64_t *__restrict__ k_in, Ctl *ctl) {
+                            int32_t n_nodes, int b1, int undirected, const int32_t *__restrict__ perm,
+                            uint64_t *__restrict__ k_out, uint64_t *__restrict__ k_in, Ctl *ctl) {
   const int64_t total = n_ins + n_del;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const bool ins = i < n_ins;
-    const int32_t u = ins ? ins_s[i] : del_s[i - n_ins];
-    const int32_t v = ins ? ins_d[i] : del_d[i - n_ins];
+    const int32_t ue = ins ? ins_s[i] : del_s[i - n_ins];
+    const int32_t ve = ins ? ins_d[i] : del_d[i - n_ins];
     const uint64_t t = ins ? 1ull : 0ull;
-    if (u < 0 || u >= n_nodes || v < 0 || v >= n_nodes) {
+    if (ue < 0 || ue >= n_nodes || ve < 0 || ve >= n_nodes) {
       set_error(ctl, ERR_EINVAL);
       if (undirected) {
         k_out[2 * i] = KEY_PAD;
@@ -47,6 +47,7 @@ __global__ void k_make_keys(const int32_t *__restrict__ ins_s, const int32_t *__
       }
       continue;
     }
+    const int32_t u = perm[ue], v = perm[ve];  // internal ids
     if (undirected) {
       // a pair stands for both directed edges; a self-loop for one
       k_out[2 * i] = ((uint64_t)u << b1) | ((uint64_t)v << 1) | t;
@@ -375,13 +376,13 @@ void launch_reset_batch(Ctl *ctl, int demand_only, hipStream_t st) {
 }
 
 void launch_make_keys(const int32_t *ins_s, const int32_t *ins_d, int64_t n_ins, const int32_t *del_s,
-                      const int32_t *del_d, int64_t n_del, int32_t n_nodes, int b1, int undirected, uint64_t *k_out,
-                      uint64_t *k_in, Ctl *ctl, hipStream_t st) {
+                      const int32_t *del_d, int64_t n_del, int32_t n_nodes, int b1, int undirected,
+                      const int32_t *perm, uint64_t *k_out, uint64_t *k_in, Ctl *ctl, hipStream_t st) {
   const int64_t total = n_ins + n_del;
   if (total == 0) return;
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
   hipLaunchKernelGGL(k_make_keys, dim3(grid), dim3(256), 0, st, ins_s, ins_d, n_ins, del_s, del_d, n_del, n_nodes,
-                     b1, undirected, k_out, k_in, ctl);
+                     b1, undirected, perm, k_out, k_in, ctl);
 }
 
 void launch_sort_segment_small(uint64_t *k0, uint64_t *k1, int32_t n_keys, int b1, int32_t *seg0, int32_t *row0,

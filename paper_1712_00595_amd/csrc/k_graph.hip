@@ -165,28 +165,31 @@ hipError_t relayout_offsets(const int32_t *len, int32_t n, int32_t *new_cap, int
 }
 
 // ------------------------------------------------------------------ export
+// external ids via inv (internal -> external)
 __global__ void k_export(const int32_t *__restrict__ off, const int32_t *__restrict__ len,
                          const int32_t *__restrict__ adj, const int32_t *__restrict__ pos, int32_t n,
-                         int32_t *__restrict__ out_src, int32_t *__restrict__ out_dst) {
+                         const int32_t *__restrict__ inv, int32_t *__restrict__ out_src,
+                         int32_t *__restrict__ out_dst) {
   const int lane = threadIdx.x % RWR_WAVE;
   const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / RWR_WAVE;
   const int64_t nw = (int64_t)gridDim.x * blockDim.x / RWR_WAVE;
   for (int64_t v = w0; v < n; v += nw) {
     const int32_t o = off[v], d = len[v], p = pos[v];
+    const int32_t ev = inv[v];
     for (int32_t e = lane; e < d; e += RWR_WAVE) {
-      out_src[p + e] = (int32_t)v;
-      out_dst[p + e] = adj[o + e];
+      out_src[p + e] = ev;
+      out_dst[p + e] = inv[adj[o + e]];
     }
   }
 }
 
-hipError_t export_rows(const DevGraphView &g, int32_t n, int32_t *out_src, int32_t *out_dst, int32_t *pos, void *temp,
-                       size_t temp_bytes, hipStream_t st) {
+hipError_t export_rows(const DevGraphView &g, int32_t n, const int32_t *inv, int32_t *out_src, int32_t *out_dst,
+                       int32_t *pos, void *temp, size_t temp_bytes, hipStream_t st) {
   size_t bytes = temp_bytes;
   hipError_t err = hipcub::DeviceScan::ExclusiveSum(temp, bytes, g.len, pos, n, st);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_export, dim3(fill_grid((int64_t)n * RWR_WAVE)), dim3(256), 0, st, g.off, g.len, g.adj, pos, n,
-                     out_src, out_dst);
+                     inv, out_src, out_dst);
   return hipSuccess;
 }
 
@@ -213,4 +216,66 @@ __global__ void k_gather_i32(const int32_t *__restrict__ src, const int32_t *__r
 
 void launch_gather_i32(const int32_t *src, const int32_t *idx, int32_t count, int32_t *out, hipStream_t st) {
   if (count > 0) hipLaunchKernelGGL(k_gather_i32, dim3(fill_grid(count)), dim3(256), 0, st, src, idx, count, out);
+}
+
+// ------------------------------------------------------------------ relabel
+// Internal vertex order: descending out-degree (ties by id), so that the
+// entries gathered most often during a sweep are contiguous and stay in L2.
+__global__ void k_out_degree(const int32_t *__restrict__ src, int64_t m, int32_t *__restrict__ deg) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&deg[src[i]], 1);
+}
+
+__global__ void k_degree_keys(const int32_t *__restrict__ deg, int32_t n, uint64_t *__restrict__ keys) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    keys[v] = ((uint64_t)(uint32_t)(INT32_MAX - deg[v]) << 32) | (uint32_t)v;
+}
+
+__global__ void k_perm_from_keys(const uint64_t *__restrict__ keys, int32_t n, int32_t *__restrict__ perm,
+                                 int32_t *__restrict__ inv) {
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)(keys[r] & 0xffffffffull);
+    perm[v] = r;
+    inv[r] = v;
+  }
+}
+
+__global__ void k_identity(int32_t *__restrict__ a, int32_t *__restrict__ b, int32_t from, int32_t to) {
+  for (int32_t v = from + blockIdx.x * blockDim.x + threadIdx.x; v < to; v += gridDim.x * blockDim.x) {
+    a[v] = v;
+    b[v] = v;
+  }
+}
+
+// out[i] = perm[in[i]] for ids in range; ids out of range pass through (the
+// builder rejects them afterwards)
+__global__ void k_map_ids(const int32_t *__restrict__ in, int64_t m, int32_t n, const int32_t *__restrict__ perm,
+                          int32_t *__restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = in[i];
+    out[i] = (v >= 0 && v < n) ? perm[v] : v;
+  }
+}
+
+// perm/inv for n nodes ordered by out-degree; [n, n_cap) identity
+hipError_t build_relabel(const int32_t *src, int64_t m, int32_t n, int32_t n_cap, int32_t *perm, int32_t *inv,
+                         int32_t *deg_tmp, uint64_t *keys, uint64_t *keys_alt, void *temp, size_t temp_bytes,
+                         hipStream_t st) {
+  launch_fill_i32(deg_tmp, n, 0, st);
+  if (m > 0) hipLaunchKernelGGL(k_out_degree, dim3(fill_grid(m)), dim3(256), 0, st, src, m, deg_tmp);
+  hipLaunchKernelGGL(k_degree_keys, dim3(fill_grid(n)), dim3(256), 0, st, deg_tmp, n, keys);
+  size_t bytes = temp_bytes;
+  hipError_t err = hipcub::DeviceRadixSort::SortKeys(temp, bytes, keys, keys_alt, n, 0, 64, st);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_perm_from_keys, dim3(fill_grid(n)), dim3(256), 0, st, keys_alt, n, perm, inv);
+  if (n_cap > n) hipLaunchKernelGGL(k_identity, dim3(fill_grid(n_cap - n)), dim3(256), 0, st, perm, inv, n, n_cap);
+  return hipSuccess;
+}
+
+void launch_identity(int32_t *perm, int32_t *inv, int32_t from, int32_t to, hipStream_t st) {
+  if (to > from) hipLaunchKernelGGL(k_identity, dim3(fill_grid(to - from)), dim3(256), 0, st, perm, inv, from, to);
+}
+
+void launch_map_ids(const int32_t *in, int64_t m, int32_t n, const int32_t *perm, int32_t *out, hipStream_t st) {
+  if (m > 0) hipLaunchKernelGGL(k_map_ids, dim3(fill_grid(m)), dim3(256), 0, st, in, m, n, perm, out);
 }

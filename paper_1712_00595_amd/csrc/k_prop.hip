@@ -713,11 +713,12 @@ __global__ void k_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double ep
   }
 }
 
-__global__ void k_scores(const double *__restrict__ r, const Ctl *ctl, int S, int j, int32_t n,
-                         double *__restrict__ out) {
+// scores in external id order: out[v] = r[perm[v], j] / sigma_j
+__global__ void k_scores(const double *__restrict__ r, const Ctl *ctl, const int32_t *__restrict__ perm, int S, int j,
+                         int32_t n, double *__restrict__ out) {
   const double inv = 1.0 / ctl->sigma[j];
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    out[v] = r[v * S + j] * inv;
+    out[v] = r[(int64_t)perm[v] * S + j] * inv;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -849,7 +850,8 @@ void launch_sigma_exact(const SlotArgs &a, int S, hipStream_t st) {
   RWR_DISPATCH_S(S, hipLaunchKernelGGL(k_sigma<SS>, dim3(a.grid_light), dim3(BLOCK), 0, st, a));
 }
 
-void launch_scores(const double *r, const Ctl *ctl, int S, int j, int32_t n, double *out, hipStream_t st) {
+void launch_scores(const double *r, const Ctl *ctl, const int32_t *perm, int S, int j, int32_t n, double *out,
+                   hipStream_t st) {
   const int grid = std::max(1, std::min((n + 255) / 256, 2048));
-  hipLaunchKernelGGL(k_scores, dim3(grid), dim3(256), 0, st, r, ctl, S, j, n, out);
+  hipLaunchKernelGGL(k_scores, dim3(grid), dim3(256), 0, st, r, ctl, perm, S, j, n, out);
 }

@@ -64,8 +64,8 @@ struct SlotArgs {
 
 // ---- delta (k_delta.hip)
 void launch_make_keys(const int32_t *ins_s, const int32_t *ins_d, int64_t n_ins, const int32_t *del_s,
-                      const int32_t *del_d, int64_t n_del, int32_t n_nodes, int b1, int undirected, uint64_t *k_out,
-                      uint64_t *k_in, Ctl *ctl, hipStream_t st);
+                      const int32_t *del_d, int64_t n_del, int32_t n_nodes, int b1, int undirected,
+                      const int32_t *perm, uint64_t *k_out, uint64_t *k_in, Ctl *ctl, hipStream_t st);
 void launch_sort_segment_small(uint64_t *k0, uint64_t *k1, int32_t n_keys, int b1, int32_t *seg0, int32_t *row0,
                                int32_t *seg1, int32_t *row1, int orientations, Ctl *ctl, hipStream_t st);
 hipError_t sort_segment_large(uint64_t *keys, uint64_t *keys_alt, int32_t n_keys, int b1, int32_t *flags,
@@ -93,7 +93,8 @@ void launch_dense_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t s
 void launch_finish(const SlotArgs &a, int S, bool fp64, hipStream_t st);
 void launch_residual(const SlotArgs &a, int S, hipStream_t st);
 void launch_refine_init(const SlotArgs &a, int S, bool fp64, hipStream_t st);
-void launch_scores(const double *r, const Ctl *ctl, int S, int j, int32_t n, double *out, hipStream_t st);
+void launch_scores(const double *r, const Ctl *ctl, const int32_t *perm, int S, int j, int32_t n, double *out,
+                   hipStream_t st);
 void launch_sigma_exact(const SlotArgs &a, int S, hipStream_t st);
 
 // ---- graph (k_graph.hip)
@@ -109,8 +110,13 @@ void build_phase2(const uint64_t *keys, int64_t m, DevGraphView g, const int32_t
 hipError_t relayout_offsets(const int32_t *len, int32_t n, int32_t *new_cap, int32_t *new_off, void *temp,
                             size_t temp_bytes, int64_t *used, hipStream_t st);
 void launch_copy_rows(const DevGraphView &g, const int32_t *new_off, int32_t *new_adj, int32_t n, hipStream_t st);
-hipError_t export_rows(const DevGraphView &g, int32_t n, int32_t *out_src, int32_t *out_dst, int32_t *pos, void *temp,
-                       size_t temp_bytes, hipStream_t st);
+hipError_t export_rows(const DevGraphView &g, int32_t n, const int32_t *inv, int32_t *out_src, int32_t *out_dst,
+                       int32_t *pos, void *temp, size_t temp_bytes, hipStream_t st);
+hipError_t build_relabel(const int32_t *src, int64_t m, int32_t n, int32_t n_cap, int32_t *perm, int32_t *inv,
+                         int32_t *deg_tmp, uint64_t *keys, uint64_t *keys_alt, void *temp, size_t temp_bytes,
+                         hipStream_t st);
+void launch_identity(int32_t *perm, int32_t *inv, int32_t from, int32_t to, hipStream_t st);
+void launch_map_ids(const int32_t *in, int64_t m, int32_t n, const int32_t *perm, int32_t *out, hipStream_t st);
 void launch_mark_heavy(const int32_t *len, int32_t n, int32_t limit, uint8_t *flags, int32_t *sel,
                        int32_t *sel_count, hipStream_t st);
 void launch_gather_i32(const int32_t *src, const int32_t *idx, int32_t count, int32_t *out, hipStream_t st);

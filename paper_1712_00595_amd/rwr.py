@@ -63,6 +63,8 @@ class Config(ctypes.Structure):
         ("undirected", ctypes.c_int32),
         ("max_iters", ctypes.c_int32),
         ("pull_ratio", ctypes.c_int32),
+        ("reorder", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -193,6 +195,7 @@ class Context:
         undirected: bool = False,
         max_iters: int = 10000,
         pull_ratio: int = 0,
+        reorder: bool = True,
         stream: Optional[int] = None,
     ):
         self._lib = load_library()
@@ -207,6 +210,7 @@ class Context:
         cfg.undirected = 1 if undirected else 0
         cfg.max_iters = max_iters
         cfg.pull_ratio = pull_ratio
+        cfg.reorder = 1 if reorder else 0
         cfg.stream = stream
         on_dev = _is_torch(src)
         s = _Arr(src, on_dev)

@@ -32,7 +32,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_struct_layouts_match_header():
     # field order and sizes mirror rwr.h; 8-byte aligned structs
-    assert ctypes.sizeof(rwr.Config) == 8 * 4 + 4 * 4 + 8
+    assert ctypes.sizeof(rwr.Config) == 8 * 4 + 4 * 6 + 8
     assert ctypes.sizeof(rwr.BatchStruct) == 8 + 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
     assert ctypes.sizeof(rwr.StatsStruct) == 4 * 4 + 8 * 2 + 8 * 5
 
@@ -42,6 +42,7 @@ def test_config_default_and_host_side_rejection():
     cfg = rwr.Config()
     assert L.rwr_config_default(ctypes.byref(cfg)) == 0
     assert cfg.c == 0.15 and cfg.eps == 1e-9 and cfg.precision == 0 and cfg.max_iters == 10000
+    assert cfg.reorder == 1
     out = ctypes.c_void_p(None)
     # invalid arguments are rejected before any device call
     seeds = (ctypes.c_int32 * 1)(0)

@@ -77,15 +77,15 @@ def test_rmat13_one_batch_exact_fp64():
         assert np.allclose(norms, twin["norms"], rtol=1e-9, atol=1e-17)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_twin_norms_and_iterations(prec):
-    print(f"[twin] prec={prec}", flush=True)
+@pytest.mark.parametrize("prec,reorder", [("fp32", True), ("fp64", True), ("fp32", False)])
+def test_twin_norms_and_iterations(prec, reorder):
+    print(f"[twin] prec={prec} reorder={reorder}", flush=True)
     g = rmat_graph(12, 40000, dead_end_self_loops=True)
     s = int(np.argmax(g.out_degree()))
     rng = np.random.default_rng(7)
     b = _batch(rng, g.n, g.src, g.dst, 20, 20)
     eps = 1e-9
-    with _ctx(g, [s], eps=eps, precision=prec, build_tol=1e-13) as ctx:
+    with _ctx(g, [s], eps=eps, precision=prec, build_tol=1e-13, reorder=reorder) as ctx:
         r_old = oracle.rwr_static(g.n, g.src, g.dst, s, 0.15)
         ctx.update_batch(b)
         n2, s2, d2 = oracle.apply_batch(g.n, g.src, g.dst, b)
