@@ -62,19 +62,19 @@ struct rwr_ctx {
   double *r = nullptr, *ybuf = nullptr, *gbuf = nullptr;
   void *x[2] = {nullptr, nullptr};
   int32_t *stamp = nullptr;
-  int32_t *front[2] = {nullptr, nullptr};
+  int32_t *fstamp = nullptr;
   int32_t *hfront = nullptr;
+  int32_t *hbase = nullptr;
   Ctl *ctl = nullptr;
   Ctl *ctl_h = nullptr;  // pinned mirror
   double *hist = nullptr;
   int32_t max_iters = 10000;
   double *part = nullptr;
   int64_t *part_i = nullptr;
-  int32_t *gcnt = nullptr;
   int64_t part_blocks = 0;
   // heavy schedule of the pull orientation
-  int32_t *h_item_row = nullptr, *h_item_chunk = nullptr, *h_rows = nullptr, *h_nchunks = nullptr, *h_cnt = nullptr;
-  double *h_acc = nullptr;
+  int32_t *h_item_row = nullptr, *h_item_chunk = nullptr, *h_rows = nullptr, *h_nchunks = nullptr, *h_first = nullptr;
+  double *h_part = nullptr;
   int32_t h_items = 0, h_nrows = 0;
   int32_t heavy_limit = 512, heavy_chunk = 4096;
   int32_t *sel = nullptr, *sel_count = nullptr;
@@ -94,7 +94,8 @@ struct rwr_ctx {
   void *temp = nullptr;
   size_t temp_bytes = 0;
   // tuning
-  int32_t grid_sparse = 512, grid_light = 2048, light_lanes = 16;
+  int32_t grid_sparse = 512, grid_light = 2048, grid_pull = 2048, light_lanes = 16;
+  int32_t n_cu = 256;
   int32_t pull_ratio = 16;
   // error budget per seed column (normalised L1)
   double err_bound[RWR_MAX_COLS] = {};
@@ -211,9 +212,10 @@ static SlotArgs slot_args(const rwr_ctx *c) {
   a.heavy.item_chunk = c->h_item_chunk;
   a.heavy.rows = c->h_rows;
   a.heavy.nchunks = c->h_nchunks;
-  a.heavy.acc = c->h_acc;
-  a.heavy.cnt = c->h_cnt;
+  a.heavy.first = c->h_first;
+  a.heavy.part = c->h_part;
   a.heavy.n_items = c->h_items;
+  a.heavy.n_rows = c->h_nrows;
   a.heavy.chunk = c->heavy_chunk;
   a.r = c->r;
   a.ybuf = c->ybuf;
@@ -221,20 +223,20 @@ static SlotArgs slot_args(const rwr_ctx *c) {
   a.x[0] = c->x[0];
   a.x[1] = c->x[1];
   a.stamp = c->stamp;
-  a.front[0] = c->front[0];
-  a.front[1] = c->front[1];
+  a.fstamp = c->fstamp;
   a.hfront = c->hfront;
+  a.hbase = c->hbase;
   a.seeds = c->seeds_d;
   a.ctl = c->ctl;
   a.hist = c->hist;
   a.part = c->part;
   a.part_i = c->part_i;
-  a.gcnt = c->gcnt;
   a.n = c->n;
   a.n_seeds = c->n_seeds;
   a.c = c->cfg.c;
   a.grid_sparse = c->grid_sparse;
   a.grid_light = c->grid_light;
+  a.grid_pull = c->grid_pull;
   a.light_lanes = c->light_lanes;
   a.mp_rows = c->mp_rows;
   a.n_mp = c->n_mp;
@@ -249,17 +251,15 @@ static rwr_status read_ctl(rwr_ctx *c) {
 
 // partial-sum buffers sized for the largest grid in use
 static rwr_status ensure_partials(rwr_ctx *c) {
-  const int64_t blocks =
-      (int64_t)c->h_items + std::max<int64_t>({c->grid_light, c->grid_sparse, (int64_t)c->n_mp}) + 64;
+  // entries: the largest grid plus the heavy-row kernel's workgroups
+  const int64_t blocks = std::max<int64_t>({c->grid_light, c->grid_sparse, c->grid_pull}) + 320;
   if (blocks <= c->part_blocks) return RWR_OK;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   dev_free(c->part);
   dev_free(c->part_i);
-  dev_free(c->gcnt);
-  const int64_t groups = blocks / 32 + 2;
-  RWR_TRY(alloc_zero(c, &c->part, (size_t)(blocks + groups) * c->S * 2));
-  RWR_TRY(alloc_zero(c, &c->part_i, (size_t)(blocks + groups) * 2));
-  RWR_TRY(alloc_zero(c, &c->gcnt, (size_t)groups));
+  const int64_t stride = std::max(16, 2 * c->S);  // padded partial-sum entries
+  RWR_TRY(alloc_zero(c, &c->part, (size_t)blocks * stride));
+  RWR_TRY(alloc_zero(c, &c->part_i, (size_t)blocks * 16));
   c->part_blocks = blocks;
   return RWR_OK;
 }
@@ -268,7 +268,7 @@ static void tune_defaults(rwr_ctx *c) {
   const int S = c->S;
   if (S == 1) {
     c->light_lanes = 16;
-    c->heavy_limit = MP_EDGES;
+    c->heavy_limit = 512;
     c->heavy_chunk = 4096;
   } else if (S <= 4) {
     c->heavy_limit = 512;
@@ -285,13 +285,14 @@ static void tune_defaults(rwr_ctx *c) {
   if (const char *e = getenv("RWR_HEAVY_CHUNK")) c->heavy_chunk = atoi(e);
   if (const char *e = getenv("RWR_PULL_RATIO")) c->pull_ratio = atoi(e);
   if (c->cfg.pull_ratio > 0) c->pull_ratio = c->cfg.pull_ratio;
-  const int lanes_per_row = (S == 1) ? c->light_lanes : (S >= 8 ? 64 : 8 * S);
-  const int rows_per_block = std::max(1, 256 / lanes_per_row);
-  const int64_t want = ((int64_t)c->n_cap + rows_per_block - 1) / rows_per_block;
-  c->grid_light = (int32_t)std::max<int64_t>(1, std::min<int64_t>(want, 4096));
-  c->grid_sparse = 1024;
+  // grids sized to the resident capacity: workgroups loop over their work
+  c->grid_light = 4 * c->n_cu;
+  c->grid_sparse = 4 * c->n_cu;
+  // the single-column sweep holds six workgroups per CU (registers)
+  c->grid_pull = (S == 1 ? 6 : 8) * c->n_cu;
   if (const char *e = getenv("RWR_GRID_LIGHT")) c->grid_light = atoi(e);
   if (const char *e = getenv("RWR_GRID_SPARSE")) c->grid_sparse = atoi(e);
+  if (const char *e = getenv("RWR_GRID_PULL")) c->grid_pull = atoi(e);
 }
 
 // Row partition of the single-column dense sweep over all n_cap rows (rows
@@ -342,11 +343,12 @@ static rwr_status plan_heavy(rwr_ctx *c) {
                               c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
-  std::vector<int32_t> item_row, item_chunk, nchunks(count);
+  std::vector<int32_t> item_row, item_chunk, nchunks(count), first(count);
   for (int32_t h = 0; h < count; ++h) {
     const int64_t planned = (int64_t)lens[h] + lens[h] / 4;
     const int32_t nch = (int32_t)std::max<int64_t>(1, (planned + c->heavy_chunk - 1) / c->heavy_chunk);
     nchunks[h] = nch;
+    first[h] = (int32_t)item_row.size();
     for (int32_t k = 0; k < nch; ++k) {
       item_row.push_back(h);
       item_chunk.push_back(k);
@@ -356,20 +358,21 @@ static rwr_status plan_heavy(rwr_ctx *c) {
   dev_free(c->h_item_chunk);
   dev_free(c->h_rows);
   dev_free(c->h_nchunks);
-  dev_free(c->h_cnt);
-  dev_free(c->h_acc);
+  dev_free(c->h_first);
+  dev_free(c->h_part);
   const int32_t items = (int32_t)item_row.size();
   RWR_TRY(alloc_zero(c, &c->h_item_row, std::max(1, items)));
   RWR_TRY(alloc_zero(c, &c->h_item_chunk, std::max(1, items)));
   RWR_TRY(alloc_zero(c, &c->h_rows, std::max(1, count)));
   RWR_TRY(alloc_zero(c, &c->h_nchunks, std::max(1, count)));
-  RWR_TRY(alloc_zero(c, &c->h_cnt, std::max(1, count)));
-  RWR_TRY(alloc_zero(c, &c->h_acc, (size_t)std::max(1, count) * c->S));
+  RWR_TRY(alloc_zero(c, &c->h_first, std::max(1, count)));
+  RWR_TRY(alloc_zero(c, &c->h_part, (size_t)std::max(1, items) * c->S));
   if (items > 0) {
     H2D(c, c->h_item_row, item_row.data(), sizeof(int32_t) * items);
     H2D(c, c->h_item_chunk, item_chunk.data(), sizeof(int32_t) * items);
     H2D(c, c->h_rows, rows.data(), sizeof(int32_t) * count);
     H2D(c, c->h_nchunks, nchunks.data(), sizeof(int32_t) * count);
+    H2D(c, c->h_first, first.data(), sizeof(int32_t) * count);
   }
   c->h_items = items;
   c->h_nrows = count;
@@ -419,9 +422,9 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
   RWR_TRY(regrow(&c->x[0], xs, c->S));
   RWR_TRY(regrow(&c->x[1], xs, c->S));
   RWR_TRY(regrow((void **)&c->stamp, 4, 1));
-  RWR_TRY(regrow((void **)&c->front[0], 4, 1));
-  RWR_TRY(regrow((void **)&c->front[1], 4, 1));
+  RWR_TRY(regrow((void **)&c->fstamp, 4, 1));
   RWR_TRY(regrow((void **)&c->hfront, 4, 1));
+  RWR_TRY(regrow((void **)&c->hbase, 4, 1));
   RWR_TRY(regrow((void **)&c->sel, 4, 2));
   RWR_TRY(regrow((void **)&c->perm, 4, 1));
   RWR_TRY(regrow((void **)&c->inv, 4, 1));
@@ -688,6 +691,7 @@ rwr_status rwr_config_default(rwr_config *cfg) {
 static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                              int32_t n_seeds, const int32_t *seeds, int32_t on_device) {
   HIP_TRY(c, hipGetDevice(&c->device));
+  HIP_TRY(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
   if (c->cfg.stream) {
     c->stream = (hipStream_t)c->cfg.stream;
   } else {
@@ -816,9 +820,9 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   launch_zero_bytes(c->x[0], xs * nS, c->stream);
   launch_zero_bytes(c->x[1], xs * nS, c->stream);
   RWR_TRY(alloc_zero(c, &c->stamp, c->n_cap));
-  RWR_TRY(alloc_zero(c, &c->front[0], c->n_cap));
-  RWR_TRY(alloc_zero(c, &c->front[1], c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->fstamp, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->hfront, c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->hbase, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->sel, (size_t)c->n_cap * 2));
   RWR_TRY(alloc_zero(c, &c->sel_count, 1));
   RWR_TRY(alloc_zero(c, &c->hist, (size_t)(c->max_iters + 2) * c->S));
@@ -1027,7 +1031,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
                    c->n / 16 + 1, c->stream);
   if (N > 0) {
     launch_offset_seed(c->S, c->keys[0], c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->g[0].v, c->r, c->ybuf,
-                       c->stamp, c->front[0], c->ctl, b1, 1.0 - c->cfg.c, (int32_t)nkeys, c->stream);
+                       c->stamp, c->ctl, b1, 1.0 - c->cfg.c, (int32_t)nkeys, c->stream);
     for (int o = 0; o < norient; ++o)
       launch_apply(c->keys[o], c->seg[o], c->row[o], c->t_dold[o], c->t_dnew[o], c->g[o].v, c->ctl, o, b1,
                    (int32_t)nkeys, c->g[o].e_cap, c->stream);
@@ -1153,20 +1157,19 @@ void rwr_destroy(rwr_ctx *c) {
   dev_free(c->x[0]);
   dev_free(c->x[1]);
   dev_free(c->stamp);
-  dev_free(c->front[0]);
-  dev_free(c->front[1]);
+  dev_free(c->fstamp);
   dev_free(c->hfront);
+  dev_free(c->hbase);
   dev_free(c->ctl);
   dev_free(c->hist);
   dev_free(c->part);
   dev_free(c->part_i);
-  dev_free(c->gcnt);
   dev_free(c->h_item_row);
   dev_free(c->h_item_chunk);
   dev_free(c->h_rows);
   dev_free(c->h_nchunks);
-  dev_free(c->h_cnt);
-  dev_free(c->h_acc);
+  dev_free(c->h_first);
+  dev_free(c->h_part);
   dev_free(c->sel);
   dev_free(c->sel_count);
   dev_free(c->mp_rows);

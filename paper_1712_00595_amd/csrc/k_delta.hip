@@ -265,7 +265,7 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
                               const int32_t *__restrict__ row, const int32_t *__restrict__ t_dold,
                               const int32_t *__restrict__ t_dnew, const int32_t *__restrict__ off,
                               const int32_t *__restrict__ adj, const double *__restrict__ r,
-                              double *__restrict__ ybuf, int32_t *__restrict__ stamp, int32_t *__restrict__ front0,
+                              double *__restrict__ ybuf, int32_t *__restrict__ stamp,
                               Ctl *ctl, int b1, double c1) {
   if (ctl->err) return;
   constexpr int P = RWR_WAVE / S;
@@ -428,20 +428,20 @@ void launch_validate_plan(const uint64_t *keys, const int32_t *seg, const int32_
 template <int S>
 static void offset_seed_s(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
                           const int32_t *t_dnew, const DevGraphView &g, const double *r, double *ybuf, int32_t *stamp,
-                          int32_t *front0, Ctl *ctl, int b1, double c1, int32_t max_rows, hipStream_t st) {
+                          Ctl *ctl, int b1, double c1, int32_t max_rows, hipStream_t st) {
   const int waves_per_block = 4;
   const int grid = (max_rows + waves_per_block - 1) / waves_per_block;
   hipLaunchKernelGGL(k_offset_seed<S>, dim3(grid), dim3(waves_per_block * RWR_WAVE), 0, st, keys, seg, row, t_dold,
-                     t_dnew, g.off, g.adj, r, ybuf, stamp, front0, ctl, b1, c1);
+                     t_dnew, g.off, g.adj, r, ybuf, stamp, ctl, b1, c1);
 }
 
 void launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
                         const int32_t *t_dnew, const DevGraphView &g, const double *r, double *ybuf, int32_t *stamp,
-                        int32_t *front0, Ctl *ctl, int b1, double c1, int32_t max_rows, hipStream_t st) {
+                        Ctl *ctl, int b1, double c1, int32_t max_rows, hipStream_t st) {
   if (max_rows <= 0) return;
 #define RWR_SEED_CASE(SS)                                                                                       \
   case SS:                                                                                                      \
-    offset_seed_s<SS>(keys, seg, row, t_dold, t_dnew, g, r, ybuf, stamp, front0, ctl, b1, c1, max_rows, st); \
+    offset_seed_s<SS>(keys, seg, row, t_dold, t_dnew, g, r, ybuf, stamp, ctl, b1, c1, max_rows, st); \
     break;
   switch (S) {
     RWR_SEED_CASE(1)

@@ -51,8 +51,9 @@ struct Ctl {
   uint32_t done_blocks; // last-arriver counter of the current kernel
   int32_t dense_iters;
   int32_t heavy_stale;  // rows that became heavy since the last schedule
-  int32_t hfcount;      // frontier nodes too long for the light push (this slot)
+  int32_t pad0;
   int64_t fedges;       // out-edges of the frontier being built
+  uint64_t hpack;       // long push rows of this slot: count << 32 | chunks
   int64_t visited;      // edges read by propagation in this run
   int64_t demand[2];    // arena slots needed by relocated rows of this batch
   uint64_t tail[2];     // first free slot of each orientation's arena

@@ -20,15 +20,17 @@ struct DevGraphView {
 };
 
 // heavy-row schedule of the dense pull: rows whose in-degree exceeds the
-// light limit are split into chunks, each handled by a whole workgroup
+// light limit are split into chunks, each handled by a whole workgroup; the
+// chunk sums are combined by a follow-up kernel
 struct HeavyView {
   const int32_t *item_row;   // work item -> heavy row index h
   const int32_t *item_chunk; // work item -> chunk number within the row
   const int32_t *rows;       // h -> node id
   const int32_t *nchunks;    // h -> chunks planned for the row
-  double *acc;               // h*S + j -> partial sums (zero between sweeps)
-  int32_t *cnt;              // h -> arrived chunks (zero between sweeps)
+  const int32_t *first;      // h -> first work item of the row
+  double *part;              // item*S + j -> chunk sum
   int32_t n_items;
+  int32_t n_rows;
   int32_t chunk;
 };
 
@@ -41,20 +43,21 @@ struct SlotArgs {
   double *ybuf;
   double *gbuf;
   void *x[2];
-  int32_t *stamp;
-  int32_t *front[2];
+  int32_t *stamp;    // node touched in the current slot (slot stamp)
+  int32_t *fstamp;   // node in the frontier of x^(i) (stamp of slot i)
   int32_t *hfront;   // frontier nodes routed to the chunked push
+  int32_t *hbase;    // first chunk number of each of them
   const int32_t *seeds;
   Ctl *ctl;
   double *hist;
   double *part;      // per-workgroup partials, then per-group partials
   int64_t *part_i;
-  int32_t *gcnt;     // per-group arrival counters (zero between kernels)
   int32_t n;
   int32_t n_seeds;
   double c;
   int32_t grid_sparse;
   int32_t grid_light;
+  int32_t grid_pull;  // workgroups of a dense sweep (each loops over items)
   int32_t light_lanes;  // lanes per row of the light pull (S > 1)
   const int32_t *mp_rows;  // row partition of the single-column dense sweep
   int32_t n_mp;            // workgroups of that partition
@@ -77,7 +80,7 @@ void launch_validate_plan(const uint64_t *keys, const int32_t *seg, const int32_
                           int32_t max_rows, hipStream_t st);
 void launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
                         const int32_t *t_dnew, const DevGraphView &g, const double *r, double *ybuf, int32_t *stamp,
-                        int32_t *front0, Ctl *ctl, int b1, double c1, int32_t max_rows, hipStream_t st);
+                        Ctl *ctl, int b1, double c1, int32_t max_rows, hipStream_t st);
 void launch_apply(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
                   const int32_t *t_dnew, const DevGraphView &g, Ctl *ctl, int orient, int b1, int32_t max_rows,
                   int64_t e_cap, hipStream_t st);
