@@ -57,7 +57,21 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the final oracle comparison")
     ap.add_argument("--cpu-sample", type=int, default=3, help="updates timed on the CPU oracle")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (calibrates the traffic counters) and exit")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+
+        nbytes = args.copy_calibration << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes}))
+        return 0
 
     if args.gpus != 1:
         print(
@@ -174,10 +188,8 @@ def main() -> int:
 
         if not args.no_check and final_ctx_scores is not None:
             t = time.time()
-            n2, s2, d2 = g.n, g.src, g.dst
-            # the final graph: apply the whole stream to the edge list
-            for b in stream:
-                n2, s2, d2 = oracle.apply_batch(n2, s2, d2, b)
+            # the final graph: the whole stream applied to the edge list
+            n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream)
             ref = oracle.rwr_static(n2, s2, d2, int(seeds[0]), c)
             err = float(np.abs(final_ctx_scores - ref).sum())
             parity = {"l1_vs_oracle": err, "gate": H["gate"], "ok": err <= H["gate"],

@@ -15,11 +15,13 @@ Contents
                       (I - (1-c) A~^T) r = c e_s (numpy / LAPACK), n <= ~2000
   * ``apply_batch``  the graph G + Delta G of a batch, by plain set
                       operations on edge keys (Section 3.4.1 for new nodes)
+  * ``apply_stream`` the same for a sequence of batches, in one pass
 """
 
 from .core import (  # noqa: F401
     OracleError,
     apply_batch,
+    apply_stream,
     cpi,
     dead_end_reachable,
     lib,

@@ -218,3 +218,50 @@ def apply_batch(n, src, dst, batch, *, undirected=False, del_nodes=()):
         dst2 = np.concatenate([b, a[~loop]])
         return n_new, src2, dst2
     return n_new, a, b
+
+
+def apply_stream(n, src, dst, batches):
+    """Edge list after applying ``batches`` in order (directed graphs).
+
+    Each batch is validated against the graph it is applied to (inserted
+    edges absent, deleted edges present, no repeats), exactly as
+    :func:`apply_batch` does, but the state is kept as the initial sorted key
+    array plus a dictionary of changed keys, so a long stream of small
+    batches costs one pass over the edge list.
+    """
+    s0 = np.asarray(src, dtype=np.int64)
+    d0 = np.asarray(dst, dtype=np.int64)
+    init = np.sort(s0 * KEY + d0)
+    changed = {}
+    n_cur = int(n)
+
+    def present(k):
+        if k in changed:
+            return changed[k]
+        i = int(np.searchsorted(init, k))
+        return i < init.shape[0] and int(init[i]) == k
+
+    for b in batches:
+        n_cur += int(getattr(b, "n_new_nodes", 0))
+        ik = [int(u) * int(KEY) + int(v) for u, v in zip(b.ins_src, b.ins_dst)]
+        dk = [int(u) * int(KEY) + int(v) for u, v in zip(b.del_src, b.del_dst)]
+        for u, v in list(zip(b.ins_src, b.ins_dst)) + list(zip(b.del_src, b.del_dst)):
+            if not (0 <= u < n_cur and 0 <= v < n_cur):
+                raise OracleError("EINVAL")
+        if len(set(ik + dk)) != len(ik) + len(dk):
+            raise OracleError("EINVAL")
+        if any(not present(k) for k in dk):
+            raise OracleError("ENOENT")
+        if any(present(k) for k in ik):
+            raise OracleError("EEXIST")
+        for k in dk:
+            changed[k] = False
+        for k in ik:
+            changed[k] = True
+    gone = np.array(sorted(k for k, p in changed.items() if not p), dtype=np.int64)
+    added = np.array(sorted(k for k, p in changed.items() if p), dtype=np.int64)
+    keys = s0 * KEY + d0
+    keep = ~np.isin(keys, gone) if gone.size else np.ones(keys.shape[0], bool)
+    fresh = added[~np.isin(added, init)] if added.size else added
+    allk = np.concatenate([keys[keep], fresh])
+    return n_cur, (allk // KEY).astype(np.int32), (allk % KEY).astype(np.int32)

@@ -104,6 +104,7 @@ struct rwr_ctx {
   std::string err;
   std::vector<double> last_hist;
   int32_t last_iters = 0;
+  double decay_ema = 0.8;  // observed per-iteration decay of ||x^(i)||_1
   // measurement: events around dense sweep launches
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;
@@ -518,10 +519,14 @@ static rwr_status build_orient(rwr_ctx *c, int o, const int32_t *rows, const int
 // Only the kernels of the current phase are launched; the phase is re-read
 // at every synchronisation (a switch mid-chunk turns the chunk's remaining
 // sparse slots into no-ops, and the next chunk starts at the device's count).
-static rwr_status run_slots(rwr_ctx *c, int mode) {
+static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, double eps_hint = 0.0) {
   const SlotArgs a = slot_args(c);
   int k = 1;
-  int chunk = 4;
+  // first chunk: predicted from the starting norm when it is known (a
+  // refinement), else a few sparse slots
+  int chunk = 3;
+  if (init_norm > 0.0 && eps_hint > 0.0 && init_norm > eps_hint)
+    chunk = std::max(1, std::min(64, (int)std::ceil(std::log(eps_hint / init_norm) / std::log(c->decay_ema))));
   double prev = -1.0;
   int prev_iter = 0;
   int dense_launched = 0, dense_base = c->prof_used;
@@ -550,7 +555,7 @@ static rwr_status run_slots(rwr_ctx *c, int mode) {
     double cur = 0.0;
     for (int j = 0; j < c->n_seeds; ++j)
       if (h.active[j]) cur = std::max(cur, h.last_norm[j]);
-    double decay = 1.0 - c->cfg.c;
+    double decay = c->decay_ema;
     if (prev > 0.0 && cur > 0.0 && h.iter > prev_iter) {
       decay = std::pow(cur / prev, 1.0 / (h.iter - prev_iter));
       decay = std::min(std::max(decay, 0.3), 0.95);
@@ -582,6 +587,14 @@ static void account_run(rwr_ctx *c, bool reset) {
                  c->stream);
   (void)hipStreamSynchronize(c->stream);
   const double cc = c->cfg.c;
+  if (iters >= 3) {
+    // per-iteration decay between iteration 1 and the last one (column 0)
+    const double n1 = c->last_hist[(size_t)1 * c->S], nk = c->last_hist[(size_t)iters * c->S];
+    if (n1 > 0.0 && nk > 0.0) {
+      const double d = std::pow(nk / n1, 1.0 / (iters - 1));
+      if (d > 0.2 && d < 0.99) c->decay_ema = 0.8 * c->decay_ema + 0.2 * d;
+    }
+  }
   for (int j = 0; j < c->n_seeds; ++j) {
     double sum_norms = 0.0;
     for (int i = 0; i <= iters; ++i) sum_norms += c->last_hist[(size_t)i * c->S + j];
@@ -633,7 +646,7 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
   const double eps_ref = c->budget * cc * min_sig / (16.0 * (1.0 - cc));
   launch_reset_run(c->ctl, c->S, mask, eps_ref, c->max_iters, dense_thresh(c), c->n / 16 + 1, c->stream);
   launch_refine_init(a, c->S, c->fp64, c->stream);
-  RWR_TRY(run_slots(c, MODE_DENSE));
+  RWR_TRY(run_slots(c, MODE_DENSE, resid * (1.0 - cc), eps_ref));
   RWR_TRY(read_ctl(c));
   if (c->ctl_h->prop_err != 0) {
     c->stale = true;
