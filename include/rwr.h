@@ -156,15 +156,19 @@ rwr_status rwr_last_norms(rwr_ctx *ctx, int32_t j, double *out, int32_t cap, int
 
 /* Measurement of the dense sweep kernel (one pull over every in-row of the
  * graph, the bandwidth-bound step of the propagation, Section 2.2).  When
- * enabled, each dense sweep launch is bracketed by two HIP events on the
- * context's stream; after each propagation the elapsed times of the launches
- * that swept the graph are summed (launches that found the propagation
- * already converged are counted separately as idle).  Adds two event records
- * per dense sweep; off by default. */
+ * enabled, each launch of the sweep kernel in a propagation run is bracketed
+ * by two HIP events on the context's stream (the epilogue and decision
+ * kernels of the slot are outside the pair); after each run the elapsed
+ * times of all these launches are summed.  Launches that swept the graph are
+ * counted as sweeps; launches enqueued ahead that found the run already
+ * converged return at once and are counted as idle (their time is in the
+ * sum).  Residual checks are not included.  Adds two event records per dense
+ * launch; off by default. */
 rwr_status rwr_profile(rwr_ctx *ctx, int32_t enable);
 
-/* Read (and with reset = 1 clear) the accumulated dense-sweep time in ms, the
- * number of timed sweeps and the number of idle launches.  Any pointer may be
+/* Read (and with reset = 1 clear) the accumulated sweep-kernel time in ms
+ * (all launches), the number of launches that swept and the number of idle
+ * launches.  Any pointer may be
  * NULL. */
 rwr_status rwr_profile_read(rwr_ctx *ctx, double *dense_ms, int64_t *dense_sweeps, int64_t *idle_launches,
                             int32_t reset);

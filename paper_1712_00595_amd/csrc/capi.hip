@@ -173,31 +173,32 @@ static rwr_status ensure_temp(rwr_ctx *c, size_t bytes) {
   return RWR_OK;
 }
 
-// one event before (start = true) or after a dense sweep launch
-static rwr_status prof_record(rwr_ctx *c, bool start) {
-  (void)start;
-  if (c->prof_used == (int)c->prof_ev.size()) {
+// the next pair of events (created on first use) that brackets one launch
+// of the sweep kernel
+static rwr_status prof_pair(rwr_ctx *c, hipEvent_t *e0, hipEvent_t *e1) {
+  while (c->prof_used + 2 > (int)c->prof_ev.size()) {
     hipEvent_t e;
     HIP_TRY(c, hipEventCreate(&e));
     c->prof_ev.push_back(e);
   }
-  HIP_TRY(c, hipEventRecord(c->prof_ev[c->prof_used++], c->stream));
+  *e0 = c->prof_ev[c->prof_used++];
+  *e1 = c->prof_ev[c->prof_used++];
   return RWR_OK;
 }
 
-// After a run: the first `real` of the `launched` dense launches swept the
-// graph (dense sweeps are contiguous); the rest found the run converged.
+// After a run: the first `real` of the `launched` sweep launches swept the
+// graph (dense sweeps are contiguous); the rest found the run converged and
+// returned at once.  All launches count towards the time.
 static rwr_status prof_collect(rwr_ctx *c, int base, int launched, int real) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (int i = 0; i < launched; ++i) {
     float ms = 0.0f;
     HIP_TRY(c, hipEventElapsedTime(&ms, c->prof_ev[base + 2 * i], c->prof_ev[base + 2 * i + 1]));
-    if (i < real) {
-      c->prof_dense_ms += ms;
+    c->prof_dense_ms += ms;
+    if (i < real)
       ++c->prof_dense_sweeps;
-    } else {
+    else
       ++c->prof_idle;
-    }
   }
   c->prof_used = base;
   return RWR_OK;
@@ -538,9 +539,9 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
     const int kend = std::min(k + chunk, c->max_iters + 2);
     for (; k < kend; ++k) {
       if (mode == MODE_DENSE) {
-        if (c->prof_on) RWR_TRY(prof_record(c, true));
-        launch_dense_slot(a, c->S, c->fp64, k, c->stream);
-        if (c->prof_on) RWR_TRY(prof_record(c, false));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->prof_on) RWR_TRY(prof_pair(c, &e0, &e1));
+        launch_dense_slot(a, c->S, c->fp64, k, c->stream, e0, e1);
         ++dense_launched;
       } else {
         launch_sparse_slot(a, c->S, c->fp64, k, c->stream);
@@ -957,7 +958,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     return RWR_EINVAL;
   }
   if (b->n_del_nodes > 0) {
-    c->err = "node deletion is expressed through edge deletions in this build";
+    c->err = "node deletion is not supported: delete the node's edges instead";
     return RWR_EINVAL;
   }
   const int64_t n_new64 = (int64_t)c->n + b->n_new_nodes;

@@ -817,8 +817,9 @@ void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st) 
 // dense sweep (or residual) + heavy rows + decision; the heavy-row kernel
 // publishes after the sweep's entries
 template <typename XT, int S, int KIND>
-static void pull_impl(const SlotArgs &a, int k, hipStream_t st) {
+static void pull_impl(const SlotArgs &a, int k, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   int grid;
+  if (ev0) (void)hipEventRecord(ev0, st);
   if constexpr (S == 1) {
     grid = std::max(1, std::min(a.heavy.n_items + a.n_mp, a.grid_pull));
     hipLaunchKernelGGL((k_pull_mp<XT, KIND>), dim3(grid), dim3(BLOCK), 0, st, a, k);
@@ -827,6 +828,7 @@ static void pull_impl(const SlotArgs &a, int k, hipStream_t st) {
     constexpr int G = S >= 8 ? 64 : 8 * S;
     hipLaunchKernelGGL((k_pull<XT, S, G, KIND>), dim3(grid), dim3(BLOCK), 0, st, a, k);
   }
+  if (ev1) (void)hipEventRecord(ev1, st);
   int hgrid = 0;
   if (a.heavy.n_rows > 0) {
     hgrid = std::max(1, std::min((a.heavy.n_rows * S + BLOCK - 1) / BLOCK, 256));
@@ -851,11 +853,11 @@ void launch_sparse_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t 
   }
 }
 
-void launch_dense_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t st) {
+void launch_dense_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (fp64) {
-    RWR_DISPATCH_S(S, (pull_impl<double, SS, KIND_DENSE>(a, k, st)));
+    RWR_DISPATCH_S(S, (pull_impl<double, SS, KIND_DENSE>(a, k, st, ev0, ev1)));
   } else {
-    RWR_DISPATCH_S(S, (pull_impl<float, SS, KIND_DENSE>(a, k, st)));
+    RWR_DISPATCH_S(S, (pull_impl<float, SS, KIND_DENSE>(a, k, st, ev0, ev1)));
   }
 }
 

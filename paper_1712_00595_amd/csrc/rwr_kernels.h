@@ -92,7 +92,10 @@ void launch_seed_init(const SlotArgs &a, int S, hipStream_t st);
 void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st);
 // iteration slot k (computes x^(k)): sparse = push + epilogue, dense = pull
 void launch_sparse_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t st);
-void launch_dense_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t st);
+// ev0/ev1 (optional) are recorded on st right before and after the sweep
+// kernel itself, not around the epilogue and decision kernels.
+void launch_dense_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t st, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
 void launch_finish(const SlotArgs &a, int S, bool fp64, hipStream_t st);
 void launch_residual(const SlotArgs &a, int S, hipStream_t st);
 void launch_refine_init(const SlotArgs &a, int S, bool fp64, hipStream_t st);
