@@ -73,9 +73,12 @@ typedef struct rwr_config {
 /* A batch is a set (Theorem 1: only the graphs before and after matter).
  * New nodes get ids n .. n+n_new_nodes-1 and may be named by this batch's
  * insertions (Section 3.4.1).  A deleted node loses every incident edge and
- * keeps its id with a zero row and column (Section 3.4.1; a seed node cannot
- * be deleted).  The same edge may not appear twice, nor be both inserted and
- * deleted.  In undirected mode a pair is given once, in either orientation. */
+ * keeps its id with a zero row and column (Section 3.4.1).  del_nodes lists
+ * distinct ids of existing nodes (< n before the batch), none of them a seed
+ * (the walk restarts there), none named by this batch's edge entries; the
+ * removed edges then count as deletions of the batch.  The same edge may not
+ * appear twice, nor be both inserted and deleted.  In undirected mode a pair
+ * is given once, in either orientation.  Any violation is RWR_EINVAL. */
 typedef struct rwr_batch {
   int64_t n_ins;
   const int32_t *ins_src;

@@ -172,7 +172,8 @@ def apply_batch(n, src, dst, batch, *, undirected=False, del_nodes=()):
     ``batch`` has ``ins_src, ins_dst, del_src, del_dst, n_new_nodes``.  Raises
     :class:`OracleError` (with code 'EINVAL', 'EEXIST' or 'ENOENT') for an
     invalid batch.  New nodes get ids n..n+k-1 (Section 3.4.1).  A deleted
-    node loses every incident edge (its row and column become zero).
+    node (an existing id, listed once, not named by the batch's edge
+    entries) loses every incident edge: its row and column become zero.
     Undirected graphs store both directions of each pair; batch pairs are
     given once.
     """
@@ -203,9 +204,15 @@ def apply_batch(n, src, dst, batch, *, undirected=False, del_nodes=()):
         raise OracleError("EEXIST")
     keep = ~np.isin(cur, dk)
     newk = np.concatenate([cur[keep], ik])
+    if len(del_nodes) == 0:
+        del_nodes = getattr(batch, "del_nodes", ())
     dn = np.asarray(del_nodes, dtype=np.int64)
     if dn.size:
-        if dn.min() < 0 or dn.max() >= n_new or np.unique(dn).shape[0] != dn.shape[0]:
+        # deleted nodes: distinct existing nodes, not named by the batch's
+        # own edge entries
+        if dn.min() < 0 or dn.max() >= n or np.unique(dn).shape[0] != dn.shape[0]:
+            raise OracleError("EINVAL")
+        if np.isin(np.concatenate([ins_s, ins_d, del_s, del_d]), dn).any():
             raise OracleError("EINVAL")
         a, b = newk // KEY, newk % KEY
         inc = np.isin(a, dn) | np.isin(b, dn)
@@ -242,6 +249,8 @@ def apply_stream(n, src, dst, batches):
         return i < init.shape[0] and int(init[i]) == k
 
     for b in batches:
+        if len(getattr(b, "del_nodes", ())):
+            raise ValueError("apply_stream takes edge batches only; use apply_batch for node deletions")
         n_cur += int(getattr(b, "n_new_nodes", 0))
         ik = [int(u) * int(KEY) + int(v) for u, v in zip(b.ins_src, b.ins_dst)]
         dk = [int(u) * int(KEY) + int(v) for u, v in zip(b.del_src, b.del_dst)]

@@ -63,6 +63,9 @@ struct rwr_ctx {
   void *x[2] = {nullptr, nullptr};
   int32_t *stamp = nullptr;
   int32_t *fstamp = nullptr;
+  int32_t *nmark = nullptr;        // 1 on nodes that the current batch deletes (per node)
+  int64_t *ndel = nullptr;         // node deletions: entry counts, then key offsets
+  int64_t ndel_cap = 0;
   int32_t *hfront = nullptr;
   int32_t *hbase = nullptr;
   Ctl *ctl = nullptr;
@@ -425,6 +428,7 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
   RWR_TRY(regrow(&c->x[1], xs, c->S));
   RWR_TRY(regrow((void **)&c->stamp, 4, 1));
   RWR_TRY(regrow((void **)&c->fstamp, 4, 1));
+  RWR_TRY(regrow((void **)&c->nmark, 4, 1));
   RWR_TRY(regrow((void **)&c->hfront, 4, 1));
   RWR_TRY(regrow((void **)&c->hbase, 4, 1));
   RWR_TRY(regrow((void **)&c->sel, 4, 2));
@@ -835,6 +839,7 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   launch_zero_bytes(c->x[1], xs * nS, c->stream);
   RWR_TRY(alloc_zero(c, &c->stamp, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->fstamp, c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->nmark, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->hfront, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->hbase, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->sel, (size_t)c->n_cap * 2));
@@ -957,9 +962,33 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     c->err = "invalid batch";
     return RWR_EINVAL;
   }
-  if (b->n_del_nodes > 0) {
-    c->err = "node deletion is not supported: delete the node's edges instead";
+  if (b->n_del_nodes > 0 && !b->del_nodes) {
+    c->err = "invalid batch";
     return RWR_EINVAL;
+  }
+  // node deletions are checked on the host: ids of existing nodes, distinct,
+  // no seed (the walk restarts there)
+  const int32_t nd = b->n_del_nodes;
+  std::vector<int32_t> dn(nd);
+  if (nd > 0) {
+    if (b->on_device)
+      D2H(c, dn.data(), b->del_nodes, sizeof(int32_t) * nd);
+    else
+      std::memcpy(dn.data(), b->del_nodes, sizeof(int32_t) * nd);
+    std::vector<int32_t> sorted = dn;
+    std::sort(sorted.begin(), sorted.end());
+    for (int32_t i = 0; i < nd; ++i) {
+      if (sorted[i] < 0 || sorted[i] >= c->n || (i > 0 && sorted[i] == sorted[i - 1])) {
+        c->err = "node deletion names an id out of range or twice";
+        return RWR_EINVAL;
+      }
+    }
+    for (int32_t sd : c->seeds_h) {
+      if (std::binary_search(sorted.begin(), sorted.end(), sd)) {
+        c->err = "a seed node cannot be deleted";
+        return RWR_EINVAL;
+      }
+    }
   }
   const int64_t n_new64 = (int64_t)c->n + b->n_new_nodes;
   if (n_new64 >= INT32_MAX - 1024) {
@@ -969,33 +998,68 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   const int32_t n_new = (int32_t)n_new64;
   RWR_TRY(grow_nodes(c, n_new));
   const int64_t N = b->n_ins + b->n_del;
-  const int64_t nkeys = c->undirected ? 2 * N : N;
+  const int64_t nints = 2 * N + nd;
+  RWR_TRY(ensure_batch(c, 1, std::max<int64_t>(nints, 1)));
+  const int32_t *ins_s = b->ins_src, *ins_d = b->ins_dst, *del_s = b->del_src, *del_d = b->del_dst;
+  int32_t *dn_dev = c->b_dev + 2 * N;
+  if (nints > 0) {
+    int32_t *h = c->b_host;
+    if (!b->on_device) {
+      std::memcpy(h, b->ins_src, sizeof(int32_t) * b->n_ins);
+      std::memcpy(h + b->n_ins, b->ins_dst, sizeof(int32_t) * b->n_ins);
+      std::memcpy(h + 2 * b->n_ins, b->del_src, sizeof(int32_t) * b->n_del);
+      std::memcpy(h + 2 * b->n_ins + b->n_del, b->del_dst, sizeof(int32_t) * b->n_del);
+    }
+    if (nd > 0) std::memcpy(h + 2 * N, dn.data(), sizeof(int32_t) * nd);
+    const int64_t lo = b->on_device ? 2 * N : 0;
+    if (nints > lo)
+      HIP_TRY(c, hipMemcpyAsync(c->b_dev + lo, h + lo, sizeof(int32_t) * (nints - lo), hipMemcpyHostToDevice,
+                                c->stream));
+    if (!b->on_device) {
+      ins_s = c->b_dev;
+      ins_d = c->b_dev + b->n_ins;
+      del_s = c->b_dev + 2 * b->n_ins;
+      del_d = c->b_dev + 2 * b->n_ins + b->n_del;
+    }
+  }
+  // entries contributed by node deletions (exact count known after marking)
+  int64_t T = 0;
+  if (nd > 0) {
+    if (nd + 1 > c->ndel_cap) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      dev_free(c->ndel);
+      RWR_TRY(alloc_zero(c, &c->ndel, 2 * (int64_t)nd + 2));
+      c->ndel_cap = 2 * (int64_t)nd + 2;
+    }
+    launch_node_mark(dn_dev, nd, c->perm, c->g[0].v, c->g[1].v, c->undirected ? 1 : 0, c->nmark, c->ndel,
+                     c->stream);
+    std::vector<int64_t> cnt(nd), off(nd);
+    D2H(c, cnt.data(), c->ndel, sizeof(int64_t) * nd);
+    for (int32_t i = 0; i < nd; ++i) {
+      off[i] = T;
+      T += cnt[i];
+    }
+    H2D(c, c->ndel, off.data(), sizeof(int64_t) * nd);
+  }
+  const int64_t nkeys = c->undirected ? 2 * (N + T) : N + T;
   if (nkeys >= INT32_MAX) {
+    if (nd > 0) launch_node_unmark(dn_dev, nd, c->perm, c->nmark, c->stream);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->err = "batch too large";
     return RWR_EINVAL;
   }
-  RWR_TRY(ensure_batch(c, std::max<int64_t>(nkeys, 1), 4 * std::max<int64_t>(N, 1)));
+  RWR_TRY(ensure_batch(c, std::max<int64_t>(nkeys, 1), std::max<int64_t>(nints, 1)));
   const int b1 = bits_for(std::max(1, n_new - 1)) + 1;
   launch_reset_batch(c->ctl, 0, c->stream);
 
-  const int32_t *ins_s = b->ins_src, *ins_d = b->ins_dst, *del_s = b->del_src, *del_d = b->del_dst;
-  if (!b->on_device && N > 0) {
-    int32_t *h = c->b_host;
-    std::memcpy(h, b->ins_src, sizeof(int32_t) * b->n_ins);
-    std::memcpy(h + b->n_ins, b->ins_dst, sizeof(int32_t) * b->n_ins);
-    std::memcpy(h + 2 * b->n_ins, b->del_src, sizeof(int32_t) * b->n_del);
-    std::memcpy(h + 2 * b->n_ins + b->n_del, b->del_dst, sizeof(int32_t) * b->n_del);
-    HIP_TRY(c, hipMemcpyAsync(c->b_dev, h, sizeof(int32_t) * 2 * N, hipMemcpyHostToDevice, c->stream));
-    ins_s = c->b_dev;
-    ins_d = c->b_dev + b->n_ins;
-    del_s = c->b_dev + 2 * b->n_ins;
-    del_d = c->b_dev + 2 * b->n_ins + b->n_del;
-  }
   const int norient = c->undirected ? 1 : 2;
   const int po = pull_orient(c);
-  if (N > 0) {
+  if (nkeys > 0) {
     launch_make_keys(ins_s, ins_d, b->n_ins, del_s, del_d, b->n_del, n_new, b1, c->undirected ? 1 : 0, c->perm,
-                     c->keys[0], c->keys[1], c->ctl, c->stream);
+                     nd > 0 ? c->nmark : nullptr, c->keys[0], c->keys[1], c->ctl, c->stream);
+    if (nd > 0)
+      launch_node_keys(dn_dev, nd, c->ndel, N, c->perm, c->g[0].v, c->g[1].v, c->undirected ? 1 : 0, c->nmark, b1,
+                       c->keys[0], c->keys[1], c->ctl, c->stream);
     if (nkeys <= SMALL_SORT_MAX) {
       launch_sort_segment_small(c->keys[0], c->keys[1], (int32_t)nkeys, b1, c->seg[0], c->row[0], c->seg[1],
                                 c->row[1], norient, c->ctl, c->stream);
@@ -1008,6 +1072,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
       launch_validate_plan(c->keys[o], c->seg[o], c->row[o], c->g[o].v, b1, c->t_dold[o], c->t_dnew[o], c->ctl, o,
                            o == 0 ? 1 : 0, o == po ? c->heavy_limit : 0, (int32_t)nkeys, c->stream);
   }
+  if (nd > 0) launch_node_unmark(dn_dev, nd, c->perm, c->nmark, c->stream);
   RWR_TRY(read_ctl(c));
   if (c->ctl_h->err != 0) {
     const int e = c->ctl_h->err;
@@ -1043,7 +1108,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   const SlotArgs a = slot_args(c);
   launch_reset_run(c->ctl, c->S, all_cols_mask(c->n_seeds), c->cfg.eps, c->max_iters, dense_thresh(c),
                    c->n / 16 + 1, c->stream);
-  if (N > 0) {
+  if (nkeys > 0) {
     launch_offset_seed(c->S, c->keys[0], c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->g[0].v, c->r, c->ybuf,
                        c->stamp, c->ctl, b1, 1.0 - c->cfg.c, (int32_t)nkeys, c->stream);
     for (int o = 0; o < norient; ++o)
@@ -1052,7 +1117,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   }
   // stored edge count (an undirected self-loop is stored once; the count only
   // steers the sparse/dense switch and the visited-edge statistic)
-  c->m += (b->n_ins - b->n_del) * (c->undirected ? 2 : 1);
+  c->m += (b->n_ins - b->n_del) * (c->undirected ? 2 : 1) - c->ctl_h->node_dels;
   launch_slot0_epilogue(a, c->S, c->fp64, c->stream);
   RWR_TRY(run_slots(c, MODE_SPARSE));
   RWR_TRY(read_ctl(c));

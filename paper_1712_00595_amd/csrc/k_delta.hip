@@ -29,7 +29,8 @@ __device__ __forceinline__ int32_t key_col(uint64_t k, int b1) {
 __global__ void k_make_keys(const int32_t *__restrict__ ins_s, const int32_t *__restrict__ ins_d, int64_t n_ins,
                             const int32_t *__restrict__ del_s, const int32_t *__restrict__ del_d, int64_t n_del,
                             int32_t n_nodes, int b1, int undirected, const int32_t *__restrict__ perm,
-                            uint64_t *__restrict__ k_out, uint64_t *__restrict__ k_in, Ctl *ctl) {
+                            const int32_t *__restrict__ mark, uint64_t *__restrict__ k_out,
+                            uint64_t *__restrict__ k_in, Ctl *ctl) {
   const int64_t total = n_ins + n_del;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const bool ins = i < n_ins;
@@ -48,6 +49,18 @@ __global__ void k_make_keys(const int32_t *__restrict__ ins_s, const int32_t *__
       continue;
     }
     const int32_t u = perm[ue], v = perm[ve];  // internal ids
+    if (mark && (mark[u] | mark[v])) {
+      // an edge entry naming a node that the same batch deletes
+      set_error(ctl, ERR_EINVAL);
+      if (undirected) {
+        k_out[2 * i] = KEY_PAD;
+        k_out[2 * i + 1] = KEY_PAD;
+      } else {
+        k_out[i] = KEY_PAD;
+        k_in[i] = KEY_PAD;
+      }
+      continue;
+    }
     if (undirected) {
       // a pair stands for both directed edges; a self-loop for one
       k_out[2 * i] = ((uint64_t)u << b1) | ((uint64_t)v << 1) | t;
@@ -57,6 +70,90 @@ __global__ void k_make_keys(const int32_t *__restrict__ ins_s, const int32_t *__
       k_in[i] = ((uint64_t)v << b1) | ((uint64_t)u << 1) | t;
     }
   }
+}
+
+// ------------------------------------------------------- node deletions
+// A deleted node loses every incident edge (its row and column of A become
+// zero; Section 3.4.1).  The removed edges enter the batch as ordinary
+// deletion keys, so validation, the offset seed and the structural update
+// treat them like any other deletion.  k_node_mark marks each deleted node
+// (internal id) and reports how many adjacency entries its keys are drawn
+// from; the host turns the counts into key offsets.
+__global__ void k_node_mark(const int32_t *__restrict__ del_nodes, int32_t n_del, const int32_t *__restrict__ perm,
+                            DevGraphView out, DevGraphView in, int undirected, int32_t *__restrict__ mark,
+                            int64_t *__restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_del) return;
+  const int32_t u = perm[del_nodes[i]];
+  mark[u] = 1;
+  cnt[i] = (int64_t)out.len[u] + (undirected ? 0 : in.len[u]);
+}
+
+// One block per deleted node u; its keys start at entry `first + off[i]`
+// (pairs of entries in undirected mode).  Directed: every out-edge (u, v),
+// and every in-edge (w, u) unless w is u (the self-loop came with the row) or
+// w is itself deleted (that edge came with w's row).  Undirected: every pair
+// {u, v} once, skipped at u when v is deleted and v < u.  Skipped entries
+// are padding.  ctl->node_dels counts the stored entries removed.
+__global__ void k_node_keys(const int32_t *__restrict__ del_nodes, const int64_t *__restrict__ off, int64_t first,
+                            const int32_t *__restrict__ perm, DevGraphView out, DevGraphView in, int undirected,
+                            const int32_t *__restrict__ mark, int b1, uint64_t *__restrict__ k_out,
+                            uint64_t *__restrict__ k_in, Ctl *ctl) {
+  __shared__ int64_t wsum[256 / RWR_WAVE];
+  const int32_t u = perm[del_nodes[blockIdx.x]];
+  const int64_t base = first + off[blockIdx.x];
+  const int32_t lo = out.len[u];
+  const int32_t li = undirected ? 0 : in.len[u];
+  const int32_t *ro = out.adj + out.off[u];
+  const int32_t *ri = in.adj + in.off[u];
+  int64_t removed = 0;
+  for (int32_t j = threadIdx.x; j < lo + li; j += blockDim.x) {
+    const int64_t e = base + j;
+    if (undirected) {
+      const int32_t v = ro[j];
+      if (v == u) {
+        k_out[2 * e] = ((uint64_t)u << b1) | ((uint64_t)u << 1);
+        k_out[2 * e + 1] = KEY_PAD;
+        removed += 1;
+      } else if (mark[v] && v < u) {
+        k_out[2 * e] = KEY_PAD;
+        k_out[2 * e + 1] = KEY_PAD;
+      } else {
+        k_out[2 * e] = ((uint64_t)u << b1) | ((uint64_t)v << 1);
+        k_out[2 * e + 1] = ((uint64_t)v << b1) | ((uint64_t)u << 1);
+        removed += 2;
+      }
+    } else if (j < lo) {
+      const int32_t v = ro[j];
+      k_out[e] = ((uint64_t)u << b1) | ((uint64_t)v << 1);
+      k_in[e] = ((uint64_t)v << b1) | ((uint64_t)u << 1);
+      removed += 1;
+    } else {
+      const int32_t w = ri[j - lo];
+      if (w == u || mark[w]) {
+        k_out[e] = KEY_PAD;
+        k_in[e] = KEY_PAD;
+      } else {
+        k_out[e] = ((uint64_t)w << b1) | ((uint64_t)u << 1);
+        k_in[e] = ((uint64_t)u << b1) | ((uint64_t)w << 1);
+        removed += 1;
+      }
+    }
+  }
+  removed = wave_xor_sum(removed, 1, RWR_WAVE);
+  if (threadIdx.x % RWR_WAVE == 0) wsum[threadIdx.x / RWR_WAVE] = removed;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int w = 0; w < (int)(blockDim.x / RWR_WAVE); ++w) t += wsum[w];
+    if (t) atomicAdd((unsigned long long *)&ctl->node_dels, (unsigned long long)t);
+  }
+}
+
+__global__ void k_node_unmark(const int32_t *__restrict__ del_nodes, int32_t n_del, const int32_t *__restrict__ perm,
+                              int32_t *__restrict__ mark) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_del) mark[perm[del_nodes[i]]] = 0;
 }
 
 // ------------------------------------------------- small batches: one block
@@ -368,6 +465,7 @@ __global__ void k_reset_batch(Ctl *ctl, int demand_only) {
   ctl->demand[0] = 0;
   ctl->demand[1] = 0;
   ctl->heavy_stale = 0;
+  if (!demand_only) ctl->node_dels = 0;
 }
 
 // ------------------------------------------------- host launchers
@@ -377,12 +475,34 @@ void launch_reset_batch(Ctl *ctl, int demand_only, hipStream_t st) {
 
 void launch_make_keys(const int32_t *ins_s, const int32_t *ins_d, int64_t n_ins, const int32_t *del_s,
                       const int32_t *del_d, int64_t n_del, int32_t n_nodes, int b1, int undirected,
-                      const int32_t *perm, uint64_t *k_out, uint64_t *k_in, Ctl *ctl, hipStream_t st) {
+                      const int32_t *perm, const int32_t *mark, uint64_t *k_out, uint64_t *k_in, Ctl *ctl,
+                      hipStream_t st) {
   const int64_t total = n_ins + n_del;
   if (total == 0) return;
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
   hipLaunchKernelGGL(k_make_keys, dim3(grid), dim3(256), 0, st, ins_s, ins_d, n_ins, del_s, del_d, n_del, n_nodes,
-                     b1, undirected, perm, k_out, k_in, ctl);
+                     b1, undirected, perm, mark, k_out, k_in, ctl);
+}
+
+void launch_node_mark(const int32_t *del_nodes, int32_t n_del, const int32_t *perm, const DevGraphView &out,
+                      const DevGraphView &in, int undirected, int32_t *mark, int64_t *cnt, hipStream_t st) {
+  if (n_del <= 0) return;
+  hipLaunchKernelGGL(k_node_mark, dim3((n_del + 255) / 256), dim3(256), 0, st, del_nodes, n_del, perm, out, in,
+                     undirected, mark, cnt);
+}
+
+void launch_node_keys(const int32_t *del_nodes, int32_t n_del, const int64_t *off, int64_t first,
+                      const int32_t *perm, const DevGraphView &out, const DevGraphView &in, int undirected,
+                      const int32_t *mark, int b1, uint64_t *k_out, uint64_t *k_in, Ctl *ctl, hipStream_t st) {
+  if (n_del <= 0) return;
+  hipLaunchKernelGGL(k_node_keys, dim3(n_del), dim3(256), 0, st, del_nodes, off, first, perm, out, in, undirected,
+                     mark, b1, k_out, k_in, ctl);
+}
+
+void launch_node_unmark(const int32_t *del_nodes, int32_t n_del, const int32_t *perm, int32_t *mark,
+                        hipStream_t st) {
+  if (n_del <= 0) return;
+  hipLaunchKernelGGL(k_node_unmark, dim3((n_del + 255) / 256), dim3(256), 0, st, del_nodes, n_del, perm, mark);
 }
 
 void launch_sort_segment_small(uint64_t *k0, uint64_t *k1, int32_t n_keys, int b1, int32_t *seg0, int32_t *row0,

@@ -59,6 +59,7 @@ struct Ctl {
   uint64_t tail[2];     // first free slot of each orientation's arena
   int64_t dense_thresh; // switch to dense once fedges exceeds this
   int64_t dense_nodes;  // ... or once the frontier holds more nodes than this
+  int64_t node_dels;    // stored adjacency entries removed by this batch's node deletions
   double eps;           // stop tolerance of this run
   int32_t active[RWR_MAX_COLS];
   double sigma[RWR_MAX_COLS];     // running sum of r per column

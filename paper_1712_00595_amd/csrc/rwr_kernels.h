@@ -68,7 +68,17 @@ struct SlotArgs {
 // ---- delta (k_delta.hip)
 void launch_make_keys(const int32_t *ins_s, const int32_t *ins_d, int64_t n_ins, const int32_t *del_s,
                       const int32_t *del_d, int64_t n_del, int32_t n_nodes, int b1, int undirected,
-                      const int32_t *perm, uint64_t *k_out, uint64_t *k_in, Ctl *ctl, hipStream_t st);
+                      const int32_t *perm, const int32_t *mark, uint64_t *k_out, uint64_t *k_in, Ctl *ctl,
+                      hipStream_t st);
+// node deletions: mark the nodes and count their adjacency entries; write
+// their incident edges as deletion keys from entry `first` on; clear marks
+void launch_node_mark(const int32_t *del_nodes, int32_t n_del, const int32_t *perm, const DevGraphView &out,
+                      const DevGraphView &in, int undirected, int32_t *mark, int64_t *cnt, hipStream_t st);
+void launch_node_keys(const int32_t *del_nodes, int32_t n_del, const int64_t *off, int64_t first,
+                      const int32_t *perm, const DevGraphView &out, const DevGraphView &in, int undirected,
+                      const int32_t *mark, int b1, uint64_t *k_out, uint64_t *k_in, Ctl *ctl, hipStream_t st);
+void launch_node_unmark(const int32_t *del_nodes, int32_t n_del, const int32_t *perm, int32_t *mark,
+                        hipStream_t st);
 void launch_sort_segment_small(uint64_t *k0, uint64_t *k1, int32_t n_keys, int b1, int32_t *seg0, int32_t *row0,
                                int32_t *seg1, int32_t *row1, int orientations, Ctl *ctl, hipStream_t st);
 hipError_t sort_segment_large(uint64_t *keys, uint64_t *keys_alt, int32_t n_keys, int b1, int32_t *flags,

@@ -247,9 +247,11 @@ class Context:
         self.close()
 
     # -- updates
-    def update(self, ins_src=None, ins_dst=None, del_src=None, del_dst=None, n_new_nodes: int = 0) -> dict:
-        on_dev = any(_is_torch(a) for a in (ins_src, ins_dst, del_src, del_dst) if a is not None)
-        a = [_Arr(x, on_dev) for x in (ins_src, ins_dst, del_src, del_dst)]
+    def update(self, ins_src=None, ins_dst=None, del_src=None, del_dst=None, n_new_nodes: int = 0,
+               del_nodes=None) -> dict:
+        arrays = (ins_src, ins_dst, del_src, del_dst, del_nodes)
+        on_dev = any(_is_torch(x) for x in arrays if x is not None)
+        a = [_Arr(x, on_dev) for x in arrays]
         if a[0].n != a[1].n or a[2].n != a[3].n:
             raise ValueError("source and destination arrays differ in length")
         b = BatchStruct()
@@ -258,8 +260,8 @@ class Context:
         b.n_del = a[2].n
         b.del_src, b.del_dst = a[2].ptr, a[3].ptr
         b.n_new_nodes = int(n_new_nodes)
-        b.n_del_nodes = 0
-        b.del_nodes = None
+        b.n_del_nodes = a[4].n
+        b.del_nodes = a[4].ptr
         b.on_device = 1 if on_dev else 0
         st = StatsStruct()
         code = self._lib.rwr_update(self._ctx, ctypes.byref(b), ctypes.byref(st))
@@ -267,7 +269,8 @@ class Context:
         return st.as_dict()
 
     def update_batch(self, batch) -> dict:
-        return self.update(batch.ins_src, batch.ins_dst, batch.del_src, batch.del_dst, batch.n_new_nodes)
+        return self.update(batch.ins_src, batch.ins_dst, batch.del_src, batch.del_dst, batch.n_new_nodes,
+                           getattr(batch, "del_nodes", None))
 
     def refine(self) -> dict:
         st = StatsStruct()
@@ -281,6 +284,14 @@ class Context:
         m = ctypes.c_int64(0)
         _check(self._lib, self._ctx, self._lib.rwr_graph_size(self._ctx, ctypes.byref(n), ctypes.byref(m)))
         return n.value
+
+    @property
+    def m(self) -> int:
+        """Stored directed edges (an undirected pair counts twice, a self-loop once)."""
+        n = ctypes.c_int32(0)
+        m = ctypes.c_int64(0)
+        _check(self._lib, self._ctx, self._lib.rwr_graph_size(self._ctx, ctypes.byref(n), ctypes.byref(m)))
+        return m.value
 
     def scores(self, j: int = 0) -> np.ndarray:
         out = np.zeros(self.n, dtype=np.float64)

@@ -22,6 +22,8 @@ class Batch:
     del_src: np.ndarray
     del_dst: np.ndarray
     n_new_nodes: int = 0
+    # nodes whose incident edges are all removed (ids of existing nodes)
+    del_nodes: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0, np.int32))
 
     @property
     def n_ins(self) -> int:
@@ -33,8 +35,8 @@ class Batch:
 
     @property
     def size(self) -> int:
-        """Edge modifications plus node insertions in the batch."""
-        return self.n_ins + self.n_del + int(self.n_new_nodes)
+        """Edge modifications plus node insertions and deletions in the batch."""
+        return self.n_ins + self.n_del + int(self.n_new_nodes) + int(self.del_nodes.shape[0])
 
 
 def _i32(a) -> np.ndarray:

@@ -263,3 +263,80 @@ def test_relayout_when_arena_fills():
         assert set(zip(es.tolist(), ed.tolist())) == set(zip(src.tolist(), dst.tolist()))
         ref = oracle.rwr_static(n, src, dst, s, 0.15)
         assert _l1(ctx.scores(0), ref) < 1e-10
+
+
+# ------------------------------------------------------------- node deletion
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_node_deletion_matches_oracle(undirected):
+    # Section 3.4.1: a deleted node's row and column become zero; exact
+    # (FP64) update against the static scores of G + Delta G
+    print(f"[node deletion] undirected={undirected}", flush=True)
+    g = rmat_graph(12, 30000, dead_end_self_loops=not undirected, undirected=undirected)
+    deg = g.out_degree()
+    s = int(np.argmax(deg))
+    order = np.argsort(-deg, kind="stable")
+    # the second-largest hub, a few ordinary nodes, two adjacent nodes and a
+    # node with a self-loop (when one exists)
+    cand = [int(order[1]), int(order[50]), int(order[400])]
+    u0, v0 = int(g.src[123]), int(g.dst[123])
+    cand += [u0, v0]
+    loops = g.src[g.src == g.dst]
+    if loops.shape[0]:
+        cand.append(int(loops[0]))
+    dn = np.array(sorted({x for x in cand if x != s}), np.int32)
+    rng = np.random.default_rng(5)
+    E = np.zeros(0, np.int32)
+    # edge entries elsewhere in the same batch (none names a deleted node)
+    es, ed = (g.pair_u, g.pair_v) if undirected else (g.src, g.dst)
+    model = EdgeSetModel(g.n, es, ed, undirected=undirected)
+    ins_s, ins_d = [], []
+    while len(ins_s) < 10:
+        u, v = (int(x) for x in rng.integers(0, g.n, 2))
+        if u == v or u in dn or v in dn or model.has(u, v) or (u, v) in zip(ins_s, ins_d) or \
+                (undirected and (v, u) in zip(ins_s, ins_d)):
+            continue
+        ins_s.append(u)
+        ins_d.append(v)
+    b = Batch(np.array(ins_s, np.int32), np.array(ins_d, np.int32), E, E, 0, dn)
+    with rwr.Context(g.n, es, ed, [s], c=0.15, eps=1e-14, precision="fp64", build_tol=1e-13, err_budget=4e-13,
+                     undirected=undirected) as ctx:
+        n0, m0 = ctx.n, ctx.m
+        st = ctx.update_batch(b)
+        n2, s2, d2 = oracle.apply_batch(g.n, g.src, g.dst, b, undirected=undirected)
+        # the running edge count (read before an export recounts it)
+        assert ctx.n == n0 and ctx.m == s2.shape[0], (m0, ctx.m, s2.shape[0])
+        ref = oracle.rwr_static(n2, s2, d2, s, 0.15)
+        assert _l1(ctx.scores(0), ref) < 1e-12, st
+        es, ed, _ = ctx.export()
+        assert set(zip(es.tolist(), ed.tolist())) == set(zip(s2.tolist(), d2.tolist()))
+        # deleting a node that has no edges left is allowed and changes nothing
+        before = ctx.scores(0)
+        ctx.update_batch(Batch(E, E, E, E, 0, dn[:1]))
+        assert _l1(ctx.scores(0), before) < 1e-13
+
+
+def test_node_deletion_rejections_leave_state_unchanged():
+    print("[node deletion errors]", flush=True)
+    g = rmat_graph(10, 5000, dead_end_self_loops=True)
+    s = int(np.argmax(g.out_degree()))
+    E = np.zeros(0, np.int32)
+    other = int(np.argsort(-g.out_degree())[3])
+    u, v = int(g.src[7]), int(g.dst[7])
+    bad = [
+        Batch(E, E, E, E, 0, np.array([s], np.int32)),                      # a seed
+        Batch(E, E, E, E, 0, np.array([other, other], np.int32)),           # listed twice
+        Batch(E, E, E, E, 0, np.array([g.n], np.int32)),                    # out of range
+        Batch(E, E, np.array([u], np.int32), np.array([v], np.int32), 0,    # edge names it
+              np.array([u if u != s else v], np.int32)),
+    ]
+    with _ctx(g, [s], eps=1e-10, precision="fp64", build_tol=1e-12) as ctx:
+        r0 = ctx.scores(0)
+        es0, ed0, _ = ctx.export()
+        for b in bad:
+            with pytest.raises(rwr.RwrError) as ei:
+                ctx.update_batch(b)
+            assert ei.value.code == -1
+        assert np.array_equal(ctx.scores(0), r0)
+        es, ed, _ = ctx.export()
+        assert np.array_equal(es, es0) and np.array_equal(ed, ed0)

@@ -337,3 +337,38 @@ def test_apply_batch_validation():
     # node deletion removes every incident edge
     n2, s2, d2 = oracle.apply_batch(3, src, dst, Batch(E, E, E, E), del_nodes=[1])
     assert n2 == 3 and set(zip(s2.tolist(), d2.tolist())) == {(2, 0)}
+    # ... and takes the list from the batch as well
+    n2, s2, d2 = oracle.apply_batch(3, src, dst, Batch(E, E, E, E, del_nodes=np.array([1], np.int32)))
+    assert set(zip(s2.tolist(), d2.tolist())) == {(2, 0)}
+    # deleted nodes: existing ids, listed once, not named by the batch's edges
+    for dn, b in (([3], Batch(E, E, E, E)), ([1, 1], Batch(E, E, E, E)),
+                  ([1], Batch(np.array([1], np.int32), np.array([0], np.int32), E, E)),
+                  ([2], Batch(E, E, np.array([2], np.int32), np.array([0], np.int32)))):
+        with pytest.raises(OracleError, match="EINVAL"):
+            oracle.apply_batch(3, src, dst, b, del_nodes=dn)
+
+
+def test_node_deletion_equals_deleting_its_edges_and_osp_stays_exact():
+    # Section 3.4.1: a deleted node's row and column become zero; Theorem 1:
+    # OSP from the old scores reaches the static scores of the new graph
+    rng = np.random.default_rng(11)
+    n = 60
+    pairs = {(int(u), int(v)) for u, v in rng.integers(0, n, size=(400, 2))}
+    pairs |= {(u, u) for u in range(n) if not any(a == u for a, _ in pairs)}
+    src = np.array([p[0] for p in sorted(pairs)], np.int32)
+    dst = np.array([p[1] for p in sorted(pairs)], np.int32)
+    E = np.zeros(0, np.int32)
+    gone = [3, 17, 18]
+    n2, s2, d2 = oracle.apply_batch(n, src, dst, Batch(E, E, E, E), del_nodes=gone)
+    inc = np.isin(src, gone) | np.isin(dst, gone)
+    n3, s3, d3 = oracle.apply_batch(n, src, dst, Batch(E, E, src[inc], dst[inc]))
+    assert n2 == n3 == n
+    assert set(zip(s2.tolist(), d2.tolist())) == set(zip(s3.tolist(), d3.tolist()))
+    assert not (np.isin(s2, gone) | np.isin(d2, gone)).any()
+    seed = 0
+    r_old = oracle.rwr_static(n, src, dst, seed, 0.15)
+    out = oracle.osp((n, src, dst), (n2, s2, d2), r_old, 0.15, 1e-15, renorm=oracle.core.RENORM_ALWAYS)
+    ref = oracle.rwr_static(n2, s2, d2, seed, 0.15)
+    assert np.abs(out["r_new"] - ref).sum() < 1e-12
+    # nothing reaches a deleted node any more
+    assert np.abs(ref[gone]).max() < 1e-15
