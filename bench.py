@@ -89,6 +89,8 @@ def main() -> int:
                     help="comma list of: eps1e-9 (headline), eps1e-6, exact; or all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the final oracle comparison")
+    ap.add_argument("--no-host-batches", action="store_true",
+                    help="skip the second headline run that hands batches over in host memory")
     ap.add_argument("--cpu-sample", type=int, default=3, help="updates timed on the CPU oracle")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one elementwise copy of MIB MiB (calibrates the traffic counters) and exit")
@@ -146,25 +148,48 @@ def main() -> int:
     }
     names = list(all_modes) if args.modes == "all" else args.modes.split(",")
     headline = names[0]
-    results = {}
-    final_ctx_scores = None
-    for name in names:
+
+    # the timed updates' batches, staged in HBM before the clock starts: one
+    # device array per field, each update passes views into them
+    def stage(batches):
+        cat = {}
+        for f in ("ins_src", "ins_dst", "del_src", "del_dst"):
+            parts = [getattr(b, f) for b in batches]
+            cat[f] = torch.as_tensor(np.concatenate(parts).astype(np.int32), device="cuda")
+        oi = np.concatenate([[0], np.cumsum([b.n_ins for b in batches])])
+        od = np.concatenate([[0], np.cumsum([b.n_del for b in batches])])
+        return [(cat["ins_src"][oi[i]:oi[i + 1]], cat["ins_dst"][oi[i]:oi[i + 1]],
+                 cat["del_src"][od[i]:od[i + 1]], cat["del_dst"][od[i]:od[i + 1]], b.n_new_nodes)
+                for i, b in enumerate(batches)]
+
+    dev_stream = stage(stream[W:W + K])
+
+    def run(name, host_batches=False, profile=False):
         mcfg = all_modes[name]
         t = time.time()
         ctx = rwr.Context(g.n, g.src, g.dst, seeds, c=c, eps=mcfg["eps"], err_budget=mcfg["err_budget"],
                           precision="fp32")
-        log(f"[{name}] context built in {time.time() - t:.2f}s")
+        log(f"[{name}{' host batches' if host_batches else ''}] context built in {time.time() - t:.2f}s")
         for b in stream[:W]:
             ctx.update_batch(b)
-        ctx.profile(name == headline)
+        ctx.profile(profile)
         ctx.profile_read(reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        stats = [ctx.update_batch(b) for b in stream[W:W + K]]
+        if host_batches:
+            stats = [ctx.update_batch(b) for b in stream[W:W + K]]
+        else:
+            stats = [ctx.update(*u[:4], n_new_nodes=u[4]) for u in dev_stream]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         prof = ctx.profile_read(reset=True)
-        el = t1 - t0
+        return ctx, stats, t1 - t0, prof
+
+    results = {}
+    final_ctx_scores = None
+    for name in names:
+        mcfg = all_modes[name]
+        ctx, stats, el, prof = run(name, profile=(name == headline))
         lat = np.array([s["ms_total"] for s in stats])
         iters = np.array([s["iters"] for s in stats])
         dense = np.array([s["dense_iters"] for s in stats])
@@ -184,17 +209,22 @@ def main() -> int:
         }
         if name == headline:
             res["prof"] = prof
-            n_now, m_now = ctx.n, None
             src_e, dst_e, _ = ctx.export()
-            m_now = int(src_e.shape[0])
-            res["n_final"], res["m_final"] = n_now, m_now
+            res["n_final"], res["m_final"] = ctx.n, int(src_e.shape[0])
             if not args.no_check:
                 final_ctx_scores = ctx.scores(0)
         log(f"[{name}] {res['updates_per_s']:.1f} updates/s, {res['ms_per_update']:.3f} ms/update, "
             f"iters {res['mean_iters']:.1f} (dense {res['mean_dense_sweeps']:.1f}), "
             f"checks {res['residual_checks']} refinements {res['refinements']}, bound {res['max_err_bound']:.2e}")
-        results[name] = res
         ctx.close()
+        if name == headline and not args.no_host_batches:
+            # the same updates with each batch handed over in host memory (one
+            # small host-to-device copy per update inside the call)
+            ctx, _, el_h, _ = run(name, host_batches=True)
+            res["host_batches_updates_per_s"] = K / el_h
+            log(f"[{name} host batches] {K / el_h:.1f} updates/s")
+            ctx.close()
+        results[name] = res
 
     H = results[headline]
     # roofline of the dominant kernel: the dense sweep (k_pull_mp, one pull

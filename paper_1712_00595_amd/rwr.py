@@ -152,6 +152,8 @@ class _Arr:
         elif on_device:
             import torch
 
+            if not _is_torch(a):
+                a = torch.as_tensor(np.asarray(a, dtype=np.int32), device="cuda")
             t = a if a.dtype == torch.int32 else a.to(torch.int32)
             self.keep = t.contiguous()
             self.ptr = self.keep.data_ptr()

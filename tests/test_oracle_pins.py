@@ -372,3 +372,32 @@ def test_node_deletion_equals_deleting_its_edges_and_osp_stays_exact():
     assert np.abs(out["r_new"] - ref).sum() < 1e-12
     # nothing reaches a deleted node any more
     assert np.abs(ref[gone]).max() < 1e-15
+
+
+def test_apply_stream_equals_batch_by_batch():
+    # the one-pass stream apply gives the same edge set as applying each
+    # batch in turn, and rejects a batch that is invalid at its position
+    from synth import EdgeSetModel, rmat_graph
+    from synth.stream import mixed_batch, single_edge_stream
+
+    g = rmat_graph(9, 3000, dead_end_self_loops=True)
+    model = EdgeSetModel(g.n, g.src, g.dst)
+    stream = single_edge_stream(model, 40)
+    rng = np.random.default_rng(3)
+    stream += [mixed_batch(rng, model, 15, 15, n_new_nodes=2) for _ in range(3)]
+    n, s, d = g.n, g.src, g.dst
+    for b in stream:
+        n, s, d = oracle.apply_batch(n, s, d, b)
+    n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream)
+    assert n2 == n and s2.shape[0] == s.shape[0]
+    assert set(zip(s.tolist(), d.tolist())) == set(zip(s2.tolist(), d2.tolist()))
+    E = np.zeros(0, np.int32)
+    # re-inserting an edge deleted earlier in the stream is valid; deleting it
+    # twice is not
+    dels = [b for b in stream if b.n_del == 1]
+    u, v = int(dels[0].del_src[0]), int(dels[0].del_dst[0])
+    again = Batch(np.array([u], np.int32), np.array([v], np.int32), E, E)
+    oracle.apply_stream(g.n, g.src, g.dst, stream + [again])
+    with pytest.raises(OracleError, match="ENOENT"):
+        oracle.apply_stream(g.n, g.src, g.dst, stream + [Batch(E, E, np.array([u], np.int32),
+                                                               np.array([v], np.int32))])
