@@ -64,6 +64,7 @@ struct rwr_ctx {
   int32_t *stamp = nullptr;
   int32_t *fstamp = nullptr;
   int32_t *nmark = nullptr;        // 1 on nodes that the current batch deletes (per node)
+  int32_t *row_order = nullptr;    // light in-rows by descending in-degree (S >= 4)
   int64_t *ndel = nullptr;         // node deletions: entry counts, then key offsets
   int64_t ndel_cap = 0;
   int32_t *hfront = nullptr;
@@ -97,7 +98,7 @@ struct rwr_ctx {
   void *temp = nullptr;
   size_t temp_bytes = 0;
   // tuning
-  int32_t grid_sparse = 512, grid_light = 2048, grid_pull = 2048, light_lanes = 16;
+  int32_t grid_sparse = 512, grid_light = 2048, grid_pull = 2048, light_lanes = 16, pull_lanes = 64;
   int32_t n_cu = 256;
   int32_t pull_ratio = 16;
   // error budget per seed column (normalised L1)
@@ -243,6 +244,9 @@ static SlotArgs slot_args(const rwr_ctx *c) {
   a.grid_light = c->grid_light;
   a.grid_pull = c->grid_pull;
   a.light_lanes = c->light_lanes;
+  a.pull_lanes = c->pull_lanes;
+  a.row_order = c->row_order;
+  a.n_order = c->n_cap;
   a.mp_rows = c->mp_rows;
   a.n_mp = c->n_mp;
   return a;
@@ -280,12 +284,14 @@ static void tune_defaults(rwr_ctx *c) {
     c->heavy_chunk = 2048;
   } else if (S <= 16) {
     c->heavy_limit = 256;
-    c->heavy_chunk = 1024;
+    c->heavy_chunk = 2048;
   } else {
     c->heavy_limit = 128;
-    c->heavy_chunk = 512;
+    c->heavy_chunk = 2048;
   }
+  c->pull_lanes = 16;
   if (const char *e = getenv("RWR_LIGHT_LANES")) c->light_lanes = atoi(e);
+  if (const char *e = getenv("RWR_PULL_LANES")) c->pull_lanes = atoi(e);
   if (const char *e = getenv("RWR_HEAVY_LIMIT")) c->heavy_limit = atoi(e);
   if (const char *e = getenv("RWR_HEAVY_CHUNK")) c->heavy_chunk = atoi(e);
   if (const char *e = getenv("RWR_PULL_RATIO")) c->pull_ratio = atoi(e);
@@ -293,8 +299,9 @@ static void tune_defaults(rwr_ctx *c) {
   // grids sized to the resident capacity: workgroups loop over their work
   c->grid_light = 4 * c->n_cu;
   c->grid_sparse = 4 * c->n_cu;
-  // the single-column sweep holds six workgroups per CU (registers)
-  c->grid_pull = (S == 1 ? 6 : 8) * c->n_cu;
+  // dense sweeps: the workgroups that fit on the chip at once (registers:
+  // six per CU for the single-column sweep, five for the vector sweep)
+  c->grid_pull = (S == 1 ? 6 : S == 2 ? 8 : 5) * c->n_cu;
   if (const char *e = getenv("RWR_GRID_LIGHT")) c->grid_light = atoi(e);
   if (const char *e = getenv("RWR_GRID_SPARSE")) c->grid_sparse = atoi(e);
   if (const char *e = getenv("RWR_GRID_PULL")) c->grid_pull = atoi(e);
@@ -331,7 +338,32 @@ static rwr_status plan_partition(rwr_ctx *c) {
 }
 
 // Heavy rows of the pull orientation: flag them, split them into chunks.
-static rwr_status plan_heavy(rwr_ctx *c) {
+// Order of the light in-rows for the multi-column sweep: every row once,
+// by descending in-degree, so that the row groups sharing a wavefront get
+// rows of about equal length.  Any permutation is correct; the order is
+// renewed only when the node capacity changes.
+static rwr_status plan_order(rwr_ctx *c) {
+  Orientation &o = c->g[pull_orient(c)];
+  std::vector<int32_t> len(c->n_cap);
+  D2H(c, len.data(), o.v.len, sizeof(int32_t) * c->n_cap);
+  const int32_t top = std::max(1, c->heavy_limit) + 1;
+  std::vector<int64_t> start(top + 1, 0);
+  for (int32_t v = 0; v < c->n_cap; ++v) ++start[top - std::min(len[v], top)];
+  int64_t acc = 0;
+  for (int32_t b = 0; b <= top; ++b) {
+    const int64_t t = start[b];
+    start[b] = acc;
+    acc += t;
+  }
+  std::vector<int32_t> order(c->n_cap);
+  for (int32_t v = 0; v < c->n_cap; ++v) order[start[top - std::min(len[v], top)]++] = v;
+  dev_free(c->row_order);
+  RWR_TRY(alloc_zero(c, &c->row_order, c->n_cap));
+  H2D(c, c->row_order, order.data(), sizeof(int32_t) * c->n_cap);
+  return RWR_OK;
+}
+
+static rwr_status plan_heavy(rwr_ctx *c, bool with_order = false) {
   Orientation &o = c->g[pull_orient(c)];
   HIP_TRY(c, hipMemsetAsync(c->sel_count, 0, sizeof(int32_t), c->stream));
   launch_mark_heavy(o.v.len, c->n, c->heavy_limit, o.v.heavy, c->sel, c->sel_count, c->stream);
@@ -382,6 +414,7 @@ static rwr_status plan_heavy(rwr_ctx *c) {
   c->h_items = items;
   c->h_nrows = count;
   if (c->S == 1) RWR_TRY(plan_partition(c));
+  if (c->S >= 4 && (with_order || !c->row_order)) RWR_TRY(plan_order(c));
   return ensure_partials(c);
 }
 
@@ -437,7 +470,7 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
   launch_identity(c->perm, c->inv, old_cap, new_cap, c->stream);
   c->n_cap = new_cap;
   tune_defaults(c);
-  RWR_TRY(plan_heavy(c));
+  RWR_TRY(plan_heavy(c, true));
   RWR_TRY(ensure_partials(c));
   return RWR_OK;
 }
@@ -845,7 +878,7 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   RWR_TRY(alloc_zero(c, &c->sel, (size_t)c->n_cap * 2));
   RWR_TRY(alloc_zero(c, &c->sel_count, 1));
   RWR_TRY(alloc_zero(c, &c->hist, (size_t)(c->max_iters + 2) * c->S));
-  RWR_TRY(plan_heavy(c));
+  RWR_TRY(plan_heavy(c, true));
   RWR_TRY(ensure_partials(c));
 
   // static scores: CPI from c*e_s (Section 2.2), then residual refinement
@@ -1237,6 +1270,9 @@ void rwr_destroy(rwr_ctx *c) {
   dev_free(c->x[1]);
   dev_free(c->stamp);
   dev_free(c->fstamp);
+  dev_free(c->nmark);
+  dev_free(c->ndel);
+  dev_free(c->row_order);
   dev_free(c->hfront);
   dev_free(c->hbase);
   dev_free(c->ctl);

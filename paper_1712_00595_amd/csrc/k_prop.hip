@@ -22,6 +22,8 @@
 // of the chip and loop over their work.
 #include <math.h>
 
+#include <type_traits>
+
 #include "rwr_common.h"
 #include "rwr_kernels.h"
 
@@ -451,6 +453,268 @@ __global__ __launch_bounds__(BLOCK) void k_pull(SlotArgs a, int k) {
   block_publish<S>(nrm, sm, 0, 0, a.part, a.part_i, blockIdx.x, sh);
 }
 
+// ------------------------------------------------ dense, S >= 4 columns
+// Each lane moves 16 bytes of a gathered row: V consecutive columns (V = 4
+// for FP32 vectors, 2 for FP64 vectors and for the residual's FP64 scores).
+// L = S / V lanes cover one edge's row; a group of G lanes works on one
+// in-row with P = G / L edge slots, each slot keeping four gathers in
+// flight.  Same sums and epilogue as k_pull, in the same fixed order per
+// column.
+// Streamed operands (adjacency, scores, the next vector) are touched once
+// per sweep: load and store them non-temporally so that the caches keep the
+// gathered rows of the current vector.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int32_t nt_load(const int32_t *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ nt_d2 nt_load2(const double *p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(p));
+}
+__device__ __forceinline__ void nt_store2(double *p, double a, double b) {
+  nt_d2 v = {a, b};
+  __builtin_nontemporal_store(v, reinterpret_cast<nt_d2 *>(p));
+}
+__device__ __forceinline__ void nt_store4(float *p, float a, float b, float c, float d) {
+  nt_f4 v = {a, b, c, d};
+  __builtin_nontemporal_store(v, reinterpret_cast<nt_f4 *>(p));
+}
+
+template <typename XT, int KIND>
+struct VecGather {
+  using GT = typename std::conditional<KIND == KIND_RESID, double, XT>::type;
+  static constexpr int V = 16 / (int)sizeof(GT);
+  using VT = typename std::conditional<sizeof(GT) == 4, float4, double2>::type;
+};
+
+template <typename XT, int S, int KIND>
+__device__ __forceinline__ void gather_vec(const SlotArgs &a, const XT *__restrict__ x, int u, int j0,
+                                           double (&g)[VecGather<XT, KIND>::V]) {
+  using VG = VecGather<XT, KIND>;
+  if constexpr (KIND == KIND_RESID) {
+    const double2 t = *reinterpret_cast<const double2 *>(a.r + col_index(u, S, j0));
+    const double dl = (double)a.out.len[u];
+    g[0] = t.x / dl;
+    g[1] = t.y / dl;
+  } else if constexpr (VG::V == 4) {
+    const float4 t = *reinterpret_cast<const float4 *>(x + col_index(u, S, j0));
+    g[0] = t.x;
+    g[1] = t.y;
+    g[2] = t.z;
+    g[3] = t.w;
+  } else {
+    const double2 t = *reinterpret_cast<const double2 *>(x + col_index(u, S, j0));
+    g[0] = t.x;
+    g[1] = t.y;
+  }
+}
+
+// the row's scores, loaded when the row starts so that the load overlaps the
+// gathers
+template <int S, int V>
+__device__ __forceinline__ void load_scores_vec(const SlotArgs &a, int v, int j0, double (&rv)[V]) {
+  const int64_t kk = col_index(v, S, j0);
+#pragma unroll
+  for (int q = 0; q < V; q += 2) {
+    const nt_d2 t = nt_load2(a.r + kk + q);
+    rv[q] = t.x;
+    rv[q + 1] = t.y;
+  }
+}
+
+template <typename XT, int S, int KIND, int V>
+__device__ __forceinline__ void pull_epilogue_vec(const SlotArgs &a, XT *__restrict__ xnext, int v, int j0,
+                                                  const double (&y)[V], double (&rv)[V], const bool (&act)[V],
+                                                  double (&nrm)[V], double (&sm)[V]) {
+  const int64_t kk = col_index(v, S, j0);
+  if constexpr (KIND == KIND_RESID) {
+    double g[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      g[q] = y[q] - rv[q];
+      if (j0 + q >= a.n_seeds || a.seeds[j0 + q] == v) g[q] = 0.0;
+      nrm[q] += fabs(g[q]);
+      sm[q] += rv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < V; q += 2) nt_store2(a.gbuf + kk + q, g[q], g[q + 1]);
+  } else {
+    const int d = a.out.len[v];
+    XT xo[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      if (act[q]) {
+        rv[q] += y[q];
+        nrm[q] += fabs(y[q]);
+        sm[q] += y[q];
+        xo[q] = d ? (XT)(y[q] / (double)d) : (XT)0;
+      } else {
+        xo[q] = (XT)0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < V; q += 2) nt_store2(a.r + kk + q, rv[q], rv[q + 1]);
+    if constexpr (V == 4) {
+      nt_store4(xnext + kk, xo[0], xo[1], xo[2], xo[3]);
+    } else {
+      nt_store2(xnext + kk, xo[0], xo[1]);
+    }
+  }
+}
+
+// block_publish for lanes holding V columns each (lane l of a group of L
+// holds columns l*V .. l*V+V-1)
+template <int S, int V>
+__device__ void block_publish_vec(double (&nrm)[V], double (&sm)[V], double *part, int64_t *part_i, int e,
+                                  BlockRed &sh) {
+  constexpr int L = S / V;
+  const int lane = threadIdx.x % RWR_WAVE, w = threadIdx.x / RWR_WAVE;
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    nrm[q] = wave_xor_sum(nrm[q], L, RWR_WAVE);
+    sm[q] = wave_xor_sum(sm[q], L, RWR_WAVE);
+  }
+  if (lane < L) {
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      sh.wn[w][lane * V + q] = nrm[q];
+      sh.ws[w][lane * V + q] = sm[q];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < S) {
+    double x = 0.0, y = 0.0;
+    for (int ww = 0; ww < NWAVES; ++ww) x += sh.wn[ww][threadIdx.x], y += sh.ws[ww][threadIdx.x];
+    part[e * entry_stride<S>() + 2 * threadIdx.x] = x;
+    part[e * entry_stride<S>() + 2 * threadIdx.x + 1] = y;
+  }
+  if (threadIdx.x == 0) {
+    part_i[(int64_t)e * 16] = 0;
+    part_i[(int64_t)e * 16 + 1] = 0;
+  }
+}
+
+// One chunk of a heavy in-row for S >= 4: the workgroup's BLOCK / L edge
+// slots each move 16 bytes per lane, four gathers in flight per slot; slot
+// sums are added in a fixed order (shuffle tree in each wave, then the
+// waves in index order).
+template <typename XT, int S, int KIND>
+__device__ __forceinline__ void heavy_item_vec(const SlotArgs &a, int item, const XT *__restrict__ xcur,
+                                               double (*hred)[RWR_MAX_COLS]) {
+  constexpr int V = VecGather<XT, KIND>::V;
+  constexpr int L = S / V;
+  constexpr int SLOTS = BLOCK / L;
+  const int lane = threadIdx.x % RWR_WAVE, w = threadIdx.x / RWR_WAVE;
+  const int slot = threadIdx.x / L, j0 = (threadIdx.x % L) * V;
+  const int h = a.heavy.item_row[item], ck = a.heavy.item_chunk[item];
+  const int v = a.heavy.rows[h];
+  const int nch = a.heavy.nchunks[h];
+  const int o = a.in.off[v], d = a.in.len[v];
+  const int e0 = ck * a.heavy.chunk;
+  const int e1 = (ck == nch - 1) ? d : min(d, e0 + a.heavy.chunk);
+  const int32_t *__restrict__ adj = a.in.adj + o;
+  double acc[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) acc[q] = 0.0;
+  for (int e = e0 + slot; e < e1; e += 4 * SLOTS) {
+    int uu[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) uu[t] = e + t * SLOTS < e1 ? nt_load(adj + e + t * SLOTS) : -1;
+    double g[4][V];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (uu[t] >= 0) {
+        gather_vec<XT, S, KIND>(a, xcur, uu[t], j0, g[t]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < V; ++q) g[t][q] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < V; ++q) acc[q] += (g[0][q] + g[1][q]) + (g[2][q] + g[3][q]);
+  }
+#pragma unroll
+  for (int q = 0; q < V; ++q) acc[q] = wave_xor_sum(acc[q], L, RWR_WAVE);
+  if (lane < L) {
+#pragma unroll
+    for (int q = 0; q < V; ++q) hred[w][j0 + q] = acc[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < S) {
+    double t = 0.0;
+    for (int ww = 0; ww < NWAVES; ++ww) t += hred[ww][threadIdx.x];
+    a.heavy.part[(int64_t)item * S + threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+template <typename XT, int S, int G, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_pull_v(SlotArgs a, int k) {
+  constexpr int V = VecGather<XT, KIND>::V;
+  constexpr int L = S / V;
+  constexpr int P = G / L;
+  static_assert(L >= 1 && G % L == 0 && G <= RWR_WAVE && P >= 1, "lane layout");
+  __shared__ BlockRed sh;
+  __shared__ double hred[NWAVES][RWR_MAX_COLS];
+  Ctl *ctl = a.ctl;
+  if (KIND == KIND_DENSE && ctl->mode != MODE_DENSE) return;
+  const XT *__restrict__ xcur = (const XT *)a.x[(k - 1) & 1];
+  XT *__restrict__ xnext = (XT *)a.x[k & 1];
+  const double c1 = 1.0 - a.c;
+  const int lane = threadIdx.x % RWR_WAVE;
+  for (int item = blockIdx.x; item < a.heavy.n_items; item += gridDim.x)
+    heavy_item_vec<XT, S, KIND>(a, item, xcur, hred);
+  const int gl = lane % G, p = gl / L, j0 = (gl % L) * V;
+  constexpr int GPB = BLOCK / G;
+  bool act[V];
+  double nrm[V], sm[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    act[q] = ctl->active[j0 + q] != 0;
+    nrm[q] = 0.0;
+    sm[q] = 0.0;
+  }
+  const int ngroups = gridDim.x * GPB;
+  for (int i = blockIdx.x * GPB + threadIdx.x / G; i < a.n_order; i += ngroups) {
+    const int v = a.row_order[i];
+    if (v >= a.n || a.in.heavy[v]) continue;
+    const int o = a.in.off[v], d = a.in.len[v];
+    const int32_t *__restrict__ adj = a.in.adj + o;
+    double rv[V];
+    if (p == 0) load_scores_vec<S, V>(a, v, j0, rv);
+    double acc[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) acc[q] = 0.0;
+    for (int e = p; e < d; e += 4 * P) {
+      int uu[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) uu[t] = e + t * P < d ? nt_load(adj + e + t * P) : -1;
+      double g[4][V];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (uu[t] >= 0) {
+          gather_vec<XT, S, KIND>(a, xcur, uu[t], j0, g[t]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < V; ++q) g[t][q] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q) acc[q] += (g[0][q] + g[1][q]) + (g[2][q] + g[3][q]);
+    }
+#pragma unroll
+    for (int off = L; off < G; off <<= 1) {
+#pragma unroll
+      for (int q = 0; q < V; ++q) acc[q] += __shfl_xor(acc[q], off, RWR_WAVE);
+    }
+    if (p == 0) {
+      double y[V];
+#pragma unroll
+      for (int q = 0; q < V; ++q) y[q] = c1 * acc[q];
+      pull_epilogue_vec<XT, S, KIND, V>(a, xnext, v, j0, y, rv, act, nrm, sm);
+    }
+  }
+  block_publish_vec<S, V>(nrm, sm, a.part, a.part_i, blockIdx.x, sh);
+}
+
 #define MP_ROWS 256
 #define MP_PER_THREAD 8
 #define MP_ROUND (MP_PER_THREAD * BLOCK)
@@ -823,10 +1087,21 @@ static void pull_impl(const SlotArgs &a, int k, hipStream_t st, hipEvent_t ev0 =
   if constexpr (S == 1) {
     grid = std::max(1, std::min(a.heavy.n_items + a.n_mp, a.grid_pull));
     hipLaunchKernelGGL((k_pull_mp<XT, KIND>), dim3(grid), dim3(BLOCK), 0, st, a, k);
+  } else if constexpr (S == 2) {
+    grid = a.grid_pull;
+    hipLaunchKernelGGL((k_pull<XT, S, 16, KIND>), dim3(grid), dim3(BLOCK), 0, st, a, k);
   } else {
     grid = a.grid_pull;
-    constexpr int G = S >= 8 ? 64 : 8 * S;
-    hipLaunchKernelGGL((k_pull<XT, S, G, KIND>), dim3(grid), dim3(BLOCK), 0, st, a, k);
+    // lanes per in-row: 16, 32 or 64, at least one edge's row
+    constexpr int L = S / VecGather<XT, KIND>::V;
+    const int g = std::max(a.pull_lanes, L);
+    if (g <= 16 && L <= 16) {
+      hipLaunchKernelGGL((k_pull_v<XT, S, (L <= 16 ? 16 : L), KIND>), dim3(grid), dim3(BLOCK), 0, st, a, k);
+    } else if (g <= 32 && L <= 32) {
+      hipLaunchKernelGGL((k_pull_v<XT, S, (L <= 32 ? 32 : L), KIND>), dim3(grid), dim3(BLOCK), 0, st, a, k);
+    } else {
+      hipLaunchKernelGGL((k_pull_v<XT, S, 64, KIND>), dim3(grid), dim3(BLOCK), 0, st, a, k);
+    }
   }
   if (ev1) (void)hipEventRecord(ev1, st);
   int hgrid = 0;

@@ -58,7 +58,10 @@ struct SlotArgs {
   int32_t grid_sparse;
   int32_t grid_light;
   int32_t grid_pull;  // workgroups of a dense sweep (each loops over items)
-  int32_t light_lanes;  // lanes per row of the light pull (S > 1)
+  int32_t light_lanes;  // lanes per row of the light push
+  int32_t pull_lanes;   // lanes per in-row of the dense sweep for S >= 4 (16, 32 or 64)
+  const int32_t *row_order;  // order of the in-rows in that sweep (a permutation of 0 .. n_cap-1)
+  int32_t n_order;           // its length (n_cap)
   const int32_t *mp_rows;  // row partition of the single-column dense sweep
   int32_t n_mp;            // workgroups of that partition
 };

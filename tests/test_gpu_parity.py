@@ -340,3 +340,63 @@ def test_node_deletion_rejections_leave_state_unchanged():
         assert np.array_equal(ctx.scores(0), r0)
         es, ed, _ = ctx.export()
         assert np.array_equal(es, es0) and np.array_equal(ed, ed0)
+
+
+# ------------------------------------------------- vectorised multi-column sweep
+
+@pytest.mark.parametrize("n_seeds,prec,lanes", [
+    (5, "fp32", 32), (9, "fp64", 32), (9, "fp32", 16), (20, "fp32", 64), (20, "fp64", 64),
+    (64, "fp32", 16), (64, "fp32", 32), (64, "fp64", 64), (33, "fp32", 64),
+])
+def test_multi_column_sweep(monkeypatch, n_seeds, prec, lanes):
+    # S = 8 .. 64 columns (padded), every lane layout of the dense sweep; each
+    # column against the oracle's static scores of G + Delta G
+    print(f"[multi-column] seeds={n_seeds} prec={prec} lanes={lanes}", flush=True)
+    monkeypatch.setenv("RWR_PULL_LANES", str(lanes))
+    from synth.rmat import sample_seeds
+
+    g = rmat_graph(12, 40000, dead_end_self_loops=True)
+    seeds = sample_seeds(g, n_seeds, seed=3)
+    rng = np.random.default_rng(n_seeds)
+    b = _batch(rng, g.n, g.src, g.dst, 200, 200, n_new=3)
+    if prec == "fp64":
+        kw = dict(eps=1e-13, err_budget=1e-11, build_tol=1e-12)
+        gate = 1e-11
+    else:
+        kw = dict(eps=1e-8)
+        gate = 2 * 1e-8 / 0.15
+    with _ctx(g, seeds, precision=prec, **kw) as ctx:
+        b1 = b
+        n1, s1, d1 = oracle.apply_batch(g.n, g.src, g.dst, b1)
+        b2 = _batch(rng, n1, s1, d1, 50, 50)
+        n2, s2, d2 = oracle.apply_batch(n1, s1, d1, b2)
+        ctx.update_batch(b1)
+        ctx.update_batch(b2)
+        for j, s in enumerate(seeds):
+            ref = oracle.rwr_static(n2, s2, d2, int(s), 0.15)
+            assert _l1(ctx.scores(j), ref) <= gate, (j, _l1(ctx.scores(j), ref))
+
+
+@pytest.mark.parametrize("n_seeds,prec", [(9, "fp32"), (64, "fp32"), (20, "fp64")])
+def test_multi_column_heavy_chunks(monkeypatch, n_seeds, prec):
+    # many heavy in-rows cut into many short chunks (limit 16, chunk 32)
+    print(f"[multi-column heavy] seeds={n_seeds} prec={prec}", flush=True)
+    monkeypatch.setenv("RWR_HEAVY_LIMIT", "16")
+    monkeypatch.setenv("RWR_HEAVY_CHUNK", "32")
+    from synth.rmat import sample_seeds
+
+    g = rmat_graph(11, 30000, dead_end_self_loops=True)
+    seeds = sample_seeds(g, n_seeds, seed=3)
+    rng = np.random.default_rng(1)
+    b = _batch(rng, g.n, g.src, g.dst, 300, 300, n_new=2)
+    kw = dict(eps=1e-13, err_budget=1e-11, build_tol=1e-12) if prec == "fp64" else dict(eps=1e-8)
+    gate = 1e-11 if prec == "fp64" else 2 * 1e-8 / 0.15
+    with _ctx(g, seeds, precision=prec, **kw) as ctx:
+        for j, s in enumerate(seeds):
+            ref = oracle.rwr_static(g.n, g.src, g.dst, int(s), 0.15)
+            assert _l1(ctx.scores(j), ref) <= gate
+        ctx.update_batch(b)
+        n2, s2, d2 = oracle.apply_batch(g.n, g.src, g.dst, b)
+        for j, s in enumerate(seeds):
+            ref = oracle.rwr_static(n2, s2, d2, int(s), 0.15)
+            assert _l1(ctx.scores(j), ref) <= gate, j
