@@ -183,6 +183,48 @@ void rwr_destroy(rwr_ctx *ctx);
  * ctx is NULL).  The string lives until the next call on the same context. */
 const char *rwr_last_error(const rwr_ctx *ctx);
 
+/* ---------------------------------------------------------------------
+ * Learned warm start (an addition to the paper's method).
+ *
+ * A small message-passing network predicts the offset result
+ * r_offset = sum_i x^(i) of Section 3.1 on a region around the offset seed;
+ * the update then propagates the exact residual
+ *   rho = q_offset - (I - (1-c) B~^T) xhat,
+ * so that r_offset = xhat + sum_i ((1-c) B~^T)^i rho holds identically and
+ * the scores and bounds are those of Algorithm 1 (Theorems 1 and 3).
+ *
+ * Network: per (node, seed column) row, 16 input features -> ReLU(F W0 + b0)
+ * (64 wide) -> three layers h' = ReLU(h Ws + a Wm + b) with
+ * a(v) = sum over in-edges u -> v inside the region of (h(u) Wp) / d_out(u)
+ * (16 wide) -> o = h wo + bo; xhat(v, j) = ||q_offset(:, j)||_1 o(v, j).
+ * Parameters are one float32 vector in the order
+ *   W0[16x64] b0[64] {Wp[64x16] Ws[64x64] Wm[16x64] b[64]} x 3 wo[64] bo[1]
+ * (row-major).  Products run on the matrix cores with bfloat16 operands and
+ * float32 accumulation; everything else in float32.
+ * ------------------------------------------------------------------- */
+
+/* Number of float32 parameters of the network (19777). */
+int64_t rwr_gnn_num_params(void);
+
+/* Evaluate the network once on an explicit region of nR nodes and S columns
+ * (host arrays): in-rows (in_off/in_len/in_adj, local ids, n_in entries) and
+ * out-rows (out_off/out_len/out_adj, n_out entries) of the region graph,
+ * dinv[nR] = 1/d_out of each node in the whole graph (0 for dead ends),
+ * feats[nR*S*16] (row = node*S + column).  Writes out[nR*S] = o when out is
+ * not NULL.  With target[nR*S] and active[S] (1: the column counts) it also
+ * computes the Huber loss (delta 1e-3, mean over active columns of the sum
+ * over rows) into *loss and its gradient into grad[rwr_gnn_num_params()],
+ * and with params_after not NULL one AdamW step from zero moments
+ * (lr 1e-3, betas 0.9/0.999, eps 1e-8, weight decay 1e-4).  For testing the
+ * network against a reference; runs on the current device, allocates and
+ * frees its own buffers.  RWR_EINVAL on malformed input (ids out of range,
+ * rows past n_in/n_out); the message is rwr_last_error(NULL). */
+rwr_status rwr_gnn_eval(const float *params, int32_t nR, int32_t S, const int32_t *in_off, const int32_t *in_len,
+                        const int32_t *in_adj, int64_t n_in, const int32_t *out_off, const int32_t *out_len,
+                        const int32_t *out_adj, int64_t n_out, const float *dinv, const float *feats,
+                        const float *target, const int32_t *active, float *out, float *grad, double *loss,
+                        float *params_after);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "gnn.h"
 #include "rwr.h"
 #include "rwr_common.h"
 #include "rwr_kernels.h"
@@ -1331,5 +1332,109 @@ rwr_status rwr_profile_read(rwr_ctx *c, double *dense_ms, int64_t *dense_sweeps,
 }
 
 const char *rwr_last_error(const rwr_ctx *c) { return c ? c->err.c_str() : g_build_error.c_str(); }
+
+int64_t rwr_gnn_num_params(void) { return gnn::LAYOUT.total; }
+
+rwr_status rwr_gnn_eval(const float *params, int32_t nR, int32_t S, const int32_t *in_off, const int32_t *in_len,
+                        const int32_t *in_adj, int64_t n_in, const int32_t *out_off, const int32_t *out_len,
+                        const int32_t *out_adj, int64_t n_out, const float *dinv, const float *feats,
+                        const float *target, const int32_t *active, float *out, float *grad, double *loss,
+                        float *params_after) {
+  g_build_error.clear();
+  if (!params || nR <= 0 || S < 1 || S > RWR_MAX_COLS || !in_off || !in_len || (n_in > 0 && !in_adj) ||
+      !out_off || !out_len || (n_out > 0 && !out_adj) || !dinv || !feats || n_in < 0 || n_out < 0) {
+    g_build_error = "invalid arguments";
+    return RWR_EINVAL;
+  }
+  if ((target == nullptr) != (active == nullptr) || ((grad || loss || params_after) && !target)) {
+    g_build_error = "gradients need a target and active columns";
+    return RWR_EINVAL;
+  }
+  for (int32_t i = 0; i < nR; ++i) {
+    if (in_len[i] < 0 || out_len[i] < 0 || in_off[i] < 0 || out_off[i] < 0 || in_off[i] + (int64_t)in_len[i] > n_in ||
+        out_off[i] + (int64_t)out_len[i] > n_out) {
+      g_build_error = "region rows out of range";
+      return RWR_EINVAL;
+    }
+  }
+  for (int64_t e = 0; e < n_in; ++e)
+    if (in_adj[e] < 0 || in_adj[e] >= nR) {
+      g_build_error = "region adjacency id out of range";
+      return RWR_EINVAL;
+    }
+  for (int64_t e = 0; e < n_out; ++e)
+    if (out_adj[e] < 0 || out_adj[e] >= nR) {
+      g_build_error = "region adjacency id out of range";
+      return RWR_EINVAL;
+    }
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    g_build_error = "hipStreamCreate failed";
+    return RWR_EHIP;
+  }
+  const int64_t rows = (int64_t)nR * S;
+  gnn::Net net;
+  std::vector<void *> tmp;
+  rwr_status ret = RWR_OK;
+  auto up = [&](const void *h, size_t bytes) -> void * {
+    void *d = nullptr;
+    if (hipMalloc(&d, std::max<size_t>(bytes, 4)) != hipSuccess) return nullptr;
+    tmp.push_back(d);
+    if (bytes && hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return nullptr;
+    return d;
+  };
+  do {
+    if (gnn::net_alloc(net, S, rows) != hipSuccess || gnn::net_set_params(net, params, st) != hipSuccess) {
+      ret = RWR_ENOMEM;
+      break;
+    }
+    gnn::RegionView g{};
+    g.in_off = (const int32_t *)up(in_off, sizeof(int32_t) * nR);
+    g.in_len = (const int32_t *)up(in_len, sizeof(int32_t) * nR);
+    g.in_adj = (const int32_t *)up(in_adj, sizeof(int32_t) * n_in);
+    g.out_off = (const int32_t *)up(out_off, sizeof(int32_t) * nR);
+    g.out_len = (const int32_t *)up(out_len, sizeof(int32_t) * nR);
+    g.out_adj = (const int32_t *)up(out_adj, sizeof(int32_t) * n_out);
+    g.dinv = (const float *)up(dinv, sizeof(float) * nR);
+    g.loc = nullptr;
+    g.nodes = nullptr;
+    g.nR = nR;
+    if (!g.in_off || !g.in_len || !g.in_adj || !g.out_off || !g.out_len || !g.out_adj || !g.dinv ||
+        hipMemcpyAsync(net.F, feats, sizeof(float) * rows * gnn::FEAT, hipMemcpyHostToDevice, st) != hipSuccess) {
+      ret = RWR_ENOMEM;
+      break;
+    }
+    gnn::net_forward(net, g, rows, st);
+    if (target) {
+      int n_act = 0;
+      std::vector<int32_t> act(RWR_MAX_COLS, 0);
+      for (int j = 0; j < S; ++j) n_act += (act[j] = active[j] ? 1 : 0);
+      if (hipMemcpyAsync(net.t, target, sizeof(float) * rows, hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(net.active, act.data(), sizeof(int32_t) * RWR_MAX_COLS, hipMemcpyHostToDevice, st) !=
+              hipSuccess) {
+        ret = RWR_EHIP;
+        break;
+      }
+      gnn::net_loss(net, rows, n_act, st);
+      gnn::net_backward(net, g, rows, st);
+      if (params_after) gnn::net_adamw(net, st);
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) {
+      ret = RWR_EHIP;
+      break;
+    }
+    if (out && hipMemcpy(out, net.o, sizeof(float) * rows, hipMemcpyDeviceToHost) != hipSuccess) ret = RWR_EHIP;
+    if (grad && hipMemcpy(grad, net.grad, sizeof(float) * gnn::LAYOUT.total, hipMemcpyDeviceToHost) != hipSuccess)
+      ret = RWR_EHIP;
+    if (loss && hipMemcpy(loss, net.loss, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) ret = RWR_EHIP;
+    if (params_after && gnn::net_get_params(net, params_after, st) != hipSuccess) ret = RWR_EHIP;
+  } while (false);
+  (void)hipStreamSynchronize(st);
+  for (void *p : tmp) (void)hipFree(p);
+  gnn::net_free(net);
+  (void)hipStreamDestroy(st);
+  if (ret != RWR_OK && g_build_error.empty()) g_build_error = "device error in rwr_gnn_eval";
+  return ret;
+}
 
 }  // extern "C"

@@ -43,6 +43,8 @@ EXPORTED = [
     "rwr_profile_read",
     "rwr_destroy",
     "rwr_last_error",
+    "rwr_gnn_num_params",
+    "rwr_gnn_eval",
 ]
 
 
@@ -129,9 +131,12 @@ def load_library(path: str = LIB_PATH):
     L.rwr_destroy.restype = None
     L.rwr_last_error.argtypes = [p]
     L.rwr_last_error.restype = ctypes.c_char_p
+    L.rwr_gnn_num_params.argtypes = []
+    L.rwr_gnn_num_params.restype = i64
+    L.rwr_gnn_eval.argtypes = [p, i32, i32, p, p, p, i64, p, p, p, i64, p, p, p, p, p, p, p, p]
     for name in EXPORTED:
         f = getattr(L, name)
-        if name not in ("rwr_destroy", "rwr_last_error"):
+        if name not in ("rwr_destroy", "rwr_last_error", "rwr_gnn_num_params"):
             f.restype = ctypes.c_int
     _lib = L
     return L
@@ -335,3 +340,57 @@ class Context:
         _check(self._lib, self._ctx,
                self._lib.rwr_last_norms(self._ctx, int(j), out.ctypes.data, ln.value, ctypes.byref(ln)))
         return out
+
+
+def _csr(n: int, a: np.ndarray, b: np.ndarray):
+    """Rows of the edges (a[e], b[e]) grouped by a, in edge order: off, len, adj."""
+    a = np.asarray(a, np.int64)
+    b = np.asarray(b, np.int32)
+    order = np.argsort(a, kind="stable")
+    cnt = np.bincount(a, minlength=n).astype(np.int32)
+    off = np.concatenate([[0], np.cumsum(cnt)[:-1]]).astype(np.int32)
+    return off, cnt, np.ascontiguousarray(b[order])
+
+
+def gnn_eval(params, nR: int, S: int, src, dst, dinv, feats, target=None, active=None, *, adam_step: bool = False):
+    """Run the warm-start network on one explicit region (see rwr_gnn_eval).
+
+    ``src``/``dst`` are the region's edges u -> v in local ids.  Returns a
+    dict with ``out`` (nR, S) and, with a target, ``loss``, ``grad`` and (if
+    ``adam_step``) ``params_after``."""
+    L = load_library()
+    P = int(L.rwr_gnn_num_params())
+    th = np.ascontiguousarray(np.asarray(params, np.float32))
+    if th.shape != (P,):
+        raise ValueError(f"expected {P} parameters")
+    in_off, in_len, in_adj = _csr(nR, dst, src)   # in-row of v lists its sources u
+    out_off, out_len, out_adj = _csr(nR, src, dst)
+    dv = np.ascontiguousarray(np.asarray(dinv, np.float32))
+    F = np.ascontiguousarray(np.asarray(feats, np.float32).reshape(nR * S, -1))
+    out = np.zeros(nR * S, np.float32)
+    res = {}
+    tg = act = grad = loss = after = None
+    if target is not None:
+        tg = np.ascontiguousarray(np.asarray(target, np.float32).reshape(-1))
+        act = np.ascontiguousarray(np.asarray(active, np.int32))
+        grad = np.zeros(P, np.float32)
+        loss = ctypes.c_double(0.0)
+        if adam_step:
+            after = np.zeros(P, np.float32)
+
+    def ptr(x):
+        return None if x is None else x.ctypes.data
+
+    code = L.rwr_gnn_eval(
+        ptr(th), int(nR), int(S), ptr(in_off), ptr(in_len), ptr(in_adj), int(in_adj.shape[0]), ptr(out_off),
+        ptr(out_len), ptr(out_adj), int(out_adj.shape[0]), ptr(dv), ptr(F), ptr(tg), ptr(act), ptr(out),
+        ptr(grad), ctypes.byref(loss) if loss is not None else None, ptr(after),
+    )
+    _check(L, None, code)
+    res["out"] = out.reshape(nR, S)
+    if target is not None:
+        res["loss"] = loss.value
+        res["grad"] = grad
+        if adam_step:
+            res["params_after"] = after
+    return res
