@@ -105,6 +105,12 @@ typedef struct rwr_stats {
   double err_bound;       /* L1 error bound of the scores after this update                */
   double residual_l1;     /* ||residual||_1 when checked, else 0                           */
   double ms_total;        /* wall time of the call (host clock)                            */
+  /* learned warm start (zero when it is off) */
+  int32_t ws_region;      /* region nodes the network ran on                               */
+  int32_t ws_accepted;    /* seed columns whose seed was replaced by the residual          */
+  double ws_resid_ratio;  /* sum_j ||rho_j||_1 / sum_j ||q_j||_1 of the prediction          */
+  double ws_loss;         /* training loss of this update, mean_j ||rho_j|| / ||q_j||      */
+  double ms_warm;         /* host wall time of the warm-start steps                        */
 } rwr_stats;
 
 /* Fill *cfg with defaults: c = 0.15, eps = 1e-9, FP32 propagation, directed,
@@ -205,6 +211,31 @@ const char *rwr_last_error(const rwr_ctx *ctx);
 
 /* Number of float32 parameters of the network (19777). */
 int64_t rwr_gnn_num_params(void);
+
+/* Set (copy from host) or read the context's network parameters.  Setting
+ * resets the optimiser state.  The first call allocates the warm-start
+ * buffers (capacity 2^21 rows unless rwr_warm_start chose another). */
+rwr_status rwr_model_set(rwr_ctx *ctx, const float *params, int64_t n);
+rwr_status rwr_model_get(rwr_ctx *ctx, float *params, int64_t cap);
+
+/* Switch the warm start of rwr_update:
+ *   mode 0: off;  1: predict (the update propagates the residual of the
+ *   prediction in every seed column where ||rho||_1 < ||q_offset||_1, else
+ *   the plain offset seed);  2: train (the update runs plainly; one AdamW
+ *   step on this update's loss mean_j ||rho_j||_1 / ||q_j||_1, the L1
+ *   distance of the prediction from the exact offset result measured
+ *   through I - (1-c) B~^T);  3: predict and train (the step follows the
+ *   prediction of this update).
+ * Before the residual is formed, the prediction is corrected so that the
+ * residual sums to zero (a residual with a non-zero sum decays only by
+ * (1-c) per iteration).
+ * hops (0..8): region = offset support plus the nodes within `hops`
+ * out-hops; a level that would take the region past max_rows / S nodes is
+ * left out (max_rows <= 0 selects 2^21 rows).  lr and weight_decay set
+ * AdamW's step size and decoupled decay.  Needs parameters (rwr_model_set);
+ * else RWR_ESTATE.  Scores stay those of Algorithm 1 in every mode. */
+rwr_status rwr_warm_start(rwr_ctx *ctx, int32_t mode, int32_t hops, int64_t max_rows, float lr,
+                          float weight_decay);
 
 /* Evaluate the network once on an explicit region of nR nodes and S columns
  * (host arrays): in-rows (in_off/in_len/in_adj, local ids, n_in entries) and

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librwr.so")
 ARCH = os.environ.get("RWR_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["k_delta.hip", "k_prop.hip", "k_graph.hip", "k_learn.hip", "capi.hip"]
+SOURCES = ["k_delta.hip", "k_prop.hip", "k_graph.hip", "k_learn.hip", "k_warm.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -17,6 +17,7 @@
 #include "rwr.h"
 #include "rwr_common.h"
 #include "rwr_kernels.h"
+#include "warm.h"
 
 namespace {
 
@@ -116,6 +117,24 @@ struct rwr_ctx {
   int prof_used = 0;
   double prof_dense_ms = 0.0;
   int64_t prof_dense_sweeps = 0, prof_idle = 0;
+  // learned warm start (rwr_warm_start)
+  struct Warm {
+    int32_t mode = 0, hops = 3;
+    int64_t max_rows = 0, max_nodes = 0;
+    gnn::Net net;
+    bool alloc = false, params = false;
+    int32_t *hop1 = nullptr, *loc1 = nullptr, *wmark = nullptr, *wlist = nullptr, *flags = nullptr;
+    int32_t *R = nullptr, *cnt = nullptr;  // cnt[0]: selected nodes, cnt[1]: touched nodes
+    float *dinv = nullptr;
+    double *xhat = nullptr, *wbuf = nullptr, *qn = nullptr, *part = nullptr, *sums = nullptr;
+    void *temp = nullptr;
+    size_t temp_bytes = 0;
+    // this update
+    int32_t nR = 0;
+    std::vector<double> qn_h;
+    int32_t accepted = 0;
+    double ratio = 0.0, loss = 0.0, ms = 0.0;
+  } ws;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -469,6 +488,21 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
   RWR_TRY(regrow((void **)&c->perm, 4, 1));
   RWR_TRY(regrow((void **)&c->inv, 4, 1));
   launch_identity(c->perm, c->inv, old_cap, new_cap, c->stream);
+  if (c->ws.alloc) {
+    RWR_TRY(regrow((void **)&c->ws.hop1, 4, 1));
+    RWR_TRY(regrow((void **)&c->ws.loc1, 4, 1));
+    RWR_TRY(regrow((void **)&c->ws.wmark, 4, 1));
+    RWR_TRY(regrow((void **)&c->ws.wlist, 4, 1));
+    RWR_TRY(regrow((void **)&c->ws.flags, 4, 1));
+    RWR_TRY(regrow((void **)&c->ws.wbuf, 8, c->S));
+    const size_t tb = ws_select_temp_bytes(new_cap);
+    if (tb > c->ws.temp_bytes) {
+      dev_free(c->ws.temp);
+      c->ws.temp = nullptr;
+      RWR_TRY(dev_alloc(c, &c->ws.temp, tb));
+      c->ws.temp_bytes = tb;
+    }
+  }
   c->n_cap = new_cap;
   tune_defaults(c);
   RWR_TRY(plan_heavy(c, true));
@@ -701,6 +735,164 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
                       8.0 * fpf * c->ctl_h->red_norm[j] / (cc * sig);
   }
   if (st) st->refined = 1;
+  return RWR_OK;
+}
+
+// ---------------------------------------------------------- warm start
+static void warm_free(rwr_ctx *c) {
+  rwr_ctx::Warm &w = c->ws;
+  dev_free(w.hop1);
+  dev_free(w.loc1);
+  dev_free(w.wmark);
+  dev_free(w.wlist);
+  dev_free(w.flags);
+  dev_free(w.R);
+  dev_free(w.cnt);
+  dev_free(w.dinv);
+  dev_free(w.xhat);
+  dev_free(w.wbuf);
+  dev_free(w.qn);
+  dev_free(w.part);
+  dev_free(w.sums);
+  if (w.temp) (void)hipFree(w.temp);
+  w.temp = nullptr;
+  w.temp_bytes = 0;
+  gnn::net_free(w.net);
+  w.alloc = false;
+  w.params = false;
+}
+
+static rwr_status warm_alloc(rwr_ctx *c, int64_t max_rows) {
+  rwr_ctx::Warm &w = c->ws;
+  w.max_rows = std::max<int64_t>(max_rows, c->S);
+  w.max_nodes = w.max_rows / c->S;
+  HIP_TRY(c, gnn::net_alloc(w.net, c->S, w.max_rows));
+  RWR_TRY(alloc_zero(c, &w.hop1, c->n_cap));
+  RWR_TRY(alloc_zero(c, &w.loc1, c->n_cap));
+  RWR_TRY(alloc_zero(c, &w.wmark, c->n_cap));
+  RWR_TRY(alloc_zero(c, &w.wlist, c->n_cap));
+  RWR_TRY(alloc_zero(c, &w.flags, c->n_cap));
+  RWR_TRY(alloc_zero(c, &w.wbuf, (size_t)c->n_cap * c->S));
+  RWR_TRY(alloc_zero(c, &w.R, w.max_nodes));
+  RWR_TRY(alloc_zero(c, &w.dinv, w.max_nodes));
+  RWR_TRY(alloc_zero(c, &w.xhat, w.max_rows));
+  RWR_TRY(alloc_zero(c, &w.cnt, 4));
+  RWR_TRY(alloc_zero(c, &w.qn, 2 * RWR_MAX_COLS));
+  RWR_TRY(alloc_zero(c, &w.sums, 3 * RWR_MAX_COLS));
+  RWR_TRY(alloc_zero(c, &w.part, (size_t)1024 * 2 * RWR_MAX_COLS));
+  w.temp_bytes = ws_select_temp_bytes(c->n_cap);
+  RWR_TRY(dev_alloc(c, &w.temp, w.temp_bytes));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  w.alloc = true;
+  return RWR_OK;
+}
+
+static gnn::RegionView warm_view(rwr_ctx *c) {
+  const rwr_ctx::Warm &w = c->ws;
+  const DevGraphView &in = c->g[pull_orient(c)].v;
+  const DevGraphView &out = c->g[0].v;
+  gnn::RegionView g{};
+  g.in_off = in.off;
+  g.in_len = in.len;
+  g.in_adj = in.adj;
+  g.out_off = out.off;
+  g.out_len = out.len;
+  g.out_adj = out.adj;
+  g.loc = w.loc1;
+  g.nodes = w.R;
+  g.dinv = w.dinv;
+  g.nR = w.nR;
+  return g;
+}
+
+// After the offset seed (q in ybuf, its support stamped) and the structural
+// update: the region (offset support and the nodes within `hops` out-hops,
+// level by level, a level that would exceed the capacity left out), the
+// features, the forward pass, the prediction and its exact residual.
+// Prediction on: the seed becomes the residual in every column where the
+// residual is smaller, and the scores take the prediction.  Training on: one
+// AdamW step on the loss mean_j ||rho_j||_1 / ||q_j||_1 of this prediction.
+static rwr_status warm_prepare(rwr_ctx *c) {
+  rwr_ctx::Warm &w = c->ws;
+  const double t0 = now_ms();
+  w.nR = 0;
+  w.accepted = 0;
+  w.ratio = 1.0;
+  w.loss = 0.0;
+  const int S = c->S;
+  const DevGraphView &in = c->g[pull_orient(c)].v;
+  const DevGraphView &out = c->g[0].v;
+  const int32_t st0 = c->ctl_h->stamp;
+  int32_t nR = 0, lvl_start = 0, n0 = 0;
+  for (int h = 0; h <= w.hops; ++h) {
+    if (h > 0) ws_expand(w.R + lvl_start, nR - lvl_start, out, h, w.hop1, c->stream);
+    ws_level_flags(c->stamp, st0, c->n, h, w.hop1, w.flags, c->stream);
+    HIP_TRY(c, ws_select(w.flags, c->n, w.wlist, w.cnt, w.temp, w.temp_bytes, c->stream));
+    int32_t k = 0;
+    D2H(c, &k, w.cnt, sizeof(int32_t));
+    if (nR + (int64_t)k > w.max_nodes) {
+      ws_unmark(w.wlist, k, w.hop1, c->stream);
+      break;
+    }
+    if (k > 0)
+      HIP_TRY(c, hipMemcpyAsync(w.R + nR, w.wlist, sizeof(int32_t) * k, hipMemcpyDeviceToDevice, c->stream));
+    if (h == 0) n0 = k;
+    lvl_start = nR;
+    nR += k;
+    if (k == 0) break;
+  }
+  w.nR = nR;
+  if (nR == 0 || n0 == 0) {
+    ws_clear(w.R, nR, w.hop1, w.loc1, c->stream);
+    w.nR = 0;
+    w.ms = now_ms() - t0;
+    return RWR_OK;
+  }
+  const int64_t rows = (int64_t)nR * S;
+  const double c1 = 1.0 - c->cfg.c;
+  ws_loc(w.R, nR, out, w.loc1, w.dinv, c->stream);
+  ws_qnorm(w.R, n0, S, c->ybuf, w.part, w.qn, c->stream);
+  ws_features(w.R, nR, S, w.hop1, in, out, c->ybuf, c->r, c->ctl, c->seeds_d, w.qn, c->n, w.net.F, c->stream);
+  gnn::net_forward(w.net, warm_view(c), rows, c->stream);
+  HIP_TRY(c, hipMemsetAsync(w.cnt + 1, 0, sizeof(int32_t), c->stream));
+  ws_predict_residual(w.R, nR, S, out, w.net.o, w.qn, c1, w.xhat, w.wbuf, w.wmark, w.wlist, w.cnt + 1, w.part,
+                      w.sums + 2 * RWR_MAX_COLS, c->stream);
+  int32_t touched = 0;
+  D2H(c, &touched, w.cnt + 1, sizeof(int32_t));
+  ws_rho_norm(w.wlist, w.cnt + 1, touched, S, c->ybuf, w.xhat, w.loc1, w.wbuf, w.part, w.sums, c->stream);
+  std::vector<double> sums(2 * S);
+  D2H(c, sums.data(), w.sums, sizeof(double) * 2 * S);
+  w.qn_h.assign(S, 0.0);
+  D2H(c, w.qn_h.data(), w.qn, sizeof(double) * S);
+  uint64_t accept = 0;
+  double num = 0.0, den = 0.0, lsum = 0.0;
+  int n_act = 0;
+  std::vector<int32_t> act(RWR_MAX_COLS, 0);
+  for (int j = 0; j < c->n_seeds; ++j) {
+    const double q = w.qn_h[j], rho = sums[j];
+    if (!(q > 0.0) || !std::isfinite(rho)) continue;
+    act[j] = 1;
+    ++n_act;
+    den += q;
+    num += rho;
+    lsum += rho / q;
+    if ((w.mode & 1) && rho < q) {
+      accept |= 1ull << j;
+      ++w.accepted;
+    }
+  }
+  w.ratio = den > 0.0 ? num / den : 1.0;
+  if ((w.mode & 2) && n_act > 0) {
+    w.loss = lsum / n_act;
+    H2D(c, w.net.active, act.data(), sizeof(int32_t) * RWR_MAX_COLS);
+    ws_resid_grad(w.R, nR, S, out, c1, c->ybuf, w.xhat, w.loc1, w.wbuf, w.net.active, n_act, w.net.dout, c->stream);
+    gnn::net_backward(w.net, warm_view(c), rows, c->stream);
+    gnn::net_adamw(w.net, c->stream);
+  }
+  ws_apply(w.wlist, w.cnt + 1, touched, S, accept, c->ybuf, c->r, w.xhat, w.loc1, w.wbuf, w.wmark, c->stamp, c->ctl,
+           w.sums + S, c->stream);
+  ws_clear(w.R, nR, w.hop1, w.loc1, c->stream);
+  w.ms = now_ms() - t0;
   return RWR_OK;
 }
 
@@ -1152,11 +1344,20 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   // stored edge count (an undirected self-loop is stored once; the count only
   // steers the sparse/dense switch and the visited-edge statistic)
   c->m += (b->n_ins - b->n_del) * (c->undirected ? 2 : 1) - c->ctl_h->node_dels;
+  const bool warm = c->ws.alloc && c->ws.mode != 0 && nkeys > 0;
+  if (warm) RWR_TRY(warm_prepare(c));
   launch_slot0_epilogue(a, c->S, c->fp64, c->stream);
   RWR_TRY(run_slots(c, MODE_SPARSE));
   RWR_TRY(read_ctl(c));
   account_run(c, false);
   fill_stats(c, st);
+  if (st && warm) {
+    st->ws_region = c->ws.nR;
+    st->ws_accepted = c->ws.accepted;
+    st->ws_resid_ratio = c->ws.ratio;
+    st->ws_loss = c->ws.loss;
+    st->ms_warm = c->ws.ms;
+  }
   rwr_status ret = RWR_OK;
   if (c->ctl_h->prop_err != 0) {
     c->stale = true;
@@ -1256,6 +1457,7 @@ rwr_status rwr_last_norms(rwr_ctx *c, int32_t j, double *out, int32_t cap, int32
 void rwr_destroy(rwr_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  warm_free(c);
   const int no = c->undirected ? 1 : 2;
   for (int o = 0; o < no; ++o) {
     dev_free(c->g[o].v.off);
@@ -1334,6 +1536,62 @@ rwr_status rwr_profile_read(rwr_ctx *c, double *dense_ms, int64_t *dense_sweeps,
 const char *rwr_last_error(const rwr_ctx *c) { return c ? c->err.c_str() : g_build_error.c_str(); }
 
 int64_t rwr_gnn_num_params(void) { return gnn::LAYOUT.total; }
+
+rwr_status rwr_warm_start(rwr_ctx *c, int32_t mode, int32_t hops, int64_t max_rows, float lr, float weight_decay) {
+  if (!c) return RWR_EINVAL;
+  if (mode < 0 || mode > 3 || hops < 0 || hops > 8 || max_rows < 0 || !(lr >= 0.0f) || !(weight_decay >= 0.0f)) {
+    c->err = "invalid warm-start settings";
+    return RWR_EINVAL;
+  }
+  if (mode == 0) {
+    c->ws.mode = 0;
+    return RWR_OK;
+  }
+  const int64_t rows = max_rows > 0 ? max_rows : ((int64_t)1 << 21);
+  if (c->ws.alloc && rows != c->ws.max_rows) {
+    std::vector<float> keep;
+    if (c->ws.params) {
+      keep.resize(gnn::LAYOUT.total);
+      HIP_TRY(c, gnn::net_get_params(c->ws.net, keep.data(), c->stream));
+    }
+    warm_free(c);
+    RWR_TRY(warm_alloc(c, rows));
+    if (!keep.empty()) {
+      HIP_TRY(c, gnn::net_set_params(c->ws.net, keep.data(), c->stream));
+      c->ws.params = true;
+    }
+  } else if (!c->ws.alloc) {
+    RWR_TRY(warm_alloc(c, rows));
+  }
+  if (!c->ws.params) {
+    c->err = "warm start needs parameters (rwr_model_set) first";
+    c->ws.mode = 0;
+    return RWR_ESTATE;
+  }
+  c->ws.mode = mode;
+  c->ws.hops = hops;
+  c->ws.net.lr = lr;
+  c->ws.net.wd = weight_decay;
+  return RWR_OK;
+}
+
+rwr_status rwr_model_set(rwr_ctx *c, const float *params, int64_t n) {
+  if (!c || !params || n != gnn::LAYOUT.total) return RWR_EINVAL;
+  if (!c->ws.alloc) RWR_TRY(warm_alloc(c, (int64_t)1 << 21));
+  HIP_TRY(c, gnn::net_set_params(c->ws.net, params, c->stream));
+  c->ws.params = true;
+  return RWR_OK;
+}
+
+rwr_status rwr_model_get(rwr_ctx *c, float *params, int64_t cap) {
+  if (!c || !params || cap < gnn::LAYOUT.total) return RWR_EINVAL;
+  if (!c->ws.params) {
+    c->err = "no model parameters set";
+    return RWR_ESTATE;
+  }
+  HIP_TRY(c, gnn::net_get_params(c->ws.net, params, c->stream));
+  return RWR_OK;
+}
 
 rwr_status rwr_gnn_eval(const float *params, int32_t nR, int32_t S, const int32_t *in_off, const int32_t *in_len,
                         const int32_t *in_adj, int64_t n_in, const int32_t *out_off, const int32_t *out_len,

@@ -41,9 +41,9 @@ struct WeightsBf16 {
 
 // Region graph view for aggregation: rows of the region's nodes in some
 // adjacency (off/len/adj over ids of that adjacency); loc maps an id of the
-// adjacency to the local index (-1: not in the region), or is NULL when the
-// ids are already local.  nodes[i] is the adjacency id of local node i (NULL:
-// identity).
+// adjacency to its local index plus one (0: not in the region), or is NULL
+// when the ids are already local.  nodes[i] is the adjacency id of local
+// node i (NULL: identity).
 struct RegionView {
   const int32_t *in_off, *in_len, *in_adj;     // in-rows (forward aggregation)
   const int32_t *out_off, *out_len, *out_adj;  // out-rows (backward aggregation)

@@ -249,7 +249,7 @@ __global__ void k_agg_fwd(RegionView g, int S, const float *__restrict__ Min, fl
     float4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int k = 0; k < d; ++k) {
       const int u = g.in_adj[o + k];
-      const int lu = g.loc ? g.loc[u] : u;
+      const int lu = g.loc ? g.loc[u] - 1 : u;
       if (lu < 0) continue;
       const float s = g.dinv[lu];
       const float4 x = *reinterpret_cast<const float4 *>(Min + ((int64_t)lu * S + j) * MSG + 4 * q);
@@ -275,7 +275,7 @@ __global__ void k_agg_bwd(RegionView g, int S, const float *__restrict__ D, floa
     float4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int k = 0; k < d; ++k) {
       const int v = g.out_adj[o + k];
-      const int lv = g.loc ? g.loc[v] : v;
+      const int lv = g.loc ? g.loc[v] - 1 : v;
       if (lv < 0) continue;
       const float4 x = *reinterpret_cast<const float4 *>(D + ((int64_t)lv * S + j) * MSG + 4 * q);
       acc.x += x.x;

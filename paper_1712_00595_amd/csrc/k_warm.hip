@@ -1,0 +1,472 @@
+// Learned warm start inside an update: the region around the offset seed,
+// the network's input features, the prediction xhat, the exact residual
+//   rho = q_offset - (I - (1-c) B~^T) xhat
+// that replaces the offset seed, and the training target r_offset / ||q||.
+//
+// Node marks kept between updates (all zero when no update runs):
+//   hop1[v]  = hop distance + 1 of a region node (0 outside the region),
+//   loc1[v]  = local index + 1 of a region node,
+//   wmark[v] = 1 while v is in the list of nodes the residual touches.
+#include <hipcub/hipcub.hpp>
+
+#include "rwr_common.h"
+#include "rwr_kernels.h"
+#include "warm.h"
+
+#define WB 256
+
+// ------------------------------------------------------------ region
+// flags[v] = 1 when v belongs to level h: the stamped offset support for
+// h = 0 (marked hop 1), else the nodes marked h + 1 by the expansion
+__global__ void k_ws_level_flags(const int32_t *__restrict__ stamp, int32_t st, int32_t n, int32_t h,
+                                 int32_t *__restrict__ hop1, int32_t *__restrict__ flags) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    int f = 0;
+    if (h == 0) {
+      if (stamp[v] == st) {
+        hop1[v] = 1;
+        f = 1;
+      }
+    } else {
+      f = hop1[v] == h + 1;
+    }
+    flags[v] = f;
+  }
+}
+
+// one wavefront per node of level h - 1: mark unvisited out-neighbours h + 1
+__global__ void k_ws_expand(const int32_t *__restrict__ list, int32_t cnt, DevGraphView out, int32_t h,
+                            int32_t *__restrict__ hop1) {
+  const int lane = threadIdx.x % RWR_WAVE;
+  for (int w = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; w < cnt; w += gridDim.x * blockDim.x / RWR_WAVE) {
+    const int u = list[w];
+    const int o = out.off[u], d = out.len[u];
+    for (int e = lane; e < d; e += RWR_WAVE) {
+      const int v = out.adj[o + e];
+      if (hop1[v] == 0) hop1[v] = h + 1;  // every writer stores the same value
+    }
+  }
+}
+
+__global__ void k_ws_unmark(const int32_t *__restrict__ list, int32_t cnt, int32_t *__restrict__ hop1) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) hop1[list[i]] = 0;
+}
+
+__global__ void k_ws_loc(const int32_t *__restrict__ R, int32_t nR, const DevGraphView out,
+                         int32_t *__restrict__ loc1, float *__restrict__ dinv) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nR; i += gridDim.x * blockDim.x) {
+    const int v = R[i];
+    loc1[v] = i + 1;
+    const int d = out.len[v];
+    dinv[i] = d ? 1.0f / (float)d : 0.0f;
+  }
+}
+
+__global__ void k_ws_clear(const int32_t *__restrict__ R, int32_t nR, int32_t *__restrict__ hop1,
+                           int32_t *__restrict__ loc1) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nR; i += gridDim.x * blockDim.x) {
+    hop1[R[i]] = 0;
+    loc1[R[i]] = 0;
+  }
+}
+
+// ------------------------------------------------------------ features
+// per-workgroup partials over the level-0 nodes (q sits in ybuf) of
+// ||q_j||_1 (entries j) and of the signed sum of q_j (entries S + j)
+__global__ __launch_bounds__(WB) void k_ws_qnorm(const int32_t *__restrict__ R, int32_t n0, int S,
+                                                 const double *__restrict__ ybuf, double *__restrict__ part) {
+  __shared__ double red[WB], sgn[WB];
+  const int j = threadIdx.x % S, rl = threadIdx.x / S, RPB = WB / S;
+  double s = 0.0, t = 0.0;
+  for (int i = blockIdx.x * RPB + rl; i < n0; i += gridDim.x * RPB) {
+    const double q = ybuf[col_index(R[i], S, j)];
+    s += fabs(q);
+    t += q;
+  }
+  red[threadIdx.x] = s;
+  sgn[threadIdx.x] = t;
+  __syncthreads();
+  if (threadIdx.x < S) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < RPB; ++q) a += red[q * S + threadIdx.x], b += sgn[q * S + threadIdx.x];
+    part[(int64_t)blockIdx.x * 2 * S + threadIdx.x] = a;
+    part[(int64_t)blockIdx.x * 2 * S + S + threadIdx.x] = b;
+  }
+}
+
+// out[j] = sum over b of part[b * S + j]
+__global__ void k_ws_sum_parts(const double *__restrict__ part, int nb, int S, double *__restrict__ out) {
+  const int j = threadIdx.x;
+  if (j >= S) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * S + j];
+  out[j] = s;
+}
+
+// The sixteen inputs of a (node, column) row; see warm.h for the list.
+__global__ void k_ws_features(const int32_t *__restrict__ R, int32_t nR, int S, const int32_t *__restrict__ hop1,
+                              DevGraphView in, DevGraphView out, const double *__restrict__ ybuf,
+                              const double *__restrict__ r, const Ctl *__restrict__ ctl,
+                              const int32_t *__restrict__ seeds, const double *__restrict__ qn, int32_t n_total,
+                              float *__restrict__ F) {
+  const int64_t rows = (int64_t)nR * S;
+  for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(row / S), j = (int)(row % S);
+    const int v = R[i];
+    const int64_t kk = col_index(v, S, j);
+    const double q = qn[j] > 0.0 ? ybuf[kk] / qn[j] : 0.0;
+    const double sig = ctl->sigma[j];
+    const double rn = sig != 0.0 ? r[kk] / sig : 0.0;
+    const int din = in.len[v], dout = out.len[v];
+    const int hp = hop1[v] - 1;
+    float f[16];
+    f[0] = log1pf((float)din) * 0.125f;
+    f[1] = log1pf((float)dout) * 0.125f;
+    f[2] = (float)q;
+    f[3] = fabsf((float)q);
+    f[4] = log1pf(fmaxf(0.0f, (float)(rn * (double)n_total))) * 0.125f;
+    f[5] = hp == 0 ? 1.0f : 0.0f;
+    f[6] = hp == 1 ? 1.0f : 0.0f;
+    f[7] = hp == 2 ? 1.0f : 0.0f;
+    f[8] = hp >= 3 ? 1.0f : 0.0f;
+    f[9] = dout == 0 ? 1.0f : 0.0f;
+    f[10] = (j < RWR_MAX_COLS && seeds[j] == v) ? 1.0f : 0.0f;
+    f[11] = dout ? 1.0f / (float)dout : 0.0f;
+    f[12] = din ? 1.0f / (float)din : 0.0f;
+    f[13] = 0.0f;
+    f[14] = 0.0f;
+    f[15] = 0.0f;
+    float4 *dst = reinterpret_cast<float4 *>(F + row * 16);
+    dst[0] = float4{f[0], f[1], f[2], f[3]};
+    dst[1] = float4{f[4], f[5], f[6], f[7]};
+    dst[2] = float4{f[8], f[9], f[10], f[11]};
+    dst[3] = float4{f[12], f[13], f[14], f[15]};
+  }
+}
+
+// ------------------------------------------------------------ prediction and residual
+// xhat = ||q_j|| o (FP64), and the region's nodes enter the touched list
+__global__ void k_ws_predict(const int32_t *__restrict__ R, int32_t nR, int S, const float *__restrict__ o,
+                             const double *__restrict__ qn, double *__restrict__ xhat, int32_t *__restrict__ wmark,
+                             int32_t *__restrict__ wlist, int32_t *__restrict__ wcount) {
+  const int64_t rows = (int64_t)nR * S;
+  for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(row % S);
+    xhat[row] = qn[j] * (double)o[row];
+    if (j == 0) {
+      const int v = R[row / S];
+      if (atomicExch(&wmark[v], 1) == 0) wlist[atomicAdd(wcount, 1)] = v;
+    }
+  }
+}
+
+// Mass of the prediction.  For any xhat, sum(rho) = sum(q) - f(xhat) with
+// f(x) = sum(x) - (1-c) sum over non-dead-end nodes of x (the column sums of
+// I - (1-c) B~^T), and f(r_offset) = sum(q) exactly.  A residual with a
+// non-zero sum decays no faster than (1-c) per iteration (the all-ones
+// vector is a left eigenvector of (1-c) B~^T without dead ends), so the
+// prediction is corrected to f(xhat') = sum(q):
+//   xhat' = xhat - beta |xhat|,  beta = (f(xhat) - sum(q)) / f(|xhat|).
+// Partials per column: [xhat, xhat on non-dead ends, |xhat|, |xhat| on
+// non-dead ends] at entries [0, S, 2S, 3S) + j.
+__global__ __launch_bounds__(WB) void k_ws_mass(const int32_t *__restrict__ R, int32_t nR, int S,
+                                                const DevGraphView out, const double *__restrict__ xhat,
+                                                double *__restrict__ part) {
+  __shared__ double red[4][WB];
+  const int j = threadIdx.x % S, rl = threadIdx.x / S, RPB = WB / S;
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  for (int i = blockIdx.x * RPB + rl; i < nR; i += gridDim.x * RPB) {
+    const double x = xhat[(int64_t)i * S + j];
+    const bool live = out.len[R[i]] > 0;
+    a += x;
+    c += fabs(x);
+    if (live) {
+      b += x;
+      d += fabs(x);
+    }
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  red[2][threadIdx.x] = c;
+  red[3][threadIdx.x] = d;
+  __syncthreads();
+  if (threadIdx.x < S) {
+    for (int k = 0; k < 4; ++k) {
+      double t = 0.0;
+      for (int q = 0; q < RPB; ++q) t += red[k][q * S + threadIdx.x];
+      part[(int64_t)blockIdx.x * 4 * S + k * S + threadIdx.x] = t;
+    }
+  }
+}
+
+// beta[j] from the partials (fixed order) and sum(q) = qn[S + j]
+__global__ void k_ws_beta(const double *__restrict__ part, int nb, int S, double c1, const double *__restrict__ qn,
+                          double *__restrict__ beta) {
+  const int j = threadIdx.x;
+  if (j >= S) return;
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    const double *p = part + (int64_t)k * 4 * S;
+    a += p[j];
+    b += p[S + j];
+    c += p[2 * S + j];
+    d += p[3 * S + j];
+  }
+  const double fx = a - c1 * b, fa = c - c1 * d;
+  beta[j] = fa > 0.0 ? (fx - qn[S + j]) / fa : 0.0;
+}
+
+__global__ void k_ws_adjust(int32_t nR, int S, const double *__restrict__ beta, double *__restrict__ xhat) {
+  const int64_t rows = (int64_t)nR * S;
+  for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const double x = xhat[row];
+    xhat[row] = x - beta[row % S] * fabs(x);
+  }
+}
+
+// P xhat pushed along out-edges into wbuf (FP64), one wavefront per region
+// node; every receiving node enters the touched list
+template <int S>
+__global__ void k_ws_push(const int32_t *__restrict__ R, int32_t nR, DevGraphView out, const double *__restrict__ xhat,
+                          double c1, double *__restrict__ wbuf, int32_t *__restrict__ wmark,
+                          int32_t *__restrict__ wlist, int32_t *__restrict__ wcount) {
+  const int lane = threadIdx.x % RWR_WAVE;
+  constexpr int PER = RWR_WAVE / S;  // edges per wavefront step
+  const int j = lane % S, p = lane / S;
+  for (int w = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; w < nR; w += gridDim.x * blockDim.x / RWR_WAVE) {
+    const int u = R[w];
+    const int o = out.off[u], d = out.len[u];
+    if (d == 0) continue;
+    const double val = c1 * xhat[(int64_t)w * S + j] / (double)d;
+    for (int e = p; e < d; e += PER) {
+      const int v = out.adj[o + e];
+      if (val != 0.0) atomic_add_f64(&wbuf[col_index(v, S, j)], val);
+      if (j == 0 && atomicExch(&wmark[v], 1) == 0) wlist[atomicAdd(wcount, 1)] = v;
+    }
+  }
+}
+
+// per-workgroup partials over the touched list of ||rho_j||_1 and of the
+// signed sum of xhat_j
+__global__ __launch_bounds__(WB) void k_ws_rho_norm(const int32_t *__restrict__ wlist, const int32_t *__restrict__ wcount,
+                                                    int S, const double *__restrict__ ybuf,
+                                                    const double *__restrict__ xhat, const int32_t *__restrict__ loc1,
+                                                    const double *__restrict__ wbuf, double *__restrict__ part) {
+  __shared__ double rn[WB], xs[WB];
+  const int cnt = *wcount;
+  const int j = threadIdx.x % S, rl = threadIdx.x / S, RPB = WB / S;
+  double a = 0.0, b = 0.0;
+  for (int i = blockIdx.x * RPB + rl; i < cnt; i += gridDim.x * RPB) {
+    const int v = wlist[i];
+    const int64_t kk = col_index(v, S, j);
+    const int li = loc1[v] - 1;
+    const double xh = li >= 0 ? xhat[(int64_t)li * S + j] : 0.0;
+    a += fabs(ybuf[kk] - xh + wbuf[kk]);
+    b += xh;
+  }
+  rn[threadIdx.x] = a;
+  xs[threadIdx.x] = b;
+  __syncthreads();
+  if (threadIdx.x < S) {
+    double t = 0.0, u = 0.0;
+    for (int q = 0; q < RPB; ++q) t += rn[q * S + threadIdx.x], u += xs[q * S + threadIdx.x];
+    part[(int64_t)blockIdx.x * 2 * S + threadIdx.x] = t;
+    part[(int64_t)blockIdx.x * 2 * S + S + threadIdx.x] = u;
+  }
+}
+
+// Accepted columns: the offset seed becomes rho and the scores take xhat;
+// every touched node is stamped so the first propagation slot reads it.
+// Clears wbuf and the marks.
+__global__ void k_ws_apply(const int32_t *__restrict__ wlist, const int32_t *__restrict__ wcount, int S,
+                           uint64_t accept, double *__restrict__ ybuf, double *__restrict__ r,
+                           const double *__restrict__ xhat, const int32_t *__restrict__ loc1,
+                           double *__restrict__ wbuf, int32_t *__restrict__ wmark, int32_t *__restrict__ stamp,
+                           const Ctl *__restrict__ ctl) {
+  const int cnt = *wcount;
+  const int32_t st = ctl->stamp;
+  const int64_t total = (int64_t)cnt * S;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / S), j = (int)(e % S);
+    const int v = wlist[i];
+    const int64_t kk = col_index(v, S, j);
+    if ((accept >> j) & 1ull) {
+      const int li = loc1[v] - 1;
+      const double xh = li >= 0 ? xhat[(int64_t)li * S + j] : 0.0;
+      ybuf[kk] = ybuf[kk] - xh + wbuf[kk];
+      r[kk] += xh;
+    }
+    wbuf[kk] = 0.0;
+    if (j == 0) {
+      wmark[v] = 0;
+      stamp[v] = st;
+    }
+  }
+}
+
+__global__ void k_ws_sigma(Ctl *ctl, int S, uint64_t accept, const double *__restrict__ xsum) {
+  const int j = threadIdx.x;
+  if (j < S && ((accept >> j) & 1ull)) ctl->sigma[j] += xsum[j];
+}
+
+// ------------------------------------------------------------ training
+// Gradient of the training loss L = mean over active columns j of
+// ||rho_j||_1 / ||q_j||_1 with respect to the network output o (xhat = ||q|| o):
+//   dL/do(u, j) = (-(I - (1-c) B~^T)^T sign(rho_j))(u) / C
+//              = (-sign(rho(u, j)) + (1-c)/d_out(u) sum over u -> v of sign(rho(v, j))) / C.
+// For the exact offset result, ||rho||_1 is the L1 distance between xhat and
+// r_offset measured through I - (1-c) B~^T.  The mass correction is taken as
+// fixed (its derivative is not followed).  One wavefront per region node.
+template <int S>
+__global__ void k_ws_resid_grad(const int32_t *__restrict__ R, int32_t nR, DevGraphView out, double c1,
+                                const double *__restrict__ ybuf, const double *__restrict__ xhat,
+                                const int32_t *__restrict__ loc1, const double *__restrict__ wbuf,
+                                const int32_t *__restrict__ active, float inv_cols, float *__restrict__ dout) {
+  const int lane = threadIdx.x % RWR_WAVE;
+  constexpr int PER = RWR_WAVE / S;
+  const int j = lane % S, p = lane / S;
+  auto rho = [&](int v) {
+    const int64_t kk = col_index(v, S, j);
+    const int li = loc1[v] - 1;
+    const double xh = li >= 0 ? xhat[(int64_t)li * S + j] : 0.0;
+    return ybuf[kk] - xh + wbuf[kk];
+  };
+  auto sgn = [](double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); };
+  for (int w = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; w < nR; w += gridDim.x * blockDim.x / RWR_WAVE) {
+    const int u = R[w];
+    const int o = out.off[u], d = out.len[u];
+    double t = 0.0;
+    for (int e = p; e < d; e += PER) t += sgn(rho(out.adj[o + e]));
+    for (int off = S; off < RWR_WAVE; off <<= 1) t += __shfl_xor(t, off, RWR_WAVE);
+    if (p == 0) {
+      const double g = -sgn(rho(u)) + (d ? c1 * t / (double)d : 0.0);
+      dout[(int64_t)w * S + j] = active[j] ? (float)g * inv_cols : 0.0f;
+    }
+  }
+}
+
+// ------------------------------------------------------------ host launchers
+static int wgrid(int64_t work, int cap = 4096) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((work + WB - 1) / WB, cap));
+}
+
+void ws_level_flags(const int32_t *stamp, int32_t st, int32_t n, int32_t h, int32_t *hop1, int32_t *flags,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_level_flags, dim3(wgrid(n)), dim3(WB), 0, s, stamp, st, n, h, hop1, flags);
+}
+
+size_t ws_select_temp_bytes(int32_t n) {
+  size_t bytes = 0;
+  (void)hipcub::DeviceSelect::Flagged(nullptr, bytes, hipcub::CountingInputIterator<int32_t>(0), (const int32_t *)nullptr,
+                                      (int32_t *)nullptr, (int32_t *)nullptr, n);
+  return bytes;
+}
+
+hipError_t ws_select(const int32_t *flags, int32_t n, int32_t *out, int32_t *count, void *temp, size_t temp_bytes,
+                     hipStream_t s) {
+  return hipcub::DeviceSelect::Flagged(temp, temp_bytes, hipcub::CountingInputIterator<int32_t>(0), flags, out, count,
+                                       n, s);
+}
+
+void ws_expand(const int32_t *list, int32_t cnt, const DevGraphView &out, int32_t h, int32_t *hop1, hipStream_t s) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_ws_expand, dim3(wgrid((int64_t)cnt * RWR_WAVE)), dim3(WB), 0, s, list, cnt, out, h, hop1);
+}
+
+void ws_unmark(const int32_t *list, int32_t cnt, int32_t *hop1, hipStream_t s) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_ws_unmark, dim3(wgrid(cnt)), dim3(WB), 0, s, list, cnt, hop1);
+}
+
+void ws_loc(const int32_t *R, int32_t nR, const DevGraphView &out, int32_t *loc1, float *dinv, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_loc, dim3(wgrid(nR)), dim3(WB), 0, s, R, nR, out, loc1, dinv);
+}
+
+void ws_clear(const int32_t *R, int32_t nR, int32_t *hop1, int32_t *loc1, hipStream_t s) {
+  if (nR <= 0) return;
+  hipLaunchKernelGGL(k_ws_clear, dim3(wgrid(nR)), dim3(WB), 0, s, R, nR, hop1, loc1);
+}
+
+void ws_qnorm(const int32_t *R, int32_t n0, int S, const double *ybuf, double *part, double *qn, hipStream_t s) {
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)n0 * S + WB - 1) / WB, 1024));
+  hipLaunchKernelGGL(k_ws_qnorm, dim3(nb), dim3(WB), 0, s, R, n0, S, ybuf, part);
+  hipLaunchKernelGGL(k_ws_sum_parts, dim3(1), dim3(128), 0, s, part, nb, 2 * S, qn);
+}
+
+void ws_features(const int32_t *R, int32_t nR, int S, const int32_t *hop1, const DevGraphView &in,
+                 const DevGraphView &out, const double *ybuf, const double *r, const Ctl *ctl, const int32_t *seeds,
+                 const double *qn, int32_t n_total, float *F, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_features, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, R, nR, S, hop1, in, out, ybuf, r,
+                     ctl, seeds, qn, n_total, F);
+}
+
+void ws_predict_residual(const int32_t *R, int32_t nR, int S, const DevGraphView &out, const float *o,
+                         const double *qn, double c1, double *xhat, double *wbuf, int32_t *wmark, int32_t *wlist,
+                         int32_t *wcount, double *part, double *beta, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_predict, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, R, nR, S, o, qn, xhat, wmark, wlist,
+                     wcount);
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)nR * S + WB - 1) / WB, 512));
+  hipLaunchKernelGGL(k_ws_mass, dim3(nb), dim3(WB), 0, s, R, nR, S, out, xhat, part);
+  hipLaunchKernelGGL(k_ws_beta, dim3(1), dim3(64), 0, s, part, nb, S, c1, qn, beta);
+  hipLaunchKernelGGL(k_ws_adjust, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, nR, S, beta, xhat);
+  const int g = wgrid((int64_t)nR * RWR_WAVE);
+  switch (S) {
+#define WS_PUSH(SS)                                                                                             \
+  case SS:                                                                                                      \
+    hipLaunchKernelGGL(k_ws_push<SS>, dim3(g), dim3(WB), 0, s, R, nR, out, xhat, c1, wbuf, wmark, wlist, wcount); \
+    break;
+    WS_PUSH(1)
+    WS_PUSH(2)
+    WS_PUSH(4)
+    WS_PUSH(8)
+    WS_PUSH(16)
+    WS_PUSH(32)
+    WS_PUSH(64)
+#undef WS_PUSH
+    default:
+      break;
+  }
+}
+
+void ws_rho_norm(const int32_t *wlist, const int32_t *wcount, int32_t cnt_hint, int S, const double *ybuf,
+                 const double *xhat, const int32_t *loc1, const double *wbuf, double *part, double *sums,
+                 hipStream_t s) {
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)cnt_hint * S + WB - 1) / WB, 1024));
+  hipLaunchKernelGGL(k_ws_rho_norm, dim3(nb), dim3(WB), 0, s, wlist, wcount, S, ybuf, xhat, loc1, wbuf, part);
+  hipLaunchKernelGGL(k_ws_sum_parts, dim3(1), dim3(128), 0, s, part, nb, 2 * S, sums);
+}
+
+void ws_apply(const int32_t *wlist, const int32_t *wcount, int32_t cnt_hint, int S, uint64_t accept, double *ybuf,
+              double *r, const double *xhat, const int32_t *loc1, double *wbuf, int32_t *wmark, int32_t *stamp,
+              Ctl *ctl, const double *xsum, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_apply, dim3(wgrid((int64_t)cnt_hint * S)), dim3(WB), 0, s, wlist, wcount, S, accept, ybuf,
+                     r, xhat, loc1, wbuf, wmark, stamp, ctl);
+  hipLaunchKernelGGL(k_ws_sigma, dim3(1), dim3(64), 0, s, ctl, S, accept, xsum);
+}
+
+void ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *ybuf,
+                   const double *xhat, const int32_t *loc1, const double *wbuf, const int32_t *active, int n_active,
+                   float *dout, hipStream_t s) {
+  const int g = wgrid((int64_t)nR * RWR_WAVE);
+  const float inv = 1.0f / (float)std::max(1, n_active);
+  switch (S) {
+#define WS_GRAD(SS)                                                                                                 \
+  case SS:                                                                                                          \
+    hipLaunchKernelGGL(k_ws_resid_grad<SS>, dim3(g), dim3(WB), 0, s, R, nR, out, c1, ybuf, xhat, loc1, wbuf, active, \
+                       inv, dout);                                                                                  \
+    break;
+    WS_GRAD(1)
+    WS_GRAD(2)
+    WS_GRAD(4)
+    WS_GRAD(8)
+    WS_GRAD(16)
+    WS_GRAD(32)
+    WS_GRAD(64)
+#undef WS_GRAD
+    default:
+      break;
+  }
+}

@@ -1,0 +1,50 @@
+// Host launchers of the learned warm start inside an update (k_warm.hip).
+//
+// Inputs of the network for (region node v, seed column j), in order:
+//   0  log(1 + d_in(v)) / 8          1  log(1 + d_out(v)) / 8
+//   2  q_offset(v, j) / ||q_j||_1    3  |input 2|
+//   4  log(1 + n * r_old(v, j) / sigma_j) / 8 (0 when negative)
+//   5..8  hop distance from the offset support: 0, 1, 2, >= 3 (one-hot)
+//   9  1 for a dead end              10 1 when v is seed j
+//   11 1/d_out(v) (0 for a dead end) 12 1/d_in(v) (0 without in-edges)
+//   13..15 zero
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rwr_common.h"
+#include "rwr_kernels.h"
+
+void ws_level_flags(const int32_t *stamp, int32_t st, int32_t n, int32_t h, int32_t *hop1, int32_t *flags,
+                    hipStream_t s);
+size_t ws_select_temp_bytes(int32_t n);
+// out = indices v < n with flags[v] != 0, in increasing order; *count (device) their number
+hipError_t ws_select(const int32_t *flags, int32_t n, int32_t *out, int32_t *count, void *temp, size_t temp_bytes,
+                     hipStream_t s);
+void ws_expand(const int32_t *list, int32_t cnt, const DevGraphView &out, int32_t h, int32_t *hop1, hipStream_t s);
+void ws_unmark(const int32_t *list, int32_t cnt, int32_t *hop1, hipStream_t s);
+void ws_loc(const int32_t *R, int32_t nR, const DevGraphView &out, int32_t *loc1, float *dinv, hipStream_t s);
+void ws_clear(const int32_t *R, int32_t nR, int32_t *hop1, int32_t *loc1, hipStream_t s);
+void ws_features(const int32_t *R, int32_t nR, int S, const int32_t *hop1, const DevGraphView &in,
+                 const DevGraphView &out, const double *ybuf, const double *r, const Ctl *ctl, const int32_t *seeds,
+                 const double *qn, int32_t n_total, float *F, hipStream_t s);
+// qn[j] = ||q_j||_1 and qn[S + j] = sum of q_j over the offset support
+void ws_qnorm(const int32_t *R, int32_t n0, int S, const double *ybuf, double *part, double *qn, hipStream_t s);
+// xhat = ||q|| o, corrected so that the residual has a zero sum; P xhat
+// pushed into wbuf; region and receiving nodes listed in wlist.  part holds
+// at least 512 * 4 * S doubles, beta S doubles.
+void ws_predict_residual(const int32_t *R, int32_t nR, int S, const DevGraphView &out, const float *o,
+                         const double *qn, double c1, double *xhat, double *wbuf, int32_t *wmark, int32_t *wlist,
+                         int32_t *wcount, double *part, double *beta, hipStream_t s);
+// sums[j] = ||rho_j||_1, sums[S + j] = sum of xhat_j
+void ws_rho_norm(const int32_t *wlist, const int32_t *wcount, int32_t cnt_hint, int S, const double *ybuf,
+                 const double *xhat, const int32_t *loc1, const double *wbuf, double *part, double *sums,
+                 hipStream_t s);
+void ws_apply(const int32_t *wlist, const int32_t *wcount, int32_t cnt_hint, int S, uint64_t accept, double *ybuf,
+              double *r, const double *xhat, const int32_t *loc1, double *wbuf, int32_t *wmark, int32_t *stamp,
+              Ctl *ctl, const double *xsum, hipStream_t s);
+// dL/do of the residual loss (see k_ws_resid_grad) into dout (rows nR * S)
+void ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *ybuf,
+                   const double *xhat, const int32_t *loc1, const double *wbuf, const int32_t *active, int n_active,
+                   float *dout, hipStream_t s);

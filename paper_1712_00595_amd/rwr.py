@@ -45,6 +45,9 @@ EXPORTED = [
     "rwr_last_error",
     "rwr_gnn_num_params",
     "rwr_gnn_eval",
+    "rwr_model_set",
+    "rwr_model_get",
+    "rwr_warm_start",
 ]
 
 
@@ -99,6 +102,11 @@ class StatsStruct(ctypes.Structure):
         ("err_bound", ctypes.c_double),
         ("residual_l1", ctypes.c_double),
         ("ms_total", ctypes.c_double),
+        ("ws_region", ctypes.c_int32),
+        ("ws_accepted", ctypes.c_int32),
+        ("ws_resid_ratio", ctypes.c_double),
+        ("ws_loss", ctypes.c_double),
+        ("ms_warm", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -134,6 +142,9 @@ def load_library(path: str = LIB_PATH):
     L.rwr_gnn_num_params.argtypes = []
     L.rwr_gnn_num_params.restype = i64
     L.rwr_gnn_eval.argtypes = [p, i32, i32, p, p, p, i64, p, p, p, i64, p, p, p, p, p, p, p, p]
+    L.rwr_model_set.argtypes = [p, p, i64]
+    L.rwr_model_get.argtypes = [p, p, i64]
+    L.rwr_warm_start.argtypes = [p, i32, i32, i64, ctypes.c_float, ctypes.c_float]
     for name in EXPORTED:
         f = getattr(L, name)
         if name not in ("rwr_destroy", "rwr_last_error", "rwr_gnn_num_params"):
@@ -278,6 +289,24 @@ class Context:
     def update_batch(self, batch) -> dict:
         return self.update(batch.ins_src, batch.ins_dst, batch.del_src, batch.del_dst, batch.n_new_nodes,
                            getattr(batch, "del_nodes", None))
+
+    # -- learned warm start
+    def model_set(self, params) -> None:
+        th = np.ascontiguousarray(np.asarray(params, np.float32))
+        _check(self._lib, self._ctx, self._lib.rwr_model_set(self._ctx, th.ctypes.data, th.shape[0]))
+
+    def model_get(self) -> np.ndarray:
+        n = int(self._lib.rwr_gnn_num_params())
+        out = np.zeros(n, np.float32)
+        _check(self._lib, self._ctx, self._lib.rwr_model_get(self._ctx, out.ctypes.data, n))
+        return out
+
+    def warm_start(self, mode: str = "predict", hops: int = 3, max_rows: int = 0, lr: float = 1e-5,
+                   weight_decay: float = 1e-4) -> None:
+        """mode: 'off', 'predict', 'train' or 'predict+train'."""
+        m = {"off": 0, "predict": 1, "train": 2, "predict+train": 3}[mode]
+        _check(self._lib, self._ctx, self._lib.rwr_warm_start(self._ctx, m, int(hops), int(max_rows), float(lr),
+                                                               float(weight_decay)))
 
     def refine(self) -> dict:
         st = StatsStruct()
