@@ -80,6 +80,149 @@ def measured_traffic(sweep_bytes: int):
         return None
 
 
+def run_batched_seeds(n_batches: int) -> dict:
+    """R-MAT scale 22, 64 uniform seeds, batches of log-uniform size in
+    [1, 10^4] edge modifications with 1% new nodes, eps = 1e-6; the dense
+    sweep here is the vectorised multi-column kernel."""
+    import torch
+
+    from paper_1712_00595_amd import rwr
+    from synth.configs import RMAT22_BATCHED, stream_for
+
+    w = RMAT22_BATCHED
+    t = time.time()
+    g = w.graph()
+    seeds = w.seeds(g)
+    stream = stream_for(w, w.model(g), n_batches)
+    log(f"[{w.name}] graph n={g.n} m={g.m}, {len(stream)} batches ({time.time() - t:.1f}s)")
+    eps = w.eps[0]
+    t = time.time()
+    ctx = rwr.Context(g.n, g.src, g.dst, seeds, c=w.c, eps=eps, precision="fp32")
+    torch.cuda.synchronize()
+    build_s = time.time() - t
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    mods = sum(b.size for b in stream)
+    t0 = time.perf_counter()
+    stats = [ctx.update_batch(b) for b in stream]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    P = ctx.profile_read(reset=True)
+    n_f = ctx.n
+    m_f = ctx.m
+    res = {
+        "batches": len(stream),
+        "edge_and_node_modifications": mods,
+        "modifications_per_s": mods / el,
+        "batches_per_s": len(stream) / el,
+        "seed_columns_x_batches_per_s": 64 * len(stream) / el,
+        "build_s": build_s,
+        "mean_iters": float(np.mean([s["iters"] for s in stats])),
+        "mean_dense_sweeps": float(np.mean([s["dense_iters"] for s in stats])),
+        "refinements": int(sum(s["refined"] for s in stats)),
+        "max_err_bound": float(max(s["err_bound"] for s in stats)),
+        "gate": 2 * eps / w.c,
+    }
+    launches = P["dense_sweeps"] + P["idle_launches"]
+    if P["dense_sweeps"]:
+        sweep_bytes = dense_sweep_bytes(n_f, m_f, 64)
+        res["roofline"] = {
+            "bound": "hbm",
+            "kernel": "k_pull_v<float, 64, 16, KIND_DENSE> (dense sweep, 64 columns)",
+            "achieved": sweep_bytes * P["dense_sweeps"] / (P["dense_ms"] * 1e-3) / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "bytes_per_sweep": sweep_bytes,
+            "avg_launch_us": 1e3 * P["dense_ms"] / launches,
+            "avg_sweep_us": 1e3 * P["dense_ms"] / P["dense_sweeps"],
+            "launches": launches,
+            "idle_launches": P["idle_launches"],
+        }
+        res["roofline"]["frac"] = res["roofline"]["achieved"] / HBM_PEAK_GBS
+    # sampled parity: 2 of the 64 columns against the oracle's static solve
+    import oracle
+
+    t = time.time()
+    n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream)
+    cols = [0, 63]
+    errs = []
+    for j in cols:
+        ref = oracle.rwr_static(n2, s2, d2, int(seeds[j]), w.c)
+        errs.append(float(np.abs(ctx.scores(j) - ref).sum()))
+    res["parity"] = {"columns": cols, "l1_vs_oracle": errs, "ok": max(errs) <= res["gate"],
+                     "oracle_s": time.time() - t}
+    ctx.close()
+    log(f"[{w.name}] {res['batches_per_s']:.2f} batches/s, {res['modifications_per_s']:.0f} modifications/s, "
+        f"parity max L1 {max(errs):.2e}")
+    return res
+
+
+def run_learned(n_train: int, n_eval: int) -> dict:
+    """R-MAT scale 21, 16 uniform seeds, 100-edge batches (50/50), eps = 1e-6:
+    online training of the warm-start network on n_train updates, then the
+    same n_eval held-out updates timed with the plain method and with the
+    trained prediction."""
+    import torch
+
+    from paper_1712_00595_amd import rwr
+    from paper_1712_00595_amd.warm import init_params
+    from synth.configs import RMAT21_LEARNED, stream_for
+
+    w = RMAT21_LEARNED
+    t = time.time()
+    g = w.graph()
+    seeds = w.seeds(g)
+    stream = stream_for(w, w.model(g), n_train + n_eval)
+    train, held = stream[:n_train], stream[n_train:]
+    log(f"[{w.name}] graph n={g.n} m={g.m}, {n_train} train + {n_eval} held-out batches ({time.time() - t:.1f}s)")
+    eps = w.eps[0]
+    kw = dict(c=w.c, eps=eps, precision="fp32")
+    th0 = init_params(5)
+    res = {"train_updates": n_train, "eval_updates": n_eval, "gate": 2 * eps / w.c}
+    t = time.time()
+    with rwr.Context(g.n, g.src, g.dst, seeds, **kw) as tr:
+        tr.model_set(th0)
+        tr.warm_start("predict+train", hops=3, lr=1e-5)
+        st = [tr.update_batch(b) for b in train]
+        th = tr.model_get()
+    res["train_s"] = time.time() - t
+    res["train_loss_first_last"] = [float(np.mean([s["ws_loss"] for s in st[:50]])),
+                                    float(np.mean([s["ws_loss"] for s in st[-50:]]))]
+    log(f"[{w.name}] trained in {res['train_s']:.1f}s, loss {res['train_loss_first_last']}")
+    for name, params in (("plain", None), ("learned", th), ("prior", th0)):
+        with rwr.Context(g.n, g.src, g.dst, seeds, **kw) as ctx:
+            for b in train:
+                ctx.update_batch(b)
+            if params is not None:
+                ctx.model_set(params)
+                ctx.warm_start("predict", hops=3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = [ctx.update_batch(b) for b in held]
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            mods = sum(b.size for b in held)
+            r = {"updates_per_s": n_eval / el, "modifications_per_s": mods / el,
+                 "mean_iters": float(np.mean([s["iters"] for s in st])),
+                 "mean_dense_sweeps": float(np.mean([s["dense_iters"] for s in st])),
+                 "max_err_bound": float(max(s["err_bound"] for s in st))}
+            if params is not None:
+                r["mean_resid_ratio"] = float(np.mean([s["ws_resid_ratio"] for s in st]))
+                r["mean_accepted_columns"] = float(np.mean([s["ws_accepted"] for s in st]))
+                r["mean_region_nodes"] = float(np.mean([s["ws_region"] for s in st]))
+                r["mean_warm_ms"] = float(np.mean([s["ms_warm"] for s in st]))
+            if name == "learned":
+                import oracle
+
+                n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream)
+                errs = [float(np.abs(ctx.scores(j) - oracle.rwr_static(n2, s2, d2, int(seeds[j]), w.c)).sum())
+                        for j in (0, 15)]
+                r["parity"] = {"columns": [0, 15], "l1_vs_oracle": errs, "ok": max(errs) <= res["gate"]}
+            res[name] = r
+            log(f"[{w.name}] {name}: {r['updates_per_s']:.1f} updates/s, iters {r['mean_iters']:.2f}")
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +235,12 @@ def main() -> int:
     ap.add_argument("--no-host-batches", action="store_true",
                     help="skip the second headline run that hands batches over in host memory")
     ap.add_argument("--cpu-sample", type=int, default=3, help="updates timed on the CPU oracle")
+    ap.add_argument("--workloads", default="",
+                    help="extra workloads run after the headline, comma list of: rmat22_batched_seeds, "
+                         "rmat21_learned_warm_start")
+    ap.add_argument("--batches", type=int, default=200, help="batches of the batched-seed workload")
+    ap.add_argument("--learned-train", type=int, default=500, help="training updates of the learned workload")
+    ap.add_argument("--learned-eval", type=int, default=100, help="held-out updates of the learned workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one elementwise copy of MIB MiB (calibrates the traffic counters) and exit")
     args = ap.parse_args()
@@ -296,6 +445,15 @@ def main() -> int:
             }
             log(f"cpu baseline: {cpu['value']:.3f} updates/s (static solve {static_s:.1f}s)")
 
+    extra = {}
+    for wname in [x for x in args.workloads.split(",") if x]:
+        if wname == "rmat22_batched_seeds":
+            extra[wname] = run_batched_seeds(args.batches)
+        elif wname == "rmat21_learned_warm_start":
+            extra[wname] = run_learned(args.learned_train, args.learned_eval)
+        else:
+            raise SystemExit(f"unknown workload {wname}")
+
     out = {
         "metric": "RWR updates/sec at L1 err<=2eps/c",
         "value": H["updates_per_s"],
@@ -325,6 +483,8 @@ def main() -> int:
         "parity": parity,
         "modes": results,
     }
+    if extra:
+        out["workloads"] = extra
     print(json.dumps(out), flush=True)
     return 0
 

@@ -125,6 +125,12 @@ struct rwr_ctx {
     bool alloc = false, params = false;
     int32_t *hop1 = nullptr, *loc1 = nullptr, *wmark = nullptr, *wlist = nullptr, *flags = nullptr;
     int32_t *R = nullptr, *cnt = nullptr;  // cnt[0]: selected nodes, cnt[1]: touched nodes
+    // the region's own edges in local ids (in-rows and out-rows)
+    int32_t *lin_cnt = nullptr, *lin_off = nullptr, *lout_cnt = nullptr, *lout_off = nullptr;
+    int32_t *lin_adj = nullptr, *lout_adj = nullptr;
+    int64_t ladj_cap = 0;
+    void *scan_temp = nullptr;
+    size_t scan_bytes = 0;
     float *dinv = nullptr;
     double *xhat = nullptr, *wbuf = nullptr, *qn = nullptr, *part = nullptr, *sums = nullptr;
     void *temp = nullptr;
@@ -748,6 +754,16 @@ static void warm_free(rwr_ctx *c) {
   dev_free(w.flags);
   dev_free(w.R);
   dev_free(w.cnt);
+  dev_free(w.lin_cnt);
+  dev_free(w.lin_off);
+  dev_free(w.lout_cnt);
+  dev_free(w.lout_off);
+  dev_free(w.lin_adj);
+  dev_free(w.lout_adj);
+  w.ladj_cap = 0;
+  if (w.scan_temp) (void)hipFree(w.scan_temp);
+  w.scan_temp = nullptr;
+  w.scan_bytes = 0;
   dev_free(w.dinv);
   dev_free(w.xhat);
   dev_free(w.wbuf);
@@ -774,6 +790,12 @@ static rwr_status warm_alloc(rwr_ctx *c, int64_t max_rows) {
   RWR_TRY(alloc_zero(c, &w.flags, c->n_cap));
   RWR_TRY(alloc_zero(c, &w.wbuf, (size_t)c->n_cap * c->S));
   RWR_TRY(alloc_zero(c, &w.R, w.max_nodes));
+  RWR_TRY(alloc_zero(c, &w.lin_cnt, w.max_nodes + 1));
+  RWR_TRY(alloc_zero(c, &w.lin_off, w.max_nodes + 1));
+  RWR_TRY(alloc_zero(c, &w.lout_cnt, w.max_nodes + 1));
+  RWR_TRY(alloc_zero(c, &w.lout_off, w.max_nodes + 1));
+  w.scan_bytes = ws_scan_temp_bytes((int32_t)w.max_nodes);
+  RWR_TRY(dev_alloc(c, &w.scan_temp, w.scan_bytes));
   RWR_TRY(alloc_zero(c, &w.dinv, w.max_nodes));
   RWR_TRY(alloc_zero(c, &w.xhat, w.max_rows));
   RWR_TRY(alloc_zero(c, &w.cnt, 4));
@@ -787,22 +809,45 @@ static rwr_status warm_alloc(rwr_ctx *c, int64_t max_rows) {
   return RWR_OK;
 }
 
+// the network's view of the region: its own edges in local ids
 static gnn::RegionView warm_view(rwr_ctx *c) {
   const rwr_ctx::Warm &w = c->ws;
-  const DevGraphView &in = c->g[pull_orient(c)].v;
-  const DevGraphView &out = c->g[0].v;
   gnn::RegionView g{};
-  g.in_off = in.off;
-  g.in_len = in.len;
-  g.in_adj = in.adj;
-  g.out_off = out.off;
-  g.out_len = out.len;
-  g.out_adj = out.adj;
-  g.loc = w.loc1;
-  g.nodes = w.R;
+  g.in_off = w.lin_off;
+  g.in_len = w.lin_cnt;
+  g.in_adj = w.lin_adj;
+  g.out_off = w.lout_off;
+  g.out_len = w.lout_cnt;
+  g.out_adj = w.lout_adj;
+  g.loc = nullptr;
+  g.nodes = nullptr;
   g.dinv = w.dinv;
   g.nR = w.nR;
   return g;
+}
+
+// local in- and out-rows of the region (after ws_loc)
+static rwr_status warm_local_graph(rwr_ctx *c) {
+  rwr_ctx::Warm &w = c->ws;
+  const DevGraphView &in = c->g[pull_orient(c)].v;
+  const DevGraphView &out = c->g[0].v;
+  HIP_TRY(c, ws_local_rows(w.R, w.nR, in, w.loc1, w.lin_cnt, w.lin_off, w.scan_temp, w.scan_bytes, c->stream));
+  HIP_TRY(c, ws_local_rows(w.R, w.nR, out, w.loc1, w.lout_cnt, w.lout_off, w.scan_temp, w.scan_bytes, c->stream));
+  int32_t tin = 0, tout = 0;
+  D2H(c, &tin, w.lin_off + w.nR, sizeof(int32_t));
+  D2H(c, &tout, w.lout_off + w.nR, sizeof(int32_t));
+  const int64_t need = std::max<int64_t>(std::max(tin, tout), 1);
+  if (need > w.ladj_cap) {
+    dev_free(w.lin_adj);
+    dev_free(w.lout_adj);
+    const int64_t cap = std::max<int64_t>(need, 2 * w.ladj_cap);
+    RWR_TRY(dev_alloc(c, (void **)&w.lin_adj, sizeof(int32_t) * cap));
+    RWR_TRY(dev_alloc(c, (void **)&w.lout_adj, sizeof(int32_t) * cap));
+    w.ladj_cap = cap;
+  }
+  ws_local_fill(w.R, w.nR, in, w.loc1, w.lin_off, w.lin_adj, c->stream);
+  ws_local_fill(w.R, w.nR, out, w.loc1, w.lout_off, w.lout_adj, c->stream);
+  return RWR_OK;
 }
 
 // After the offset seed (q in ybuf, its support stamped) and the structural
@@ -851,6 +896,7 @@ static rwr_status warm_prepare(rwr_ctx *c) {
   const int64_t rows = (int64_t)nR * S;
   const double c1 = 1.0 - c->cfg.c;
   ws_loc(w.R, nR, out, w.loc1, w.dinv, c->stream);
+  RWR_TRY(warm_local_graph(c));
   ws_qnorm(w.R, n0, S, c->ybuf, w.part, w.qn, c->stream);
   ws_features(w.R, nR, S, w.hop1, in, out, c->ybuf, c->r, c->ctl, c->seeds_d, w.qn, c->n, w.net.F, c->stream);
   gnn::net_forward(w.net, warm_view(c), rows, c->stream);
@@ -1158,9 +1204,9 @@ static rwr_status ensure_batch(rwr_ctx *c, int64_t nkeys, int64_t nints) {
     dev_free(c->flags);
     dev_free(c->pos);
     RWR_TRY(alloc_zero(c, &c->keys_alt, cap));
-    RWR_TRY(alloc_zero(c, &c->flags, cap));
-    RWR_TRY(alloc_zero(c, &c->pos, cap));
-    RWR_TRY(ensure_temp(c, sort_temp_bytes((int32_t)cap)));
+    RWR_TRY(alloc_zero(c, &c->flags, cap + 1));
+    RWR_TRY(alloc_zero(c, &c->pos, cap + 1));
+    RWR_TRY(ensure_temp(c, std::max(sort_temp_bytes((int32_t)cap), seed_scan_temp_bytes((int32_t)cap))));
     c->bcap = cap;
   }
   if (nints > c->b_host_cap) {
@@ -1335,8 +1381,9 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   launch_reset_run(c->ctl, c->S, all_cols_mask(c->n_seeds), c->cfg.eps, c->max_iters, dense_thresh(c),
                    c->n / 16 + 1, c->stream);
   if (nkeys > 0) {
-    launch_offset_seed(c->S, c->keys[0], c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->g[0].v, c->r, c->ybuf,
-                       c->stamp, c->ctl, b1, 1.0 - c->cfg.c, (int32_t)nkeys, c->stream);
+    HIP_TRY(c, launch_offset_seed(c->S, c->keys[0], c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->g[0].v,
+                                  c->r, c->ybuf, c->stamp, c->ctl, b1, 1.0 - c->cfg.c, (int32_t)nkeys, c->flags,
+                                  c->pos, c->temp, c->temp_bytes, 4 * c->n_cu, c->stream));
     for (int o = 0; o < norient; ++o)
       launch_apply(c->keys[o], c->seg[o], c->row[o], c->t_dold[o], c->t_dnew[o], c->g[o].v, c->ctl, o, b1,
                    (int32_t)nkeys, c->g[o].e_cap, c->stream);

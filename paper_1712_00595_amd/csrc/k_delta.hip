@@ -353,45 +353,71 @@ __global__ void k_validate_plan(const uint64_t *__restrict__ keys, const int32_t
 }
 
 // ------------------------------------------------- offset seed
-// One wavefront per touched row u of A~ (before the row is rewritten).
-// Lane layout: column j = lane % S, edge slot p = lane / S.  Contributions go
-// to ybuf (FP64, atomically); every node receiving a non-zero contribution is
-// appended once to frontier list 0.
+// Work items: touched row u of A~ (before the row is rewritten) cut into
+// chunks of SEED_CHUNK old neighbours; item 0 of a row also takes the row's
+// inserted neighbours.  k_seed_items counts the items of each touched row
+// (0 past the touched rows); an exclusive prefix sum gives each row's first
+// item, and the total is the entry at index max_rows.
+#define SEED_CHUNK 1024
+
+__global__ void k_seed_items(const int32_t *__restrict__ t_dold, const Ctl *__restrict__ ctl, int32_t max_rows,
+                             int32_t *__restrict__ items) {
+  const int32_t nT = ctl->err ? 0 : ctl->nT[0];
+  for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t <= max_rows; t += gridDim.x * blockDim.x)
+    items[t] = t < nT ? max(1, (t_dold[t] + SEED_CHUNK - 1) / SEED_CHUNK) : 0;
+}
+
+// One wavefront per item, the waves looping over all items.  Lane layout:
+// column j = lane % S, edge slot p = lane / S.  Contributions go to ybuf
+// (FP64, atomically); receiving nodes are stamped.
 template <int S>
 __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *__restrict__ seg,
                               const int32_t *__restrict__ row, const int32_t *__restrict__ t_dold,
-                              const int32_t *__restrict__ t_dnew, const int32_t *__restrict__ off,
-                              const int32_t *__restrict__ adj, const double *__restrict__ r,
-                              double *__restrict__ ybuf, int32_t *__restrict__ stamp,
-                              Ctl *ctl, int b1, double c1) {
+                              const int32_t *__restrict__ t_dnew, const int32_t *__restrict__ item_off,
+                              const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
+                              const double *__restrict__ r, double *__restrict__ ybuf, int32_t *__restrict__ stamp,
+                              Ctl *ctl, int b1, double c1, int32_t max_rows) {
   if (ctl->err) return;
   constexpr int P = RWR_WAVE / S;
   const int lane = threadIdx.x % RWR_WAVE;
   const int j = lane % S, p = lane / S;
-  const int32_t t = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE;
-  if (t >= ctl->nT[0]) return;
-  const int32_t u = row[t], b = seg[t], e = seg[t + 1];
-  const int32_t d_old = t_dold[t], d_new = t_dnew[t];
-  const double ru = r[col_index(u, S, j)];
-  const double w_old = d_old ? c1 * ru / (double)d_old : 0.0;
-  const double w_new = d_new ? c1 * ru / (double)d_new : 0.0;
-  const bool any_r = __ballot(ru != 0.0) != 0ull;
-  if (!any_r) return;
+  const int32_t nT = ctl->nT[0];
+  const int32_t total = item_off[max_rows];
   const int32_t st = ctl->stamp;
-  const int32_t o = off[u];
-  for (int32_t i = p; i < d_old; i += P) {
-    const int32_t v = adj[o + i];
-    const bool del = seg_find(keys, b, e, u, v, b1) >= 0;  // validated: a hit is a deletion
-    const double contrib = del ? -w_old : (w_new - w_old);
-    if (contrib != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], contrib);
-    if (j == 0 && (del || d_new != d_old)) stamp[v] = st;
-  }
-  for (int32_t i = b + p; i < e; i += P) {
-    const uint64_t k = keys[i];
-    if (!(k & 1ull)) continue;
-    const int32_t v = key_col(k, b1);
-    if (w_new != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], w_new);
-    if (j == 0) stamp[v] = st;
+  for (int32_t it = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; it < total;
+       it += gridDim.x * blockDim.x / RWR_WAVE) {
+    // the touched row of item `it`: last t with item_off[t] <= it
+    int32_t lo = 0, hi = nT - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (item_off[mid] <= it) lo = mid;
+      else hi = mid - 1;
+    }
+    const int32_t t = lo;
+    const int32_t k = it - item_off[t];
+    const int32_t u = row[t], b = seg[t], e = seg[t + 1];
+    const int32_t d_old = t_dold[t], d_new = t_dnew[t];
+    const double ru = r[col_index(u, S, j)];
+    if (__ballot(ru != 0.0) == 0ull) continue;
+    const double w_old = d_old ? c1 * ru / (double)d_old : 0.0;
+    const double w_new = d_new ? c1 * ru / (double)d_new : 0.0;
+    const int32_t o = off[u];
+    const int32_t i1 = min(d_old, (k + 1) * SEED_CHUNK);
+    for (int32_t i = k * SEED_CHUNK + p; i < i1; i += P) {
+      const int32_t v = adj[o + i];
+      const bool del = seg_find(keys, b, e, u, v, b1) >= 0;  // validated: a hit is a deletion
+      const double contrib = del ? -w_old : (w_new - w_old);
+      if (contrib != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], contrib);
+      if (j == 0 && (del || d_new != d_old)) stamp[v] = st;
+    }
+    if (k != 0) continue;
+    for (int32_t i = b + p; i < e; i += P) {
+      const uint64_t kk = keys[i];
+      if (!(kk & 1ull)) continue;
+      const int32_t v = key_col(kk, b1);
+      if (w_new != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], w_new);
+      if (j == 0) stamp[v] = st;
+    }
   }
 }
 
@@ -547,21 +573,27 @@ void launch_validate_plan(const uint64_t *keys, const int32_t *seg, const int32_
 
 template <int S>
 static void offset_seed_s(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
-                          const int32_t *t_dnew, const DevGraphView &g, const double *r, double *ybuf, int32_t *stamp,
-                          Ctl *ctl, int b1, double c1, int32_t max_rows, hipStream_t st) {
-  const int waves_per_block = 4;
-  const int grid = (max_rows + waves_per_block - 1) / waves_per_block;
-  hipLaunchKernelGGL(k_offset_seed<S>, dim3(grid), dim3(waves_per_block * RWR_WAVE), 0, st, keys, seg, row, t_dold,
-                     t_dnew, g.off, g.adj, r, ybuf, stamp, ctl, b1, c1);
+                          const int32_t *t_dnew, const int32_t *item_off, const DevGraphView &g, const double *r,
+                          double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1, int32_t max_rows, int grid,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_offset_seed<S>, dim3(grid), dim3(256), 0, st, keys, seg, row, t_dold, t_dnew, item_off, g.off,
+                     g.adj, r, ybuf, stamp, ctl, b1, c1, max_rows);
 }
 
-void launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
-                        const int32_t *t_dnew, const DevGraphView &g, const double *r, double *ybuf, int32_t *stamp,
-                        Ctl *ctl, int b1, double c1, int32_t max_rows, hipStream_t st) {
-  if (max_rows <= 0) return;
-#define RWR_SEED_CASE(SS)                                                                                       \
-  case SS:                                                                                                      \
-    offset_seed_s<SS>(keys, seg, row, t_dold, t_dnew, g, r, ybuf, stamp, ctl, b1, c1, max_rows, st); \
+hipError_t launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row,
+                              const int32_t *t_dold, const int32_t *t_dnew, const DevGraphView &g, const double *r,
+                              double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1, int32_t max_rows,
+                              int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes, int grid,
+                              hipStream_t st) {
+  if (max_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seed_items, dim3(std::min(4096, (max_rows + 256) / 256)), dim3(256), 0, st, t_dold, ctl,
+                     max_rows, items);
+  hipError_t e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, items, item_off, max_rows + 1, st);
+  if (e != hipSuccess) return e;
+#define RWR_SEED_CASE(SS)                                                                                        \
+  case SS:                                                                                                       \
+    offset_seed_s<SS>(keys, seg, row, t_dold, t_dnew, item_off, g, r, ybuf, stamp, ctl, b1, c1, max_rows, grid, \
+                      st);                                                                                       \
     break;
   switch (S) {
     RWR_SEED_CASE(1)
@@ -573,6 +605,13 @@ void launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const i
     RWR_SEED_CASE(64)
   }
 #undef RWR_SEED_CASE
+  return hipSuccess;
+}
+
+size_t seed_scan_temp_bytes(int32_t max_rows) {
+  size_t bytes = 0;
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, (const int32_t *)nullptr, (int32_t *)nullptr, max_rows + 1);
+  return bytes;
 }
 
 void launch_apply(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,

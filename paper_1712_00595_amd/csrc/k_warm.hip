@@ -15,6 +15,8 @@
 
 #define WB 256
 
+__device__ __forceinline__ uint64_t lanemask_below(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
+
 // ------------------------------------------------------------ region
 // flags[v] = 1 when v belongs to level h: the stamped offset support for
 // h = 0 (marked hop 1), else the nodes marked h + 1 by the expansion
@@ -67,6 +69,42 @@ __global__ void k_ws_clear(const int32_t *__restrict__ R, int32_t nR, int32_t *_
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nR; i += gridDim.x * blockDim.x) {
     hop1[R[i]] = 0;
     loc1[R[i]] = 0;
+  }
+}
+
+// ------------------------------------------------------------ local region graph
+// The region's own edges in local ids, so that the network's aggregations
+// touch only them: rows of the region nodes in one orientation of the device
+// graph, filtered to neighbours inside the region, in row order.
+// One wavefront per region node.
+__global__ void k_ws_count_local(const int32_t *__restrict__ R, int32_t nR, DevGraphView gv,
+                                 const int32_t *__restrict__ loc1, int32_t *__restrict__ cnt) {
+  const int lane = threadIdx.x % RWR_WAVE;
+  for (int w = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; w < nR; w += gridDim.x * blockDim.x / RWR_WAVE) {
+    const int v = R[w];
+    const int o = gv.off[v], d = gv.len[v];
+    int c = 0;
+    for (int e = lane; e < d; e += RWR_WAVE) c += loc1[gv.adj[o + e]] > 0;
+    for (int off = 1; off < RWR_WAVE; off <<= 1) c += __shfl_xor(c, off, RWR_WAVE);
+    if (lane == 0) cnt[w] = c;
+  }
+}
+
+__global__ void k_ws_fill_local(const int32_t *__restrict__ R, int32_t nR, DevGraphView gv,
+                                const int32_t *__restrict__ loc1, const int32_t *__restrict__ off,
+                                int32_t *__restrict__ adj) {
+  const int lane = threadIdx.x % RWR_WAVE;
+  for (int w = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; w < nR; w += gridDim.x * blockDim.x / RWR_WAVE) {
+    const int v = R[w];
+    const int o = gv.off[v], d = gv.len[v];
+    int base = off[w];
+    for (int e0 = 0; e0 < d; e0 += RWR_WAVE) {
+      const int e = e0 + lane;
+      const int l = e < d ? loc1[gv.adj[o + e]] : 0;
+      const uint64_t m = __ballot(l > 0);
+      if (l > 0) adj[base + __popcll(m & lanemask_below(lane))] = l - 1;
+      base += __popcll(m);
+    }
   }
 }
 
@@ -379,6 +417,26 @@ void ws_expand(const int32_t *list, int32_t cnt, const DevGraphView &out, int32_
 void ws_unmark(const int32_t *list, int32_t cnt, int32_t *hop1, hipStream_t s) {
   if (cnt <= 0) return;
   hipLaunchKernelGGL(k_ws_unmark, dim3(wgrid(cnt)), dim3(WB), 0, s, list, cnt, hop1);
+}
+
+size_t ws_scan_temp_bytes(int32_t n) {
+  size_t bytes = 0;
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, (const int32_t *)nullptr, (int32_t *)nullptr, n + 1);
+  return bytes;
+}
+
+hipError_t ws_local_rows(const int32_t *R, int32_t nR, const DevGraphView &gv, const int32_t *loc1, int32_t *cnt,
+                         int32_t *off, void *temp, size_t temp_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_count_local, dim3(wgrid((int64_t)nR * RWR_WAVE)), dim3(WB), 0, s, R, nR, gv, loc1, cnt);
+  // cnt[nR] is 0, so off[nR] is the total
+  hipError_t e = hipMemsetAsync(cnt + nR, 0, sizeof(int32_t), s);
+  if (e != hipSuccess) return e;
+  return hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, cnt, off, nR + 1, s);
+}
+
+void ws_local_fill(const int32_t *R, int32_t nR, const DevGraphView &gv, const int32_t *loc1, const int32_t *off,
+                   int32_t *adj, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_fill_local, dim3(wgrid((int64_t)nR * RWR_WAVE)), dim3(WB), 0, s, R, nR, gv, loc1, off, adj);
 }
 
 void ws_loc(const int32_t *R, int32_t nR, const DevGraphView &out, int32_t *loc1, float *dinv, hipStream_t s) {

@@ -91,9 +91,14 @@ size_t sort_temp_bytes(int32_t n_keys);
 void launch_validate_plan(const uint64_t *keys, const int32_t *seg, const int32_t *row, const DevGraphView &g, int b1,
                           int32_t *t_dold, int32_t *t_dnew, Ctl *ctl, int orient, int check, int heavy_limit,
                           int32_t max_rows, hipStream_t st);
-void launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
-                        const int32_t *t_dnew, const DevGraphView &g, const double *r, double *ybuf, int32_t *stamp,
-                        Ctl *ctl, int b1, double c1, int32_t max_rows, hipStream_t st);
+// q_offset into ybuf; touched rows cut into chunks (items: max_rows + 1
+// ints, item_off: max_rows + 1 ints, temp: seed_scan_temp_bytes(max_rows))
+hipError_t launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row,
+                              const int32_t *t_dold, const int32_t *t_dnew, const DevGraphView &g, const double *r,
+                              double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1, int32_t max_rows,
+                              int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes, int grid,
+                              hipStream_t st);
+size_t seed_scan_temp_bytes(int32_t max_rows);
 void launch_apply(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
                   const int32_t *t_dnew, const DevGraphView &g, Ctl *ctl, int orient, int b1, int32_t max_rows,
                   int64_t e_cap, hipStream_t st);

@@ -25,6 +25,14 @@ hipError_t ws_select(const int32_t *flags, int32_t n, int32_t *out, int32_t *cou
 void ws_expand(const int32_t *list, int32_t cnt, const DevGraphView &out, int32_t h, int32_t *hop1, hipStream_t s);
 void ws_unmark(const int32_t *list, int32_t cnt, int32_t *hop1, hipStream_t s);
 void ws_loc(const int32_t *R, int32_t nR, const DevGraphView &out, int32_t *loc1, float *dinv, hipStream_t s);
+// Local rows of the region in orientation gv: cnt[i] = neighbours of R[i]
+// inside the region (cnt has nR + 1 entries), off = exclusive prefix sum
+// (off[nR] = total); then the rows themselves in local ids.
+size_t ws_scan_temp_bytes(int32_t n);
+hipError_t ws_local_rows(const int32_t *R, int32_t nR, const DevGraphView &gv, const int32_t *loc1, int32_t *cnt,
+                         int32_t *off, void *temp, size_t temp_bytes, hipStream_t s);
+void ws_local_fill(const int32_t *R, int32_t nR, const DevGraphView &gv, const int32_t *loc1, const int32_t *off,
+                   int32_t *adj, hipStream_t s);
 void ws_clear(const int32_t *R, int32_t nR, int32_t *hop1, int32_t *loc1, hipStream_t s);
 void ws_features(const int32_t *R, int32_t nR, int S, const int32_t *hop1, const DevGraphView &in,
                  const DevGraphView &out, const double *ybuf, const double *r, const Ctl *ctl, const int32_t *seeds,

@@ -41,6 +41,8 @@ def init_params(seed: int = 5, copy_prior: bool = True, scale: float = 1.0) -> n
             ws[:2, :] = 0.0
             ws[0, 0] = ws[1, 1] = 1.0
             parts[f"Wm{l}"][:, :2] = 0.0
-        parts["wo"][:] *= 0.01
+        # the other units start silent at the output: even a small output on
+        # each of many region nodes would add up to more than ||q||
+        parts["wo"][:] = 0.0
         parts["wo"][0], parts["wo"][1] = 1.0, -1.0
     return np.concatenate([parts[n].reshape(-1) for n, _ in layout()]).astype(np.float32)
