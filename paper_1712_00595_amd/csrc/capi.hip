@@ -123,11 +123,15 @@ struct rwr_ctx {
     int64_t max_rows = 0, max_nodes = 0;
     gnn::Net net;
     bool alloc = false, params = false;
-    int32_t *hop1 = nullptr, *loc1 = nullptr, *wmark = nullptr, *wlist = nullptr, *flags = nullptr;
+    int32_t *hop1 = nullptr, *loc1 = nullptr, *wlist = nullptr, *flags = nullptr;
     int32_t *R = nullptr, *cnt = nullptr;  // cnt[0]: selected nodes, cnt[1]: touched nodes
     // the region's own edges in local ids (in-rows and out-rows)
     int32_t *lin_cnt = nullptr, *lin_off = nullptr, *lout_cnt = nullptr, *lout_off = nullptr;
     int32_t *lin_adj = nullptr, *lout_adj = nullptr;
+    int32_t *items = nullptr, *item_off = nullptr;  // gradient work items over the region's out-rows
+    int32_t *lin_items = nullptr, *lout_items = nullptr;  // aggregation work items
+    int32_t n_in_items = 0, n_out_items = 0;
+    float *gacc = nullptr;
     int64_t ladj_cap = 0;
     void *scan_temp = nullptr;
     size_t scan_bytes = 0;
@@ -271,6 +275,7 @@ static SlotArgs slot_args(const rwr_ctx *c) {
   a.grid_pull = c->grid_pull;
   a.light_lanes = c->light_lanes;
   a.pull_lanes = c->pull_lanes;
+  a.zero_seed_rows = 1;
   a.row_order = c->row_order;
   a.n_order = c->n_cap;
   a.mp_rows = c->mp_rows;
@@ -497,7 +502,6 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
   if (c->ws.alloc) {
     RWR_TRY(regrow((void **)&c->ws.hop1, 4, 1));
     RWR_TRY(regrow((void **)&c->ws.loc1, 4, 1));
-    RWR_TRY(regrow((void **)&c->ws.wmark, 4, 1));
     RWR_TRY(regrow((void **)&c->ws.wlist, 4, 1));
     RWR_TRY(regrow((void **)&c->ws.flags, 4, 1));
     RWR_TRY(regrow((void **)&c->ws.wbuf, 8, c->S));
@@ -749,7 +753,6 @@ static void warm_free(rwr_ctx *c) {
   rwr_ctx::Warm &w = c->ws;
   dev_free(w.hop1);
   dev_free(w.loc1);
-  dev_free(w.wmark);
   dev_free(w.wlist);
   dev_free(w.flags);
   dev_free(w.R);
@@ -760,6 +763,11 @@ static void warm_free(rwr_ctx *c) {
   dev_free(w.lout_off);
   dev_free(w.lin_adj);
   dev_free(w.lout_adj);
+  dev_free(w.items);
+  dev_free(w.item_off);
+  dev_free(w.lin_items);
+  dev_free(w.lout_items);
+  dev_free(w.gacc);
   w.ladj_cap = 0;
   if (w.scan_temp) (void)hipFree(w.scan_temp);
   w.scan_temp = nullptr;
@@ -785,7 +793,6 @@ static rwr_status warm_alloc(rwr_ctx *c, int64_t max_rows) {
   HIP_TRY(c, gnn::net_alloc(w.net, c->S, w.max_rows));
   RWR_TRY(alloc_zero(c, &w.hop1, c->n_cap));
   RWR_TRY(alloc_zero(c, &w.loc1, c->n_cap));
-  RWR_TRY(alloc_zero(c, &w.wmark, c->n_cap));
   RWR_TRY(alloc_zero(c, &w.wlist, c->n_cap));
   RWR_TRY(alloc_zero(c, &w.flags, c->n_cap));
   RWR_TRY(alloc_zero(c, &w.wbuf, (size_t)c->n_cap * c->S));
@@ -794,6 +801,11 @@ static rwr_status warm_alloc(rwr_ctx *c, int64_t max_rows) {
   RWR_TRY(alloc_zero(c, &w.lin_off, w.max_nodes + 1));
   RWR_TRY(alloc_zero(c, &w.lout_cnt, w.max_nodes + 1));
   RWR_TRY(alloc_zero(c, &w.lout_off, w.max_nodes + 1));
+  RWR_TRY(alloc_zero(c, &w.items, w.max_nodes + 1));
+  RWR_TRY(alloc_zero(c, &w.lin_items, w.max_nodes + 1));
+  RWR_TRY(alloc_zero(c, &w.lout_items, w.max_nodes + 1));
+  RWR_TRY(alloc_zero(c, &w.item_off, w.max_nodes + 1));
+  RWR_TRY(alloc_zero(c, &w.gacc, w.max_rows));
   w.scan_bytes = ws_scan_temp_bytes((int32_t)w.max_nodes);
   RWR_TRY(dev_alloc(c, &w.scan_temp, w.scan_bytes));
   RWR_TRY(alloc_zero(c, &w.dinv, w.max_nodes));
@@ -819,6 +831,10 @@ static gnn::RegionView warm_view(rwr_ctx *c) {
   g.out_off = w.lout_off;
   g.out_len = w.lout_cnt;
   g.out_adj = w.lout_adj;
+  g.in_items = w.lin_items;
+  g.out_items = w.lout_items;
+  g.n_in_items = w.n_in_items;
+  g.n_out_items = w.n_out_items;
   g.loc = nullptr;
   g.nodes = nullptr;
   g.dinv = w.dinv;
@@ -847,6 +863,12 @@ static rwr_status warm_local_graph(rwr_ctx *c) {
   }
   ws_local_fill(w.R, w.nR, in, w.loc1, w.lin_off, w.lin_adj, c->stream);
   ws_local_fill(w.R, w.nR, out, w.loc1, w.lout_off, w.lout_adj, c->stream);
+  HIP_TRY(c, ws_chunk_items(w.lin_cnt, w.nR, gnn::AGG_CHUNK, w.items, w.lin_items, w.scan_temp, w.scan_bytes,
+                            c->stream));
+  HIP_TRY(c, ws_chunk_items(w.lout_cnt, w.nR, gnn::AGG_CHUNK, w.items, w.lout_items, w.scan_temp, w.scan_bytes,
+                            c->stream));
+  D2H(c, &w.n_in_items, w.lin_items + w.nR, sizeof(int32_t));
+  D2H(c, &w.n_out_items, w.lout_items + w.nR, sizeof(int32_t));
   return RWR_OK;
 }
 
@@ -900,12 +922,15 @@ static rwr_status warm_prepare(rwr_ctx *c) {
   ws_qnorm(w.R, n0, S, c->ybuf, w.part, w.qn, c->stream);
   ws_features(w.R, nR, S, w.hop1, in, out, c->ybuf, c->r, c->ctl, c->seeds_d, w.qn, c->n, w.net.F, c->stream);
   gnn::net_forward(w.net, warm_view(c), rows, c->stream);
-  HIP_TRY(c, hipMemsetAsync(w.cnt + 1, 0, sizeof(int32_t), c->stream));
-  ws_predict_residual(w.R, nR, S, out, w.net.o, w.qn, c1, w.xhat, w.wbuf, w.wmark, w.wlist, w.cnt + 1, w.part,
-                      w.sums + 2 * RWR_MAX_COLS, c->stream);
-  int32_t touched = 0;
-  D2H(c, &touched, w.cnt + 1, sizeof(int32_t));
-  ws_rho_norm(w.wlist, w.cnt + 1, touched, S, c->ybuf, w.xhat, w.loc1, w.wbuf, w.part, w.sums, c->stream);
+  // prediction in wbuf (dense), (1-c) B~^T xhat - xhat in gbuf, rho = q + that
+  ws_predict(w.R, nR, S, out, w.net.o, w.qn, c1, w.xhat, w.wbuf, w.part, w.sums + 2 * RWR_MAX_COLS, c->stream);
+  {
+    SlotArgs a = slot_args(c);
+    a.r = w.wbuf;
+    a.zero_seed_rows = 0;
+    launch_apply_p(a, S, c->stream);
+  }
+  ws_rho(c->n, S, c->ybuf, c->gbuf, w.wbuf, w.part, w.sums, c->stream);
   std::vector<double> sums(2 * S);
   D2H(c, sums.data(), w.sums, sizeof(double) * 2 * S);
   w.qn_h.assign(S, 0.0);
@@ -931,12 +956,13 @@ static rwr_status warm_prepare(rwr_ctx *c) {
   if ((w.mode & 2) && n_act > 0) {
     w.loss = lsum / n_act;
     H2D(c, w.net.active, act.data(), sizeof(int32_t) * RWR_MAX_COLS);
-    ws_resid_grad(w.R, nR, S, out, c1, c->ybuf, w.xhat, w.loc1, w.wbuf, w.net.active, n_act, w.net.dout, c->stream);
+    HIP_TRY(c, ws_resid_grad(w.R, nR, S, out, c1, c->gbuf, w.gacc, w.items, w.item_off, w.scan_temp, w.scan_bytes,
+                             w.net.active, n_act, w.net.dout, c->stream));
     gnn::net_backward(w.net, warm_view(c), rows, c->stream);
     gnn::net_adamw(w.net, c->stream);
   }
-  ws_apply(w.wlist, w.cnt + 1, touched, S, accept, c->ybuf, c->r, w.xhat, w.loc1, w.wbuf, w.wmark, c->stamp, c->ctl,
-           w.sums + S, c->stream);
+  ws_apply(c->n, S, accept, c->ybuf, c->gbuf, c->r, w.wbuf, c->stamp, c->ctl, w.sums + S, c->stream);
+  ws_unscatter(w.R, nR, S, w.wbuf, c->stream);
   ws_clear(w.R, nR, w.hop1, w.loc1, c->stream);
   w.ms = now_ms() - t0;
   return RWR_OK;
@@ -1701,10 +1727,20 @@ rwr_status rwr_gnn_eval(const float *params, int32_t nR, int32_t S, const int32_
     g.out_len = (const int32_t *)up(out_len, sizeof(int32_t) * nR);
     g.out_adj = (const int32_t *)up(out_adj, sizeof(int32_t) * n_out);
     g.dinv = (const float *)up(dinv, sizeof(float) * nR);
+    std::vector<int32_t> ii(nR + 1, 0), oi(nR + 1, 0);
+    for (int32_t i = 0; i < nR; ++i) {
+      ii[i + 1] = ii[i] + (in_len[i] + gnn::AGG_CHUNK - 1) / gnn::AGG_CHUNK;
+      oi[i + 1] = oi[i] + (out_len[i] + gnn::AGG_CHUNK - 1) / gnn::AGG_CHUNK;
+    }
+    g.in_items = (const int32_t *)up(ii.data(), sizeof(int32_t) * (nR + 1));
+    g.out_items = (const int32_t *)up(oi.data(), sizeof(int32_t) * (nR + 1));
+    g.n_in_items = ii[nR];
+    g.n_out_items = oi[nR];
     g.loc = nullptr;
     g.nodes = nullptr;
     g.nR = nR;
-    if (!g.in_off || !g.in_len || !g.in_adj || !g.out_off || !g.out_len || !g.out_adj || !g.dinv ||
+    if (!g.in_off || !g.in_len || !g.in_adj || !g.out_off || !g.out_len || !g.out_adj || !g.dinv || !g.in_items ||
+        !g.out_items ||
         hipMemcpyAsync(net.F, feats, sizeof(float) * rows * gnn::FEAT, hipMemcpyHostToDevice, st) != hipSuccess) {
       ret = RWR_ENOMEM;
       break;

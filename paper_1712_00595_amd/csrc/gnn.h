@@ -19,6 +19,7 @@ constexpr int FEAT = 16;
 constexpr int HID = 64;
 constexpr int MSG = 16;
 constexpr int LAYERS = 3;
+constexpr int AGG_CHUNK = 128;  // edges per aggregation work item
 
 // parameter vector layout (float32), in this order:
 //   W0[FEAT x HID] b0[HID]  { Wp[HID x MSG] Ws[HID x HID] Wm[MSG x HID] b[HID] } x LAYERS  wo[HID] bo[1]
@@ -47,6 +48,12 @@ struct WeightsBf16 {
 struct RegionView {
   const int32_t *in_off, *in_len, *in_adj;     // in-rows (forward aggregation)
   const int32_t *out_off, *out_len, *out_adj;  // out-rows (backward aggregation)
+  // work items: rows cut into AGG_CHUNK-edge chunks; *_items[i] = first item
+  // of local row i (exclusive prefix of the chunk counts, nR + 1 entries),
+  // n_*_items the total.  Rows of one chunk are written, rows of several
+  // chunks accumulated.
+  const int32_t *in_items, *out_items;
+  int32_t n_in_items, n_out_items;
   const int32_t *loc;
   const int32_t *nodes;
   const float *dinv;  // 1/d_out of each local node (0 for dead ends)

@@ -236,55 +236,80 @@ __global__ void k_reduce_part(const float *__restrict__ part, int nb, int count,
 }
 
 // ------------------------------------------------------------ aggregation
-// Y[i*S+j][q] = sum over in-edges u -> v of region node i of dinv[lu] M[lu*S+j][q]
-__global__ void k_agg_fwd(RegionView g, int S, const float *__restrict__ Min, float *__restrict__ Y) {
-  const int64_t total = (int64_t)g.nR * S * 4;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int q = (int)(e % 4);
-    const int64_t rj = e / 4;
-    const int j = (int)(rj % S);
-    const int i = (int)(rj / S);
-    const int v = g.nodes ? g.nodes[i] : i;
-    const int o = g.in_off[v], d = g.in_len[v];
-    float4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < d; ++k) {
-      const int u = g.in_adj[o + k];
-      const int lu = g.loc ? g.loc[u] - 1 : u;
-      if (lu < 0) continue;
-      const float s = g.dinv[lu];
-      const float4 x = *reinterpret_cast<const float4 *>(Min + ((int64_t)lu * S + j) * MSG + 4 * q);
-      acc.x += s * x.x;
-      acc.y += s * x.y;
-      acc.z += s * x.z;
-      acc.w += s * x.w;
+// Work unit = (item, c) with c = 4 j + q over the 4 S float4 slices of a
+// row (node i, column j, message entries 4q .. 4q+3).  Forward (IN = true):
+//   Y[i*S+j][.] = sum over in-edges u -> i of dinv[u] M[u*S+j][.]
+// backward (IN = false):
+//   Y[i*S+j][.] = dinv[i] sum over out-edges i -> v of M[v*S+j][.]
+// Four gathers in flight per thread.  A row of several chunks is zeroed
+// beforehand and its chunks accumulate with float atomics.
+template <bool IN>
+__global__ void k_agg(RegionView g, int S, const float *__restrict__ Min, float *__restrict__ Y) {
+  const int32_t *items = IN ? g.in_items : g.out_items;
+  const int32_t n_items = IN ? g.n_in_items : g.n_out_items;
+  const int32_t *roff = IN ? g.in_off : g.out_off;
+  const int32_t *rlen = IN ? g.in_len : g.out_len;
+  const int32_t *radj = IN ? g.in_adj : g.out_adj;
+  const int per = 4 * S;
+  const int64_t total = (int64_t)n_items * per;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t it = (int32_t)(t / per);
+    const int cidx = (int)(t % per);
+    const int j = cidx / 4, q = cidx % 4;
+    int32_t lo = 0, hi = g.nR - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (items[mid] <= it) lo = mid;
+      else hi = mid - 1;
     }
-    *reinterpret_cast<float4 *>(Y + rj * MSG + 4 * q) = acc;
+    const int i = lo;
+    const int k = it - items[i];
+    const int nch = items[i + 1] - items[i];
+    const int o = roff[i], d = rlen[i];
+    const int e0 = k * AGG_CHUNK, e1 = min(d, e0 + AGG_CHUNK);
+    float4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int e = e0; e < e1; e += 4) {
+      int uu[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) uu[x] = e + x < e1 ? radj[o + e + x] : -1;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        if (uu[x] < 0) continue;
+        const float s = IN ? g.dinv[uu[x]] : 1.0f;
+        const float4 m = *reinterpret_cast<const float4 *>(Min + ((int64_t)uu[x] * S + j) * MSG + 4 * q);
+        acc.x += s * m.x;
+        acc.y += s * m.y;
+        acc.z += s * m.z;
+        acc.w += s * m.w;
+      }
+    }
+    if (!IN) {
+      const float s = g.dinv[i];
+      acc.x *= s;
+      acc.y *= s;
+      acc.z *= s;
+      acc.w *= s;
+    }
+    float *dst = Y + ((int64_t)i * S + j) * MSG + 4 * q;
+    if (nch == 1) {
+      *reinterpret_cast<float4 *>(dst) = acc;
+    } else {
+      atomicAdd(dst, acc.x);
+      atomicAdd(dst + 1, acc.y);
+      atomicAdd(dst + 2, acc.z);
+      atomicAdd(dst + 3, acc.w);
+    }
   }
 }
 
-// transpose: Y[i*S+j][q] = dinv[i] * sum over out-edges u -> v of region node i of D[lv*S+j][q]
-__global__ void k_agg_bwd(RegionView g, int S, const float *__restrict__ D, float *__restrict__ Y) {
-  const int64_t total = (int64_t)g.nR * S * 4;
+// zero the rows of several chunks (and rows without edges) before k_agg
+template <bool IN>
+__global__ void k_agg_zero(RegionView g, int S, float *__restrict__ Y) {
+  const int32_t *items = IN ? g.in_items : g.out_items;
+  const int64_t total = (int64_t)g.nR * S * MSG;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int q = (int)(e % 4);
-    const int64_t rj = e / 4;
-    const int j = (int)(rj % S);
-    const int i = (int)(rj / S);
-    const int u = g.nodes ? g.nodes[i] : i;
-    const int o = g.out_off[u], d = g.out_len[u];
-    float4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < d; ++k) {
-      const int v = g.out_adj[o + k];
-      const int lv = g.loc ? g.loc[v] - 1 : v;
-      if (lv < 0) continue;
-      const float4 x = *reinterpret_cast<const float4 *>(D + ((int64_t)lv * S + j) * MSG + 4 * q);
-      acc.x += x.x;
-      acc.y += x.y;
-      acc.z += x.z;
-      acc.w += x.w;
-    }
-    const float s = g.dinv[i];
-    *reinterpret_cast<float4 *>(Y + rj * MSG + 4 * q) = float4{s * acc.x, s * acc.y, s * acc.z, s * acc.w};
+    const int i = (int)(e / ((int64_t)S * MSG));
+    if (items[i + 1] - items[i] != 1) Y[e] = 0.0f;
   }
 }
 
@@ -458,16 +483,22 @@ static const __bf16 *bwd_w(const Net &n, int i) { return n.wb.bwd + mat_table().
 
 static int gemm_grid(int64_t rows) { return grid_for((rows + 15) / 16, GB / WAVE, 8192); }
 
+template <bool IN>
+static void agg(const RegionView &g, int S, int64_t rows, const float *Min, float *Y, hipStream_t st) {
+  hipLaunchKernelGGL(k_agg_zero<IN>, dim3(grid_for(rows * MSG, GB)), dim3(GB), 0, st, g, S, Y);
+  const int64_t work = (int64_t)(IN ? g.n_in_items : g.n_out_items) * 4 * S;
+  if (work > 0) hipLaunchKernelGGL(k_agg<IN>, dim3(grid_for(work, GB, 8192)), dim3(GB), 0, st, g, S, Min, Y);
+}
+
 void net_forward(Net &n, const RegionView &g, int64_t rows, hipStream_t st) {
   const float *th = n.theta;
   const int gg = gemm_grid(rows);
   hipLaunchKernelGGL((k_gemm<FEAT, 0, HID, EPI_BIAS_RELU>), dim3(gg), dim3(GB), 0, st, rows, n.F, nullptr,
                      fwd_w(n, 0), nullptr, th + LAYOUT.b0, nullptr, n.h[0]);
-  const int ga = grid_for(rows * 4, GB);
   for (int l = 0; l < LAYERS; ++l) {
     hipLaunchKernelGGL((k_gemm<HID, 0, MSG, EPI_NONE>), dim3(gg), dim3(GB), 0, st, rows, n.h[l], nullptr,
                        fwd_w(n, 1 + 3 * l), nullptr, nullptr, nullptr, n.m);
-    hipLaunchKernelGGL(k_agg_fwd, dim3(ga), dim3(GB), 0, st, g, n.S, n.m, n.a[l]);
+    agg<true>(g, n.S, rows, n.m, n.a[l], st);
     hipLaunchKernelGGL((k_gemm<HID, MSG, HID, EPI_BIAS_RELU>), dim3(gg), dim3(GB), 0, st, rows, n.h[l], n.a[l],
                        fwd_w(n, 2 + 3 * l), fwd_w(n, 3 + 3 * l), th + LAYOUT.b[l], nullptr, n.h[l + 1]);
   }
@@ -501,7 +532,6 @@ void net_backward(Net &n, const RegionView &g, int64_t rows, hipStream_t st) {
   float *G = n.grad;
   const float *th = n.theta;
   const int gg = gemm_grid(rows);
-  const int ga = grid_for(rows * 4, GB);
   // output layer
   colsum<HID, 1>(n, rows, n.h[LAYERS], n.dout, G + LAYOUT.wo, st);
   colsum<1, 0>(n, rows, n.dout, nullptr, G + LAYOUT.bo, st);
@@ -515,7 +545,7 @@ void net_backward(Net &n, const RegionView &g, int64_t rows, hipStream_t st) {
     // da = dz Wm^T ; dm = aggregation transpose of da
     hipLaunchKernelGGL((k_gemm<HID, 0, MSG, EPI_NONE>), dim3(gg), dim3(GB), 0, st, rows, n.dz, nullptr,
                        bwd_w(n, 3 + 3 * l), nullptr, nullptr, nullptr, n.da);
-    hipLaunchKernelGGL(k_agg_bwd, dim3(ga), dim3(GB), 0, st, g, n.S, n.da, n.dm);
+    agg<false>(g, n.S, rows, n.da, n.dm, st);
     wgrad<HID, MSG>(n, rows, n.h[l], n.dm, G + LAYOUT.Wp[l], st);
     // dz of layer l = (dz Ws^T + dm Wp^T) masked by h_l > 0
     hipLaunchKernelGGL((k_gemm<HID, MSG, HID, EPI_RELU_MASK>), dim3(gg), dim3(GB), 0, st, rows, n.dz, n.dm,

@@ -357,7 +357,7 @@ __device__ __forceinline__ void pull_epilogue(const SlotArgs &a, XT *__restrict_
   if constexpr (KIND == KIND_RESID) {
     const double rv = a.r[kk];
     double g = y - rv;
-    if (j >= a.n_seeds || a.seeds[j] == v) g = 0.0;
+    if (j >= a.n_seeds || (a.zero_seed_rows && a.seeds[j] == v)) g = 0.0;
     a.gbuf[kk] = g;
     nrm += fabs(g);
     sm += rv;
@@ -530,7 +530,7 @@ __device__ __forceinline__ void pull_epilogue_vec(const SlotArgs &a, XT *__restr
 #pragma unroll
     for (int q = 0; q < V; ++q) {
       g[q] = y[q] - rv[q];
-      if (j0 + q >= a.n_seeds || a.seeds[j0 + q] == v) g[q] = 0.0;
+      if (j0 + q >= a.n_seeds || (a.zero_seed_rows && a.seeds[j0 + q] == v)) g[q] = 0.0;
       nrm[q] += fabs(g[q]);
       sm[q] += rv[q];
     }
@@ -858,7 +858,7 @@ __global__ __launch_bounds__(BLOCK) void k_pull_mp(SlotArgs a, int k) {
       const double y = c1 * M.rowacc[t];
       if constexpr (KIND == KIND_RESID) {
         double g = y - rv;
-        if (a.n_seeds < 1 || a.seeds[0] == v) g = 0.0;
+        if (a.n_seeds < 1 || (a.zero_seed_rows && a.seeds[0] == v)) g = 0.0;
         a.gbuf[v] = g;
         nrm += fabs(g);
         sm += rv;
@@ -1081,7 +1081,8 @@ void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st) 
 // dense sweep (or residual) + heavy rows + decision; the heavy-row kernel
 // publishes after the sweep's entries
 template <typename XT, int S, int KIND>
-static void pull_impl(const SlotArgs &a, int k, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+static void pull_impl(const SlotArgs &a, int k, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                      bool decide = true) {
   int grid;
   if (ev0) (void)hipEventRecord(ev0, st);
   if constexpr (S == 1) {
@@ -1109,7 +1110,7 @@ static void pull_impl(const SlotArgs &a, int k, hipStream_t st, hipEvent_t ev0 =
     hgrid = std::max(1, std::min((a.heavy.n_rows * S + BLOCK - 1) / BLOCK, 256));
     hipLaunchKernelGGL((k_heavy_epi<XT, S, KIND>), dim3(hgrid), dim3(BLOCK), 0, st, a, k, grid);
   }
-  decide_impl<S>(a, KIND, grid + hgrid, k & 1, st);
+  if (decide) decide_impl<S>(a, KIND, grid + hgrid, k & 1, st);
 }
 
 template <typename XT, int S>
@@ -1151,6 +1152,10 @@ void launch_finish(const SlotArgs &a, int S, bool fp64, hipStream_t st) {
 
 void launch_residual(const SlotArgs &a, int S, hipStream_t st) {
   RWR_DISPATCH_S(S, (pull_impl<double, SS, KIND_RESID>(a, 1, st)));
+}
+
+void launch_apply_p(const SlotArgs &a, int S, hipStream_t st) {
+  RWR_DISPATCH_S(S, (pull_impl<double, SS, KIND_RESID>(a, 1, st, nullptr, nullptr, false)));
 }
 
 template <typename XT, int S>

@@ -4,9 +4,10 @@
 // that replaces the offset seed, and the training target r_offset / ||q||.
 //
 // Node marks kept between updates (all zero when no update runs):
-//   hop1[v]  = hop distance + 1 of a region node (0 outside the region),
-//   loc1[v]  = local index + 1 of a region node,
-//   wmark[v] = 1 while v is in the list of nodes the residual touches.
+//   hop1[v] = hop distance + 1 of a region node (0 outside the region),
+//   loc1[v] = local index + 1 of a region node.
+// The dense FP64 vector w holds the prediction on the region rows during an
+// update and is zero otherwise.
 #include <hipcub/hipcub.hpp>
 
 #include "rwr_common.h"
@@ -184,20 +185,13 @@ __global__ void k_ws_features(const int32_t *__restrict__ R, int32_t nR, int S, 
 }
 
 // ------------------------------------------------------------ prediction and residual
-// xhat = ||q_j|| o (FP64), and the region's nodes enter the touched list
-__global__ void k_ws_predict(const int32_t *__restrict__ R, int32_t nR, int S, const float *__restrict__ o,
-                             const double *__restrict__ qn, double *__restrict__ xhat, int32_t *__restrict__ wmark,
-                             int32_t *__restrict__ wlist, int32_t *__restrict__ wcount) {
+// xhat = ||q_j|| o (FP64)
+__global__ void k_ws_predict(int32_t nR, int S, const float *__restrict__ o, const double *__restrict__ qn,
+                             double *__restrict__ xhat) {
   const int64_t rows = (int64_t)nR * S;
   for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < rows;
-       row += (int64_t)gridDim.x * blockDim.x) {
-    const int j = (int)(row % S);
-    xhat[row] = qn[j] * (double)o[row];
-    if (j == 0) {
-      const int v = R[row / S];
-      if (atomicExch(&wmark[v], 1) == 0) wlist[atomicAdd(wcount, 1)] = v;
-    }
-  }
+       row += (int64_t)gridDim.x * blockDim.x)
+    xhat[row] = qn[row % S] * (double)o[row];
 }
 
 // Mass of the prediction.  For any xhat, sum(rho) = sum(q) - f(xhat) with
@@ -256,54 +250,42 @@ __global__ void k_ws_beta(const double *__restrict__ part, int nb, int S, double
   beta[j] = fa > 0.0 ? (fx - qn[S + j]) / fa : 0.0;
 }
 
-__global__ void k_ws_adjust(int32_t nR, int S, const double *__restrict__ beta, double *__restrict__ xhat) {
+// xhat' = xhat - beta |xhat|, scattered into the dense vector w (rows R)
+__global__ void k_ws_adjust_scatter(const int32_t *__restrict__ R, int32_t nR, int S, const double *__restrict__ beta,
+                                    double *__restrict__ xhat, double *__restrict__ w) {
   const int64_t rows = (int64_t)nR * S;
   for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < rows;
        row += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(row % S);
     const double x = xhat[row];
-    xhat[row] = x - beta[row % S] * fabs(x);
+    const double y = x - beta[j] * fabs(x);
+    xhat[row] = y;
+    w[col_index(R[row / S], S, j)] = y;
   }
 }
 
-// P xhat pushed along out-edges into wbuf (FP64), one wavefront per region
-// node; every receiving node enters the touched list
-template <int S>
-__global__ void k_ws_push(const int32_t *__restrict__ R, int32_t nR, DevGraphView out, const double *__restrict__ xhat,
-                          double c1, double *__restrict__ wbuf, int32_t *__restrict__ wmark,
-                          int32_t *__restrict__ wlist, int32_t *__restrict__ wcount) {
-  const int lane = threadIdx.x % RWR_WAVE;
-  constexpr int PER = RWR_WAVE / S;  // edges per wavefront step
-  const int j = lane % S, p = lane / S;
-  for (int w = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; w < nR; w += gridDim.x * blockDim.x / RWR_WAVE) {
-    const int u = R[w];
-    const int o = out.off[u], d = out.len[u];
-    if (d == 0) continue;
-    const double val = c1 * xhat[(int64_t)w * S + j] / (double)d;
-    for (int e = p; e < d; e += PER) {
-      const int v = out.adj[o + e];
-      if (val != 0.0) atomic_add_f64(&wbuf[col_index(v, S, j)], val);
-      if (j == 0 && atomicExch(&wmark[v], 1) == 0) wlist[atomicAdd(wcount, 1)] = v;
-    }
-  }
+__global__ void k_ws_unscatter(const int32_t *__restrict__ R, int32_t nR, int S, double *__restrict__ w) {
+  const int64_t rows = (int64_t)nR * S;
+  for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < rows;
+       row += (int64_t)gridDim.x * blockDim.x)
+    w[col_index(R[row / S], S, (int)(row % S))] = 0.0;
 }
 
-// per-workgroup partials over the touched list of ||rho_j||_1 and of the
-// signed sum of xhat_j
-__global__ __launch_bounds__(WB) void k_ws_rho_norm(const int32_t *__restrict__ wlist, const int32_t *__restrict__ wcount,
-                                                    int S, const double *__restrict__ ybuf,
-                                                    const double *__restrict__ xhat, const int32_t *__restrict__ loc1,
-                                                    const double *__restrict__ wbuf, double *__restrict__ part) {
+// rho = q + g over every node, where g = (1-c) B~^T xhat - xhat (gbuf):
+// rho replaces g in gbuf; partials of ||rho_j||_1 (entries j) and of the
+// sum of xhat_j (entries S + j)
+__global__ __launch_bounds__(WB) void k_ws_rho(int32_t n, int S, const double *__restrict__ ybuf,
+                                               double *__restrict__ gbuf, const double *__restrict__ w,
+                                               double *__restrict__ part) {
   __shared__ double rn[WB], xs[WB];
-  const int cnt = *wcount;
   const int j = threadIdx.x % S, rl = threadIdx.x / S, RPB = WB / S;
   double a = 0.0, b = 0.0;
-  for (int i = blockIdx.x * RPB + rl; i < cnt; i += gridDim.x * RPB) {
-    const int v = wlist[i];
+  for (int v = blockIdx.x * RPB + rl; v < n; v += gridDim.x * RPB) {
     const int64_t kk = col_index(v, S, j);
-    const int li = loc1[v] - 1;
-    const double xh = li >= 0 ? xhat[(int64_t)li * S + j] : 0.0;
-    a += fabs(ybuf[kk] - xh + wbuf[kk]);
-    b += xh;
+    const double rho = ybuf[kk] + gbuf[kk];
+    gbuf[kk] = rho;
+    a += fabs(rho);
+    b += w[kk];
   }
   rn[threadIdx.x] = a;
   xs[threadIdx.x] = b;
@@ -317,31 +299,20 @@ __global__ __launch_bounds__(WB) void k_ws_rho_norm(const int32_t *__restrict__ 
 }
 
 // Accepted columns: the offset seed becomes rho and the scores take xhat;
-// every touched node is stamped so the first propagation slot reads it.
-// Clears wbuf and the marks.
-__global__ void k_ws_apply(const int32_t *__restrict__ wlist, const int32_t *__restrict__ wcount, int S,
-                           uint64_t accept, double *__restrict__ ybuf, double *__restrict__ r,
-                           const double *__restrict__ xhat, const int32_t *__restrict__ loc1,
-                           double *__restrict__ wbuf, int32_t *__restrict__ wmark, int32_t *__restrict__ stamp,
-                           const Ctl *__restrict__ ctl) {
-  const int cnt = *wcount;
+// nodes where an accepted rho is non-zero are stamped so that the first
+// propagation slot reads them (stamps are never removed here).
+__global__ void k_ws_apply(int32_t n, int S, uint64_t accept, double *__restrict__ ybuf,
+                           const double *__restrict__ gbuf, double *__restrict__ r, const double *__restrict__ w,
+                           int32_t *__restrict__ stamp, const Ctl *__restrict__ ctl) {
   const int32_t st = ctl->stamp;
-  const int64_t total = (int64_t)cnt * S;
+  const int64_t total = (int64_t)n * S;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e / S), j = (int)(e % S);
-    const int v = wlist[i];
-    const int64_t kk = col_index(v, S, j);
-    if ((accept >> j) & 1ull) {
-      const int li = loc1[v] - 1;
-      const double xh = li >= 0 ? xhat[(int64_t)li * S + j] : 0.0;
-      ybuf[kk] = ybuf[kk] - xh + wbuf[kk];
-      r[kk] += xh;
-    }
-    wbuf[kk] = 0.0;
-    if (j == 0) {
-      wmark[v] = 0;
-      stamp[v] = st;
-    }
+    const int j = (int)(e % S);
+    if (!((accept >> j) & 1ull)) continue;
+    const double rho = gbuf[e];
+    ybuf[e] = rho;
+    r[e] += w[e];
+    if (rho != 0.0) stamp[e / S] = st;  // every writer stores the same value
   }
 }
 
@@ -357,32 +328,57 @@ __global__ void k_ws_sigma(Ctl *ctl, int S, uint64_t accept, const double *__res
 //              = (-sign(rho(u, j)) + (1-c)/d_out(u) sum over u -> v of sign(rho(v, j))) / C.
 // For the exact offset result, ||rho||_1 is the L1 distance between xhat and
 // r_offset measured through I - (1-c) B~^T.  The mass correction is taken as
-// fixed (its derivative is not followed).  One wavefront per region node.
+// fixed (its derivative is not followed).  The sums over out-rows run over
+// items of GRAD_CHUNK edges (one wavefront each), added with float atomics.
+#define GRAD_CHUNK 1024
+
+__device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
+__global__ void k_ws_grad_items(const int32_t *__restrict__ R, int32_t nR, DevGraphView out,
+                                int32_t *__restrict__ items) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= nR; i += gridDim.x * blockDim.x)
+    items[i] = i < nR ? (out.len[R[i]] + GRAD_CHUNK - 1) / GRAD_CHUNK : 0;
+}
+
 template <int S>
-__global__ void k_ws_resid_grad(const int32_t *__restrict__ R, int32_t nR, DevGraphView out, double c1,
-                                const double *__restrict__ ybuf, const double *__restrict__ xhat,
-                                const int32_t *__restrict__ loc1, const double *__restrict__ wbuf,
-                                const int32_t *__restrict__ active, float inv_cols, float *__restrict__ dout) {
-  const int lane = threadIdx.x % RWR_WAVE;
+__global__ void k_ws_grad_sum(const int32_t *__restrict__ R, int32_t nR, DevGraphView out,
+                              const int32_t *__restrict__ item_off, const double *__restrict__ rho,
+                              float *__restrict__ gacc) {
   constexpr int PER = RWR_WAVE / S;
+  const int lane = threadIdx.x % RWR_WAVE;
   const int j = lane % S, p = lane / S;
-  auto rho = [&](int v) {
-    const int64_t kk = col_index(v, S, j);
-    const int li = loc1[v] - 1;
-    const double xh = li >= 0 ? xhat[(int64_t)li * S + j] : 0.0;
-    return ybuf[kk] - xh + wbuf[kk];
-  };
-  auto sgn = [](double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); };
-  for (int w = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; w < nR; w += gridDim.x * blockDim.x / RWR_WAVE) {
-    const int u = R[w];
-    const int o = out.off[u], d = out.len[u];
-    double t = 0.0;
-    for (int e = p; e < d; e += PER) t += sgn(rho(out.adj[o + e]));
-    for (int off = S; off < RWR_WAVE; off <<= 1) t += __shfl_xor(t, off, RWR_WAVE);
-    if (p == 0) {
-      const double g = -sgn(rho(u)) + (d ? c1 * t / (double)d : 0.0);
-      dout[(int64_t)w * S + j] = active[j] ? (float)g * inv_cols : 0.0f;
+  const int32_t total = item_off[nR];
+  for (int32_t it = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; it < total;
+       it += gridDim.x * blockDim.x / RWR_WAVE) {
+    int32_t lo = 0, hi = nR - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (item_off[mid] <= it) lo = mid;
+      else hi = mid - 1;
     }
+    const int32_t i = lo, k = it - item_off[i];
+    const int u = R[i];
+    const int o = out.off[u], d = out.len[u];
+    const int e1 = min(d, (k + 1) * GRAD_CHUNK);
+    double t = 0.0;
+    for (int e = k * GRAD_CHUNK + p; e < e1; e += PER) t += sgn(rho[col_index(out.adj[o + e], S, j)]);
+    for (int off = S; off < RWR_WAVE; off <<= 1) t += __shfl_xor(t, off, RWR_WAVE);
+    if (p == 0 && t != 0.0) atomicAdd(&gacc[(int64_t)i * S + j], (float)t);
+  }
+}
+
+__global__ void k_ws_grad_final(const int32_t *__restrict__ R, int32_t nR, int S, DevGraphView out, double c1,
+                                const double *__restrict__ rho, float *__restrict__ gacc,
+                                const int32_t *__restrict__ active, float inv_cols, float *__restrict__ dout) {
+  const int64_t rows = (int64_t)nR * S;
+  for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(row % S);
+    const int u = R[row / S];
+    const int d = out.len[u];
+    const double g = -sgn(rho[col_index(u, S, j)]) + (d ? c1 * (double)gacc[row] / (double)d : 0.0);
+    dout[row] = active[j] ? (float)g * inv_cols : 0.0f;
+    gacc[row] = 0.0f;
   }
 }
 
@@ -434,6 +430,17 @@ hipError_t ws_local_rows(const int32_t *R, int32_t nR, const DevGraphView &gv, c
   return hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, cnt, off, nR + 1, s);
 }
 
+__global__ void k_ws_chunks(const int32_t *__restrict__ cnt, int32_t nR, int32_t chunk, int32_t *__restrict__ items) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= nR; i += gridDim.x * blockDim.x)
+    items[i] = i < nR ? (cnt[i] + chunk - 1) / chunk : 0;
+}
+
+hipError_t ws_chunk_items(const int32_t *cnt, int32_t nR, int32_t chunk, int32_t *tmp, int32_t *items, void *temp,
+                          size_t temp_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_chunks, dim3(wgrid((int64_t)nR + 1)), dim3(WB), 0, s, cnt, nR, chunk, tmp);
+  return hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, tmp, items, nR + 1, s);
+}
+
 void ws_local_fill(const int32_t *R, int32_t nR, const DevGraphView &gv, const int32_t *loc1, const int32_t *off,
                    int32_t *adj, hipStream_t s) {
   hipLaunchKernelGGL(k_ws_fill_local, dim3(wgrid((int64_t)nR * RWR_WAVE)), dim3(WB), 0, s, R, nR, gv, loc1, off, adj);
@@ -461,60 +468,47 @@ void ws_features(const int32_t *R, int32_t nR, int S, const int32_t *hop1, const
                      ctl, seeds, qn, n_total, F);
 }
 
-void ws_predict_residual(const int32_t *R, int32_t nR, int S, const DevGraphView &out, const float *o,
-                         const double *qn, double c1, double *xhat, double *wbuf, int32_t *wmark, int32_t *wlist,
-                         int32_t *wcount, double *part, double *beta, hipStream_t s) {
-  hipLaunchKernelGGL(k_ws_predict, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, R, nR, S, o, qn, xhat, wmark, wlist,
-                     wcount);
+void ws_predict(const int32_t *R, int32_t nR, int S, const DevGraphView &out, const float *o, const double *qn,
+                double c1, double *xhat, double *w, double *part, double *beta, hipStream_t s) {
+  const int g = wgrid((int64_t)nR * S);
+  hipLaunchKernelGGL(k_ws_predict, dim3(g), dim3(WB), 0, s, nR, S, o, qn, xhat);
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)nR * S + WB - 1) / WB, 512));
   hipLaunchKernelGGL(k_ws_mass, dim3(nb), dim3(WB), 0, s, R, nR, S, out, xhat, part);
   hipLaunchKernelGGL(k_ws_beta, dim3(1), dim3(64), 0, s, part, nb, S, c1, qn, beta);
-  hipLaunchKernelGGL(k_ws_adjust, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, nR, S, beta, xhat);
-  const int g = wgrid((int64_t)nR * RWR_WAVE);
-  switch (S) {
-#define WS_PUSH(SS)                                                                                             \
-  case SS:                                                                                                      \
-    hipLaunchKernelGGL(k_ws_push<SS>, dim3(g), dim3(WB), 0, s, R, nR, out, xhat, c1, wbuf, wmark, wlist, wcount); \
-    break;
-    WS_PUSH(1)
-    WS_PUSH(2)
-    WS_PUSH(4)
-    WS_PUSH(8)
-    WS_PUSH(16)
-    WS_PUSH(32)
-    WS_PUSH(64)
-#undef WS_PUSH
-    default:
-      break;
-  }
+  hipLaunchKernelGGL(k_ws_adjust_scatter, dim3(g), dim3(WB), 0, s, R, nR, S, beta, xhat, w);
 }
 
-void ws_rho_norm(const int32_t *wlist, const int32_t *wcount, int32_t cnt_hint, int S, const double *ybuf,
-                 const double *xhat, const int32_t *loc1, const double *wbuf, double *part, double *sums,
-                 hipStream_t s) {
-  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)cnt_hint * S + WB - 1) / WB, 1024));
-  hipLaunchKernelGGL(k_ws_rho_norm, dim3(nb), dim3(WB), 0, s, wlist, wcount, S, ybuf, xhat, loc1, wbuf, part);
+void ws_unscatter(const int32_t *R, int32_t nR, int S, double *w, hipStream_t s) {
+  if (nR <= 0) return;
+  hipLaunchKernelGGL(k_ws_unscatter, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, R, nR, S, w);
+}
+
+void ws_rho(int32_t n, int S, const double *ybuf, double *gbuf, const double *w, double *part, double *sums,
+            hipStream_t s) {
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)n * S + WB - 1) / WB, 1024));
+  hipLaunchKernelGGL(k_ws_rho, dim3(nb), dim3(WB), 0, s, n, S, ybuf, gbuf, w, part);
   hipLaunchKernelGGL(k_ws_sum_parts, dim3(1), dim3(128), 0, s, part, nb, 2 * S, sums);
 }
 
-void ws_apply(const int32_t *wlist, const int32_t *wcount, int32_t cnt_hint, int S, uint64_t accept, double *ybuf,
-              double *r, const double *xhat, const int32_t *loc1, double *wbuf, int32_t *wmark, int32_t *stamp,
-              Ctl *ctl, const double *xsum, hipStream_t s) {
-  hipLaunchKernelGGL(k_ws_apply, dim3(wgrid((int64_t)cnt_hint * S)), dim3(WB), 0, s, wlist, wcount, S, accept, ybuf,
-                     r, xhat, loc1, wbuf, wmark, stamp, ctl);
-  hipLaunchKernelGGL(k_ws_sigma, dim3(1), dim3(64), 0, s, ctl, S, accept, xsum);
+void ws_apply(int32_t n, int S, uint64_t accept, double *ybuf, const double *gbuf, double *r, const double *w,
+              int32_t *stamp, Ctl *ctl, const double *xsum, hipStream_t s) {
+  if (accept) {
+    hipLaunchKernelGGL(k_ws_apply, dim3(wgrid((int64_t)n * S)), dim3(WB), 0, s, n, S, accept, ybuf, gbuf, r, w, stamp,
+                       ctl);
+    hipLaunchKernelGGL(k_ws_sigma, dim3(1), dim3(64), 0, s, ctl, S, accept, xsum);
+  }
 }
 
-void ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *ybuf,
-                   const double *xhat, const int32_t *loc1, const double *wbuf, const int32_t *active, int n_active,
-                   float *dout, hipStream_t s) {
-  const int g = wgrid((int64_t)nR * RWR_WAVE);
-  const float inv = 1.0f / (float)std::max(1, n_active);
+hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *rho,
+                         float *gacc, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
+                         const int32_t *active, int n_active, float *dout, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_grad_items, dim3(wgrid((int64_t)nR + 1)), dim3(WB), 0, s, R, nR, out, items);
+  hipError_t e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, items, item_off, nR + 1, s);
+  if (e != hipSuccess) return e;
   switch (S) {
-#define WS_GRAD(SS)                                                                                                 \
-  case SS:                                                                                                          \
-    hipLaunchKernelGGL(k_ws_resid_grad<SS>, dim3(g), dim3(WB), 0, s, R, nR, out, c1, ybuf, xhat, loc1, wbuf, active, \
-                       inv, dout);                                                                                  \
+#define WS_GRAD(SS)                                                                                              \
+  case SS:                                                                                                       \
+    hipLaunchKernelGGL(k_ws_grad_sum<SS>, dim3(1024), dim3(WB), 0, s, R, nR, out, item_off, rho, gacc);          \
     break;
     WS_GRAD(1)
     WS_GRAD(2)
@@ -527,4 +521,8 @@ void ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out,
     default:
       break;
   }
+  const float inv = 1.0f / (float)std::max(1, n_active);
+  hipLaunchKernelGGL(k_ws_grad_final, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, R, nR, S, out, c1, rho, gacc,
+                     active, inv, dout);
+  return hipSuccess;
 }

@@ -60,6 +60,7 @@ struct SlotArgs {
   int32_t grid_pull;  // workgroups of a dense sweep (each loops over items)
   int32_t light_lanes;  // lanes per row of the light push
   int32_t pull_lanes;   // lanes per in-row of the dense sweep for S >= 4 (16, 32 or 64)
+  int32_t zero_seed_rows;   // residual sweep: 1 zeroes the seed row of each column (the restart term)
   const int32_t *row_order;  // order of the in-rows in that sweep (a permutation of 0 .. n_cap-1)
   int32_t n_order;           // its length (n_cap)
   const int32_t *mp_rows;  // row partition of the single-column dense sweep
@@ -116,6 +117,9 @@ void launch_dense_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t s
                        hipEvent_t ev1 = nullptr);
 void launch_finish(const SlotArgs &a, int S, bool fp64, hipStream_t st);
 void launch_residual(const SlotArgs &a, int S, hipStream_t st);
+// g = (1-c) B~^T (r / d_out) - r over every node (the residual sweep on the
+// vector in a.r, written to a.gbuf), without the decision kernel
+void launch_apply_p(const SlotArgs &a, int S, hipStream_t st);
 void launch_refine_init(const SlotArgs &a, int S, bool fp64, hipStream_t st);
 void launch_scores(const double *r, const Ctl *ctl, const int32_t *perm, int S, int j, int32_t n, double *out,
                    hipStream_t st);

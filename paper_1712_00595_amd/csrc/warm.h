@@ -33,26 +33,31 @@ hipError_t ws_local_rows(const int32_t *R, int32_t nR, const DevGraphView &gv, c
                          int32_t *off, void *temp, size_t temp_bytes, hipStream_t s);
 void ws_local_fill(const int32_t *R, int32_t nR, const DevGraphView &gv, const int32_t *loc1, const int32_t *off,
                    int32_t *adj, hipStream_t s);
+// items = exclusive prefix of ceil(cnt[i] / chunk) (nR + 1 entries; tmp is
+// scratch of nR + 1 ints)
+hipError_t ws_chunk_items(const int32_t *cnt, int32_t nR, int32_t chunk, int32_t *tmp, int32_t *items, void *temp,
+                          size_t temp_bytes, hipStream_t s);
 void ws_clear(const int32_t *R, int32_t nR, int32_t *hop1, int32_t *loc1, hipStream_t s);
 void ws_features(const int32_t *R, int32_t nR, int S, const int32_t *hop1, const DevGraphView &in,
                  const DevGraphView &out, const double *ybuf, const double *r, const Ctl *ctl, const int32_t *seeds,
                  const double *qn, int32_t n_total, float *F, hipStream_t s);
 // qn[j] = ||q_j||_1 and qn[S + j] = sum of q_j over the offset support
 void ws_qnorm(const int32_t *R, int32_t n0, int S, const double *ybuf, double *part, double *qn, hipStream_t s);
-// xhat = ||q|| o, corrected so that the residual has a zero sum; P xhat
-// pushed into wbuf; region and receiving nodes listed in wlist.  part holds
-// at least 512 * 4 * S doubles, beta S doubles.
-void ws_predict_residual(const int32_t *R, int32_t nR, int S, const DevGraphView &out, const float *o,
-                         const double *qn, double c1, double *xhat, double *wbuf, int32_t *wmark, int32_t *wlist,
-                         int32_t *wcount, double *part, double *beta, hipStream_t s);
-// sums[j] = ||rho_j||_1, sums[S + j] = sum of xhat_j
-void ws_rho_norm(const int32_t *wlist, const int32_t *wcount, int32_t cnt_hint, int S, const double *ybuf,
-                 const double *xhat, const int32_t *loc1, const double *wbuf, double *part, double *sums,
-                 hipStream_t s);
-void ws_apply(const int32_t *wlist, const int32_t *wcount, int32_t cnt_hint, int S, uint64_t accept, double *ybuf,
-              double *r, const double *xhat, const int32_t *loc1, double *wbuf, int32_t *wmark, int32_t *stamp,
-              Ctl *ctl, const double *xsum, hipStream_t s);
-// dL/do of the residual loss (see k_ws_resid_grad) into dout (rows nR * S)
-void ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *ybuf,
-                   const double *xhat, const int32_t *loc1, const double *wbuf, const int32_t *active, int n_active,
-                   float *dout, hipStream_t s);
+// xhat = ||q|| o, corrected so that the residual has a zero sum, and
+// scattered into the dense FP64 vector w (zero outside the region).  part
+// holds at least 512 * 4 * S doubles, beta S doubles.
+void ws_predict(const int32_t *R, int32_t nR, int S, const DevGraphView &out, const float *o, const double *qn,
+                double c1, double *xhat, double *w, double *part, double *beta, hipStream_t s);
+void ws_unscatter(const int32_t *R, int32_t nR, int S, double *w, hipStream_t s);
+// gbuf holds g = (1-c) B~^T xhat - xhat on every node; rho = q + g replaces
+// it; sums[j] = ||rho_j||_1, sums[S + j] = sum of xhat_j
+void ws_rho(int32_t n, int S, const double *ybuf, double *gbuf, const double *w, double *part, double *sums,
+            hipStream_t s);
+// accepted columns: ybuf = rho, r += xhat, sigma += sum xhat, stamps
+void ws_apply(int32_t n, int S, uint64_t accept, double *ybuf, const double *gbuf, double *r, const double *w,
+              int32_t *stamp, Ctl *ctl, const double *xsum, hipStream_t s);
+// dL/do of the residual loss (see k_ws_grad_final) into dout (rows nR * S);
+// gacc (nR * S floats) must be zero and is left zero
+hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *rho,
+                         float *gacc, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
+                         const int32_t *active, int n_active, float *dout, hipStream_t s);
