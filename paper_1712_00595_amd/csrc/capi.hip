@@ -331,8 +331,8 @@ static void tune_defaults(rwr_ctx *c) {
   c->grid_light = 4 * c->n_cu;
   c->grid_sparse = 4 * c->n_cu;
   // dense sweeps: the workgroups that fit on the chip at once (registers:
-  // six per CU for the single-column sweep, five for the vector sweep)
-  c->grid_pull = (S == 1 ? 6 : S == 2 ? 8 : 5) * c->n_cu;
+  // and LDS: five per CU for both the single-column and the vector sweep)
+  c->grid_pull = (S == 1 ? 5 : S == 2 ? 8 : 5) * c->n_cu;
   if (const char *e = getenv("RWR_GRID_LIGHT")) c->grid_light = atoi(e);
   if (const char *e = getenv("RWR_GRID_SPARSE")) c->grid_sparse = atoi(e);
   if (const char *e = getenv("RWR_GRID_PULL")) c->grid_pull = atoi(e);

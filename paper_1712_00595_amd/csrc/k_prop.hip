@@ -379,7 +379,7 @@ __device__ __forceinline__ void pull_epilogue(const SlotArgs &a, XT *__restrict_
 // independent gathers in flight.
 template <typename XT, int S, int KIND>
 __device__ __forceinline__ void heavy_item(const SlotArgs &a, int item, const XT *__restrict__ xcur,
-                                           double (*hred)[RWR_MAX_COLS]) {
+                                           double (*hred)[RWR_MAX_COLS], const XT *xc = nullptr, int ncache = 0) {
   constexpr int PP = RWR_WAVE / S;
   constexpr int STRIDE = NWAVES * PP;
   const int lane = threadIdx.x % RWR_WAVE, w = threadIdx.x / RWR_WAVE;
@@ -393,15 +393,19 @@ __device__ __forceinline__ void heavy_item(const SlotArgs &a, int item, const XT
   const int32_t *__restrict__ adj = a.in.adj + o;
   double acc = 0.0;
   int e = e0 + w * PP + pp;
+  auto get = [&](int u) -> double {
+    if (S == 1 && u < ncache) return (double)xc[u];
+    return Gather<XT, S, KIND>::get(a, xcur, u, jj);
+  };
   for (; e + 3 * STRIDE < e1; e += 4 * STRIDE) {
     const int u0 = adj[e], u1 = adj[e + STRIDE], u2 = adj[e + 2 * STRIDE], u3 = adj[e + 3 * STRIDE];
-    const double g0 = Gather<XT, S, KIND>::get(a, xcur, u0, jj);
-    const double g1 = Gather<XT, S, KIND>::get(a, xcur, u1, jj);
-    const double g2 = Gather<XT, S, KIND>::get(a, xcur, u2, jj);
-    const double g3 = Gather<XT, S, KIND>::get(a, xcur, u3, jj);
+    const double g0 = get(u0);
+    const double g1 = get(u1);
+    const double g2 = get(u2);
+    const double g3 = get(u3);
     acc += (g0 + g1) + (g2 + g3);
   }
-  for (; e < e1; e += STRIDE) acc += Gather<XT, S, KIND>::get(a, xcur, adj[e], jj);
+  for (; e < e1; e += STRIDE) acc += get(adj[e]);
   acc = wave_xor_sum(acc, S, RWR_WAVE);
   if (lane < S) hred[w][lane] = acc;
   __syncthreads();
@@ -719,6 +723,7 @@ __global__ __launch_bounds__(BLOCK) void k_pull_v(SlotArgs a, int k) {
 #define MP_PER_THREAD 8
 #define MP_ROUND (MP_PER_THREAD * BLOCK)
 #define MP_SHORT 32  // rows with at most this many in-edges are summed by their owner thread
+#define MP_CACHE 4096  // leading entries of the FP32 vector kept in LDS by the single-column sweep
 
 // Dense sweep for one seed column, merge-path style.  Work item b owns the
 // rows mp_rows[b] .. mp_rows[b+1] (at most MP_ROWS rows and about MP_EDGES
@@ -728,8 +733,15 @@ __global__ __launch_bounds__(BLOCK) void k_pull_v(SlotArgs a, int k) {
 // loads and gathers) into LDS.  Then each short row's owner thread adds its segment, and each
 // long row is added by a whole wave (strided lanes, shuffle tree).  Row sums
 // accumulate round by round in LDS; every order is fixed (deterministic).
+// Nodes are numbered by descending out-degree, so the leading entries of the
+// vector are the most gathered ones: in the FP32 propagation sweep each
+// workgroup copies the first MP_CACHE entries into LDS once and reads them
+// there (a third of the gathers at R-MAT scale 20).
 template <typename XT, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_pull_mp(SlotArgs a, int k) {
+  constexpr bool FP32_PROP = KIND == KIND_DENSE && sizeof(XT) == 4;
+  constexpr int CACHE = FP32_PROP ? MP_CACHE : 0;
+  using PT = typename std::conditional<FP32_PROP, float, double>::type;  // staged gathers
   struct MpShared {
     int32_t pref[MP_ROWS + 1];
     int32_t off[MP_ROWS];
@@ -737,16 +749,22 @@ __global__ __launch_bounds__(BLOCK) void k_pull_mp(SlotArgs a, int k) {
     int32_t wsum[NWAVES];
     int32_t wlong[NWAVES];
     double rowacc[MP_ROWS];
-    double prod[MP_ROUND];
+    PT prod[MP_ROUND];
   };
   __shared__ union {
     BlockRed red;
     MpShared mp;
   } U;
   __shared__ double hred[NWAVES][RWR_MAX_COLS];
+  __shared__ XT xc[CACHE > 0 ? CACHE : 1];
   Ctl *ctl = a.ctl;
   if (KIND == KIND_DENSE && ctl->mode != MODE_DENSE) return;
   const XT *__restrict__ xcur = (const XT *)a.x[(k - 1) & 1];
+  const int ncache = CACHE > 0 ? min(CACHE, a.n) : 0;
+  if constexpr (CACHE > 0) {
+    for (int i = threadIdx.x; i < ncache; i += BLOCK) xc[i] = xcur[i];
+    __syncthreads();
+  }
   XT *__restrict__ xnext = (XT *)a.x[k & 1];
   const double c1 = 1.0 - a.c;
   const bool act = ctl->active[0] != 0;
@@ -754,7 +772,7 @@ __global__ __launch_bounds__(BLOCK) void k_pull_mp(SlotArgs a, int k) {
   const int total_items = a.heavy.n_items + a.n_mp;
   for (int item = blockIdx.x; item < total_items; item += gridDim.x) {
     if (item < a.heavy.n_items) {
-      heavy_item<XT, 1, KIND>(a, item, xcur, hred);
+      heavy_item<XT, 1, KIND>(a, item, xcur, hred, xc, ncache);
       continue;
     }
     MpShared &M = U.mp;
@@ -826,9 +844,16 @@ __global__ __launch_bounds__(BLOCK) void k_pull_mp(SlotArgs a, int k) {
           uq[q] = a.in.adj[M.off[row] + (i - M.pref[row])];
         }
       }
-      double gq[MP_PER_THREAD];
+      PT gq[MP_PER_THREAD];
 #pragma unroll
-      for (int q = 0; q < MP_PER_THREAD; ++q) gq[q] = uq[q] >= 0 ? Gather<XT, 1, KIND>::get(a, xcur, uq[q], 0) : 0.0;
+      for (int q = 0; q < MP_PER_THREAD; ++q) {
+        if (uq[q] < 0)
+          gq[q] = (PT)0;
+        else if (uq[q] < ncache)
+          gq[q] = (PT)xc[uq[q]];
+        else
+          gq[q] = (PT)Gather<XT, 1, KIND>::get(a, xcur, uq[q], 0);
+      }
 #pragma unroll
       for (int q = 0; q < MP_PER_THREAD; ++q) M.prod[MP_PER_THREAD * t + q] = gq[q];
       __syncthreads();
@@ -837,7 +862,7 @@ __global__ __launch_bounds__(BLOCK) void k_pull_mp(SlotArgs a, int k) {
         const int hi = min(M.pref[t + 1], base + MP_ROUND) - base;
         if (hi > lo) {
           double s = 0.0;
-          for (int kk = lo; kk < hi; ++kk) s += M.prod[kk];
+          for (int kk = lo; kk < hi; ++kk) s += (double)M.prod[kk];
           M.rowacc[t] += s;
         }
       }
@@ -847,7 +872,7 @@ __global__ __launch_bounds__(BLOCK) void k_pull_mp(SlotArgs a, int k) {
         const int hi = min(M.pref[rr + 1], base + MP_ROUND) - base;
         if (hi <= lo) continue;  // uniform in the wave
         double s = 0.0;
-        for (int kk = lo + lane; kk < hi; kk += RWR_WAVE) s += M.prod[kk];
+        for (int kk = lo + lane; kk < hi; kk += RWR_WAVE) s += (double)M.prod[kk];
         s = wave_xor_sum(s, 1, RWR_WAVE);
         if (lane == 0) M.rowacc[rr] += s;
       }
