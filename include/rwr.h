@@ -66,7 +66,9 @@ typedef struct rwr_config {
                         out-edges exceed m/pull_ratio; <= 0 selects the tuned default   */
   int32_t reorder;   /* 1: number nodes internally by descending out-degree (ids at
                         this interface are unchanged); 0: keep the caller's order      */
-  int32_t reserved;  /* must be 0                                                       */
+  int32_t autotune;  /* 1: the build's static solve times candidate shapes of the dense
+                        sweep (lanes per row, workgroups) on its first sweeps and keeps
+                        the fastest; 0: the fixed defaults                               */
   void *stream;      /* hipStream_t to run on; NULL: the library creates its own        */
 } rwr_config;
 
@@ -114,7 +116,7 @@ typedef struct rwr_stats {
 } rwr_stats;
 
 /* Fill *cfg with defaults: c = 0.15, eps = 1e-9, FP32 propagation, directed,
- * internal degree ordering on. */
+ * internal degree ordering on, sweep-shape tuning on. */
 rwr_status rwr_config_default(rwr_config *cfg);
 
 /* Build a context: copy the graph (n nodes, m edges (src[e], dst[e]); in
@@ -158,6 +160,11 @@ rwr_status rwr_graph_size(const rwr_ctx *ctx, int32_t *n, int64_t *m);
  * deg_out when not NULL.  For checking and checkpointing; not a hot path. */
 rwr_status rwr_graph_export(rwr_ctx *ctx, int32_t *src, int32_t *dst, int64_t cap, int64_t *m_out,
                             int32_t *deg_out);
+
+/* Shape of the dense sweep in use: lanes per in-row (multi-column sweep)
+ * and workgroups, and the median time of one sweep at that shape measured
+ * while tuning (0 when the shape was not tuned).  Any pointer may be NULL. */
+rwr_status rwr_sweep_shape(const rwr_ctx *ctx, int32_t *lanes_per_row, int32_t *workgroups, double *tuned_ms);
 
 /* Per-iteration ||x^(i)||_1 of seed column j during the last update (i = 0 is
  * ||q_offset||_1): copies min(cap, iters+1) values to out, count to *len. */

@@ -117,6 +117,18 @@ struct rwr_ctx {
   int prof_used = 0;
   double prof_dense_ms = 0.0;
   int64_t prof_dense_sweeps = 0, prof_idle = 0;
+  // sweep-shape tuning: the first dense sweeps of the build's static solve
+  // rotate through candidate (lanes per row, workgroups) pairs, each timed
+  // with events; the fastest by median is kept
+  struct Tune {
+    bool on = false;
+    std::vector<std::pair<int32_t, int32_t>> cand;
+    std::vector<std::vector<float>> ms;
+    int reps = 3, launched = 0, limit = 0;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> pending;  // candidate of each launch of the current chunk
+    double best_ms = 0.0;
+  } tune;
   // learned warm start (rwr_warm_start)
   struct Warm {
     int32_t mode = 0, hops = 3;
@@ -596,6 +608,49 @@ static rwr_status build_orient(rwr_ctx *c, int o, const int32_t *rows, const int
   return RWR_OK;
 }
 
+static void tune_begin(rwr_ctx *c) {
+  rwr_ctx::Tune &t = c->tune;
+  t.cand.clear();
+  const int cu = c->n_cu;
+  if (c->S == 1) {
+    for (int g : {3, 4, 5}) t.cand.push_back({c->pull_lanes, g * cu});
+  } else if (c->S == 2) {
+    for (int g : {4, 6, 8}) t.cand.push_back({c->pull_lanes, g * cu});
+  } else {
+    for (int l : {16, 32, 64})
+      for (int g : {4, 5}) t.cand.push_back({l, g * cu});
+  }
+  t.ms.assign(t.cand.size(), {});
+  t.launched = 0;
+  t.limit = 4 * t.reps * (int)t.cand.size();
+  t.on = true;
+}
+
+static bool tune_done(const rwr_ctx::Tune &t) {
+  for (const auto &v : t.ms)
+    if ((int)v.size() < t.reps) return false;
+  return true;
+}
+
+static void tune_finish(rwr_ctx *c) {
+  rwr_ctx::Tune &t = c->tune;
+  t.on = false;
+  int best = -1;
+  float bms = 0.0f;
+  for (size_t i = 0; i < t.cand.size(); ++i) {
+    std::vector<float> v = t.ms[i];
+    if (v.empty()) continue;
+    std::sort(v.begin(), v.end());
+    const float med = v[v.size() / 2];
+    if (best < 0 || med < bms) best = (int)i, bms = med;
+  }
+  if (best >= 0) {
+    c->pull_lanes = t.cand[best].first;
+    c->grid_pull = t.cand[best].second;
+    t.best_ms = bms;
+  }
+}
+
 // Enqueue iteration slots until the device reports MODE_DONE.  The slot that
 // computes x^(0) must already be enqueued; `mode` is the phase it leaves
 // (sparse after an offset seed or a seed vector, dense after a residual).
@@ -613,7 +668,10 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
   double prev = -1.0;
   int prev_iter = 0;
   int dense_launched = 0, dense_base = c->prof_used;
+  rwr_ctx::Tune &tn = c->tune;
   while (true) {
+    const int dense_before = c->ctl_h->dense_iters;
+    tn.pending.clear();
     if (k > c->max_iters + 1) {
       c->err = "iteration slots exhausted without completion";
       return RWR_EHIP;
@@ -622,15 +680,42 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
     for (; k < kend; ++k) {
       if (mode == MODE_DENSE) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (c->prof_on) RWR_TRY(prof_pair(c, &e0, &e1));
-        launch_dense_slot(a, c->S, c->fp64, k, c->stream, e0, e1);
-        ++dense_launched;
+        if (tn.on && tn.launched < tn.limit) {
+          // a tuning launch: the next candidate shape, timed
+          const int ci = tn.launched++ % (int)tn.cand.size();
+          const size_t q = 2 * tn.pending.size();
+          while (tn.ev.size() < q + 2) {
+            hipEvent_t e;
+            HIP_TRY(c, hipEventCreate(&e));
+            tn.ev.push_back(e);
+          }
+          tn.pending.push_back(ci);
+          SlotArgs at = a;
+          at.pull_lanes = tn.cand[ci].first;
+          at.grid_pull = tn.cand[ci].second;
+          launch_dense_slot(at, c->S, c->fp64, k, c->stream, tn.ev[q], tn.ev[q + 1]);
+        } else {
+          if (c->prof_on) RWR_TRY(prof_pair(c, &e0, &e1));
+          launch_dense_slot(a, c->S, c->fp64, k, c->stream, e0, e1);
+          ++dense_launched;
+        }
       } else {
         launch_sparse_slot(a, c->S, c->fp64, k, c->stream);
       }
     }
     RWR_TRY(read_ctl(c));
     const Ctl &h = *c->ctl_h;
+    if (!tn.pending.empty()) {
+      // the first `real` tuning launches of the chunk swept; the rest were idle
+      const int real = std::max(0, h.dense_iters - dense_before);
+      for (int i = 0; i < (int)tn.pending.size() && i < real; ++i) {
+        float ms = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, tn.ev[2 * i], tn.ev[2 * i + 1]));
+        tn.ms[tn.pending[i]].push_back(ms);
+      }
+      tn.pending.clear();
+      if (tune_done(tn) || tn.launched >= tn.limit) tune_finish(c);
+    }
     if (h.mode == MODE_DONE) break;
     mode = h.mode;
     k = h.iter;
@@ -999,7 +1084,7 @@ rwr_status rwr_config_default(rwr_config *cfg) {
   cfg->max_iters = 10000;
   cfg->pull_ratio = 0;
   cfg->reorder = 1;
-  cfg->reserved = 0;
+  cfg->autotune = 1;
   cfg->stream = nullptr;
   return RWR_OK;
 }
@@ -1146,7 +1231,18 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   RWR_TRY(plan_heavy(c, true));
   RWR_TRY(ensure_partials(c));
 
-  // static scores: CPI from c*e_s (Section 2.2), then residual refinement
+  // static scores: CPI from c*e_s (Section 2.2), then residual refinement.
+  // Its first dense sweeps also choose the sweep shape (unless fixed by the
+  // caller's configuration or the environment).
+  if (c->cfg.autotune && !getenv("RWR_PULL_LANES") && !getenv("RWR_GRID_PULL")) {
+    tune_begin(c);
+    int32_t gmax = 0;
+    for (const auto &cd : c->tune.cand) gmax = std::max(gmax, cd.second);
+    const int32_t keep = c->grid_pull;
+    c->grid_pull = std::max(c->grid_pull, gmax);
+    RWR_TRY(ensure_partials(c));
+    c->grid_pull = keep;
+  }
   const double build_tol = c->cfg.build_tol > 0 ? c->cfg.build_tol : 0.25 * c->budget;
   const double cc = c->cfg.c;
   const double eps0 = std::min(c->cfg.eps, build_tol * cc / (4.0 * (1.0 - cc)));
@@ -1171,6 +1267,7 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
     if (!st.refined) break;
   }
   c->budget = saved;
+  if (c->tune.on) tune_finish(c);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return RWR_OK;
 }
@@ -1582,6 +1679,7 @@ void rwr_destroy(rwr_ctx *c) {
   if (c->b_host) (void)hipHostFree(c->b_host);
   if (c->ctl_h) (void)hipHostFree(c->ctl_h);
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->tune.ev) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1607,6 +1705,14 @@ rwr_status rwr_profile_read(rwr_ctx *c, double *dense_ms, int64_t *dense_sweeps,
 }
 
 const char *rwr_last_error(const rwr_ctx *c) { return c ? c->err.c_str() : g_build_error.c_str(); }
+
+rwr_status rwr_sweep_shape(const rwr_ctx *c, int32_t *lanes_per_row, int32_t *workgroups, double *tuned_ms) {
+  if (!c) return RWR_EINVAL;
+  if (lanes_per_row) *lanes_per_row = c->pull_lanes;
+  if (workgroups) *workgroups = c->grid_pull;
+  if (tuned_ms) *tuned_ms = c->tune.best_ms;
+  return RWR_OK;
+}
 
 int64_t rwr_gnn_num_params(void) { return gnn::LAYOUT.total; }
 

@@ -39,6 +39,7 @@ EXPORTED = [
     "rwr_graph_size",
     "rwr_graph_export",
     "rwr_last_norms",
+    "rwr_sweep_shape",
     "rwr_profile",
     "rwr_profile_read",
     "rwr_destroy",
@@ -69,7 +70,7 @@ class Config(ctypes.Structure):
         ("max_iters", ctypes.c_int32),
         ("pull_ratio", ctypes.c_int32),
         ("reorder", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("autotune", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -133,6 +134,7 @@ def load_library(path: str = LIB_PATH):
     L.rwr_graph_size.argtypes = [p, ctypes.POINTER(i32), ctypes.POINTER(i64)]
     L.rwr_graph_export.argtypes = [p, p, p, i64, ctypes.POINTER(i64), p]
     L.rwr_last_norms.argtypes = [p, i32, p, i32, ctypes.POINTER(i32)]
+    L.rwr_sweep_shape.argtypes = [p, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     L.rwr_profile.argtypes = [p, i32]
     L.rwr_profile_read.argtypes = [p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), ctypes.POINTER(i64), i32]
     L.rwr_destroy.argtypes = [p]
@@ -214,6 +216,7 @@ class Context:
         max_iters: int = 10000,
         pull_ratio: int = 0,
         reorder: bool = True,
+        autotune: bool = True,
         stream: Optional[int] = None,
     ):
         self._lib = load_library()
@@ -229,6 +232,7 @@ class Context:
         cfg.max_iters = max_iters
         cfg.pull_ratio = pull_ratio
         cfg.reorder = 1 if reorder else 0
+        cfg.autotune = 1 if autotune else 0
         cfg.stream = stream
         on_dev = _is_torch(src)
         s = _Arr(src, on_dev)
@@ -328,6 +332,14 @@ class Context:
         m = ctypes.c_int64(0)
         _check(self._lib, self._ctx, self._lib.rwr_graph_size(self._ctx, ctypes.byref(n), ctypes.byref(m)))
         return m.value
+
+    def sweep_shape(self) -> dict:
+        lanes = ctypes.c_int32(0)
+        groups = ctypes.c_int32(0)
+        ms = ctypes.c_double(0.0)
+        _check(self._lib, self._ctx, self._lib.rwr_sweep_shape(self._ctx, ctypes.byref(lanes), ctypes.byref(groups),
+                                                                ctypes.byref(ms)))
+        return {"lanes_per_row": lanes.value, "workgroups": groups.value, "tuned_ms": ms.value}
 
     def scores(self, j: int = 0) -> np.ndarray:
         out = np.zeros(self.n, dtype=np.float64)

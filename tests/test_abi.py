@@ -42,7 +42,7 @@ def test_config_default_and_host_side_rejection():
     cfg = rwr.Config()
     assert L.rwr_config_default(ctypes.byref(cfg)) == 0
     assert cfg.c == 0.15 and cfg.eps == 1e-9 and cfg.precision == 0 and cfg.max_iters == 10000
-    assert cfg.reorder == 1
+    assert cfg.reorder == 1 and cfg.autotune == 1
     out = ctypes.c_void_p(None)
     # invalid arguments are rejected before any device call
     seeds = (ctypes.c_int32 * 1)(0)

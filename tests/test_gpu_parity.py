@@ -400,3 +400,25 @@ def test_multi_column_heavy_chunks(monkeypatch, n_seeds, prec):
         for j, s in enumerate(seeds):
             ref = oracle.rwr_static(n2, s2, d2, int(s), 0.15)
             assert _l1(ctx.scores(j), ref) <= gate, j
+
+
+@pytest.mark.parametrize("n_seeds", [1, 16])
+def test_sweep_shape_tuning(monkeypatch, n_seeds):
+    # the build's static solve times candidate shapes and keeps one; the
+    # scores do not depend on the shape
+    print(f"[tuning] seeds={n_seeds}", flush=True)
+    monkeypatch.delenv("RWR_PULL_LANES", raising=False)
+    monkeypatch.delenv("RWR_GRID_PULL", raising=False)
+    from synth.rmat import sample_seeds
+
+    g = rmat_graph(13, 120000, dead_end_self_loops=True)
+    seeds = sample_seeds(g, n_seeds, seed=3)
+    kw = dict(eps=1e-12, precision="fp64", build_tol=1e-11)
+    with _ctx(g, seeds, autotune=True, **kw) as tuned, _ctx(g, seeds, autotune=False, **kw) as fixed:
+        sh = tuned.sweep_shape()
+        assert sh["tuned_ms"] > 0.0 and sh["workgroups"] > 0
+        assert fixed.sweep_shape()["tuned_ms"] == 0.0
+        for j in (0, n_seeds - 1):
+            ref = oracle.rwr_static(g.n, g.src, g.dst, int(seeds[j]), 0.15)
+            assert _l1(tuned.scores(j), ref) < 1e-11
+            assert _l1(fixed.scores(j), ref) < 1e-11
