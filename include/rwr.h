@@ -143,8 +143,10 @@ rwr_status rwr_build(const rwr_config *cfg, int32_t n, int64_t m, const int32_t 
  * is marked stale (rwr_refine() clears it).  stats may be NULL. */
 rwr_status rwr_update(rwr_ctx *ctx, const rwr_batch *batch, rwr_stats *stats);
 
-/* Evaluate the FP64 residual of the current scores and propagate it until
- * the certified error is below the budget (clears a stale context). */
+/* Evaluate the FP64 residual of the current scores and, in the columns whose
+ * certified error exceeds an eighth of the budget, propagate it until the
+ * certified error is below an eighth of the budget (clears a stale
+ * context). */
 rwr_status rwr_refine(rwr_ctx *ctx, rwr_stats *stats);
 
 /* Copy the normalised scores of seed column j (n doubles) to out (capacity

@@ -106,6 +106,7 @@ struct rwr_ctx {
   // error budget per seed column (normalised L1)
   double err_bound[RWR_MAX_COLS] = {};
   double budget = 0.0;
+  double refine_target = 0.9;  // refinements aim at this fraction of the budget
   bool stale = false;
   std::string err;
   std::vector<double> last_hist;
@@ -338,6 +339,10 @@ static void tune_defaults(rwr_ctx *c) {
   if (const char *e = getenv("RWR_HEAVY_LIMIT")) c->heavy_limit = atoi(e);
   if (const char *e = getenv("RWR_HEAVY_CHUNK")) c->heavy_chunk = atoi(e);
   if (const char *e = getenv("RWR_PULL_RATIO")) c->pull_ratio = atoi(e);
+  if (const char *e = getenv("RWR_REFINE_TARGET")) {
+    const double t = atof(e);
+    if (t > 0.0 && t < 1.0) c->refine_target = t;
+  }
   if (c->cfg.pull_ratio > 0) c->pull_ratio = c->cfg.pull_ratio;
   // grids sized to the resident capacity: workgroups loop over their work
   c->grid_light = 4 * c->n_cu;
@@ -782,10 +787,13 @@ static void account_run(rwr_ctx *c, bool reset) {
 // it exceeds the budget, the FP64 residual g = P r - r (seed entries zeroed)
 // is evaluated: it certifies ||r/sigma - r*/sigma*||_1 <= 2 ||g||_1 / (c sigma).
 // Columns whose certified error is still above the budget are refined: g is
-// propagated (r += sum_i P^i g) down to an eighth of the budget.  `force`
+// propagated (r += sum_i P^i g) down to a fraction of the budget (0.9 in
+// updates: the next check comes sooner, but each refinement is short, which
+// costs fewer sweeps per update overall).  `force`
 // evaluates the residual regardless of the running bound, and refines above
 // `refine_at` (a fraction of the budget).
-static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double refine_at = 1.0) {
+static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double refine_at = 1.0,
+                                   double target = -1.0) {
   double worst = 0.0;
   for (int j = 0; j < c->n_seeds; ++j) worst = std::max(worst, c->err_bound[j]);
   if (!force && worst <= c->budget) return RWR_OK;
@@ -810,8 +818,9 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
   if (mask == 0) return RWR_OK;
   double min_sig = 1e300;
   for (int j = 0; j < c->n_seeds; ++j) min_sig = std::min(min_sig, std::fabs(c->ctl_h->sigma[j]));
-  // truncation bound of the refinement: 2 (1-c)/c * eps_ref / sigma = budget/8
-  const double eps_ref = c->budget * cc * min_sig / (16.0 * (1.0 - cc));
+  // truncation bound of the refinement: 2 (1-c)/c * eps_ref / sigma = target * budget
+  const double tgt = target > 0.0 ? target : c->refine_target;
+  const double eps_ref = tgt * c->budget * cc * min_sig / (2.0 * (1.0 - cc));
   launch_reset_run(c->ctl, c->S, mask, eps_ref, c->max_iters, dense_thresh(c), c->n / 16 + 1, c->stream);
   launch_refine_init(a, c->S, c->fp64, c->stream);
   RWR_TRY(run_slots(c, MODE_DENSE, resid * (1.0 - cc), eps_ref));
@@ -1552,7 +1561,7 @@ rwr_status rwr_refine(rwr_ctx *c, rwr_stats *st) {
   if (st) std::memset(st, 0, sizeof(*st));
   const double t0 = now_ms();
   c->stale = false;
-  rwr_status s = check_and_refine(c, true, st, 0.125);
+  rwr_status s = check_and_refine(c, true, st, 0.125, 0.125);
   if (s != RWR_OK) return s;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (st) {
