@@ -223,6 +223,86 @@ def run_learned(n_train: int, n_eval: int) -> dict:
     return res
 
 
+def run_churn(n_batches: int, check: bool) -> dict:
+    """Symmetrised R-MAT scale 23 (134,217,728 pairs stored in both
+    directions), c = 0.05, 16 uniform seeds, eps = 1e-9; each batch deletes
+    1% of the pairs, inserts as many uniform absent pairs and adds 1000 nodes
+    with 1-8 edges.  Batches are generated before the clock starts."""
+    import torch
+
+    from paper_1712_00595_amd import rwr
+    from synth.churn import PairPool, churn_stream
+    from synth.configs import RMAT23_UNDIRECTED
+
+    w = RMAT23_UNDIRECTED
+    t = time.time()
+    g = w.graph()
+    seeds = w.seeds(g)
+    pool = PairPool(g.n, g.pair_u, g.pair_v)
+    stream = list(churn_stream(pool, n_batches, 0.01, 1000, seed=4))
+    log(f"[{w.name}] graph n={g.n} pairs={g.pair_u.shape[0]}, {len(stream)} batches ({time.time() - t:.1f}s)")
+    eps = w.eps[0]
+    t = time.time()
+    ctx = rwr.Context(g.n, g.pair_u, g.pair_v, seeds, c=w.c, eps=eps, precision="fp32", undirected=True)
+    torch.cuda.synchronize()
+    build_s = time.time() - t
+    log(f"[{w.name}] context built in {build_s:.1f}s")
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    mods = sum(b.size for b in stream)
+    t0 = time.perf_counter()
+    stats = [ctx.update_batch(b) for b in stream]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    P = ctx.profile_read(reset=True)
+    res = {
+        "batches": len(stream),
+        "batches_configured": 100,
+        "edge_and_node_modifications": mods,
+        "modifications_per_s": mods / el,
+        "batches_per_s": len(stream) / el,
+        "build_s": build_s,
+        "mean_iters": float(np.mean([s["iters"] for s in stats])),
+        "mean_dense_sweeps": float(np.mean([s["dense_iters"] for s in stats])),
+        "refinements": int(sum(s["refined"] for s in stats)),
+        "max_err_bound": float(max(s["err_bound"] for s in stats)),
+        "gate": 2 * eps / w.c,
+    }
+    launches = P["dense_sweeps"] + P["idle_launches"]
+    if P["dense_sweeps"]:
+        sweep_bytes = dense_sweep_bytes(ctx.n, ctx.m, 16)
+        res["roofline"] = {
+            "bound": "hbm",
+            "kernel": "k_pull_v<float, 16, *, KIND_DENSE> (dense sweep, 16 columns)",
+            "achieved": sweep_bytes * P["dense_sweeps"] / (P["dense_ms"] * 1e-3) / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "bytes_per_sweep": sweep_bytes,
+            "avg_launch_us": 1e3 * P["dense_ms"] / launches,
+            "avg_sweep_us": 1e3 * P["dense_ms"] / P["dense_sweeps"],
+            "launches": launches,
+            "idle_launches": P["idle_launches"],
+        }
+        res["roofline"]["frac"] = res["roofline"]["achieved"] / HBM_PEAK_GBS
+    res["sweep_shape"] = ctx.sweep_shape()
+    if check:
+        import oracle
+
+        t = time.time()
+        lo = np.minimum(pool.keys // (1 << 32), pool.keys % (1 << 32))
+        hi = np.maximum(pool.keys // (1 << 32), pool.keys % (1 << 32))
+        loop = lo == hi
+        s2 = np.concatenate([lo, hi[~loop]]).astype(np.int32)
+        d2 = np.concatenate([hi, lo[~loop]]).astype(np.int32)
+        ref = oracle.rwr_static(pool.n, s2, d2, int(seeds[0]), w.c, tol=1e-12)
+        err = float(np.abs(ctx.scores(0) - ref).sum())
+        res["parity"] = {"columns": [0], "l1_vs_oracle": [err], "oracle_tol": 1e-12, "ok": err <= res["gate"],
+                         "oracle_s": time.time() - t}
+    ctx.close()
+    log(f"[{w.name}] {res['batches_per_s']:.3f} batches/s, {res['modifications_per_s']:.0f} modifications/s")
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,8 +317,10 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=3, help="updates timed on the CPU oracle")
     ap.add_argument("--workloads", default="",
                     help="extra workloads run after the headline, comma list of: rmat22_batched_seeds, "
-                         "rmat21_learned_warm_start")
+                         "rmat21_learned_warm_start, rmat23_undirected_churn")
     ap.add_argument("--batches", type=int, default=200, help="batches of the batched-seed workload")
+    ap.add_argument("--churn-batches", type=int, default=10, help="batches of the undirected churn workload")
+    ap.add_argument("--churn-check", action="store_true", help="check one column of the churn workload (slow)")
     ap.add_argument("--learned-train", type=int, default=500, help="training updates of the learned workload")
     ap.add_argument("--learned-eval", type=int, default=100, help="held-out updates of the learned workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -451,6 +533,8 @@ def main() -> int:
             extra[wname] = run_batched_seeds(args.batches)
         elif wname == "rmat21_learned_warm_start":
             extra[wname] = run_learned(args.learned_train, args.learned_eval)
+        elif wname == "rmat23_undirected_churn":
+            extra[wname] = run_churn(args.churn_batches, args.churn_check)
         else:
             raise SystemExit(f"unknown workload {wname}")
 
