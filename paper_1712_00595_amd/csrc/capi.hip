@@ -130,6 +130,14 @@ struct rwr_ctx {
     std::vector<int> pending;  // candidate of each launch of the current chunk
     double best_ms = 0.0;
   } tune;
+  // HIP graph of two consecutive dense iteration slots (an even and an odd
+  // one: the kernels depend on the slot index only through its parity),
+  // replayed for pairs of dense slots; captured again whenever the kernel
+  // arguments change
+  bool graphs = true;
+  hipGraphExec_t pair_exec = nullptr;
+  SlotArgs pair_args{};
+  int64_t graph_replays = 0;
   // learned warm start (rwr_warm_start)
   struct Warm {
     int32_t mode = 0, hops = 3;
@@ -339,6 +347,7 @@ static void tune_defaults(rwr_ctx *c) {
   if (const char *e = getenv("RWR_HEAVY_LIMIT")) c->heavy_limit = atoi(e);
   if (const char *e = getenv("RWR_HEAVY_CHUNK")) c->heavy_chunk = atoi(e);
   if (const char *e = getenv("RWR_PULL_RATIO")) c->pull_ratio = atoi(e);
+  if (const char *e = getenv("RWR_GRAPHS")) c->graphs = atoi(e) != 0;
   if (const char *e = getenv("RWR_REFINE_TARGET")) {
     const double t = atof(e);
     if (t > 0.0 && t < 1.0) c->refine_target = t;
@@ -656,6 +665,35 @@ static void tune_finish(rwr_ctx *c) {
   }
 }
 
+static void pair_graph_drop(rwr_ctx *c) {
+  if (c->pair_exec) (void)hipGraphExecDestroy(c->pair_exec);
+  c->pair_exec = nullptr;
+}
+
+// the pair graph for arguments a (captured on first use or when a changed)
+static rwr_status pair_graph(rwr_ctx *c, const SlotArgs &a) {
+  if (c->pair_exec && std::memcmp(&c->pair_args, &a, sizeof(SlotArgs)) == 0) return RWR_OK;
+  pair_graph_drop(c);
+  hipGraph_t g = nullptr;
+  HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  launch_dense_slot(a, c->S, c->fp64, 2, c->stream);
+  launch_dense_slot(a, c->S, c->fp64, 3, c->stream);
+  const hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (e != hipSuccess || !g) {
+    c->err = std::string("graph capture failed: ") + hipGetErrorString(e);
+    return RWR_EHIP;
+  }
+  const hipError_t ei = hipGraphInstantiate(&c->pair_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    c->pair_exec = nullptr;
+    c->err = std::string("graph instantiation failed: ") + hipGetErrorString(ei);
+    return RWR_EHIP;
+  }
+  c->pair_args = a;
+  return RWR_OK;
+}
+
 // Enqueue iteration slots until the device reports MODE_DONE.  The slot that
 // computes x^(0) must already be enqueued; `mode` is the phase it leaves
 // (sparse after an offset seed or a seed vector, dense after a residual).
@@ -699,6 +737,12 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
           at.pull_lanes = tn.cand[ci].first;
           at.grid_pull = tn.cand[ci].second;
           launch_dense_slot(at, c->S, c->fp64, k, c->stream, tn.ev[q], tn.ev[q + 1]);
+        } else if (c->graphs && !c->prof_on && (k & 1) == 0 && k + 1 < kend) {
+          // two dense slots (k even, k + 1) from the captured graph
+          RWR_TRY(pair_graph(c, a));
+          HIP_TRY(c, hipGraphLaunch(c->pair_exec, c->stream));
+          ++c->graph_replays;
+          ++k;
         } else {
           if (c->prof_on) RWR_TRY(prof_pair(c, &e0, &e1));
           launch_dense_slot(a, c->S, c->fp64, k, c->stream, e0, e1);
@@ -1689,6 +1733,7 @@ void rwr_destroy(rwr_ctx *c) {
   if (c->ctl_h) (void)hipHostFree(c->ctl_h);
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->tune.ev) (void)hipEventDestroy(e);
+  pair_graph_drop(c);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

@@ -422,3 +422,35 @@ def test_sweep_shape_tuning(monkeypatch, n_seeds):
             ref = oracle.rwr_static(g.n, g.src, g.dst, int(seeds[j]), 0.15)
             assert _l1(tuned.scores(j), ref) < 1e-11
             assert _l1(fixed.scores(j), ref) < 1e-11
+
+
+def test_graph_replay_matches_eager(monkeypatch):
+    # dense iteration pairs replayed from a captured HIP graph give the same
+    # propagation as eager launches, update after update (each update replays
+    # the graph several times; eager work and synchronisations in between)
+    print("[graph replay]", flush=True)
+    g = rmat_graph(13, 120000, dead_end_self_loops=True)
+    s = int(np.argmax(g.out_degree()))
+    model = EdgeSetModel(g.n, g.src, g.dst)
+    rng = np.random.default_rng(12)
+    batches = [mixed_batch(rng, model, 20, 20) for _ in range(12)] + single_edge_stream(model, 12)
+    kw = dict(eps=1e-12, precision="fp64", build_tol=1e-11, err_budget=1e-10)
+    monkeypatch.setenv("RWR_GRAPHS", "0")
+    eager = _ctx(g, [s], **kw)
+    monkeypatch.setenv("RWR_GRAPHS", "1")
+    graph = _ctx(g, [s], **kw)
+    try:
+        n, src, dst = g.n, g.src, g.dst
+        dense = 0
+        for b in batches:
+            se = eager.update_batch(b)
+            sg = graph.update_batch(b)
+            dense += sg["dense_iters"]
+            assert sg["iters"] == se["iters"], (sg["iters"], se["iters"])
+            assert _l1(graph.scores(0), eager.scores(0)) < 1e-13
+        assert dense >= 4  # dense pairs ran
+        n, src, dst = oracle.apply_stream(g.n, g.src, g.dst, batches)
+        assert _l1(graph.scores(0), oracle.rwr_static(n, src, dst, s, 0.15)) < 1e-10
+    finally:
+        eager.close()
+        graph.close()
