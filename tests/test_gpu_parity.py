@@ -454,3 +454,47 @@ def test_graph_replay_matches_eager(monkeypatch):
     finally:
         eager.close()
         graph.close()
+
+
+# ------------------------------------------- full-size workloads (sampled)
+
+@pytest.mark.slow
+def test_full_size_single_edge_stream():
+    # the bench's workload at full size (R-MAT scale 20, one seed, FP32
+    # propagation, eps = 1e-9, the launch shape the bench uses), 100 updates
+    # of its stream, against the oracle's static solve of the final graph
+    print("[full size scale 20]", flush=True)
+    from synth.configs import RMAT20_SINGLE_EDGE, stream_for
+
+    w = RMAT20_SINGLE_EDGE
+    g = w.graph()
+    seeds = w.seeds(g)
+    stream = stream_for(w, w.model(g), 100)
+    with _ctx(g, seeds, c=w.c, eps=1e-9, precision="fp32") as ctx:
+        stats = [ctx.update_batch(b) for b in stream]
+        assert max(s["err_bound"] for s in stats) <= 2e-9 / w.c
+        n, s, d = oracle.apply_stream(g.n, g.src, g.dst, stream)
+        ref = oracle.rwr_static(n, s, d, int(seeds[0]), w.c)
+        assert _l1(ctx.scores(0), ref) <= 2e-9 / w.c
+
+
+@pytest.mark.slow
+def test_full_size_64_columns_scale20():
+    # 64 uniform seeds on the scale-20 graph with batches of the batched-seed
+    # workload's kind; 4 sampled columns against the oracle
+    print("[full size 64 columns]", flush=True)
+    from synth.configs import RMAT20_SINGLE_EDGE
+    from synth.rmat import sample_seeds
+    from synth.stream import loguniform_batch_stream
+
+    g = RMAT20_SINGLE_EDGE.graph()
+    seeds = sample_seeds(g, 64, seed=3)
+    stream = loguniform_batch_stream(EdgeSetModel(g.n, g.src, g.dst), 8, max_size=2000, seed=4)
+    eps = 1e-6
+    with _ctx(g, seeds, c=0.15, eps=eps, precision="fp32") as ctx:
+        for b in stream:
+            ctx.update_batch(b)
+        n, s, d = oracle.apply_stream(g.n, g.src, g.dst, stream)
+        for j in (0, 21, 42, 63):
+            ref = oracle.rwr_static(n, s, d, int(seeds[j]), 0.15)
+            assert _l1(ctx.scores(j), ref) <= 2 * eps / 0.15, j
