@@ -48,7 +48,7 @@ def cpu_count_used() -> int:
     return 1
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_pull_mp_rmat20_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_pull_wv_rmat20_traffic.md")
 SWEEP_SOURCE = os.path.join(ROOT, "paper_1712_00595_amd", "csrc", "k_prop.hip")
 
 
@@ -462,7 +462,7 @@ def main() -> int:
         results[name] = res
 
     H = results[headline]
-    # roofline of the dominant kernel: the dense sweep (k_pull_mp, one pull
+    # roofline of the dominant kernel: the dense sweep (k_pull_wv, one pull
     # over every in-row).  Every launch in the timed region is timed; the
     # algorithmic bytes per launch average the launches that swept (launches
     # that found the run converged move no data but count in the time).
@@ -477,7 +477,7 @@ def main() -> int:
         traffic = measured_traffic(sweep_bytes)
         roof = {
             "bound": "hbm",
-            "kernel": "k_pull_mp<float, KIND_DENSE> (dense sweep, one seed, FP32 gather)",
+            "kernel": "k_pull_wv<float, KIND_DENSE, 4, 4096> (dense sweep, one seed, FP32 gather)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

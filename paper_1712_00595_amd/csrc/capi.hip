@@ -62,6 +62,7 @@ struct rwr_ctx {
   bool undirected = false, fp64 = false;
   Orientation g[2];
   double *r = nullptr, *ybuf = nullptr, *gbuf = nullptr;
+  double *xres = nullptr;  // r / d_out, gathered by the residual sweep
   void *x[2] = {nullptr, nullptr};
   int32_t *stamp = nullptr;
   int32_t *fstamp = nullptr;
@@ -277,6 +278,7 @@ static SlotArgs slot_args(const rwr_ctx *c) {
   a.r = c->r;
   a.ybuf = c->ybuf;
   a.gbuf = c->gbuf;
+  a.xres = c->xres;
   a.x[0] = c->x[0];
   a.x[1] = c->x[1];
   a.stamp = c->stamp;
@@ -330,7 +332,7 @@ static void tune_defaults(rwr_ctx *c) {
   if (S == 1) {
     c->light_lanes = 16;
     c->heavy_limit = 512;
-    c->heavy_chunk = 4096;
+    c->heavy_chunk = 1024;
   } else if (S <= 4) {
     c->heavy_limit = 512;
     c->heavy_chunk = 2048;
@@ -358,15 +360,16 @@ static void tune_defaults(rwr_ctx *c) {
   c->grid_sparse = 4 * c->n_cu;
   // dense sweeps: the workgroups that fit on the chip at once (registers:
   // and LDS: five per CU for both the single-column and the vector sweep)
-  c->grid_pull = (S == 1 ? 5 : S == 2 ? 8 : 5) * c->n_cu;
+  c->grid_pull = (S == 1 ? 6 : S == 2 ? 8 : 5) * c->n_cu;
   if (const char *e = getenv("RWR_GRID_LIGHT")) c->grid_light = atoi(e);
   if (const char *e = getenv("RWR_GRID_SPARSE")) c->grid_sparse = atoi(e);
   if (const char *e = getenv("RWR_GRID_PULL")) c->grid_pull = atoi(e);
 }
 
 // Row partition of the single-column dense sweep over all n_cap rows (rows
-// beyond n are empty): consecutive rows, at most 256 per workgroup and about
-// MP_EDGES light in-edges (rows above the heavy limit count as empty).
+// beyond n are empty): consecutive rows, at most WV_ROWS per wavefront item
+// and about WV_EDGES light in-edges (rows above the heavy limit count as
+// empty).
 static rwr_status plan_partition(rwr_ctx *c) {
   Orientation &o = c->g[pull_orient(c)];
   std::vector<int32_t> len(c->n_cap);
@@ -376,9 +379,11 @@ static rwr_status plan_partition(rwr_ctx *c) {
   rows.push_back(0);
   int64_t acc = 0;
   int cnt = 0;
+  const int max_rows = WV_ROWS;
+  const int64_t max_edges = WV_EDGES;
   for (int32_t v = 0; v < c->n_cap; ++v) {
     const int64_t l = len[v] > c->heavy_limit ? 0 : len[v];
-    if (cnt > 0 && (cnt == 256 || acc + l > MP_EDGES)) {
+    if (cnt > 0 && (cnt == max_rows || acc + l > max_edges)) {
       rows.push_back(v);
       acc = 0;
       cnt = 0;
@@ -514,6 +519,7 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
   RWR_TRY(regrow((void **)&c->r, 8, c->S));
   RWR_TRY(regrow((void **)&c->ybuf, 8, c->S));
   RWR_TRY(regrow((void **)&c->gbuf, 8, c->S));
+  RWR_TRY(regrow((void **)&c->xres, 8, c->S));
   RWR_TRY(regrow(&c->x[0], xs, c->S));
   RWR_TRY(regrow(&c->x[1], xs, c->S));
   RWR_TRY(regrow((void **)&c->stamp, 4, 1));
@@ -627,7 +633,7 @@ static void tune_begin(rwr_ctx *c) {
   t.cand.clear();
   const int cu = c->n_cu;
   if (c->S == 1) {
-    for (int g : {3, 4, 5}) t.cand.push_back({c->pull_lanes, g * cu});
+    for (int g : {4, 5, 6}) t.cand.push_back({c->pull_lanes, g * cu});
   } else if (c->S == 2) {
     for (int g : {4, 6, 8}) t.cand.push_back({c->pull_lanes, g * cu});
   } else {
@@ -1268,6 +1274,7 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   RWR_TRY(alloc_zero(c, &c->r, nS));
   RWR_TRY(alloc_zero(c, &c->ybuf, nS));
   RWR_TRY(alloc_zero(c, &c->gbuf, nS));
+  RWR_TRY(alloc_zero(c, &c->xres, nS));
   const size_t xs = c->fp64 ? 8 : 4;
   RWR_TRY(dev_alloc(c, &c->x[0], xs * nS));
   RWR_TRY(dev_alloc(c, &c->x[1], xs * nS));
@@ -1692,6 +1699,7 @@ void rwr_destroy(rwr_ctx *c) {
   dev_free(c->r);
   dev_free(c->ybuf);
   dev_free(c->gbuf);
+  dev_free(c->xres);
   dev_free(c->x[0]);
   dev_free(c->x[1]);
   dev_free(c->stamp);

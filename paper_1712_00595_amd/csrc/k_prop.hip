@@ -30,6 +30,7 @@
 #define BLOCK 256
 #define NWAVES (BLOCK / RWR_WAVE)
 #define DECIDE_BLOCK 1024
+#define HEAVY_FOLD 1024  // at most this many heavy row-columns are finished inside the decision kernel
 
 enum { KIND_SPARSE = 0, KIND_DENSE = 1, KIND_REFINE = 2, KIND_RESID = 3, KIND_SIGMA = 4 };
 
@@ -96,12 +97,18 @@ struct DecideShared {
   int s_active;
 };
 
+template <typename XT, int S, int KIND>
+__device__ __forceinline__ void pull_epilogue(const SlotArgs &a, XT *__restrict__ xnext, int v, int j, double y,
+                                              bool act, double &nrm, double &sm);
+
 // One workgroup: totals of entries 0..count-1, then the decision of the
 // iteration (kind SPARSE/DENSE/REFINE), or the residual / column-sum results.
+// With `fold` (after a dense or residual sweep with few heavy rows) it first
+// finishes the heavy rows itself: chunk sums added in order, row epilogue.
 // Every sum runs in a fixed order: strided per thread, then a shuffle tree in
 // each wave, then the waves in index order.
-template <int S>
-__global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, int count, int new_list) {
+template <typename XT, int S>
+__global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, int count, int new_list, int fold) {
   __shared__ DecideShared sh;
   constexpr int NW = DECIDE_BLOCK / RWR_WAVE;
   Ctl *ctl = a.ctl;
@@ -114,6 +121,23 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
   for (int e = q; e < count; e += TPC) {
     A += a.part[e * entry_stride<S>() + 2 * j];
     B += a.part[e * entry_stride<S>() + 2 * j + 1];
+  }
+  if (fold) {
+    const double c1 = 1.0 - a.c;
+    const bool act = ctl->active[j] != 0;
+    XT *__restrict__ xnext = (XT *)a.x[new_list];
+    double hn = 0.0, hs = 0.0;
+    for (int h = q; h < a.heavy.n_rows; h += TPC) {
+      const int f = a.heavy.first[h], nch = a.heavy.nchunks[h];
+      double y = 0.0;
+      for (int qq = 0; qq < nch; ++qq) y += a.heavy.part[(int64_t)(f + qq) * S + j];
+      if (kind == KIND_RESID)
+        pull_epilogue<double, S, KIND_RESID>(a, nullptr, a.heavy.rows[h], j, c1 * y, act, hn, hs);
+      else
+        pull_epilogue<XT, S, KIND_DENSE>(a, xnext, a.heavy.rows[h], j, c1 * y, act, hn, hs);
+    }
+    A += hn;
+    B += hs;
   }
   int64_t ia = 0, ib = 0;
   for (int e = t; e < count; e += DECIDE_BLOCK) {
@@ -341,7 +365,7 @@ template <typename XT, int S, int KIND>
 struct Gather {
   __device__ __forceinline__ static double get(const SlotArgs &a, const XT *__restrict__ x, int u, int j) {
     if constexpr (KIND == KIND_RESID) {
-      return a.r[col_index(u, S, j)] / (double)a.out.len[u];
+      return a.xres[col_index(u, S, j)];
     } else {
       return (double)x[col_index(u, S, j)];
     }
@@ -379,7 +403,7 @@ __device__ __forceinline__ void pull_epilogue(const SlotArgs &a, XT *__restrict_
 // independent gathers in flight.
 template <typename XT, int S, int KIND>
 __device__ __forceinline__ void heavy_item(const SlotArgs &a, int item, const XT *__restrict__ xcur,
-                                           double (*hred)[RWR_MAX_COLS], const XT *xc = nullptr, int ncache = 0) {
+                                           double (*hred)[RWR_MAX_COLS]) {
   constexpr int PP = RWR_WAVE / S;
   constexpr int STRIDE = NWAVES * PP;
   const int lane = threadIdx.x % RWR_WAVE, w = threadIdx.x / RWR_WAVE;
@@ -393,10 +417,7 @@ __device__ __forceinline__ void heavy_item(const SlotArgs &a, int item, const XT
   const int32_t *__restrict__ adj = a.in.adj + o;
   double acc = 0.0;
   int e = e0 + w * PP + pp;
-  auto get = [&](int u) -> double {
-    if (S == 1 && u < ncache) return (double)xc[u];
-    return Gather<XT, S, KIND>::get(a, xcur, u, jj);
-  };
+  auto get = [&](int u) -> double { return Gather<XT, S, KIND>::get(a, xcur, u, jj); };
   for (; e + 3 * STRIDE < e1; e += 4 * STRIDE) {
     const int u0 = adj[e], u1 = adj[e + STRIDE], u2 = adj[e + 2 * STRIDE], u3 = adj[e + 3 * STRIDE];
     const double g0 = get(u0);
@@ -494,10 +515,9 @@ __device__ __forceinline__ void gather_vec(const SlotArgs &a, const XT *__restri
                                            double (&g)[VecGather<XT, KIND>::V]) {
   using VG = VecGather<XT, KIND>;
   if constexpr (KIND == KIND_RESID) {
-    const double2 t = *reinterpret_cast<const double2 *>(a.r + col_index(u, S, j0));
-    const double dl = (double)a.out.len[u];
-    g[0] = t.x / dl;
-    g[1] = t.y / dl;
+    const double2 t = *reinterpret_cast<const double2 *>(a.xres + col_index(u, S, j0));
+    g[0] = t.x;
+    g[1] = t.y;
   } else if constexpr (VG::V == 4) {
     const float4 t = *reinterpret_cast<const float4 *>(x + col_index(u, S, j0));
     g[0] = t.x;
@@ -719,188 +739,269 @@ __global__ __launch_bounds__(BLOCK) void k_pull_v(SlotArgs a, int k) {
   block_publish_vec<S, V>(nrm, sm, a.part, a.part_i, blockIdx.x, sh);
 }
 
-#define MP_ROWS 256
-#define MP_PER_THREAD 8
-#define MP_ROUND (MP_PER_THREAD * BLOCK)
-#define MP_SHORT 32  // rows with at most this many in-edges are summed by their owner thread
-#define MP_CACHE 4096  // leading entries of the FP32 vector kept in LDS by the single-column sweep
+#define WV_PER_LANE 8                       // consecutive in-edges per lane in a round
+#define WV_ROUND (WV_PER_LANE * RWR_WAVE)   // in-edges per round of a wave item
+static_assert(WV_ROUND == WV_EDGES && WV_ROWS == RWR_WAVE, "wave item shape");
 
-// Dense sweep for one seed column, merge-path style.  Work item b owns the
-// rows mp_rows[b] .. mp_rows[b+1] (at most MP_ROWS rows and about MP_EDGES
-// light in-edges; heavy rows count as empty).  The rows' in-edges are
-// numbered consecutively; in each round thread t fetches MP_PER_THREAD
-// consecutive edges of the round (one binary search, then independent index
-// loads and gathers) into LDS.  Then each short row's owner thread adds its segment, and each
-// long row is added by a whole wave (strided lanes, shuffle tree).  Row sums
-// accumulate round by round in LDS; every order is fixed (deterministic).
-// Nodes are numbered by descending out-degree, so the leading entries of the
-// vector are the most gathered ones: in the FP32 propagation sweep each
-// workgroup copies the first MP_CACHE entries into LDS once and reads them
-// there (a third of the gathers at R-MAT scale 20).
-template <typename XT, int KIND>
-__global__ __launch_bounds__(BLOCK) void k_pull_mp(SlotArgs a, int k) {
-  constexpr bool FP32_PROP = KIND == KIND_DENSE && sizeof(XT) == 4;
-  constexpr int CACHE = FP32_PROP ? MP_CACHE : 0;
-  using PT = typename std::conditional<FP32_PROP, float, double>::type;  // staged gathers
-  struct MpShared {
-    int32_t pref[MP_ROWS + 1];
-    int32_t off[MP_ROWS];
-    int32_t longs[MP_ROWS];
-    int32_t wsum[NWAVES];
-    int32_t wlong[NWAVES];
-    double rowacc[MP_ROWS];
-    PT prod[MP_ROUND];
+// Order LDS accesses between the lanes of one wavefront (LDS requests of a
+// wavefront complete in issue order; the fences keep the compiler from
+// moving accesses across this point).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS of one wavefront's light item: the row of each entry of the round,
+// off - pref per row, and the finished row sums
+struct alignas(16) WaveBuf {
+  int16_t rmap[WV_ROUND];
+  int32_t base[WV_ROWS];
+  double rsum[WV_ROWS];
+};
+
+// Per-lane row data of one wave item (lane i holds row r0 + i)
+struct WvRows {
+  int r0, nr;    // first row, number of rows (uniform)
+  int d, off;    // light in-degree (0 for a heavy row or no row), in-row offset
+  int dout;      // out-degree
+  bool light;    // the lane holds a row that is not heavy
+  double rv;     // r of the row
+};
+
+template <int KIND>
+__device__ __forceinline__ WvRows wv_rows(const SlotArgs &a, int b, int lane) {
+  WvRows m;
+  m.r0 = a.mp_rows[b];
+  m.nr = max(0, min(a.mp_rows[b + 1], a.n) - m.r0);
+  m.d = 0;
+  m.off = 0;
+  m.dout = 0;
+  m.light = false;
+  m.rv = 0.0;
+  if (lane < m.nr) {
+    const int v = m.r0 + lane;
+    m.light = a.in.heavy[v] == 0;
+    m.off = a.in.off[v];
+    const int d = a.in.len[v];
+    m.d = m.light ? d : 0;
+    if constexpr (KIND != KIND_RESID) m.dout = a.out.len[v];
+    m.rv = a.r[v];
+  }
+  return m;
+}
+
+// Dense sweep for one seed column at wavefront granularity: every wavefront
+// takes its own work items, with no workgroup barrier between items, so the
+// load chains (row data -> in-row indices -> gathers) of all resident
+// wavefronts overlap.  Items, in index order:
+//   heavy chunks: a range of at most heavy.chunk in-edges of one heavy row;
+//     lanes take consecutive edges, WV_PER_LANE loads in flight each; the
+//     chunk sum (fixed shuffle tree) goes to heavy.part[item];
+//   light items: rows mp_rows[b] .. mp_rows[b+1] (at most WV_ROWS rows and
+//     about WV_ROUND light in-edges), merge-path style.  The rows' in-edges
+//     are numbered consecutively; in each round lane t takes WV_PER_LANE
+//     consecutive entries.  The row of every entry comes from a row map
+//     (each row marks its first entry in LDS, then a running maximum over
+//     the lane's entries and across the wave), so all index loads and
+//     gathers of a lane are independent.  Sums by row: runs inside the lane,
+//     then a segmented scan of the lanes' last runs across the wave; the
+//     lane holding a row's last entry stores the row total.  A row that
+//     continues into the next round carries its partial sum.  The row data
+//     of the wavefront's next item is loaded while the current one runs.
+// Every sum runs in a fixed order (deterministic).  Nodes are numbered by
+// descending out-degree, so the leading entries of the gathered vector are
+// the most gathered ones: the workgroup copies the first CACHE entries into
+// LDS once and reads them there (4096 FP32 entries serve about a third of
+// the gathers of an R-MAT graph of a million nodes).
+template <typename XT, int KIND, int NWV, int CACHE>
+__global__ __launch_bounds__(NWV * RWR_WAVE) void k_pull_wv(SlotArgs a, int k) {
+  constexpr int BLOCKW = NWV * RWR_WAVE;
+  using PT = typename std::conditional<sizeof(XT) == 4 && KIND == KIND_DENSE, float, double>::type;
+  struct Red {
+    double n[NWV], s[NWV];
   };
   __shared__ union {
-    BlockRed red;
-    MpShared mp;
+    Red red;
+    WaveBuf wb[NWV];
   } U;
-  __shared__ double hred[NWAVES][RWR_MAX_COLS];
   __shared__ XT xc[CACHE > 0 ? CACHE : 1];
   Ctl *ctl = a.ctl;
   if (KIND == KIND_DENSE && ctl->mode != MODE_DENSE) return;
   const XT *__restrict__ xcur = (const XT *)a.x[(k - 1) & 1];
   const int ncache = CACHE > 0 ? min(CACHE, a.n) : 0;
   if constexpr (CACHE > 0) {
-    for (int i = threadIdx.x; i < ncache; i += BLOCK) xc[i] = xcur[i];
+    const XT *src = KIND == KIND_RESID ? (const XT *)a.xres : xcur;
+    for (int i = threadIdx.x; i < ncache; i += BLOCKW) xc[i] = src[i];
     __syncthreads();
   }
   XT *__restrict__ xnext = (XT *)a.x[k & 1];
   const double c1 = 1.0 - a.c;
   const bool act = ctl->active[0] != 0;
+  const int lane = threadIdx.x % RWR_WAVE, w = threadIdx.x / RWR_WAVE;
+  auto get = [&](int u) -> PT {
+    if (CACHE > 0 && u < ncache) return (PT)xc[u];
+    return (PT)Gather<XT, 1, KIND>::get(a, xcur, u, 0);
+  };
   double nrm = 0.0, sm = 0.0;
-  const int total_items = a.heavy.n_items + a.n_mp;
-  for (int item = blockIdx.x; item < total_items; item += gridDim.x) {
-    if (item < a.heavy.n_items) {
-      heavy_item<XT, 1, KIND>(a, item, xcur, hred, xc, ncache);
-      continue;
+  const int nwaves = gridDim.x * NWV;
+  const int nh = a.heavy.n_items;
+  int it = blockIdx.x * NWV + w;
+  // heavy-row chunks
+  for (; it < nh; it += nwaves) {
+    const int h = a.heavy.item_row[it], ck = a.heavy.item_chunk[it];
+    const int v = a.heavy.rows[h], nch = a.heavy.nchunks[h];
+    const int o = a.in.off[v], d = a.in.len[v];
+    const int e0 = ck * a.heavy.chunk;
+    const int e1 = (ck == nch - 1) ? d : min(d, e0 + a.heavy.chunk);
+    const int32_t *__restrict__ adj = a.in.adj + o;
+    double acc = 0.0;
+    for (int e = e0 + lane; e < e1; e += WV_ROUND) {
+      int uq[WV_PER_LANE];
+#pragma unroll
+      for (int q = 0; q < WV_PER_LANE; ++q) uq[q] = e + q * RWR_WAVE < e1 ? nt_load(adj + e + q * RWR_WAVE) : -1;
+      PT gq[WV_PER_LANE];
+#pragma unroll
+      for (int q = 0; q < WV_PER_LANE; ++q) gq[q] = uq[q] < 0 ? (PT)0 : get(uq[q]);
+      double s4[WV_PER_LANE / 2];
+#pragma unroll
+      for (int q = 0; q < WV_PER_LANE / 2; ++q) s4[q] = (double)gq[2 * q] + (double)gq[2 * q + 1];
+#pragma unroll
+      for (int q = 0; q < WV_PER_LANE / 4; ++q) acc += s4[2 * q] + s4[2 * q + 1];
     }
-    MpShared &M = U.mp;
-    const int b = item - a.heavy.n_items;
-    const int r0 = a.mp_rows[b];
-    const int r1 = min(a.mp_rows[b + 1], a.n);
-    const int nr = max(0, r1 - r0);
-    const int t = threadIdx.x;
-    const int lane = t % RWR_WAVE, w = t / RWR_WAVE;
-    int d = 0;
-    bool heavy = false;
-    if (t < nr) {
-      const int v = r0 + t;
-      heavy = a.in.heavy[v] != 0;
-      d = heavy ? 0 : a.in.len[v];
-      M.off[t] = a.in.off[v];
-    }
-    M.rowacc[t] = 0.0;
-    // exclusive scan of the row lengths; list of the long rows
-    int incl = d;
+    acc = wave_xor_sum(acc, 1, RWR_WAVE);
+    if (lane == 0) a.heavy.part[it] = acc;
+  }
+  // light items
+  WaveBuf &B = U.wb[w];
+  int b = it - nh;
+  WvRows cur{};
+  if (b < a.n_mp) cur = wv_rows<KIND>(a, b, lane);
+  while (b < a.n_mp) {
+    const int bn = b + nwaves;
+    // exclusive scan of the row lengths: row t owns entries pref_t .. incl_t - 1
+    int incl = cur.d;
     for (int s2 = 1; s2 < RWR_WAVE; s2 <<= 1) {
       const int y = __shfl_up(incl, s2, RWR_WAVE);
       if (lane >= s2) incl += y;
     }
-    const bool is_long = d > MP_SHORT;
-    const uint64_t lm = __ballot(is_long);
-    if (lane == RWR_WAVE - 1) M.wsum[w] = incl;
-    if (lane == 0) M.wlong[w] = __popcll(lm);
-    __syncthreads();
-    int wb = 0, lb = 0, nl = 0;
-    for (int ww = 0; ww < NWAVES; ++ww) {
-      if (ww < w) wb += M.wsum[ww], lb += M.wlong[ww];
-      nl += M.wlong[ww];
-    }
-    M.pref[t] = wb + incl - d;
-    if (t == BLOCK - 1) M.pref[BLOCK] = wb + incl;
-    if (is_long) M.longs[lb + __popcll(lm & lanemask_lt())] = t;
-    __syncthreads();
-    const int total = M.pref[nr];
-    // operands of the row epilogue, fetched early so their latency overlaps
-    // the gathers
-    int dout = 0;
-    double rv = 0.0;
-    if (t < nr && !heavy) {
-      dout = a.out.len[r0 + t];
-      rv = a.r[r0 + t];
-    }
-    for (int base = 0; base < total; base += MP_ROUND) {
-      const int i0 = base + MP_PER_THREAD * t;
-      int row = 0;
-      if (i0 < total) {
-        int lo = 0, hi = nr - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (M.pref[mid] <= i0)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        row = lo;
-      }
-      int uq[MP_PER_THREAD];
+    const int my_pref = incl - cur.d;
+    const int total = __shfl(incl, RWR_WAVE - 1, RWR_WAVE);
+    B.base[lane] = cur.off - my_pref;
+    B.rsum[lane] = 0.0;
+    WvRows nxt{};
+    if (bn < a.n_mp) nxt = wv_rows<KIND>(a, bn, lane);
+    int carry_row = -1;  // row of the previous round's last entry
+    double carry = 0.0;  // its partial sum up to there
+    for (int base0 = 0; base0 < total; base0 += WV_ROUND) {
+      // row of every entry of the round: each row marks its first entry,
+      // then a running maximum (lane-local over 8 entries, then the wave)
+      int4 *rm4 = reinterpret_cast<int4 *>(B.rmap);
+      rm4[lane] = make_int4(-1, -1, -1, -1);
+      wave_lds_sync();
+      if (cur.d > 0 && my_pref >= base0 && my_pref < base0 + WV_ROUND) B.rmap[my_pref - base0] = (int16_t)lane;
+      wave_lds_sync();
+      const int4 mk = rm4[lane];
+      int r[WV_PER_LANE];
+      r[0] = (int16_t)(mk.x & 0xffff);
+      r[1] = (int16_t)(mk.x >> 16);
+      r[2] = (int16_t)(mk.y & 0xffff);
+      r[3] = (int16_t)(mk.y >> 16);
+      r[4] = (int16_t)(mk.z & 0xffff);
+      r[5] = (int16_t)(mk.z >> 16);
+      r[6] = (int16_t)(mk.w & 0xffff);
+      r[7] = (int16_t)(mk.w >> 16);
+      if (lane == 0) r[0] = max(r[0], carry_row);  // the round may start inside a row
 #pragma unroll
-      for (int q = 0; q < MP_PER_THREAD; ++q) {
-        const int i = i0 + q;
-        uq[q] = -1;
-        if (i < total) {
-          while (M.pref[row + 1] <= i) ++row;
-          uq[q] = a.in.adj[M.off[row] + (i - M.pref[row])];
-        }
+      for (int q = 1; q < WV_PER_LANE; ++q) r[q] = max(r[q], r[q - 1]);
+      int mx = r[WV_PER_LANE - 1];
+      for (int s2 = 1; s2 < RWR_WAVE; s2 <<= 1) {
+        const int y = __shfl_up(mx, s2, RWR_WAVE);
+        if (lane >= s2) mx = max(mx, y);
       }
-      PT gq[MP_PER_THREAD];
+      int before = __shfl_up(mx, 1, RWR_WAVE);
+      if (lane == 0) before = -1;
+      const int i0 = base0 + WV_PER_LANE * lane;
 #pragma unroll
-      for (int q = 0; q < MP_PER_THREAD; ++q) {
-        if (uq[q] < 0)
-          gq[q] = (PT)0;
-        else if (uq[q] < ncache)
-          gq[q] = (PT)xc[uq[q]];
-        else
-          gq[q] = (PT)Gather<XT, 1, KIND>::get(a, xcur, uq[q], 0);
-      }
+      for (int q = 0; q < WV_PER_LANE; ++q) r[q] = i0 + q < total ? max(r[q], before) : WV_ROWS;
+      int uq[WV_PER_LANE];
 #pragma unroll
-      for (int q = 0; q < MP_PER_THREAD; ++q) M.prod[MP_PER_THREAD * t + q] = gq[q];
-      __syncthreads();
-      if (t < nr && d <= MP_SHORT) {
-        const int lo = max(M.pref[t], base) - base;
-        const int hi = min(M.pref[t + 1], base + MP_ROUND) - base;
-        if (hi > lo) {
-          double s = 0.0;
-          for (int kk = lo; kk < hi; ++kk) s += (double)M.prod[kk];
-          M.rowacc[t] += s;
+      for (int q = 0; q < WV_PER_LANE; ++q) uq[q] = r[q] < WV_ROWS ? a.in.adj[B.base[r[q]] + i0 + q] : -1;
+      PT gq[WV_PER_LANE];
+#pragma unroll
+      for (int q = 0; q < WV_PER_LANE; ++q) gq[q] = uq[q] < 0 ? (PT)0 : get(uq[q]);
+      // sums by row: runs inside the lane, then a segmented scan of the
+      // lanes' last runs across the wave (fixed order: left to right)
+      double sq[WV_PER_LANE];
+      sq[0] = (lane == 0 && r[0] == carry_row) ? carry + (double)gq[0] : (double)gq[0];
+#pragma unroll
+      for (int q = 1; q < WV_PER_LANE; ++q) sq[q] = r[q] == r[q - 1] ? sq[q - 1] + (double)gq[q] : (double)gq[q];
+      const int last_prev = __shfl_up(r[WV_PER_LANE - 1], 1, RWR_WAVE);
+      const bool cont = lane > 0 && last_prev == r[0];  // the first run continues the previous lane's last
+      double v = sq[WV_PER_LANE - 1];
+      int f = (!cont || r[0] != r[WV_PER_LANE - 1]) ? 1 : 0;
+      for (int s2 = 1; s2 < RWR_WAVE; s2 <<= 1) {
+        const double vu = __shfl_up(v, s2, RWR_WAVE);
+        const int fu = __shfl_up(f, s2, RWR_WAVE);
+        if (lane >= s2) {
+          if (!f) v = vu + v;
+          f |= fu;
         }
       }
-      for (int li = w; li < nl; li += NWAVES) {
-        const int rr = M.longs[li];
-        const int lo = max(M.pref[rr], base) - base;
-        const int hi = min(M.pref[rr + 1], base + MP_ROUND) - base;
-        if (hi <= lo) continue;  // uniform in the wave
-        double s = 0.0;
-        for (int kk = lo + lane; kk < hi; kk += RWR_WAVE) s += (double)M.prod[kk];
-        s = wave_xor_sum(s, 1, RWR_WAVE);
-        if (lane == 0) M.rowacc[rr] += s;
+      const double v_prev = __shfl_up(v, 1, RWR_WAVE);
+      const double cin = cont ? v_prev : 0.0;
+      // a run ends where the row's last entry is; its total goes to rsum
+      const int end_last = __shfl(incl, r[WV_PER_LANE - 1] & (RWR_WAVE - 1), RWR_WAVE);
+#pragma unroll
+      for (int q = 0; q < WV_PER_LANE; ++q) {
+        const bool ends = q < WV_PER_LANE - 1 ? r[q + 1] != r[q] : i0 + q + 1 == end_last;
+        if (r[q] < WV_ROWS && ends) B.rsum[r[q]] = r[q] == r[0] ? cin + sq[q] : sq[q];
       }
-      __syncthreads();
+      carry_row = __shfl(r[WV_PER_LANE - 1], RWR_WAVE - 1, RWR_WAVE);
+      carry = __shfl(v, RWR_WAVE - 1, RWR_WAVE);
+      wave_lds_sync();
     }
-    if (t < nr && !heavy) {
-      const int v = r0 + t;
-      const double y = c1 * M.rowacc[t];
+    const double acc = B.rsum[lane];
+    if (cur.light) {
+      const int v = cur.r0 + lane;
+      const double y = c1 * acc;
       if constexpr (KIND == KIND_RESID) {
-        double g = y - rv;
+        double g = y - cur.rv;
         if (a.n_seeds < 1 || (a.zero_seed_rows && a.seeds[0] == v)) g = 0.0;
         a.gbuf[v] = g;
         nrm += fabs(g);
-        sm += rv;
+        sm += cur.rv;
       } else {
         if (act) {
-          a.r[v] = rv + y;
+          a.r[v] = cur.rv + y;
           nrm += fabs(y);
           sm += y;
-          xnext[v] = dout ? (XT)(y / (double)dout) : (XT)0;
+          xnext[v] = cur.dout ? (XT)(y / (double)cur.dout) : (XT)0;
         } else {
           xnext[v] = (XT)0;
         }
       }
     }
-    __syncthreads();
+    cur = nxt;
+    b = bn;
   }
-  block_publish<1>(nrm, sm, 0, 0, a.part, a.part_i, blockIdx.x, U.red);
+  // partial sums of the workgroup: shuffle tree per wave, waves in order
+  nrm = wave_xor_sum(nrm, 1, RWR_WAVE);
+  sm = wave_xor_sum(sm, 1, RWR_WAVE);
+  __syncthreads();
+  if (lane == 0) {
+    U.red.n[w] = nrm;
+    U.red.s[w] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tn = 0.0, ts = 0.0;
+    for (int ww = 0; ww < NWV; ++ww) tn += U.red.n[ww], ts += U.red.s[ww];
+    a.part[blockIdx.x * entry_stride<1>()] = tn;
+    a.part[blockIdx.x * entry_stride<1>() + 1] = ts;
+    a.part_i[(int64_t)blockIdx.x * 16] = 0;
+    a.part_i[(int64_t)blockIdx.x * 16 + 1] = 0;
+  }
 }
 
 // Heavy rows after a dense sweep: the chunk sums of row h (items first[h] ..
@@ -924,6 +1025,17 @@ __global__ __launch_bounds__(BLOCK) void k_heavy_epi(SlotArgs a, int k, int entr
     pull_epilogue<XT, S, KIND>(a, xnext, a.heavy.rows[h], j, c1 * s, act, nrm, sm);
   }
   block_publish<S>(nrm, sm, 0, 0, a.part, a.part_i, entry_base + blockIdx.x, sh);
+}
+
+// input of the residual sweep: xres = r / d_out (0 for a node without
+// out-edges), so that its gathers read one value per in-edge
+template <int S>
+__global__ __launch_bounds__(BLOCK) void k_prescale(SlotArgs a) {
+  const int64_t total = (int64_t)a.n * S;
+  for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < total; i += (int64_t)gridDim.x * BLOCK) {
+    const int d = a.out.len[i / S];
+    a.xres[i] = d ? a.r[i] / (double)d : 0.0;
+  }
 }
 
 // ------------------------------------------------------------------ others
@@ -1080,9 +1192,9 @@ void launch_reset_run(Ctl *ctl, int32_t S, uint64_t mask, double eps, int32_t ma
     } break;                     \
   }
 
-template <int S>
-static void decide_impl(const SlotArgs &a, int kind, int count, int new_list, hipStream_t st) {
-  hipLaunchKernelGGL(k_decide<S>, dim3(1), dim3(DECIDE_BLOCK), 0, st, a, kind, count, new_list);
+template <int S, typename XT = float>
+static void decide_impl(const SlotArgs &a, int kind, int count, int new_list, hipStream_t st, int fold = 0) {
+  hipLaunchKernelGGL((k_decide<XT, S>), dim3(1), dim3(DECIDE_BLOCK), 0, st, a, kind, count, new_list, fold);
 }
 
 void launch_seed_init(const SlotArgs &a, int S, hipStream_t st) {
@@ -1109,10 +1221,14 @@ template <typename XT, int S, int KIND>
 static void pull_impl(const SlotArgs &a, int k, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                       bool decide = true) {
   int grid;
+  if constexpr (KIND == KIND_RESID)
+    hipLaunchKernelGGL(k_prescale<S>, dim3(a.grid_light), dim3(BLOCK), 0, st, a);
   if (ev0) (void)hipEventRecord(ev0, st);
   if constexpr (S == 1) {
-    grid = std::max(1, std::min(a.heavy.n_items + a.n_mp, a.grid_pull));
-    hipLaunchKernelGGL((k_pull_mp<XT, KIND>), dim3(grid), dim3(BLOCK), 0, st, a, k);
+    // cached leading entries: 16 KB of the FP32 vector, or of r / d_out
+    constexpr int CW = (KIND == KIND_DENSE && sizeof(XT) == 4) ? 4096 : KIND == KIND_RESID ? 2048 : 0;
+    grid = std::max(1, std::min((a.heavy.n_items + a.n_mp + NWAVES - 1) / NWAVES, a.grid_pull));
+    hipLaunchKernelGGL((k_pull_wv<XT, KIND, NWAVES, CW>), dim3(grid), dim3(BLOCK), 0, st, a, k);
   } else if constexpr (S == 2) {
     grid = a.grid_pull;
     hipLaunchKernelGGL((k_pull<XT, S, 16, KIND>), dim3(grid), dim3(BLOCK), 0, st, a, k);
@@ -1130,12 +1246,14 @@ static void pull_impl(const SlotArgs &a, int k, hipStream_t st, hipEvent_t ev0 =
     }
   }
   if (ev1) (void)hipEventRecord(ev1, st);
+  // few heavy rows: the decision kernel finishes them (one launch less)
+  const bool fold = decide && (int64_t)a.heavy.n_rows * S <= HEAVY_FOLD;
   int hgrid = 0;
-  if (a.heavy.n_rows > 0) {
+  if (a.heavy.n_rows > 0 && !fold) {
     hgrid = std::max(1, std::min((a.heavy.n_rows * S + BLOCK - 1) / BLOCK, 256));
     hipLaunchKernelGGL((k_heavy_epi<XT, S, KIND>), dim3(hgrid), dim3(BLOCK), 0, st, a, k, grid);
   }
-  if (decide) decide_impl<S>(a, KIND, grid + hgrid, k & 1, st);
+  if (decide) decide_impl<S, XT>(a, KIND, grid + hgrid, k & 1, st, fold ? 1 : 0);
 }
 
 template <typename XT, int S>

@@ -42,6 +42,7 @@ struct SlotArgs {
   double *r;
   double *ybuf;
   double *gbuf;
+  double *xres;  // r / d_out per node and column (residual sweep gathers)
   void *x[2];
   int32_t *stamp;    // node touched in the current slot (slot stamp)
   int32_t *fstamp;   // node in the frontier of x^(i) (stamp of slot i)
@@ -64,10 +65,11 @@ struct SlotArgs {
   const int32_t *row_order;  // order of the in-rows in that sweep (a permutation of 0 .. n_cap-1)
   int32_t n_order;           // its length (n_cap)
   const int32_t *mp_rows;  // row partition of the single-column dense sweep
-  int32_t n_mp;            // workgroups of that partition
+  int32_t n_mp;            // items of that partition
 };
 
-#define MP_EDGES 2048  // light in-edges per workgroup of the single-column sweep
+#define WV_ROWS 64      // rows per wave item of the wave-granular single-column sweep
+#define WV_EDGES 512    // light in-edges per wave item (one round of the wavefront)
 
 // ---- delta (k_delta.hip)
 void launch_make_keys(const int32_t *ins_s, const int32_t *ins_d, int64_t n_ins, const int32_t *del_s,
