@@ -110,9 +110,14 @@ struct rwr_ctx {
   double refine_target = 0.9;  // refinements aim at this fraction of the budget
   bool stale = false;
   std::string err;
-  std::vector<double> last_hist;
+  std::vector<double> last_hist;  // host copy of the last run's norms (made on request)
+  bool hist_host_valid = false;
   int32_t last_iters = 0;
   double decay_ema = 0.8;  // observed per-iteration decay of ||x^(i)||_1
+  // sparse and dense iterations of the recent update runs
+  double sparse_ema = 1.0, dense_ema = 0.0;
+  int32_t update_runs = 0;
+  bool built = false;  // the static solve is done (update runs follow)
   // measurement: events around dense sweep launches
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;
@@ -714,6 +719,14 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
   int chunk = 3;
   if (init_norm > 0.0 && eps_hint > 0.0 && init_norm > eps_hint)
     chunk = std::max(1, std::min(64, (int)std::ceil(std::log(eps_hint / init_norm) / std::log(c->decay_ema))));
+  // an update run: the first chunk holds the sparse slots recent update runs
+  // needed.  (Enqueueing their predicted dense slots behind them as well, which
+  // the slot guards allow, cost more in idle launches whenever a run stayed
+  // sparse one slot longer than predicted than the host round trip it saved.)
+  rwr_ctx::Tune &tn0 = c->tune;
+  const bool update_run = mode == MODE_SPARSE && init_norm < 0.0 && c->built && !tn0.on;
+  const int sparse_end = 1 << 30;
+  if (update_run && c->update_runs >= 2) chunk = std::max(1, std::min(16, (int)std::lround(c->sparse_ema)));
   double prev = -1.0;
   int prev_iter = 0;
   int dense_launched = 0, dense_base = c->prof_used;
@@ -727,7 +740,7 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
     }
     const int kend = std::min(k + chunk, c->max_iters + 2);
     for (; k < kend; ++k) {
-      if (mode == MODE_DENSE) {
+      if (mode == MODE_DENSE || k >= sparse_end) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tn.on && tn.launched < tn.limit) {
           // a tuning launch: the next candidate shape, timed
@@ -790,6 +803,18 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
     prev_iter = h.iter;
   }
   if (c->prof_on) RWR_TRY(prof_collect(c, dense_base, dense_launched, c->ctl_h->dense_iters));
+  if (update_run) {
+    const Ctl &h = *c->ctl_h;
+    const int dense = h.dense_iters, sparse = std::max(0, h.iter - 1 - dense);
+    if (c->update_runs == 0) {
+      c->sparse_ema = sparse;
+      c->dense_ema = dense;
+    } else {
+      c->sparse_ema = 0.8 * c->sparse_ema + 0.2 * sparse;
+      c->dense_ema = 0.8 * c->dense_ema + 0.2 * dense;
+    }
+    ++c->update_runs;
+  }
   launch_finish(a, c->S, c->fp64, c->stream);
   return RWR_OK;
 }
@@ -805,22 +830,19 @@ static void account_run(rwr_ctx *c, bool reset) {
   const Ctl &h = *c->ctl_h;
   const int iters = std::max(0, h.iter - 1);
   c->last_iters = iters;
-  c->last_hist.assign((size_t)(iters + 1) * c->S, 0.0);
-  (void)hipMemcpyAsync(c->last_hist.data(), c->hist, sizeof(double) * c->last_hist.size(), hipMemcpyDeviceToHost,
-                 c->stream);
-  (void)hipStreamSynchronize(c->stream);
+  c->hist_host_valid = false;
   const double cc = c->cfg.c;
-  if (iters >= 3) {
-    // per-iteration decay between iteration 1 and the last one (column 0)
-    const double n1 = c->last_hist[(size_t)1 * c->S], nk = c->last_hist[(size_t)iters * c->S];
+  const int k0 = h.last_it[0];
+  if (k0 >= 3) {
+    // per-iteration decay between iteration 1 and column 0's last one
+    const double n1 = h.norm1[0], nk = h.last_norm[0];
     if (n1 > 0.0 && nk > 0.0) {
-      const double d = std::pow(nk / n1, 1.0 / (iters - 1));
+      const double d = std::pow(nk / n1, 1.0 / (k0 - 1));
       if (d > 0.2 && d < 0.99) c->decay_ema = 0.8 * c->decay_ema + 0.2 * d;
     }
   }
   for (int j = 0; j < c->n_seeds; ++j) {
-    double sum_norms = 0.0;
-    for (int i = 0; i <= iters; ++i) sum_norms += c->last_hist[(size_t)i * c->S + j];
+    const double sum_norms = h.sum_norm[j];
     const double sig = std::fabs(h.sigma[j]) > 0 ? std::fabs(h.sigma[j]) : 1.0;
     const double tail = 2.0 * (1.0 - cc) / cc * h.last_norm[j] / sig;
     const double rnd = 2.0 * fp32_factor(c) * sum_norms / (cc * sig);
@@ -874,7 +896,6 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
   launch_reset_run(c->ctl, c->S, mask, eps_ref, c->max_iters, dense_thresh(c), c->n / 16 + 1, c->stream);
   launch_refine_init(a, c->S, c->fp64, c->stream);
   RWR_TRY(run_slots(c, MODE_DENSE, resid * (1.0 - cc), eps_ref));
-  RWR_TRY(read_ctl(c));
   if (c->ctl_h->prop_err != 0) {
     c->stale = true;
     c->err = "refinement did not converge";
@@ -1121,7 +1142,7 @@ static void fill_stats(rwr_ctx *c, rwr_stats *st) {
   st->touched_rows = h.nT[0];
   double q = 0.0, lx = 0.0;
   for (int j = 0; j < c->n_seeds; ++j) {
-    if (!c->last_hist.empty()) q = std::max(q, c->last_hist[j]);
+    q = std::max(q, h.norm0[j]);
     lx = std::max(lx, h.last_norm[j]);
   }
   st->q_off_l1 = q;
@@ -1363,6 +1384,7 @@ rwr_status rwr_build(const rwr_config *cfg, int32_t n, int64_t m, const int32_t 
     rwr_destroy(c);
     return s;
   }
+  c->built = true;
   *out = c;
   return RWR_OK;
 }
@@ -1577,8 +1599,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   const bool warm = c->ws.alloc && c->ws.mode != 0 && nkeys > 0;
   if (warm) RWR_TRY(warm_prepare(c));
   launch_slot0_epilogue(a, c->S, c->fp64, c->stream);
-  RWR_TRY(run_slots(c, MODE_SPARSE));
-  RWR_TRY(read_ctl(c));
+  RWR_TRY(run_slots(c, MODE_SPARSE));  // leaves ctl_h at the run's final state
   account_run(c, false);
   fill_stats(c, st);
   if (st && warm) {
@@ -1678,6 +1699,14 @@ rwr_status rwr_graph_export(rwr_ctx *c, int32_t *src, int32_t *dst, int64_t cap,
 rwr_status rwr_last_norms(rwr_ctx *c, int32_t j, double *out, int32_t cap, int32_t *len) {
   if (!c || j < 0 || j >= c->n_seeds || !len) return RWR_EINVAL;
   const int32_t total = c->last_iters + 1;
+  if (!c->hist_host_valid) {
+    // the device history of the last run, copied on first request
+    c->last_hist.assign((size_t)total * c->S, 0.0);
+    HIP_TRY(c, hipMemcpyAsync(c->last_hist.data(), c->hist, sizeof(double) * c->last_hist.size(),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->hist_host_valid = true;
+  }
   const int32_t k = std::min(cap, total);
   for (int32_t i = 0; i < k && out; ++i) out[i] = c->last_hist[(size_t)i * c->S + j];
   *len = total;

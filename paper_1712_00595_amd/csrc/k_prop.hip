@@ -39,6 +39,15 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (RWR_WAVE - lane));
 }
 
+// A kernel of iteration slot k runs only while the run is in its phase and
+// at an iteration of k's parity: slots of both phases may then be enqueued
+// for the same k (exactly one of them runs; the kernels use k only through
+// its parity, so a slot enqueued for k runs correctly as any iteration of
+// that parity).
+__device__ __forceinline__ bool slot_live(const Ctl *ctl, int mode, int k) {
+  return ctl->mode == mode && ((ctl->iter ^ k) & 1) == 0;
+}
+
 // ------------------------------------------------------------------ partials
 // Partial-sum entry e: S columns x {norm, sum} at part[e * stride], two
 // counters at part_i[e * 16].  Entries are padded to at least 128 bytes.
@@ -112,8 +121,8 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
   __shared__ DecideShared sh;
   constexpr int NW = DECIDE_BLOCK / RWR_WAVE;
   Ctl *ctl = a.ctl;
-  if (kind == KIND_SPARSE && ctl->mode != MODE_SPARSE) return;
-  if (kind == KIND_DENSE && ctl->mode != MODE_DENSE) return;
+  if (kind == KIND_SPARSE && !slot_live(ctl, MODE_SPARSE, new_list)) return;
+  if (kind == KIND_DENSE && !slot_live(ctl, MODE_DENSE, new_list)) return;
   constexpr int TPC = DECIDE_BLOCK / S;
   const int t = threadIdx.x, j = t % S, q = t / S;
   const int lane = t % RWR_WAVE, w = t / RWR_WAVE;
@@ -188,6 +197,10 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
     if (act) {
       ctl->sigma[t] += su;
       ctl->last_norm[t] = nr;
+      ctl->last_it[t] = it;
+      ctl->sum_norm[t] += nr;
+      if (it == 0) ctl->norm0[t] = nr;
+      if (it == 1) ctl->norm1[t] = nr;
       if (!isfinite(nr) || !isfinite(su)) ctl->prop_err = ERR_ENUMERIC;
       if (it >= 1 && nr <= ctl->eps)
         ctl->active[t] = 0;
@@ -236,7 +249,7 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
 template <typename XT, int S, int G>
 __global__ __launch_bounds__(BLOCK) void k_push(SlotArgs a, int k) {
   Ctl *ctl = a.ctl;
-  if (ctl->mode != MODE_SPARSE) return;
+  if (!slot_live(ctl, MODE_SPARSE, k)) return;
   const int cur = (k - 1) & 1;
   const XT *__restrict__ xcur = (const XT *)a.x[cur];
   const int32_t st = ctl->stamp;
@@ -275,7 +288,7 @@ template <typename XT, int S>
 __global__ __launch_bounds__(BLOCK) void k_push_heavy(SlotArgs a, int k) {
   __shared__ int32_t s_base[HBASE_LDS];
   Ctl *ctl = a.ctl;
-  if (ctl->mode != MODE_SPARSE) return;
+  if (!slot_live(ctl, MODE_SPARSE, k)) return;
   const unsigned long long pk = ctl->hpack;
   const int nh = (int)(pk >> 32);
   const int total = (int)(pk & 0xffffffffull);
@@ -323,7 +336,7 @@ template <typename XT, int S>
 __global__ __launch_bounds__(BLOCK) void k_epi(SlotArgs a, int k, double scale, int first) {
   __shared__ BlockRed sh;
   Ctl *ctl = a.ctl;
-  if (ctl->mode != MODE_SPARSE) return;
+  if (!slot_live(ctl, MODE_SPARSE, k)) return;
   const int nw = k & 1, old = nw ^ 1;
   XT *__restrict__ xnew = (XT *)a.x[nw];
   XT *__restrict__ xold = (XT *)a.x[old];
@@ -445,7 +458,7 @@ __global__ __launch_bounds__(BLOCK) void k_pull(SlotArgs a, int k) {
   __shared__ BlockRed sh;
   __shared__ double hred[NWAVES][RWR_MAX_COLS];
   Ctl *ctl = a.ctl;
-  if (KIND == KIND_DENSE && ctl->mode != MODE_DENSE) return;
+  if (KIND == KIND_DENSE && !slot_live(ctl, MODE_DENSE, k)) return;
   const XT *__restrict__ xcur = (const XT *)a.x[(k - 1) & 1];
   XT *__restrict__ xnext = (XT *)a.x[k & 1];
   const double c1 = 1.0 - a.c;
@@ -679,7 +692,7 @@ __global__ __launch_bounds__(BLOCK) void k_pull_v(SlotArgs a, int k) {
   __shared__ BlockRed sh;
   __shared__ double hred[NWAVES][RWR_MAX_COLS];
   Ctl *ctl = a.ctl;
-  if (KIND == KIND_DENSE && ctl->mode != MODE_DENSE) return;
+  if (KIND == KIND_DENSE && !slot_live(ctl, MODE_DENSE, k)) return;
   const XT *__restrict__ xcur = (const XT *)a.x[(k - 1) & 1];
   XT *__restrict__ xnext = (XT *)a.x[k & 1];
   const double c1 = 1.0 - a.c;
@@ -827,7 +840,7 @@ __global__ __launch_bounds__(NWV * RWR_WAVE) void k_pull_wv(SlotArgs a, int k) {
   } U;
   __shared__ XT xc[CACHE > 0 ? CACHE : 1];
   Ctl *ctl = a.ctl;
-  if (KIND == KIND_DENSE && ctl->mode != MODE_DENSE) return;
+  if (KIND == KIND_DENSE && !slot_live(ctl, MODE_DENSE, k)) return;
   const XT *__restrict__ xcur = (const XT *)a.x[(k - 1) & 1];
   const int ncache = CACHE > 0 ? min(CACHE, a.n) : 0;
   if constexpr (CACHE > 0) {
@@ -1011,7 +1024,7 @@ template <typename XT, int S, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_heavy_epi(SlotArgs a, int k, int entry_base) {
   __shared__ BlockRed sh;
   Ctl *ctl = a.ctl;
-  if (KIND == KIND_DENSE && ctl->mode != MODE_DENSE) return;
+  if (KIND == KIND_DENSE && !slot_live(ctl, MODE_DENSE, k)) return;
   XT *__restrict__ xnext = (XT *)a.x[k & 1];
   const double c1 = 1.0 - a.c;
   const int j = threadIdx.x % S;
@@ -1120,6 +1133,10 @@ __global__ void k_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double ep
     const int a = (t < S) && ((active_mask >> t) & 1ull);
     ctl->active[t] = a;
     ctl->last_norm[t] = 0.0;
+    ctl->norm0[t] = 0.0;
+    ctl->norm1[t] = 0.0;
+    ctl->sum_norm[t] = 0.0;
+    ctl->last_it[t] = 0;
   }
   if (t == 0) {
     ctl->prop_err = 0;

@@ -66,6 +66,10 @@ struct Ctl {
   double last_norm[RWR_MAX_COLS]; // ||x^(iter)||_1 of each column when it stopped
   double red_norm[RWR_MAX_COLS];  // scratch: ||.||_1 of the current kernel
   double red_sum[RWR_MAX_COLS];   // scratch: signed sum of the current kernel
+  double norm0[RWR_MAX_COLS];     // ||x^(0)||_1 of this run
+  double norm1[RWR_MAX_COLS];     // ||x^(1)||_1 of this run
+  double sum_norm[RWR_MAX_COLS];  // sum over the run's iterations of ||x^(i)||_1
+  int32_t last_it[RWR_MAX_COLS];  // iteration of last_norm
 };
 
 // history of per-iteration norms: hist[i * S + j] = ||x^(i)[:, j]||_1
