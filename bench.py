@@ -44,6 +44,14 @@ def dense_sweep_bytes(n: int, m: int, S: int = 1) -> int:
     return 4 * (n + 1) + 4 * m + 4 * n + 4 * n * S + 4 * n * S + 16 * n * S
 
 
+def rank_accuracy(accuracy, got, ref) -> dict:
+    """Spearman's rank correlation and top-k overlaps of the scores against
+    the oracle's (the L1 distance is reported beside them)."""
+    out = accuracy.compare(got, ref, ks=(10, 100, 1000))
+    out.pop("l1")
+    return out
+
+
 def cpu_count_used() -> int:
     return 1
 
@@ -148,12 +156,16 @@ def run_batched_seeds(n_batches: int, check: bool = True) -> dict:
 
     t = time.time()
     n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream)
+    from paper_1712_00595_amd import accuracy
+
     cols = [0, 63]
-    errs = []
+    errs, ranks = [], []
     for j in cols:
         ref = oracle.rwr_static(n2, s2, d2, int(seeds[j]), w.c)
-        errs.append(float(np.abs(ctx.scores(j) - ref).sum()))
-    res["parity"] = {"columns": cols, "l1_vs_oracle": errs, "ok": max(errs) <= res["gate"],
+        got = ctx.scores(j)
+        errs.append(float(np.abs(got - ref).sum()))
+        ranks.append(rank_accuracy(accuracy, got, ref))
+    res["parity"] = {"columns": cols, "l1_vs_oracle": errs, "rank_accuracy": ranks, "ok": max(errs) <= res["gate"],
                      "oracle_s": time.time() - t}
     ctx.close()
     log(f"[{w.name}] {res['batches_per_s']:.2f} batches/s, {res['modifications_per_s']:.0f} modifications/s, "
@@ -218,12 +230,110 @@ def run_learned(n_train: int, n_eval: int, check: bool = True) -> dict:
             if name == "learned" and check:
                 import oracle
 
+                from paper_1712_00595_amd import accuracy
+
                 n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream)
-                errs = [float(np.abs(ctx.scores(j) - oracle.rwr_static(n2, s2, d2, int(seeds[j]), w.c)).sum())
-                        for j in (0, 15)]
-                r["parity"] = {"columns": [0, 15], "l1_vs_oracle": errs, "ok": max(errs) <= res["gate"]}
+                errs, ranks = [], []
+                for j in (0, 15):
+                    ref = oracle.rwr_static(n2, s2, d2, int(seeds[j]), w.c)
+                    got = ctx.scores(j)
+                    errs.append(float(np.abs(got - ref).sum()))
+                    ranks.append(rank_accuracy(accuracy, got, ref))
+                r["parity"] = {"columns": [0, 15], "l1_vs_oracle": errs, "rank_accuracy": ranks,
+                               "ok": max(errs) <= res["gate"]}
             res[name] = r
             log(f"[{w.name}] {name}: {r['updates_per_s']:.1f} updates/s, iters {r['mean_iters']:.2f}")
+    return res
+
+
+def run_delta_study(check: bool, per_group: int = 10) -> dict:
+    """Effects of Delta G (Section 3.3; the size and location experiments of
+    Section 4) on the scale-20 R-MAT graph, one seed, eps = 1e-9, FP32
+    propagation and no error-budget refinement (plain OSP-T, as measured in
+    the paper).  Location: nodes sorted by their RWR score in 100 equal
+    groups, `per_group` sampled nodes per group with at least one out-edge;
+    for each, one out-edge (u, v) is deleted (the measured update) and then
+    re-inserted.  Size: k uniform existing edges deleted in one batch for
+    k = 1 .. 1e5, then re-inserted.  Every update is checked against the
+    cost model: Theorem 2's iteration bound from ||q_offset||_1 and, before
+    propagation, from ||D r_old||_1."""
+    from paper_1712_00595_amd import accuracy, costmodel, rwr
+    from synth.configs import RMAT20_SINGLE_EDGE
+
+    w = RMAT20_SINGLE_EDGE
+    t0 = time.time()
+    g = w.graph()
+    seeds = w.seeds(g)
+    eps, c = 1e-9, w.c
+    log(f"[rmat20_delta_study] graph n={g.n} m={g.m} ({time.time() - t0:.1f}s)")
+    order = np.argsort(g.src, kind="stable")
+    dst_sorted = g.dst[order]
+    start = np.concatenate([[0], np.cumsum(np.bincount(g.src, minlength=g.n))])
+    rng = np.random.default_rng(4)
+    e32 = np.zeros(0, np.int32)
+
+    def within(st):
+        return (st["iters"] <= costmodel.iterations_bound(st["q_off_l1"], eps, c),
+                st["iters"] <= costmodel.iterations_bound_before(st["dr_l1"], eps, c))
+
+    res = {"graph": "directed R-MAT scale 20 (as the headline)", "c": c, "eps": eps, "refinement": "off"}
+    # location: groups of nodes by descending score
+    with rwr.Context(g.n, g.src, g.dst, seeds, c=c, eps=eps, precision="fp32", err_budget=1.0) as ctx:
+        score = ctx.scores(0)
+        by_score = np.argsort(-score, kind="stable")
+        groups = np.array_split(by_score, 100)
+        rows = []
+        for gi, grp in enumerate(groups):
+            cand = grp[start[grp + 1] > start[grp]]
+            pick = rng.choice(cand, size=min(per_group, cand.shape[0]), replace=False)
+            for u in pick:
+                u = int(u)
+                v = int(dst_sorted[start[u] + rng.integers(0, start[u + 1] - start[u])])
+                st = ctx.update(del_src=np.array([u], np.int32), del_dst=np.array([v], np.int32))
+                ctx.update(ins_src=np.array([u], np.int32), ins_dst=np.array([v], np.int32))
+                rows.append((gi, st["iters"], st["ms_total"], st["q_off_l1"], st["dr_l1"], st["visited_edges"],
+                             *within(st)))
+    R = np.array(rows, dtype=np.float64)
+    gmean = lambda col: [float(R[R[:, 0] == gi, col].mean()) for gi in range(100)]  # noqa: E731
+    mean_iters = gmean(1)
+    res["location"] = {
+        "groups": 100, "per_group": per_group, "updates": int(R.shape[0]),
+        "mean_iters": mean_iters, "mean_ms": gmean(2), "mean_q_off_l1": gmean(3), "mean_dr_l1": gmean(4),
+        "mean_visited_edges": gmean(5),
+        # rank correlation of the group's score rank with its iterations
+        # (negative: higher scores, more iterations)
+        "spearman_group_vs_iters": accuracy.spearman(np.arange(100), mean_iters),
+        "iters_within_bound_q": float(R[:, 6].mean()), "iters_within_bound_dr": float(R[:, 7].mean()),
+    }
+    log(f"[rmat20_delta_study] location: iters top group {mean_iters[0]:.1f}, bottom {mean_iters[-1]:.1f}")
+    # size: one batch of k deletions, then the same edges re-inserted
+    sizes = []
+    with rwr.Context(g.n, g.src, g.dst, seeds, c=c, eps=eps, precision="fp32", err_budget=1.0) as ctx:
+        for k in (1, 10, 100, 1000, 10000, 100000):
+            idx = rng.choice(g.m, size=k, replace=False)
+            ds, dd = g.src[idx].astype(np.int32), g.dst[idx].astype(np.int32)
+            st = ctx.update(del_src=ds, del_dst=dd)
+            row = {"k": k, "iters": st["iters"], "dense_iters": st["dense_iters"], "ms": st["ms_total"],
+                   "q_off_l1": st["q_off_l1"], "dr_l1": st["dr_l1"], "visited_edges": st["visited_edges"],
+                   "bound_q": costmodel.iterations_bound(st["q_off_l1"], eps, c),
+                   "bound_dr": costmodel.iterations_bound_before(st["dr_l1"], eps, c),
+                   "err_bound": st["err_bound"]}
+            if check:
+                import oracle
+
+                from synth.stream import Batch
+
+                b = Batch(ins_src=e32, ins_dst=e32, del_src=ds, del_dst=dd, n_new_nodes=0)
+                n2, s2, d2 = oracle.apply_batch(g.n, g.src, g.dst, b)
+                ref = oracle.rwr_static(n2, s2, d2, int(seeds[0]), c)
+                got = ctx.scores(0)
+                row["l1_vs_oracle"] = float(np.abs(got - ref).sum())
+                row["spearman"] = accuracy.spearman(got, ref)
+            sizes.append(row)
+            ctx.update(ins_src=ds, ins_dst=dd)
+            log(f"[rmat20_delta_study] size {k}: iters {row['iters']} (bounds {row['bound_q']}, {row['bound_dr']}), "
+                f"{row['ms']:.2f} ms")
+    res["size"] = sizes
     return res
 
 
@@ -298,10 +408,13 @@ def run_churn(n_batches: int, check: bool) -> dict:
         loop = lo == hi
         s2 = np.concatenate([lo, hi[~loop]]).astype(np.int32)
         d2 = np.concatenate([hi, lo[~loop]]).astype(np.int32)
+        from paper_1712_00595_amd import accuracy
+
         ref = oracle.rwr_static(pool.n, s2, d2, int(seeds[0]), w.c, tol=1e-12)
-        err = float(np.abs(ctx.scores(0) - ref).sum())
-        res["parity"] = {"columns": [0], "l1_vs_oracle": [err], "oracle_tol": 1e-12, "ok": err <= res["gate"],
-                         "oracle_s": time.time() - t}
+        got = ctx.scores(0)
+        err = float(np.abs(got - ref).sum())
+        res["parity"] = {"columns": [0], "l1_vs_oracle": [err], "rank_accuracy": [rank_accuracy(accuracy, got, ref)],
+                         "oracle_tol": 1e-12, "ok": err <= res["gate"], "oracle_s": time.time() - t}
     ctx.close()
     log(f"[{w.name}] {res['batches_per_s']:.3f} batches/s, {res['modifications_per_s']:.0f} modifications/s")
     return res
@@ -321,7 +434,7 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=3, help="updates timed on the CPU oracle")
     ap.add_argument("--workloads", default="",
                     help="extra workloads run after the headline, comma list of: rmat22_batched_seeds, "
-                         "rmat21_learned_warm_start, rmat23_undirected_churn")
+                         "rmat21_learned_warm_start, rmat23_undirected_churn, rmat20_delta_study")
     ap.add_argument("--batches", type=int, default=200, help="batches of the batched-seed workload")
     ap.add_argument("--churn-batches", type=int, default=10, help="batches of the undirected churn workload")
     ap.add_argument("--churn-check", action="store_true", help="check one column of the churn workload (slow)")
@@ -500,9 +613,12 @@ def main() -> int:
             t = time.time()
             # the final graph: the whole stream applied to the edge list
             n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream)
+            from paper_1712_00595_amd import accuracy
+
             ref = oracle.rwr_static(n2, s2, d2, int(seeds[0]), c)
             err = float(np.abs(final_ctx_scores - ref).sum())
             parity = {"l1_vs_oracle": err, "gate": H["gate"], "ok": err <= H["gate"],
+                      "rank_accuracy": rank_accuracy(accuracy, final_ctx_scores, ref),
                       "oracle_static_s": time.time() - t}
             log(f"parity: L1 {err:.3e} vs gate {H['gate']:.3e} ({time.time() - t:.1f}s)")
         if not args.no_cpu_baseline:
@@ -539,6 +655,8 @@ def main() -> int:
             extra[wname] = run_learned(args.learned_train, args.learned_eval, not args.no_check)
         elif wname == "rmat23_undirected_churn":
             extra[wname] = run_churn(args.churn_batches, args.churn_check)
+        elif wname == "rmat20_delta_study":
+            extra[wname] = run_delta_study(not args.no_check)
         else:
             raise SystemExit(f"unknown workload {wname}")
 

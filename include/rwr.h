@@ -113,6 +113,10 @@ typedef struct rwr_stats {
   double ws_resid_ratio;  /* sum_j ||rho_j||_1 / sum_j ||q_j||_1 of the prediction          */
   double ws_loss;         /* training loss of this update, mean_j ||rho_j|| / ||q_j||      */
   double ms_warm;         /* host wall time of the warm-start steps                        */
+  /* cost model of the batch (Section 3.3, effects of Delta G): ||D r_old||_1 with
+     D_uu = sum_v |B~[u,v] - A~[u,v]| (row L1 norm of the change of u's row), an
+     upper bound of ||q_offset||_1 / (1-c) known before propagation          */
+  double dr_l1;
 } rwr_stats;
 
 /* Fill *cfg with defaults: c = 0.15, eps = 1e-9, FP32 propagation, directed,

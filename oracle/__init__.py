@@ -16,6 +16,8 @@ Contents
   * ``apply_batch``  the graph G + Delta G of a batch, by plain set
                       operations on edge keys (Section 3.4.1 for new nodes)
   * ``apply_stream`` the same for a sequence of batches, in one pass
+  * ``delta_weight`` ||D r_old||_1 of the effects of Delta G (Section 3.3),
+                      the bound of ||q_offset||_1 / (1-c) before propagation
 """
 
 from .core import (  # noqa: F401
@@ -24,6 +26,7 @@ from .core import (  # noqa: F401
     apply_stream,
     cpi,
     dead_end_reachable,
+    delta_weight,
     lib,
     osp,
     rwr_dense,

@@ -163,6 +163,32 @@ def rwr_dense(n, src, dst, seed, c) -> np.ndarray:
     return r
 
 
+def delta_weight(old, new, r_old) -> float:
+    """||D r_old||_1 of the section on the effects of Delta G (Section 3.3):
+    D is diagonal with D_uu = sum_v |B~[u,v] - A~[u,v]|, the L1 norm of the
+    change of u's row of the row-normalised adjacency, so that
+    ||q_offset||_1 <= (1-c) ||D r_old||_1.  Old rows are padded to the new
+    node count as empty rows, r_old with zeros.  Plain definition with scipy
+    sparse matrices (no reuse of the update arithmetic).  Parity pinned by
+    closed forms for single-edge edits and by the inequality above."""
+    import scipy.sparse as sp
+
+    n0, s0, d0 = old
+    n1, s1, d1 = new
+
+    def normalised(n, s, d):
+        s = np.asarray(s, dtype=np.int64)
+        d = np.asarray(d, dtype=np.int64)
+        deg = np.bincount(s, minlength=n).astype(np.float64)
+        return sp.csr_matrix((1.0 / deg[s], (s, d)), shape=(n1, n1))
+
+    delta = normalised(n1, s1, d1) - normalised(n0, s0, d0)
+    D = np.asarray(abs(delta).sum(axis=1)).ravel()
+    r = np.zeros(n1, dtype=np.float64)
+    r[:n0] = np.abs(_f64(r_old))
+    return float(D @ r)
+
+
 KEY = np.int64(1) << np.int64(32)
 
 

@@ -1147,6 +1147,9 @@ static void fill_stats(rwr_ctx *c, rwr_stats *st) {
   }
   st->q_off_l1 = q;
   st->last_x_l1 = lx;
+  double dr = 0.0;
+  for (int j = 0; j < c->n_seeds; ++j) dr = std::max(dr, h.dr_l1[j]);
+  st->dr_l1 = dr;
 }
 
 // ------------------------------------------------------------------ ABI

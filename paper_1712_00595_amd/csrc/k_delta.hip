@@ -411,6 +411,18 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
       if (j == 0 && (del || d_new != d_old)) stamp[v] = st;
     }
     if (k != 0) continue;
+    if (p == 0) {
+      // cost model: D_uu |r_old(u)|, D_uu = sum_v |B~[u,v] - A~[u,v]| =
+      // kept |1/d_new - 1/d_old| + inserted / d_new + deleted / d_old
+      int32_t n_ins = 0;
+      for (int32_t i = b; i < e; ++i) n_ins += (int32_t)(keys[i] & 1ull);
+      const int32_t n_del = (e - b) - n_ins, kept = d_old - n_del;
+      double du = 0.0;
+      if (d_old > 0 && d_new > 0) du += kept * fabs(1.0 / d_new - 1.0 / d_old);
+      if (d_new > 0) du += n_ins / (double)d_new;
+      if (d_old > 0) du += n_del / (double)d_old;
+      atomic_add_f64(&ctl->dr_l1[j], du * fabs(ru));
+    }
     for (int32_t i = b + p; i < e; i += P) {
       const uint64_t kk = keys[i];
       if (!(kk & 1ull)) continue;
@@ -491,7 +503,10 @@ __global__ void k_reset_batch(Ctl *ctl, int demand_only) {
   ctl->demand[0] = 0;
   ctl->demand[1] = 0;
   ctl->heavy_stale = 0;
-  if (!demand_only) ctl->node_dels = 0;
+  if (!demand_only) {
+    ctl->node_dels = 0;
+    for (int j = 0; j < RWR_MAX_COLS; ++j) ctl->dr_l1[j] = 0.0;
+  }
 }
 
 // ------------------------------------------------- host launchers

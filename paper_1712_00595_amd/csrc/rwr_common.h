@@ -70,6 +70,7 @@ struct Ctl {
   double norm1[RWR_MAX_COLS];     // ||x^(1)||_1 of this run
   double sum_norm[RWR_MAX_COLS];  // sum over the run's iterations of ||x^(i)||_1
   int32_t last_it[RWR_MAX_COLS];  // iteration of last_norm
+  double dr_l1[RWR_MAX_COLS];     // ||D r_old||_1 of the batch (D: row L1 norms of B~ - A~)
 };
 
 // history of per-iteration norms: hist[i * S + j] = ||x^(i)[:, j]||_1

@@ -108,6 +108,7 @@ class StatsStruct(ctypes.Structure):
         ("ws_resid_ratio", ctypes.c_double),
         ("ws_loss", ctypes.c_double),
         ("ms_warm", ctypes.c_double),
+        ("dr_l1", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

@@ -1,0 +1,64 @@
+"""The cost-model statistic of an update on the GPU (effects of Delta G,
+Section 3.3): the library's ||D r_old||_1 against the oracle's plain
+definition, the bound ||q_offset||_1 <= (1-c) ||D r_old||_1, and the
+iteration bounds of Theorem 2 — for edge batches with new nodes, a change at
+the largest hub, a node deletion, and an undirected graph."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_00595_amd import costmodel
+from synth import EdgeSetModel, rmat_graph
+from synth.rmat import sample_seeds
+from synth.stream import Batch, mixed_batch
+
+pytestmark = pytest.mark.gpu
+
+rwr = pytest.importorskip("paper_1712_00595_amd.rwr")
+
+C = 0.15
+EPS = 1e-12
+
+
+def _batches(g, undirected):
+    es, ed = (g.pair_u, g.pair_v) if undirected else (g.src, g.dst)
+    model = EdgeSetModel(g.n, es, ed, undirected=undirected)
+    rng = np.random.default_rng(7)
+    out = [mixed_batch(rng, model, 40, 40, n_new_nodes=2), mixed_batch(rng, model, 1, 0)]
+    # one deletion at the largest hub
+    hub = int(np.argmax(g.out_degree()))
+    v = int(g.dst[np.flatnonzero(g.src == hub)[0]])
+    E = np.zeros(0, np.int32)
+    if not undirected:
+        out.append(Batch(E, E, np.array([hub], np.int32), np.array([v], np.int32), 0))
+        # a node deletion (last: it leaves a dead end, and the scores are
+        # compared before the batch with sum 1)
+        out.append(Batch(E, E, E, E, 0, np.array([int(np.argsort(-g.out_degree())[10])], np.int32)))
+    return out
+
+
+@pytest.mark.parametrize("n_seeds,undirected", [(1, False), (3, False), (2, True)])
+def test_delta_weight_matches_oracle(n_seeds, undirected):
+    print(f"[cost model] seeds={n_seeds} undirected={undirected}", flush=True)
+    g = rmat_graph(11, 20000, dead_end_self_loops=not undirected, undirected=undirected)
+    seeds = sample_seeds(g, n_seeds, seed=3)
+    es, ed = (g.pair_u, g.pair_v) if undirected else (g.src, g.dst)
+    kw = dict(c=C, eps=EPS, precision="fp64", build_tol=1e-13, err_budget=1e-11, undirected=undirected)
+    with rwr.Context(g.n, es, ed, seeds, **kw) as ctx:
+        n, s, d = g.n, g.src, g.dst
+        for b in _batches(g, undirected):
+            # the library propagates the unnormalised scores (CPI from c e_s)
+            before = []
+            for sd in seeds:
+                q = np.zeros(n)
+                q[int(sd)] = C
+                before.append(oracle.cpi(n, s, d, q, C, 1e-15)[0])
+            st = ctx.update_batch(b)
+            n2, s2, d2 = oracle.apply_batch(n, s, d, b, undirected=undirected)
+            dw = max(oracle.delta_weight((n, s, d), (n2, s2, d2), r) for r in before)
+            assert st["dr_l1"] == pytest.approx(dw, rel=1e-8), (st["dr_l1"], dw)
+            assert st["q_off_l1"] <= (1 - C) * st["dr_l1"] * (1 + 1e-9)
+            assert st["iters"] <= costmodel.iterations_bound(st["q_off_l1"], EPS, C)
+            assert st["iters"] <= costmodel.iterations_bound_before(st["dr_l1"], EPS, C)
+            n, s, d = n2, s2, d2

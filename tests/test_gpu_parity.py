@@ -475,7 +475,14 @@ def test_full_size_single_edge_stream():
         assert max(s["err_bound"] for s in stats) <= 2e-9 / w.c
         n, s, d = oracle.apply_stream(g.n, g.src, g.dst, stream)
         ref = oracle.rwr_static(n, s, d, int(seeds[0]), w.c)
-        assert _l1(ctx.scores(0), ref) <= 2e-9 / w.c
+        got = ctx.scores(0)
+        assert _l1(got, ref) <= 2e-9 / w.c
+        # rank accuracy (the experiments' second metric): Spearman and top-k
+        from paper_1712_00595_amd import accuracy
+
+        acc = accuracy.compare(got, ref, ks=(10, 100, 1000))
+        print(acc, flush=True)
+        assert acc["spearman"] > 0.9999 and acc["top100_overlap"] >= 0.99, acc
 
 
 @pytest.mark.slow
