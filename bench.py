@@ -426,7 +426,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--modes", default="eps1e-9",
-                    help="comma list of: eps1e-9 (headline), eps1e-6, exact; or all")
+                    help="comma list of: eps1e-9 (headline), eps1e-6, exact, pagerank; or all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the final oracle comparison")
     ap.add_argument("--no-host-batches", action="store_true",
@@ -493,6 +493,8 @@ def main() -> int:
         # exact: the certified budget is the 1e-9 gate itself; eps is chosen so
         # one update's truncation bound is a tenth of it
         "exact": dict(eps=1e-9 * c / (20 * (1 - c)), err_budget=1e-9, gate=1e-9),
+        # global PageRank: the uniform restart vector instead of the seed node
+        "pagerank": dict(eps=1e-9, err_budget=0.0, gate=2 * 1e-9 / c, q="uniform"),
     }
     names = list(all_modes) if args.modes == "all" else args.modes.split(",")
     headline = names[0]
@@ -515,8 +517,12 @@ def main() -> int:
     def run(name, host_batches=False, profile=False):
         mcfg = all_modes[name]
         t = time.time()
-        ctx = rwr.Context(g.n, g.src, g.dst, seeds, c=c, eps=mcfg["eps"], err_budget=mcfg["err_budget"],
-                          precision="fp32")
+        if mcfg.get("q") == "uniform":
+            ctx = rwr.Context(g.n, g.src, g.dst, q=np.full(g.n, 1.0 / g.n), c=c, eps=mcfg["eps"],
+                              err_budget=mcfg["err_budget"], precision="fp32")
+        else:
+            ctx = rwr.Context(g.n, g.src, g.dst, seeds, c=c, eps=mcfg["eps"], err_budget=mcfg["err_budget"],
+                              precision="fp32")
         log(f"[{name}{' host batches' if host_batches else ''}] context built in {time.time() - t:.2f}s")
         for b in stream[:W]:
             ctx.update_batch(b)
@@ -555,6 +561,18 @@ def main() -> int:
             "gate": mcfg["gate"],
             "visited_edges_per_update": float(np.mean([s["visited_edges"] for s in stats])),
         }
+        if mcfg.get("q") == "uniform" and not args.no_check:
+            import oracle
+            from paper_1712_00595_amd import accuracy
+
+            n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream[:W + K])
+            qp = np.zeros(n2)
+            qp[: g.n] = 1.0 / g.n  # nodes added by the stream restart with probability 0
+            ref = oracle.rwr_static_vector(n2, s2, d2, qp, c)
+            got = ctx.scores(0)
+            err = float(np.abs(got - ref).sum())
+            res["parity"] = {"l1_vs_oracle": err, "ok": err <= mcfg["gate"],
+                             "rank_accuracy": rank_accuracy(accuracy, got, ref)}
         if name == headline:
             res["prof"] = prof
             src_e, dst_e, _ = ctx.export()

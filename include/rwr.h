@@ -135,6 +135,21 @@ rwr_status rwr_config_default(rwr_config *cfg);
 rwr_status rwr_build(const rwr_config *cfg, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                      int32_t n_seeds, const int32_t *seeds, int32_t edges_on_device, rwr_ctx **out);
 
+/* Build a context whose columns restart to general seed vectors instead of
+ * seed nodes: column j solves r_j = (1-c) A~^T r_j + c q_j (Eq. (1) with the
+ * restart vector q_j in place of e_s; q_j = 1/n everywhere is global
+ * PageRank), by cumulative power iteration from c*q_j (Section 2.2).  q is a
+ * HOST array of n * n_cols doubles, node-major (q[v * n_cols + j]), copied;
+ * every column must be nonnegative, finite and sum to 1 within 1e-9
+ * (RWR_EINVAL otherwise).  Updates (rwr_update) propagate offsets exactly as
+ * for seed nodes (the offset seed does not depend on q); the residual checks
+ * use the full restart term c q.  q stays fixed: nodes added later have
+ * q = 0, a deleted node keeps its entry.  The learned warm start is not
+ * available on such a context (RWR_ESTATE).  Other arguments and ownership
+ * as rwr_build. */
+rwr_status rwr_build_vectors(const rwr_config *cfg, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                             int32_t n_cols, const double *q, int32_t edges_on_device, rwr_ctx **out);
+
 /* Apply one batch and update the scores (Algorithm 1): delta-apply on the
  * device graph, offset seed q_offset = (1-c)(B~^T - A~^T) r_old, cumulative
  * propagation on the new graph until ||x^(i)||_1 <= eps, merge into r, and

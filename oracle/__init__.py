@@ -10,6 +10,8 @@ Contents
                       1e-14 in FP64, then Theorem 4's dead-end normalisation
                       (C, single-threaded; ``rwr_oracle.c``)
   * ``cpi``          cumulative power iteration for any seed vector
+  * ``rwr_static_vector`` static scores for a general restart vector q
+                      (global PageRank for q = 1/n), Theorem 4 as above
   * ``osp``          one OSP / OSP-T update, Section 3.1 / Algorithm 1
   * ``rwr_dense``    the same static RWR by a dense LU solve of
                       (I - (1-c) A~^T) r = c e_s (numpy / LAPACK), n <= ~2000
@@ -31,5 +33,7 @@ from .core import (  # noqa: F401
     osp,
     rwr_dense,
     rwr_static,
+    rwr_static_vector,
+    reachable_from,
     row_normalised_dense,
 )

@@ -163,6 +163,40 @@ def rwr_dense(n, src, dst, seed, c) -> np.ndarray:
     return r
 
 
+def reachable_from(n, src, dst, sources) -> np.ndarray:
+    """Boolean mask of the nodes reachable from any node in ``sources``
+    (breadth-first over out-edges, plain numpy)."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    order = np.argsort(src, kind="stable")
+    dsorted = dst[order]
+    start = np.concatenate([[0], np.cumsum(np.bincount(src, minlength=n))])
+    seen = np.zeros(n, dtype=bool)
+    front = np.unique(np.asarray(sources, dtype=np.int64))
+    seen[front] = True
+    while front.shape[0]:
+        lens = start[front + 1] - start[front]
+        idx = np.repeat(start[front], lens) + (np.arange(lens.sum()) - np.repeat(np.cumsum(lens) - lens, lens))
+        nxt = np.unique(dsorted[idx])
+        nxt = nxt[~seen[nxt]]
+        seen[nxt] = True
+        front = nxt
+    return seen
+
+
+def rwr_static_vector(n, src, dst, q, c, tol=STATIC_TOL, max_iter=STATIC_MAX_ITERS):
+    """Static scores for a general restart vector q (Eq. (1) with q in place
+    of e_s; q = 1/n is global PageRank): CPI of Section 2.2 from c q, then
+    Theorem 4's normalisation when a dead end is reachable from the support
+    of q."""
+    q = _f64(q)
+    r, _ = cpi(n, src, dst, c * q, c, tol, max_iter)
+    deg = np.bincount(np.asarray(src, dtype=np.int64), minlength=n)
+    if np.any(reachable_from(n, src, dst, np.flatnonzero(q != 0.0)) & (deg == 0)):
+        r = r / r.sum()
+    return r
+
+
 def delta_weight(old, new, r_old) -> float:
     """||D r_old||_1 of the section on the effects of Delta G (Section 3.3):
     D is diagonal with D_uu = sum_v |B~[u,v] - A~[u,v]|, the L1 norm of the

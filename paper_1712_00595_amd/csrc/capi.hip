@@ -63,6 +63,8 @@ struct rwr_ctx {
   Orientation g[2];
   double *r = nullptr, *ybuf = nullptr, *gbuf = nullptr;
   double *xres = nullptr;  // r / d_out, gathered by the residual sweep
+  double *qvec = nullptr;  // seed vectors in internal ids (node-major), when built from vectors
+  bool qmode = false;
   void *x[2] = {nullptr, nullptr};
   int32_t *stamp = nullptr;
   int32_t *fstamp = nullptr;
@@ -303,7 +305,8 @@ static SlotArgs slot_args(const rwr_ctx *c) {
   a.grid_pull = c->grid_pull;
   a.light_lanes = c->light_lanes;
   a.pull_lanes = c->pull_lanes;
-  a.zero_seed_rows = 1;
+  a.zero_seed_rows = c->qmode ? 0 : 1;
+  a.qvec = c->qvec;
   a.row_order = c->row_order;
   a.n_order = c->n_cap;
   a.mp_rows = c->mp_rows;
@@ -525,6 +528,7 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
   RWR_TRY(regrow((void **)&c->ybuf, 8, c->S));
   RWR_TRY(regrow((void **)&c->gbuf, 8, c->S));
   RWR_TRY(regrow((void **)&c->xres, 8, c->S));
+  if (c->qmode) RWR_TRY(regrow((void **)&c->qvec, 8, c->S));
   RWR_TRY(regrow(&c->x[0], xs, c->S));
   RWR_TRY(regrow(&c->x[1], xs, c->S));
   RWR_TRY(regrow((void **)&c->stamp, 4, 1));
@@ -1173,7 +1177,7 @@ rwr_status rwr_config_default(rwr_config *cfg) {
 }
 
 static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                             int32_t n_seeds, const int32_t *seeds, int32_t on_device) {
+                             int32_t n_seeds, const int32_t *seeds, int32_t on_device, const double *q = nullptr) {
   HIP_TRY(c, hipGetDevice(&c->device));
   HIP_TRY(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
   if (c->cfg.stream) {
@@ -1190,7 +1194,8 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   c->n_seeds = n_seeds;
   c->S = next_pow2_cols(n_seeds);
   c->budget = c->cfg.err_budget > 0 ? c->cfg.err_budget : 2.0 * c->cfg.eps / c->cfg.c;
-  c->seeds_h.assign(seeds, seeds + n_seeds);
+  c->qmode = q != nullptr;
+  if (seeds) c->seeds_h.assign(seeds, seeds + n_seeds);
   tune_defaults(c);
 
   HIP_TRY(c, hipHostMalloc((void **)&c->ctl_h, sizeof(Ctl), hipHostMallocDefault));
@@ -1280,7 +1285,17 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   if (s == RWR_OK && !c->undirected) s = build_orient(c, 1, mdst, msrc, m2);
   (void)hipFree(msrc);
   (void)hipFree(mdst);
-  {
+  if (s == RWR_OK && c->qmode) {
+    // seed vectors in internal ids (no seed nodes)
+    launch_fill_i32(c->seeds_d, RWR_MAX_COLS, -1, c->stream);
+    std::vector<int32_t> perm(n);
+    D2H(c, perm.data(), c->perm, sizeof(int32_t) * n);
+    std::vector<double> qi((size_t)c->n_cap * c->S, 0.0);
+    for (int32_t v = 0; v < n; ++v)
+      for (int32_t j = 0; j < n_seeds; ++j) qi[(size_t)perm[v] * c->S + j] = q[(size_t)v * n_seeds + j];
+    RWR_TRY(dev_alloc(c, (void **)&c->qvec, sizeof(double) * qi.size()));
+    H2D(c, c->qvec, qi.data(), sizeof(double) * qi.size());
+  } else if (s == RWR_OK) {
     // seeds in internal ids
     int32_t *tmp = nullptr;
     RWR_TRY(dev_alloc(c, (void **)&tmp, sizeof(int32_t) * RWR_MAX_COLS));
@@ -1333,7 +1348,10 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   const SlotArgs a = slot_args(c);
   launch_reset_run(c->ctl, c->S, all_cols_mask(n_seeds), eps0, c->max_iters, dense_thresh(c), c->n / 16 + 1,
                    c->stream);
-  launch_seed_init(a, c->S, c->stream);
+  if (c->qmode)
+    launch_seed_init_q(a, c->S, c->stream);
+  else
+    launch_seed_init(a, c->S, c->stream);
   launch_slot0_epilogue(a, c->S, c->fp64, c->stream);
   RWR_TRY(run_slots(c, MODE_SPARSE));
   RWR_TRY(read_ctl(c));
@@ -1382,6 +1400,46 @@ rwr_status rwr_build(const rwr_config *cfg, int32_t n, int64_t m, const int32_t 
   rwr_ctx *c = new rwr_ctx();
   c->cfg = cf;
   rwr_status s = build_impl(c, n, m, src, dst, n_seeds, seeds, edges_on_device);
+  if (s != RWR_OK) {
+    g_build_error = c->err;
+    rwr_destroy(c);
+    return s;
+  }
+  c->built = true;
+  *out = c;
+  return RWR_OK;
+}
+
+rwr_status rwr_build_vectors(const rwr_config *cfg, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                             int32_t n_cols, const double *q, int32_t edges_on_device, rwr_ctx **out) {
+  if (!out) return RWR_EINVAL;
+  *out = nullptr;
+  rwr_config def;
+  rwr_config_default(&def);
+  const rwr_config &cf = cfg ? *cfg : def;
+  if (n <= 0 || m < 0 || (m > 0 && (!src || !dst)) || n_cols < 1 || n_cols > RWR_MAX_COLS || !q ||
+      !(cf.c > 0.0 && cf.c < 1.0) || !(cf.eps > 0.0) || n >= INT32_MAX - 1024) {
+    g_build_error = "invalid argument";
+    return RWR_EINVAL;
+  }
+  for (int32_t j = 0; j < n_cols; ++j) {
+    double sum = 0.0;
+    for (int32_t v = 0; v < n; ++v) {
+      const double x = q[(size_t)v * n_cols + j];
+      if (!(x >= 0.0) || !std::isfinite(x)) {
+        g_build_error = "seed vector entry negative or not finite";
+        return RWR_EINVAL;
+      }
+      sum += x;
+    }
+    if (std::fabs(sum - 1.0) > 1e-9) {
+      g_build_error = "seed vector does not sum to 1";
+      return RWR_EINVAL;
+    }
+  }
+  rwr_ctx *c = new rwr_ctx();
+  c->cfg = cf;
+  rwr_status s = build_impl(c, n, m, src, dst, n_cols, nullptr, edges_on_device, q);
   if (s != RWR_OK) {
     g_build_error = c->err;
     rwr_destroy(c);
@@ -1732,6 +1790,7 @@ void rwr_destroy(rwr_ctx *c) {
   dev_free(c->ybuf);
   dev_free(c->gbuf);
   dev_free(c->xres);
+  dev_free(c->qvec);
   dev_free(c->x[0]);
   dev_free(c->x[1]);
   dev_free(c->stamp);
@@ -1819,6 +1878,10 @@ rwr_status rwr_warm_start(rwr_ctx *c, int32_t mode, int32_t hops, int64_t max_ro
   if (mode == 0) {
     c->ws.mode = 0;
     return RWR_OK;
+  }
+  if (c->qmode) {
+    c->err = "the learned warm start needs seed nodes (its features mark them)";
+    return RWR_ESTATE;
   }
   const int64_t rows = max_rows > 0 ? max_rows : ((int64_t)1 << 21);
   if (c->ws.alloc && rows != c->ws.max_rows) {

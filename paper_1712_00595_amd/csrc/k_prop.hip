@@ -1040,6 +1040,26 @@ __global__ __launch_bounds__(BLOCK) void k_heavy_epi(SlotArgs a, int k, int entr
   block_publish<S>(nrm, sm, 0, 0, a.part, a.part_i, entry_base + blockIdx.x, sh);
 }
 
+// Restart term of seed vectors after a residual sweep: g += c q on every
+// node, then the workgroup's partial sums of ||g||_1 and of r (they replace
+// the sweep's own partials).  The seed-vector columns have no seed rows, so
+// the sweep left g = P r - r everywhere.
+template <int S>
+__global__ __launch_bounds__(BLOCK) void k_resid_q(SlotArgs a) {
+  __shared__ BlockRed sh;
+  const int j = threadIdx.x % S;
+  constexpr int NPB = BLOCK / S;
+  double nrm = 0.0, sm = 0.0;
+  for (int v = blockIdx.x * NPB + threadIdx.x / S; v < a.n; v += gridDim.x * NPB) {
+    const int64_t kk = col_index(v, S, j);
+    const double g = j < a.n_seeds ? a.gbuf[kk] + a.c * a.qvec[kk] : 0.0;
+    a.gbuf[kk] = g;
+    nrm += fabs(g);
+    sm += a.r[kk];
+  }
+  block_publish<S>(nrm, sm, 0, 0, a.part, a.part_i, blockIdx.x, sh);
+}
+
 // input of the residual sweep: xres = r / d_out (0 for a node without
 // out-edges), so that its gathers read one value per in-edge
 template <int S>
@@ -1218,6 +1238,24 @@ void launch_seed_init(const SlotArgs &a, int S, hipStream_t st) {
   RWR_DISPATCH_S(S, hipLaunchKernelGGL(k_seed_init<SS>, dim3(1), dim3(64), 0, st, a));
 }
 
+// x^(0) = c q for seed vectors (Section 2.2 with a general restart vector)
+template <int S>
+__global__ __launch_bounds__(BLOCK) void k_seed_init_q(SlotArgs a) {
+  const int32_t st = a.ctl->stamp;
+  const int64_t total = (int64_t)a.n * S;
+  for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < total; i += (int64_t)gridDim.x * BLOCK) {
+    const double y = a.c * a.qvec[i];
+    if (y != 0.0) {
+      a.ybuf[i] = y;
+      a.stamp[i / S] = st;
+    }
+  }
+}
+
+void launch_seed_init_q(const SlotArgs &a, int S, hipStream_t st) {
+  RWR_DISPATCH_S(S, hipLaunchKernelGGL(k_seed_init_q<SS>, dim3(a.grid_light), dim3(BLOCK), 0, st, a));
+}
+
 template <typename XT, int S>
 static void slot0_impl(const SlotArgs &a, hipStream_t st) {
   hipLaunchKernelGGL((k_epi<XT, S>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, 0, 1.0, 1);
@@ -1263,6 +1301,19 @@ static void pull_impl(const SlotArgs &a, int k, hipStream_t st, hipEvent_t ev0 =
     }
   }
   if (ev1) (void)hipEventRecord(ev1, st);
+  if constexpr (KIND == KIND_RESID) {
+    if (decide && a.qvec) {
+      // seed vectors: heavy rows, then the restart term c q with the
+      // residual's partial sums, then the decision over those partials
+      if (a.heavy.n_rows > 0) {
+        const int hg = std::max(1, std::min((a.heavy.n_rows * S + BLOCK - 1) / BLOCK, 256));
+        hipLaunchKernelGGL((k_heavy_epi<XT, S, KIND>), dim3(hg), dim3(BLOCK), 0, st, a, k, grid);
+      }
+      hipLaunchKernelGGL(k_resid_q<S>, dim3(a.grid_light), dim3(BLOCK), 0, st, a);
+      decide_impl<S, XT>(a, KIND, a.grid_light, k & 1, st, 0);
+      return;
+    }
+  }
   // few heavy rows: the decision kernel finishes them (one launch less)
   const bool fold = decide && (int64_t)a.heavy.n_rows * S <= HEAVY_FOLD;
   int hgrid = 0;

@@ -62,6 +62,8 @@ struct SlotArgs {
   int32_t light_lanes;  // lanes per row of the light push
   int32_t pull_lanes;   // lanes per in-row of the dense sweep for S >= 4 (16, 32 or 64)
   int32_t zero_seed_rows;   // residual sweep: 1 zeroes the seed row of each column (the restart term)
+  const double *qvec;       // seed vectors (node-major, S per node) or null; when set, the residual
+                            // check adds their restart term c q after the sweep
   const int32_t *row_order;  // order of the in-rows in that sweep (a permutation of 0 .. n_cap-1)
   int32_t n_order;           // its length (n_cap)
   const int32_t *mp_rows;  // row partition of the single-column dense sweep
@@ -110,6 +112,7 @@ void launch_apply(const uint64_t *keys, const int32_t *seg, const int32_t *row, 
 void launch_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double eps, int32_t max_iters, int64_t dense_thresh,
                       int64_t dense_nodes, hipStream_t st);
 void launch_seed_init(const SlotArgs &a, int S, hipStream_t st);
+void launch_seed_init_q(const SlotArgs &a, int S, hipStream_t st);
 void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st);
 // iteration slot k (computes x^(k)): sparse = push + epilogue, dense = pull
 void launch_sparse_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t st);

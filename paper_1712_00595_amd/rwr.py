@@ -33,6 +33,7 @@ STATUS = {
 EXPORTED = [
     "rwr_config_default",
     "rwr_build",
+    "rwr_build_vectors",
     "rwr_update",
     "rwr_refine",
     "rwr_scores",
@@ -129,6 +130,7 @@ def load_library(path: str = LIB_PATH):
     p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     L.rwr_config_default.argtypes = [ctypes.POINTER(Config)]
     L.rwr_build.argtypes = [ctypes.POINTER(Config), i32, i64, p, p, i32, p, i32, ctypes.POINTER(p)]
+    L.rwr_build_vectors.argtypes = [ctypes.POINTER(Config), i32, i64, p, p, i32, p, i32, ctypes.POINTER(p)]
     L.rwr_update.argtypes = [p, ctypes.POINTER(BatchStruct), ctypes.POINTER(StatsStruct)]
     L.rwr_refine.argtypes = [p, ctypes.POINTER(StatsStruct)]
     L.rwr_scores.argtypes = [p, i32, p, i64, i32]
@@ -206,8 +208,9 @@ class Context:
         n: int,
         src,
         dst,
-        seeds,
+        seeds=None,
         *,
+        q=None,
         c: float = 0.15,
         eps: float = 1e-9,
         err_budget: float = 0.0,
@@ -238,12 +241,24 @@ class Context:
         on_dev = _is_torch(src)
         s = _Arr(src, on_dev)
         d = _Arr(dst, on_dev)
-        sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.int32))
         out = ctypes.c_void_p(None)
-        code = self._lib.rwr_build(
-            ctypes.byref(cfg), int(n), s.n, s.ptr, d.ptr, int(sd.shape[0]), sd.ctypes.data, 1 if on_dev else 0,
-            ctypes.byref(out),
-        )
+        if q is not None:
+            # seed vectors: n x S (or n) restart distributions, each summing to 1
+            qa = np.asarray(q, dtype=np.float64)
+            if qa.ndim == 1:
+                qa = qa[:, None]
+            qa = np.ascontiguousarray(qa)
+            code = self._lib.rwr_build_vectors(
+                ctypes.byref(cfg), int(n), s.n, s.ptr, d.ptr, int(qa.shape[1]), qa.ctypes.data, 1 if on_dev else 0,
+                ctypes.byref(out),
+            )
+            sd = np.full(qa.shape[1], -1, np.int32)
+        else:
+            sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.int32))
+            code = self._lib.rwr_build(
+                ctypes.byref(cfg), int(n), s.n, s.ptr, d.ptr, int(sd.shape[0]), sd.ctypes.data, 1 if on_dev else 0,
+                ctypes.byref(out),
+            )
         _check(self._lib, None, code)
         self._ctx = out
         self.n_seeds = int(sd.shape[0])
