@@ -897,7 +897,8 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
   // truncation bound of the refinement: 2 (1-c)/c * eps_ref / sigma = target * budget
   const double tgt = target > 0.0 ? target : c->refine_target;
   const double eps_ref = tgt * c->budget * cc * min_sig / (2.0 * (1.0 - cc));
-  launch_reset_run(c->ctl, c->S, mask, eps_ref, c->max_iters, dense_thresh(c), c->n / 16 + 1, c->stream);
+  launch_reset_run(c->ctl, c->S, mask, eps_ref, c->max_iters, dense_thresh(c), c->n / 16 + 1, c->stream,
+                   c->max_iters + 2);
   launch_refine_init(a, c->S, c->fp64, c->stream);
   RWR_TRY(run_slots(c, MODE_DENSE, resid * (1.0 - cc), eps_ref));
   if (c->ctl_h->prop_err != 0) {
@@ -1326,7 +1327,8 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   RWR_TRY(alloc_zero(c, &c->hbase, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->sel, (size_t)c->n_cap * 2));
   RWR_TRY(alloc_zero(c, &c->sel_count, 1));
-  RWR_TRY(alloc_zero(c, &c->hist, (size_t)(c->max_iters + 2) * c->S));
+  // norms of the update runs, then of the refinement runs (kept apart)
+  RWR_TRY(alloc_zero(c, &c->hist, (size_t)2 * (c->max_iters + 2) * c->S));
   RWR_TRY(plan_heavy(c, true));
   RWR_TRY(ensure_partials(c));
 

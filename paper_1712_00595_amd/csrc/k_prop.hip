@@ -193,7 +193,7 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
     const double nr = sh.s_norm[t];
     const double su = sh.s_sum[t];
     const bool act = ctl->active[t] != 0;
-    a.hist[(int64_t)it * S + t] = act ? nr : 0.0;
+    a.hist[(int64_t)(ctl->hist_base + it) * S + t] = act ? nr : 0.0;
     if (act) {
       ctl->sigma[t] += su;
       ctl->last_norm[t] = nr;
@@ -1147,7 +1147,7 @@ __global__ __launch_bounds__(BLOCK) void k_finish(SlotArgs a) {
 }
 
 __global__ void k_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double eps, int32_t max_iters,
-                            int64_t dense_thresh, int64_t dense_nodes) {
+                            int64_t dense_thresh, int64_t dense_nodes, int32_t hist_base) {
   const int t = threadIdx.x;
   if (t < RWR_MAX_COLS) {
     const int a = (t < S) && ((active_mask >> t) & 1ull);
@@ -1175,6 +1175,7 @@ __global__ void k_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double ep
     ctl->dense_nodes = dense_nodes;
     ctl->eps = eps;
     ctl->hpack = 0;
+    ctl->hist_base = hist_base;
   }
 }
 
@@ -1193,8 +1194,9 @@ static constexpr int push_lanes() {
 }
 
 void launch_reset_run(Ctl *ctl, int32_t S, uint64_t mask, double eps, int32_t max_iters, int64_t dense_thresh,
-                      int64_t dense_nodes, hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_run, dim3(1), dim3(64), 0, st, ctl, S, mask, eps, max_iters, dense_thresh, dense_nodes);
+                      int64_t dense_nodes, hipStream_t st, int32_t hist_base) {
+  hipLaunchKernelGGL(k_reset_run, dim3(1), dim3(64), 0, st, ctl, S, mask, eps, max_iters, dense_thresh, dense_nodes,
+                     hist_base);
 }
 
 #define RWR_DISPATCH_S(S, CALL)  \

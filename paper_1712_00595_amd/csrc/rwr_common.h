@@ -51,7 +51,7 @@ struct Ctl {
   uint32_t done_blocks; // last-arriver counter of the current kernel
   int32_t dense_iters;
   int32_t heavy_stale;  // rows that became heavy since the last schedule
-  int32_t pad0;
+  int32_t hist_base;    // first history row of this run (update runs 0, refinements after them)
   int64_t fedges;       // out-edges of the frontier being built
   uint64_t hpack;       // long push rows of this slot: count << 32 | chunks
   int64_t visited;      // edges read by propagation in this run

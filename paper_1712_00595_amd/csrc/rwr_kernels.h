@@ -109,8 +109,10 @@ void launch_apply(const uint64_t *keys, const int32_t *seg, const int32_t *row, 
                   int64_t e_cap, hipStream_t st);
 
 // ---- propagation (k_prop.hip); fp64 selects the propagation type
+// hist_base: first row of the norm history this run writes (0 for update
+// runs; refinements write after them, so the update's norms stay readable)
 void launch_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double eps, int32_t max_iters, int64_t dense_thresh,
-                      int64_t dense_nodes, hipStream_t st);
+                      int64_t dense_nodes, hipStream_t st, int32_t hist_base = 0);
 void launch_seed_init(const SlotArgs &a, int S, hipStream_t st);
 void launch_seed_init_q(const SlotArgs &a, int S, hipStream_t st);
 void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st);

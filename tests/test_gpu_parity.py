@@ -505,3 +505,22 @@ def test_full_size_64_columns_scale20():
         for j in (0, 21, 42, 63):
             ref = oracle.rwr_static(n, s, d, int(seeds[j]), 0.15)
             assert _l1(ctx.scores(j), ref) <= 2 * eps / 0.15, j
+
+
+def test_last_norms_are_the_update_run_after_a_refinement():
+    # the norm history reported for an update is its own propagation's, also
+    # when a residual refinement ran after it
+    print("[last norms after refinement]", flush=True)
+    g = rmat_graph(11, 20000, dead_end_self_loops=True)
+    s = int(np.argmax(g.out_degree()))
+    model = EdgeSetModel(g.n, g.src, g.dst)
+    b = mixed_batch(np.random.default_rng(3), model, 20, 20)
+    # a budget below one update's truncation bound: every update refines
+    with _ctx(g, [s], eps=1e-9, precision="fp32", err_budget=2e-9) as ctx:
+        st = ctx.update_batch(b)
+        assert st["refined"] == 1
+        norms = ctx.last_norms(0)
+        assert norms.shape[0] == st["iters"] + 1
+        assert norms[0] == pytest.approx(st["q_off_l1"], rel=1e-12)
+        assert norms[-1] == pytest.approx(st["last_x_l1"], rel=1e-12)
+        assert norms[-1] <= 1e-9 < norms[-2]
