@@ -338,9 +338,11 @@ static rwr_status ensure_partials(rwr_ctx *c) {
 static void tune_defaults(rwr_ctx *c) {
   const int S = c->S;
   if (S == 1) {
+    // wave items take rows of up to 1024 in-edges (two rounds); longer rows
+    // are cut into 2048-edge chunks (fewer heavy rows to finish per sweep)
     c->light_lanes = 16;
-    c->heavy_limit = 512;
-    c->heavy_chunk = 1024;
+    c->heavy_limit = 1024;
+    c->heavy_chunk = 2048;
   } else if (S <= 4) {
     c->heavy_limit = 512;
     c->heavy_chunk = 2048;
