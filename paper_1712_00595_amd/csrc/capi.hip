@@ -86,6 +86,7 @@ struct rwr_ctx {
   double *h_part = nullptr;
   int32_t h_items = 0, h_nrows = 0;
   int32_t heavy_limit = 512, heavy_chunk = 4096;
+  int32_t fold_max = 2048;  // heavy row-columns finished inside the decision kernel
   int32_t *sel = nullptr, *sel_count = nullptr;
   // row partition of the single-column dense sweep
   int32_t *mp_rows = nullptr;
@@ -305,6 +306,7 @@ static SlotArgs slot_args(const rwr_ctx *c) {
   a.grid_pull = c->grid_pull;
   a.light_lanes = c->light_lanes;
   a.pull_lanes = c->pull_lanes;
+  a.fold_max = c->fold_max;
   a.zero_seed_rows = c->qmode ? 0 : 1;
   a.qvec = c->qvec;
   a.row_order = c->row_order;
@@ -360,6 +362,7 @@ static void tune_defaults(rwr_ctx *c) {
   if (const char *e = getenv("RWR_HEAVY_CHUNK")) c->heavy_chunk = atoi(e);
   if (const char *e = getenv("RWR_PULL_RATIO")) c->pull_ratio = atoi(e);
   if (const char *e = getenv("RWR_GRAPHS")) c->graphs = atoi(e) != 0;
+  if (const char *e = getenv("RWR_HEAVY_FOLD")) c->fold_max = atoi(e);
   if (const char *e = getenv("RWR_REFINE_TARGET")) {
     const double t = atof(e);
     if (t > 0.0 && t < 1.0) c->refine_target = t;

@@ -30,7 +30,6 @@
 #define BLOCK 256
 #define NWAVES (BLOCK / RWR_WAVE)
 #define DECIDE_BLOCK 1024
-#define HEAVY_FOLD 1024  // at most this many heavy row-columns are finished inside the decision kernel
 
 enum { KIND_SPARSE = 0, KIND_DENSE = 1, KIND_REFINE = 2, KIND_RESID = 3, KIND_SIGMA = 4 };
 
@@ -1317,7 +1316,7 @@ static void pull_impl(const SlotArgs &a, int k, hipStream_t st, hipEvent_t ev0 =
     }
   }
   // few heavy rows: the decision kernel finishes them (one launch less)
-  const bool fold = decide && (int64_t)a.heavy.n_rows * S <= HEAVY_FOLD;
+  const bool fold = decide && (int64_t)a.heavy.n_rows * S <= a.fold_max;
   int hgrid = 0;
   if (a.heavy.n_rows > 0 && !fold) {
     hgrid = std::max(1, std::min((a.heavy.n_rows * S + BLOCK - 1) / BLOCK, 256));

@@ -61,6 +61,7 @@ struct SlotArgs {
   int32_t grid_pull;  // workgroups of a dense sweep (each loops over items)
   int32_t light_lanes;  // lanes per row of the light push
   int32_t pull_lanes;   // lanes per in-row of the dense sweep for S >= 4 (16, 32 or 64)
+  int32_t fold_max;     // heavy row-columns at most that the decision kernel finishes itself
   int32_t zero_seed_rows;   // residual sweep: 1 zeroes the seed row of each column (the restart term)
   const double *qvec;       // seed vectors (node-major, S per node) or null; when set, the residual
                             // check adds their restart term c q after the sweep
