@@ -7,19 +7,22 @@
 //   sparse: push over the out-rows of the frontier (nodes with x != 0) with
 //           FP64 atomics into ybuf, then an epilogue over the stamped nodes;
 //   dense : pull over the in-rows of every node.  In-rows longer than the
-//           light limit are cut into chunks, one workgroup each.
+//           heavy limit are cut into chunks (one wavefront each for one
+//           seed column, one workgroup each for several).
 // Every epilogue is fused: accumulate into r (FP64), L1 norm and signed sum
 // per seed column, and the next pre-scaled vector.
 //
 // No workgroup waits for another inside a kernel.  Each workgroup writes its
 // partial sums (and each heavy-row chunk its partial row sum) with plain
-// stores; a small follow-up kernel finishes the heavy rows, and a
-// single-workgroup kernel (k_decide) adds all partials in a fixed order
-// (deterministic), records ||x^(i)||_1, retires converged columns and picks
-// the phase of the next iteration.  Every kernel of an iteration slot first
-// checks that phase, so the host can enqueue slots without waiting; slots
-// after convergence exit at once.  Grids are sized to the resident capacity
-// of the chip and loop over their work.
+// stores; the heavy rows are finished by a small follow-up kernel or, when
+// there are few, by the decision kernel: a single workgroup (k_decide) that
+// adds all partials in a fixed order (deterministic), records ||x^(i)||_1,
+// retires converged columns and picks the phase of the next iteration.
+// Every kernel of an iteration slot first checks that phase and the parity
+// of the iteration count, so the host can enqueue slots without waiting;
+// slots after convergence, or of the phase not in effect, exit at once.
+// Grids are sized to the resident capacity of the chip and loop over their
+// work.
 #include <math.h>
 
 #include <type_traits>

@@ -67,7 +67,7 @@ struct SlotArgs {
                             // check adds their restart term c q after the sweep
   const int32_t *row_order;  // order of the in-rows in that sweep (a permutation of 0 .. n_cap-1)
   int32_t n_order;           // its length (n_cap)
-  const int32_t *mp_rows;  // row partition of the single-column dense sweep
+  const int32_t *mp_rows;  // row partition of the single-column dense sweep (wavefront items)
   int32_t n_mp;            // items of that partition
 };
 
