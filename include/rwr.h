@@ -117,6 +117,10 @@ typedef struct rwr_stats {
      D_uu = sum_v |B~[u,v] - A~[u,v]| (row L1 norm of the change of u's row), an
      upper bound of ||q_offset||_1 / (1-c) known before propagation          */
   double dr_l1;
+  /* ||g||_1 of the FP64 residual evaluated after the previous update and
+     propagated with this update's offset seed (x^(0) = q_offset + g), 0 when
+     none was carried; q_offset_l1 stays the offset seed's own norm          */
+  double carry_l1;
 } rwr_stats;
 
 /* Fill *cfg with defaults: c = 0.15, eps = 1e-9, FP32 propagation, directed,

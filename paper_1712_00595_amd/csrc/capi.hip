@@ -120,6 +120,13 @@ struct rwr_ctx {
   // sparse and dense iterations of the recent update runs
   double sparse_ema = 1.0, dense_ema = 0.0;
   int32_t update_runs = 0;
+  // residual carry: when the next update would exceed the error budget, the
+  // FP64 residual is evaluated now and added to that update's seed
+  bool carry_on = true;
+  bool carry_pending = false;  // gbuf holds the residual to carry
+  double tail_ema = -1.0;      // recent per-update bound increments (max over columns)
+  double carry_iters_ema = -1.0;  // iterations of recent carried update runs
+  bool last_carried = false;      // the last update run had a carried vector in its seed
   bool built = false;  // the static solve is done (update runs follow)
   // measurement: events around dense sweep launches
   bool prof_on = false;
@@ -363,6 +370,7 @@ static void tune_defaults(rwr_ctx *c) {
   if (const char *e = getenv("RWR_PULL_RATIO")) c->pull_ratio = atoi(e);
   if (const char *e = getenv("RWR_GRAPHS")) c->graphs = atoi(e) != 0;
   if (const char *e = getenv("RWR_HEAVY_FOLD")) c->fold_max = atoi(e);
+  if (const char *e = getenv("RWR_CARRY")) c->carry_on = atoi(e) != 0;
   if (const char *e = getenv("RWR_REFINE_TARGET")) {
     const double t = atof(e);
     if (t > 0.0 && t < 1.0) c->refine_target = t;
@@ -720,7 +728,8 @@ static rwr_status pair_graph(rwr_ctx *c, const SlotArgs &a) {
 // Only the kernels of the current phase are launched; the phase is re-read
 // at every synchronisation (a switch mid-chunk turns the chunk's remaining
 // sparse slots into no-ops, and the next chunk starts at the device's count).
-static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, double eps_hint = 0.0) {
+static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, double eps_hint = 0.0,
+                           int first_chunk = 0) {
   const SlotArgs a = slot_args(c);
   int k = 1;
   // first chunk: predicted from the starting norm when it is known (a
@@ -736,6 +745,7 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
   const bool update_run = mode == MODE_SPARSE && init_norm < 0.0 && c->built && !tn0.on;
   const int sparse_end = 1 << 30;
   if (update_run && c->update_runs >= 2) chunk = std::max(1, std::min(16, (int)std::lround(c->sparse_ema)));
+  if (first_chunk > 0) chunk = std::min(first_chunk, 64);
   double prev = -1.0;
   int prev_iter = 0;
   int dense_launched = 0, dense_base = c->prof_used;
@@ -834,8 +844,9 @@ static int64_t dense_thresh(const rwr_ctx *c) { return std::max<int64_t>(1, c->m
 
 static double fp32_factor(const rwr_ctx *c) { return c->fp64 ? 0.0 : 8.0 * std::ldexp(1.0, -24); }
 
-// bookkeeping after a propagation run: per-column bound increments
-static void account_run(rwr_ctx *c, bool reset) {
+// bookkeeping after a propagation run: per-column bound increments; returns
+// the largest increment
+static double account_run(rwr_ctx *c, bool reset) {
   const Ctl &h = *c->ctl_h;
   const int iters = std::max(0, h.iter - 1);
   c->last_iters = iters;
@@ -850,6 +861,7 @@ static void account_run(rwr_ctx *c, bool reset) {
       if (d > 0.2 && d < 0.99) c->decay_ema = 0.8 * c->decay_ema + 0.2 * d;
     }
   }
+  double inc = 0.0;
   for (int j = 0; j < c->n_seeds; ++j) {
     const double sum_norms = h.sum_norm[j];
     const double sig = std::fabs(h.sigma[j]) > 0 ? std::fabs(h.sigma[j]) : 1.0;
@@ -859,7 +871,9 @@ static void account_run(rwr_ctx *c, bool reset) {
       c->err_bound[j] = tail + rnd;
     else
       c->err_bound[j] += tail + rnd;
+    inc = std::max(inc, tail + rnd);
   }
+  return inc;
 }
 
 // Keep every column's error bound within the budget.  The running bound is
@@ -877,7 +891,13 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
                                    double target = -1.0) {
   double worst = 0.0;
   for (int j = 0; j < c->n_seeds; ++j) worst = std::max(worst, c->err_bound[j]);
-  if (!force && worst <= c->budget) return RWR_OK;
+  // the residual carry (updates only, not with the learned warm start, which
+  // uses the residual buffer itself): check now when the next update would
+  // likely exceed the budget, and carry the residual into its seed
+  const bool carry = !force && c->carry_on && !(c->ws.alloc && c->ws.mode != 0);
+  if (!force && worst <= c->budget && !(carry && c->tail_ema > 0.0 && worst + c->tail_ema > c->budget))
+    return RWR_OK;
+  c->carry_pending = false;
   const SlotArgs a = slot_args(c);
   launch_residual(a, c->S, c->stream);
   RWR_TRY(read_ctl(c));
@@ -896,7 +916,10 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
     st->checked = 1;
     st->residual_l1 = resid;
   }
-  if (mask == 0) return RWR_OK;
+  if (mask == 0) {
+    c->carry_pending = carry;
+    return RWR_OK;
+  }
   double min_sig = 1e300;
   for (int j = 0; j < c->n_seeds; ++j) min_sig = std::min(min_sig, std::fabs(c->ctl_h->sigma[j]));
   // truncation bound of the refinement: 2 (1-c)/c * eps_ref / sigma = target * budget
@@ -1150,13 +1173,15 @@ static void fill_stats(rwr_ctx *c, rwr_stats *st) {
   st->dense_iters = h.dense_iters;
   st->visited_edges = h.visited + (int64_t)h.dense_iters * c->m;
   st->touched_rows = h.nT[0];
-  double q = 0.0, lx = 0.0;
+  double q = 0.0, lx = 0.0, cl = 0.0;
   for (int j = 0; j < c->n_seeds; ++j) {
-    q = std::max(q, h.norm0[j]);
+    q = std::max(q, c->last_carried ? h.qoff_l1[j] : h.norm0[j]);
     lx = std::max(lx, h.last_norm[j]);
+    if (c->last_carried) cl = std::max(cl, h.carry_l1[j]);
   }
   st->q_off_l1 = q;
   st->last_x_l1 = lx;
+  st->carry_l1 = cl;
   double dr = 0.0;
   for (int j = 0; j < c->n_seeds; ++j) dr = std::max(dr, h.dr_l1[j]);
   st->dr_l1 = dr;
@@ -1665,10 +1690,24 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   // steers the sparse/dense switch and the visited-edge statistic)
   c->m += (b->n_ins - b->n_del) * (c->undirected ? 2 : 1) - c->ctl_h->node_dels;
   const bool warm = c->ws.alloc && c->ws.mode != 0 && nkeys > 0;
+  // a residual evaluated after the previous update joins this update's seed:
+  // the run then converges to the new scores from the exact residual, and the
+  // error bound restarts from this run's truncation
+  const bool carried = c->carry_pending && !warm;
+  c->carry_pending = false;
+  c->last_carried = carried;
+  if (carried) launch_carry_seed(a, c->S, c->stream);
   if (warm) RWR_TRY(warm_prepare(c));
   launch_slot0_epilogue(a, c->S, c->fp64, c->stream);
-  RWR_TRY(run_slots(c, MODE_SPARSE));  // leaves ctl_h at the run's final state
-  account_run(c, false);
+  // a carried residual is spread over the graph: the run goes dense at once
+  const int cchunk = c->carry_iters_ema > 0.0 ? (int)std::lround(c->carry_iters_ema) : 3;
+  RWR_TRY(run_slots(c, carried ? MODE_DENSE : MODE_SPARSE, -1.0, 0.0, carried ? std::max(1, cchunk) : 0));
+  const double inc = account_run(c, carried);
+  c->tail_ema = c->tail_ema < 0.0 ? inc : std::max(inc, 0.5 * (c->tail_ema + inc));
+  if (carried) {
+    const double its = std::max(0, c->ctl_h->iter - 1);
+    c->carry_iters_ema = c->carry_iters_ema < 0.0 ? its : 0.7 * c->carry_iters_ema + 0.3 * its;
+  }
   fill_stats(c, st);
   if (st && warm) {
     st->ws_region = c->ws.nR;
@@ -1719,9 +1758,10 @@ rwr_status rwr_scores(rwr_ctx *c, int32_t j, double *out, int64_t cap, int32_t o
     c->err = "output capacity below the node count";
     return RWR_EINVAL;
   }
-  double *dst = out_on_device ? out : c->gbuf;
+  // staged in the residual sweep's scratch (gbuf may hold a carried residual)
+  double *dst = out_on_device ? out : c->xres;
   launch_scores(c->r, c->ctl, c->perm, c->S, j, c->n, dst, c->stream);
-  if (!out_on_device) HIP_TRY(c, hipMemcpyAsync(out, c->gbuf, sizeof(double) * c->n, hipMemcpyDeviceToHost, c->stream));
+  if (!out_on_device) HIP_TRY(c, hipMemcpyAsync(out, c->xres, sizeof(double) * c->n, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return RWR_OK;
 }

@@ -128,32 +128,49 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
   constexpr int TPC = DECIDE_BLOCK / S;
   const int t = threadIdx.x, j = t % S, q = t / S;
   const int lane = t % RWR_WAVE, w = t / RWR_WAVE;
+  // heavy rows to finish here (at most two per thread, see fold_max): their
+  // row data is loaded first, so that it arrives with the partials
+  const int nh = fold ? a.heavy.n_rows : 0;
+  int hf[2] = {0, 0}, hc[2] = {0, 0}, hv[2] = {0, 0};
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int h = q + u * TPC;
+    if (h < nh) {
+      hf[u] = a.heavy.first[h];
+      hc[u] = a.heavy.nchunks[h];
+      hv[u] = a.heavy.rows[h];
+    }
+  }
   double A = 0.0, B = 0.0;
   for (int e = q; e < count; e += TPC) {
     A += a.part[e * entry_stride<S>() + 2 * j];
     B += a.part[e * entry_stride<S>() + 2 * j + 1];
   }
-  if (fold) {
+  if (nh > 0) {
     const double c1 = 1.0 - a.c;
     const bool act = ctl->active[j] != 0;
     XT *__restrict__ xnext = (XT *)a.x[new_list];
     double hn = 0.0, hs = 0.0;
-    for (int h = q; h < a.heavy.n_rows; h += TPC) {
-      const int f = a.heavy.first[h], nch = a.heavy.nchunks[h];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (q + u * TPC >= nh) break;
       double y = 0.0;
-      for (int qq = 0; qq < nch; ++qq) y += a.heavy.part[(int64_t)(f + qq) * S + j];
+      for (int qq = 0; qq < hc[u]; ++qq) y += a.heavy.part[(int64_t)(hf[u] + qq) * S + j];
       if (kind == KIND_RESID)
-        pull_epilogue<double, S, KIND_RESID>(a, nullptr, a.heavy.rows[h], j, c1 * y, act, hn, hs);
+        pull_epilogue<double, S, KIND_RESID>(a, nullptr, hv[u], j, c1 * y, act, hn, hs);
       else
-        pull_epilogue<XT, S, KIND_DENSE>(a, xnext, a.heavy.rows[h], j, c1 * y, act, hn, hs);
+        pull_epilogue<XT, S, KIND_DENSE>(a, xnext, hv[u], j, c1 * y, act, hn, hs);
     }
     A += hn;
     B += hs;
   }
+  // frontier counters: only a sparse slot publishes them
   int64_t ia = 0, ib = 0;
-  for (int e = t; e < count; e += DECIDE_BLOCK) {
-    ia += a.part_i[(int64_t)e * 16];
-    ib += a.part_i[(int64_t)e * 16 + 1];
+  if (kind == KIND_SPARSE) {
+    for (int e = t; e < count; e += DECIDE_BLOCK) {
+      ia += a.part_i[(int64_t)e * 16];
+      ib += a.part_i[(int64_t)e * 16 + 1];
+    }
   }
   A = wave_xor_sum(A, S, RWR_WAVE);
   B = wave_xor_sum(B, S, RWR_WAVE);
@@ -1042,6 +1059,40 @@ __global__ __launch_bounds__(BLOCK) void k_heavy_epi(SlotArgs a, int k, int entr
   block_publish<S>(nrm, sm, 0, 0, a.part, a.part_i, entry_base + blockIdx.x, sh);
 }
 
+// The residual of the previous update carried into this update's seed:
+// ybuf += g and the node is stamped, so x^(0) = q_offset + g.  (The exact
+// residual of the current scores in the new graph is q_offset + g, where g
+// is their residual in the old graph, Section 3.1 applied to r.)  Adds
+// ||q_offset||_1 and ||g||_1 of each column to the batch statistics.
+template <int S>
+__global__ __launch_bounds__(BLOCK) void k_carry_seed(SlotArgs a) {
+  __shared__ double sq[BLOCK], sg[BLOCK];
+  const int32_t st = a.ctl->stamp;
+  const int j = threadIdx.x % S;
+  constexpr int NPB = BLOCK / S;
+  double nq = 0.0, ng = 0.0;
+  for (int v = blockIdx.x * NPB + threadIdx.x / S; v < a.n; v += gridDim.x * NPB) {
+    const int64_t kk = col_index(v, S, j);
+    // ybuf is zero off the offset seed's stamped nodes
+    const double g = a.gbuf[kk], y = a.ybuf[kk];
+    nq += fabs(y);
+    if (g != 0.0) {
+      ng += fabs(g);
+      a.ybuf[kk] = y + g;
+      a.stamp[v] = st;
+    }
+  }
+  sq[threadIdx.x] = nq;
+  sg[threadIdx.x] = ng;
+  __syncthreads();
+  if (threadIdx.x < S) {
+    double tq = 0.0, tg = 0.0;
+    for (int i = threadIdx.x; i < BLOCK; i += S) tq += sq[i], tg += sg[i];
+    if (tq != 0.0) atomic_add_f64(&a.ctl->qoff_l1[threadIdx.x], tq);
+    if (tg != 0.0) atomic_add_f64(&a.ctl->carry_l1[threadIdx.x], tg);
+  }
+}
+
 // Restart term of seed vectors after a residual sweep: g += c q on every
 // node, then the workgroup's partial sums of ||g||_1 and of r (they replace
 // the sweep's own partials).  The seed-vector columns have no seed rows, so
@@ -1260,6 +1311,10 @@ void launch_seed_init_q(const SlotArgs &a, int S, hipStream_t st) {
   RWR_DISPATCH_S(S, hipLaunchKernelGGL(k_seed_init_q<SS>, dim3(a.grid_light), dim3(BLOCK), 0, st, a));
 }
 
+void launch_carry_seed(const SlotArgs &a, int S, hipStream_t st) {
+  RWR_DISPATCH_S(S, hipLaunchKernelGGL(k_carry_seed<SS>, dim3(a.grid_light), dim3(BLOCK), 0, st, a));
+}
+
 template <typename XT, int S>
 static void slot0_impl(const SlotArgs &a, hipStream_t st) {
   hipLaunchKernelGGL((k_epi<XT, S>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, 0, 1.0, 1);
@@ -1319,7 +1374,7 @@ static void pull_impl(const SlotArgs &a, int k, hipStream_t st, hipEvent_t ev0 =
     }
   }
   // few heavy rows: the decision kernel finishes them (one launch less)
-  const bool fold = decide && (int64_t)a.heavy.n_rows * S <= a.fold_max;
+  const bool fold = decide && (int64_t)a.heavy.n_rows * S <= std::min(a.fold_max, 2 * DECIDE_BLOCK);
   int hgrid = 0;
   if (a.heavy.n_rows > 0 && !fold) {
     hgrid = std::max(1, std::min((a.heavy.n_rows * S + BLOCK - 1) / BLOCK, 256));

@@ -116,6 +116,8 @@ void launch_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double eps, int
                       int64_t dense_nodes, hipStream_t st, int32_t hist_base = 0);
 void launch_seed_init(const SlotArgs &a, int S, hipStream_t st);
 void launch_seed_init_q(const SlotArgs &a, int S, hipStream_t st);
+// ybuf += gbuf on every node with a nonzero residual (stamped): a carried residual
+void launch_carry_seed(const SlotArgs &a, int S, hipStream_t st);
 void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st);
 // iteration slot k (computes x^(k)): sparse = push + epilogue, dense = pull
 void launch_sparse_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t st);

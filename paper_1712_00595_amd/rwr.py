@@ -110,6 +110,7 @@ class StatsStruct(ctypes.Structure):
         ("ws_loss", ctypes.c_double),
         ("ms_warm", ctypes.c_double),
         ("dr_l1", ctypes.c_double),
+        ("carry_l1", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

@@ -34,7 +34,7 @@ def test_struct_layouts_match_header():
     # field order and sizes mirror rwr.h; 8-byte aligned structs
     assert ctypes.sizeof(rwr.Config) == 8 * 4 + 4 * 6 + 8
     assert ctypes.sizeof(rwr.BatchStruct) == 8 + 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
-    assert ctypes.sizeof(rwr.StatsStruct) == 4 * 4 + 8 * 2 + 8 * 5 + 4 * 2 + 8 * 3 + 8
+    assert ctypes.sizeof(rwr.StatsStruct) == 4 * 4 + 8 * 2 + 8 * 5 + 4 * 2 + 8 * 3 + 8 + 8
 
 
 def test_config_default_and_host_side_rejection():

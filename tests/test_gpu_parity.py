@@ -149,6 +149,50 @@ def test_new_node_with_only_out_edges():
 
 # ------------------------------------------------------------ streams / modes
 
+@pytest.mark.parametrize("prec,n_seeds", [("fp32", 1), ("fp64", 3)])
+def test_carried_residual_matches_oracle(monkeypatch, prec, n_seeds):
+    # the residual evaluated after one update joins the next update's seed;
+    # every update stays within the gate against the oracle, the carried
+    # updates included, and matches a context that never carries
+    print(f"[carry] prec={prec} seeds={n_seeds}", flush=True)
+    g = rmat_graph(11, 20000, dead_end_self_loops=True)
+    seeds = [int(v) for v in np.argsort(-g.out_degree())[:n_seeds]]
+    model = EdgeSetModel(g.n, g.src, g.dst)
+    rng = np.random.default_rng(11)
+    # FP32: small batches, so that the rounding term leaves room below the
+    # gate for the certified error and no refinement is needed
+    k = 3 if prec == "fp32" else 30
+    batches = [mixed_batch(rng, model, k, k, n_new_nodes=1 if t % 4 == 0 else 0) for t in range(12)]
+    eps = 1e-9 if prec == "fp32" else 1e-12
+    kw = dict(eps=eps, precision=prec) if prec == "fp32" else dict(eps=eps, precision=prec, build_tol=1e-12)
+    gate = 2 * eps / 0.15
+    finals = []
+    for carry in ("1", "0"):
+        monkeypatch.setenv("RWR_CARRY", carry)
+        n, src, dst = g.n, g.src, g.dst
+        carried = 0
+        with _ctx(g, seeds, **kw) as ctx:
+            for t, b in enumerate(batches):
+                st = ctx.update_batch(b)
+                n, src, dst = oracle.apply_batch(n, src, dst, b)
+                assert st["err_bound"] <= gate
+                if st["carry_l1"] > 0.0:
+                    carried += 1
+                    assert st["q_off_l1"] <= (1 - 0.15) * st["dr_l1"] * (1 + 1e-9)
+                if carry == "1" and (st["carry_l1"] > 0.0 or t == len(batches) - 1):
+                    for j, sd in enumerate(seeds):
+                        ref = oracle.rwr_static(n, src, dst, sd, 0.15)
+                        err = _l1(ctx.scores(j), ref)
+                        assert err <= st["err_bound"] + 1e-13, (t, j, err, st)
+            finals.append([ctx.scores(j) for j in range(n_seeds)])
+        if carry == "1":
+            assert carried >= 3, carried
+        else:
+            assert carried == 0
+    for a, b in zip(*finals):
+        assert _l1(a, b) <= 2 * gate
+
+
 @pytest.mark.parametrize("eps", [1e-6, 1e-9])
 def test_single_edge_stream_within_gate(eps):
     print(f"[stream] eps={eps}", flush=True)
