@@ -122,8 +122,19 @@ struct rwr_ctx {
   int32_t update_runs = 0;
   // residual carry: when the next update would exceed the error budget, the
   // FP64 residual is evaluated now and added to that update's seed
+  // The last iterate of an update run that ended dense is left unpropagated
+  // (deferred) in x[tail_slot] and carried into the next update's seed the
+  // same way; its truncation bound tail_pend[j] then leaves the error bound.
+  // Deferring makes the next run dense from its first sweep, which pays only
+  // when residual checks would otherwise come often: when one update's bound
+  // increment is at least half the budget.
+  // carry_level: 0 off, 1 residual only, 2 residual and (when it pays)
+  // deferred iterate, 3 residual and always the deferred iterate.
+  int carry_level = 2;
   bool carry_on = true;
   bool carry_pending = false;  // gbuf holds the residual to carry
+  int tail_slot = -1;          // x buffer holding a deferred last iterate (-1: none)
+  double tail_pend[RWR_MAX_COLS] = {};
   double tail_ema = -1.0;      // recent per-update bound increments (max over columns)
   double carry_iters_ema = -1.0;  // iterations of recent carried update runs
   bool last_carried = false;      // the last update run had a carried vector in its seed
@@ -370,7 +381,8 @@ static void tune_defaults(rwr_ctx *c) {
   if (const char *e = getenv("RWR_PULL_RATIO")) c->pull_ratio = atoi(e);
   if (const char *e = getenv("RWR_GRAPHS")) c->graphs = atoi(e) != 0;
   if (const char *e = getenv("RWR_HEAVY_FOLD")) c->fold_max = atoi(e);
-  if (const char *e = getenv("RWR_CARRY")) c->carry_on = atoi(e) != 0;
+  if (const char *e = getenv("RWR_CARRY")) c->carry_level = std::max(0, std::min(3, atoi(e)));
+  c->carry_on = c->carry_level > 0;
   if (const char *e = getenv("RWR_REFINE_TARGET")) {
     const double t = atof(e);
     if (t > 0.0 && t < 1.0) c->refine_target = t;
@@ -729,7 +741,7 @@ static rwr_status pair_graph(rwr_ctx *c, const SlotArgs &a) {
 // at every synchronisation (a switch mid-chunk turns the chunk's remaining
 // sparse slots into no-ops, and the next chunk starts at the device's count).
 static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, double eps_hint = 0.0,
-                           int first_chunk = 0) {
+                           int first_chunk = 0, bool keep_tail = false) {
   const SlotArgs a = slot_args(c);
   int k = 1;
   // first chunk: predicted from the starting norm when it is known (a
@@ -834,6 +846,11 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
     }
     ++c->update_runs;
   }
+  // a run that ended dense may leave its last iterate for the next update
+  if (keep_tail && c->ctl_h->ended_dense && c->ctl_h->prop_err == 0) {
+    c->tail_slot = (c->ctl_h->iter - 1) & 1;
+    return RWR_OK;
+  }
   launch_finish(a, c->S, c->fp64, c->stream);
   return RWR_OK;
 }
@@ -844,9 +861,24 @@ static int64_t dense_thresh(const rwr_ctx *c) { return std::max<int64_t>(1, c->m
 
 static double fp32_factor(const rwr_ctx *c) { return c->fp64 ? 0.0 : 8.0 * std::ldexp(1.0, -24); }
 
+// Give up a deferred last iterate: its truncation bound stays in the error
+// bound, and both x buffers are cleared (every other run starts from zero
+// buffers).
+static void drop_tail(rwr_ctx *c) {
+  if (c->tail_slot < 0) return;
+  const size_t bytes = (size_t)c->n_cap * c->S * (c->fp64 ? 8 : 4);
+  launch_zero_bytes(c->x[0], bytes, c->stream);
+  launch_zero_bytes(c->x[1], bytes, c->stream);
+  c->tail_slot = -1;
+  for (int j = 0; j < RWR_MAX_COLS; ++j) c->tail_pend[j] = 0.0;
+}
+
 // bookkeeping after a propagation run: per-column bound increments; returns
-// the largest increment
-static double account_run(rwr_ctx *c, bool reset) {
+// the largest increment.  `reset`: the run started from an exact residual
+// (the bound restarts); `tail_in`: the run carried the previous run's
+// deferred iterate (whose pending bound it replaces).  A column whose last
+// iterate this run deferred keeps that iterate's bound in tail_pend.
+static double account_run(rwr_ctx *c, bool reset, bool tail_in = false) {
   const Ctl &h = *c->ctl_h;
   const int iters = std::max(0, h.iter - 1);
   c->last_iters = iters;
@@ -867,10 +899,10 @@ static double account_run(rwr_ctx *c, bool reset) {
     const double sig = std::fabs(h.sigma[j]) > 0 ? std::fabs(h.sigma[j]) : 1.0;
     const double tail = 2.0 * (1.0 - cc) / cc * h.last_norm[j] / sig;
     const double rnd = 2.0 * fp32_factor(c) * sum_norms / (cc * sig);
-    if (reset)
-      c->err_bound[j] = tail + rnd;
-    else
-      c->err_bound[j] += tail + rnd;
+    const double base = reset ? 0.0 : c->err_bound[j] - (tail_in ? c->tail_pend[j] : 0.0);
+    c->err_bound[j] = base + tail + rnd;
+    // only a column still active in the final sweep has its iterate in x[tail_slot]
+    c->tail_pend[j] = (c->tail_slot >= 0 && h.last_it[j] == h.iter - 1) ? tail : 0.0;
     inc = std::max(inc, tail + rnd);
   }
   return inc;
@@ -889,15 +921,20 @@ static double account_run(rwr_ctx *c, bool reset) {
 // `refine_at` (a fraction of the budget).
 static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double refine_at = 1.0,
                                    double target = -1.0) {
-  double worst = 0.0;
-  for (int j = 0; j < c->n_seeds; ++j) worst = std::max(worst, c->err_bound[j]);
+  double worst = 0.0, next = 0.0;
+  for (int j = 0; j < c->n_seeds; ++j) {
+    worst = std::max(worst, c->err_bound[j]);
+    // a deferred iterate's bound is replaced by the next run's
+    next = std::max(next, c->err_bound[j] - c->tail_pend[j]);
+  }
   // the residual carry (updates only, not with the learned warm start, which
   // uses the residual buffer itself): check now when the next update would
   // likely exceed the budget, and carry the residual into its seed
   const bool carry = !force && c->carry_on && !(c->ws.alloc && c->ws.mode != 0);
-  if (!force && worst <= c->budget && !(carry && c->tail_ema > 0.0 && worst + c->tail_ema > c->budget))
+  if (!force && worst <= c->budget && !(carry && c->tail_ema > 0.0 && next + c->tail_ema > c->budget))
     return RWR_OK;
   c->carry_pending = false;
+  drop_tail(c);  // the residual includes the deferred iterate's effect
   const SlotArgs a = slot_args(c);
   launch_residual(a, c->S, c->stream);
   RWR_TRY(read_ctl(c));
@@ -1678,10 +1715,23 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   const SlotArgs a = slot_args(c);
   launch_reset_run(c->ctl, c->S, all_cols_mask(c->n_seeds), c->cfg.eps, c->max_iters, dense_thresh(c),
                    c->n / 16 + 1, c->stream);
+  const bool warm = c->ws.alloc && c->ws.mode != 0 && nkeys > 0;
+  if (warm) {
+    drop_tail(c);
+    c->carry_pending = false;
+  }
+  // a deferred last iterate z: gbuf = z, and the offset seed is that of
+  // r - z, whose residual in the old graph is z
+  const bool tail_in = c->tail_slot >= 0;
+  if (tail_in) {
+    launch_tail_unscale(a, c->S, c->fp64, c->tail_slot, c->stream);
+    c->tail_slot = -1;
+  }
   if (nkeys > 0) {
     HIP_TRY(c, launch_offset_seed(c->S, c->keys[0], c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->g[0].v,
-                                  c->r, c->ybuf, c->stamp, c->ctl, b1, 1.0 - c->cfg.c, (int32_t)nkeys, c->flags,
-                                  c->pos, c->temp, c->temp_bytes, 4 * c->n_cu, c->stream));
+                                  c->r, tail_in ? c->gbuf : nullptr, c->ybuf, c->stamp, c->ctl, b1,
+                                  1.0 - c->cfg.c, (int32_t)nkeys, c->flags, c->pos, c->temp, c->temp_bytes,
+                                  4 * c->n_cu, c->stream));
     for (int o = 0; o < norient; ++o)
       launch_apply(c->keys[o], c->seg[o], c->row[o], c->t_dold[o], c->t_dnew[o], c->g[o].v, c->ctl, o, b1,
                    (int32_t)nkeys, c->g[o].e_cap, c->stream);
@@ -1689,20 +1739,23 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   // stored edge count (an undirected self-loop is stored once; the count only
   // steers the sparse/dense switch and the visited-edge statistic)
   c->m += (b->n_ins - b->n_del) * (c->undirected ? 2 : 1) - c->ctl_h->node_dels;
-  const bool warm = c->ws.alloc && c->ws.mode != 0 && nkeys > 0;
-  // a residual evaluated after the previous update joins this update's seed:
-  // the run then converges to the new scores from the exact residual, and the
-  // error bound restarts from this run's truncation
-  const bool carried = c->carry_pending && !warm;
+  // a residual evaluated after the previous update (or the deferred last
+  // iterate) joins this update's seed: the run then converges to the new
+  // scores from an exact residual; after a residual the error bound restarts
+  // from this run's truncation
+  const bool resid_in = c->carry_pending;
+  const bool carried = resid_in || tail_in;
   c->carry_pending = false;
   c->last_carried = carried;
   if (carried) launch_carry_seed(a, c->S, c->stream);
   if (warm) RWR_TRY(warm_prepare(c));
-  launch_slot0_epilogue(a, c->S, c->fp64, c->stream);
-  // a carried residual is spread over the graph: the run goes dense at once
+  launch_slot0_epilogue(a, c->S, c->fp64, c->stream, tail_in ? 2 : 1);
+  // a carried vector is spread over the graph: the run goes dense at once
   const int cchunk = c->carry_iters_ema > 0.0 ? (int)std::lround(c->carry_iters_ema) : 3;
-  RWR_TRY(run_slots(c, carried ? MODE_DENSE : MODE_SPARSE, -1.0, 0.0, carried ? std::max(1, cchunk) : 0));
-  const double inc = account_run(c, carried);
+  const bool keep = !warm && !(c->ws.alloc && c->ws.mode != 0) &&
+                    (c->carry_level >= 3 || (c->carry_level == 2 && c->tail_ema >= 0.5 * c->budget));
+  RWR_TRY(run_slots(c, carried ? MODE_DENSE : MODE_SPARSE, -1.0, 0.0, carried ? std::max(1, cchunk) : 0, keep));
+  const double inc = account_run(c, resid_in, tail_in);
   c->tail_ema = c->tail_ema < 0.0 ? inc : std::max(inc, 0.5 * (c->tail_ema + inc));
   if (carried) {
     const double its = std::max(0, c->ctl_h->iter - 1);

@@ -375,8 +375,9 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
                               const int32_t *__restrict__ row, const int32_t *__restrict__ t_dold,
                               const int32_t *__restrict__ t_dnew, const int32_t *__restrict__ item_off,
                               const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
-                              const double *__restrict__ r, double *__restrict__ ybuf, int32_t *__restrict__ stamp,
-                              Ctl *ctl, int b1, double c1, int32_t max_rows) {
+                              const double *__restrict__ r, const double *__restrict__ rsub,
+                              double *__restrict__ ybuf, int32_t *__restrict__ stamp, Ctl *ctl, int b1, double c1,
+                              int32_t max_rows) {
   if (ctl->err) return;
   constexpr int P = RWR_WAVE / S;
   const int lane = threadIdx.x % RWR_WAVE;
@@ -397,7 +398,8 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
     const int32_t k = it - item_off[t];
     const int32_t u = row[t], b = seg[t], e = seg[t + 1];
     const int32_t d_old = t_dold[t], d_new = t_dnew[t];
-    const double ru = r[col_index(u, S, j)];
+    // the scores without a deferred last iterate (rsub) when one is carried
+    const double ru = rsub ? r[col_index(u, S, j)] - rsub[col_index(u, S, j)] : r[col_index(u, S, j)];
     if (__ballot(ru != 0.0) == 0ull) continue;
     const double w_old = d_old ? c1 * ru / (double)d_old : 0.0;
     const double w_new = d_new ? c1 * ru / (double)d_new : 0.0;
@@ -593,17 +595,17 @@ void launch_validate_plan(const uint64_t *keys, const int32_t *seg, const int32_
 template <int S>
 static void offset_seed_s(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
                           const int32_t *t_dnew, const int32_t *item_off, const DevGraphView &g, const double *r,
-                          double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1, int32_t max_rows, int grid,
-                          hipStream_t st) {
+                          const double *rsub, double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1,
+                          int32_t max_rows, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_offset_seed<S>, dim3(grid), dim3(256), 0, st, keys, seg, row, t_dold, t_dnew, item_off, g.off,
-                     g.adj, r, ybuf, stamp, ctl, b1, c1, max_rows);
+                     g.adj, r, rsub, ybuf, stamp, ctl, b1, c1, max_rows);
 }
 
 hipError_t launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row,
                               const int32_t *t_dold, const int32_t *t_dnew, const DevGraphView &g, const double *r,
-                              double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1, int32_t max_rows,
-                              int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes, int grid,
-                              hipStream_t st) {
+                              const double *rsub, double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1,
+                              int32_t max_rows, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
+                              int grid, hipStream_t st) {
   if (max_rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_seed_items, dim3(std::min(4096, (max_rows + 256) / 256)), dim3(256), 0, st, t_dold, ctl,
                      max_rows, items);
@@ -611,8 +613,8 @@ hipError_t launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, c
   if (e != hipSuccess) return e;
 #define RWR_SEED_CASE(SS)                                                                                        \
   case SS:                                                                                                       \
-    offset_seed_s<SS>(keys, seg, row, t_dold, t_dnew, item_off, g, r, ybuf, stamp, ctl, b1, c1, max_rows, grid, \
-                      st);                                                                                       \
+    offset_seed_s<SS>(keys, seg, row, t_dold, t_dnew, item_off, g, r, rsub, ybuf, stamp, ctl, b1, c1, max_rows, \
+                      grid, st);                                                                                 \
     break;
   switch (S) {
     RWR_SEED_CASE(1)

@@ -375,9 +375,11 @@ __global__ __launch_bounds__(BLOCK) void k_epi(SlotArgs a, int k, double scale, 
     a.ybuf[kk] = 0.0;
     const int d = a.out.len[v];
     if (act) {
-      a.r[kk] += y;
+      // a deferred last iterate in the seed is already part of r
+      const double add = first == 2 ? y - a.gbuf[kk] : y;
+      a.r[kk] += add;
       nrm += fabs(y);
-      sm += y;
+      sm += add;
       xnew[kk] = d ? (XT)(y / (double)d) : (XT)0;
     } else {
       xnew[kk] = (XT)0;
@@ -1093,6 +1095,26 @@ __global__ __launch_bounds__(BLOCK) void k_carry_seed(SlotArgs a) {
   }
 }
 
+// The last iterate x^(k) of the previous update, left unpropagated in x[last]
+// (pre-scaled by 1/d_out): r already contains it, and the residual of
+// r - x^(k) in the old graph is x^(k) itself (Section 3.1's expansion), so it
+// is carried like a residual.  gbuf = d_out * x[last] with the degrees before
+// the batch; both x buffers are cleared for the next run.
+template <typename XT>
+__global__ __launch_bounds__(BLOCK) void k_tail_unscale(SlotArgs a, int S, int last) {
+  XT *__restrict__ x0 = (XT *)a.x[0];
+  XT *__restrict__ x1 = (XT *)a.x[1];
+  const XT *__restrict__ xl = last ? x1 : x0;
+  const int64_t total = (int64_t)a.n * S;
+  for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < total; i += (int64_t)gridDim.x * BLOCK) {
+    const int d = a.out.len[i / S];
+    const double xv = (double)xl[i];
+    a.gbuf[i] = d ? xv * (double)d : 0.0;
+    x0[i] = (XT)0;
+    x1[i] = (XT)0;
+  }
+}
+
 // Restart term of seed vectors after a residual sweep: g += c q on every
 // node, then the workgroup's partial sums of ||g||_1 and of r (they replace
 // the sweep's own partials).  The seed-vector columns have no seed rows, so
@@ -1316,17 +1338,29 @@ void launch_carry_seed(const SlotArgs &a, int S, hipStream_t st) {
 }
 
 template <typename XT, int S>
-static void slot0_impl(const SlotArgs &a, hipStream_t st) {
-  hipLaunchKernelGGL((k_epi<XT, S>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, 0, 1.0, 1);
+static void slot0_impl(const SlotArgs &a, hipStream_t st, int first) {
+  hipLaunchKernelGGL((k_epi<XT, S>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, 0, 1.0, first);
   decide_impl<S>(a, KIND_SPARSE, a.grid_light, 0, st);
 }
 
-void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st) {
+void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st, int first) {
   if (fp64) {
-    RWR_DISPATCH_S(S, (slot0_impl<double, SS>(a, st)));
+    RWR_DISPATCH_S(S, (slot0_impl<double, SS>(a, st, first)));
   } else {
-    RWR_DISPATCH_S(S, (slot0_impl<float, SS>(a, st)));
+    RWR_DISPATCH_S(S, (slot0_impl<float, SS>(a, st, first)));
   }
+}
+
+template <typename XT>
+static void tail_unscale_impl(const SlotArgs &a, int S, int last, hipStream_t st) {
+  hipLaunchKernelGGL((k_tail_unscale<XT>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, S, last);
+}
+
+void launch_tail_unscale(const SlotArgs &a, int S, bool fp64, int last, hipStream_t st) {
+  if (fp64)
+    tail_unscale_impl<double>(a, S, last, st);
+  else
+    tail_unscale_impl<float>(a, S, last, st);
 }
 
 // dense sweep (or residual) + heavy rows + decision; the heavy-row kernel

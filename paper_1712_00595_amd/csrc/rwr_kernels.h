@@ -97,13 +97,14 @@ size_t sort_temp_bytes(int32_t n_keys);
 void launch_validate_plan(const uint64_t *keys, const int32_t *seg, const int32_t *row, const DevGraphView &g, int b1,
                           int32_t *t_dold, int32_t *t_dnew, Ctl *ctl, int orient, int check, int heavy_limit,
                           int32_t max_rows, hipStream_t st);
-// q_offset into ybuf; touched rows cut into chunks (items: max_rows + 1
-// ints, item_off: max_rows + 1 ints, temp: seed_scan_temp_bytes(max_rows))
+// q_offset of r - rsub (rsub may be null) into ybuf; touched rows cut into
+// chunks (items: max_rows + 1 ints, item_off: max_rows + 1 ints, temp:
+// seed_scan_temp_bytes(max_rows))
 hipError_t launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row,
                               const int32_t *t_dold, const int32_t *t_dnew, const DevGraphView &g, const double *r,
-                              double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1, int32_t max_rows,
-                              int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes, int grid,
-                              hipStream_t st);
+                              const double *rsub, double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1,
+                              int32_t max_rows, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
+                              int grid, hipStream_t st);
 size_t seed_scan_temp_bytes(int32_t max_rows);
 void launch_apply(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
                   const int32_t *t_dnew, const DevGraphView &g, Ctl *ctl, int orient, int b1, int32_t max_rows,
@@ -118,7 +119,12 @@ void launch_seed_init(const SlotArgs &a, int S, hipStream_t st);
 void launch_seed_init_q(const SlotArgs &a, int S, hipStream_t st);
 // ybuf += gbuf on every node with a nonzero residual (stamped): a carried residual
 void launch_carry_seed(const SlotArgs &a, int S, hipStream_t st);
-void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st);
+// deferred last iterate: gbuf = d_out * x[last] (unscaled, with the degrees
+// before the batch is applied), then both x buffers are cleared
+void launch_tail_unscale(const SlotArgs &a, int S, bool fp64, int last, hipStream_t st);
+// first = 2: the seed holds a deferred last iterate (gbuf) that r already
+// contains, so r and sigma take y - gbuf
+void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st, int first = 1);
 // iteration slot k (computes x^(k)): sparse = push + epilogue, dense = pull
 void launch_sparse_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t st);
 // ev0/ev1 (optional) are recorded on st right before and after the sweep
