@@ -255,12 +255,17 @@ static rwr_status ensure_temp(rwr_ctx *c, size_t bytes) {
   return RWR_OK;
 }
 
+// Timing events: without the system-scope fence an event's recording would
+// otherwise add (a write-back and invalidation of the caches, which also slows
+// the kernel after it); they are only read after a stream synchronisation.
+static hipError_t timing_event(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
+
 // the next pair of events (created on first use) that brackets one launch
 // of the sweep kernel
 static rwr_status prof_pair(rwr_ctx *c, hipEvent_t *e0, hipEvent_t *e1) {
   while (c->prof_used + 2 > (int)c->prof_ev.size()) {
     hipEvent_t e;
-    HIP_TRY(c, hipEventCreate(&e));
+    HIP_TRY(c, timing_event(&e));
     c->prof_ev.push_back(e);
   }
   *e0 = c->prof_ev[c->prof_used++];
@@ -779,7 +784,7 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
           const size_t q = 2 * tn.pending.size();
           while (tn.ev.size() < q + 2) {
             hipEvent_t e;
-            HIP_TRY(c, hipEventCreate(&e));
+            HIP_TRY(c, timing_event(&e));
             tn.ev.push_back(e);
           }
           tn.pending.push_back(ci);
