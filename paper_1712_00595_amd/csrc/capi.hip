@@ -1752,7 +1752,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   const bool carried = resid_in || tail_in;
   c->carry_pending = false;
   c->last_carried = carried;
-  if (carried) launch_carry_seed(a, c->S, c->stream);
+  if (carried) launch_carry_seed(a, c->S, c->fp64, tail_in, c->stream);
   if (warm) RWR_TRY(warm_prepare(c));
   launch_slot0_epilogue(a, c->S, c->fp64, c->stream, tail_in ? 2 : 1);
   // a carried vector is spread over the graph: the run goes dense at once

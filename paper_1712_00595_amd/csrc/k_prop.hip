@@ -1065,9 +1065,11 @@ __global__ __launch_bounds__(BLOCK) void k_heavy_epi(SlotArgs a, int k, int entr
 // ybuf += g and the node is stamped, so x^(0) = q_offset + g.  (The exact
 // residual of the current scores in the new graph is q_offset + g, where g
 // is their residual in the old graph, Section 3.1 applied to r.)  Adds
-// ||q_offset||_1 and ||g||_1 of each column to the batch statistics.
-template <int S>
-__global__ __launch_bounds__(BLOCK) void k_carry_seed(SlotArgs a) {
+// ||q_offset||_1 and ||g||_1 of each column to the batch statistics.  With
+// clear_x (g is a deferred iterate still held in x) both x buffers are
+// cleared for the run.
+template <typename XT, int S>
+__global__ __launch_bounds__(BLOCK) void k_carry_seed(SlotArgs a, int clear_x) {
   __shared__ double sq[BLOCK], sg[BLOCK];
   const int32_t st = a.ctl->stamp;
   const int j = threadIdx.x % S;
@@ -1075,6 +1077,10 @@ __global__ __launch_bounds__(BLOCK) void k_carry_seed(SlotArgs a) {
   double nq = 0.0, ng = 0.0;
   for (int v = blockIdx.x * NPB + threadIdx.x / S; v < a.n; v += gridDim.x * NPB) {
     const int64_t kk = col_index(v, S, j);
+    if (clear_x) {
+      ((XT *)a.x[0])[kk] = (XT)0;
+      ((XT *)a.x[1])[kk] = (XT)0;
+    }
     // ybuf is zero off the offset seed's stamped nodes
     const double g = a.gbuf[kk], y = a.ybuf[kk];
     nq += fabs(y);
@@ -1099,19 +1105,15 @@ __global__ __launch_bounds__(BLOCK) void k_carry_seed(SlotArgs a) {
 // (pre-scaled by 1/d_out): r already contains it, and the residual of
 // r - x^(k) in the old graph is x^(k) itself (Section 3.1's expansion), so it
 // is carried like a residual.  gbuf = d_out * x[last] with the degrees before
-// the batch; both x buffers are cleared for the next run.
+// the batch.  x is left as it is (a batch found invalid afterwards leaves the
+// iterate deferred); the carry kernel clears it.
 template <typename XT>
 __global__ __launch_bounds__(BLOCK) void k_tail_unscale(SlotArgs a, int S, int last) {
-  XT *__restrict__ x0 = (XT *)a.x[0];
-  XT *__restrict__ x1 = (XT *)a.x[1];
-  const XT *__restrict__ xl = last ? x1 : x0;
+  const XT *__restrict__ xl = (const XT *)a.x[last];
   const int64_t total = (int64_t)a.n * S;
   for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < total; i += (int64_t)gridDim.x * BLOCK) {
     const int d = a.out.len[i / S];
-    const double xv = (double)xl[i];
-    a.gbuf[i] = d ? xv * (double)d : 0.0;
-    x0[i] = (XT)0;
-    x1[i] = (XT)0;
+    a.gbuf[i] = d ? (double)xl[i] * (double)d : 0.0;
   }
 }
 
@@ -1333,8 +1335,14 @@ void launch_seed_init_q(const SlotArgs &a, int S, hipStream_t st) {
   RWR_DISPATCH_S(S, hipLaunchKernelGGL(k_seed_init_q<SS>, dim3(a.grid_light), dim3(BLOCK), 0, st, a));
 }
 
-void launch_carry_seed(const SlotArgs &a, int S, hipStream_t st) {
-  RWR_DISPATCH_S(S, hipLaunchKernelGGL(k_carry_seed<SS>, dim3(a.grid_light), dim3(BLOCK), 0, st, a));
+void launch_carry_seed(const SlotArgs &a, int S, bool fp64, bool clear_x, hipStream_t st) {
+  if (fp64) {
+    RWR_DISPATCH_S(S, hipLaunchKernelGGL((k_carry_seed<double, SS>), dim3(a.grid_light), dim3(BLOCK), 0, st, a,
+                                         clear_x ? 1 : 0));
+  } else {
+    RWR_DISPATCH_S(S, hipLaunchKernelGGL((k_carry_seed<float, SS>), dim3(a.grid_light), dim3(BLOCK), 0, st, a,
+                                         clear_x ? 1 : 0));
+  }
 }
 
 template <typename XT, int S>

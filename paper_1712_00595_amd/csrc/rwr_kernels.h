@@ -117,10 +117,11 @@ void launch_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double eps, int
                       int64_t dense_nodes, hipStream_t st, int32_t hist_base = 0);
 void launch_seed_init(const SlotArgs &a, int S, hipStream_t st);
 void launch_seed_init_q(const SlotArgs &a, int S, hipStream_t st);
-// ybuf += gbuf on every node with a nonzero residual (stamped): a carried residual
-void launch_carry_seed(const SlotArgs &a, int S, hipStream_t st);
+// ybuf += gbuf on every node with a nonzero residual (stamped): a carried
+// residual or deferred iterate; clear_x also clears both x buffers
+void launch_carry_seed(const SlotArgs &a, int S, bool fp64, bool clear_x, hipStream_t st);
 // deferred last iterate: gbuf = d_out * x[last] (unscaled, with the degrees
-// before the batch is applied), then both x buffers are cleared
+// before the batch is applied); x is left unchanged
 void launch_tail_unscale(const SlotArgs &a, int S, bool fp64, int last, hipStream_t st);
 // first = 2: the seed holds a deferred last iterate (gbuf) that r already
 // contains, so r and sigma take y - gbuf
