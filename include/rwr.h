@@ -117,9 +117,9 @@ typedef struct rwr_stats {
      D_uu = sum_v |B~[u,v] - A~[u,v]| (row L1 norm of the change of u's row), an
      upper bound of ||q_offset||_1 / (1-c) known before propagation          */
   double dr_l1;
-  /* ||g||_1 of the FP64 residual evaluated after the previous update and
-     propagated with this update's offset seed (x^(0) = q_offset + g), 0 when
-     none was carried; q_offset_l1 stays the offset seed's own norm          */
+  /* ||p||_1 of a vector carried from an earlier update into this one's first
+     dense sweep (the FP64 residual of a check that needed no refinement, or
+     the last iterate a run left unpropagated), 0 when none joined          */
   double carry_l1;
 } rwr_stats;
 

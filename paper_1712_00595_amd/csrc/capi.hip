@@ -120,24 +120,23 @@ struct rwr_ctx {
   // sparse and dense iterations of the recent update runs
   double sparse_ema = 1.0, dense_ema = 0.0;
   int32_t update_runs = 0;
-  // residual carry: when the next update would exceed the error budget, the
-  // FP64 residual is evaluated now and added to that update's seed
-  // The last iterate of an update run that ended dense is left unpropagated
-  // (deferred) in x[tail_slot] and carried into the next update's seed the
-  // same way; its truncation bound tail_pend[j] then leaves the error bound.
-  // Deferring makes the next run dense from its first sweep, which pays only
-  // when residual checks would otherwise come often: when one update's bound
-  // increment is at least half the budget.
-  // carry_level: 0 off, 1 residual only, 2 residual and (when it pays)
-  // deferred iterate, 3 residual and always the deferred iterate.
+  // Carried vectors.  A pending vector p (gbuf, per column) is part of r, and
+  // r - p has residual p: the next update takes the offset seed of r - p and
+  // adds p to its first dense sweep's input, so the run converges from an
+  // exact residual and p's bound leaves the error bound.  Sources: the FP64
+  // residual of a check that needed no refinement (checked early when the
+  // next update would likely pass the budget), and the last iterate of an
+  // update run that ended dense (left in x[tail_slot] instead of being
+  // cleared; its truncation bound is then not spent).
+  // carry_level: 0 off, 1 residual only, 2 residual and last iterate.
   int carry_level = 2;
-  bool carry_on = true;
-  bool carry_pending = false;  // gbuf holds the residual to carry
-  int tail_slot = -1;          // x buffer holding a deferred last iterate (-1: none)
-  double tail_pend[RWR_MAX_COLS] = {};
-  double tail_ema = -1.0;      // recent per-update bound increments (max over columns)
-  double carry_iters_ema = -1.0;  // iterations of recent carried update runs
-  bool last_carried = false;      // the last update run had a carried vector in its seed
+  uint64_t pend = 0;         // columns with a pending vector in gbuf
+  int tail_slot = -1;        // x buffer holding deferred last iterates (-1: none)
+  uint64_t tail_cols = 0;    // their columns
+  double pend_b[RWR_MAX_COLS] = {};   // error bound each pending (or deferred) vector carries
+  double pend_l1[RWR_MAX_COLS] = {};  // its L1 norm
+  double last_carry_l1 = 0.0;         // statistic of the last update
+  double tail_ema = -1.0;    // recent per-update bound increments (max over columns)
   bool built = false;  // the static solve is done (update runs follow)
   // measurement: events around dense sweep launches
   bool prof_on = false;
@@ -386,8 +385,7 @@ static void tune_defaults(rwr_ctx *c) {
   if (const char *e = getenv("RWR_PULL_RATIO")) c->pull_ratio = atoi(e);
   if (const char *e = getenv("RWR_GRAPHS")) c->graphs = atoi(e) != 0;
   if (const char *e = getenv("RWR_HEAVY_FOLD")) c->fold_max = atoi(e);
-  if (const char *e = getenv("RWR_CARRY")) c->carry_level = std::max(0, std::min(3, atoi(e)));
-  c->carry_on = c->carry_level > 0;
+  if (const char *e = getenv("RWR_CARRY")) c->carry_level = std::max(0, std::min(2, atoi(e)));
   if (const char *e = getenv("RWR_REFINE_TARGET")) {
     const double t = atof(e);
     if (t > 0.0 && t < 1.0) c->refine_target = t;
@@ -746,7 +744,7 @@ static rwr_status pair_graph(rwr_ctx *c, const SlotArgs &a) {
 // at every synchronisation (a switch mid-chunk turns the chunk's remaining
 // sparse slots into no-ops, and the next chunk starts at the device's count).
 static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, double eps_hint = 0.0,
-                           int first_chunk = 0, bool keep_tail = false) {
+                           bool keep_tail = false, uint64_t inject = 0) {
   const SlotArgs a = slot_args(c);
   int k = 1;
   // first chunk: predicted from the starting norm when it is known (a
@@ -762,7 +760,6 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
   const bool update_run = mode == MODE_SPARSE && init_norm < 0.0 && c->built && !tn0.on;
   const int sparse_end = 1 << 30;
   if (update_run && c->update_runs >= 2) chunk = std::max(1, std::min(16, (int)std::lround(c->sparse_ema)));
-  if (first_chunk > 0) chunk = std::min(first_chunk, 64);
   double prev = -1.0;
   int prev_iter = 0;
   int dense_launched = 0, dense_base = c->prof_used;
@@ -777,6 +774,11 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
     const int kend = std::min(k + chunk, c->max_iters + 2);
     for (; k < kend; ++k) {
       if (mode == MODE_DENSE || k >= sparse_end) {
+        if (inject) {
+          // pending vectors join the first dense sweep's input
+          launch_inject(a, c->S, c->fp64, k, inject, c->stream);
+          inject = 0;
+        }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tn.on && tn.launched < tn.limit) {
           // a tuning launch: the next candidate shape, timed
@@ -854,6 +856,9 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
   // a run that ended dense may leave its last iterate for the next update
   if (keep_tail && c->ctl_h->ended_dense && c->ctl_h->prop_err == 0) {
     c->tail_slot = (c->ctl_h->iter - 1) & 1;
+    c->tail_cols = 0;
+    for (int j = 0; j < c->n_seeds; ++j)
+      if (c->ctl_h->last_it[j] == c->ctl_h->iter - 1) c->tail_cols |= 1ull << j;
     return RWR_OK;
   }
   launch_finish(a, c->S, c->fp64, c->stream);
@@ -866,24 +871,28 @@ static int64_t dense_thresh(const rwr_ctx *c) { return std::max<int64_t>(1, c->m
 
 static double fp32_factor(const rwr_ctx *c) { return c->fp64 ? 0.0 : 8.0 * std::ldexp(1.0, -24); }
 
-// Give up a deferred last iterate: its truncation bound stays in the error
-// bound, and both x buffers are cleared (every other run starts from zero
-// buffers).
-static void drop_tail(rwr_ctx *c) {
-  if (c->tail_slot < 0) return;
-  const size_t bytes = (size_t)c->n_cap * c->S * (c->fp64 ? 8 : 4);
-  launch_zero_bytes(c->x[0], bytes, c->stream);
-  launch_zero_bytes(c->x[1], bytes, c->stream);
+// Give up every carried vector (before a residual check, which supersedes
+// them, or the learned warm start): each one's bound stays in the error bound
+// (r - p has residual p, so r is within that bound), and the x buffers are
+// cleared (every other run starts from zero buffers).
+static void drop_carry(rwr_ctx *c) {
+  if (c->tail_slot >= 0) {
+    const size_t bytes = (size_t)c->n_cap * c->S * (c->fp64 ? 8 : 4);
+    launch_zero_bytes(c->x[0], bytes, c->stream);
+    launch_zero_bytes(c->x[1], bytes, c->stream);
+  }
   c->tail_slot = -1;
-  for (int j = 0; j < RWR_MAX_COLS; ++j) c->tail_pend[j] = 0.0;
+  c->tail_cols = 0;
+  c->pend = 0;
+  for (int j = 0; j < RWR_MAX_COLS; ++j) c->pend_b[j] = 0.0;
 }
 
 // bookkeeping after a propagation run: per-column bound increments; returns
-// the largest increment.  `reset`: the run started from an exact residual
-// (the bound restarts); `tail_in`: the run carried the previous run's
-// deferred iterate (whose pending bound it replaces).  A column whose last
-// iterate this run deferred keeps that iterate's bound in tail_pend.
-static double account_run(rwr_ctx *c, bool reset, bool tail_in = false) {
+// the largest increment.  `reset`: the run started from exact scores (the
+// bound restarts); `inj`: columns whose pending vector joined the run (its
+// bound is replaced by the run's).  A column whose last iterate the run
+// deferred records that iterate's bound and norm.
+static double account_run(rwr_ctx *c, bool reset, uint64_t inj = 0) {
   const Ctl &h = *c->ctl_h;
   const int iters = std::max(0, h.iter - 1);
   c->last_iters = iters;
@@ -904,10 +913,14 @@ static double account_run(rwr_ctx *c, bool reset, bool tail_in = false) {
     const double sig = std::fabs(h.sigma[j]) > 0 ? std::fabs(h.sigma[j]) : 1.0;
     const double tail = 2.0 * (1.0 - cc) / cc * h.last_norm[j] / sig;
     const double rnd = 2.0 * fp32_factor(c) * sum_norms / (cc * sig);
-    const double base = reset ? 0.0 : c->err_bound[j] - (tail_in ? c->tail_pend[j] : 0.0);
+    const bool took = (inj >> j) & 1ull;
+    const double base = reset ? 0.0 : c->err_bound[j] - (took ? c->pend_b[j] : 0.0);
     c->err_bound[j] = base + tail + rnd;
-    // only a column still active in the final sweep has its iterate in x[tail_slot]
-    c->tail_pend[j] = (c->tail_slot >= 0 && h.last_it[j] == h.iter - 1) ? tail : 0.0;
+    if (took) c->pend_b[j] = 0.0;
+    if ((c->tail_cols >> j) & 1ull) {
+      c->pend_b[j] = tail;
+      c->pend_l1[j] = h.last_norm[j];
+    }
     inc = std::max(inc, tail + rnd);
   }
   return inc;
@@ -929,17 +942,16 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
   double worst = 0.0, next = 0.0;
   for (int j = 0; j < c->n_seeds; ++j) {
     worst = std::max(worst, c->err_bound[j]);
-    // a deferred iterate's bound is replaced by the next run's
-    next = std::max(next, c->err_bound[j] - c->tail_pend[j]);
+    // a carried vector's bound is replaced by the next run's
+    next = std::max(next, c->err_bound[j] - c->pend_b[j]);
   }
   // the residual carry (updates only, not with the learned warm start, which
   // uses the residual buffer itself): check now when the next update would
-  // likely exceed the budget, and carry the residual into its seed
-  const bool carry = !force && c->carry_on && !(c->ws.alloc && c->ws.mode != 0);
+  // likely pass the budget, and carry the residual into it
+  const bool carry = !force && c->carry_level >= 1 && !(c->ws.alloc && c->ws.mode != 0);
   if (!force && worst <= c->budget && !(carry && c->tail_ema > 0.0 && next + c->tail_ema > c->budget))
     return RWR_OK;
-  c->carry_pending = false;
-  drop_tail(c);  // the residual includes the deferred iterate's effect
+  drop_carry(c);  // the residual supersedes the carried vectors
   const SlotArgs a = slot_args(c);
   launch_residual(a, c->S, c->stream);
   RWR_TRY(read_ctl(c));
@@ -959,7 +971,17 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
     st->residual_l1 = resid;
   }
   if (mask == 0) {
-    c->carry_pending = carry;
+    if (carry) {
+      // keep g as a pending vector: r += g (then r - g has residual g) and
+      // sigma exactly; the certificate still bounds r + g
+      launch_add_resid(a, c->S, c->stream);
+      launch_sigma_exact(a, c->S, c->stream);
+      c->pend = all_cols_mask(c->n_seeds);
+      for (int j = 0; j < c->n_seeds; ++j) {
+        c->pend_b[j] = c->err_bound[j];
+        c->pend_l1[j] = c->ctl_h->red_norm[j];
+      }
+    }
     return RWR_OK;
   }
   double min_sig = 1e300;
@@ -1215,15 +1237,14 @@ static void fill_stats(rwr_ctx *c, rwr_stats *st) {
   st->dense_iters = h.dense_iters;
   st->visited_edges = h.visited + (int64_t)h.dense_iters * c->m;
   st->touched_rows = h.nT[0];
-  double q = 0.0, lx = 0.0, cl = 0.0;
+  double q = 0.0, lx = 0.0;
   for (int j = 0; j < c->n_seeds; ++j) {
-    q = std::max(q, c->last_carried ? h.qoff_l1[j] : h.norm0[j]);
+    q = std::max(q, h.norm0[j]);
     lx = std::max(lx, h.last_norm[j]);
-    if (c->last_carried) cl = std::max(cl, h.carry_l1[j]);
   }
   st->q_off_l1 = q;
   st->last_x_l1 = lx;
-  st->carry_l1 = cl;
+  st->carry_l1 = c->last_carry_l1;
   double dr = 0.0;
   for (int j = 0; j < c->n_seeds; ++j) dr = std::max(dr, h.dr_l1[j]);
   st->dr_l1 = dr;
@@ -1721,20 +1742,19 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   launch_reset_run(c->ctl, c->S, all_cols_mask(c->n_seeds), c->cfg.eps, c->max_iters, dense_thresh(c),
                    c->n / 16 + 1, c->stream);
   const bool warm = c->ws.alloc && c->ws.mode != 0 && nkeys > 0;
-  if (warm) {
-    drop_tail(c);
-    c->carry_pending = false;
-  }
-  // a deferred last iterate z: gbuf = z, and the offset seed is that of
-  // r - z, whose residual in the old graph is z
-  const bool tail_in = c->tail_slot >= 0;
-  if (tail_in) {
-    launch_tail_unscale(a, c->S, c->fp64, c->tail_slot, c->stream);
+  if (warm) drop_carry(c);
+  // carried vectors into gbuf (deferred last iterates unscaled with the
+  // degrees before the batch); the offset seed is that of r - p
+  if (c->tail_slot >= 0 || c->pend) {
+    const uint64_t tails = c->tail_slot >= 0 ? c->tail_cols : 0;
+    launch_carry_prepare(a, c->S, c->fp64, c->tail_slot, tails, c->pend & ~tails, c->stream);
+    c->pend |= tails;
     c->tail_slot = -1;
+    c->tail_cols = 0;
   }
   if (nkeys > 0) {
     HIP_TRY(c, launch_offset_seed(c->S, c->keys[0], c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->g[0].v,
-                                  c->r, tail_in ? c->gbuf : nullptr, c->ybuf, c->stamp, c->ctl, b1,
+                                  c->r, c->pend ? c->gbuf : nullptr, c->ybuf, c->stamp, c->ctl, b1,
                                   1.0 - c->cfg.c, (int32_t)nkeys, c->flags, c->pos, c->temp, c->temp_bytes,
                                   4 * c->n_cu, c->stream));
     for (int o = 0; o < norient; ++o)
@@ -1744,28 +1764,22 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   // stored edge count (an undirected self-loop is stored once; the count only
   // steers the sparse/dense switch and the visited-edge statistic)
   c->m += (b->n_ins - b->n_del) * (c->undirected ? 2 : 1) - c->ctl_h->node_dels;
-  // a residual evaluated after the previous update (or the deferred last
-  // iterate) joins this update's seed: the run then converges to the new
-  // scores from an exact residual; after a residual the error bound restarts
-  // from this run's truncation
-  const bool resid_in = c->carry_pending;
-  const bool carried = resid_in || tail_in;
-  c->carry_pending = false;
-  c->last_carried = carried;
-  if (carried) launch_carry_seed(a, c->S, c->fp64, tail_in, c->stream);
   if (warm) RWR_TRY(warm_prepare(c));
-  launch_slot0_epilogue(a, c->S, c->fp64, c->stream, tail_in ? 2 : 1);
-  // a carried vector is spread over the graph: the run goes dense at once
-  const int cchunk = c->carry_iters_ema > 0.0 ? (int)std::lround(c->carry_iters_ema) : 3;
-  const bool keep = !warm && !(c->ws.alloc && c->ws.mode != 0) &&
-                    (c->carry_level >= 3 || (c->carry_level == 2 && c->tail_ema >= 0.5 * c->budget));
-  RWR_TRY(run_slots(c, carried ? MODE_DENSE : MODE_SPARSE, -1.0, 0.0, carried ? std::max(1, cchunk) : 0, keep));
-  const double inc = account_run(c, resid_in, tail_in);
+  launch_slot0_epilogue(a, c->S, c->fp64, c->stream);
+  const bool keep = c->carry_level >= 2 && !(c->ws.alloc && c->ws.mode != 0);
+  RWR_TRY(run_slots(c, MODE_SPARSE, -1.0, 0.0, keep, c->pend));
+  // columns whose pending vector joined the run (it reached the dense phase)
+  uint64_t inj = 0;
+  double cl = 0.0;
+  for (int j = 0; j < c->n_seeds; ++j)
+    if (((c->pend >> j) & 1ull) && c->ctl_h->inj[j]) {
+      inj |= 1ull << j;
+      cl = std::max(cl, c->pend_l1[j]);
+    }
+  c->last_carry_l1 = cl;
+  c->pend &= ~inj;
+  const double inc = account_run(c, false, inj);
   c->tail_ema = c->tail_ema < 0.0 ? inc : std::max(inc, 0.5 * (c->tail_ema + inc));
-  if (carried) {
-    const double its = std::max(0, c->ctl_h->iter - 1);
-    c->carry_iters_ema = c->carry_iters_ema < 0.0 ? its : 0.7 * c->carry_iters_ema + 0.3 * its;
-  }
   fill_stats(c, st);
   if (st && warm) {
     st->ws_region = c->ws.nR;

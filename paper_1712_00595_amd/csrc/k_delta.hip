@@ -542,11 +542,7 @@ __global__ void k_reset_batch(Ctl *ctl, int demand_only) {
   ctl->heavy_stale = 0;
   if (!demand_only) {
     ctl->node_dels = 0;
-    for (int j = 0; j < RWR_MAX_COLS; ++j) {
-      ctl->dr_l1[j] = 0.0;
-      ctl->qoff_l1[j] = 0.0;
-      ctl->carry_l1[j] = 0.0;
-    }
+    for (int j = 0; j < RWR_MAX_COLS; ++j) ctl->dr_l1[j] = 0.0;
   }
 }
 

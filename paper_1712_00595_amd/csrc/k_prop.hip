@@ -375,11 +375,9 @@ __global__ __launch_bounds__(BLOCK) void k_epi(SlotArgs a, int k, double scale, 
     a.ybuf[kk] = 0.0;
     const int d = a.out.len[v];
     if (act) {
-      // a deferred last iterate in the seed is already part of r
-      const double add = first == 2 ? y - a.gbuf[kk] : y;
-      a.r[kk] += add;
+      a.r[kk] += y;
       nrm += fabs(y);
-      sm += add;
+      sm += y;
       xnew[kk] = d ? (XT)(y / (double)d) : (XT)0;
     } else {
       xnew[kk] = (XT)0;
@@ -1061,60 +1059,68 @@ __global__ __launch_bounds__(BLOCK) void k_heavy_epi(SlotArgs a, int k, int entr
   block_publish<S>(nrm, sm, 0, 0, a.part, a.part_i, entry_base + blockIdx.x, sh);
 }
 
-// The residual of the previous update carried into this update's seed:
-// ybuf += g and the node is stamped, so x^(0) = q_offset + g.  (The exact
-// residual of the current scores in the new graph is q_offset + g, where g
-// is their residual in the old graph, Section 3.1 applied to r.)  Adds
-// ||q_offset||_1 and ||g||_1 of each column to the batch statistics.  With
-// clear_x (g is a deferred iterate still held in x) both x buffers are
-// cleared for the run.
-template <typename XT, int S>
-__global__ __launch_bounds__(BLOCK) void k_carry_seed(SlotArgs a, int clear_x) {
-  __shared__ double sq[BLOCK], sg[BLOCK];
-  const int32_t st = a.ctl->stamp;
-  const int j = threadIdx.x % S;
-  constexpr int NPB = BLOCK / S;
-  double nq = 0.0, ng = 0.0;
-  for (int v = blockIdx.x * NPB + threadIdx.x / S; v < a.n; v += gridDim.x * NPB) {
-    const int64_t kk = col_index(v, S, j);
-    if (clear_x) {
-      ((XT *)a.x[0])[kk] = (XT)0;
-      ((XT *)a.x[1])[kk] = (XT)0;
+// Carried vectors (one column per seed, FP64 in gbuf).  A pending vector p is
+// part of r, and r - p has residual p in the graph before the batch (Section
+// 3.1's expansion).  Two kinds: the last iterate x^(k) of a run that ended in
+// the dense phase, left in x[last] pre-scaled by 1/d_out (it was added to r,
+// and r - x^(k) has residual x^(k)); and the FP64 residual g of an earlier
+// check, added to r when it is kept.
+//
+// Before an update: gbuf = d_out * x[last] for the columns in tail_mask (with
+// the degrees before the batch), the pending vector for the columns in
+// keep_mask, 0 elsewhere; both x buffers are cleared for the run.
+template <typename XT>
+__global__ __launch_bounds__(BLOCK) void k_carry_prepare(SlotArgs a, int S, int last, uint64_t tail_mask,
+                                                         uint64_t keep_mask) {
+  XT *__restrict__ x0 = (XT *)a.x[0];
+  XT *__restrict__ x1 = (XT *)a.x[1];
+  const XT *__restrict__ xl = (last == 1) ? x1 : x0;
+  const int64_t total = (int64_t)a.n * S;
+  for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < total; i += (int64_t)gridDim.x * BLOCK) {
+    const int j = (int)(i % S);
+    double p = 0.0;
+    if (last >= 0 && ((tail_mask >> j) & 1ull)) {
+      const int d = a.out.len[i / S];
+      p = d ? (double)xl[i] * (double)d : 0.0;
+    } else if ((keep_mask >> j) & 1ull) {
+      p = a.gbuf[i];
     }
-    // ybuf is zero off the offset seed's stamped nodes
-    const double g = a.gbuf[kk], y = a.ybuf[kk];
-    nq += fabs(y);
-    if (g != 0.0) {
-      ng += fabs(g);
-      a.ybuf[kk] = y + g;
-      a.stamp[v] = st;
-    }
-  }
-  sq[threadIdx.x] = nq;
-  sg[threadIdx.x] = ng;
-  __syncthreads();
-  if (threadIdx.x < S) {
-    double tq = 0.0, tg = 0.0;
-    for (int i = threadIdx.x; i < BLOCK; i += S) tq += sq[i], tg += sg[i];
-    if (tq != 0.0) atomic_add_f64(&a.ctl->qoff_l1[threadIdx.x], tq);
-    if (tg != 0.0) atomic_add_f64(&a.ctl->carry_l1[threadIdx.x], tg);
+    a.gbuf[i] = p;
+    x0[i] = (XT)0;
+    x1[i] = (XT)0;
   }
 }
 
-// The last iterate x^(k) of the previous update, left unpropagated in x[last]
-// (pre-scaled by 1/d_out): r already contains it, and the residual of
-// r - x^(k) in the old graph is x^(k) itself (Section 3.1's expansion), so it
-// is carried like a residual.  gbuf = d_out * x[last] with the degrees before
-// the batch.  x is left as it is (a batch found invalid afterwards leaves the
-// iterate deferred); the carry kernel clears it.
-template <typename XT>
-__global__ __launch_bounds__(BLOCK) void k_tail_unscale(SlotArgs a, int S, int last) {
-  const XT *__restrict__ xl = (const XT *)a.x[last];
-  const int64_t total = (int64_t)a.n * S;
-  for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < total; i += (int64_t)gridDim.x * BLOCK) {
-    const int d = a.out.len[i / S];
-    a.gbuf[i] = d ? (double)xl[i] * (double)d : 0.0;
+// The pending vectors join the run at its first dense sweep (slot k): they are
+// added to that sweep's input, x^(k-1) += p (pre-scaled by the new 1/d_out),
+// so that every later iterate carries their propagation.  r already holds p.
+// Columns that stopped before the dense phase keep theirs pending; ctl->inj
+// records which columns took it.
+template <typename XT, int S>
+__global__ __launch_bounds__(BLOCK) void k_inject(SlotArgs a, int k, uint64_t mask) {
+  Ctl *ctl = a.ctl;
+  if (!slot_live(ctl, MODE_DENSE, k)) return;
+  XT *__restrict__ xin = (XT *)a.x[(k - 1) & 1];
+  const int j = threadIdx.x % S;
+  constexpr int NPB = BLOCK / S;
+  const bool take = ((mask >> j) & 1ull) && ctl->active[j] != 0;
+  if (blockIdx.x == 0 && threadIdx.x < S) ctl->inj[threadIdx.x] = take ? 1 : 0;
+  if (!take) return;
+  for (int v = blockIdx.x * NPB + threadIdx.x / S; v < a.n; v += gridDim.x * NPB) {
+    const int64_t kk = col_index(v, S, j);
+    const double p = a.gbuf[kk];
+    const int d = a.out.len[v];
+    if (p != 0.0 && d) xin[kk] = (XT)((double)xin[kk] + p / (double)d);
   }
+}
+
+// r += g for a residual that is kept as a pending vector (then sigma is
+// recomputed exactly)
+template <int S>
+__global__ __launch_bounds__(BLOCK) void k_add_resid(SlotArgs a) {
+  const int64_t total = (int64_t)a.n * S;
+  for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < total; i += (int64_t)gridDim.x * BLOCK)
+    if ((int)(i % S) < a.n_seeds) a.r[i] += a.gbuf[i];
 }
 
 // Restart term of seed vectors after a residual sweep: g += c q on every
@@ -1234,6 +1240,7 @@ __global__ void k_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double ep
     ctl->norm1[t] = 0.0;
     ctl->sum_norm[t] = 0.0;
     ctl->last_it[t] = 0;
+    ctl->inj[t] = 0;
   }
   if (t == 0) {
     ctl->prop_err = 0;
@@ -1335,40 +1342,40 @@ void launch_seed_init_q(const SlotArgs &a, int S, hipStream_t st) {
   RWR_DISPATCH_S(S, hipLaunchKernelGGL(k_seed_init_q<SS>, dim3(a.grid_light), dim3(BLOCK), 0, st, a));
 }
 
-void launch_carry_seed(const SlotArgs &a, int S, bool fp64, bool clear_x, hipStream_t st) {
+void launch_inject(const SlotArgs &a, int S, bool fp64, int k, uint64_t mask, hipStream_t st) {
   if (fp64) {
-    RWR_DISPATCH_S(S, hipLaunchKernelGGL((k_carry_seed<double, SS>), dim3(a.grid_light), dim3(BLOCK), 0, st, a,
-                                         clear_x ? 1 : 0));
+    RWR_DISPATCH_S(S, hipLaunchKernelGGL((k_inject<double, SS>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, k, mask));
   } else {
-    RWR_DISPATCH_S(S, hipLaunchKernelGGL((k_carry_seed<float, SS>), dim3(a.grid_light), dim3(BLOCK), 0, st, a,
-                                         clear_x ? 1 : 0));
+    RWR_DISPATCH_S(S, hipLaunchKernelGGL((k_inject<float, SS>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, k, mask));
   }
+}
+
+void launch_add_resid(const SlotArgs &a, int S, hipStream_t st) {
+  RWR_DISPATCH_S(S, hipLaunchKernelGGL(k_add_resid<SS>, dim3(a.grid_light), dim3(BLOCK), 0, st, a));
 }
 
 template <typename XT, int S>
-static void slot0_impl(const SlotArgs &a, hipStream_t st, int first) {
-  hipLaunchKernelGGL((k_epi<XT, S>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, 0, 1.0, first);
+static void slot0_impl(const SlotArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL((k_epi<XT, S>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, 0, 1.0, 1);
   decide_impl<S>(a, KIND_SPARSE, a.grid_light, 0, st);
 }
 
-void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st, int first) {
+void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st) {
   if (fp64) {
-    RWR_DISPATCH_S(S, (slot0_impl<double, SS>(a, st, first)));
+    RWR_DISPATCH_S(S, (slot0_impl<double, SS>(a, st)));
   } else {
-    RWR_DISPATCH_S(S, (slot0_impl<float, SS>(a, st, first)));
+    RWR_DISPATCH_S(S, (slot0_impl<float, SS>(a, st)));
   }
 }
 
-template <typename XT>
-static void tail_unscale_impl(const SlotArgs &a, int S, int last, hipStream_t st) {
-  hipLaunchKernelGGL((k_tail_unscale<XT>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, S, last);
-}
-
-void launch_tail_unscale(const SlotArgs &a, int S, bool fp64, int last, hipStream_t st) {
+void launch_carry_prepare(const SlotArgs &a, int S, bool fp64, int last, uint64_t tail_mask, uint64_t keep_mask,
+                          hipStream_t st) {
   if (fp64)
-    tail_unscale_impl<double>(a, S, last, st);
+    hipLaunchKernelGGL((k_carry_prepare<double>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, S, last, tail_mask,
+                       keep_mask);
   else
-    tail_unscale_impl<float>(a, S, last, st);
+    hipLaunchKernelGGL((k_carry_prepare<float>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, S, last, tail_mask,
+                       keep_mask);
 }
 
 // dense sweep (or residual) + heavy rows + decision; the heavy-row kernel

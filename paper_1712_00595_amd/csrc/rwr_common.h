@@ -71,8 +71,7 @@ struct Ctl {
   double sum_norm[RWR_MAX_COLS];  // sum over the run's iterations of ||x^(i)||_1
   int32_t last_it[RWR_MAX_COLS];  // iteration of last_norm
   double dr_l1[RWR_MAX_COLS];     // ||D r_old||_1 of the batch (D: row L1 norms of B~ - A~)
-  double qoff_l1[RWR_MAX_COLS];   // ||q_offset||_1 when a carried vector joined the seed
-  double carry_l1[RWR_MAX_COLS];  // ||carried vector||_1 of this update
+  int32_t inj[RWR_MAX_COLS];      // the column's pending carried vector joined this run
 };
 
 // history of per-iteration norms: hist[i * S + j] = ||x^(i)[:, j]||_1

@@ -117,15 +117,17 @@ void launch_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double eps, int
                       int64_t dense_nodes, hipStream_t st, int32_t hist_base = 0);
 void launch_seed_init(const SlotArgs &a, int S, hipStream_t st);
 void launch_seed_init_q(const SlotArgs &a, int S, hipStream_t st);
-// ybuf += gbuf on every node with a nonzero residual (stamped): a carried
-// residual or deferred iterate; clear_x also clears both x buffers
-void launch_carry_seed(const SlotArgs &a, int S, bool fp64, bool clear_x, hipStream_t st);
-// deferred last iterate: gbuf = d_out * x[last] (unscaled, with the degrees
-// before the batch is applied); x is left unchanged
-void launch_tail_unscale(const SlotArgs &a, int S, bool fp64, int last, hipStream_t st);
-// first = 2: the seed holds a deferred last iterate (gbuf) that r already
-// contains, so r and sigma take y - gbuf
-void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st, int first = 1);
+// carried vectors in gbuf before an update: d_out * x[last] for tail_mask
+// columns (last = -1: none), the pending vector for keep_mask columns, 0
+// elsewhere; clears both x buffers
+void launch_carry_prepare(const SlotArgs &a, int S, bool fp64, int last, uint64_t tail_mask, uint64_t keep_mask,
+                          hipStream_t st);
+// before the first dense slot k of a run: x^(k-1) += gbuf / d_out for the
+// active columns in mask (ctl->inj records them)
+void launch_inject(const SlotArgs &a, int S, bool fp64, int k, uint64_t mask, hipStream_t st);
+// r += gbuf over the seed columns
+void launch_add_resid(const SlotArgs &a, int S, hipStream_t st);
+void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st);
 // iteration slot k (computes x^(k)): sparse = push + epilogue, dense = pull
 void launch_sparse_slot(const SlotArgs &a, int S, bool fp64, int k, hipStream_t st);
 // ev0/ev1 (optional) are recorded on st right before and after the sweep
