@@ -199,6 +199,72 @@ def test_carried_residual_matches_oracle(monkeypatch, prec, n_seeds):
             assert _l1(a, b) <= 2 * gate
 
 
+def test_carried_vector_through_errors_sparse_runs_and_warm_start():
+    # a carried vector left by one update survives rejected batches and an
+    # update whose run never reaches the dense phase (it stays pending), joins
+    # the next dense run, and is given up when the learned warm start takes
+    # over; the scores stay within the reported bound of the oracle throughout
+    print("[carry paths]", flush=True)
+    from oracle import gnn
+
+    g = rmat_graph(11, 20000, dead_end_self_loops=True)
+    s = int(np.argmax(g.out_degree()))
+    model = EdgeSetModel(g.n, g.src, g.dst)
+    rng = np.random.default_rng(21)
+    n, src, dst = g.n, g.src, g.dst
+
+    def check(ctx, st, what):
+        ref = oracle.rwr_static(n, src, dst, s, 0.15)
+        err = _l1(ctx.scores(0), ref)
+        assert err <= st["err_bound"] + 1e-13, (what, err, st)
+        assert st["err_bound"] <= 2 * 1e-9 / 0.15, (what, st)
+
+    with _ctx(g, [s], eps=1e-9, precision="fp32") as ctx:
+        for t in range(2):
+            b = mixed_batch(rng, model, 20, 20)
+            st = ctx.update_batch(b)
+            n, src, dst = oracle.apply_batch(n, src, dst, b)
+            check(ctx, st, f"warm-up {t}")
+        assert st["dense_iters"] > 0  # its last iterate is left for the next update
+        before = ctx.scores(0)
+        e_src, e_dst = int(src[0]), int(dst[0])
+        with pytest.raises(rwr.RwrError):
+            ctx.update(ins_src=[e_src], ins_dst=[e_dst])
+        with pytest.raises(rwr.RwrError):
+            ctx.update(ins_src=[0], ins_dst=[n + 5])
+        assert np.array_equal(ctx.scores(0), before)
+        # an edge out of a node with score 0: the offset seed is empty, the run
+        # stays sparse and the carried vector stays pending
+        sc = ctx.scores(0)
+        u = int(np.flatnonzero(sc == 0.0)[0])
+        w = next(v for v in range(g.n) if v != u and not model.has(u, v))
+        b = Batch(np.array([u], np.int32), np.array([w], np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32), 0)
+        model.insert(u, w)
+        st = ctx.update_batch(b)
+        n, src, dst = oracle.apply_batch(n, src, dst, b)
+        assert st["dense_iters"] == 0 and st["carry_l1"] == 0.0, st
+        check(ctx, st, "sparse run")
+        b = mixed_batch(rng, model, 20, 20)
+        st = ctx.update_batch(b)
+        n, src, dst = oracle.apply_batch(n, src, dst, b)
+        assert st["dense_iters"] > 0 and st["carry_l1"] > 0.0, st
+        check(ctx, st, "joined")
+        # the learned warm start (a network that predicts the offset seed)
+        p = {k: np.zeros(gnn.SHAPES[k]) for k in gnn.ORDER}
+        p["W0"][2, 0], p["W0"][2, 1] = 1.0, -1.0
+        for layer in range(1, gnn.LAYERS + 1):
+            p[f"Ws{layer}"][0, 0] = p[f"Ws{layer}"][1, 1] = 1.0
+        p["wo"][0], p["wo"][1] = 1.0, -1.0
+        ctx.model_set(gnn.pack(p).astype(np.float32))
+        ctx.warm_start("predict", hops=2)
+        for t in range(2):
+            b = mixed_batch(rng, model, 20, 20)
+            st = ctx.update_batch(b)
+            n, src, dst = oracle.apply_batch(n, src, dst, b)
+            assert st["carry_l1"] == 0.0, st
+            check(ctx, st, f"warm start {t}")
+
+
 @pytest.mark.parametrize("eps", [1e-6, 1e-9])
 def test_single_edge_stream_within_gate(eps):
     print(f"[stream] eps={eps}", flush=True)
