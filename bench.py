@@ -608,7 +608,7 @@ def main() -> int:
         traffic = measured_traffic(sweep_bytes)
         roof = {
             "bound": "hbm",
-            "kernel": "k_pull_wv<float, KIND_DENSE, 4, 4096> (dense sweep, one seed, FP32 gather)",
+            "kernel": "k_pull_wv<float, KIND_DENSE, 4, 6144> (dense sweep, one seed, FP32 gather)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -845,7 +845,8 @@ __device__ __forceinline__ WvRows wv_rows(const SlotArgs &a, int b, int lane) {
 // descending out-degree, so the leading entries of the gathered vector are
 // the most gathered ones: the workgroup copies the first CACHE entries into
 // LDS once and reads them there (4096 FP32 entries serve about a third of
-// the gathers of an R-MAT graph of a million nodes).
+// the gathers of an R-MAT graph of a million nodes; 6144 are kept, which
+// still allows five workgroups per CU).
 template <typename XT, int KIND, int NWV, int CACHE>
 __global__ __launch_bounds__(NWV * RWR_WAVE) void k_pull_wv(SlotArgs a, int k) {
   constexpr int BLOCKW = NWV * RWR_WAVE;
@@ -1389,7 +1390,7 @@ static void pull_impl(const SlotArgs &a, int k, hipStream_t st, hipEvent_t ev0 =
   if (ev0) (void)hipEventRecord(ev0, st);
   if constexpr (S == 1) {
     // cached leading entries: 16 KB of the FP32 vector, or of r / d_out
-    constexpr int CW = (KIND == KIND_DENSE && sizeof(XT) == 4) ? 4096 : KIND == KIND_RESID ? 2048 : 0;
+    constexpr int CW = (KIND == KIND_DENSE && sizeof(XT) == 4) ? 6144 : KIND == KIND_RESID ? 2048 : 0;
     grid = std::max(1, std::min((a.heavy.n_items + a.n_mp + NWAVES - 1) / NWAVES, a.grid_pull));
     hipLaunchKernelGGL((k_pull_wv<XT, KIND, NWAVES, CW>), dim3(grid), dim3(BLOCK), 0, st, a, k);
   } else if constexpr (S == 2) {
