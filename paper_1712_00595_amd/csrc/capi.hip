@@ -992,7 +992,11 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
   launch_reset_run(c->ctl, c->S, mask, eps_ref, c->max_iters, dense_thresh(c), c->n / 16 + 1, c->stream,
                    c->max_iters + 2);
   launch_refine_init(a, c->S, c->fp64, c->stream);
-  RWR_TRY(run_slots(c, MODE_DENSE, resid * (1.0 - cc), eps_ref));
+  // in a stream the refinement's last iterate is left for the next update too
+  // (otherwise its truncation, near the budget, pushes the next update's
+  // bound over it and the refinements follow one another)
+  const bool keep = carry && c->carry_level >= 2;
+  RWR_TRY(run_slots(c, MODE_DENSE, resid * (1.0 - cc), eps_ref, keep));
   if (c->ctl_h->prop_err != 0) {
     c->stale = true;
     c->err = "refinement did not converge";
@@ -1003,8 +1007,12 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
     if (!((mask >> j) & 1ull)) continue;
     const double sig = std::fabs(c->ctl_h->sigma[j]);
     // truncation of the refinement + FP32 rounding of propagating g
-    c->err_bound[j] = 2.0 * (1.0 - cc) / cc * c->ctl_h->last_norm[j] / sig +
-                      8.0 * fpf * c->ctl_h->red_norm[j] / (cc * sig);
+    const double tail = 2.0 * (1.0 - cc) / cc * c->ctl_h->last_norm[j] / sig;
+    c->err_bound[j] = tail + 8.0 * fpf * c->ctl_h->red_norm[j] / (cc * sig);
+    if ((c->tail_cols >> j) & 1ull) {
+      c->pend_b[j] = tail;
+      c->pend_l1[j] = c->ctl_h->last_norm[j];
+    }
   }
   if (st) st->refined = 1;
   return RWR_OK;
