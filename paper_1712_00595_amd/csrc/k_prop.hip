@@ -106,6 +106,7 @@ struct DecideShared {
   double s_sum[RWR_MAX_COLS];
   int64_t s_i[2];
   int s_active;
+  int s_bad;  // a column's norm or sum is not finite
 };
 
 template <typename XT, int S, int KIND>
@@ -123,11 +124,33 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
   __shared__ DecideShared sh;
   constexpr int NW = DECIDE_BLOCK / RWR_WAVE;
   Ctl *ctl = a.ctl;
-  if (kind == KIND_SPARSE && !slot_live(ctl, MODE_SPARSE, new_list)) return;
-  if (kind == KIND_DENSE && !slot_live(ctl, MODE_DENSE, new_list)) return;
   constexpr int TPC = DECIDE_BLOCK / S;
   const int t = threadIdx.x, j = t % S, q = t / S;
   const int lane = t % RWR_WAVE, w = t / RWR_WAVE;
+  // The control values this kernel reads are loaded up front, together with
+  // the partials below, so that their latencies overlap (the slot test would
+  // otherwise hold every later load back).  Only this kernel writes them.
+  const int mode0 = ctl->mode, it = ctl->iter;
+  const bool actj = ctl->active[j] != 0;
+  const double eps0 = ctl->eps;
+  const int hb = ctl->hist_base;
+  double sig0 = 0.0, sumn0 = 0.0;
+  if (t < S) {
+    sig0 = ctl->sigma[t];
+    sumn0 = ctl->sum_norm[t];
+  }
+  int perr0 = 0, maxit = 0, dit = 0, stp = 0;
+  int64_t fed = 0, dth = 0, dno = 0, vis = 0;
+  if (t == 0) {
+    perr0 = ctl->prop_err;
+    maxit = ctl->max_iters;
+    dit = ctl->dense_iters;
+    stp = ctl->stamp;
+    fed = ctl->fedges;
+    dth = ctl->dense_thresh;
+    dno = ctl->dense_nodes;
+    vis = ctl->visited;
+  }
   // heavy rows to finish here (at most two per thread, see fold_max): their
   // row data is loaded first, so that it arrives with the partials
   const int nh = fold ? a.heavy.n_rows : 0;
@@ -146,9 +169,13 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
     A += a.part[e * entry_stride<S>() + 2 * j];
     B += a.part[e * entry_stride<S>() + 2 * j + 1];
   }
+  // a slot enqueued past the end of the run, or of the other phase
+  const bool live_par = ((it ^ new_list) & 1) == 0;
+  if (kind == KIND_SPARSE && !(mode0 == MODE_SPARSE && live_par)) return;
+  if (kind == KIND_DENSE && !(mode0 == MODE_DENSE && live_par)) return;
   if (nh > 0) {
     const double c1 = 1.0 - a.c;
-    const bool act = ctl->active[j] != 0;
+    const bool act = actj;
     XT *__restrict__ xnext = (XT *)a.x[new_list];
     double hn = 0.0, hs = 0.0;
 #pragma unroll
@@ -184,7 +211,10 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
     sh.wi[w][0] = ia;
     sh.wi[w][1] = ib;
   }
-  if (t == 0) sh.s_active = 0;
+  if (t == 0) {
+    sh.s_active = 0;
+    sh.s_bad = 0;
+  }
   __syncthreads();
   if (t < S) {
     double X = 0.0, Y = 0.0;
@@ -207,21 +237,22 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
     }
     return;
   }
-  const int it = ctl->iter;
   if (t < S) {
     const double nr = sh.s_norm[t];
     const double su = sh.s_sum[t];
-    const bool act = ctl->active[t] != 0;
-    a.hist[(int64_t)(ctl->hist_base + it) * S + t] = act ? nr : 0.0;
-    if (act) {
-      ctl->sigma[t] += su;
+    a.hist[(int64_t)(hb + it) * S + t] = actj ? nr : 0.0;
+    if (actj) {
+      ctl->sigma[t] = sig0 + su;
       ctl->last_norm[t] = nr;
       ctl->last_it[t] = it;
-      ctl->sum_norm[t] += nr;
+      ctl->sum_norm[t] = sumn0 + nr;
       if (it == 0) ctl->norm0[t] = nr;
       if (it == 1) ctl->norm1[t] = nr;
-      if (!isfinite(nr) || !isfinite(su)) ctl->prop_err = ERR_ENUMERIC;
-      if (it >= 1 && nr <= ctl->eps)
+      if (!isfinite(nr) || !isfinite(su)) {
+        ctl->prop_err = ERR_ENUMERIC;
+        sh.s_bad = 1;
+      }
+      if (it >= 1 && nr <= eps0)
         ctl->active[t] = 0;
       else
         atomicAdd(&sh.s_active, 1);
@@ -233,23 +264,23 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
     ctl->n_active = na;
     ctl->iter = it + 1;
     // the push of a sparse slot read the out-rows of the previous frontier
-    if (kind == KIND_SPARSE) ctl->visited += ctl->fedges;
-    if (kind == KIND_DENSE) ctl->dense_iters += 1;
+    if (kind == KIND_SPARSE) ctl->visited = vis + fed;
+    if (kind == KIND_DENSE) ctl->dense_iters = dit + 1;
     if (kind == KIND_DENSE || kind == KIND_REFINE) ctl->ended_dense = 1;
-    int mode = ctl->mode;
-    if (ctl->prop_err != 0 || na == 0) {
+    int mode = mode0;
+    if (perr0 != 0 || sh.s_bad || na == 0) {
       mode = MODE_DONE;
-    } else if (it >= ctl->max_iters) {
+    } else if (it >= maxit) {
       mode = MODE_DONE;
       ctl->prop_err = ERR_ENOCONV;
     } else if (kind == KIND_REFINE) {
       mode = MODE_DENSE;
-    } else if (kind == KIND_SPARSE && (sh.s_i[0] > ctl->dense_thresh || sh.s_i[1] > ctl->dense_nodes)) {
+    } else if (kind == KIND_SPARSE && (sh.s_i[0] > dth || sh.s_i[1] > dno)) {
       mode = MODE_DENSE;
     }
     ctl->fedges = kind == KIND_SPARSE ? sh.s_i[0] : 0;
     if (kind == KIND_SPARSE) ctl->fcount[new_list] = (int32_t)sh.s_i[1];
-    ctl->stamp = ctl->stamp + 1;
+    ctl->stamp = stp + 1;
     ctl->hpack = 0;
     ctl->mode = mode;
   }
