@@ -296,6 +296,9 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
 // epilogue scans the stamps).  A longer row gets a slot in the long-row list
 // and a range of chunk numbers from one 64-bit atomic (slot in the high half,
 // chunk base in the low half), so the chunk bases increase with the slot.
+// Each wavefront tests 64 consecutive nodes at once (one coalesced load of
+// their frontier stamps) and hands the frontier nodes among them to its
+// groups of G lanes, one node per group at a time.
 template <typename XT, int S, int G>
 __global__ __launch_bounds__(BLOCK) void k_push(SlotArgs a, int k) {
   Ctl *ctl = a.ctl;
@@ -304,28 +307,40 @@ __global__ __launch_bounds__(BLOCK) void k_push(SlotArgs a, int k) {
   const XT *__restrict__ xcur = (const XT *)a.x[cur];
   const int32_t st = ctl->stamp;
   constexpr int P = G / S;
-  const int lane = threadIdx.x % RWR_WAVE, gl = lane % G, j = gl % S, p = gl / S;
-  constexpr int GPB = BLOCK / G;
-  const int ngroups = gridDim.x * GPB;
-  for (int u = blockIdx.x * GPB + threadIdx.x / G; u < a.n; u += ngroups) {
-    if (a.fstamp[u] != st - 1) continue;  // not in the frontier of x^(k-1)
-    const int d = a.out.len[u];
-    if (d > PUSH_LIGHT_MAX) {
-      if (gl == 0) {
-        const unsigned long long nch = (unsigned long long)((d + PUSH_CHUNK - 1) / PUSH_CHUNK);
-        const unsigned long long old = atomicAdd((unsigned long long *)&ctl->hpack, (1ull << 32) | nch);
-        const int slot = (int)(old >> 32);
-        a.hfront[slot] = u;
-        a.hbase[slot] = (int32_t)(old & 0xffffffffull);
+  constexpr int GPW = RWR_WAVE / G;  // groups per wavefront
+  const int lane = threadIdx.x % RWR_WAVE, gl = lane % G, j = gl % S, p = gl / S, grp = lane / G;
+  const int nwv = gridDim.x * (BLOCK / RWR_WAVE);
+  for (int base = (blockIdx.x * (BLOCK / RWR_WAVE) + threadIdx.x / RWR_WAVE) * RWR_WAVE; base < a.n;
+       base += nwv * RWR_WAVE) {
+    const int ul = base + lane;
+    // frontier of x^(k-1) among the 64 nodes (the mask is the same in every lane)
+    unsigned long long m = __ballot(ul < a.n && a.fstamp[ul] == st - 1);
+    while (m) {
+      // group grp takes the grp-th lowest frontier node left in m
+      unsigned long long mm = m;
+      for (int q = 0; q < grp; ++q) mm &= mm - 1;
+#pragma unroll
+      for (int q = 0; q < GPW; ++q) m &= m - 1;
+      if (!mm) continue;
+      const int u = base + __builtin_ctzll(mm);
+      const int d = a.out.len[u];
+      if (d > PUSH_LIGHT_MAX) {
+        if (gl == 0) {
+          const unsigned long long nch = (unsigned long long)((d + PUSH_CHUNK - 1) / PUSH_CHUNK);
+          const unsigned long long old = atomicAdd((unsigned long long *)&ctl->hpack, (1ull << 32) | nch);
+          const int slot = (int)(old >> 32);
+          a.hfront[slot] = u;
+          a.hbase[slot] = (int32_t)(old & 0xffffffffull);
+        }
+        continue;
       }
-      continue;
-    }
-    const XT xv = xcur[col_index(u, S, j)];
-    const int o = a.out.off[u];
-    for (int e = p; e < d; e += P) {
-      const int v = a.out.adj[o + e];
-      if (xv != (XT)0) atomic_add_f64(&a.ybuf[col_index(v, S, j)], (double)xv);
-      if (j == 0) a.stamp[v] = st;
+      const XT xv = xcur[col_index(u, S, j)];
+      const int o = a.out.off[u];
+      for (int e = p; e < d; e += P) {
+        const int v = a.out.adj[o + e];
+        if (xv != (XT)0) atomic_add_f64(&a.ybuf[col_index(v, S, j)], (double)xv);
+        if (j == 0) a.stamp[v] = st;
+      }
     }
   }
 }
