@@ -1590,6 +1590,27 @@ static rwr_status ensure_batch(rwr_ctx *c, int64_t nkeys, int64_t nints) {
   return RWR_OK;
 }
 
+// per-orientation arguments of the batch kernels (check: the out orientation
+// tests the batch against the graph)
+static OrientPair orient_pair(const rwr_ctx *c, bool check) {
+  OrientPair P{};
+  const int po = pull_orient(c);
+  for (int o = 0; o < 2; ++o) {
+    OrientArgs &q = P.o[o];
+    q.keys = c->keys[o];
+    q.seg = c->seg[o];
+    q.row = c->row[o];
+    q.g = c->g[o].v;
+    q.t_dold = c->t_dold[o];
+    q.t_dnew = c->t_dnew[o];
+    q.orient = o;
+    q.check = (check && o == 0) ? 1 : 0;
+    q.heavy_limit = o == po ? c->heavy_limit : 0;
+    q.e_cap = c->g[o].e_cap;
+  }
+  return P;
+}
+
 rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   if (!c || !b) return RWR_EINVAL;
   const double t0 = now_ms();
@@ -1694,7 +1715,6 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   launch_reset_batch(c->ctl, 0, c->stream);
 
   const int norient = c->undirected ? 1 : 2;
-  const int po = pull_orient(c);
   if (nkeys > 0) {
     launch_make_keys(ins_s, ins_d, b->n_ins, del_s, del_d, b->n_del, n_new, b1, c->undirected ? 1 : 0, c->perm,
                      nd > 0 ? c->nmark : nullptr, c->keys[0], c->keys[1], c->ctl, c->stream);
@@ -1709,9 +1729,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
         HIP_TRY(c, sort_segment_large(c->keys[o], c->keys_alt, (int32_t)nkeys, b1, c->flags, c->pos, c->seg[o],
                                       c->row[o], c->temp, c->temp_bytes, c->ctl, o, c->stream));
     }
-    for (int o = 0; o < norient; ++o)
-      launch_validate_plan(c->keys[o], c->seg[o], c->row[o], c->g[o].v, b1, c->t_dold[o], c->t_dnew[o], c->ctl, o,
-                           o == 0 ? 1 : 0, o == po ? c->heavy_limit : 0, (int32_t)nkeys, c->stream);
+    launch_validate_plan(orient_pair(c, true), norient, b1, c->ctl, (int32_t)nkeys, c->stream);
   }
   if (nd > 0) launch_node_unmark(dn_dev, nd, c->perm, c->nmark, c->stream);
   RWR_TRY(read_ctl(c));
@@ -1739,9 +1757,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     }
     if (!again) break;
     launch_reset_batch(c->ctl, 1, c->stream);
-    for (int o = 0; o < norient; ++o)
-      launch_validate_plan(c->keys[o], c->seg[o], c->row[o], c->g[o].v, b1, c->t_dold[o], c->t_dnew[o], c->ctl, o, 0,
-                           o == po ? c->heavy_limit : 0, (int32_t)nkeys, c->stream);
+    launch_validate_plan(orient_pair(c, false), norient, b1, c->ctl, (int32_t)nkeys, c->stream);
     RWR_TRY(read_ctl(c));
   }
   // the batch is valid: commit the node count and apply
@@ -1765,9 +1781,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
                                   c->r, c->pend ? c->gbuf : nullptr, c->ybuf, c->stamp, c->ctl, b1,
                                   1.0 - c->cfg.c, (int32_t)nkeys, c->flags, c->pos, c->temp, c->temp_bytes,
                                   4 * c->n_cu, c->stream));
-    for (int o = 0; o < norient; ++o)
-      launch_apply(c->keys[o], c->seg[o], c->row[o], c->t_dold[o], c->t_dnew[o], c->g[o].v, c->ctl, o, b1,
-                   (int32_t)nkeys, c->g[o].e_cap, c->stream);
+    launch_apply(orient_pair(c, false), norient, b1, c->ctl, (int32_t)nkeys, c->stream);
   }
   // stored edge count (an undirected self-loop is stored once; the count only
   // steers the sparse/dense switch and the visited-edge statistic)

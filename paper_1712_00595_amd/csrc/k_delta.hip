@@ -306,11 +306,19 @@ __device__ __forceinline__ int32_t grown_cap(int32_t d) { return d + max(4, d >>
 // checks the batch against the graph: an inserted edge must be absent
 // (EEXIST), a deleted edge present (ENOENT).  Records old/new degree of each
 // touched row and the arena demand of rows that outgrow their capacity.
-__global__ void k_validate_plan(const uint64_t *__restrict__ keys, const int32_t *__restrict__ seg,
-                                const int32_t *__restrict__ row, const int32_t *__restrict__ off,
-                                const int32_t *__restrict__ len, const int32_t *__restrict__ cap,
-                                const int32_t *__restrict__ adj, int b1, int32_t *__restrict__ t_dold,
-                                int32_t *__restrict__ t_dnew, Ctl *ctl, int orient, int check, int heavy_limit) {
+// Both orientations in one launch (blockIdx.y selects one).
+__global__ void k_validate_plan(OrientPair P, int b1, Ctl *ctl) {
+  const OrientArgs &q = P.o[blockIdx.y];
+  const uint64_t *__restrict__ keys = q.keys;
+  const int32_t *__restrict__ seg = q.seg;
+  const int32_t *__restrict__ row = q.row;
+  const int32_t *__restrict__ off = q.g.off;
+  const int32_t *__restrict__ len = q.g.len;
+  const int32_t *__restrict__ cap = q.g.cap;
+  const int32_t *__restrict__ adj = q.g.adj;
+  int32_t *__restrict__ t_dold = q.t_dold;
+  int32_t *__restrict__ t_dnew = q.t_dnew;
+  const int orient = q.orient, check = q.check, heavy_limit = q.heavy_limit;
   const int lane = threadIdx.x % RWR_WAVE;
   const int32_t t = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE;
   if (t >= ctl->nT[orient]) return;
@@ -474,11 +482,19 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
 // One wavefront per touched row: drop deleted entries (stable compaction in
 // place, or into a fresh arena slot when the row outgrows its capacity), then
 // append the inserted entries.
-__global__ void k_apply(const uint64_t *__restrict__ keys, const int32_t *__restrict__ seg,
-                        const int32_t *__restrict__ row, const int32_t *__restrict__ t_dold,
-                        const int32_t *__restrict__ t_dnew, int32_t *__restrict__ off, int32_t *__restrict__ len,
-                        int32_t *__restrict__ cap, int32_t *__restrict__ adj, Ctl *ctl, int orient, int b1,
-                        int64_t e_cap) {
+__global__ void k_apply(OrientPair P, int b1, Ctl *ctl) {
+  const OrientArgs &q = P.o[blockIdx.y];
+  const uint64_t *__restrict__ keys = q.keys;
+  const int32_t *__restrict__ seg = q.seg;
+  const int32_t *__restrict__ row = q.row;
+  const int32_t *__restrict__ t_dold = q.t_dold;
+  const int32_t *__restrict__ t_dnew = q.t_dnew;
+  int32_t *__restrict__ off = q.g.off;
+  int32_t *__restrict__ len = q.g.len;
+  int32_t *__restrict__ cap = q.g.cap;
+  int32_t *__restrict__ adj = q.g.adj;
+  const int orient = q.orient;
+  const int64_t e_cap = q.e_cap;
   if (ctl->err) return;
   const int lane = threadIdx.x % RWR_WAVE;
   const int32_t t = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE;
@@ -613,14 +629,11 @@ size_t sort_temp_bytes(int32_t n_keys) {
   return std::max(a, b);
 }
 
-void launch_validate_plan(const uint64_t *keys, const int32_t *seg, const int32_t *row, const DevGraphView &g, int b1,
-                          int32_t *t_dold, int32_t *t_dnew, Ctl *ctl, int orient, int check, int heavy_limit,
-                          int32_t max_rows, hipStream_t st) {
+void launch_validate_plan(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st) {
   if (max_rows <= 0) return;
   const int waves_per_block = 4;
   const int grid = (max_rows + waves_per_block - 1) / waves_per_block;
-  hipLaunchKernelGGL(k_validate_plan, dim3(grid), dim3(waves_per_block * RWR_WAVE), 0, st, keys, seg, row, g.off,
-                     g.len, g.cap, g.adj, b1, t_dold, t_dnew, ctl, orient, check, heavy_limit);
+  hipLaunchKernelGGL(k_validate_plan, dim3(grid, norient), dim3(waves_per_block * RWR_WAVE), 0, st, P, b1, ctl);
 }
 
 template <int S>
@@ -670,12 +683,9 @@ size_t seed_scan_temp_bytes(int32_t max_rows) {
   return bytes;
 }
 
-void launch_apply(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
-                  const int32_t *t_dnew, const DevGraphView &g, Ctl *ctl, int orient, int b1, int32_t max_rows,
-                  int64_t e_cap, hipStream_t st) {
+void launch_apply(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st) {
   if (max_rows <= 0) return;
   const int waves_per_block = 4;
   const int grid = (max_rows + waves_per_block - 1) / waves_per_block;
-  hipLaunchKernelGGL(k_apply, dim3(grid), dim3(waves_per_block * RWR_WAVE), 0, st, keys, seg, row, t_dold, t_dnew,
-                     g.off, g.len, g.cap, g.adj, ctl, orient, b1, e_cap);
+  hipLaunchKernelGGL(k_apply, dim3(grid, norient), dim3(waves_per_block * RWR_WAVE), 0, st, P, b1, ctl);
 }

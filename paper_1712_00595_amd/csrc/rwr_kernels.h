@@ -94,9 +94,24 @@ hipError_t sort_segment_large(uint64_t *keys, uint64_t *keys_alt, int32_t n_keys
                               int32_t *pos, int32_t *seg, int32_t *row, void *temp, size_t temp_bytes, Ctl *ctl,
                               int orient, hipStream_t st);
 size_t sort_temp_bytes(int32_t n_keys);
-void launch_validate_plan(const uint64_t *keys, const int32_t *seg, const int32_t *row, const DevGraphView &g, int b1,
-                          int32_t *t_dold, int32_t *t_dnew, Ctl *ctl, int orient, int check, int heavy_limit,
-                          int32_t max_rows, hipStream_t st);
+// per-orientation arguments of the batch check and the structural apply;
+// one launch serves both orientations (o[0..norient-1])
+struct OrientArgs {
+  const uint64_t *keys;
+  const int32_t *seg;
+  const int32_t *row;
+  DevGraphView g;
+  int32_t *t_dold;
+  int32_t *t_dnew;
+  int32_t orient;
+  int32_t check;        // test inserted/deleted entries against the graph
+  int32_t heavy_limit;  // count rows that become heavy (pull orientation)
+  int64_t e_cap;        // arena capacity
+};
+struct OrientPair {
+  OrientArgs o[2];
+};
+void launch_validate_plan(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st);
 // q_offset of r - rsub (rsub may be null) into ybuf; touched rows cut into
 // chunks (items: max_rows + 1 ints, item_off: max_rows + 1 ints, temp:
 // seed_scan_temp_bytes(max_rows))
@@ -106,9 +121,7 @@ hipError_t launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, c
                               int32_t max_rows, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
                               int grid, hipStream_t st);
 size_t seed_scan_temp_bytes(int32_t max_rows);
-void launch_apply(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
-                  const int32_t *t_dnew, const DevGraphView &g, Ctl *ctl, int orient, int b1, int32_t max_rows,
-                  int64_t e_cap, hipStream_t st);
+void launch_apply(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st);
 
 // ---- propagation (k_prop.hip); fp64 selects the propagation type
 // hist_base: first row of the norm history this run writes (0 for update
