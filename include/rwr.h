@@ -159,6 +159,13 @@ rwr_status rwr_build_vectors(const rwr_config *cfg, int32_t n, int64_t m, const 
  * propagation on the new graph until ||x^(i)||_1 <= eps, merge into r, and
  * Theorem 4's rescaling.  If the accumulated error bound exceeds the budget,
  * the FP64 residual is evaluated and, if needed, propagated (refinement).
+ * Between updates the library may carry a vector p that r already contains
+ * and that r - p has as its residual (the last iterate of a run that ended in
+ * the dense phase, or a residual that needed no refinement): the next update
+ * then takes the offset seed of r - p and adds p to its first dense sweep
+ * (stats->carry_l1); the scores read between updates are r, within
+ * stats->err_bound.  Environment RWR_CARRY = 0 / 1 / 2: no carrying / the
+ * residual only / both (default).
  * The batch is validated on the device before anything changes: on
  * RWR_EINVAL / RWR_EEXIST / RWR_ENOENT the graph and the scores are
  * unchanged.  On RWR_ENOCONV the graph is updated, the scores hold the
