@@ -11,14 +11,6 @@ __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
 }
-__global__ void k_fill_u8(uint8_t *p, int64_t count, uint8_t v) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-__global__ void k_fill_f64(double *p, int64_t count, double v) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
 __global__ void k_zero_u32(uint32_t *p, int64_t count) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0u;
@@ -28,12 +20,6 @@ static int fill_grid(int64_t count) { return (int)std::max<int64_t>(1, std::min<
 
 void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st) {
   if (count > 0) hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(count)), dim3(256), 0, st, p, count, v);
-}
-void launch_fill_u8(uint8_t *p, int64_t count, uint8_t v, hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_fill_u8, dim3(fill_grid(count)), dim3(256), 0, st, p, count, v);
-}
-void launch_fill_f64(double *p, int64_t count, double v, hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_fill_f64, dim3(fill_grid(count)), dim3(256), 0, st, p, count, v);
 }
 // byte count must be a multiple of 4 (all buffers here are)
 void launch_zero_bytes(void *p, size_t bytes, hipStream_t st) {

@@ -159,8 +159,6 @@ void launch_sigma_exact(const SlotArgs &a, int S, hipStream_t st);
 
 // ---- graph (k_graph.hip)
 void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st);
-void launch_fill_u8(uint8_t *p, int64_t count, uint8_t v, hipStream_t st);
-void launch_fill_f64(double *p, int64_t count, double v, hipStream_t st);
 void launch_zero_bytes(void *p, size_t bytes, hipStream_t st);
 size_t build_temp_bytes(int64_t m, int32_t n);
 hipError_t build_phase1(const int32_t *rows, const int32_t *cols, int64_t m, int32_t n, DevGraphView g, void *temp,
