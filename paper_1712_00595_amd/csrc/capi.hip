@@ -1768,8 +1768,9 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   const bool warm = c->ws.alloc && c->ws.mode != 0 && nkeys > 0;
   if (warm) drop_carry(c);
   // carried vectors into gbuf (deferred last iterates unscaled with the
-  // degrees before the batch); the offset seed is that of r - p
-  if (c->tail_slot >= 0 || c->pend) {
+  // degrees before the batch; normally done at the end of the previous
+  // update); the offset seed is that of r - p
+  if (c->tail_slot >= 0) {
     const uint64_t tails = c->tail_slot >= 0 ? c->tail_cols : 0;
     launch_carry_prepare(a, c->S, c->fp64, c->tail_slot, tails, c->pend & ~tails, c->stream);
     c->pend |= tails;
@@ -1825,6 +1826,16 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     for (int j = 0; j < c->n_seeds; ++j) worst = std::max(worst, c->err_bound[j]);
     st->err_bound = worst;
     st->ms_total = now_ms() - t0;
+  }
+  // A last iterate left in x is unscaled into gbuf now, with the degrees the
+  // next batch starts from, so that this pass runs while the host prepares
+  // the next call (it is not waited for here).
+  if (ret == RWR_OK && c->tail_slot >= 0) {
+    const SlotArgs an = slot_args(c);
+    launch_carry_prepare(an, c->S, c->fp64, c->tail_slot, c->tail_cols, c->pend & ~c->tail_cols, c->stream);
+    c->pend |= c->tail_cols;
+    c->tail_slot = -1;
+    c->tail_cols = 0;
   }
   return ret;
 }
