@@ -1,17 +1,20 @@
 #!/usr/bin/env python3
 """Dynamic RWR update throughput on one MI355X.
 
-Workload (the single-GPU configuration the metric is quoted on): directed
-R-MAT scale 20 (1,048,576 nodes, 16,777,216 edges + a self-loop on every dead
-end), restart c = 0.15, one seed (the largest out-degree node), a stream of
-single-edge updates (50% insertion of a new uniform pair, 50% deletion of a
-uniform existing edge).  A step is one update: delta-apply, offset seed,
-propagation to ||x||_1 <= eps, merge -- the whole hot path.  Propagation runs
-in FP32, scores accumulate in FP64.
+Headline workload (the largest single-GPU configuration by bytes per sweep):
+directed R-MAT scale 22 (4,194,304 nodes, 67,108,864 edges + a self-loop on
+every dead end), restart c = 0.15, 64 seed nodes sampled uniformly, eps = 1e-6
+(error gate 2*eps/c), a stream of batches of log-uniform size in [1, 10^4]
+edge modifications with 1% new nodes carrying 1-8 out-edges.  A step is one
+batch: delta-apply, offset seed for all 64 columns, propagation of the N x 64
+block until every column has ||x||_1 <= eps, merge and the stream error
+check -- the whole hot path.  Propagation runs in FP32, scores accumulate in
+FP64.  ``value`` counts edge and node modifications per second with every
+column kept within the gate; ``--steps`` counts batches.
 
-The headline mode is OSP-T with eps = 1e-9 (error gate 2*eps/c); the same
-stream is also run with eps = 1e-6 and in exact mode (gate 1e-9 on the L1
-error, certified by the library's FP64 residual checks).
+The single-seed scale-20 stream of single-edge updates (eps = 1e-9) is
+reported under ``modes`` (its working set fits the Infinity Cache: a latency
+figure, not an HBM one).
 
 Printed: one JSON line on stdout; progress on stderr.
 """
@@ -56,18 +59,30 @@ def cpu_count_used() -> int:
     return 1
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_pull_wv_rmat20_traffic.md")
+TRAFFIC_C2 = os.path.join(ROOT, "profiles", "k_pull_wv_rmat20_traffic.md")
+TRAFFIC_C3 = os.path.join(ROOT, "profiles", "k_pull_v_rmat22_s64_traffic.md")
 SWEEP_SOURCE = os.path.join(ROOT, "paper_1712_00595_amd", "csrc", "k_prop.hip")
 
 
-def measured_traffic(sweep_bytes: int):
+def host_cpu_model() -> str:
+    """The host CPU's model name (as lscpu prints it)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def measured_traffic(sweep_bytes: int, summary: str = TRAFFIC_C2):
     """HBM bytes of one sweep from the committed counter summary, or None
     when the sweep kernel's source has changed since the counters were taken
     (its sha256 is recorded in the summary) or the workload differs."""
     import hashlib
 
     try:
-        text = open(TRAFFIC_SUMMARY).read()
+        text = open(summary).read()
     except OSError:
         return None
     fields = {}
@@ -88,88 +103,169 @@ def measured_traffic(sweep_bytes: int):
         return None
 
 
-def run_batched_seeds(n_batches: int, check: bool = True) -> dict:
-    """R-MAT scale 22, 64 uniform seeds, batches of log-uniform size in
-    [1, 10^4] edge modifications with 1% new nodes, eps = 1e-6; the dense
-    sweep here is the vectorised multi-column kernel."""
+def stage_batches(batches):
+    """The batches' arrays copied to HBM before the clock starts: one device
+    array per field, each batch a view into them."""
+    import torch
+
+    cat = {}
+    for f in ("ins_src", "ins_dst", "del_src", "del_dst"):
+        parts = [getattr(b, f) for b in batches]
+        cat[f] = torch.as_tensor(np.concatenate(parts).astype(np.int32), device="cuda")
+    oi = np.concatenate([[0], np.cumsum([b.n_ins for b in batches])])
+    od = np.concatenate([[0], np.cumsum([b.n_del for b in batches])])
+    return [(cat["ins_src"][oi[i]:oi[i + 1]], cat["ins_dst"][oi[i]:oi[i + 1]],
+             cat["del_src"][od[i]:od[i + 1]], cat["del_dst"][od[i]:od[i + 1]], b.n_new_nodes)
+            for i, b in enumerate(batches)]
+
+
+def run_batched_seeds(K: int, W: int, check: bool = True, cpu_baseline: bool = True) -> dict:
+    """The headline: R-MAT scale 22, 64 uniform seeds, batches of log-uniform
+    size in [1, 10^4] edge modifications with 1% new nodes, eps = 1e-6; the
+    dense sweep here is the vectorised multi-column kernel.  W warm-up
+    batches, then K timed batches staged in HBM.  The timed pass runs the
+    library's default path (no per-launch events, HIP-graph replay on); a
+    second pass over the same batches on a fresh context times every launch
+    of the dense sweep with HIP events for the roofline."""
     import torch
 
     from paper_1712_00595_amd import rwr
     from synth.configs import RMAT22_BATCHED, stream_for
 
     w = RMAT22_BATCHED
+    S = w.n_seeds
     t = time.time()
     g = w.graph()
     seeds = w.seeds(g)
-    stream = stream_for(w, w.model(g), n_batches)
-    log(f"[{w.name}] graph n={g.n} m={g.m}, {len(stream)} batches ({time.time() - t:.1f}s)")
+    stream = stream_for(w, w.model(g), W + K)
+    log(f"[{w.name}] graph n={g.n} m={g.m}, {W} warm-up + {K} timed batches ({time.time() - t:.1f}s)")
     eps = w.eps[0]
-    t = time.time()
-    ctx = rwr.Context(g.n, g.src, g.dst, seeds, c=w.c, eps=eps, precision="fp32")
-    torch.cuda.synchronize()
-    build_s = time.time() - t
-    ctx.profile(True)
-    ctx.profile_read(reset=True)
-    mods = sum(b.size for b in stream)
-    t0 = time.perf_counter()
-    stats = [ctx.update_batch(b) for b in stream]
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    P = ctx.profile_read(reset=True)
-    n_f = ctx.n
-    m_f = ctx.m
+    dev = stage_batches(stream[W:])
+    mods = sum(b.size for b in stream[W:])
+
+    def one_pass(profile: bool):
+        t = time.time()
+        ctx = rwr.Context(g.n, g.src, g.dst, seeds, c=w.c, eps=eps, precision="fp32")
+        torch.cuda.synchronize()
+        build_s = time.time() - t
+        for b in stream[:W]:
+            ctx.update_batch(b)
+        ctx.profile(profile)
+        ctx.profile_read(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = [ctx.update(*u[:4], n_new_nodes=u[4]) for u in dev]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        return ctx, stats, el, ctx.profile_read(reset=True), build_s
+
+    ctx, stats, el, _, build_s = one_pass(False)
+    lat = np.array([s["ms_total"] for s in stats])
     res = {
-        "batches": len(stream),
+        "batches": K,
+        "warmup_batches": W,
         "edge_and_node_modifications": mods,
         "modifications_per_s": mods / el,
-        "batches_per_s": len(stream) / el,
-        "seed_columns_x_batches_per_s": 64 * len(stream) / el,
+        "batches_per_s": K / el,
+        "ms_per_batch": 1e3 * el / K,
+        "seed_columns_x_batches_per_s": S * K / el,
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
         "build_s": build_s,
         "mean_iters": float(np.mean([s["iters"] for s in stats])),
         "mean_dense_sweeps": float(np.mean([s["dense_iters"] for s in stats])),
+        "residual_checks": int(sum(s["checked"] for s in stats)),
         "refinements": int(sum(s["refined"] for s in stats)),
         "max_err_bound": float(max(s["err_bound"] for s in stats)),
         "gate": 2 * eps / w.c,
+        "sweep_shape": ctx.sweep_shape(),
     }
+    log(f"[{w.name}] {res['batches_per_s']:.2f} batches/s, {res['modifications_per_s']:.0f} modifications/s, "
+        f"iters {res['mean_iters']:.2f} (dense {res['mean_dense_sweeps']:.2f}), checks {res['residual_checks']}, "
+        f"refinements {res['refinements']}, bound {res['max_err_bound']:.2e}")
+    final_scores = {}
+    cols = [0, S - 1]
+    if check:
+        for j in cols:
+            final_scores[j] = ctx.scores(j)
+    n_f, m_f = ctx.n, ctx.m
+    ctx.close()
+
+    # the roofline pass: the same batches, every sweep launch timed with
+    # HIP events on the library's stream
+    ctx, stats_p, el_p, P, _ = one_pass(True)
+    shape = ctx.sweep_shape()
+    ctx.close()
+    res["profiled_pass_batches_per_s"] = K / el_p
     launches = P["dense_sweeps"] + P["idle_launches"]
     if P["dense_sweeps"]:
-        sweep_bytes = dense_sweep_bytes(n_f, m_f, 64)
+        sweep_bytes = dense_sweep_bytes(n_f, m_f, S)
+        avg_us = 1e3 * P["dense_ms"] / launches
+        bytes_per_launch = sweep_bytes * P["dense_sweeps"] / launches
+        achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
+        traffic = measured_traffic(sweep_bytes, TRAFFIC_C3)
         res["roofline"] = {
             "bound": "hbm",
-            "kernel": "k_pull_v<float, 64, 16, KIND_DENSE> (dense sweep, 64 columns)",
-            "achieved": sweep_bytes * P["dense_sweeps"] / (P["dense_ms"] * 1e-3) / 1e9,
+            "kernel": f"k_pull_v<float, {S}, {shape['lanes_per_row']}, KIND_DENSE> (dense sweep, {S} columns)",
+            "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None if traffic is None else traffic * P["dense_sweeps"] / launches,
             "bytes_per_sweep": sweep_bytes,
-            "avg_launch_us": 1e3 * P["dense_ms"] / launches,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_us": avg_us,
             "avg_sweep_us": 1e3 * P["dense_ms"] / P["dense_sweeps"],
             "launches": launches,
             "idle_launches": P["idle_launches"],
         }
-        res["roofline"]["frac"] = res["roofline"]["achieved"] / HBM_PEAK_GBS
-    # sampled parity: 2 of the 64 columns against the oracle's static solve
-    if not check:
-        ctx.close()
-        log(f"[{w.name}] {res['batches_per_s']:.2f} batches/s, {res['modifications_per_s']:.0f} modifications/s")
-        return res
-    import oracle
+        log(f"[{w.name}] sweep {res['roofline']['avg_sweep_us']:.1f} us, {achieved:.0f} GB/s algorithmic "
+            f"= {achieved / HBM_PEAK_GBS:.3f} of peak")
 
-    t = time.time()
-    n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream)
-    from paper_1712_00595_amd import accuracy
+    if check or cpu_baseline:
+        import oracle
 
-    cols = [0, 63]
-    errs, ranks = [], []
-    for j in cols:
-        ref = oracle.rwr_static(n2, s2, d2, int(seeds[j]), w.c)
-        got = ctx.scores(j)
-        errs.append(float(np.abs(got - ref).sum()))
-        ranks.append(rank_accuracy(accuracy, got, ref))
-    res["parity"] = {"columns": cols, "l1_vs_oracle": errs, "rank_accuracy": ranks, "ok": max(errs) <= res["gate"],
-                     "oracle_s": time.time() - t}
-    ctx.close()
-    log(f"[{w.name}] {res['batches_per_s']:.2f} batches/s, {res['modifications_per_s']:.0f} modifications/s, "
-        f"parity max L1 {max(errs):.2e}")
+        from paper_1712_00595_amd import accuracy
+    if check:
+        # sampled parity: the first and last columns against the oracle's
+        # static solve of the final graph
+        t = time.time()
+        n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream)
+        errs, ranks = [], []
+        for j in cols:
+            ref = oracle.rwr_static(n2, s2, d2, int(seeds[j]), w.c)
+            got = final_scores[j]
+            errs.append(float(np.abs(got - ref).sum()))
+            ranks.append(rank_accuracy(accuracy, got, ref))
+        res["parity"] = {"columns": cols, "l1_vs_oracle": errs, "gate": res["gate"], "rank_accuracy": ranks,
+                         "ok": max(errs) <= res["gate"], "oracle_s": time.time() - t}
+        log(f"[{w.name}] parity: max L1 {max(errs):.3e} vs gate {res['gate']:.3e} ({time.time() - t:.1f}s)")
+    if cpu_baseline:
+        # the oracle's Algorithm 1 (one seed column, single-threaded FP64,
+        # full edge sweeps) on the first batch of the stream from the oracle's
+        # static scores; scaled to all 64 columns
+        t = time.time()
+        r_old = oracle.rwr_static(g.n, g.src, g.dst, int(seeds[0]), w.c)
+        static_s = time.time() - t
+        b0 = stream[0]
+        t = time.time()
+        n1, s1, d1 = oracle.apply_batch(g.n, g.src, g.dst, b0)
+        oracle.osp((g.n, g.src, g.dst), (n1, s1, d1), r_old, w.c, eps, renorm=1)
+        col_s = time.time() - t
+        res["cpu_baseline"] = {
+            "value": b0.size / (S * col_s),
+            "unit": "updates/s",
+            "cores": cpu_count_used(),
+            "kind": "oracle",
+            "sample": f"Algorithm 1 (oracle/rwr_oracle.c, single-threaded FP64, full edge sweeps) for seed column 0 "
+                      f"on the first batch of the stream ({b0.size} modifications) from the oracle's static scores, "
+                      f"{col_s:.1f}s; rate scaled to all {S} columns; static solve of the initial graph took "
+                      f"{static_s:.1f}s",
+            "static_solve_s": static_s,
+            "host_cpu": host_cpu_model(),
+            "host_threads": os.cpu_count(),
+        }
+        log(f"[{w.name}] cpu baseline: {res['cpu_baseline']['value']:.3f} updates/s ({col_s:.1f}s for one column)")
     return res
 
 
@@ -420,22 +516,223 @@ def run_churn(n_batches: int, check: bool) -> dict:
     return res
 
 
+def run_c2_modes(names, K: int, W: int, check: bool, cpu_baseline: bool, cpu_sample: int,
+                 host_batches: bool = False) -> dict:
+    """The scale-20 single-seed stream of single-edge updates: the modes in
+    ``names`` (eps = 1e-9 first), each a fresh context, W warm-up and K timed
+    updates staged in HBM."""
+    import torch
+
+    from paper_1712_00595_amd import rwr
+    from synth.configs import RMAT20_SINGLE_EDGE, stream_for
+
+    w = RMAT20_SINGLE_EDGE
+    t = time.time()
+    g = w.graph()
+    seeds = w.seeds(g)
+    model = w.model(g)
+    stream = stream_for(w, model, W + K)
+    log(f"graph n={g.n} m={g.m} seed={int(seeds[0])} stream={len(stream)} updates ({time.time() - t:.1f}s)")
+
+    c = w.c
+    all_modes = {
+        "eps1e-9": dict(eps=1e-9, err_budget=0.0, gate=2 * 1e-9 / c),
+        "eps1e-6": dict(eps=1e-6, err_budget=0.0, gate=2 * 1e-6 / c),
+        # exact: the certified budget is the 1e-9 gate itself; eps is chosen so
+        # one update's truncation bound is a tenth of it
+        "exact": dict(eps=1e-9 * c / (20 * (1 - c)), err_budget=1e-9, gate=1e-9),
+        # global PageRank: the uniform restart vector instead of the seed node
+        "pagerank": dict(eps=1e-9, err_budget=0.0, gate=2 * 1e-9 / c, q="uniform"),
+    }
+    headline = names[0]
+
+    # the timed updates' batches, staged in HBM before the clock starts: one
+    # device array per field, each update passes views into them
+    dev_stream = stage_batches(stream[W:W + K])
+
+    def run(name, host_batches=False, profile=False):
+        mcfg = all_modes[name]
+        t = time.time()
+        if mcfg.get("q") == "uniform":
+            ctx = rwr.Context(g.n, g.src, g.dst, q=np.full(g.n, 1.0 / g.n), c=c, eps=mcfg["eps"],
+                              err_budget=mcfg["err_budget"], precision="fp32")
+        else:
+            ctx = rwr.Context(g.n, g.src, g.dst, seeds, c=c, eps=mcfg["eps"], err_budget=mcfg["err_budget"],
+                              precision="fp32")
+        log(f"[{name}{' host batches' if host_batches else ''}] context built in {time.time() - t:.2f}s")
+        for b in stream[:W]:
+            ctx.update_batch(b)
+        ctx.profile(profile)
+        ctx.profile_read(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if host_batches:
+            stats = [ctx.update_batch(b) for b in stream[W:W + K]]
+        else:
+            stats = [ctx.update(*u[:4], n_new_nodes=u[4]) for u in dev_stream]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = ctx.profile_read(reset=True)
+        return ctx, stats, t1 - t0, prof
+
+    results = {}
+    final_ctx_scores = None
+    for name in names:
+        mcfg = all_modes[name]
+        ctx, stats, el, _ = run(name)
+        lat = np.array([s["ms_total"] for s in stats])
+        iters = np.array([s["iters"] for s in stats])
+        dense = np.array([s["dense_iters"] for s in stats])
+        res = {
+            "updates_per_s": K / el,
+            "ms_per_update": 1e3 * el / K,
+            "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)),
+            "mean_iters": float(iters.mean()),
+            "mean_dense_sweeps": float(dense.mean()),
+            "residual_checks": int(sum(s["checked"] for s in stats)),
+            "refinements": int(sum(s["refined"] for s in stats)),
+            "max_err_bound": float(max(s["err_bound"] for s in stats)),
+            "eps": mcfg["eps"],
+            "gate": mcfg["gate"],
+            "visited_edges_per_update": float(np.mean([s["visited_edges"] for s in stats])),
+        }
+        if mcfg.get("q") == "uniform" and check:
+            import oracle
+            from paper_1712_00595_amd import accuracy
+
+            n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream[:W + K])
+            qp = np.zeros(n2)
+            qp[: g.n] = 1.0 / g.n  # nodes added by the stream restart with probability 0
+            ref = oracle.rwr_static_vector(n2, s2, d2, qp, c)
+            got = ctx.scores(0)
+            err = float(np.abs(got - ref).sum())
+            res["parity"] = {"l1_vs_oracle": err, "ok": err <= mcfg["gate"],
+                             "rank_accuracy": rank_accuracy(accuracy, got, ref)}
+        if name == headline:
+            src_e, dst_e, _ = ctx.export()
+            res["n_final"], res["m_final"] = ctx.n, int(src_e.shape[0])
+            if check:
+                final_ctx_scores = ctx.scores(0)
+        log(f"[{name}] {res['updates_per_s']:.1f} updates/s, {res['ms_per_update']:.3f} ms/update, "
+            f"iters {res['mean_iters']:.1f} (dense {res['mean_dense_sweeps']:.1f}), "
+            f"checks {res['residual_checks']} refinements {res['refinements']}, bound {res['max_err_bound']:.2e}")
+        ctx.close()
+        if name == headline:
+            # the same updates again with every sweep launch timed by HIP
+            # events (the roofline of the single-column sweep)
+            ctx, _, el_p, prof = run(name, profile=True)
+            res["prof"] = prof
+            res["profiled_pass_updates_per_s"] = K / el_p
+            ctx.close()
+        if name == headline and host_batches:
+            # the same updates with each batch handed over in host memory (one
+            # small host-to-device copy per update inside the call)
+            ctx, _, el_h, _ = run(name, host_batches=True)
+            res["host_batches_updates_per_s"] = K / el_h
+            log(f"[{name} host batches] {K / el_h:.1f} updates/s")
+            ctx.close()
+        results[name] = res
+
+    H = results[headline]
+    # roofline of the dominant kernel: the dense sweep (k_pull_wv, one pull
+    # over every in-row).  Every launch in the timed region is timed; the
+    # algorithmic bytes per launch average the launches that swept (launches
+    # that found the run converged move no data but count in the time).
+    roof = None
+    P = H["prof"]
+    launches = P["dense_sweeps"] + P["idle_launches"]
+    if P["dense_sweeps"] > 0:
+        sweep_bytes = dense_sweep_bytes(H["n_final"], H["m_final"])
+        avg_us = 1e3 * P["dense_ms"] / launches
+        bytes_per_launch = sweep_bytes * P["dense_sweeps"] / launches
+        achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
+        traffic = measured_traffic(sweep_bytes, TRAFFIC_C2)
+        roof = {
+            "bound": "hbm",
+            "kernel": "k_pull_wv<float, KIND_DENSE, 4, 6144> (dense sweep, one seed, FP32 gather)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None if traffic is None else traffic * P["dense_sweeps"] / launches,
+            "bytes_per_sweep": sweep_bytes,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_us": avg_us,
+            "avg_sweep_us": 1e3 * P["dense_ms"] / P["dense_sweeps"],
+            "launches": launches,
+            "idle_launches": P["idle_launches"],
+        }
+
+    parity = None
+    cpu = None
+    if check or cpu_baseline:
+        import oracle
+
+        if check and final_ctx_scores is not None:
+            t = time.time()
+            # the final graph: the whole stream applied to the edge list
+            n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream)
+            from paper_1712_00595_amd import accuracy
+
+            ref = oracle.rwr_static(n2, s2, d2, int(seeds[0]), c)
+            err = float(np.abs(final_ctx_scores - ref).sum())
+            parity = {"l1_vs_oracle": err, "gate": H["gate"], "ok": err <= H["gate"],
+                      "rank_accuracy": rank_accuracy(accuracy, final_ctx_scores, ref),
+                      "oracle_static_s": time.time() - t}
+            log(f"parity: L1 {err:.3e} vs gate {H['gate']:.3e} ({time.time() - t:.1f}s)")
+        if cpu_baseline:
+            t = time.time()
+            r_old = oracle.rwr_static(g.n, g.src, g.dst, int(seeds[0]), c)
+            static_s = time.time() - t
+            n0, s0, d0 = g.n, g.src, g.dst
+            sample = stream[:cpu_sample]
+            t = time.time()
+            for b in sample:
+                n1, s1, d1 = oracle.apply_batch(n0, s0, d0, b)
+                out = oracle.osp((n0, s0, d0), (n1, s1, d1), r_old, c, all_modes[headline]["eps"], renorm=1)
+                r_old, n0, s0, d0 = out["r_new"], n1, s1, d1
+            el = time.time() - t
+            cpu = {
+                "value": len(sample) / el,
+                "unit": "updates/s",
+                "cores": cpu_count_used(),
+                "kind": "oracle",
+                "sample": f"Algorithm 1 (oracle/rwr_oracle.c, single-threaded FP64, full edge sweeps) on the first "
+                          f"{len(sample)} updates of the same stream at eps={all_modes[headline]['eps']:g}, from the "
+                          f"oracle's static scores; static solve of the initial graph took {static_s:.1f}s",
+                "static_solve_s": static_s,
+                "host_cpu": host_cpu_model(),
+                "host_threads": os.cpu_count(),
+            }
+            log(f"cpu baseline: {cpu['value']:.3f} updates/s (static solve {static_s:.1f}s)")
+
+    H["roofline"] = roof
+    H["cpu_baseline"] = cpu
+    H["parity"] = parity
+    H["workload"] = w.name
+    H["cache_resident"] = "the working set (about 0.1 GB) fits the 256 MB Infinity Cache: a latency figure"
+    return results
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200, help="timed batches of the headline workload")
+    ap.add_argument("--warmup", type=int, default=5, help="warm-up batches of the headline workload")
     ap.add_argument("--modes", default="eps1e-9",
-                    help="comma list of: eps1e-9 (headline), eps1e-6, exact, pagerank; or all")
+                    help="modes of the scale-20 single-edge stream reported under 'modes': comma list of "
+                         "eps1e-9, eps1e-6, exact, pagerank; all; or none")
+    ap.add_argument("--c2-steps", type=int, default=1000, help="timed updates of the single-edge stream")
+    ap.add_argument("--c2-warmup", type=int, default=20, help="warm-up updates of the single-edge stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-check", action="store_true", help="skip the final oracle comparison")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle comparisons")
     ap.add_argument("--no-host-batches", action="store_true",
-                    help="skip the second headline run that hands batches over in host memory")
-    ap.add_argument("--cpu-sample", type=int, default=3, help="updates timed on the CPU oracle")
+                    help="skip the single-edge stream's run that hands batches over in host memory")
+    ap.add_argument("--cpu-sample", type=int, default=3, help="single-edge updates timed on the CPU oracle")
     ap.add_argument("--workloads", default="",
-                    help="extra workloads run after the headline, comma list of: rmat22_batched_seeds, "
+                    help="extra workloads run after the headline, comma list of: "
                          "rmat21_learned_warm_start, rmat23_undirected_churn, rmat20_delta_study")
-    ap.add_argument("--batches", type=int, default=200, help="batches of the batched-seed workload")
     ap.add_argument("--churn-batches", type=int, default=10, help="batches of the undirected churn workload")
     ap.add_argument("--churn-check", action="store_true", help="check one column of the churn workload (slow)")
     ap.add_argument("--learned-train", type=int, default=500, help="training updates of the learned workload")
@@ -474,218 +771,35 @@ def main() -> int:
         return 3
     torch.cuda.set_device(0)
 
-    from paper_1712_00595_amd import rwr
-    from synth.configs import RMAT20_SINGLE_EDGE, stream_for
-
-    w = RMAT20_SINGLE_EDGE
-    K, W = args.steps, args.warmup
-    t = time.time()
-    g = w.graph()
-    seeds = w.seeds(g)
-    model = w.model(g)
-    stream = stream_for(w, model, W + K)
-    log(f"graph n={g.n} m={g.m} seed={int(seeds[0])} stream={len(stream)} updates ({time.time() - t:.1f}s)")
-
-    c = w.c
-    all_modes = {
-        "eps1e-9": dict(eps=1e-9, err_budget=0.0, gate=2 * 1e-9 / c),
-        "eps1e-6": dict(eps=1e-6, err_budget=0.0, gate=2 * 1e-6 / c),
-        # exact: the certified budget is the 1e-9 gate itself; eps is chosen so
-        # one update's truncation bound is a tenth of it
-        "exact": dict(eps=1e-9 * c / (20 * (1 - c)), err_budget=1e-9, gate=1e-9),
-        # global PageRank: the uniform restart vector instead of the seed node
-        "pagerank": dict(eps=1e-9, err_budget=0.0, gate=2 * 1e-9 / c, q="uniform"),
-    }
-    names = list(all_modes) if args.modes == "all" else args.modes.split(",")
-    headline = names[0]
-
-    # the timed updates' batches, staged in HBM before the clock starts: one
-    # device array per field, each update passes views into them
-    def stage(batches):
-        cat = {}
-        for f in ("ins_src", "ins_dst", "del_src", "del_dst"):
-            parts = [getattr(b, f) for b in batches]
-            cat[f] = torch.as_tensor(np.concatenate(parts).astype(np.int32), device="cuda")
-        oi = np.concatenate([[0], np.cumsum([b.n_ins for b in batches])])
-        od = np.concatenate([[0], np.cumsum([b.n_del for b in batches])])
-        return [(cat["ins_src"][oi[i]:oi[i + 1]], cat["ins_dst"][oi[i]:oi[i + 1]],
-                 cat["del_src"][od[i]:od[i + 1]], cat["del_dst"][od[i]:od[i + 1]], b.n_new_nodes)
-                for i, b in enumerate(batches)]
-
-    dev_stream = stage(stream[W:W + K])
-
-    def run(name, host_batches=False, profile=False):
-        mcfg = all_modes[name]
-        t = time.time()
-        if mcfg.get("q") == "uniform":
-            ctx = rwr.Context(g.n, g.src, g.dst, q=np.full(g.n, 1.0 / g.n), c=c, eps=mcfg["eps"],
-                              err_budget=mcfg["err_budget"], precision="fp32")
-        else:
-            ctx = rwr.Context(g.n, g.src, g.dst, seeds, c=c, eps=mcfg["eps"], err_budget=mcfg["err_budget"],
-                              precision="fp32")
-        log(f"[{name}{' host batches' if host_batches else ''}] context built in {time.time() - t:.2f}s")
-        for b in stream[:W]:
-            ctx.update_batch(b)
-        ctx.profile(profile)
-        ctx.profile_read(reset=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        if host_batches:
-            stats = [ctx.update_batch(b) for b in stream[W:W + K]]
-        else:
-            stats = [ctx.update(*u[:4], n_new_nodes=u[4]) for u in dev_stream]
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        prof = ctx.profile_read(reset=True)
-        return ctx, stats, t1 - t0, prof
-
-    results = {}
-    final_ctx_scores = None
-    for name in names:
-        mcfg = all_modes[name]
-        ctx, stats, el, prof = run(name, profile=(name == headline))
-        lat = np.array([s["ms_total"] for s in stats])
-        iters = np.array([s["iters"] for s in stats])
-        dense = np.array([s["dense_iters"] for s in stats])
-        res = {
-            "updates_per_s": K / el,
-            "ms_per_update": 1e3 * el / K,
-            "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)),
-            "mean_iters": float(iters.mean()),
-            "mean_dense_sweeps": float(dense.mean()),
-            "residual_checks": int(sum(s["checked"] for s in stats)),
-            "refinements": int(sum(s["refined"] for s in stats)),
-            "max_err_bound": float(max(s["err_bound"] for s in stats)),
-            "eps": mcfg["eps"],
-            "gate": mcfg["gate"],
-            "visited_edges_per_update": float(np.mean([s["visited_edges"] for s in stats])),
-        }
-        if mcfg.get("q") == "uniform" and not args.no_check:
-            import oracle
-            from paper_1712_00595_amd import accuracy
-
-            n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream[:W + K])
-            qp = np.zeros(n2)
-            qp[: g.n] = 1.0 / g.n  # nodes added by the stream restart with probability 0
-            ref = oracle.rwr_static_vector(n2, s2, d2, qp, c)
-            got = ctx.scores(0)
-            err = float(np.abs(got - ref).sum())
-            res["parity"] = {"l1_vs_oracle": err, "ok": err <= mcfg["gate"],
-                             "rank_accuracy": rank_accuracy(accuracy, got, ref)}
-        if name == headline:
-            res["prof"] = prof
-            src_e, dst_e, _ = ctx.export()
-            res["n_final"], res["m_final"] = ctx.n, int(src_e.shape[0])
-            if not args.no_check:
-                final_ctx_scores = ctx.scores(0)
-        log(f"[{name}] {res['updates_per_s']:.1f} updates/s, {res['ms_per_update']:.3f} ms/update, "
-            f"iters {res['mean_iters']:.1f} (dense {res['mean_dense_sweeps']:.1f}), "
-            f"checks {res['residual_checks']} refinements {res['refinements']}, bound {res['max_err_bound']:.2e}")
-        ctx.close()
-        if name == headline and not args.no_host_batches:
-            # the same updates with each batch handed over in host memory (one
-            # small host-to-device copy per update inside the call)
-            ctx, _, el_h, _ = run(name, host_batches=True)
-            res["host_batches_updates_per_s"] = K / el_h
-            log(f"[{name} host batches] {K / el_h:.1f} updates/s")
-            ctx.close()
-        results[name] = res
-
-    H = results[headline]
-    # roofline of the dominant kernel: the dense sweep (k_pull_wv, one pull
-    # over every in-row).  Every launch in the timed region is timed; the
-    # algorithmic bytes per launch average the launches that swept (launches
-    # that found the run converged move no data but count in the time).
-    roof = None
-    P = H["prof"]
-    launches = P["dense_sweeps"] + P["idle_launches"]
-    if P["dense_sweeps"] > 0:
-        sweep_bytes = dense_sweep_bytes(H["n_final"], H["m_final"])
-        avg_us = 1e3 * P["dense_ms"] / launches
-        bytes_per_launch = sweep_bytes * P["dense_sweeps"] / launches
-        achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
-        traffic = measured_traffic(sweep_bytes)
-        roof = {
-            "bound": "hbm",
-            "kernel": "k_pull_wv<float, KIND_DENSE, 4, 6144> (dense sweep, one seed, FP32 gather)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None if traffic is None else traffic * P["dense_sweeps"] / launches,
-            "bytes_per_sweep": sweep_bytes,
-            "bytes_per_launch": bytes_per_launch,
-            "avg_launch_us": avg_us,
-            "avg_sweep_us": 1e3 * P["dense_ms"] / P["dense_sweeps"],
-            "launches": launches,
-            "idle_launches": P["idle_launches"],
-        }
-
-    parity = None
-    cpu = None
-    if not args.no_check or not args.no_cpu_baseline:
-        import oracle
-
-        if not args.no_check and final_ctx_scores is not None:
-            t = time.time()
-            # the final graph: the whole stream applied to the edge list
-            n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream)
-            from paper_1712_00595_amd import accuracy
-
-            ref = oracle.rwr_static(n2, s2, d2, int(seeds[0]), c)
-            err = float(np.abs(final_ctx_scores - ref).sum())
-            parity = {"l1_vs_oracle": err, "gate": H["gate"], "ok": err <= H["gate"],
-                      "rank_accuracy": rank_accuracy(accuracy, final_ctx_scores, ref),
-                      "oracle_static_s": time.time() - t}
-            log(f"parity: L1 {err:.3e} vs gate {H['gate']:.3e} ({time.time() - t:.1f}s)")
-        if not args.no_cpu_baseline:
-            t = time.time()
-            r_old = oracle.rwr_static(g.n, g.src, g.dst, int(seeds[0]), c)
-            static_s = time.time() - t
-            n0, s0, d0 = g.n, g.src, g.dst
-            sample = stream[: args.cpu_sample]
-            t = time.time()
-            for b in sample:
-                n1, s1, d1 = oracle.apply_batch(n0, s0, d0, b)
-                out = oracle.osp((n0, s0, d0), (n1, s1, d1), r_old, c, all_modes[headline]["eps"], renorm=1)
-                r_old, n0, s0, d0 = out["r_new"], n1, s1, d1
-            el = time.time() - t
-            cpu = {
-                "value": len(sample) / el,
-                "unit": "updates/s",
-                "cores": cpu_count_used(),
-                "kind": "oracle",
-                "sample": f"Algorithm 1 (oracle/rwr_oracle.c, single-threaded FP64, full edge sweeps) on the first "
-                          f"{len(sample)} updates of the same stream at eps={all_modes[headline]['eps']:g}, from the "
-                          f"oracle's static scores; static solve of the initial graph took {static_s:.1f}s",
-                "static_solve_s": static_s,
-                "host_cpu": platform.processor() or platform.machine(),
-                "host_threads": os.cpu_count(),
-            }
-            log(f"cpu baseline: {cpu['value']:.3f} updates/s (static solve {static_s:.1f}s)")
+    check, cpu = not args.no_check, not args.no_cpu_baseline
+    H = run_batched_seeds(args.steps, args.warmup, check, cpu)
+    modes = {}
+    if args.modes != "none":
+        names = ["eps1e-9", "eps1e-6", "exact", "pagerank"] if args.modes == "all" else args.modes.split(",")
+        modes = run_c2_modes(names, args.c2_steps, args.c2_warmup, check, False, args.cpu_sample,
+                             not args.no_host_batches)
 
     extra = {}
     for wname in [x for x in args.workloads.split(",") if x]:
-        if wname == "rmat22_batched_seeds":
-            extra[wname] = run_batched_seeds(args.batches, not args.no_check)
-        elif wname == "rmat21_learned_warm_start":
-            extra[wname] = run_learned(args.learned_train, args.learned_eval, not args.no_check)
+        if wname == "rmat21_learned_warm_start":
+            extra[wname] = run_learned(args.learned_train, args.learned_eval, check)
         elif wname == "rmat23_undirected_churn":
             extra[wname] = run_churn(args.churn_batches, args.churn_check)
         elif wname == "rmat20_delta_study":
-            extra[wname] = run_delta_study(not args.no_check)
+            extra[wname] = run_delta_study(check)
         else:
             raise SystemExit(f"unknown workload {wname}")
 
+    from synth.configs import RMAT22_BATCHED as w
+
     out = {
         "metric": "RWR updates/sec at L1 err<=2eps/c",
-        "value": H["updates_per_s"],
+        "value": H["modifications_per_s"],
         "unit": "updates/s",
         "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": H["ms_per_update"],
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": H["ms_per_batch"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -693,19 +807,22 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": w.name,
-            "graph": f"directed R-MAT scale {w.scale} (a,b,c,d)=(.57,.19,.19,.05), {g.n} nodes, {g.m} stored edges "
-                     f"incl. dead-end self-loops",
-            "c": c,
-            "eps": all_modes[headline]["eps"],
+            "graph": f"directed R-MAT scale {w.scale} (a,b,c,d)=(.57,.19,.19,.05), {w.m} edges + dead-end "
+                     f"self-loops, seeded vertex permutation",
+            "c": w.c,
+            "eps": w.eps[0],
             "gate_l1": H["gate"],
-            "seeds": 1,
-            "updates": "single-edge, 50% insert new uniform pair / 50% delete uniform existing edge",
+            "seeds": w.n_seeds,
+            "step": "one batch of log-uniform size in [1, 10^4] edge modifications (50% insertions of absent "
+                    "pairs / 50% deletions of existing edges) with 1% new nodes carrying 1-8 out-edges; an update "
+                    "is one edge or node modification, every seed column within the gate after every batch",
             "propagation": "f32 vectors, f64 score accumulation",
         },
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "parity": parity,
-        "modes": results,
+        "roofline": H.get("roofline"),
+        "cpu_baseline": H.get("cpu_baseline"),
+        "parity": H.get("parity"),
+        "headline": {k: v for k, v in H.items() if k not in ("roofline", "cpu_baseline", "parity")},
+        "modes": modes,
     }
     if extra:
         out["workloads"] = extra

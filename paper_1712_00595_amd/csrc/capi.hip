@@ -675,7 +675,7 @@ static void tune_begin(rwr_ctx *c) {
     for (int g : {4, 6, 8}) t.cand.push_back({c->pull_lanes, g * cu});
   } else {
     for (int l : {16, 32, 64})
-      for (int g : {4, 5}) t.cand.push_back({l, g * cu});
+      for (int g : {5, 6, 7}) t.cand.push_back({l, g * cu});
   }
   t.ms.assign(t.cand.size(), {});
   t.launched = 0;

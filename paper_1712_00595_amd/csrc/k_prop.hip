@@ -588,24 +588,39 @@ struct VecGather {
   using VT = typename std::conditional<sizeof(GT) == 4, float4, double2>::type;
 };
 
+// One 16-byte gather, kept in its storage type while it is in flight (the
+// FP64 widening happens when it is added, so four gathers in flight hold 16
+// registers, not 32).
 template <typename XT, int S, int KIND>
-__device__ __forceinline__ void gather_vec(const SlotArgs &a, const XT *__restrict__ x, int u, int j0,
-                                           double (&g)[VecGather<XT, KIND>::V]) {
-  using VG = VecGather<XT, KIND>;
+__device__ __forceinline__ typename VecGather<XT, KIND>::VT gather_vec(const SlotArgs &a, const XT *__restrict__ x,
+                                                                       int u, int j0) {
+  using VT = typename VecGather<XT, KIND>::VT;
   if constexpr (KIND == KIND_RESID) {
-    const double2 t = *reinterpret_cast<const double2 *>(a.xres + col_index(u, S, j0));
-    g[0] = t.x;
-    g[1] = t.y;
-  } else if constexpr (VG::V == 4) {
-    const float4 t = *reinterpret_cast<const float4 *>(x + col_index(u, S, j0));
-    g[0] = t.x;
-    g[1] = t.y;
-    g[2] = t.z;
-    g[3] = t.w;
+    return *reinterpret_cast<const VT *>(a.xres + col_index(u, S, j0));
   } else {
-    const double2 t = *reinterpret_cast<const double2 *>(x + col_index(u, S, j0));
-    g[0] = t.x;
-    g[1] = t.y;
+    return *reinterpret_cast<const VT *>(x + col_index(u, S, j0));
+  }
+}
+
+template <typename VT>
+__device__ __forceinline__ VT vzero() {
+  VT z;
+  if constexpr (sizeof(z.x) == 4) {
+    z = VT{0.f, 0.f, 0.f, 0.f};
+  } else {
+    z = VT{0.0, 0.0};
+  }
+  return z;
+}
+
+// acc[q] += (g0 + g1) + (g2 + g3) per column, in FP64
+template <int V, typename VT>
+__device__ __forceinline__ void vacc4(double (&acc)[V], const VT (&g)[4]) {
+  acc[0] += ((double)g[0].x + (double)g[1].x) + ((double)g[2].x + (double)g[3].x);
+  acc[1] += ((double)g[0].y + (double)g[1].y) + ((double)g[2].y + (double)g[3].y);
+  if constexpr (V == 4) {
+    acc[2] += ((double)g[0].z + (double)g[1].z) + ((double)g[2].z + (double)g[3].z);
+    acc[3] += ((double)g[0].w + (double)g[1].w) + ((double)g[2].w + (double)g[3].w);
   }
 }
 
@@ -702,6 +717,7 @@ template <typename XT, int S, int KIND>
 __device__ __forceinline__ void heavy_item_vec(const SlotArgs &a, int item, const XT *__restrict__ xcur,
                                                double (*hred)[RWR_MAX_COLS]) {
   constexpr int V = VecGather<XT, KIND>::V;
+  using VT = typename VecGather<XT, KIND>::VT;
   constexpr int L = S / V;
   constexpr int SLOTS = BLOCK / L;
   const int lane = threadIdx.x % RWR_WAVE, w = threadIdx.x / RWR_WAVE;
@@ -720,18 +736,10 @@ __device__ __forceinline__ void heavy_item_vec(const SlotArgs &a, int item, cons
     int uu[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) uu[t] = e + t * SLOTS < e1 ? nt_load(adj + e + t * SLOTS) : -1;
-    double g[4][V];
+    VT g[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (uu[t] >= 0) {
-        gather_vec<XT, S, KIND>(a, xcur, uu[t], j0, g[t]);
-      } else {
-#pragma unroll
-        for (int q = 0; q < V; ++q) g[t][q] = 0.0;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < V; ++q) acc[q] += (g[0][q] + g[1][q]) + (g[2][q] + g[3][q]);
+    for (int t = 0; t < 4; ++t) g[t] = uu[t] >= 0 ? gather_vec<XT, S, KIND>(a, xcur, uu[t], j0) : vzero<VT>();
+    vacc4<V>(acc, g);
   }
 #pragma unroll
   for (int q = 0; q < V; ++q) acc[q] = wave_xor_sum(acc[q], L, RWR_WAVE);
@@ -751,6 +759,7 @@ __device__ __forceinline__ void heavy_item_vec(const SlotArgs &a, int item, cons
 template <typename XT, int S, int G, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_pull_v(SlotArgs a, int k) {
   constexpr int V = VecGather<XT, KIND>::V;
+  using VT = typename VecGather<XT, KIND>::VT;
   constexpr int L = S / V;
   constexpr int P = G / L;
   static_assert(L >= 1 && G % L == 0 && G <= RWR_WAVE && P >= 1, "lane layout");
@@ -780,8 +789,6 @@ __global__ __launch_bounds__(BLOCK) void k_pull_v(SlotArgs a, int k) {
     if (v >= a.n || a.in.heavy[v]) continue;
     const int o = a.in.off[v], d = a.in.len[v];
     const int32_t *__restrict__ adj = a.in.adj + o;
-    double rv[V];
-    if (p == 0) load_scores_vec<S, V>(a, v, j0, rv);
     double acc[V];
 #pragma unroll
     for (int q = 0; q < V; ++q) acc[q] = 0.0;
@@ -789,18 +796,10 @@ __global__ __launch_bounds__(BLOCK) void k_pull_v(SlotArgs a, int k) {
       int uu[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) uu[t] = e + t * P < d ? nt_load(adj + e + t * P) : -1;
-      double g[4][V];
+      VT g[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (uu[t] >= 0) {
-          gather_vec<XT, S, KIND>(a, xcur, uu[t], j0, g[t]);
-        } else {
-#pragma unroll
-          for (int q = 0; q < V; ++q) g[t][q] = 0.0;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < V; ++q) acc[q] += (g[0][q] + g[1][q]) + (g[2][q] + g[3][q]);
+      for (int t = 0; t < 4; ++t) g[t] = uu[t] >= 0 ? gather_vec<XT, S, KIND>(a, xcur, uu[t], j0) : vzero<VT>();
+      vacc4<V>(acc, g);
     }
 #pragma unroll
     for (int off = L; off < G; off <<= 1) {
@@ -808,7 +807,8 @@ __global__ __launch_bounds__(BLOCK) void k_pull_v(SlotArgs a, int k) {
       for (int q = 0; q < V; ++q) acc[q] += __shfl_xor(acc[q], off, RWR_WAVE);
     }
     if (p == 0) {
-      double y[V];
+      double y[V], rv[V];
+      load_scores_vec<S, V>(a, v, j0, rv);
 #pragma unroll
       for (int q = 0; q < V; ++q) y[q] = c1 * acc[q];
       pull_epilogue_vec<XT, S, KIND, V>(a, xnext, v, j0, y, rv, act, nrm, sm);

@@ -36,13 +36,19 @@ def test_traffic_summary_checks_the_kernel_source(tmp_path, monkeypatch):
     summ = tmp_path / "t.md"
     summ.write_text(f"- kernel_source_sha256: `{sha}`\n- algorithmic_bytes_per_sweep: `1000`\n"
                     f"- hbm_bytes_per_sweep: `1500`\n")
-    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(summ))
     monkeypatch.setattr(bench, "SWEEP_SOURCE", str(src))
-    assert bench.measured_traffic(1000) == 1500.0
-    assert bench.measured_traffic(1000.5) == 1500.0 * 1000.5 / 1000  # the same workload, a few edges apart
-    assert bench.measured_traffic(2000) is None  # another workload
+    assert bench.measured_traffic(1000, str(summ)) == 1500.0
+    # the same workload, a few edges apart
+    assert bench.measured_traffic(1000.5, str(summ)) == 1500.0 * 1000.5 / 1000
+    assert bench.measured_traffic(2000, str(summ)) is None  # another workload
+    assert bench.measured_traffic(1000, str(tmp_path / "missing.md")) is None
     src.write_text("changed kernel source")
-    assert bench.measured_traffic(1000) is None  # the counters no longer describe the kernel
+    assert bench.measured_traffic(1000, str(summ)) is None  # the counters no longer describe the kernel
+
+
+def test_host_cpu_model_is_named():
+    name = bench.host_cpu_model()
+    assert isinstance(name, str) and name
 
 
 def test_rank_accuracy_report():
