@@ -130,6 +130,9 @@ struct rwr_ctx {
   // cleared; its truncation bound is then not spent).
   // carry_level: 0 off, 1 residual only, 2 residual and last iterate.
   int carry_level = 2;
+  // columns of a run that may leave its last iterate retire together
+  // (RWR_LOCKSTEP = 0: each at its own stop test)
+  bool lockstep = true;
   uint64_t pend = 0;         // columns with a pending vector in gbuf
   int tail_slot = -1;        // x buffer holding deferred last iterates (-1: none)
   uint64_t tail_cols = 0;    // their columns
@@ -386,6 +389,7 @@ static void tune_defaults(rwr_ctx *c) {
   if (const char *e = getenv("RWR_GRAPHS")) c->graphs = atoi(e) != 0;
   if (const char *e = getenv("RWR_HEAVY_FOLD")) c->fold_max = atoi(e);
   if (const char *e = getenv("RWR_CARRY")) c->carry_level = std::max(0, std::min(2, atoi(e)));
+  if (const char *e = getenv("RWR_LOCKSTEP")) c->lockstep = atoi(e) != 0;
   if (const char *e = getenv("RWR_REFINE_TARGET")) {
     const double t = atof(e);
     if (t > 0.0 && t < 1.0) c->refine_target = t;
@@ -989,13 +993,14 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
   // truncation bound of the refinement: 2 (1-c)/c * eps_ref / sigma = target * budget
   const double tgt = target > 0.0 ? target : c->refine_target;
   const double eps_ref = tgt * c->budget * cc * min_sig / (2.0 * (1.0 - cc));
-  launch_reset_run(c->ctl, c->S, mask, eps_ref, c->max_iters, dense_thresh(c), c->n / 16 + 1, c->stream,
-                   c->max_iters + 2);
-  launch_refine_init(a, c->S, c->fp64, c->stream);
   // in a stream the refinement's last iterate is left for the next update too
   // (otherwise its truncation, near the budget, pushes the next update's
-  // bound over it and the refinements follow one another)
+  // bound over it and the refinements follow one another); its columns then
+  // retire together so that every one of them leaves its last iterate
   const bool keep = carry && c->carry_level >= 2;
+  launch_reset_run(c->ctl, c->S, mask, eps_ref, c->max_iters, dense_thresh(c), c->n / 16 + 1, c->stream,
+                   c->max_iters + 2, keep && c->lockstep ? 1 : 0);
+  launch_refine_init(a, c->S, c->fp64, c->stream);
   RWR_TRY(run_slots(c, MODE_DENSE, resid * (1.0 - cc), eps_ref, keep));
   if (c->ctl_h->prop_err != 0) {
     c->stale = true;
@@ -1763,9 +1768,13 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   // the batch is valid: commit the node count and apply
   c->n = n_new;
   const SlotArgs a = slot_args(c);
-  launch_reset_run(c->ctl, c->S, all_cols_mask(c->n_seeds), c->cfg.eps, c->max_iters, dense_thresh(c),
-                   c->n / 16 + 1, c->stream);
   const bool warm = c->ws.alloc && c->ws.mode != 0 && nkeys > 0;
+  // a run that may leave its last iterate for the next update: its columns
+  // retire together, so that every column leaves one (a column that stopped
+  // earlier would otherwise spend its truncation bound)
+  const bool keep = c->carry_level >= 2 && !(c->ws.alloc && c->ws.mode != 0);
+  launch_reset_run(c->ctl, c->S, all_cols_mask(c->n_seeds), c->cfg.eps, c->max_iters, dense_thresh(c),
+                   c->n / 16 + 1, c->stream, 0, keep && c->lockstep ? 1 : 0);
   if (warm) drop_carry(c);
   // carried vectors into gbuf (deferred last iterates unscaled with the
   // degrees before the batch; normally done at the end of the previous
@@ -1789,7 +1798,6 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   c->m += (b->n_ins - b->n_del) * (c->undirected ? 2 : 1) - c->ctl_h->node_dels;
   if (warm) RWR_TRY(warm_prepare(c));
   launch_slot0_epilogue(a, c->S, c->fp64, c->stream);
-  const bool keep = c->carry_level >= 2 && !(c->ws.alloc && c->ws.mode != 0);
   RWR_TRY(run_slots(c, MODE_SPARSE, -1.0, 0.0, keep, c->pend));
   // columns whose pending vector joined the run (it reached the dense phase)
   uint64_t inj = 0;

@@ -105,7 +105,8 @@ struct DecideShared {
   double s_norm[RWR_MAX_COLS];
   double s_sum[RWR_MAX_COLS];
   int64_t s_i[2];
-  int s_active;
+  int s_active;  // columns still above eps
+  int s_nact;    // columns active in this iteration
   int s_bad;  // a column's norm or sum is not finite
 };
 
@@ -134,6 +135,7 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
   const bool actj = ctl->active[j] != 0;
   const double eps0 = ctl->eps;
   const int hb = ctl->hist_base;
+  const int lock = ctl->lockstep;
   double sig0 = 0.0, sumn0 = 0.0;
   if (t < S) {
     sig0 = ctl->sigma[t];
@@ -213,6 +215,7 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
   }
   if (t == 0) {
     sh.s_active = 0;
+    sh.s_nact = 0;
     sh.s_bad = 0;
   }
   __syncthreads();
@@ -252,15 +255,17 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
         ctl->prop_err = ERR_ENUMERIC;
         sh.s_bad = 1;
       }
-      if (it >= 1 && nr <= eps0)
-        ctl->active[t] = 0;
-      else
-        atomicAdd(&sh.s_active, 1);
+      const bool conv = it >= 1 && nr <= eps0;
+      if (!conv) atomicAdd(&sh.s_active, 1);
+      if (conv && !lock) ctl->active[t] = 0;
+      atomicAdd(&sh.s_nact, 1);
     }
   }
   __syncthreads();
+  // lockstep: the columns retire together once none is left above eps
+  if (lock && t < S && actj && sh.s_active == 0) ctl->active[t] = 0;
   if (t == 0) {
-    const int na = sh.s_active;
+    const int na = lock ? (sh.s_active > 0 ? sh.s_nact : 0) : sh.s_active;
     ctl->n_active = na;
     ctl->iter = it + 1;
     // the push of a sparse slot read the out-rows of the previous frontier
@@ -1157,7 +1162,12 @@ __global__ __launch_bounds__(BLOCK) void k_inject(SlotArgs a, int k, uint64_t ma
     const int64_t kk = col_index(v, S, j);
     const double p = a.gbuf[kk];
     const int d = a.out.len[v];
-    if (p != 0.0 && d) xin[kk] = (XT)((double)xin[kk] + p / (double)d);
+    if (p != 0.0) {
+      if (d) xin[kk] = (XT)((double)xin[kk] + p / (double)d);
+      // the column leaves the pending set: its entries of gbuf must read 0,
+      // since the next offset seed takes r - gbuf in every column
+      a.gbuf[kk] = 0.0;
+    }
   }
 }
 
@@ -1277,7 +1287,7 @@ __global__ __launch_bounds__(BLOCK) void k_finish(SlotArgs a) {
 }
 
 __global__ void k_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double eps, int32_t max_iters,
-                            int64_t dense_thresh, int64_t dense_nodes, int32_t hist_base) {
+                            int64_t dense_thresh, int64_t dense_nodes, int32_t hist_base, int32_t lockstep) {
   const int t = threadIdx.x;
   if (t < RWR_MAX_COLS) {
     const int a = (t < S) && ((active_mask >> t) & 1ull);
@@ -1307,6 +1317,7 @@ __global__ void k_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double ep
     ctl->eps = eps;
     ctl->hpack = 0;
     ctl->hist_base = hist_base;
+    ctl->lockstep = lockstep;
   }
 }
 
@@ -1325,9 +1336,9 @@ static constexpr int push_lanes() {
 }
 
 void launch_reset_run(Ctl *ctl, int32_t S, uint64_t mask, double eps, int32_t max_iters, int64_t dense_thresh,
-                      int64_t dense_nodes, hipStream_t st, int32_t hist_base) {
+                      int64_t dense_nodes, hipStream_t st, int32_t hist_base, int32_t lockstep) {
   hipLaunchKernelGGL(k_reset_run, dim3(1), dim3(64), 0, st, ctl, S, mask, eps, max_iters, dense_thresh, dense_nodes,
-                     hist_base);
+                     hist_base, lockstep);
 }
 
 #define RWR_DISPATCH_S(S, CALL)  \

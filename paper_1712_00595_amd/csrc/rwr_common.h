@@ -46,6 +46,7 @@ struct Ctl {
   int32_t max_iters;
   int32_t n_active;     // columns still propagating
   int32_t ended_dense;  // some dense sweep ran during this propagation
+  int32_t lockstep;     // columns retire together, when the last of them passes the stop test
   int32_t fcount[2];    // frontier sizes (frontier of x^(i) is list i % 2)
   int32_t nT[2];        // touched rows per orientation (0 = out/CSR, 1 = in/CSC)
   uint32_t done_blocks; // last-arriver counter of the current kernel

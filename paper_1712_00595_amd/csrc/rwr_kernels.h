@@ -125,9 +125,16 @@ void launch_apply(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t ma
 
 // ---- propagation (k_prop.hip); fp64 selects the propagation type
 // hist_base: first row of the norm history this run writes (0 for update
-// runs; refinements write after them, so the update's norms stay readable)
+// runs; refinements write after them, so the update's norms stay readable).
+// lockstep: a column that passes the stop test keeps propagating until every
+// column of the run has passed it, and then all retire at once (their last
+// iterates then sit in the same x buffer, so a run's tail can be carried for
+// every column; the extra iterations only shrink the converged columns'
+// truncation, and the dense sweep reads every column of a gathered row
+// anyway).  0: each column retires at its own stop test (Algorithm 1 per
+// seed).
 void launch_reset_run(Ctl *ctl, int32_t S, uint64_t active_mask, double eps, int32_t max_iters, int64_t dense_thresh,
-                      int64_t dense_nodes, hipStream_t st, int32_t hist_base = 0);
+                      int64_t dense_nodes, hipStream_t st, int32_t hist_base = 0, int32_t lockstep = 0);
 void launch_seed_init(const SlotArgs &a, int S, hipStream_t st);
 void launch_seed_init_q(const SlotArgs &a, int S, hipStream_t st);
 // carried vectors in gbuf before an update: d_out * x[last] for tail_mask
