@@ -208,3 +208,143 @@ def region(n, src, dst, start, hops: int, cap: int):
         order += nxt
         level = nxt
     return np.array(order, dtype=np.int64), np.array([hop[v] for v in order], dtype=np.int64)
+
+
+# ------------------------------------------------------------ inside an update
+#
+# What an update computes when the warm start is on, written out plainly for
+# one batch: the region around the offset seed, the network's inputs, the
+# prediction with its mass correction, the exact residual and the training
+# loss with its gradient.  Row order: region node i, seed column j at
+# row i * S + j; nodes are the graph's own ids.
+
+def propagation_operator(n, src, dst, c):
+    """P = (1-c) B~^T as a sparse matrix: P[v, u] = (1-c) / d_out(u) for every
+    edge u -> v (Section 2.1's row normalisation; dead-end rows are zero)."""
+    import scipy.sparse as sp
+
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    deg = np.bincount(src, minlength=n).astype(np.float64)
+    return sp.csr_matrix(((1.0 - c) / deg[src], (dst, src)), shape=(n, n))
+
+
+def offset_support(old, new, r_old):
+    """Level 0 of the region: every node v whose coefficient B~[u, v] -
+    A~[u, v] is non-zero for some row u that the batch changed and whose old
+    score is non-zero in some column (Section 3.1: these are the nodes the
+    offset seed q = (1-c)(B~^T - A~^T) r_old can reach in one step).  ``old``
+    and ``new`` are (n, src, dst); r_old has old-n rows (one column per seed,
+    or a vector)."""
+    import scipy.sparse as sp
+
+    n0, s0, d0 = old
+    n1, s1, d1 = new
+
+    def normalised(n, s, d):
+        s = np.asarray(s, dtype=np.int64)
+        d = np.asarray(d, dtype=np.int64)
+        deg = np.bincount(s, minlength=n).astype(np.float64)
+        return sp.csr_matrix((1.0 / deg[s], (s, d)), shape=(n1, n1))
+
+    delta = (normalised(n1, s1, d1) - normalised(n0, s0, d0)).tocoo()
+    r = np.zeros((n1,) + np.shape(r_old)[1:])
+    r[:n0] = np.asarray(r_old, np.float64)
+    live_row = np.any(r.reshape(n1, -1) != 0.0, axis=1)
+    keep = (delta.data != 0.0) & live_row[delta.row]
+    return np.unique(delta.col[keep])
+
+
+def features(n_total, src, dst, nodes, hop, q, r_old, sigma, seeds):
+    """The sixteen inputs of every (region node, column) row, as float32:
+    0 log(1+d_in)/8, 1 log(1+d_out)/8, 2 q/||q_j||_1, 3 |q|/||q_j||_1,
+    4 log(1 + max(0, n r_old/sigma_j))/8, 5..8 hop 0, 1, 2, >=3 (one-hot),
+    9 dead end, 10 seed of the column, 11 1/d_out (0 for a dead end),
+    12 1/d_in (0 without in-edges), 13..15 zero.  Degrees are those of the
+    graph after the batch; q is the offset seed (n x S), r_old the scores
+    before the batch (n x S, rows of new nodes zero), sigma their column
+    sums."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    nodes = np.asarray(nodes, dtype=np.int64)
+    n = q.shape[0]
+    S = q.shape[1]
+    dout = np.bincount(src, minlength=n)[nodes].astype(np.float64)
+    din = np.bincount(dst, minlength=n)[nodes].astype(np.float64)
+    qn = np.abs(q).sum(axis=0)
+    F = np.zeros((nodes.shape[0], S, FEAT))
+    F[:, :, 0] = (np.log1p(din) / 8.0)[:, None]
+    F[:, :, 1] = (np.log1p(dout) / 8.0)[:, None]
+    qq = np.where(qn > 0, q[nodes] / np.where(qn > 0, qn, 1.0), 0.0)
+    F[:, :, 2] = qq
+    F[:, :, 3] = np.abs(qq)
+    rn = np.where(sigma != 0, r_old[nodes] / np.where(sigma != 0, sigma, 1.0), 0.0)
+    F[:, :, 4] = np.log1p(np.maximum(0.0, rn * n_total)) / 8.0
+    for k in range(4):
+        F[:, :, 5 + k] = ((hop == k) if k < 3 else (hop >= 3))[:, None]
+    F[:, :, 9] = (dout == 0)[:, None]
+    F[:, :, 10] = nodes[:, None] == np.asarray(seeds, np.int64)[None, :]
+    F[:, :, 11] = np.where(dout > 0, 1.0 / np.maximum(dout, 1.0), 0.0)[:, None]
+    F[:, :, 12] = np.where(din > 0, 1.0 / np.maximum(din, 1.0), 0.0)[:, None]
+    return F.astype(np.float32).astype(np.float64)
+
+
+def local_edges(src, dst, nodes):
+    """Edges of the graph with both ends in the region, in local ids."""
+    loc = -np.ones(int(max(np.max(src), np.max(dst), np.max(nodes))) + 1, dtype=np.int64)
+    loc[np.asarray(nodes, np.int64)] = np.arange(len(nodes))
+    ls, ld = loc[np.asarray(src, np.int64)], loc[np.asarray(dst, np.int64)]
+    keep = (ls >= 0) & (ld >= 0)
+    return ls[keep], ld[keep]
+
+
+def mass_correction(xhat, live, c, qsum):
+    """The prediction corrected so that its residual sums to zero in every
+    column.  The column sums of I - (1-c) B~^T are w_v = 1 - (1-c) [v is not
+    a dead end], so sum(rho) = sum(q) - f(xhat) with f(x) = sum_v w_v x_v;
+    xhat' = xhat - beta |xhat| with beta = (f(xhat) - sum(q)) / f(|xhat|)
+    (beta = 0 when f(|xhat|) = 0).  Returns (xhat', beta, f(|xhat|), w)."""
+    w = 1.0 - (1.0 - c) * np.asarray(live, np.float64)
+    fx = (w[:, None] * xhat).sum(axis=0)
+    fa = (w[:, None] * np.abs(xhat)).sum(axis=0)
+    beta = np.where(fa > 0, (fx - qsum) / np.where(fa > 0, fa, 1.0), 0.0)
+    return xhat - beta[None, :] * np.abs(xhat), beta, fa, w
+
+
+def residual_loss(theta, F, lsrc, ldst, dinv, nodes, q, P, live, c, *, follow=True, rnd=False):
+    """Training loss of the warm start inside an update and its gradient.
+
+    xhat = ||q_j||_1 o on the region rows (o the network output), corrected
+    by :func:`mass_correction`, zero elsewhere; rho = q - (I - P) xhat' on
+    every node; L = mean over the columns with ||q_j||_1 > 0 of
+    ||rho_j||_1 / ||q_j||_1.  dL/dxhat' = (-(I - P)^T sign(rho)) / (C ||q_j||_1).
+    With follow=True the gradient goes through the correction exactly:
+      dL/dxhat_v = (1 - beta s_v) (dL/dxhat'_v - w_v K / f(|xhat|)),
+      K = sum_u dL/dxhat'_u |xhat_u|,  s = sign(xhat);
+    with follow=False the correction is held fixed (dL/dxhat = dL/dxhat').
+    Then dL/do = ||q_j||_1 dL/dxhat and the network's backward pass gives
+    dL/dtheta.  ``P`` is :func:`propagation_operator` of the graph after the
+    batch, ``live`` marks region nodes that are not dead ends."""
+    nodes = np.asarray(nodes, np.int64)
+    o, cache = forward(theta, F, lsrc, ldst, dinv, rnd=rnd)
+    qn = np.abs(q).sum(axis=0)
+    qsum = q[nodes].sum(axis=0)
+    active = qn > 0
+    C = max(1, int(active.sum()))
+    xhat = qn[None, :] * o
+    xc, beta, fa, w = mass_correction(xhat, live, c, qsum)
+    X = np.zeros_like(q)
+    X[nodes] = xc
+    rho = q - X + P @ X
+    L = float(np.sum(np.abs(rho).sum(axis=0)[active] / qn[active]) / C)
+    sg = np.sign(rho)
+    gprime = ((-sg + P.T @ sg)[nodes]) * np.where(active, 1.0 / (C * np.where(qn > 0, qn, 1.0)), 0.0)[None, :]
+    if follow:
+        K = (gprime * np.abs(xhat)).sum(axis=0)
+        corr = np.where(fa > 0, K / np.where(fa > 0, fa, 1.0), 0.0)
+        gx = (1.0 - beta[None, :] * np.sign(xhat)) * (gprime - w[:, None] * corr[None, :])
+    else:
+        gx = gprime
+    do = qn[None, :] * gx
+    grad = backward(theta, F, lsrc, ldst, dinv, cache, do, rnd=rnd)
+    return {"loss": L, "grad": grad, "do": do, "o": o, "rho": rho, "xhat": xc, "beta": beta, "active": active}
