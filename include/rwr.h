@@ -276,6 +276,20 @@ rwr_status rwr_model_get(rwr_ctx *ctx, float *params, int64_t cap);
 rwr_status rwr_warm_start(rwr_ctx *ctx, int32_t mode, int32_t hops, int64_t max_rows, float lr,
                           float weight_decay);
 
+/* Read back what the warm start of the last rwr_update computed (for checking
+ * it against a reference): the region's nodes in the network's row order
+ * (caller ids; nodes[cap]), the hop of each from the offset support
+ * (hops[cap]), the network output o and dL/do of the training loss (row =
+ * region node * row_cols + seed column; cap * row_cols floats each, row_cols
+ * = the seed count rounded up to a power of two, padding columns zero), and
+ * the parameter gradient of that training step (rwr_gnn_num_params()
+ * floats; the parameters have since taken the AdamW step).  *n_region = 0
+ * when the last update ran no warm start.  Any output array may be NULL;
+ * dout and grad need a training step in the last update (RWR_ESTATE), cap
+ * must be at least *n_region (RWR_EINVAL). */
+rwr_status rwr_warm_inspect(rwr_ctx *ctx, int32_t *nodes, int32_t *hops, float *o, float *dout, float *grad,
+                            int64_t cap, int32_t *n_region, int32_t *row_cols);
+
 /* Evaluate the network once on an explicit region of nR nodes and S columns
  * (host arrays): in-rows (in_off/in_len/in_adj, local ids, n_in entries) and
  * out-rows (out_off/out_len/out_adj, n_out entries) of the region graph,

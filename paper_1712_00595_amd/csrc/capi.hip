@@ -181,7 +181,10 @@ struct rwr_ctx {
     int32_t *items = nullptr, *item_off = nullptr;  // gradient work items over the region's out-rows
     int32_t *lin_items = nullptr, *lout_items = nullptr;  // aggregation work items
     int32_t n_in_items = 0, n_out_items = 0;
-    float *gacc = nullptr;
+    double *gpart = nullptr;  // gradient item partials (one per item and column)
+    int64_t gpart_cap = 0;
+    double *kpart = nullptr;  // per-workgroup partials of the correction's K
+    double *fa = nullptr;     // f(|xhat|) per column
     int64_t ladj_cap = 0;
     void *scan_temp = nullptr;
     size_t scan_bytes = 0;
@@ -191,6 +194,8 @@ struct rwr_ctx {
     size_t temp_bytes = 0;
     // this update
     int32_t nR = 0;
+    std::vector<int32_t> level_end;  // end row of each hop level of the last region
+    bool trained = false;            // the last update took a training step
     std::vector<double> qn_h;
     int32_t accepted = 0;
     double ratio = 0.0, loss = 0.0, ms = 0.0;
@@ -1042,7 +1047,10 @@ static void warm_free(rwr_ctx *c) {
   dev_free(w.item_off);
   dev_free(w.lin_items);
   dev_free(w.lout_items);
-  dev_free(w.gacc);
+  dev_free(w.gpart);
+  w.gpart_cap = 0;
+  dev_free(w.kpart);
+  dev_free(w.fa);
   w.ladj_cap = 0;
   if (w.scan_temp) (void)hipFree(w.scan_temp);
   w.scan_temp = nullptr;
@@ -1080,7 +1088,8 @@ static rwr_status warm_alloc(rwr_ctx *c, int64_t max_rows) {
   RWR_TRY(alloc_zero(c, &w.lin_items, w.max_nodes + 1));
   RWR_TRY(alloc_zero(c, &w.lout_items, w.max_nodes + 1));
   RWR_TRY(alloc_zero(c, &w.item_off, w.max_nodes + 1));
-  RWR_TRY(alloc_zero(c, &w.gacc, w.max_rows));
+  RWR_TRY(alloc_zero(c, &w.kpart, (size_t)WS_KPART_BLOCKS * RWR_MAX_COLS));
+  RWR_TRY(alloc_zero(c, &w.fa, RWR_MAX_COLS));
   w.scan_bytes = ws_scan_temp_bytes((int32_t)w.max_nodes);
   RWR_TRY(dev_alloc(c, &w.scan_temp, w.scan_bytes));
   RWR_TRY(alloc_zero(c, &w.dinv, w.max_nodes));
@@ -1161,6 +1170,8 @@ static rwr_status warm_prepare(rwr_ctx *c) {
   w.accepted = 0;
   w.ratio = 1.0;
   w.loss = 0.0;
+  w.trained = false;
+  w.level_end.clear();
   const int S = c->S;
   const DevGraphView &in = c->g[pull_orient(c)].v;
   const DevGraphView &out = c->g[0].v;
@@ -1182,6 +1193,7 @@ static rwr_status warm_prepare(rwr_ctx *c) {
     lvl_start = nR;
     nR += k;
     if (k == 0) break;
+    w.level_end.push_back(nR);
   }
   w.nR = nR;
   if (nR == 0 || n0 == 0) {
@@ -1198,7 +1210,8 @@ static rwr_status warm_prepare(rwr_ctx *c) {
   ws_features(w.R, nR, S, w.hop1, in, out, c->ybuf, c->r, c->ctl, c->seeds_d, w.qn, c->n, w.net.F, c->stream);
   gnn::net_forward(w.net, warm_view(c), rows, c->stream);
   // prediction in wbuf (dense), (1-c) B~^T xhat - xhat in gbuf, rho = q + that
-  ws_predict(w.R, nR, S, out, w.net.o, w.qn, c1, w.xhat, w.wbuf, w.part, w.sums + 2 * RWR_MAX_COLS, c->stream);
+  double *beta = w.sums + 2 * RWR_MAX_COLS;
+  ws_predict(w.R, nR, S, out, w.net.o, w.qn, c1, w.xhat, w.wbuf, w.part, beta, w.fa, c->stream);
   {
     SlotArgs a = slot_args(c);
     a.r = w.wbuf;
@@ -1231,10 +1244,21 @@ static rwr_status warm_prepare(rwr_ctx *c) {
   if ((w.mode & 2) && n_act > 0) {
     w.loss = lsum / n_act;
     H2D(c, w.net.active, act.data(), sizeof(int32_t) * RWR_MAX_COLS);
-    HIP_TRY(c, ws_resid_grad(w.R, nR, S, out, c1, c->gbuf, w.gacc, w.items, w.item_off, w.scan_temp, w.scan_bytes,
-                             w.net.active, n_act, w.net.dout, c->stream));
+    // item partials of the gradient: at most one item per region row plus
+    // one per GRAD_CHUNK out-edges
+    const int64_t need = ((int64_t)nR + c->m / 1024 + 2) * S;
+    if (need > w.gpart_cap) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      dev_free(w.gpart);
+      w.gpart_cap = 0;
+      RWR_TRY(dev_alloc(c, (void **)&w.gpart, sizeof(double) * need));
+      w.gpart_cap = need;
+    }
+    HIP_TRY(c, ws_resid_grad(w.R, nR, S, out, c1, c->gbuf, w.gpart, w.items, w.item_off, w.scan_temp, w.scan_bytes,
+                             w.net.active, n_act, w.net.o, w.qn, beta, w.fa, w.kpart, w.net.dout, c->stream));
     gnn::net_backward(w.net, warm_view(c), rows, c->stream);
     gnn::net_adamw(w.net, c->stream);
+    w.trained = true;
   }
   ws_apply(c->n, S, accept, c->ybuf, c->gbuf, c->r, w.wbuf, c->stamp, c->ctl, w.sums + S, c->stream);
   ws_unscatter(w.R, nR, S, w.wbuf, c->stream);
@@ -1407,6 +1431,7 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
     int32_t *tmp = nullptr;
     RWR_TRY(dev_alloc(c, (void **)&tmp, sizeof(int32_t) * RWR_MAX_COLS));
     H2D(c, tmp, seeds, sizeof(int32_t) * n_seeds);
+    launch_fill_i32(c->seeds_d, RWR_MAX_COLS, -1, c->stream);  // padding columns name no node
     launch_map_ids(tmp, n_seeds, n, c->perm, c->seeds_d, c->stream);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     (void)hipFree(tmp);
@@ -2086,6 +2111,40 @@ rwr_status rwr_model_get(rwr_ctx *c, float *params, int64_t cap) {
     return RWR_ESTATE;
   }
   HIP_TRY(c, gnn::net_get_params(c->ws.net, params, c->stream));
+  return RWR_OK;
+}
+
+rwr_status rwr_warm_inspect(rwr_ctx *c, int32_t *nodes, int32_t *hops, float *o, float *dout, float *grad,
+                            int64_t cap, int32_t *n_region, int32_t *row_cols) {
+  if (!c || !n_region) return RWR_EINVAL;
+  const rwr_ctx::Warm &w = c->ws;
+  *n_region = w.alloc ? w.nR : 0;
+  if (row_cols) *row_cols = c->S;
+  if (!w.alloc || w.nR == 0) return RWR_OK;
+  if ((dout || grad) && !w.trained) {
+    c->err = "the last update took no training step";
+    return RWR_ESTATE;
+  }
+  if ((nodes || hops || o || dout) && cap < w.nR) {
+    c->err = "inspection capacity below the region size";
+    return RWR_EINVAL;
+  }
+  const int64_t rows = (int64_t)w.nR * c->S;
+  if (nodes) {
+    // region rows in caller ids (wlist is free between updates)
+    launch_gather_i32(c->inv, w.R, w.nR, w.wlist, c->stream);
+    D2H(c, nodes, w.wlist, sizeof(int32_t) * w.nR);
+  }
+  if (hops) {
+    int32_t h = 0;
+    for (int32_t i = 0; i < w.nR; ++i) {
+      while (h < (int32_t)w.level_end.size() && i >= w.level_end[h]) ++h;
+      hops[i] = h;
+    }
+  }
+  if (o) D2H(c, o, w.net.o, sizeof(float) * rows);
+  if (dout) D2H(c, dout, w.net.dout, sizeof(float) * rows);
+  if (grad) D2H(c, grad, w.net.grad, sizeof(float) * gnn::LAYOUT.total);
   return RWR_OK;
 }
 

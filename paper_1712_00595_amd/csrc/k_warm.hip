@@ -233,9 +233,10 @@ __global__ __launch_bounds__(WB) void k_ws_mass(const int32_t *__restrict__ R, i
   }
 }
 
-// beta[j] from the partials (fixed order) and sum(q) = qn[S + j]
+// beta[j] from the partials (fixed order) and sum(q) = qn[S + j]; fa[j] =
+// f(|xhat_j|), which the gradient through the correction needs
 __global__ void k_ws_beta(const double *__restrict__ part, int nb, int S, double c1, const double *__restrict__ qn,
-                          double *__restrict__ beta) {
+                          double *__restrict__ beta, double *__restrict__ fabs_out) {
   const int j = threadIdx.x;
   if (j >= S) return;
   double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
@@ -248,6 +249,7 @@ __global__ void k_ws_beta(const double *__restrict__ part, int nb, int S, double
   }
   const double fx = a - c1 * b, fa = c - c1 * d;
   beta[j] = fa > 0.0 ? (fx - qn[S + j]) / fa : 0.0;
+  fabs_out[j] = fa;
 }
 
 // xhat' = xhat - beta |xhat|, scattered into the dense vector w (rows R)
@@ -323,13 +325,20 @@ __global__ void k_ws_sigma(Ctl *ctl, int S, uint64_t accept, const double *__res
 
 // ------------------------------------------------------------ training
 // Gradient of the training loss L = mean over active columns j of
-// ||rho_j||_1 / ||q_j||_1 with respect to the network output o (xhat = ||q|| o):
-//   dL/do(u, j) = (-(I - (1-c) B~^T)^T sign(rho_j))(u) / C
-//              = (-sign(rho(u, j)) + (1-c)/d_out(u) sum over u -> v of sign(rho(v, j))) / C.
+// ||rho_j||_1 / ||q_j||_1 with respect to the network output o (xhat =
+// ||q|| o, corrected to xhat' = xhat - beta |xhat|, rho = q - (I - P) xhat',
+// P = (1-c) B~^T).  With the correction held fixed:
+//   d(u, j) = (-(I - P)^T sign(rho_j))(u) / C
+//           = (-sign(rho(u, j)) + (1-c)/d_out(u) sum over u -> v of sign(rho(v, j))) / C,
+// and through the correction exactly (beta depends on xhat):
+//   dL/do(v, j) = (1 - beta_j s(v, j)) (d(v, j) - w_v ||q_j|| K_j / f_j),
+//   K_j = sum_u d(u, j) |o(u, j)|,  f_j = f(|xhat_j|),  s = sign(o),
+//   w_v = 1 for a dead end, c otherwise (the column sums of I - P).
 // For the exact offset result, ||rho||_1 is the L1 distance between xhat and
-// r_offset measured through I - (1-c) B~^T.  The mass correction is taken as
-// fixed (its derivative is not followed).  The sums over out-rows run over
-// items of GRAD_CHUNK edges (one wavefront each), added with float atomics.
+// r_offset measured through I - P.  Out-rows are cut into items of
+// GRAD_CHUNK edges (one wavefront each); every sum runs in a fixed order
+// (item partials, then each row's items in order, then per-workgroup column
+// partials and their sum), so the gradient does not depend on timing.
 #define GRAD_CHUNK 1024
 
 __device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
@@ -340,10 +349,11 @@ __global__ void k_ws_grad_items(const int32_t *__restrict__ R, int32_t nR, DevGr
     items[i] = i < nR ? (out.len[R[i]] + GRAD_CHUNK - 1) / GRAD_CHUNK : 0;
 }
 
+// gpart[it * S + j] = sum of sign(rho(v, j)) over the out-edges u -> v of item it
 template <int S>
 __global__ void k_ws_grad_sum(const int32_t *__restrict__ R, int32_t nR, DevGraphView out,
                               const int32_t *__restrict__ item_off, const double *__restrict__ rho,
-                              float *__restrict__ gacc) {
+                              double *__restrict__ gpart) {
   constexpr int PER = RWR_WAVE / S;
   const int lane = threadIdx.x % RWR_WAVE;
   const int j = lane % S, p = lane / S;
@@ -363,22 +373,64 @@ __global__ void k_ws_grad_sum(const int32_t *__restrict__ R, int32_t nR, DevGrap
     double t = 0.0;
     for (int e = k * GRAD_CHUNK + p; e < e1; e += PER) t += sgn(rho[col_index(out.adj[o + e], S, j)]);
     for (int off = S; off < RWR_WAVE; off <<= 1) t += __shfl_xor(t, off, RWR_WAVE);
-    if (p == 0 && t != 0.0) atomicAdd(&gacc[(int64_t)i * S + j], (float)t);
+    if (p == 0) gpart[(int64_t)it * S + j] = t;
   }
 }
 
-__global__ void k_ws_grad_final(const int32_t *__restrict__ R, int32_t nR, int S, DevGraphView out, double c1,
-                                const double *__restrict__ rho, float *__restrict__ gacc,
-                                const int32_t *__restrict__ active, float inv_cols, float *__restrict__ dout) {
+// d(u, j) with the correction held fixed (into dout), and per-workgroup
+// partials of K_j = sum d |o| (entries blockIdx * S + j).  The grid stride
+// is a multiple of S, so each thread keeps one column.
+__global__ __launch_bounds__(WB) void k_ws_grad_fixed(const int32_t *__restrict__ R, int32_t nR, int S,
+                                                      DevGraphView out, double c1, const double *__restrict__ rho,
+                                                      const double *__restrict__ gpart,
+                                                      const int32_t *__restrict__ item_off,
+                                                      const int32_t *__restrict__ active, double inv_cols,
+                                                      const float *__restrict__ o, float *__restrict__ dout,
+                                                      double *__restrict__ kpart) {
+  __shared__ double red[WB];
+  const int64_t rows = (int64_t)nR * S;
+  const int j = threadIdx.x % S;
+  double kk = 0.0;
+  for (int64_t row = blockIdx.x * (int64_t)WB + threadIdx.x; row < rows; row += (int64_t)gridDim.x * WB) {
+    const int i = (int)(row / S);
+    const int u = R[i];
+    const int d = out.len[u];
+    double t = 0.0;
+    for (int32_t it = item_off[i]; it < item_off[i + 1]; ++it) t += gpart[(int64_t)it * S + j];
+    const double g = active[j] ? (-sgn(rho[col_index(u, S, j)]) + (d ? c1 * t / (double)d : 0.0)) * inv_cols : 0.0;
+    dout[row] = (float)g;
+    kk += (double)(float)g * fabs((double)o[row]);
+  }
+  red[threadIdx.x] = kk;
+  __syncthreads();
+  if (threadIdx.x < S) {
+    double a = 0.0;
+    for (int q = threadIdx.x; q < WB; q += S) a += red[q];
+    kpart[(int64_t)blockIdx.x * S + threadIdx.x] = a;
+  }
+}
+
+// dL/do through the correction: dout = (1 - beta s)(d - w ||q|| K / f)
+__global__ void k_ws_grad_corr(const int32_t *__restrict__ R, int32_t nR, int S, DevGraphView out, double c1,
+                               const double *__restrict__ kpart, int nb, const double *__restrict__ qn,
+                               const double *__restrict__ beta, const double *__restrict__ fa,
+                               const float *__restrict__ o, float *__restrict__ dout) {
+  __shared__ double corr[RWR_MAX_COLS];
+  if (threadIdx.x < S) {
+    const int j = threadIdx.x;
+    double K = 0.0;
+    for (int b = 0; b < nb; ++b) K += kpart[(int64_t)b * S + j];
+    corr[j] = fa[j] > 0.0 ? qn[j] * K / fa[j] : 0.0;
+  }
+  __syncthreads();
   const int64_t rows = (int64_t)nR * S;
   for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < rows;
        row += (int64_t)gridDim.x * blockDim.x) {
     const int j = (int)(row % S);
-    const int u = R[row / S];
-    const int d = out.len[u];
-    const double g = -sgn(rho[col_index(u, S, j)]) + (d ? c1 * (double)gacc[row] / (double)d : 0.0);
-    dout[row] = active[j] ? (float)g * inv_cols : 0.0f;
-    gacc[row] = 0.0f;
+    if (fa[j] <= 0.0) continue;
+    const double w = out.len[R[row / S]] > 0 ? 1.0 - c1 : 1.0;
+    const double s = sgn((double)o[row]);
+    dout[row] = (float)((1.0 - beta[j] * s) * ((double)dout[row] - w * corr[j]));
   }
 }
 
@@ -469,12 +521,12 @@ void ws_features(const int32_t *R, int32_t nR, int S, const int32_t *hop1, const
 }
 
 void ws_predict(const int32_t *R, int32_t nR, int S, const DevGraphView &out, const float *o, const double *qn,
-                double c1, double *xhat, double *w, double *part, double *beta, hipStream_t s) {
+                double c1, double *xhat, double *w, double *part, double *beta, double *fa, hipStream_t s) {
   const int g = wgrid((int64_t)nR * S);
   hipLaunchKernelGGL(k_ws_predict, dim3(g), dim3(WB), 0, s, nR, S, o, qn, xhat);
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)nR * S + WB - 1) / WB, 512));
   hipLaunchKernelGGL(k_ws_mass, dim3(nb), dim3(WB), 0, s, R, nR, S, out, xhat, part);
-  hipLaunchKernelGGL(k_ws_beta, dim3(1), dim3(64), 0, s, part, nb, S, c1, qn, beta);
+  hipLaunchKernelGGL(k_ws_beta, dim3(1), dim3(64), 0, s, part, nb, S, c1, qn, beta, fa);
   hipLaunchKernelGGL(k_ws_adjust_scatter, dim3(g), dim3(WB), 0, s, R, nR, S, beta, xhat, w);
 }
 
@@ -500,15 +552,16 @@ void ws_apply(int32_t n, int S, uint64_t accept, double *ybuf, const double *gbu
 }
 
 hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *rho,
-                         float *gacc, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
-                         const int32_t *active, int n_active, float *dout, hipStream_t s) {
+                         double *gpart, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
+                         const int32_t *active, int n_active, const float *o, const double *qn, const double *beta,
+                         const double *fa, double *kpart, float *dout, hipStream_t s) {
   hipLaunchKernelGGL(k_ws_grad_items, dim3(wgrid((int64_t)nR + 1)), dim3(WB), 0, s, R, nR, out, items);
   hipError_t e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, items, item_off, nR + 1, s);
   if (e != hipSuccess) return e;
   switch (S) {
 #define WS_GRAD(SS)                                                                                              \
   case SS:                                                                                                       \
-    hipLaunchKernelGGL(k_ws_grad_sum<SS>, dim3(1024), dim3(WB), 0, s, R, nR, out, item_off, rho, gacc);          \
+    hipLaunchKernelGGL(k_ws_grad_sum<SS>, dim3(1024), dim3(WB), 0, s, R, nR, out, item_off, rho, gpart);         \
     break;
     WS_GRAD(1)
     WS_GRAD(2)
@@ -521,8 +574,11 @@ hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView
     default:
       break;
   }
-  const float inv = 1.0f / (float)std::max(1, n_active);
-  hipLaunchKernelGGL(k_ws_grad_final, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, R, nR, S, out, c1, rho, gacc,
-                     active, inv, dout);
+  const double inv = 1.0 / (double)std::max(1, n_active);
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)nR * S + WB - 1) / WB, WS_KPART_BLOCKS));
+  hipLaunchKernelGGL(k_ws_grad_fixed, dim3(nb), dim3(WB), 0, s, R, nR, S, out, c1, rho, gpart, item_off, active, inv,
+                     o, dout, kpart);
+  hipLaunchKernelGGL(k_ws_grad_corr, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, R, nR, S, out, c1, kpart, nb, qn,
+                     beta, fa, o, dout);
   return hipSuccess;
 }

@@ -45,9 +45,10 @@ void ws_features(const int32_t *R, int32_t nR, int S, const int32_t *hop1, const
 void ws_qnorm(const int32_t *R, int32_t n0, int S, const double *ybuf, double *part, double *qn, hipStream_t s);
 // xhat = ||q|| o, corrected so that the residual has a zero sum, and
 // scattered into the dense FP64 vector w (zero outside the region).  part
-// holds at least 512 * 4 * S doubles, beta S doubles.
+// holds at least 512 * 4 * S doubles, beta and fa S doubles each (the
+// correction's beta and f(|xhat|) per column).
 void ws_predict(const int32_t *R, int32_t nR, int S, const DevGraphView &out, const float *o, const double *qn,
-                double c1, double *xhat, double *w, double *part, double *beta, hipStream_t s);
+                double c1, double *xhat, double *w, double *part, double *beta, double *fa, hipStream_t s);
 void ws_unscatter(const int32_t *R, int32_t nR, int S, double *w, hipStream_t s);
 // gbuf holds g = (1-c) B~^T xhat - xhat on every node; rho = q + g replaces
 // it; sums[j] = ||rho_j||_1, sums[S + j] = sum of xhat_j
@@ -56,8 +57,13 @@ void ws_rho(int32_t n, int S, const double *ybuf, double *gbuf, const double *w,
 // accepted columns: ybuf = rho, r += xhat, sigma += sum xhat, stamps
 void ws_apply(int32_t n, int S, uint64_t accept, double *ybuf, const double *gbuf, double *r, const double *w,
               int32_t *stamp, Ctl *ctl, const double *xsum, hipStream_t s);
-// dL/do of the residual loss (see k_ws_grad_final) into dout (rows nR * S);
-// gacc (nR * S floats) must be zero and is left zero
+// dL/do of the residual loss through the mass correction (see
+// k_ws_grad_fixed / k_ws_grad_corr) into dout (rows nR * S); gpart holds one
+// double per (gradient item, column): at least (nR + edges of the region's
+// out-rows / 1024 + 1) * S; kpart WS_KPART_BLOCKS * S doubles.  Fixed-order
+// sums only.
+#define WS_KPART_BLOCKS 1024
 hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *rho,
-                         float *gacc, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
-                         const int32_t *active, int n_active, float *dout, hipStream_t s);
+                         double *gpart, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
+                         const int32_t *active, int n_active, const float *o, const double *qn, const double *beta,
+                         const double *fa, double *kpart, float *dout, hipStream_t s);

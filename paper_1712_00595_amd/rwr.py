@@ -50,6 +50,7 @@ EXPORTED = [
     "rwr_model_set",
     "rwr_model_get",
     "rwr_warm_start",
+    "rwr_warm_inspect",
 ]
 
 
@@ -151,6 +152,7 @@ def load_library(path: str = LIB_PATH):
     L.rwr_model_set.argtypes = [p, p, i64]
     L.rwr_model_get.argtypes = [p, p, i64]
     L.rwr_warm_start.argtypes = [p, i32, i32, i64, ctypes.c_float, ctypes.c_float]
+    L.rwr_warm_inspect.argtypes = [p, p, p, p, p, p, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     for name in EXPORTED:
         f = getattr(L, name)
         if name not in ("rwr_destroy", "rwr_last_error", "rwr_gnn_num_params"):
@@ -328,6 +330,28 @@ class Context:
         m = {"off": 0, "predict": 1, "train": 2, "predict+train": 3}[mode]
         _check(self._lib, self._ctx, self._lib.rwr_warm_start(self._ctx, m, int(hops), int(max_rows), float(lr),
                                                                float(weight_decay)))
+
+    def warm_inspect(self, with_grad: bool = True) -> dict:
+        """What the warm start of the last update computed: region nodes (in
+        the network's row order) and their hops, the output o and dL/do
+        (region node x padded seed columns) and the parameter gradient of
+        its training step (when with_grad)."""
+        nR = ctypes.c_int32(0)
+        cols = ctypes.c_int32(0)
+        _check(self._lib, self._ctx, self._lib.rwr_warm_inspect(self._ctx, None, None, None, None, None, 0,
+                                                                 ctypes.byref(nR), ctypes.byref(cols)))
+        n, S = nR.value, cols.value
+        nodes = np.zeros(n, np.int32)
+        hops = np.zeros(n, np.int32)
+        o = np.zeros((n, S), np.float32)
+        dout = np.zeros((n, S), np.float32)
+        grad = np.zeros(int(self._lib.rwr_gnn_num_params()), np.float32)
+        if n:
+            _check(self._lib, self._ctx, self._lib.rwr_warm_inspect(
+                self._ctx, nodes.ctypes.data, hops.ctypes.data, o.ctypes.data,
+                dout.ctypes.data if with_grad else None, grad.ctypes.data if with_grad else None, n,
+                ctypes.byref(nR), ctypes.byref(cols)))
+        return {"nodes": nodes, "hops": hops, "o": o, "dout": dout, "grad": grad}
 
     def refine(self) -> dict:
         st = StatsStruct()
