@@ -111,7 +111,7 @@ typedef struct rwr_stats {
   int32_t ws_region;      /* region nodes the network ran on                               */
   int32_t ws_accepted;    /* seed columns whose seed was replaced by the residual          */
   double ws_resid_ratio;  /* sum_j ||rho_j||_1 / sum_j ||q_j||_1 of the prediction          */
-  double ws_loss;         /* training loss of this update, mean_j ||rho_j|| / ||q_j||      */
+  double ws_loss;         /* training loss of this update, sum_j ||rho_j|| / sum_j ||q_j|| */
   double ms_warm;         /* host wall time of the warm-start steps                        */
   /* cost model of the batch (Section 3.3, effects of Delta G): ||D r_old||_1 with
      D_uu = sum_v |B~[u,v] - A~[u,v]| (row L1 norm of the change of u's row), an
@@ -257,13 +257,22 @@ int64_t rwr_gnn_num_params(void);
 rwr_status rwr_model_set(rwr_ctx *ctx, const float *params, int64_t n);
 rwr_status rwr_model_get(rwr_ctx *ctx, float *params, int64_t cap);
 
+/* Training options of the network: mask (rwr_gnn_num_params() floats, or
+ * NULL for every parameter) marks the parameters the optimiser steps (1) and
+ * those it holds at their value (0); the first warmup_steps steps of AdamW
+ * scale the step size linearly from lr / warmup_steps up to lr.  Copied; kept
+ * across rwr_model_set.  RWR_EINVAL on a wrong count or a negative
+ * warm-up. */
+rwr_status rwr_model_trainable(rwr_ctx *ctx, const float *mask, int64_t n, int32_t warmup_steps);
+
 /* Switch the warm start of rwr_update:
  *   mode 0: off;  1: predict (the update propagates the residual of the
  *   prediction in every seed column where ||rho||_1 < ||q_offset||_1, else
  *   the plain offset seed);  2: train (the update runs plainly; one AdamW
- *   step on this update's loss mean_j ||rho_j||_1 / ||q_j||_1, the L1
+ *   step on this update's loss sum_j ||rho_j||_1 / sum_j ||q_j||_1, the L1
  *   distance of the prediction from the exact offset result measured
- *   through I - (1-c) B~^T);  3: predict and train (the step follows the
+ *   through I - (1-c) B~^T, relative to the seed; its gradient follows the
+ *   correction below);  3: predict and train (the step follows the
  *   prediction of this update).
  * Before the residual is formed, the prediction is corrected so that the
  * residual sums to zero (a residual with a non-zero sum decays only by

@@ -260,7 +260,8 @@ def features(n_total, src, dst, nodes, hop, q, r_old, sigma, seeds):
     0 log(1+d_in)/8, 1 log(1+d_out)/8, 2 q/||q_j||_1, 3 |q|/||q_j||_1,
     4 log(1 + max(0, n r_old/sigma_j))/8, 5..8 hop 0, 1, 2, >=3 (one-hot),
     9 dead end, 10 seed of the column, 11 1/d_out (0 for a dead end),
-    12 1/d_in (0 without in-edges), 13..15 zero.  Degrees are those of the
+    12 1/d_in (0 without in-edges), 13 input 3 * input 0, 14 input 3 *
+    input 1, 15 input 2 * input 0 (in float32).  Degrees are those of the
     graph after the batch; q is the offset seed (n x S), r_old the scores
     before the batch (n x S, rows of new nodes zero), sigma their column
     sums."""
@@ -286,7 +287,11 @@ def features(n_total, src, dst, nodes, hop, q, r_old, sigma, seeds):
     F[:, :, 10] = nodes[:, None] == np.asarray(seeds, np.int64)[None, :]
     F[:, :, 11] = np.where(dout > 0, 1.0 / np.maximum(dout, 1.0), 0.0)[:, None]
     F[:, :, 12] = np.where(din > 0, 1.0 / np.maximum(din, 1.0), 0.0)[:, None]
-    return F.astype(np.float32).astype(np.float64)
+    F = F.astype(np.float32)
+    F[:, :, 13] = F[:, :, 3] * F[:, :, 0]
+    F[:, :, 14] = F[:, :, 3] * F[:, :, 1]
+    F[:, :, 15] = F[:, :, 2] * F[:, :, 0]
+    return F.astype(np.float64)
 
 
 def local_edges(src, dst, nodes):
@@ -316,8 +321,9 @@ def residual_loss(theta, F, lsrc, ldst, dinv, nodes, q, P, live, c, *, follow=Tr
 
     xhat = ||q_j||_1 o on the region rows (o the network output), corrected
     by :func:`mass_correction`, zero elsewhere; rho = q - (I - P) xhat' on
-    every node; L = mean over the columns with ||q_j||_1 > 0 of
-    ||rho_j||_1 / ||q_j||_1.  dL/dxhat' = (-(I - P)^T sign(rho)) / (C ||q_j||_1).
+    every node; over the active columns (||q_j||_1 > 0),
+    L = sum_j ||rho_j||_1 / sum_j ||q_j||_1 and dL/dxhat' = (-(I - P)^T
+    sign(rho)) / Q with Q = sum_j ||q_j||_1.
     With follow=True the gradient goes through the correction exactly:
       dL/dxhat_v = (1 - beta s_v) (dL/dxhat'_v - w_v K / f(|xhat|)),
       K = sum_u dL/dxhat'_u |xhat_u|,  s = sign(xhat);
@@ -330,15 +336,15 @@ def residual_loss(theta, F, lsrc, ldst, dinv, nodes, q, P, live, c, *, follow=Tr
     qn = np.abs(q).sum(axis=0)
     qsum = q[nodes].sum(axis=0)
     active = qn > 0
-    C = max(1, int(active.sum()))
+    Q = float(qn[active].sum())
     xhat = qn[None, :] * o
     xc, beta, fa, w = mass_correction(xhat, live, c, qsum)
     X = np.zeros_like(q)
     X[nodes] = xc
     rho = q - X + P @ X
-    L = float(np.sum(np.abs(rho).sum(axis=0)[active] / qn[active]) / C)
+    L = float(np.abs(rho).sum(axis=0)[active].sum() / Q) if Q > 0 else 0.0
     sg = np.sign(rho)
-    gprime = ((-sg + P.T @ sg)[nodes]) * np.where(active, 1.0 / (C * np.where(qn > 0, qn, 1.0)), 0.0)[None, :]
+    gprime = ((-sg + P.T @ sg)[nodes]) * np.where(active, 1.0 / Q if Q > 0 else 0.0, 0.0)[None, :]
     if follow:
         K = (gprime * np.abs(xhat)).sum(axis=0)
         corr = np.where(fa > 0, K / np.where(fa > 0, fa, 1.0), 0.0)

@@ -196,6 +196,8 @@ struct rwr_ctx {
     int32_t nR = 0;
     std::vector<int32_t> level_end;  // end row of each hop level of the last region
     bool trained = false;            // the last update took a training step
+    std::vector<float> mask_h;       // trainable-parameter mask (empty: all train)
+    int32_t warmup = 0;              // step-size warm-up of the optimiser
     std::vector<double> qn_h;
     int32_t accepted = 0;
     double ratio = 0.0, loss = 0.0, ms = 0.0;
@@ -1162,7 +1164,8 @@ static rwr_status warm_local_graph(rwr_ctx *c) {
 // features, the forward pass, the prediction and its exact residual.
 // Prediction on: the seed becomes the residual in every column where the
 // residual is smaller, and the scores take the prediction.  Training on: one
-// AdamW step on the loss mean_j ||rho_j||_1 / ||q_j||_1 of this prediction.
+// AdamW step on the loss sum_j ||rho_j||_1 / sum_j ||q_j||_1 of this
+// prediction.
 static rwr_status warm_prepare(rwr_ctx *c) {
   rwr_ctx::Warm &w = c->ws;
   const double t0 = now_ms();
@@ -1224,7 +1227,7 @@ static rwr_status warm_prepare(rwr_ctx *c) {
   w.qn_h.assign(S, 0.0);
   D2H(c, w.qn_h.data(), w.qn, sizeof(double) * S);
   uint64_t accept = 0;
-  double num = 0.0, den = 0.0, lsum = 0.0;
+  double num = 0.0, den = 0.0;
   int n_act = 0;
   std::vector<int32_t> act(RWR_MAX_COLS, 0);
   for (int j = 0; j < c->n_seeds; ++j) {
@@ -1234,7 +1237,6 @@ static rwr_status warm_prepare(rwr_ctx *c) {
     ++n_act;
     den += q;
     num += rho;
-    lsum += rho / q;
     if ((w.mode & 1) && rho < q) {
       accept |= 1ull << j;
       ++w.accepted;
@@ -1242,7 +1244,7 @@ static rwr_status warm_prepare(rwr_ctx *c) {
   }
   w.ratio = den > 0.0 ? num / den : 1.0;
   if ((w.mode & 2) && n_act > 0) {
-    w.loss = lsum / n_act;
+    w.loss = num / den;
     H2D(c, w.net.active, act.data(), sizeof(int32_t) * RWR_MAX_COLS);
     // item partials of the gradient: at most one item per region row plus
     // one per GRAD_CHUNK out-edges
@@ -1255,7 +1257,7 @@ static rwr_status warm_prepare(rwr_ctx *c) {
       w.gpart_cap = need;
     }
     HIP_TRY(c, ws_resid_grad(w.R, nR, S, out, c1, c->gbuf, w.gpart, w.items, w.item_off, w.scan_temp, w.scan_bytes,
-                             w.net.active, n_act, w.net.o, w.qn, beta, w.fa, w.kpart, w.net.dout, c->stream));
+                             w.net.active, den, w.net.o, w.qn, beta, w.fa, w.kpart, w.net.dout, c->stream));
     gnn::net_backward(w.net, warm_view(c), rows, c->stream);
     gnn::net_adamw(w.net, c->stream);
     w.trained = true;
@@ -2075,12 +2077,18 @@ rwr_status rwr_warm_start(rwr_ctx *c, int32_t mode, int32_t hops, int64_t max_ro
       keep.resize(gnn::LAYOUT.total);
       HIP_TRY(c, gnn::net_get_params(c->ws.net, keep.data(), c->stream));
     }
+    std::vector<float> mask = c->ws.mask_h;
+    const int32_t warmup = c->ws.warmup;
     warm_free(c);
     RWR_TRY(warm_alloc(c, rows));
     if (!keep.empty()) {
       HIP_TRY(c, gnn::net_set_params(c->ws.net, keep.data(), c->stream));
       c->ws.params = true;
     }
+    c->ws.mask_h = mask;
+    c->ws.warmup = warmup;
+    c->ws.net.warmup = warmup;
+    if (!mask.empty()) HIP_TRY(c, gnn::net_set_mask(c->ws.net, mask.data(), c->stream));
   } else if (!c->ws.alloc) {
     RWR_TRY(warm_alloc(c, rows));
   }
@@ -2101,6 +2109,19 @@ rwr_status rwr_model_set(rwr_ctx *c, const float *params, int64_t n) {
   if (!c->ws.alloc) RWR_TRY(warm_alloc(c, (int64_t)1 << 21));
   HIP_TRY(c, gnn::net_set_params(c->ws.net, params, c->stream));
   c->ws.params = true;
+  return RWR_OK;
+}
+
+rwr_status rwr_model_trainable(rwr_ctx *c, const float *mask, int64_t n, int32_t warmup_steps) {
+  if (!c || (mask && n != gnn::LAYOUT.total) || warmup_steps < 0) return RWR_EINVAL;
+  if (!c->ws.alloc) RWR_TRY(warm_alloc(c, (int64_t)1 << 21));
+  if (mask)
+    c->ws.mask_h.assign(mask, mask + n);
+  else
+    c->ws.mask_h.clear();
+  c->ws.warmup = warmup_steps;
+  c->ws.net.warmup = warmup_steps;
+  HIP_TRY(c, gnn::net_set_mask(c->ws.net, mask ? c->ws.mask_h.data() : nullptr, c->stream));
   return RWR_OK;
 }
 

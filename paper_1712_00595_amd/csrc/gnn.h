@@ -68,6 +68,8 @@ struct Net {
   WeightsBf16 wb;
   int64_t step = 0;
   float lr = 1e-3f, wd = 1e-4f;
+  int64_t warmup = 0;      // steps of linear step-size warm-up
+  float *mask = nullptr;   // trainable parameters (1) and held ones (0); null: all train
   // activations
   float *F = nullptr;                 // rows x FEAT
   float *h[LAYERS + 1] = {};          // rows x HID
@@ -96,7 +98,9 @@ void net_forward(Net &n, const RegionView &g, int64_t rows, hipStream_t st);
 void net_loss(Net &n, int64_t rows, int n_active, hipStream_t st);
 // gradients into n.grad (overwritten)
 void net_backward(Net &n, const RegionView &g, int64_t rows, hipStream_t st);
-// one AdamW step from n.grad
+// one AdamW step from n.grad (masked parameters are held)
 void net_adamw(Net &n, hipStream_t st);
+// trainable-parameter mask (host, LAYOUT.total floats; null: every parameter trains)
+hipError_t net_set_mask(Net &n, const float *host, hipStream_t st);
 
 }  // namespace gnn

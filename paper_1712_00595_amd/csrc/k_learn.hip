@@ -380,10 +380,14 @@ __global__ void k_out_bwd(int64_t M, const float *__restrict__ dout, const float
 }
 
 // ------------------------------------------------------------ optimiser
+// mask (may be null): parameters whose entry is 0 are held (no step, moments
+// untouched)
 __global__ void k_adamw(int64_t n, float *__restrict__ theta, const float *__restrict__ g, float *__restrict__ m1,
-                        float *__restrict__ m2, float lr, float wd, float c1, float c2) {
+                        float *__restrict__ m2, const float *__restrict__ mask, float lr, float wd, float c1,
+                        float c2) {
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (mask && mask[i] == 0.0f) continue;
     const float gi = g[i];
     const float a = b1 * m1[i] + (1.0f - b1) * gi;
     const float b = b2 * m2[i] + (1.0f - b2) * gi * gi;
@@ -448,7 +452,7 @@ hipError_t net_alloc(Net &n, int S, int64_t max_rows) {
 
 void net_free(Net &n) {
   void *ps[] = {n.theta, n.grad, n.m1, n.m2, n.wb.fwd, n.wb.bwd, n.F, n.m, n.o, n.t, n.dh, n.dz, n.da, n.dm,
-                n.dout, n.part, n.loss_part, n.loss, n.active};
+                n.dout, n.part, n.loss_part, n.loss, n.active, n.mask};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   for (int l = 0; l <= LAYERS; ++l)
@@ -560,9 +564,22 @@ void net_adamw(Net &n, hipStream_t st) {
   ++n.step;
   const float c1 = 1.0f - powf(0.9f, (float)n.step);
   const float c2 = 1.0f - powf(0.999f, (float)n.step);
+  // linear warm-up of the step size over the first `warmup` steps
+  const float lr = n.warmup > 0 && n.step < n.warmup ? n.lr * (float)n.step / (float)n.warmup : n.lr;
   hipLaunchKernelGGL(k_adamw, dim3(grid_for(LAYOUT.total, GB)), dim3(GB), 0, st, LAYOUT.total, n.theta, n.grad,
-                     n.m1, n.m2, n.lr, n.wd, c1, c2);
+                     n.m1, n.m2, n.mask, lr, n.wd, c1, c2);
   net_prepare_weights(n, st);
+}
+
+hipError_t net_set_mask(Net &n, const float *host, hipStream_t st) {
+  if (!host) {
+    if (n.mask) (void)hipFree(n.mask);
+    n.mask = nullptr;
+    return hipSuccess;
+  }
+  if (!n.mask) GNN_TRY(dalloc(&n.mask, LAYOUT.total));
+  GNN_TRY(hipMemcpyAsync(n.mask, host, sizeof(float) * LAYOUT.total, hipMemcpyHostToDevice, st));
+  return hipStreamSynchronize(st);
 }
 
 }  // namespace gnn

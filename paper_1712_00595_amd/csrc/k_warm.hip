@@ -173,9 +173,11 @@ __global__ void k_ws_features(const int32_t *__restrict__ R, int32_t nR, int S, 
     f[10] = (j < RWR_MAX_COLS && seeds[j] == v) ? 1.0f : 0.0f;
     f[11] = dout ? 1.0f / (float)dout : 0.0f;
     f[12] = din ? 1.0f / (float)din : 0.0f;
-    f[13] = 0.0f;
-    f[14] = 0.0f;
-    f[15] = 0.0f;
+    // the degree inputs scaled by the offset seed (they grow with it, as
+    // the prediction must)
+    f[13] = f[3] * f[0];
+    f[14] = f[3] * f[1];
+    f[15] = f[2] * f[0];
     float4 *dst = reinterpret_cast<float4 *>(F + row * 16);
     dst[0] = float4{f[0], f[1], f[2], f[3]};
     dst[1] = float4{f[4], f[5], f[6], f[7]};
@@ -324,12 +326,14 @@ __global__ void k_ws_sigma(Ctl *ctl, int S, uint64_t accept, const double *__res
 }
 
 // ------------------------------------------------------------ training
-// Gradient of the training loss L = mean over active columns j of
-// ||rho_j||_1 / ||q_j||_1 with respect to the network output o (xhat =
-// ||q|| o, corrected to xhat' = xhat - beta |xhat|, rho = q - (I - P) xhat',
-// P = (1-c) B~^T).  With the correction held fixed:
-//   d(u, j) = (-(I - P)^T sign(rho_j))(u) / C
-//           = (-sign(rho(u, j)) + (1-c)/d_out(u) sum over u -> v of sign(rho(v, j))) / C,
+// Gradient of the training loss L = sum_j ||rho_j||_1 / sum_j ||q_j||_1 over
+// the active columns (the columns with the largest residuals set the
+// iteration count, and eps is absolute) with respect to the network output o
+// (xhat = ||q|| o, corrected to xhat' = xhat - beta |xhat|, rho = q - (I - P)
+// xhat', P = (1-c) B~^T).  With the correction held fixed:
+//   d(u, j) = ||q_j|| (-(I - P)^T sign(rho_j))(u) / Q
+//           = ||q_j|| (-sign(rho(u, j)) + (1-c)/d_out(u) sum over u -> v of sign(rho(v, j))) / Q,
+//   Q = sum over active columns of ||q_j||_1,
 // and through the correction exactly (beta depends on xhat):
 //   dL/do(v, j) = (1 - beta_j s(v, j)) (d(v, j) - w_v ||q_j|| K_j / f_j),
 //   K_j = sum_u d(u, j) |o(u, j)|,  f_j = f(|xhat_j|),  s = sign(o),
@@ -384,7 +388,8 @@ __global__ __launch_bounds__(WB) void k_ws_grad_fixed(const int32_t *__restrict_
                                                       DevGraphView out, double c1, const double *__restrict__ rho,
                                                       const double *__restrict__ gpart,
                                                       const int32_t *__restrict__ item_off,
-                                                      const int32_t *__restrict__ active, double inv_cols,
+                                                      const int32_t *__restrict__ active,
+                                                      const double *__restrict__ qn, double inv_q,
                                                       const float *__restrict__ o, float *__restrict__ dout,
                                                       double *__restrict__ kpart) {
   __shared__ double red[WB];
@@ -397,7 +402,8 @@ __global__ __launch_bounds__(WB) void k_ws_grad_fixed(const int32_t *__restrict_
     const int d = out.len[u];
     double t = 0.0;
     for (int32_t it = item_off[i]; it < item_off[i + 1]; ++it) t += gpart[(int64_t)it * S + j];
-    const double g = active[j] ? (-sgn(rho[col_index(u, S, j)]) + (d ? c1 * t / (double)d : 0.0)) * inv_cols : 0.0;
+    const double g =
+        active[j] ? (-sgn(rho[col_index(u, S, j)]) + (d ? c1 * t / (double)d : 0.0)) * qn[j] * inv_q : 0.0;
     dout[row] = (float)g;
     kk += (double)(float)g * fabs((double)o[row]);
   }
@@ -553,8 +559,8 @@ void ws_apply(int32_t n, int S, uint64_t accept, double *ybuf, const double *gbu
 
 hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *rho,
                          double *gpart, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
-                         const int32_t *active, int n_active, const float *o, const double *qn, const double *beta,
-                         const double *fa, double *kpart, float *dout, hipStream_t s) {
+                         const int32_t *active, double q_active, const float *o, const double *qn,
+                         const double *beta, const double *fa, double *kpart, float *dout, hipStream_t s) {
   hipLaunchKernelGGL(k_ws_grad_items, dim3(wgrid((int64_t)nR + 1)), dim3(WB), 0, s, R, nR, out, items);
   hipError_t e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, items, item_off, nR + 1, s);
   if (e != hipSuccess) return e;
@@ -574,10 +580,10 @@ hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView
     default:
       break;
   }
-  const double inv = 1.0 / (double)std::max(1, n_active);
+  const double inv = q_active > 0.0 ? 1.0 / q_active : 0.0;
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)nR * S + WB - 1) / WB, WS_KPART_BLOCKS));
-  hipLaunchKernelGGL(k_ws_grad_fixed, dim3(nb), dim3(WB), 0, s, R, nR, S, out, c1, rho, gpart, item_off, active, inv,
-                     o, dout, kpart);
+  hipLaunchKernelGGL(k_ws_grad_fixed, dim3(nb), dim3(WB), 0, s, R, nR, S, out, c1, rho, gpart, item_off, active, qn,
+                     inv, o, dout, kpart);
   hipLaunchKernelGGL(k_ws_grad_corr, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, R, nR, S, out, c1, kpart, nb, qn,
                      beta, fa, o, dout);
   return hipSuccess;

@@ -7,7 +7,8 @@
 //   5..8  hop distance from the offset support: 0, 1, 2, >= 3 (one-hot)
 //   9  1 for a dead end              10 1 when v is seed j
 //   11 1/d_out(v) (0 for a dead end) 12 1/d_in(v) (0 without in-edges)
-//   13..15 zero
+//   13 input 3 * input 0             14 input 3 * input 1
+//   15 input 2 * input 0
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -65,5 +66,5 @@ void ws_apply(int32_t n, int S, uint64_t accept, double *ybuf, const double *gbu
 #define WS_KPART_BLOCKS 1024
 hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *rho,
                          double *gpart, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
-                         const int32_t *active, int n_active, const float *o, const double *qn, const double *beta,
-                         const double *fa, double *kpart, float *dout, hipStream_t s);
+                         const int32_t *active, double q_active, const float *o, const double *qn,
+                         const double *beta, const double *fa, double *kpart, float *dout, hipStream_t s);

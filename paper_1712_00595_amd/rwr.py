@@ -51,6 +51,7 @@ EXPORTED = [
     "rwr_model_get",
     "rwr_warm_start",
     "rwr_warm_inspect",
+    "rwr_model_trainable",
 ]
 
 
@@ -153,6 +154,7 @@ def load_library(path: str = LIB_PATH):
     L.rwr_model_get.argtypes = [p, p, i64]
     L.rwr_warm_start.argtypes = [p, i32, i32, i64, ctypes.c_float, ctypes.c_float]
     L.rwr_warm_inspect.argtypes = [p, p, p, p, p, p, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.rwr_model_trainable.argtypes = [p, p, i64, i32]
     for name in EXPORTED:
         f = getattr(L, name)
         if name not in ("rwr_destroy", "rwr_last_error", "rwr_gnn_num_params"):
@@ -323,6 +325,16 @@ class Context:
         out = np.zeros(n, np.float32)
         _check(self._lib, self._ctx, self._lib.rwr_model_get(self._ctx, out.ctypes.data, n))
         return out
+
+    def model_trainable(self, mask=None, warmup: int = 0) -> None:
+        """Parameters the optimiser steps (mask 1) or holds (0); None: all.
+        warmup: steps of linear step-size warm-up."""
+        if mask is None:
+            _check(self._lib, self._ctx, self._lib.rwr_model_trainable(self._ctx, None, 0, int(warmup)))
+            return
+        mk = np.ascontiguousarray(np.asarray(mask, np.float32))
+        _check(self._lib, self._ctx, self._lib.rwr_model_trainable(self._ctx, mk.ctypes.data, mk.shape[0],
+                                                                    int(warmup)))
 
     def warm_start(self, mode: str = "predict", hops: int = 3, max_rows: int = 0, lr: float = 1e-5,
                    weight_decay: float = 1e-4) -> None:

@@ -20,6 +20,13 @@ the untrained network already predicts something useful:
 
 Every other unit starts silent at the output (wo = 0): even a small output on
 each of many region nodes would add up to more than ||q||.
+
+For the same reason the trainable network is kept positively homogeneous in
+the offset seed (``trainable_mask``): biases stay zero and only the inputs
+that scale with q (2, 3 and the q-scaled degrees 13-15) have weights, so
+every unit's activation, and the prediction, grows with q.  A unit driven by
+the degree inputs alone would add the same amount on every region node
+whatever the seed, which no training signal can keep in check.
 """
 
 from __future__ import annotations
@@ -28,8 +35,9 @@ import numpy as np
 
 FEAT, HID, MSG, LAYERS = 16, 64, 16, 3
 
-# inputs 2 and 3 of a row: q / ||q|| and |q| / ||q||
+# inputs 2 and 3 of a row: q / ||q|| and |q| / ||q||; 13-15 q-scaled degrees
 _Q, _QABS = 2, 3
+Q_INPUTS = (2, 3, 13, 14, 15)
 
 
 def layout():
@@ -52,6 +60,10 @@ def init_params(seed: int = 5, prior: str = "propagation", c: float = 0.15, scal
             parts[name] = scale * rng.uniform(-1.0, 1.0, size=shape) / np.sqrt(shape[0])
     if prior == "none":
         return np.concatenate([parts[n].reshape(-1) for n, _ in layout()]).astype(np.float32)
+    # homogeneous in q: no weight on the inputs that do not scale with it
+    for f in range(FEAT):
+        if f not in Q_INPUTS:
+            parts["W0"][f, :] = 0.0
     k = 4 if prior == "propagation" else 2  # units reserved for the prior
     # reserved units take input only from the prior's own paths
     parts["W0"][:, :k] = 0.0
@@ -91,4 +103,18 @@ def init_params(seed: int = 5, prior: str = "propagation", c: float = 0.15, scal
             wm[0, 2] = wm[1, 3] = c1
             ws[2, 2] = ws[3, 3] = 1.0
         parts["wo"][2], parts["wo"][3] = 1.0, -1.0
+    return np.concatenate([parts[n].reshape(-1) for n, _ in layout()]).astype(np.float32)
+
+
+def trainable_mask() -> np.ndarray:
+    """1 for the parameters the optimiser may step, 0 for the ones held at
+    zero so that the network stays positively homogeneous in q: every bias
+    and the first-layer weights of the inputs that do not scale with q."""
+    parts = {name: np.ones(shape) for name, shape in layout()}
+    for name in parts:
+        if name.startswith("b"):
+            parts[name][:] = 0.0
+    for f in range(FEAT):
+        if f not in Q_INPUTS:
+            parts["W0"][f, :] = 0.0
     return np.concatenate([parts[n].reshape(-1) for n, _ in layout()]).astype(np.float32)

@@ -102,55 +102,62 @@ def test_settings_are_checked():
 
 
 def test_training_keeps_exactness_and_the_trained_network_gains():
-    # online training (residual loss, AdamW) on 150 updates of a stream, then
-    # 30 held-out updates run with and without the prediction: the scores
-    # stay within the OSP-T gate, and the prediction shrinks the propagated
-    # seed and the iteration count against plain OSP on the same updates
+    # online training (residual loss, AdamW on the trainable parameters of the
+    # homogeneous network, step-size warm-up) on 600 updates of a stream,
+    # starting from the copy prior (the network predicts q itself); then 30
+    # held-out updates run plainly, with the untrained copy prior and with
+    # the trained network: the scores stay within the OSP-T gate, and the
+    # trained network leaves a residual less than half the copy prior's and
+    # takes fewer iterations than both the copy prior and plain OSP-T.  The
+    # analytic propagation prior (four terms of the offset series) is printed
+    # beside it: training from the copy prior comes close to it.
     print("[warm train]", flush=True)
-    from paper_1712_00595_amd.warm import init_params
+    from paper_1712_00595_amd.warm import init_params, trainable_mask
 
     g = rmat_graph(12, 40000, dead_end_self_loops=True)
     seeds = sample_seeds(g, 4, seed=3)
     model = EdgeSetModel(g.n, g.src, g.dst)
     rng = np.random.default_rng(4)
-    train = [mixed_batch(rng, model, 50, 50) for _ in range(150)]
+    train = [mixed_batch(rng, model, 50, 50) for _ in range(600)]
     held = [mixed_batch(rng, model, 50, 50) for _ in range(30)]
     eps = 1e-9
     kw = dict(eps=eps, precision="fp32")
-    th0 = init_params(5)
+    th0 = init_params(5, prior="copy")
     with rwr.Context(g.n, g.src, g.dst, seeds, **kw) as trainer:
         trainer.model_set(th0)
-        trainer.warm_start("predict+train", hops=3, lr=1e-5)
+        trainer.model_trainable(trainable_mask(), warmup=30)
+        trainer.warm_start("predict+train", hops=3, lr=3e-4)
         losses = [trainer.update_batch(b)["ws_loss"] for b in train]
         th = trainer.model_get()
     assert np.all(np.isfinite(losses)) and not np.array_equal(th, th0)
-    assert np.mean(losses[-30:]) < 1.0
+    # parameters outside the mask did not move
+    assert np.array_equal(th[trainable_mask() == 0], th0[trainable_mask() == 0])
+    assert np.mean(losses[-50:]) < 0.5 * np.mean(losses[:20])
     res = {}
-    for name, params in (("trained", th), ("prior", th0)):
-        with rwr.Context(g.n, g.src, g.dst, seeds, **kw) as plain, \
-                rwr.Context(g.n, g.src, g.dst, seeds, **kw) as warm:
-            warm.model_set(params)
-            warm.warm_start("predict", hops=3)
+    for name, params in (("plain", None), ("copy prior", th0), ("trained", th),
+                         ("propagation prior", init_params(5, prior="propagation"))):
+        with rwr.Context(g.n, g.src, g.dst, seeds, **kw) as ctx:
             for b in train:
-                plain.update_batch(b)
-                warm.update_batch(b)
-            ip, iw, ratio = [], [], []
+                ctx.update_batch(b)
+            if params is not None:
+                ctx.model_set(params)
+                ctx.warm_start("predict", hops=3)
+            it, ratio = [], []
             for b in held:
-                ip.append(plain.update_batch(b)["iters"])
-                st = warm.update_batch(b)
-                iw.append(st["iters"])
+                st = ctx.update_batch(b)
+                it.append(st["iters"])
                 ratio.append(st["ws_resid_ratio"])
-            res[name] = (np.mean(ip), np.mean(iw), np.mean(ratio))
+            res[name] = (float(np.mean(it)), float(np.mean(ratio)))
             if name == "trained":
                 n, s, d = g.n, g.src, g.dst
                 for b in train + held:
                     n, s, d = oracle.apply_batch(n, s, d, b)
                 for j, sd in enumerate(seeds):
                     ref = oracle.rwr_static(n, s, d, int(sd), 0.15)
-                    assert _l1(warm.scores(j), ref) <= 2 * eps / 0.15
-    print("held-out (plain iters, warm iters, residual ratio): " + str(res), flush=True)
-    # against plain OSP on the same updates; the untrained copy prior is
-    # printed beside it (training is not claimed to beat it at this size)
-    ip, iw, ratio = res["trained"]
-    assert ratio < 0.9
-    assert iw < ip
+                    assert _l1(ctx.scores(j), ref) <= 2 * eps / 0.15
+    print("held-out (mean iterations, residual ratio): " + str(res), flush=True)
+    it_plain, _ = res["plain"]
+    it_copy, r_copy = res["copy prior"]
+    it_tr, r_tr = res["trained"]
+    assert r_tr < 0.5 * r_copy, res
+    assert it_tr < it_copy and it_tr < it_plain, res

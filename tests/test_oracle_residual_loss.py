@@ -112,8 +112,9 @@ def test_exact_gradient_matches_central_differences(seed):
 def test_holding_the_correction_fixed_is_a_measured_approximation():
     # the gradient that ignores the correction's derivative (the correction
     # taken as a constant) has the same loss but differs from the exact
-    # gradient by a large amount, and in some of these cases it does not even
-    # point downhill: it is not a usable training signal
+    # gradient by 30 % or more of its norm in every case here; without the
+    # first layer's homogeneity (weights on the degree inputs) it is not
+    # even a descent direction in some of them
     gaps, cosines = [], []
     for seed in range(6):
         case = _case(seed)
@@ -123,8 +124,17 @@ def test_holding_the_correction_fixed_is_a_measured_approximation():
         ge, gf = exact["grad"], fixed["grad"]
         gaps.append(np.linalg.norm(ge - gf) / np.linalg.norm(ge))
         cosines.append(ge @ gf / (np.linalg.norm(ge) * np.linalg.norm(gf)))
-    assert min(gaps) > 0.1, gaps
-    assert min(cosines) < 0.0 < max(cosines), cosines
+    assert min(gaps) > 0.3, gaps
+    neg = []
+    for seed in range(6):
+        case = _case(seed)
+        p = gnn.unpack(case["theta"])
+        p["W0"] = p["W0"] + 0.3 * np.random.default_rng(seed).uniform(-1, 1, p["W0"].shape)
+        case["theta"] = gnn.pack(p)
+        ge = gnn.residual_loss(**case)["grad"]
+        gf = gnn.residual_loss(**case, follow=False)["grad"]
+        neg.append(ge @ gf / (np.linalg.norm(ge) * np.linalg.norm(gf)))
+    assert min(neg) < 0.0, neg
 
 
 def test_corrected_residual_sums_to_zero_with_dead_ends():
@@ -231,4 +241,6 @@ def test_features_closed_forms():
     assert f1[10] == 1 and f3[10] == 0
     assert f1[11] == pytest.approx(0.5) and f3[11] == 0
     assert f1[12] == pytest.approx(1.0) and f3[12] == pytest.approx(1.0)
-    assert np.all(F[..., 13:] == 0)
+    assert f1[13] == pytest.approx(0.5 * np.log(2) / 8, rel=1e-6)
+    assert f1[14] == pytest.approx(0.5 * np.log(3) / 8, rel=1e-6)
+    assert f3[15] == pytest.approx(-0.25 * np.log(2) / 8, rel=1e-6)
