@@ -318,6 +318,22 @@ rwr_status rwr_gnn_eval(const float *params, int32_t nR, int32_t S, const int32_
                         const float *target, const int32_t *active, float *out, float *grad, double *loss,
                         float *params_after);
 
+/* The same evaluation as rwr_gnn_eval, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops): it
+ * allocates nothing, running in one fixed array of 24 MiB that each device
+ * the library runs on holds from this function's first call on it until the
+ * process ends.  Limits: nR * S <= 8192 rows and n_in, n_out <= 131072 edges
+ * (RWR_EINVAL beyond them, message in rwr_last_error(NULL)).  stream: the
+ * hipStream_t to run on (NULL: the default stream); the call is synchronous
+ * on return.  Arguments, outputs and results as rwr_gnn_eval.  Every call on
+ * a device shares that device's array: calls that overlap on one device race
+ * and must be serialised by the caller. */
+rwr_status rwr_gnn_eval_noalloc(const float *params, int32_t nR, int32_t S, const int32_t *in_off,
+                                const int32_t *in_len, const int32_t *in_adj, int64_t n_in, const int32_t *out_off,
+                                const int32_t *out_len, const int32_t *out_adj, int64_t n_out, const float *dinv,
+                                const float *feats, const float *target, const int32_t *active, float *out,
+                                float *grad, double *loss, float *params_after, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

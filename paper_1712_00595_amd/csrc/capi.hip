@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1289,6 +1290,104 @@ static void fill_stats(rwr_ctx *c, rwr_stats *st) {
   st->dr_l1 = dr;
 }
 
+// argument checks shared by rwr_gnn_eval and rwr_gnn_eval_noalloc
+static rwr_status gnn_eval_check(const float *params, int32_t nR, int32_t S, const int32_t *in_off,
+                                 const int32_t *in_len, const int32_t *in_adj, int64_t n_in, const int32_t *out_off,
+                                 const int32_t *out_len, const int32_t *out_adj, int64_t n_out, const float *dinv,
+                                 const float *feats, const float *target, const int32_t *active, float *grad,
+                                 double *loss, float *params_after) {
+  if (!params || nR <= 0 || S < 1 || S > RWR_MAX_COLS || !in_off || !in_len || (n_in > 0 && !in_adj) ||
+      !out_off || !out_len || (n_out > 0 && !out_adj) || !dinv || !feats || n_in < 0 || n_out < 0) {
+    g_build_error = "invalid arguments";
+    return RWR_EINVAL;
+  }
+  if ((target == nullptr) != (active == nullptr) || ((grad || loss || params_after) && !target)) {
+    g_build_error = "gradients need a target and active columns";
+    return RWR_EINVAL;
+  }
+  for (int32_t i = 0; i < nR; ++i) {
+    if (in_len[i] < 0 || out_len[i] < 0 || in_off[i] < 0 || out_off[i] < 0 || in_off[i] + (int64_t)in_len[i] > n_in ||
+        out_off[i] + (int64_t)out_len[i] > n_out) {
+      g_build_error = "region rows out of range";
+      return RWR_EINVAL;
+    }
+  }
+  for (int64_t e = 0; e < n_in; ++e)
+    if (in_adj[e] < 0 || in_adj[e] >= nR) {
+      g_build_error = "region adjacency id out of range";
+      return RWR_EINVAL;
+    }
+  for (int64_t e = 0; e < n_out; ++e)
+    if (out_adj[e] < 0 || out_adj[e] >= nR) {
+      g_build_error = "region adjacency id out of range";
+      return RWR_EINVAL;
+    }
+  return RWR_OK;
+}
+
+// --------------------------------------------- evaluation without allocation
+// rwr_gnn_eval_noalloc runs the network in one fixed file-scope device array
+// instead of memory it allocates: regions of at most NA_MAX_ROWS (node,
+// column) rows and NA_MAX_EDGES edges per orientation.  Each device holds its
+// own copy of the array until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress gives on that device (the array's
+// name on the host is a stand-in, not a device address).
+#define NA_MAX_ROWS 8192
+#define NA_MAX_EDGES 131072
+#define NA_BYTES (24u << 20)
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+static std::mutex g_na_mu;
+static void *g_na_ptr[64] = {};
+
+// the array's device address on the current device (looked up once per device)
+static rwr_status noalloc_scratch(void **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    g_build_error = "no usable current device";
+    return RWR_EHIP;
+  }
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      g_build_error = std::string("hipGetSymbolAddress of the scratch array failed: ") + hipGetErrorString(e);
+      return RWR_EHIP;
+    }
+    g_na_ptr[dev] = ptr;
+  }
+  *out = g_na_ptr[dev];
+  return RWR_OK;
+}
+
+// items[i] = sum over k < i of ceil(len[k] / chunk), i = 0 .. nR (one
+// workgroup of NA_SCAN threads: per-thread ranges, then a scan of their sums)
+#define NA_SCAN 1024
+__global__ __launch_bounds__(NA_SCAN) void k_na_items(const int32_t *__restrict__ len, int32_t nR, int32_t chunk,
+                                                      int32_t *__restrict__ items) {
+  __shared__ int32_t tot[NA_SCAN];
+  const int t = threadIdx.x;
+  const int32_t per = (nR + NA_SCAN - 1) / NA_SCAN;
+  const int32_t lo = min(nR, t * per), hi = min(nR, lo + per);
+  int32_t s = 0;
+  for (int32_t i = lo; i < hi; ++i) s += (len[i] + chunk - 1) / chunk;
+  tot[t] = s;
+  __syncthreads();
+  for (int off = 1; off < NA_SCAN; off <<= 1) {
+    const int32_t v = t >= off ? tot[t - off] : 0;
+    __syncthreads();
+    tot[t] += v;
+    __syncthreads();
+  }
+  int32_t acc = tot[t] - s;  // exclusive prefix of this thread's range
+  for (int32_t i = lo; i < hi; ++i) {
+    items[i] = acc;
+    acc += (len[i] + chunk - 1) / chunk;
+  }
+  if (t == NA_SCAN - 1) items[nR] = tot[t];
+}
+
 // ------------------------------------------------------------------ ABI
 extern "C" {
 
@@ -2169,38 +2268,126 @@ rwr_status rwr_warm_inspect(rwr_ctx *c, int32_t *nodes, int32_t *hops, float *o,
   return RWR_OK;
 }
 
+rwr_status rwr_gnn_eval_noalloc(const float *params, int32_t nR, int32_t S, const int32_t *in_off,
+                                const int32_t *in_len, const int32_t *in_adj, int64_t n_in, const int32_t *out_off,
+                                const int32_t *out_len, const int32_t *out_adj, int64_t n_out, const float *dinv,
+                                const float *feats, const float *target, const int32_t *active, float *out,
+                                float *grad, double *loss, float *params_after, void *stream) {
+  g_build_error.clear();
+  RWR_TRY(gnn_eval_check(params, nR, S, in_off, in_len, in_adj, n_in, out_off, out_len, out_adj, n_out, dinv, feats,
+                         target, active, grad, loss, params_after));
+  const int64_t rows = (int64_t)nR * S;
+  if (rows > NA_MAX_ROWS || n_in > NA_MAX_EDGES || n_out > NA_MAX_EDGES) {
+    g_build_error = "region exceeds the fixed scratch of rwr_gnn_eval_noalloc (" + std::to_string(NA_MAX_ROWS) +
+                    " rows, " + std::to_string(NA_MAX_EDGES) + " edges per orientation)";
+    return RWR_EINVAL;
+  }
+  void *base = nullptr;
+  RWR_TRY(noalloc_scratch(&base));
+  const hipStream_t st = (hipStream_t)stream;
+  // the network's buffers, then the region arrays, carved from the scratch
+  gnn::Net net;
+  size_t used = gnn::net_view(net, S, NA_MAX_ROWS, base, NA_BYTES);
+  char *p = static_cast<char *>(base);
+  auto take = [&](size_t bytes) -> void * {
+    const size_t b = (bytes + 255) / 256 * 256;
+    if (used == 0 || used + b > NA_BYTES) {
+      used = 0;
+      return nullptr;
+    }
+    void *q = p + used;
+    used += b;
+    return q;
+  };
+  int32_t *d_in_off = (int32_t *)take(sizeof(int32_t) * NA_MAX_ROWS);
+  int32_t *d_in_len = (int32_t *)take(sizeof(int32_t) * NA_MAX_ROWS);
+  int32_t *d_out_off = (int32_t *)take(sizeof(int32_t) * NA_MAX_ROWS);
+  int32_t *d_out_len = (int32_t *)take(sizeof(int32_t) * NA_MAX_ROWS);
+  int32_t *d_in_items = (int32_t *)take(sizeof(int32_t) * (NA_MAX_ROWS + 1));
+  int32_t *d_out_items = (int32_t *)take(sizeof(int32_t) * (NA_MAX_ROWS + 1));
+  int32_t *d_in_adj = (int32_t *)take(sizeof(int32_t) * NA_MAX_EDGES);
+  int32_t *d_out_adj = (int32_t *)take(sizeof(int32_t) * NA_MAX_EDGES);
+  float *d_dinv = (float *)take(sizeof(float) * NA_MAX_ROWS);
+  if (used == 0) {
+    g_build_error = "scratch layout does not fit";
+    return RWR_ENOMEM;
+  }
+#define NA_TRY(expr)                                                  \
+  do {                                                                \
+    const hipError_t _e = (expr);                                     \
+    if (_e != hipSuccess) {                                           \
+      g_build_error = std::string(#expr) + ": " + hipGetErrorString(_e); \
+      return RWR_EHIP;                                                \
+    }                                                                 \
+  } while (0)
+  const int64_t P = gnn::LAYOUT.total;
+  // parameters; the optimiser starts from zero moments (the scratch keeps
+  // the previous call's contents)
+  NA_TRY(hipMemcpyAsync(net.theta, params, sizeof(float) * P, hipMemcpyHostToDevice, st));
+  launch_zero_bytes(net.m1, sizeof(float) * P, st);
+  launch_zero_bytes(net.m2, sizeof(float) * P, st);
+  net.step = 0;
+  gnn::net_prepare_weights(net, st);
+  NA_TRY(hipMemcpyAsync(d_in_off, in_off, sizeof(int32_t) * nR, hipMemcpyHostToDevice, st));
+  NA_TRY(hipMemcpyAsync(d_in_len, in_len, sizeof(int32_t) * nR, hipMemcpyHostToDevice, st));
+  NA_TRY(hipMemcpyAsync(d_out_off, out_off, sizeof(int32_t) * nR, hipMemcpyHostToDevice, st));
+  NA_TRY(hipMemcpyAsync(d_out_len, out_len, sizeof(int32_t) * nR, hipMemcpyHostToDevice, st));
+  if (n_in > 0) NA_TRY(hipMemcpyAsync(d_in_adj, in_adj, sizeof(int32_t) * n_in, hipMemcpyHostToDevice, st));
+  if (n_out > 0) NA_TRY(hipMemcpyAsync(d_out_adj, out_adj, sizeof(int32_t) * n_out, hipMemcpyHostToDevice, st));
+  NA_TRY(hipMemcpyAsync(d_dinv, dinv, sizeof(float) * nR, hipMemcpyHostToDevice, st));
+  NA_TRY(hipMemcpyAsync(net.F, feats, sizeof(float) * rows * gnn::FEAT, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_na_items, dim3(1), dim3(NA_SCAN), 0, st, d_in_len, nR, (int32_t)gnn::AGG_CHUNK, d_in_items);
+  hipLaunchKernelGGL(k_na_items, dim3(1), dim3(NA_SCAN), 0, st, d_out_len, nR, (int32_t)gnn::AGG_CHUNK, d_out_items);
+  int64_t ni = 0, no = 0;
+  for (int32_t i = 0; i < nR; ++i) {
+    ni += (in_len[i] + gnn::AGG_CHUNK - 1) / gnn::AGG_CHUNK;
+    no += (out_len[i] + gnn::AGG_CHUNK - 1) / gnn::AGG_CHUNK;
+  }
+  gnn::RegionView g{};
+  g.in_off = d_in_off;
+  g.in_len = d_in_len;
+  g.in_adj = d_in_adj;
+  g.out_off = d_out_off;
+  g.out_len = d_out_len;
+  g.out_adj = d_out_adj;
+  g.in_items = d_in_items;
+  g.out_items = d_out_items;
+  g.n_in_items = (int32_t)ni;
+  g.n_out_items = (int32_t)no;
+  g.loc = nullptr;
+  g.nodes = nullptr;
+  g.dinv = d_dinv;
+  g.nR = nR;
+  gnn::net_forward(net, g, rows, st);
+  if (target) {
+    int32_t act[RWR_MAX_COLS] = {};
+    int n_act = 0;
+    for (int j = 0; j < S; ++j) n_act += (act[j] = active[j] ? 1 : 0);
+    NA_TRY(hipMemcpyAsync(net.t, target, sizeof(float) * rows, hipMemcpyHostToDevice, st));
+    NA_TRY(hipMemcpyAsync(net.active, act, sizeof(int32_t) * RWR_MAX_COLS, hipMemcpyHostToDevice, st));
+    gnn::net_loss(net, rows, n_act, st);
+    gnn::net_backward(net, g, rows, st);
+    if (params_after) gnn::net_adamw(net, st);
+    // act lives on this stack frame: the copy must finish before return
+    NA_TRY(hipStreamSynchronize(st));
+  }
+  if (out) NA_TRY(hipMemcpyAsync(out, net.o, sizeof(float) * rows, hipMemcpyDeviceToHost, st));
+  if (grad) NA_TRY(hipMemcpyAsync(grad, net.grad, sizeof(float) * P, hipMemcpyDeviceToHost, st));
+  if (loss) NA_TRY(hipMemcpyAsync(loss, net.loss, sizeof(double), hipMemcpyDeviceToHost, st));
+  if (params_after) NA_TRY(hipMemcpyAsync(params_after, net.theta, sizeof(float) * P, hipMemcpyDeviceToHost, st));
+  NA_TRY(hipStreamSynchronize(st));
+#undef NA_TRY
+  return RWR_OK;
+}
+
 rwr_status rwr_gnn_eval(const float *params, int32_t nR, int32_t S, const int32_t *in_off, const int32_t *in_len,
                         const int32_t *in_adj, int64_t n_in, const int32_t *out_off, const int32_t *out_len,
                         const int32_t *out_adj, int64_t n_out, const float *dinv, const float *feats,
                         const float *target, const int32_t *active, float *out, float *grad, double *loss,
                         float *params_after) {
   g_build_error.clear();
-  if (!params || nR <= 0 || S < 1 || S > RWR_MAX_COLS || !in_off || !in_len || (n_in > 0 && !in_adj) ||
-      !out_off || !out_len || (n_out > 0 && !out_adj) || !dinv || !feats || n_in < 0 || n_out < 0) {
-    g_build_error = "invalid arguments";
-    return RWR_EINVAL;
-  }
-  if ((target == nullptr) != (active == nullptr) || ((grad || loss || params_after) && !target)) {
-    g_build_error = "gradients need a target and active columns";
-    return RWR_EINVAL;
-  }
-  for (int32_t i = 0; i < nR; ++i) {
-    if (in_len[i] < 0 || out_len[i] < 0 || in_off[i] < 0 || out_off[i] < 0 || in_off[i] + (int64_t)in_len[i] > n_in ||
-        out_off[i] + (int64_t)out_len[i] > n_out) {
-      g_build_error = "region rows out of range";
-      return RWR_EINVAL;
-    }
-  }
-  for (int64_t e = 0; e < n_in; ++e)
-    if (in_adj[e] < 0 || in_adj[e] >= nR) {
-      g_build_error = "region adjacency id out of range";
-      return RWR_EINVAL;
-    }
-  for (int64_t e = 0; e < n_out; ++e)
-    if (out_adj[e] < 0 || out_adj[e] >= nR) {
-      g_build_error = "region adjacency id out of range";
-      return RWR_EINVAL;
-    }
+  RWR_TRY(gnn_eval_check(params, nR, S, in_off, in_len, in_adj, n_in, out_off, out_len, out_adj, n_out, dinv, feats,
+                         target, active, grad, loss, params_after));
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
     g_build_error = "hipStreamCreate failed";

@@ -88,6 +88,11 @@ struct Net {
 
 hipError_t net_alloc(Net &n, int S, int64_t max_rows);
 void net_free(Net &n);
+// Lay the buffers of a network for up to max_rows rows over caller memory
+// (device address base, `bytes` available) instead of allocating them.
+// Returns the bytes taken, or 0 (and an empty Net) when they do not fit.
+// Such a Net must not be passed to net_free or net_set_mask.
+size_t net_view(Net &n, int S, int64_t max_rows, void *base, size_t bytes);
 // copy host parameters (float32, LAYOUT.total) and reset the optimiser
 hipError_t net_set_params(Net &n, const float *host, hipStream_t st);
 hipError_t net_get_params(const Net &n, float *host, hipStream_t st);

@@ -8,6 +8,9 @@
 // second kernel adds in a fixed order, so results do not depend on timing.
 #include <math.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "gnn.h"
 
 namespace gnn {
@@ -448,6 +451,62 @@ hipError_t net_alloc(Net &n, int S, int64_t max_rows) {
   GNN_TRY(dalloc(&n.loss, 1));
   GNN_TRY(dalloc(&n.active, 64));
   return hipSuccess;
+}
+
+size_t net_view(Net &n, int S, int64_t max_rows, void *base, size_t bytes) {
+  n = Net{};
+  n.S = S;
+  n.max_rows = max_rows;
+  char *p = static_cast<char *>(base);
+  size_t used = 0;
+  bool fit = true;
+  auto take = [&](auto **dst, int64_t count) {
+    using T = std::remove_reference_t<decltype(**dst)>;
+    const size_t b = ((size_t)count * sizeof(T) + 255) / 256 * 256;
+    if (used + b > bytes) {
+      fit = false;
+      *dst = nullptr;
+      return;
+    }
+    *dst = reinterpret_cast<T *>(p + used);
+    used += b;
+  };
+  const int64_t P = LAYOUT.total;
+  take(&n.theta, P);
+  take(&n.grad, P);
+  take(&n.m1, P);
+  take(&n.m2, P);
+  const MatTable t = mat_table();
+  int64_t f = 0, b = 0;
+  for (int i = 0; i < NMAT; ++i) {
+    f += (int64_t)t.N[i] * pad32(t.K[i]);
+    b += (int64_t)t.K[i] * pad32(t.N[i]);
+  }
+  take(&n.wb.fwd, f);
+  take(&n.wb.bwd, b);
+  take(&n.F, max_rows * FEAT);
+  for (int l = 0; l <= LAYERS; ++l) take(&n.h[l], max_rows * HID);
+  for (int l = 0; l < LAYERS; ++l) take(&n.a[l], max_rows * MSG);
+  take(&n.m, max_rows * MSG);
+  take(&n.o, max_rows);
+  take(&n.t, max_rows);
+  take(&n.dh, max_rows * HID);
+  take(&n.dz, max_rows * HID);
+  take(&n.da, max_rows * MSG);
+  take(&n.dm, max_rows * MSG);
+  take(&n.dout, max_rows);
+  // weight-gradient partials: one block of HID x HID per 128 rows (the
+  // same partition as an allocated network uses for these rows)
+  n.part_cap = std::max<int64_t>(1, (max_rows + 127) / 128) * HID * HID;
+  take(&n.part, n.part_cap);
+  take(&n.loss_part, 4096);
+  take(&n.loss, 1);
+  take(&n.active, 64);
+  if (!fit) {
+    n = Net{};
+    return 0;
+  }
+  return used;
 }
 
 void net_free(Net &n) {

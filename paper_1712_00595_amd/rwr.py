@@ -52,6 +52,7 @@ EXPORTED = [
     "rwr_warm_start",
     "rwr_warm_inspect",
     "rwr_model_trainable",
+    "rwr_gnn_eval_noalloc",
 ]
 
 
@@ -155,6 +156,7 @@ def load_library(path: str = LIB_PATH):
     L.rwr_warm_start.argtypes = [p, i32, i32, i64, ctypes.c_float, ctypes.c_float]
     L.rwr_warm_inspect.argtypes = [p, p, p, p, p, p, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.rwr_model_trainable.argtypes = [p, p, i64, i32]
+    L.rwr_gnn_eval_noalloc.argtypes = [p, i32, i32, p, p, p, i64, p, p, p, i64, p, p, p, p, p, p, p, p, p]
     for name in EXPORTED:
         f = getattr(L, name)
         if name not in ("rwr_destroy", "rwr_last_error", "rwr_gnn_num_params"):
@@ -446,12 +448,15 @@ def _csr(n: int, a: np.ndarray, b: np.ndarray):
     return off, cnt, np.ascontiguousarray(b[order])
 
 
-def gnn_eval(params, nR: int, S: int, src, dst, dinv, feats, target=None, active=None, *, adam_step: bool = False):
+def gnn_eval(params, nR: int, S: int, src, dst, dinv, feats, target=None, active=None, *, adam_step: bool = False,
+             noalloc: bool = False, stream: Optional[int] = None):
     """Run the warm-start network on one explicit region (see rwr_gnn_eval).
 
     ``src``/``dst`` are the region's edges u -> v in local ids.  Returns a
     dict with ``out`` (nR, S) and, with a target, ``loss``, ``grad`` and (if
-    ``adam_step``) ``params_after``."""
+    ``adam_step``) ``params_after``.  ``noalloc`` calls
+    rwr_gnn_eval_noalloc instead (no device allocation; on ``stream``, a
+    hipStream_t handle, or the default stream)."""
     L = load_library()
     P = int(L.rwr_gnn_num_params())
     th = np.ascontiguousarray(np.asarray(params, np.float32))
@@ -475,11 +480,15 @@ def gnn_eval(params, nR: int, S: int, src, dst, dinv, feats, target=None, active
     def ptr(x):
         return None if x is None else x.ctypes.data
 
-    code = L.rwr_gnn_eval(
+    args = (
         ptr(th), int(nR), int(S), ptr(in_off), ptr(in_len), ptr(in_adj), int(in_adj.shape[0]), ptr(out_off),
         ptr(out_len), ptr(out_adj), int(out_adj.shape[0]), ptr(dv), ptr(F), ptr(tg), ptr(act), ptr(out),
         ptr(grad), ctypes.byref(loss) if loss is not None else None, ptr(after),
     )
+    if noalloc:
+        code = L.rwr_gnn_eval_noalloc(*args, stream)
+    else:
+        code = L.rwr_gnn_eval(*args)
     _check(L, None, code)
     res["out"] = out.reshape(nR, S)
     if target is not None:
