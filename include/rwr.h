@@ -70,6 +70,23 @@ typedef struct rwr_config {
                         sweep (lanes per row, workgroups) on its first sweeps and keeps
                         the fastest; 0: the fixed defaults                               */
   void *stream;      /* hipStream_t to run on; NULL: the library creates its own        */
+  int32_t deterministic; /* 1: results do not depend on timing -- no floating-point atomics
+                            on the score path: the offset seed is summed in a fixed order
+                            and propagation runs dense pull sweeps only (no sparse push
+                            phase); two runs of the same stream give bitwise equal scores */
+  int32_t node_deletion; /* 0: a deleted node loses every incident edge (row and column);
+                            1: only its row, as Section 3.4.1 states it (its in-edges stay
+                            and it becomes a dead end, Theorem 4); undirected graphs store
+                            one structure, so there both readings remove every pair     */
+  int32_t phase_timing;  /* 1: rwr_stats.ms_delta .. ms_merge from HIP events (a few
+                            event records per update); 0: those fields are 0           */
+  /* device memory of the context: when dev_alloc is set, every device buffer the
+     context keeps comes from dev_alloc(bytes, stream, alloc_user) and goes back
+     through dev_free(p, stream, alloc_user) (e.g. a framework's caching allocator);
+     NULL: hipMalloc / hipFree.  dev_alloc returns NULL on failure (RWR_ENOMEM). */
+  void *(*dev_alloc)(size_t bytes, void *stream, void *user);
+  void (*dev_free)(void *p, void *stream, void *user);
+  void *alloc_user;
 } rwr_config;
 
 /* A batch is a set (Theorem 1: only the graphs before and after matter).
@@ -121,6 +138,13 @@ typedef struct rwr_stats {
      dense sweep (the FP64 residual of a check that needed no refinement, or
      the last iterate a run left unpropagated), 0 when none joined          */
   double carry_l1;
+  int32_t fallback;       /* warm start: columns with an offset seed that kept it (the
+                             prediction's residual was not smaller)                        */
+  int32_t flushed;        /* columns whose error bound passed the budget and were refined  */
+  /* GPU time per phase (config phase_timing = 1, else 0): batch upload, check and
+     structural apply; offset seed (Section 3.1); learned warm start; propagation
+     (Algorithm 1's loop); stream error check, refinement and clean-up           */
+  double ms_delta, ms_seed, ms_model, ms_prop, ms_merge;
 } rwr_stats;
 
 /* Fill *cfg with defaults: c = 0.15, eps = 1e-9, FP32 propagation, directed,
@@ -176,8 +200,18 @@ rwr_status rwr_update(rwr_ctx *ctx, const rwr_batch *batch, rwr_stats *stats);
 /* Evaluate the FP64 residual of the current scores and, in the columns whose
  * certified error exceeds an eighth of the budget, propagate it until the
  * certified error is below an eighth of the budget (clears a stale
- * context). */
+ * context).  Its iteration guard is the larger of max_iters and Theorem 2's
+ * bound for the residual's norm, so a context left stale by RWR_ENOCONV can
+ * recover. */
 rwr_status rwr_refine(rwr_ctx *ctx, rwr_stats *stats);
+
+/* Replace the scores of seed column j by in[0..n) (normalised scores in
+ * caller ids, n = the node count; host memory, or device memory when
+ * in_on_device = 1), e.g. scores computed elsewhere.  Their error is unknown:
+ * the column's error bound becomes infinite, so the next rwr_update, or
+ * rwr_refine, evaluates the FP64 residual and refines.  Carried vectors are
+ * dropped. */
+rwr_status rwr_scores_set(rwr_ctx *ctx, int32_t j, const double *in, int64_t n, int32_t in_on_device);
 
 /* Copy the normalised scores of seed column j (n doubles) to out (capacity
  * cap elements; host memory, or device memory when out_on_device = 1). */

@@ -226,14 +226,17 @@ def delta_weight(old, new, r_old) -> float:
 KEY = np.int64(1) << np.int64(32)
 
 
-def apply_batch(n, src, dst, batch, *, undirected=False, del_nodes=()):
+def apply_batch(n, src, dst, batch, *, undirected=False, del_nodes=(), rows_only=False):
     """Edge list of G + Delta G.
 
     ``batch`` has ``ins_src, ins_dst, del_src, del_dst, n_new_nodes``.  Raises
     :class:`OracleError` (with code 'EINVAL', 'EEXIST' or 'ENOENT') for an
     invalid batch.  New nodes get ids n..n+k-1 (Section 3.4.1).  A deleted
     node (an existing id, listed once, not named by the batch's edge
-    entries) loses every incident edge: its row and column become zero.
+    entries) loses every incident edge: its row and column become zero
+    (reading G9); with ``rows_only`` it loses its out-edges only, the zero
+    row Section 3.4.1 states, and keeps its in-edges (a directed graph's
+    reading; undirected graphs lose every pair either way).
     Undirected graphs store both directions of each pair; batch pairs are
     given once.
     """
@@ -275,7 +278,7 @@ def apply_batch(n, src, dst, batch, *, undirected=False, del_nodes=()):
         if np.isin(np.concatenate([ins_s, ins_d, del_s, del_d]), dn).any():
             raise OracleError("EINVAL")
         a, b = newk // KEY, newk % KEY
-        inc = np.isin(a, dn) | np.isin(b, dn)
+        inc = np.isin(a, dn) if (rows_only and not undirected) else (np.isin(a, dn) | np.isin(b, dn))
         newk = newk[~inc]
     a = (newk // KEY).astype(np.int32)
     b = (newk % KEY).astype(np.int32)

@@ -78,7 +78,10 @@ struct rwr_ctx {
   Ctl *ctl = nullptr;
   Ctl *ctl_h = nullptr;  // pinned mirror
   double *hist = nullptr;
-  int32_t max_iters = 10000;
+  int32_t max_iters = 10000;   // iteration guard of an update run
+  int32_t solve_iters = 10000; // of a build or refinement run (at least Theorem 2's bound)
+  bool rows_only = false;      // node deletion removes the row only
+  hipEvent_t ph_ev[7] = {};    // phase-timing events (created on first use)
   double *part = nullptr;
   int64_t *part_i = nullptr;
   int64_t part_blocks = 0;
@@ -200,7 +203,7 @@ struct rwr_ctx {
     std::vector<float> mask_h;       // trainable-parameter mask (empty: all train)
     int32_t warmup = 0;              // step-size warm-up of the optimiser
     std::vector<double> qn_h;
-    int32_t accepted = 0;
+    int32_t accepted = 0, fallback = 0;
     double ratio = 0.0, loss = 0.0, ms = 0.0;
   } ws;
 };
@@ -756,7 +759,8 @@ static rwr_status pair_graph(rwr_ctx *c, const SlotArgs &a) {
 // at every synchronisation (a switch mid-chunk turns the chunk's remaining
 // sparse slots into no-ops, and the next chunk starts at the device's count).
 static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, double eps_hint = 0.0,
-                           bool keep_tail = false, uint64_t inject = 0) {
+                           bool keep_tail = false, uint64_t inject = 0, int guard = -1) {
+  const int max_it = guard > 0 ? guard : c->max_iters;
   const SlotArgs a = slot_args(c);
   int k = 1;
   // first chunk: predicted from the starting norm when it is known (a
@@ -779,11 +783,11 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
   while (true) {
     const int dense_before = c->ctl_h->dense_iters;
     tn.pending.clear();
-    if (k > c->max_iters + 1) {
+    if (k > max_it + 1) {
       c->err = "iteration slots exhausted without completion";
       return RWR_EHIP;
     }
-    const int kend = std::min(k + chunk, c->max_iters + 2);
+    const int kend = std::min(k + chunk, max_it + 2);
     for (; k < kend; ++k) {
       if (mode == MODE_DENSE || k >= sparse_end) {
         if (inject) {
@@ -973,6 +977,11 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
   for (int j = 0; j < c->n_seeds; ++j) {
     const double sig = std::fabs(c->ctl_h->sigma[j]);
     const double g = c->ctl_h->red_norm[j];
+    if (!std::isfinite(g) || !std::isfinite(sig)) {
+      c->stale = true;
+      c->err = "non-finite residual or score sum";
+      return RWR_ENUMERIC;
+    }
     resid = std::max(resid, g);
     const double cert = 2.0 * g / (cc * sig);
     c->err_bound[j] = cert;
@@ -1006,10 +1015,10 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
   // bound over it and the refinements follow one another); its columns then
   // retire together so that every one of them leaves its last iterate
   const bool keep = carry && c->carry_level >= 2;
-  launch_reset_run(c->ctl, c->S, mask, eps_ref, c->max_iters, dense_thresh(c), c->n / 16 + 1, c->stream,
+  launch_reset_run(c->ctl, c->S, mask, eps_ref, c->solve_iters, dense_thresh(c), c->n / 16 + 1, c->stream,
                    c->max_iters + 2, keep && c->lockstep ? 1 : 0);
   launch_refine_init(a, c->S, c->fp64, c->stream);
-  RWR_TRY(run_slots(c, MODE_DENSE, resid * (1.0 - cc), eps_ref, keep));
+  RWR_TRY(run_slots(c, MODE_DENSE, resid * (1.0 - cc), eps_ref, keep, 0, c->solve_iters));
   if (c->ctl_h->prop_err != 0) {
     c->stale = true;
     c->err = "refinement did not converge";
@@ -1027,7 +1036,10 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
       c->pend_l1[j] = c->ctl_h->last_norm[j];
     }
   }
-  if (st) st->refined = 1;
+  if (st) {
+    st->refined = 1;
+    st->flushed = __builtin_popcountll(mask);
+  }
   return RWR_OK;
 }
 
@@ -1172,6 +1184,7 @@ static rwr_status warm_prepare(rwr_ctx *c) {
   const double t0 = now_ms();
   w.nR = 0;
   w.accepted = 0;
+  w.fallback = 0;
   w.ratio = 1.0;
   w.loss = 0.0;
   w.trained = false;
@@ -1241,6 +1254,8 @@ static rwr_status warm_prepare(rwr_ctx *c) {
     if ((w.mode & 1) && rho < q) {
       accept |= 1ull << j;
       ++w.accepted;
+    } else if (w.mode & 1) {
+      ++w.fallback;
     }
   }
   w.ratio = den > 0.0 ? num / den : 1.0;
@@ -1421,6 +1436,10 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   c->undirected = c->cfg.undirected != 0;
   c->fp64 = c->cfg.precision == RWR_PROP_FP64;
   c->max_iters = c->cfg.max_iters > 0 ? c->cfg.max_iters : 10000;
+  // builds and refinements start from a norm of at most about 1 and stop
+  // above 1e-16: Theorem 2 bounds their iterations by log_{1-c}(1e-16)
+  c->solve_iters = std::max<int32_t>(c->max_iters, (int32_t)std::ceil(std::log(1e-16) / std::log(1.0 - c->cfg.c)) + 64);
+  c->rows_only = c->cfg.node_deletion == 1 && !c->cfg.undirected;
   c->n = n;
   c->n_cap = (int32_t)std::min<int64_t>((int64_t)n + std::max<int64_t>(1024, n / 16), INT32_MAX - 1);
   c->n_seeds = n_seeds;
@@ -1560,7 +1579,9 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   RWR_TRY(alloc_zero(c, &c->sel, (size_t)c->n_cap * 2));
   RWR_TRY(alloc_zero(c, &c->sel_count, 1));
   // norms of the update runs, then of the refinement runs (kept apart)
-  RWR_TRY(alloc_zero(c, &c->hist, (size_t)2 * (c->max_iters + 2) * c->S));
+  // norms of the update runs (max_iters + 2 rows), then of the build and
+  // refinement runs (solve_iters + 2 rows)
+  RWR_TRY(alloc_zero(c, &c->hist, (size_t)(c->max_iters + 2 + c->solve_iters + 2) * c->S));
   RWR_TRY(plan_heavy(c, true));
   RWR_TRY(ensure_partials(c));
 
@@ -1580,14 +1601,14 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   const double cc = c->cfg.c;
   const double eps0 = std::min(c->cfg.eps, build_tol * cc / (4.0 * (1.0 - cc)));
   const SlotArgs a = slot_args(c);
-  launch_reset_run(c->ctl, c->S, all_cols_mask(n_seeds), eps0, c->max_iters, dense_thresh(c), c->n / 16 + 1,
+  launch_reset_run(c->ctl, c->S, all_cols_mask(n_seeds), eps0, c->solve_iters, dense_thresh(c), c->n / 16 + 1,
                    c->stream);
   if (c->qmode)
     launch_seed_init_q(a, c->S, c->stream);
   else
     launch_seed_init(a, c->S, c->stream);
   launch_slot0_epilogue(a, c->S, c->fp64, c->stream);
-  RWR_TRY(run_slots(c, MODE_SPARSE));
+  RWR_TRY(run_slots(c, MODE_SPARSE, -1.0, 0.0, false, 0, c->solve_iters));
   RWR_TRY(read_ctl(c));
   if (c->ctl_h->prop_err != 0) {
     c->err = "initial solve did not converge";
@@ -1742,6 +1763,20 @@ static OrientPair orient_pair(const rwr_ctx *c, bool check) {
   return P;
 }
 
+// phase-timing event i on the context's stream (config phase_timing)
+static rwr_status phase_mark(rwr_ctx *c, int i) {
+  if (!c->cfg.phase_timing) return RWR_OK;
+  if (!c->ph_ev[i]) HIP_TRY(c, timing_event(&c->ph_ev[i]));
+  HIP_TRY(c, hipEventRecord(c->ph_ev[i], c->stream));
+  return RWR_OK;
+}
+
+static double phase_ms(rwr_ctx *c, int a, int b) {
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, c->ph_ev[a], c->ph_ev[b]) != hipSuccess) return 0.0;
+  return ms;
+}
+
 rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   if (!c || !b) return RWR_EINVAL;
   const double t0 = now_ms();
@@ -1750,6 +1785,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     c->err = "context is stale (an earlier update did not converge); call rwr_refine";
     return RWR_ESTATE;
   }
+  RWR_TRY(phase_mark(c, 0));
   if (b->n_ins < 0 || b->n_del < 0 || b->n_new_nodes < 0 || b->n_del_nodes < 0 ||
       (b->n_ins > 0 && (!b->ins_src || !b->ins_dst)) || (b->n_del > 0 && (!b->del_src || !b->del_dst))) {
     c->err = "invalid batch";
@@ -1824,8 +1860,8 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
       RWR_TRY(alloc_zero(c, &c->ndel, 2 * (int64_t)nd + 2));
       c->ndel_cap = 2 * (int64_t)nd + 2;
     }
-    launch_node_mark(dn_dev, nd, c->perm, c->g[0].v, c->g[1].v, c->undirected ? 1 : 0, c->nmark, c->ndel,
-                     c->stream);
+    launch_node_mark(dn_dev, nd, c->perm, c->g[0].v, c->g[1].v, c->undirected ? 1 : 0, c->rows_only ? 1 : 0,
+                     c->nmark, c->ndel, c->stream);
     std::vector<int64_t> cnt(nd), off(nd);
     D2H(c, cnt.data(), c->ndel, sizeof(int64_t) * nd);
     for (int32_t i = 0; i < nd; ++i) {
@@ -1850,8 +1886,8 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     launch_make_keys(ins_s, ins_d, b->n_ins, del_s, del_d, b->n_del, n_new, b1, c->undirected ? 1 : 0, c->perm,
                      nd > 0 ? c->nmark : nullptr, c->keys[0], c->keys[1], c->ctl, c->stream);
     if (nd > 0)
-      launch_node_keys(dn_dev, nd, c->ndel, N, c->perm, c->g[0].v, c->g[1].v, c->undirected ? 1 : 0, c->nmark, b1,
-                       c->keys[0], c->keys[1], c->ctl, c->stream);
+      launch_node_keys(dn_dev, nd, c->ndel, N, c->perm, c->g[0].v, c->g[1].v, c->undirected ? 1 : 0,
+                       c->rows_only ? 1 : 0, c->nmark, b1, c->keys[0], c->keys[1], c->ctl, c->stream);
     if (nkeys <= SMALL_SORT_MAX) {
       launch_sort_segment_small(c->keys[0], c->keys[1], (int32_t)nkeys, b1, c->seg[0], c->row[0], c->seg[1],
                                 c->row[1], norient, c->ctl, c->stream);
@@ -1892,6 +1928,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     RWR_TRY(read_ctl(c));
   }
   // the batch is valid: commit the node count and apply
+  RWR_TRY(phase_mark(c, 1));
   c->n = n_new;
   const SlotArgs a = slot_args(c);
   const bool warm = c->ws.alloc && c->ws.mode != 0 && nkeys > 0;
@@ -1912,19 +1949,22 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     c->tail_slot = -1;
     c->tail_cols = 0;
   }
-  if (nkeys > 0) {
+  if (nkeys > 0)
     HIP_TRY(c, launch_offset_seed(c->S, c->keys[0], c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->g[0].v,
                                   c->r, c->pend ? c->gbuf : nullptr, c->ybuf, c->stamp, c->ctl, b1,
                                   1.0 - c->cfg.c, (int32_t)nkeys, c->flags, c->pos, c->temp, c->temp_bytes,
                                   4 * c->n_cu, c->stream));
-    launch_apply(orient_pair(c, false), norient, b1, c->ctl, (int32_t)nkeys, c->stream);
-  }
+  RWR_TRY(phase_mark(c, 2));
+  if (nkeys > 0) launch_apply(orient_pair(c, false), norient, b1, c->ctl, (int32_t)nkeys, c->stream);
+  RWR_TRY(phase_mark(c, 3));
   // stored edge count (an undirected self-loop is stored once; the count only
   // steers the sparse/dense switch and the visited-edge statistic)
   c->m += (b->n_ins - b->n_del) * (c->undirected ? 2 : 1) - c->ctl_h->node_dels;
   if (warm) RWR_TRY(warm_prepare(c));
+  RWR_TRY(phase_mark(c, 4));
   launch_slot0_epilogue(a, c->S, c->fp64, c->stream);
   RWR_TRY(run_slots(c, MODE_SPARSE, -1.0, 0.0, keep, c->pend));
+  RWR_TRY(phase_mark(c, 5));
   // columns whose pending vector joined the run (it reached the dense phase)
   uint64_t inj = 0;
   double cl = 0.0;
@@ -1942,6 +1982,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     st->ws_region = c->ws.nR;
     st->ws_accepted = c->ws.accepted;
     st->ws_resid_ratio = c->ws.ratio;
+    st->fallback = c->ws.fallback;
     st->ws_loss = c->ws.loss;
     st->ms_warm = c->ws.ms;
   }
@@ -1954,12 +1995,20 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     RWR_TRY(check_and_refine(c, false, st));
   }
   if (c->ctl_h->heavy_stale > 0) RWR_TRY(plan_heavy(c));
+  RWR_TRY(phase_mark(c, 6));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (st) {
     double worst = 0.0;
     for (int j = 0; j < c->n_seeds; ++j) worst = std::max(worst, c->err_bound[j]);
     st->err_bound = worst;
     st->ms_total = now_ms() - t0;
+    if (c->cfg.phase_timing) {
+      st->ms_delta = phase_ms(c, 0, 1) + phase_ms(c, 2, 3);
+      st->ms_seed = phase_ms(c, 1, 2);
+      st->ms_model = phase_ms(c, 3, 4);
+      st->ms_prop = phase_ms(c, 4, 5);
+      st->ms_merge = phase_ms(c, 5, 6);
+    }
   }
   // A last iterate left in x is unscaled into gbuf now, with the degrees the
   // next batch starts from, so that this pass runs while the host prepares
@@ -2002,6 +2051,27 @@ rwr_status rwr_scores(rwr_ctx *c, int32_t j, double *out, int64_t cap, int32_t o
   launch_scores(c->r, c->ctl, c->perm, c->S, j, c->n, dst, c->stream);
   if (!out_on_device) HIP_TRY(c, hipMemcpyAsync(out, c->xres, sizeof(double) * c->n, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return RWR_OK;
+}
+
+rwr_status rwr_scores_set(rwr_ctx *c, int32_t j, const double *in, int64_t n, int32_t in_on_device) {
+  if (!c || !in || j < 0 || j >= c->n_seeds) return RWR_EINVAL;
+  if (n != c->n) {
+    c->err = "score count differs from the node count";
+    return RWR_EINVAL;
+  }
+  // the carried vectors belong to the scores being replaced
+  drop_carry(c);
+  const double *src = in;
+  if (!in_on_device) {
+    // staged in the residual sweep's scratch (free between calls)
+    HIP_TRY(c, hipMemcpyAsync(c->xres, in, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    src = c->xres;
+  }
+  launch_set_scores(src, c->perm, c->S, j, c->n, c->r, c->stream);
+  launch_sigma_exact(slot_args(c), c->S, c->stream);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->err_bound[j] = HUGE_VAL;
   return RWR_OK;
 }
 
@@ -2118,6 +2188,8 @@ void rwr_destroy(rwr_ctx *c) {
   if (c->ctl_h) (void)hipHostFree(c->ctl_h);
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->tune.ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ph_ev)
+    if (e) (void)hipEventDestroy(e);
   pair_graph_drop(c);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;

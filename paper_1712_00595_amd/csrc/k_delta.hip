@@ -80,30 +80,31 @@ __global__ void k_make_keys(const int32_t *__restrict__ ins_s, const int32_t *__
 // (internal id) and reports how many adjacency entries its keys are drawn
 // from; the host turns the counts into key offsets.
 __global__ void k_node_mark(const int32_t *__restrict__ del_nodes, int32_t n_del, const int32_t *__restrict__ perm,
-                            DevGraphView out, DevGraphView in, int undirected, int32_t *__restrict__ mark,
-                            int64_t *__restrict__ cnt) {
+                            DevGraphView out, DevGraphView in, int undirected, int rows_only,
+                            int32_t *__restrict__ mark, int64_t *__restrict__ cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_del) return;
   const int32_t u = perm[del_nodes[i]];
   mark[u] = 1;
-  cnt[i] = (int64_t)out.len[u] + (undirected ? 0 : in.len[u]);
+  cnt[i] = (int64_t)out.len[u] + (undirected || rows_only ? 0 : in.len[u]);
 }
 
 // One block per deleted node u; its keys start at entry `first + off[i]`
 // (pairs of entries in undirected mode).  Directed: every out-edge (u, v),
-// and every in-edge (w, u) unless w is u (the self-loop came with the row) or
-// w is itself deleted (that edge came with w's row).  Undirected: every pair
+// and (unless rows_only: the row alone, Section 3.4.1 read literally) every
+// in-edge (w, u) unless w is u (the self-loop came with the row) or w is
+// itself deleted (that edge came with w's row).  Undirected: every pair
 // {u, v} once, skipped at u when v is deleted and v < u.  Skipped entries
 // are padding.  ctl->node_dels counts the stored entries removed.
 __global__ void k_node_keys(const int32_t *__restrict__ del_nodes, const int64_t *__restrict__ off, int64_t first,
                             const int32_t *__restrict__ perm, DevGraphView out, DevGraphView in, int undirected,
-                            const int32_t *__restrict__ mark, int b1, uint64_t *__restrict__ k_out,
+                            int rows_only, const int32_t *__restrict__ mark, int b1, uint64_t *__restrict__ k_out,
                             uint64_t *__restrict__ k_in, Ctl *ctl) {
   __shared__ int64_t wsum[256 / RWR_WAVE];
   const int32_t u = perm[del_nodes[blockIdx.x]];
   const int64_t base = first + off[blockIdx.x];
   const int32_t lo = out.len[u];
-  const int32_t li = undirected ? 0 : in.len[u];
+  const int32_t li = undirected || rows_only ? 0 : in.len[u];
   const int32_t *ro = out.adj + out.off[u];
   const int32_t *ri = in.adj + in.off[u];
   int64_t removed = 0;
@@ -579,18 +580,20 @@ void launch_make_keys(const int32_t *ins_s, const int32_t *ins_d, int64_t n_ins,
 }
 
 void launch_node_mark(const int32_t *del_nodes, int32_t n_del, const int32_t *perm, const DevGraphView &out,
-                      const DevGraphView &in, int undirected, int32_t *mark, int64_t *cnt, hipStream_t st) {
+                      const DevGraphView &in, int undirected, int rows_only, int32_t *mark, int64_t *cnt,
+                      hipStream_t st) {
   if (n_del <= 0) return;
   hipLaunchKernelGGL(k_node_mark, dim3((n_del + 255) / 256), dim3(256), 0, st, del_nodes, n_del, perm, out, in,
-                     undirected, mark, cnt);
+                     undirected, rows_only, mark, cnt);
 }
 
 void launch_node_keys(const int32_t *del_nodes, int32_t n_del, const int64_t *off, int64_t first,
                       const int32_t *perm, const DevGraphView &out, const DevGraphView &in, int undirected,
-                      const int32_t *mark, int b1, uint64_t *k_out, uint64_t *k_in, Ctl *ctl, hipStream_t st) {
+                      int rows_only, const int32_t *mark, int b1, uint64_t *k_out, uint64_t *k_in, Ctl *ctl,
+                      hipStream_t st) {
   if (n_del <= 0) return;
   hipLaunchKernelGGL(k_node_keys, dim3(n_del), dim3(256), 0, st, del_nodes, off, first, perm, out, in, undirected,
-                     mark, b1, k_out, k_in, ctl);
+                     rows_only, mark, b1, k_out, k_in, ctl);
 }
 
 void launch_node_unmark(const int32_t *del_nodes, int32_t n_del, const int32_t *perm, int32_t *mark,

@@ -1557,6 +1557,17 @@ static void sigma_impl(const SlotArgs &a, hipStream_t st) {
 
 void launch_sigma_exact(const SlotArgs &a, int S, hipStream_t st) { RWR_DISPATCH_S(S, (sigma_impl<SS>(a, st))); }
 
+__global__ void k_set_scores(const double *__restrict__ in, const int32_t *__restrict__ perm, int S, int j, int32_t n,
+                             double *__restrict__ r) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    r[(int64_t)perm[v] * S + j] = in[v];
+}
+
+void launch_set_scores(const double *in, const int32_t *perm, int S, int j, int32_t n, double *r, hipStream_t st) {
+  const int grid = std::max(1, std::min((n + 255) / 256, 2048));
+  hipLaunchKernelGGL(k_set_scores, dim3(grid), dim3(256), 0, st, in, perm, S, j, n, r);
+}
+
 void launch_scores(const double *r, const Ctl *ctl, const int32_t *perm, int S, int j, int32_t n, double *out,
                    hipStream_t st) {
   const int grid = std::max(1, std::min((n + 255) / 256, 2048));

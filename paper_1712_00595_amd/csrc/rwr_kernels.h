@@ -80,12 +80,17 @@ void launch_make_keys(const int32_t *ins_s, const int32_t *ins_d, int64_t n_ins,
                       const int32_t *perm, const int32_t *mark, uint64_t *k_out, uint64_t *k_in, Ctl *ctl,
                       hipStream_t st);
 // node deletions: mark the nodes and count their adjacency entries; write
-// their incident edges as deletion keys from entry `first` on; clear marks
+// their incident edges (rows_only: their out-edges only) as deletion keys
+// from entry `first` on; clear marks
 void launch_node_mark(const int32_t *del_nodes, int32_t n_del, const int32_t *perm, const DevGraphView &out,
-                      const DevGraphView &in, int undirected, int32_t *mark, int64_t *cnt, hipStream_t st);
+                      const DevGraphView &in, int undirected, int rows_only, int32_t *mark, int64_t *cnt,
+                      hipStream_t st);
 void launch_node_keys(const int32_t *del_nodes, int32_t n_del, const int64_t *off, int64_t first,
                       const int32_t *perm, const DevGraphView &out, const DevGraphView &in, int undirected,
-                      const int32_t *mark, int b1, uint64_t *k_out, uint64_t *k_in, Ctl *ctl, hipStream_t st);
+                      int rows_only, const int32_t *mark, int b1, uint64_t *k_out, uint64_t *k_in, Ctl *ctl,
+                      hipStream_t st);
+// scores of column j from caller values (caller ids): r[perm[v]*S + j] = in[v]
+void launch_set_scores(const double *in, const int32_t *perm, int S, int j, int32_t n, double *r, hipStream_t st);
 void launch_node_unmark(const int32_t *del_nodes, int32_t n_del, const int32_t *perm, int32_t *mark,
                         hipStream_t st);
 void launch_sort_segment_small(uint64_t *k0, uint64_t *k1, int32_t n_keys, int b1, int32_t *seg0, int32_t *row0,

@@ -53,6 +53,7 @@ EXPORTED = [
     "rwr_warm_inspect",
     "rwr_model_trainable",
     "rwr_gnn_eval_noalloc",
+    "rwr_scores_set",
 ]
 
 
@@ -76,6 +77,12 @@ class Config(ctypes.Structure):
         ("reorder", ctypes.c_int32),
         ("autotune", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
+        ("deterministic", ctypes.c_int32),
+        ("node_deletion", ctypes.c_int32),
+        ("phase_timing", ctypes.c_int32),
+        ("dev_alloc", ctypes.c_void_p),
+        ("dev_free", ctypes.c_void_p),
+        ("alloc_user", ctypes.c_void_p),
     ]
 
 
@@ -114,6 +121,13 @@ class StatsStruct(ctypes.Structure):
         ("ms_warm", ctypes.c_double),
         ("dr_l1", ctypes.c_double),
         ("carry_l1", ctypes.c_double),
+        ("fallback", ctypes.c_int32),
+        ("flushed", ctypes.c_int32),
+        ("ms_delta", ctypes.c_double),
+        ("ms_seed", ctypes.c_double),
+        ("ms_model", ctypes.c_double),
+        ("ms_prop", ctypes.c_double),
+        ("ms_merge", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -156,6 +170,7 @@ def load_library(path: str = LIB_PATH):
     L.rwr_warm_start.argtypes = [p, i32, i32, i64, ctypes.c_float, ctypes.c_float]
     L.rwr_warm_inspect.argtypes = [p, p, p, p, p, p, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.rwr_model_trainable.argtypes = [p, p, i64, i32]
+    L.rwr_scores_set.argtypes = [p, i32, p, i64, i32]
     L.rwr_gnn_eval_noalloc.argtypes = [p, i32, i32, p, p, p, i64, p, p, p, i64, p, p, p, p, p, p, p, p, p]
     for name in EXPORTED:
         f = getattr(L, name)
@@ -229,6 +244,9 @@ class Context:
         reorder: bool = True,
         autotune: bool = True,
         stream: Optional[int] = None,
+        deterministic: bool = False,
+        node_deletion: str = "incident",
+        phase_timing: bool = False,
     ):
         self._lib = load_library()
         self._ctx = ctypes.c_void_p(None)
@@ -245,6 +263,9 @@ class Context:
         cfg.reorder = 1 if reorder else 0
         cfg.autotune = 1 if autotune else 0
         cfg.stream = stream
+        cfg.deterministic = 1 if deterministic else 0
+        cfg.node_deletion = {"incident": 0, "row": 1}[node_deletion]
+        cfg.phase_timing = 1 if phase_timing else 0
         on_dev = _is_torch(src)
         s = _Arr(src, on_dev)
         d = _Arr(dst, on_dev)
@@ -400,6 +421,11 @@ class Context:
         out = np.zeros(self.n, dtype=np.float64)
         _check(self._lib, self._ctx, self._lib.rwr_scores(self._ctx, int(j), out.ctypes.data, out.shape[0], 0))
         return out
+
+    def scores_set(self, j: int, values) -> None:
+        """Replace column j's scores (normalised, caller ids); see rwr_scores_set."""
+        v = np.ascontiguousarray(np.asarray(values, np.float64))
+        _check(self._lib, self._ctx, self._lib.rwr_scores_set(self._ctx, int(j), v.ctypes.data, v.shape[0], 0))
 
     def scores_device(self, j: int, out) -> None:
         """Write column j into a float64 CUDA tensor of at least n elements."""

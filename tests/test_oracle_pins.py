@@ -374,6 +374,35 @@ def test_node_deletion_equals_deleting_its_edges_and_osp_stays_exact():
     assert np.abs(ref[gone]).max() < 1e-15
 
 
+def test_literal_node_deletion_zeroes_the_row_only():
+    # Section 3.4.1 read literally: the deleted node's row becomes zero and
+    # its in-edges stay, so it turns into a dead end and Theorem 4's
+    # rescaling applies; the same as deleting its out-edges, and OSP from
+    # the old scores still reaches the static scores (Theorem 1)
+    rng = np.random.default_rng(12)
+    n = 50
+    pairs = {(int(u), int(v)) for u, v in rng.integers(0, n, size=(300, 2))}
+    pairs |= {(u, u) for u in range(n) if not any(a == u for a, _ in pairs)}
+    src = np.array([p[0] for p in sorted(pairs)], np.int32)
+    dst = np.array([p[1] for p in sorted(pairs)], np.int32)
+    E = np.zeros(0, np.int32)
+    gone = [4, 9]
+    n2, s2, d2 = oracle.apply_batch(n, src, dst, Batch(E, E, E, E), del_nodes=gone, rows_only=True)
+    out_e = np.isin(src, gone)
+    n3, s3, d3 = oracle.apply_batch(n, src, dst, Batch(E, E, src[out_e], dst[out_e]))
+    assert set(zip(s2.tolist(), d2.tolist())) == set(zip(s3.tolist(), d3.tolist()))
+    assert not np.isin(s2, gone).any() and np.isin(d2, gone).any()  # in-edges stay
+    # every node lost its whole row in the default reading instead
+    n4, s4, d4 = oracle.apply_batch(n, src, dst, Batch(E, E, E, E), del_nodes=gone)
+    assert s4.shape[0] < s2.shape[0]
+    seed = 0
+    r_old = oracle.rwr_static(n, src, dst, seed, 0.15)
+    out = oracle.osp((n, src, dst), (n2, s2, d2), r_old, 0.15, 1e-15, renorm=oracle.core.RENORM_ALWAYS)
+    ref = oracle.rwr_static(n2, s2, d2, seed, 0.15)
+    assert np.abs(out["r_new"] - ref).sum() < 1e-12
+    assert abs(ref.sum() - 1.0) < 1e-12  # Theorem 4: the dead ends rescale to unit mass
+
+
 def test_apply_stream_equals_batch_by_batch():
     # the one-pass stream apply gives the same edge set as applying each
     # batch in turn, and rejects a batch that is invalid at its position
