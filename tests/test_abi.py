@@ -30,11 +30,31 @@ def test_every_declared_symbol_is_exported():
         assert hasattr(L, name), name
 
 
-def test_struct_layouts_match_header():
-    # field order and sizes mirror rwr.h; 8-byte aligned structs
-    assert ctypes.sizeof(rwr.Config) == 8 * 4 + 4 * 6 + 8
-    assert ctypes.sizeof(rwr.BatchStruct) == 8 + 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
-    assert ctypes.sizeof(rwr.StatsStruct) == 4 * 4 + 8 * 2 + 8 * 5 + 4 * 2 + 8 * 3 + 8 + 8
+def test_struct_layouts_match_header(tmp_path):
+    # every field's offset and every struct's size, as a C compiler lays out
+    # rwr.h, equals the binding's ctypes mirror
+    import subprocess
+
+    structs = {"rwr_config": rwr.Config, "rwr_batch": rwr.BatchStruct, "rwr_stats": rwr.StatsStruct}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rwr.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-std=c11", f"-I{inc}", str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 def test_config_default_and_host_side_rejection():
