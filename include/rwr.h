@@ -45,7 +45,8 @@ typedef enum rwr_status {
   RWR_ENOENT = -5,   /* batch deletes an edge that is not present               */
   RWR_ENOCONV = -6,  /* max_iters reached before ||x^(i)||_1 <= eps             */
   RWR_ENUMERIC = -7, /* non-finite norm met during propagation                  */
-  RWR_ESTATE = -8    /* context unusable (an earlier call left it stale)        */
+  RWR_ESTATE = -8,   /* context unusable (an earlier call left it stale)        */
+  RWR_EIO = -9       /* checkpoint file cannot be written, read or recognised   */
 } rwr_status;
 
 /* Precision of the propagated vectors x^(i).  Scores r and their sums are
@@ -71,9 +72,13 @@ typedef struct rwr_config {
                         the fastest; 0: the fixed defaults                               */
   void *stream;      /* hipStream_t to run on; NULL: the library creates its own        */
   int32_t deterministic; /* 1: results do not depend on timing -- no floating-point atomics
-                            on the score path: the offset seed is summed in a fixed order
-                            and propagation runs dense pull sweeps only (no sparse push
-                            phase); two runs of the same stream give bitwise equal scores */
+                            on the score path: the offset seed is summed per node in a
+                            fixed order after the structural apply, propagation runs dense
+                            pull sweeps only (no sparse push phase), the sweep shape is not
+                            tuned by timing (autotune ignored), and the warm-start
+                            network's aggregations sum each row in edge order; two runs of
+                            the same stream on the same device give bitwise equal scores,
+                            statistics and trained parameters                          */
   int32_t node_deletion; /* 0: a deleted node loses every incident edge (row and column);
                             1: only its row, as Section 3.4.1 states it (its in-edges stay
                             and it becomes a dead end, Theorem 4); undirected graphs store
@@ -81,9 +86,13 @@ typedef struct rwr_config {
   int32_t phase_timing;  /* 1: rwr_stats.ms_delta .. ms_merge from HIP events (a few
                             event records per update); 0: those fields are 0           */
   /* device memory of the context: when dev_alloc is set, every device buffer the
-     context keeps comes from dev_alloc(bytes, stream, alloc_user) and goes back
-     through dev_free(p, stream, alloc_user) (e.g. a framework's caching allocator);
-     NULL: hipMalloc / hipFree.  dev_alloc returns NULL on failure (RWR_ENOMEM). */
+     context keeps or stages comes from dev_alloc(bytes, stream, alloc_user) and goes
+     back through dev_free(p, stream, alloc_user) (e.g. a framework's caching
+     allocator); `stream` is the context's stream, on which all its device work runs,
+     so a freed block may be reused by work queued after the free on that stream.
+     Both NULL: hipMalloc / hipFree; one without the other is RWR_EINVAL.  dev_alloc
+     returns NULL on failure (RWR_ENOMEM) and 256-byte aligned memory otherwise.
+     (Pinned host memory of the control block still comes from hipHostMalloc.)     */
   void *(*dev_alloc)(size_t bytes, void *stream, void *user);
   void (*dev_free)(void *p, void *stream, void *user);
   void *alloc_user;
@@ -257,6 +266,28 @@ rwr_status rwr_profile_read(rwr_ctx *ctx, double *dense_ms, int64_t *dense_sweep
 
 /* Free every resource of the context; NULL is allowed. */
 void rwr_destroy(rwr_ctx *ctx);
+
+/* Checkpoint of a context (not part of the paper's method; for restarts of a
+ * long update stream).  rwr_save writes everything the next update reads --
+ * graph in its internal layout (node numbering, each row's entries in
+ * storage order), scores, carried vectors and their bounds, the control block
+ * (sigma per column, Theorem 4), run statistics, the sweep shape and the
+ * heavy-row / row-order plans, and the warm-start network with its optimiser
+ * state -- to `path` (written to path + ".part", then renamed).  rwr_load makes
+ * a new context from such a file; `runtime` supplies only the fields that
+ * cannot be saved (stream, dev_alloc, dev_free, alloc_user, phase_timing;
+ * NULL: defaults), the rest of the configuration comes from the file.  A loaded
+ * context continues the stream as the saved one would: with
+ * deterministic = 1 on the same device, bitwise.  The format is the library's
+ * own (native byte order, tied to this version: RWR_EIO otherwise).  Call
+ * rwr_save between updates; the context is unchanged by it. */
+rwr_status rwr_save(rwr_ctx *ctx, const char *path);
+rwr_status rwr_load(const char *path, const rwr_config *runtime, rwr_ctx **out);
+
+/* The configuration a context runs with (cfg, may be NULL), its column count
+ * (n_seeds) and seed ids (seeds: room for RWR_MAX_COLS, -1 for columns built
+ * from vectors; may be NULL). */
+rwr_status rwr_context_info(const rwr_ctx *ctx, rwr_config *cfg, int32_t *n_seeds, int32_t *seeds);
 
 /* Text of the last error recorded on ctx (or of the last failed rwr_build when
  * ctx is NULL).  The string lives until the next call on the same context. */

@@ -81,6 +81,8 @@ struct rwr_ctx {
   int32_t max_iters = 10000;   // iteration guard of an update run
   int32_t solve_iters = 10000; // of a build or refinement run (at least Theorem 2's bound)
   bool rows_only = false;      // node deletion removes the row only
+  bool det = false;            // no floating-point atomics on the score path
+  int32_t *tmark = nullptr;    // 2 n_cap: changed-row marks of the fixed-order offset seed (det)
   hipEvent_t ph_ev[7] = {};    // phase-timing events (created on first use)
   double *part = nullptr;
   int64_t *part_i = nullptr;
@@ -175,7 +177,9 @@ struct rwr_ctx {
   struct Warm {
     int32_t mode = 0, hops = 3;
     int64_t max_rows = 0, max_nodes = 0;
-    gnn::Net net;
+    gnn::Net net;          // laid over net_mem (gnn::net_view)
+    void *net_mem = nullptr;
+    float *mask_d = nullptr;  // trainable-parameter mask on the device (null: all train)
     bool alloc = false, params = false;
     int32_t *hop1 = nullptr, *loc1 = nullptr, *wlist = nullptr, *flags = nullptr;
     int32_t *R = nullptr, *cnt = nullptr;  // cnt[0]: selected nodes, cnt[1]: touched nodes
@@ -224,9 +228,20 @@ struct rwr_ctx {
     if (_s != RWR_OK) return _s;       \
   } while (0)
 
+// Device memory of a context: the caller's allocator when the configuration
+// names one (frees are ordered on the context's stream, which every kernel of
+// the context runs on), else hipMalloc / hipFree.
 static rwr_status dev_alloc(rwr_ctx *c, void **p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 256;
+  if (c->cfg.dev_alloc) {
+    *p = c->cfg.dev_alloc(bytes, (void *)c->stream, c->cfg.alloc_user);
+    if (!*p) {
+      c->err = "dev_alloc(" + std::to_string(bytes) + " bytes) returned NULL";
+      return RWR_ENOMEM;
+    }
+    return RWR_OK;
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     c->err = "hipMalloc(" + std::to_string(bytes) + " bytes) failed: " + hipGetErrorString(e);
@@ -253,15 +268,20 @@ static rwr_status alloc_zero(rwr_ctx *c, T **p, size_t count) {
 }
 
 template <typename T>
-static void dev_free(T *&p) {
-  if (p) (void)hipFree((void *)p);
+static void dev_free(rwr_ctx *c, T *&p) {
+  if (p) {
+    if (c->cfg.dev_free)
+      c->cfg.dev_free((void *)p, (void *)c->stream, c->cfg.alloc_user);
+    else
+      (void)hipFree((void *)p);
+  }
   p = nullptr;
 }
 
 static rwr_status ensure_temp(rwr_ctx *c, size_t bytes) {
   if (bytes <= c->temp_bytes) return RWR_OK;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  dev_free(c->temp);
+  dev_free(c, c->temp);
   c->temp_bytes = 0;
   RWR_TRY(dev_alloc(c, &c->temp, bytes));
   c->temp_bytes = bytes;
@@ -364,8 +384,8 @@ static rwr_status ensure_partials(rwr_ctx *c) {
   const int64_t blocks = std::max<int64_t>({c->grid_light, c->grid_sparse, c->grid_pull}) + 320;
   if (blocks <= c->part_blocks) return RWR_OK;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  dev_free(c->part);
-  dev_free(c->part_i);
+  dev_free(c, c->part);
+  dev_free(c, c->part_i);
   const int64_t stride = std::max(16, 2 * c->S);  // padded partial-sum entries
   RWR_TRY(alloc_zero(c, &c->part, (size_t)blocks * stride));
   RWR_TRY(alloc_zero(c, &c->part_i, (size_t)blocks * 16));
@@ -443,7 +463,7 @@ static rwr_status plan_partition(rwr_ctx *c) {
     ++cnt;
   }
   rows.push_back(c->n_cap);
-  dev_free(c->mp_rows);
+  dev_free(c, c->mp_rows);
   RWR_TRY(dev_alloc(c, (void **)&c->mp_rows, sizeof(int32_t) * rows.size()));
   H2D(c, c->mp_rows, rows.data(), sizeof(int32_t) * rows.size());
   c->n_mp = (int32_t)rows.size() - 1;
@@ -470,7 +490,7 @@ static rwr_status plan_order(rwr_ctx *c) {
   }
   std::vector<int32_t> order(c->n_cap);
   for (int32_t v = 0; v < c->n_cap; ++v) order[start[top - std::min(len[v], top)]++] = v;
-  dev_free(c->row_order);
+  dev_free(c, c->row_order);
   RWR_TRY(alloc_zero(c, &c->row_order, c->n_cap));
   H2D(c, c->row_order, order.data(), sizeof(int32_t) * c->n_cap);
   return RWR_OK;
@@ -504,12 +524,12 @@ static rwr_status plan_heavy(rwr_ctx *c, bool with_order = false) {
       item_chunk.push_back(k);
     }
   }
-  dev_free(c->h_item_row);
-  dev_free(c->h_item_chunk);
-  dev_free(c->h_rows);
-  dev_free(c->h_nchunks);
-  dev_free(c->h_first);
-  dev_free(c->h_part);
+  dev_free(c, c->h_item_row);
+  dev_free(c, c->h_item_chunk);
+  dev_free(c, c->h_rows);
+  dev_free(c, c->h_nchunks);
+  dev_free(c, c->h_first);
+  dev_free(c, c->h_part);
   const int32_t items = (int32_t)item_row.size();
   RWR_TRY(alloc_zero(c, &c->h_item_row, std::max(1, items)));
   RWR_TRY(alloc_zero(c, &c->h_item_chunk, std::max(1, items)));
@@ -553,7 +573,7 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
         return RWR_EHIP;
       }
       (void)hipStreamSynchronize(c->stream);
-      (void)hipFree(*p);
+      dev_free(c, *p);
     }
     *p = np;
     return RWR_OK;
@@ -577,6 +597,7 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
   RWR_TRY(regrow((void **)&c->stamp, 4, 1));
   RWR_TRY(regrow((void **)&c->fstamp, 4, 1));
   RWR_TRY(regrow((void **)&c->nmark, 4, 1));
+  if (c->det) RWR_TRY(regrow((void **)&c->tmark, 4, 2));
   RWR_TRY(regrow((void **)&c->hfront, 4, 1));
   RWR_TRY(regrow((void **)&c->hbase, 4, 1));
   RWR_TRY(regrow((void **)&c->sel, 4, 2));
@@ -591,14 +612,13 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
     RWR_TRY(regrow((void **)&c->ws.wbuf, 8, c->S));
     const size_t tb = ws_select_temp_bytes(new_cap);
     if (tb > c->ws.temp_bytes) {
-      dev_free(c->ws.temp);
+      dev_free(c, c->ws.temp);
       c->ws.temp = nullptr;
       RWR_TRY(dev_alloc(c, &c->ws.temp, tb));
       c->ws.temp_bytes = tb;
     }
   }
   c->n_cap = new_cap;
-  tune_defaults(c);
   RWR_TRY(plan_heavy(c, true));
   RWR_TRY(ensure_partials(c));
   return RWR_OK;
@@ -625,9 +645,9 @@ static rwr_status relayout(rwr_ctx *c, int o, int64_t arena_min) {
   RWR_TRY(dev_alloc(c, (void **)&new_adj, sizeof(int32_t) * e_cap));
   launch_copy_rows(g.v, new_off, new_adj, c->n, c->stream);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  (void)hipFree(g.v.adj);
-  (void)hipFree(g.v.off);
-  (void)hipFree(g.v.cap);
+  dev_free(c, g.v.adj);
+  dev_free(c, g.v.off);
+  dev_free(c, g.v.cap);
   g.v.adj = new_adj;
   g.v.off = new_off;
   g.v.cap = new_capv;
@@ -657,9 +677,9 @@ static rwr_status build_orient(rwr_ctx *c, int o, const int32_t *rows, const int
                           c->stream));
   RWR_TRY(read_ctl(c));
   if (c->ctl_h->err != 0) {
-    (void)hipFree(keys);
-    (void)hipFree(keys_alt);
-    (void)hipFree(sstart);
+    dev_free(c, keys);
+    dev_free(c, keys_alt);
+    dev_free(c, sstart);
     c->err = "edge list has an id out of range or a repeated edge";
     return RWR_EINVAL;
   }
@@ -672,9 +692,9 @@ static rwr_status build_orient(rwr_ctx *c, int o, const int32_t *rows, const int
   RWR_TRY(alloc_zero(c, &g.v.adj, g.e_cap));
   build_phase2(keys, m, g.v, sstart, c->stream);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  (void)hipFree(keys);
-  (void)hipFree(keys_alt);
-  (void)hipFree(sstart);
+  dev_free(c, keys);
+  dev_free(c, keys_alt);
+  dev_free(c, sstart);
   uint64_t tail = (uint64_t)used;
   H2D(c, &c->ctl->tail[o], &tail, sizeof(tail));
   return RWR_OK;
@@ -883,7 +903,13 @@ static rwr_status run_slots(rwr_ctx *c, int mode, double init_norm = -1.0, doubl
 
 static uint64_t all_cols_mask(int n_seeds) { return n_seeds >= 64 ? ~0ull : ((1ull << n_seeds) - 1ull); }
 
-static int64_t dense_thresh(const rwr_ctx *c) { return std::max<int64_t>(1, c->m / std::max(1, c->pull_ratio)); }
+// frontier edges above which a run leaves the sparse push for dense pull
+// sweeps; -1 (deterministic): dense from the first iteration, since the push
+// scatters with floating-point atomics
+static int64_t dense_thresh(const rwr_ctx *c) {
+  if (c->det) return -1;
+  return std::max<int64_t>(1, c->m / std::max(1, c->pull_ratio));
+}
 
 static double fp32_factor(const rwr_ctx *c) { return c->fp64 ? 0.0 : 8.0 * std::ldexp(1.0, -24); }
 
@@ -1046,49 +1072,71 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
 // ---------------------------------------------------------- warm start
 static void warm_free(rwr_ctx *c) {
   rwr_ctx::Warm &w = c->ws;
-  dev_free(w.hop1);
-  dev_free(w.loc1);
-  dev_free(w.wlist);
-  dev_free(w.flags);
-  dev_free(w.R);
-  dev_free(w.cnt);
-  dev_free(w.lin_cnt);
-  dev_free(w.lin_off);
-  dev_free(w.lout_cnt);
-  dev_free(w.lout_off);
-  dev_free(w.lin_adj);
-  dev_free(w.lout_adj);
-  dev_free(w.items);
-  dev_free(w.item_off);
-  dev_free(w.lin_items);
-  dev_free(w.lout_items);
-  dev_free(w.gpart);
+  dev_free(c, w.hop1);
+  dev_free(c, w.loc1);
+  dev_free(c, w.wlist);
+  dev_free(c, w.flags);
+  dev_free(c, w.R);
+  dev_free(c, w.cnt);
+  dev_free(c, w.lin_cnt);
+  dev_free(c, w.lin_off);
+  dev_free(c, w.lout_cnt);
+  dev_free(c, w.lout_off);
+  dev_free(c, w.lin_adj);
+  dev_free(c, w.lout_adj);
+  dev_free(c, w.items);
+  dev_free(c, w.item_off);
+  dev_free(c, w.lin_items);
+  dev_free(c, w.lout_items);
+  dev_free(c, w.gpart);
   w.gpart_cap = 0;
-  dev_free(w.kpart);
-  dev_free(w.fa);
+  dev_free(c, w.kpart);
+  dev_free(c, w.fa);
   w.ladj_cap = 0;
-  if (w.scan_temp) (void)hipFree(w.scan_temp);
+  dev_free(c, w.scan_temp);
   w.scan_temp = nullptr;
   w.scan_bytes = 0;
-  dev_free(w.dinv);
-  dev_free(w.xhat);
-  dev_free(w.wbuf);
-  dev_free(w.qn);
-  dev_free(w.part);
-  dev_free(w.sums);
-  if (w.temp) (void)hipFree(w.temp);
+  dev_free(c, w.dinv);
+  dev_free(c, w.xhat);
+  dev_free(c, w.wbuf);
+  dev_free(c, w.qn);
+  dev_free(c, w.part);
+  dev_free(c, w.sums);
+  dev_free(c, w.temp);
   w.temp = nullptr;
   w.temp_bytes = 0;
-  gnn::net_free(w.net);
+  dev_free(c, w.net_mem);
+  dev_free(c, w.mask_d);
+  w.net = gnn::Net{};
   w.alloc = false;
   w.params = false;
+}
+
+// trainable-parameter mask of the warm-start network (host floats, null: all train)
+static rwr_status warm_set_mask(rwr_ctx *c, const float *host) {
+  rwr_ctx::Warm &w = c->ws;
+  if (!host) {
+    dev_free(c, w.mask_d);
+    w.net.mask = nullptr;
+    return RWR_OK;
+  }
+  if (!w.mask_d) RWR_TRY(dev_alloc(c, (void **)&w.mask_d, sizeof(float) * gnn::LAYOUT.total));
+  H2D(c, w.mask_d, host, sizeof(float) * gnn::LAYOUT.total);
+  w.net.mask = w.mask_d;
+  return RWR_OK;
 }
 
 static rwr_status warm_alloc(rwr_ctx *c, int64_t max_rows) {
   rwr_ctx::Warm &w = c->ws;
   w.max_rows = std::max<int64_t>(max_rows, c->S);
   w.max_nodes = w.max_rows / c->S;
-  HIP_TRY(c, gnn::net_alloc(w.net, c->S, w.max_rows));
+  const size_t nb = gnn::net_view(w.net, c->S, w.max_rows, nullptr, 0, gnn::NET_PART_CAP);
+  RWR_TRY(dev_alloc(c, &w.net_mem, nb));
+  if (gnn::net_view(w.net, c->S, w.max_rows, w.net_mem, nb, gnn::NET_PART_CAP) != nb) {
+    c->err = "network buffers do not fit";
+    return RWR_ENOMEM;
+  }
+  w.net.det = c->det ? 1 : 0;
   RWR_TRY(alloc_zero(c, &w.hop1, c->n_cap));
   RWR_TRY(alloc_zero(c, &w.loc1, c->n_cap));
   RWR_TRY(alloc_zero(c, &w.wlist, c->n_cap));
@@ -1153,8 +1201,8 @@ static rwr_status warm_local_graph(rwr_ctx *c) {
   D2H(c, &tout, w.lout_off + w.nR, sizeof(int32_t));
   const int64_t need = std::max<int64_t>(std::max(tin, tout), 1);
   if (need > w.ladj_cap) {
-    dev_free(w.lin_adj);
-    dev_free(w.lout_adj);
+    dev_free(c, w.lin_adj);
+    dev_free(c, w.lout_adj);
     const int64_t cap = std::max<int64_t>(need, 2 * w.ladj_cap);
     RWR_TRY(dev_alloc(c, (void **)&w.lin_adj, sizeof(int32_t) * cap));
     RWR_TRY(dev_alloc(c, (void **)&w.lout_adj, sizeof(int32_t) * cap));
@@ -1267,7 +1315,7 @@ static rwr_status warm_prepare(rwr_ctx *c) {
     const int64_t need = ((int64_t)nR + c->m / 1024 + 2) * S;
     if (need > w.gpart_cap) {
       HIP_TRY(c, hipStreamSynchronize(c->stream));
-      dev_free(w.gpart);
+      dev_free(c, w.gpart);
       w.gpart_cap = 0;
       RWR_TRY(dev_alloc(c, (void **)&w.gpart, sizeof(double) * need));
       w.gpart_cap = need;
@@ -1301,7 +1349,7 @@ static void fill_stats(rwr_ctx *c, rwr_stats *st) {
   st->last_x_l1 = lx;
   st->carry_l1 = c->last_carry_l1;
   double dr = 0.0;
-  for (int j = 0; j < c->n_seeds; ++j) dr = std::max(dr, h.dr_l1[j]);
+  for (int j = 0; j < c->n_seeds; ++j) dr = std::max(dr, c->det ? std::ldexp((double)h.dr_fix[j], -52) : h.dr_l1[j]);
   st->dr_l1 = dr;
 }
 
@@ -1440,6 +1488,7 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   // above 1e-16: Theorem 2 bounds their iterations by log_{1-c}(1e-16)
   c->solve_iters = std::max<int32_t>(c->max_iters, (int32_t)std::ceil(std::log(1e-16) / std::log(1.0 - c->cfg.c)) + 64);
   c->rows_only = c->cfg.node_deletion == 1 && !c->cfg.undirected;
+  c->det = c->cfg.deterministic != 0;
   c->n = n;
   c->n_cap = (int32_t)std::min<int64_t>((int64_t)n + std::max<int64_t>(1024, n / 16), INT32_MAX - 1);
   c->n_seeds = n_seeds;
@@ -1519,9 +1568,9 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
     HIP_TRY(c, build_relabel(src_d, m2, n, c->n_cap, c->perm, c->inv, deg, k1, k2, c->temp, c->temp_bytes,
                              c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    (void)hipFree(k1);
-    (void)hipFree(k2);
-    (void)hipFree(deg);
+    dev_free(c, k1);
+    dev_free(c, k2);
+    dev_free(c, deg);
   } else {
     launch_identity(c->perm, c->inv, 0, c->n_cap, c->stream);
   }
@@ -1529,13 +1578,13 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   launch_map_ids(dst_d, m2, n, c->perm, mdst, c->stream);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (own_edges) {
-    (void)hipFree(src_d);
-    (void)hipFree(dst_d);
+    dev_free(c, src_d);
+    dev_free(c, dst_d);
   }
   rwr_status s = build_orient(c, 0, msrc, mdst, m2);
   if (s == RWR_OK && !c->undirected) s = build_orient(c, 1, mdst, msrc, m2);
-  (void)hipFree(msrc);
-  (void)hipFree(mdst);
+  dev_free(c, msrc);
+  dev_free(c, mdst);
   if (s == RWR_OK && c->qmode) {
     // seed vectors in internal ids (no seed nodes)
     launch_fill_i32(c->seeds_d, RWR_MAX_COLS, -1, c->stream);
@@ -1554,7 +1603,7 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
     launch_fill_i32(c->seeds_d, RWR_MAX_COLS, -1, c->stream);  // padding columns name no node
     launch_map_ids(tmp, n_seeds, n, c->perm, c->seeds_d, c->stream);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    (void)hipFree(tmp);
+    dev_free(c, tmp);
   }
   if (s != RWR_OK) return s;
   if (c->undirected) c->g[1] = c->g[0];
@@ -1574,11 +1623,11 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   RWR_TRY(alloc_zero(c, &c->stamp, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->fstamp, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->nmark, c->n_cap));
+  if (c->det) RWR_TRY(alloc_zero(c, &c->tmark, (size_t)c->n_cap * 2));
   RWR_TRY(alloc_zero(c, &c->hfront, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->hbase, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->sel, (size_t)c->n_cap * 2));
   RWR_TRY(alloc_zero(c, &c->sel_count, 1));
-  // norms of the update runs, then of the refinement runs (kept apart)
   // norms of the update runs (max_iters + 2 rows), then of the build and
   // refinement runs (solve_iters + 2 rows)
   RWR_TRY(alloc_zero(c, &c->hist, (size_t)(c->max_iters + 2 + c->solve_iters + 2) * c->S));
@@ -1588,7 +1637,8 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   // static scores: CPI from c*e_s (Section 2.2), then residual refinement.
   // Its first dense sweeps also choose the sweep shape (unless fixed by the
   // caller's configuration or the environment).
-  if (c->cfg.autotune && !getenv("RWR_PULL_LANES") && !getenv("RWR_GRID_PULL")) {
+  // (not in deterministic mode: the shape sets each row's summation order)
+  if (c->cfg.autotune && !c->det && !getenv("RWR_PULL_LANES") && !getenv("RWR_GRID_PULL")) {
     tune_begin(c);
     int32_t gmax = 0;
     for (const auto &cd : c->tune.cand) gmax = std::max(gmax, cd.second);
@@ -1652,6 +1702,10 @@ rwr_status rwr_build(const rwr_config *cfg, int32_t n, int64_t m, const int32_t 
         return RWR_EINVAL;
       }
   }
+  if ((cf.dev_alloc == nullptr) != (cf.dev_free == nullptr)) {
+    g_build_error = "dev_alloc and dev_free must be given together";
+    return RWR_EINVAL;
+  }
   rwr_ctx *c = new rwr_ctx();
   c->cfg = cf;
   rwr_status s = build_impl(c, n, m, src, dst, n_seeds, seeds, edges_on_device);
@@ -1692,6 +1746,10 @@ rwr_status rwr_build_vectors(const rwr_config *cfg, int32_t n, int64_t m, const 
       return RWR_EINVAL;
     }
   }
+  if ((cf.dev_alloc == nullptr) != (cf.dev_free == nullptr)) {
+    g_build_error = "dev_alloc and dev_free must be given together";
+    return RWR_EINVAL;
+  }
   rwr_ctx *c = new rwr_ctx();
   c->cfg = cf;
   rwr_status s = build_impl(c, n, m, src, dst, n_cols, nullptr, edges_on_device, q);
@@ -1710,20 +1768,20 @@ static rwr_status ensure_batch(rwr_ctx *c, int64_t nkeys, int64_t nints) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const int64_t cap = std::max<int64_t>(nkeys, 2 * c->bcap);
     for (int o = 0; o < 2; ++o) {
-      dev_free(c->keys[o]);
-      dev_free(c->seg[o]);
-      dev_free(c->row[o]);
-      dev_free(c->t_dold[o]);
-      dev_free(c->t_dnew[o]);
+      dev_free(c, c->keys[o]);
+      dev_free(c, c->seg[o]);
+      dev_free(c, c->row[o]);
+      dev_free(c, c->t_dold[o]);
+      dev_free(c, c->t_dnew[o]);
       RWR_TRY(alloc_zero(c, &c->keys[o], cap));
       RWR_TRY(alloc_zero(c, &c->seg[o], cap + 1));
       RWR_TRY(alloc_zero(c, &c->row[o], cap + 1));
       RWR_TRY(alloc_zero(c, &c->t_dold[o], cap + 1));
       RWR_TRY(alloc_zero(c, &c->t_dnew[o], cap + 1));
     }
-    dev_free(c->keys_alt);
-    dev_free(c->flags);
-    dev_free(c->pos);
+    dev_free(c, c->keys_alt);
+    dev_free(c, c->flags);
+    dev_free(c, c->pos);
     RWR_TRY(alloc_zero(c, &c->keys_alt, cap));
     RWR_TRY(alloc_zero(c, &c->flags, cap + 1));
     RWR_TRY(alloc_zero(c, &c->pos, cap + 1));
@@ -1733,7 +1791,7 @@ static rwr_status ensure_batch(rwr_ctx *c, int64_t nkeys, int64_t nints) {
   if (nints > c->b_host_cap) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (c->b_host) (void)hipHostFree(c->b_host);
-    dev_free(c->b_dev);
+    dev_free(c, c->b_dev);
     const int64_t cap = std::max<int64_t>(nints, 2 * c->b_host_cap);
     HIP_TRY(c, hipHostMalloc((void **)&c->b_host, sizeof(int32_t) * cap, hipHostMallocDefault));
     RWR_TRY(dev_alloc(c, (void **)&c->b_dev, sizeof(int32_t) * cap));
@@ -1856,7 +1914,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   if (nd > 0) {
     if (nd + 1 > c->ndel_cap) {
       HIP_TRY(c, hipStreamSynchronize(c->stream));
-      dev_free(c->ndel);
+      dev_free(c, c->ndel);
       RWR_TRY(alloc_zero(c, &c->ndel, 2 * (int64_t)nd + 2));
       c->ndel_cap = 2 * (int64_t)nd + 2;
     }
@@ -1949,13 +2007,21 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     c->tail_slot = -1;
     c->tail_cols = 0;
   }
+  // the offset seed of r - p; deterministic: only its support here, its
+  // values summed in a fixed order once the batch is applied
+  const double *rsub = c->pend ? c->gbuf : nullptr;
   if (nkeys > 0)
     HIP_TRY(c, launch_offset_seed(c->S, c->keys[0], c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->g[0].v,
-                                  c->r, c->pend ? c->gbuf : nullptr, c->ybuf, c->stamp, c->ctl, b1,
-                                  1.0 - c->cfg.c, (int32_t)nkeys, c->flags, c->pos, c->temp, c->temp_bytes,
-                                  4 * c->n_cu, c->stream));
+                                  c->r, rsub, c->det ? nullptr : c->ybuf, c->stamp, c->ctl, b1, 1.0 - c->cfg.c,
+                                  (int32_t)nkeys, c->flags, c->pos, c->temp, c->temp_bytes, 4 * c->n_cu, c->stream));
   RWR_TRY(phase_mark(c, 2));
   if (nkeys > 0) launch_apply(orient_pair(c, false), norient, b1, c->ctl, (int32_t)nkeys, c->stream);
+  if (nkeys > 0 && c->det) {
+    const int po = pull_orient(c);
+    HIP_TRY(c, launch_offset_pull(c->S, orient_pair(c, false), po, c->g[po].v, c->stamp, c->ctl, c->n, c->tmark,
+                                  c->tmark + c->n_cap, b1, c->r, rsub, c->ybuf, 1.0 - c->cfg.c, (int32_t)nkeys,
+                                  8 * c->n_cu, c->stream));
+  }
   RWR_TRY(phase_mark(c, 3));
   // stored edge count (an undirected self-loop is stored once; the count only
   // steers the sparse/dense switch and the visited-edge statistic)
@@ -2107,9 +2173,9 @@ rwr_status rwr_graph_export(rwr_ctx *c, int32_t *src, int32_t *dst, int64_t cap,
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   D2H(c, src, ds, sizeof(int32_t) * m);
   D2H(c, dst, dd, sizeof(int32_t) * m);
-  (void)hipFree(ds);
-  (void)hipFree(dd);
-  (void)hipFree(pos);
+  dev_free(c, ds);
+  dev_free(c, dd);
+  dev_free(c, pos);
   return RWR_OK;
 }
 
@@ -2136,54 +2202,55 @@ void rwr_destroy(rwr_ctx *c) {
   warm_free(c);
   const int no = c->undirected ? 1 : 2;
   for (int o = 0; o < no; ++o) {
-    dev_free(c->g[o].v.off);
-    dev_free(c->g[o].v.len);
-    dev_free(c->g[o].v.cap);
-    dev_free(c->g[o].v.adj);
-    dev_free(c->g[o].v.heavy);
+    dev_free(c, c->g[o].v.off);
+    dev_free(c, c->g[o].v.len);
+    dev_free(c, c->g[o].v.cap);
+    dev_free(c, c->g[o].v.adj);
+    dev_free(c, c->g[o].v.heavy);
   }
-  dev_free(c->r);
-  dev_free(c->ybuf);
-  dev_free(c->gbuf);
-  dev_free(c->xres);
-  dev_free(c->qvec);
-  dev_free(c->x[0]);
-  dev_free(c->x[1]);
-  dev_free(c->stamp);
-  dev_free(c->fstamp);
-  dev_free(c->nmark);
-  dev_free(c->ndel);
-  dev_free(c->row_order);
-  dev_free(c->hfront);
-  dev_free(c->hbase);
-  dev_free(c->ctl);
-  dev_free(c->hist);
-  dev_free(c->part);
-  dev_free(c->part_i);
-  dev_free(c->h_item_row);
-  dev_free(c->h_item_chunk);
-  dev_free(c->h_rows);
-  dev_free(c->h_nchunks);
-  dev_free(c->h_first);
-  dev_free(c->h_part);
-  dev_free(c->sel);
-  dev_free(c->sel_count);
-  dev_free(c->mp_rows);
-  dev_free(c->seeds_d);
-  dev_free(c->perm);
-  dev_free(c->inv);
-  dev_free(c->b_dev);
+  dev_free(c, c->r);
+  dev_free(c, c->ybuf);
+  dev_free(c, c->gbuf);
+  dev_free(c, c->xres);
+  dev_free(c, c->qvec);
+  dev_free(c, c->x[0]);
+  dev_free(c, c->x[1]);
+  dev_free(c, c->stamp);
+  dev_free(c, c->fstamp);
+  dev_free(c, c->nmark);
+  dev_free(c, c->tmark);
+  dev_free(c, c->ndel);
+  dev_free(c, c->row_order);
+  dev_free(c, c->hfront);
+  dev_free(c, c->hbase);
+  dev_free(c, c->ctl);
+  dev_free(c, c->hist);
+  dev_free(c, c->part);
+  dev_free(c, c->part_i);
+  dev_free(c, c->h_item_row);
+  dev_free(c, c->h_item_chunk);
+  dev_free(c, c->h_rows);
+  dev_free(c, c->h_nchunks);
+  dev_free(c, c->h_first);
+  dev_free(c, c->h_part);
+  dev_free(c, c->sel);
+  dev_free(c, c->sel_count);
+  dev_free(c, c->mp_rows);
+  dev_free(c, c->seeds_d);
+  dev_free(c, c->perm);
+  dev_free(c, c->inv);
+  dev_free(c, c->b_dev);
   for (int o = 0; o < 2; ++o) {
-    dev_free(c->keys[o]);
-    dev_free(c->seg[o]);
-    dev_free(c->row[o]);
-    dev_free(c->t_dold[o]);
-    dev_free(c->t_dnew[o]);
+    dev_free(c, c->keys[o]);
+    dev_free(c, c->seg[o]);
+    dev_free(c, c->row[o]);
+    dev_free(c, c->t_dold[o]);
+    dev_free(c, c->t_dnew[o]);
   }
-  dev_free(c->keys_alt);
-  dev_free(c->flags);
-  dev_free(c->pos);
-  dev_free(c->temp);
+  dev_free(c, c->keys_alt);
+  dev_free(c, c->flags);
+  dev_free(c, c->pos);
+  dev_free(c, c->temp);
   if (c->b_host) (void)hipHostFree(c->b_host);
   if (c->ctl_h) (void)hipHostFree(c->ctl_h);
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
@@ -2216,6 +2283,476 @@ rwr_status rwr_profile_read(rwr_ctx *c, double *dense_ms, int64_t *dense_sweeps,
 }
 
 const char *rwr_last_error(const rwr_ctx *c) { return c ? c->err.c_str() : g_build_error.c_str(); }
+
+rwr_status rwr_context_info(const rwr_ctx *c, rwr_config *cfg, int32_t *n_seeds, int32_t *seeds) {
+  if (!c) return RWR_EINVAL;
+  if (cfg) *cfg = c->cfg;
+  if (n_seeds) *n_seeds = c->n_seeds;
+  if (seeds) {
+    for (int32_t j = 0; j < c->n_seeds; ++j) seeds[j] = c->qmode ? -1 : c->seeds_h[j];
+  }
+  return RWR_OK;
+}
+
+// ------------------------------------------------------------------ checkpoint
+// A checkpoint holds what the next update reads, in the context's internal
+// layout: node numbering, each row's entries in storage order, the heavy-row,
+// row-order and partition plans and the sweep shape, so that a loaded context
+// repeats the saved one's arithmetic exactly.  Native byte order: CkptHead,
+// then the sections in the order rwr_save writes them.
+namespace {
+constexpr char CKPT_MAGIC[8] = {'R', 'W', 'R', 'C', 'K', 'P', 'T', '1'};
+constexpr uint32_t CKPT_VERSION = 1;
+struct CkptHead {
+  char magic[8];
+  uint32_t version, head_bytes, cfg_bytes, ctl_bytes;
+  rwr_config cfg;  // runtime fields (stream, allocator hooks, user pointer) cleared
+  int32_t n, n_cap, n_seeds, S, max_iters, solve_iters;
+  int64_t m;
+  int64_t m_o[2];  // stored entries per orientation
+  int32_t undirected, fp64, rows_only, det, qmode, stale, lockstep, carry_level;
+  int32_t tail_slot, update_runs, last_iters, pad0;
+  uint64_t pend, tail_cols;
+  double budget, refine_target, decay_ema, sparse_ema, dense_ema, last_carry_l1, tail_ema;
+  double err_bound[RWR_MAX_COLS], pend_b[RWR_MAX_COLS], pend_l1[RWR_MAX_COLS];
+  int32_t grid_sparse, grid_light, grid_pull, light_lanes, pull_lanes, pull_ratio;
+  int32_t heavy_limit, heavy_chunk, fold_max, h_items, h_nrows, n_mp, has_order, pad1;
+  // learned warm start
+  int32_t ws_alloc, ws_params, ws_mode, ws_hops, ws_warmup, ws_has_mask;
+  int64_t ws_max_rows, ws_step;
+  float ws_lr, ws_wd;
+};
+
+struct File {
+  FILE *f = nullptr;
+  ~File() {
+    if (f) std::fclose(f);
+  }
+};
+}  // namespace
+
+#define CK_IO(c, ok, what)               \
+  do {                                   \
+    if (!(ok)) {                         \
+      (c)->err = std::string(what);      \
+      return RWR_EIO;                    \
+    }                                    \
+  } while (0)
+
+// device range -> file (staged through host memory)
+static rwr_status ck_put_dev(rwr_ctx *c, FILE *f, const void *dev, size_t bytes) {
+  if (bytes == 0) return RWR_OK;
+  std::vector<char> h(bytes);
+  D2H(c, h.data(), dev, bytes);
+  CK_IO(c, std::fwrite(h.data(), 1, bytes, f) == bytes, "checkpoint write failed");
+  return RWR_OK;
+}
+
+static rwr_status ck_get_dev(rwr_ctx *c, FILE *f, void *dev, size_t bytes) {
+  if (bytes == 0) return RWR_OK;
+  std::vector<char> h(bytes);
+  CK_IO(c, std::fread(h.data(), 1, bytes, f) == bytes, "checkpoint truncated");
+  H2D(c, dev, h.data(), bytes);
+  return RWR_OK;
+}
+
+rwr_status rwr_save(rwr_ctx *c, const char *path) {
+  if (!c || !path) return RWR_EINVAL;
+  if (!c->built) {
+    c->err = "context not built";
+    return RWR_ESTATE;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  RWR_TRY(read_ctl(c));
+  const int no = c->undirected ? 1 : 2;
+  const size_t nS = (size_t)c->n * c->S;
+  const size_t xs = c->fp64 ? 8 : 4;
+  // rows of each orientation, compacted in storage order
+  std::vector<std::vector<int32_t>> lens(no), adjs(no);
+  for (int o = 0; o < no; ++o) {
+    lens[o].resize(c->n);
+    D2H(c, lens[o].data(), c->g[o].v.len, sizeof(int32_t) * c->n);
+    std::vector<int32_t> coff(std::max(1, c->n));
+    int64_t acc = 0;
+    for (int32_t v = 0; v < c->n; ++v) {
+      coff[v] = (int32_t)acc;
+      acc += lens[o][v];
+    }
+    adjs[o].resize(acc);
+    if (acc > 0) {
+      int32_t *doff = nullptr, *dadj = nullptr;
+      RWR_TRY(dev_alloc(c, (void **)&doff, sizeof(int32_t) * coff.size()));
+      rwr_status s = dev_alloc(c, (void **)&dadj, sizeof(int32_t) * acc);
+      if (s == RWR_OK) s = copy_sync(c, doff, coff.data(), sizeof(int32_t) * coff.size(), hipMemcpyHostToDevice);
+      if (s == RWR_OK) {
+        launch_copy_rows(c->g[o].v, doff, dadj, c->n, c->stream);
+        s = copy_sync(c, adjs[o].data(), dadj, sizeof(int32_t) * acc, hipMemcpyDeviceToHost);
+      }
+      dev_free(c, doff);
+      dev_free(c, dadj);
+      RWR_TRY(s);
+    }
+  }
+  CkptHead h{};
+  std::memcpy(h.magic, CKPT_MAGIC, 8);
+  h.version = CKPT_VERSION;
+  h.head_bytes = sizeof(CkptHead);
+  h.cfg_bytes = sizeof(rwr_config);
+  h.ctl_bytes = sizeof(Ctl);
+  h.cfg = c->cfg;
+  h.cfg.stream = nullptr;
+  h.cfg.dev_alloc = nullptr;
+  h.cfg.dev_free = nullptr;
+  h.cfg.alloc_user = nullptr;
+  h.n = c->n;
+  h.n_cap = c->n_cap;
+  h.n_seeds = c->n_seeds;
+  h.S = c->S;
+  h.max_iters = c->max_iters;
+  h.solve_iters = c->solve_iters;
+  h.m = c->m;
+  for (int o = 0; o < no; ++o) h.m_o[o] = (int64_t)adjs[o].size();
+  h.undirected = c->undirected;
+  h.fp64 = c->fp64;
+  h.rows_only = c->rows_only;
+  h.det = c->det;
+  h.qmode = c->qmode;
+  h.stale = c->stale;
+  h.lockstep = c->lockstep;
+  h.carry_level = c->carry_level;
+  h.tail_slot = c->tail_slot;
+  h.update_runs = c->update_runs;
+  h.last_iters = c->last_iters;
+  h.pend = c->pend;
+  h.tail_cols = c->tail_cols;
+  h.budget = c->budget;
+  h.refine_target = c->refine_target;
+  h.decay_ema = c->decay_ema;
+  h.sparse_ema = c->sparse_ema;
+  h.dense_ema = c->dense_ema;
+  h.last_carry_l1 = c->last_carry_l1;
+  h.tail_ema = c->tail_ema;
+  std::memcpy(h.err_bound, c->err_bound, sizeof(h.err_bound));
+  std::memcpy(h.pend_b, c->pend_b, sizeof(h.pend_b));
+  std::memcpy(h.pend_l1, c->pend_l1, sizeof(h.pend_l1));
+  h.grid_sparse = c->grid_sparse;
+  h.grid_light = c->grid_light;
+  h.grid_pull = c->grid_pull;
+  h.light_lanes = c->light_lanes;
+  h.pull_lanes = c->pull_lanes;
+  h.pull_ratio = c->pull_ratio;
+  h.heavy_limit = c->heavy_limit;
+  h.heavy_chunk = c->heavy_chunk;
+  h.fold_max = c->fold_max;
+  h.h_items = c->h_items;
+  h.h_nrows = c->h_nrows;
+  h.n_mp = c->mp_rows ? c->n_mp : -1;
+  h.has_order = c->row_order ? 1 : 0;
+  const rwr_ctx::Warm &w = c->ws;
+  h.ws_alloc = w.alloc;
+  h.ws_params = w.params;
+  h.ws_mode = w.mode;
+  h.ws_hops = w.hops;
+  h.ws_warmup = w.warmup;
+  h.ws_has_mask = !w.mask_h.empty();
+  h.ws_max_rows = w.max_rows;
+  h.ws_step = w.net.step;
+  h.ws_lr = w.net.lr;
+  h.ws_wd = w.net.wd;
+
+  const std::string tmp = std::string(path) + ".part";
+  File F;
+  F.f = std::fopen(tmp.c_str(), "wb");
+  CK_IO(c, F.f, "cannot open " + tmp + " for writing");
+  FILE *f = F.f;
+  auto put = [&](const void *p, size_t bytes) { return bytes == 0 || std::fwrite(p, 1, bytes, f) == bytes; };
+  CK_IO(c, put(&h, sizeof(h)), "checkpoint write failed");
+  CK_IO(c, put(c->seeds_h.data(), sizeof(int32_t) * c->seeds_h.size()), "checkpoint write failed");
+  CK_IO(c, put(c->ctl_h, sizeof(Ctl)), "checkpoint write failed");
+  RWR_TRY(ck_put_dev(c, f, c->seeds_d, sizeof(int32_t) * RWR_MAX_COLS));
+  RWR_TRY(ck_put_dev(c, f, c->perm, sizeof(int32_t) * c->n_cap));
+  RWR_TRY(ck_put_dev(c, f, c->inv, sizeof(int32_t) * c->n_cap));
+  RWR_TRY(ck_put_dev(c, f, c->r, sizeof(double) * nS));
+  RWR_TRY(ck_put_dev(c, f, c->gbuf, sizeof(double) * nS));
+  if (c->qmode) RWR_TRY(ck_put_dev(c, f, c->qvec, sizeof(double) * nS));
+  if (c->tail_slot >= 0) RWR_TRY(ck_put_dev(c, f, c->x[c->tail_slot], xs * nS));
+  for (int o = 0; o < no; ++o) {
+    CK_IO(c, put(lens[o].data(), sizeof(int32_t) * lens[o].size()), "checkpoint write failed");
+    CK_IO(c, put(adjs[o].data(), sizeof(int32_t) * adjs[o].size()), "checkpoint write failed");
+    RWR_TRY(ck_put_dev(c, f, c->g[o].v.heavy, c->n_cap));
+  }
+  RWR_TRY(ck_put_dev(c, f, c->h_item_row, sizeof(int32_t) * c->h_items));
+  RWR_TRY(ck_put_dev(c, f, c->h_item_chunk, sizeof(int32_t) * c->h_items));
+  RWR_TRY(ck_put_dev(c, f, c->h_rows, sizeof(int32_t) * c->h_nrows));
+  RWR_TRY(ck_put_dev(c, f, c->h_nchunks, sizeof(int32_t) * c->h_nrows));
+  RWR_TRY(ck_put_dev(c, f, c->h_first, sizeof(int32_t) * c->h_nrows));
+  if (h.has_order) RWR_TRY(ck_put_dev(c, f, c->row_order, sizeof(int32_t) * c->n_cap));
+  if (h.n_mp >= 0) RWR_TRY(ck_put_dev(c, f, c->mp_rows, sizeof(int32_t) * (c->n_mp + 1)));
+  if (w.alloc && w.params) {
+    const size_t P = sizeof(float) * gnn::LAYOUT.total;
+    RWR_TRY(ck_put_dev(c, f, w.net.theta, P));
+    RWR_TRY(ck_put_dev(c, f, w.net.m1, P));
+    RWR_TRY(ck_put_dev(c, f, w.net.m2, P));
+  }
+  if (h.ws_has_mask) CK_IO(c, put(w.mask_h.data(), sizeof(float) * w.mask_h.size()), "checkpoint write failed");
+  CK_IO(c, std::fflush(f) == 0, "checkpoint write failed");
+  std::fclose(F.f);
+  F.f = nullptr;
+  CK_IO(c, std::rename(tmp.c_str(), path) == 0, "cannot rename " + tmp + " to " + path);
+  return RWR_OK;
+}
+
+static rwr_status load_impl(rwr_ctx *c, FILE *f, const CkptHead &h) {
+  auto get = [&](void *p, size_t bytes) { return bytes == 0 || std::fread(p, 1, bytes, f) == bytes; };
+  HIP_TRY(c, hipGetDevice(&c->device));
+  HIP_TRY(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+  if (c->cfg.stream) {
+    c->stream = (hipStream_t)c->cfg.stream;
+  } else {
+    HIP_TRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  c->n = h.n;
+  c->n_cap = h.n_cap;
+  c->m = h.m;
+  c->n_seeds = h.n_seeds;
+  c->S = h.S;
+  c->max_iters = h.max_iters;
+  c->solve_iters = h.solve_iters;
+  c->undirected = h.undirected;
+  c->fp64 = h.fp64;
+  c->rows_only = h.rows_only;
+  c->det = h.det;
+  c->qmode = h.qmode;
+  c->stale = h.stale;
+  c->lockstep = h.lockstep;
+  c->carry_level = h.carry_level;
+  c->tail_slot = h.tail_slot;
+  c->update_runs = h.update_runs;
+  c->last_iters = h.last_iters;
+  c->pend = h.pend;
+  c->tail_cols = h.tail_cols;
+  c->budget = h.budget;
+  c->refine_target = h.refine_target;
+  c->decay_ema = h.decay_ema;
+  c->sparse_ema = h.sparse_ema;
+  c->dense_ema = h.dense_ema;
+  c->last_carry_l1 = h.last_carry_l1;
+  c->tail_ema = h.tail_ema;
+  std::memcpy(c->err_bound, h.err_bound, sizeof(h.err_bound));
+  std::memcpy(c->pend_b, h.pend_b, sizeof(h.pend_b));
+  std::memcpy(c->pend_l1, h.pend_l1, sizeof(h.pend_l1));
+  tune_defaults(c);  // settings that only the environment sets (graph replay, ...)
+  c->grid_sparse = h.grid_sparse;
+  c->grid_light = h.grid_light;
+  c->grid_pull = h.grid_pull;
+  c->light_lanes = h.light_lanes;
+  c->pull_lanes = h.pull_lanes;
+  c->pull_ratio = h.pull_ratio;
+  c->heavy_limit = h.heavy_limit;
+  c->heavy_chunk = h.heavy_chunk;
+  c->fold_max = h.fold_max;
+  c->lockstep = h.lockstep;
+  c->carry_level = h.carry_level;
+  c->refine_target = h.refine_target;
+  const int no = c->undirected ? 1 : 2;
+  const size_t nS = (size_t)c->n * c->S, nSc = (size_t)c->n_cap * c->S;
+  const size_t xs = c->fp64 ? 8 : 4;
+
+  c->seeds_h.resize(h.n_seeds);
+  CK_IO(c, get(c->seeds_h.data(), sizeof(int32_t) * h.n_seeds), "checkpoint truncated");
+  HIP_TRY(c, hipHostMalloc((void **)&c->ctl_h, sizeof(Ctl), hipHostMallocDefault));
+  CK_IO(c, get(c->ctl_h, sizeof(Ctl)), "checkpoint truncated");
+  RWR_TRY(alloc_zero(c, &c->ctl, 1));
+  RWR_TRY(alloc_zero(c, &c->seeds_d, RWR_MAX_COLS));
+  RWR_TRY(ck_get_dev(c, f, c->seeds_d, sizeof(int32_t) * RWR_MAX_COLS));
+  RWR_TRY(alloc_zero(c, &c->perm, c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->inv, c->n_cap));
+  RWR_TRY(ck_get_dev(c, f, c->perm, sizeof(int32_t) * c->n_cap));
+  RWR_TRY(ck_get_dev(c, f, c->inv, sizeof(int32_t) * c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->r, nSc));
+  RWR_TRY(alloc_zero(c, &c->ybuf, nSc));
+  RWR_TRY(alloc_zero(c, &c->gbuf, nSc));
+  RWR_TRY(alloc_zero(c, &c->xres, nSc));
+  RWR_TRY(ck_get_dev(c, f, c->r, sizeof(double) * nS));
+  RWR_TRY(ck_get_dev(c, f, c->gbuf, sizeof(double) * nS));
+  if (c->qmode) {
+    RWR_TRY(alloc_zero(c, &c->qvec, nSc));
+    RWR_TRY(ck_get_dev(c, f, c->qvec, sizeof(double) * nS));
+  }
+  RWR_TRY(dev_alloc(c, &c->x[0], xs * nSc));
+  RWR_TRY(dev_alloc(c, &c->x[1], xs * nSc));
+  launch_zero_bytes(c->x[0], xs * nSc, c->stream);
+  launch_zero_bytes(c->x[1], xs * nSc, c->stream);
+  if (c->tail_slot >= 0) RWR_TRY(ck_get_dev(c, f, c->x[c->tail_slot], xs * nS));
+
+  // graph: each orientation laid out afresh (slack per row and an arena, as
+  // a relayout makes them) with the saved row contents
+  RWR_TRY(ensure_temp(c, build_temp_bytes(1, c->n_cap)));
+  for (int o = 0; o < no; ++o) {
+    Orientation &g = c->g[o];
+    RWR_TRY(alloc_zero(c, &g.v.off, c->n_cap));
+    RWR_TRY(alloc_zero(c, &g.v.len, c->n_cap));
+    RWR_TRY(alloc_zero(c, &g.v.cap, c->n_cap));
+    RWR_TRY(alloc_zero(c, &g.v.heavy, c->n_cap));
+    std::vector<int32_t> len(c->n), adj(h.m_o[o]);
+    CK_IO(c, get(len.data(), sizeof(int32_t) * len.size()), "checkpoint truncated");
+    CK_IO(c, get(adj.data(), sizeof(int32_t) * adj.size()), "checkpoint truncated");
+    std::vector<int32_t> coff(std::max(1, c->n));
+    int64_t acc = 0;
+    for (int32_t v = 0; v < c->n; ++v) {
+      if (len[v] < 0) CK_IO(c, false, "checkpoint corrupt (row length)");
+      coff[v] = (int32_t)acc;
+      acc += len[v];
+    }
+    CK_IO(c, acc == h.m_o[o], "checkpoint corrupt (edge count)");
+    for (int32_t x : adj) CK_IO(c, x >= 0 && x < c->n, "checkpoint corrupt (node id)");
+    H2D(c, g.v.len, len.data(), sizeof(int32_t) * c->n);
+    int64_t used = 0;
+    HIP_TRY(c, relayout_offsets(g.v.len, c->n, g.v.cap, g.v.off, c->temp, c->temp_bytes, &used, c->stream));
+    g.e_cap = used + std::max<int64_t>(used / 4, 65536);
+    if (g.e_cap >= INT32_MAX) {
+      c->err = "adjacency capacity exceeds 2^31 slots";
+      return RWR_ENOMEM;
+    }
+    RWR_TRY(dev_alloc(c, (void **)&g.v.adj, sizeof(int32_t) * g.e_cap));
+    if (acc > 0) {
+      int32_t *doff = nullptr, *dadj = nullptr;
+      RWR_TRY(dev_alloc(c, (void **)&doff, sizeof(int32_t) * coff.size()));
+      rwr_status s = dev_alloc(c, (void **)&dadj, sizeof(int32_t) * acc);
+      if (s == RWR_OK) s = copy_sync(c, doff, coff.data(), sizeof(int32_t) * coff.size(), hipMemcpyHostToDevice);
+      if (s == RWR_OK) s = copy_sync(c, dadj, adj.data(), sizeof(int32_t) * acc, hipMemcpyHostToDevice);
+      if (s == RWR_OK) {
+        DevGraphView src = g.v;
+        src.off = doff;
+        src.adj = dadj;
+        launch_copy_rows(src, g.v.off, g.v.adj, c->n, c->stream);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) s = RWR_EHIP;
+      }
+      dev_free(c, doff);
+      dev_free(c, dadj);
+      RWR_TRY(s);
+    }
+    RWR_TRY(ck_get_dev(c, f, g.v.heavy, c->n_cap));
+    c->ctl_h->tail[o] = (uint64_t)used;
+  }
+  if (c->undirected) c->g[1] = c->g[0];
+  Ctl ctl = *c->ctl_h;
+  ctl.err = 0;
+  ctl.done_blocks = 0;
+  H2D(c, c->ctl, &ctl, sizeof(Ctl));
+
+  RWR_TRY(alloc_zero(c, &c->stamp, c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->fstamp, c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->nmark, c->n_cap));
+  if (c->det) RWR_TRY(alloc_zero(c, &c->tmark, (size_t)c->n_cap * 2));
+  RWR_TRY(alloc_zero(c, &c->hfront, c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->hbase, c->n_cap));
+  RWR_TRY(alloc_zero(c, &c->sel, (size_t)c->n_cap * 2));
+  RWR_TRY(alloc_zero(c, &c->sel_count, 1));
+  RWR_TRY(alloc_zero(c, &c->hist, (size_t)(c->max_iters + 2 + c->solve_iters + 2) * c->S));
+
+  // plans as saved
+  c->h_items = h.h_items;
+  c->h_nrows = h.h_nrows;
+  RWR_TRY(alloc_zero(c, &c->h_item_row, std::max(1, h.h_items)));
+  RWR_TRY(alloc_zero(c, &c->h_item_chunk, std::max(1, h.h_items)));
+  RWR_TRY(alloc_zero(c, &c->h_rows, std::max(1, h.h_nrows)));
+  RWR_TRY(alloc_zero(c, &c->h_nchunks, std::max(1, h.h_nrows)));
+  RWR_TRY(alloc_zero(c, &c->h_first, std::max(1, h.h_nrows)));
+  RWR_TRY(alloc_zero(c, &c->h_part, (size_t)std::max(1, h.h_items) * c->S));
+  RWR_TRY(ck_get_dev(c, f, c->h_item_row, sizeof(int32_t) * h.h_items));
+  RWR_TRY(ck_get_dev(c, f, c->h_item_chunk, sizeof(int32_t) * h.h_items));
+  RWR_TRY(ck_get_dev(c, f, c->h_rows, sizeof(int32_t) * h.h_nrows));
+  RWR_TRY(ck_get_dev(c, f, c->h_nchunks, sizeof(int32_t) * h.h_nrows));
+  RWR_TRY(ck_get_dev(c, f, c->h_first, sizeof(int32_t) * h.h_nrows));
+  if (h.has_order) {
+    RWR_TRY(alloc_zero(c, &c->row_order, c->n_cap));
+    RWR_TRY(ck_get_dev(c, f, c->row_order, sizeof(int32_t) * c->n_cap));
+  }
+  if (h.n_mp >= 0) {
+    c->n_mp = h.n_mp;
+    RWR_TRY(dev_alloc(c, (void **)&c->mp_rows, sizeof(int32_t) * (h.n_mp + 1)));
+    RWR_TRY(ck_get_dev(c, f, c->mp_rows, sizeof(int32_t) * (h.n_mp + 1)));
+  }
+  RWR_TRY(ensure_partials(c));
+
+  // learned warm start
+  if (h.ws_alloc) {
+    RWR_TRY(warm_alloc(c, h.ws_max_rows));
+    rwr_ctx::Warm &w = c->ws;
+    if (h.ws_params) {
+      const int64_t P = gnn::LAYOUT.total;
+      std::vector<float> th(P);
+      CK_IO(c, get(th.data(), sizeof(float) * P), "checkpoint truncated");
+      HIP_TRY(c, gnn::net_set_params(w.net, th.data(), c->stream));
+      RWR_TRY(ck_get_dev(c, f, w.net.m1, sizeof(float) * P));
+      RWR_TRY(ck_get_dev(c, f, w.net.m2, sizeof(float) * P));
+      w.net.step = h.ws_step;
+      w.params = true;
+    }
+    w.mode = h.ws_mode;
+    w.hops = h.ws_hops;
+    w.warmup = h.ws_warmup;
+    w.net.warmup = h.ws_warmup;
+    w.net.lr = h.ws_lr;
+    w.net.wd = h.ws_wd;
+  }
+  if (h.ws_has_mask) {
+    c->ws.mask_h.resize(gnn::LAYOUT.total);
+    CK_IO(c, get(c->ws.mask_h.data(), sizeof(float) * gnn::LAYOUT.total), "checkpoint truncated");
+    if (c->ws.alloc) RWR_TRY(warm_set_mask(c, c->ws.mask_h.data()));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return RWR_OK;
+}
+
+rwr_status rwr_load(const char *path, const rwr_config *runtime, rwr_ctx **out) {
+  if (!path || !out) return RWR_EINVAL;
+  *out = nullptr;
+  g_build_error.clear();
+  if (runtime && ((runtime->dev_alloc == nullptr) != (runtime->dev_free == nullptr))) {
+    g_build_error = "dev_alloc and dev_free must be given together";
+    return RWR_EINVAL;
+  }
+  File F;
+  F.f = std::fopen(path, "rb");
+  if (!F.f) {
+    g_build_error = std::string("cannot open ") + path;
+    return RWR_EIO;
+  }
+  CkptHead h{};
+  if (std::fread(&h, 1, sizeof(h), F.f) != sizeof(h) || std::memcmp(h.magic, CKPT_MAGIC, 8) != 0 ||
+      h.version != CKPT_VERSION || h.head_bytes != sizeof(CkptHead) || h.cfg_bytes != sizeof(rwr_config) ||
+      h.ctl_bytes != sizeof(Ctl)) {
+    g_build_error = std::string(path) + " is not a checkpoint of this library version";
+    return RWR_EIO;
+  }
+  if (h.n <= 0 || h.n > h.n_cap || h.n_seeds < 1 || h.n_seeds > RWR_MAX_COLS || h.S < h.n_seeds ||
+      h.S > RWR_MAX_COLS || h.m_o[0] < 0 || h.m_o[1] < 0 || h.h_items < 0 || h.h_nrows < 0 ||
+      h.m_o[0] > INT32_MAX || h.m_o[1] > INT32_MAX || h.tail_slot < -1 || h.tail_slot > 1) {
+    g_build_error = std::string(path) + ": corrupt header";
+    return RWR_EIO;
+  }
+  rwr_ctx *c = new rwr_ctx();
+  c->cfg = h.cfg;
+  if (runtime) {
+    c->cfg.stream = runtime->stream;
+    c->cfg.dev_alloc = runtime->dev_alloc;
+    c->cfg.dev_free = runtime->dev_free;
+    c->cfg.alloc_user = runtime->alloc_user;
+    c->cfg.phase_timing = runtime->phase_timing;
+  }
+  rwr_status s = load_impl(c, F.f, h);
+  if (s != RWR_OK) {
+    g_build_error = c->err;
+    rwr_destroy(c);
+    return s;
+  }
+  c->built = true;
+  *out = c;
+  return RWR_OK;
+}
 
 rwr_status rwr_sweep_shape(const rwr_ctx *c, int32_t *lanes_per_row, int32_t *workgroups, double *tuned_ms) {
   if (!c) return RWR_EINVAL;
@@ -2259,7 +2796,7 @@ rwr_status rwr_warm_start(rwr_ctx *c, int32_t mode, int32_t hops, int64_t max_ro
     c->ws.mask_h = mask;
     c->ws.warmup = warmup;
     c->ws.net.warmup = warmup;
-    if (!mask.empty()) HIP_TRY(c, gnn::net_set_mask(c->ws.net, mask.data(), c->stream));
+    if (!mask.empty()) RWR_TRY(warm_set_mask(c, mask.data()));
   } else if (!c->ws.alloc) {
     RWR_TRY(warm_alloc(c, rows));
   }
@@ -2292,7 +2829,7 @@ rwr_status rwr_model_trainable(rwr_ctx *c, const float *mask, int64_t n, int32_t
     c->ws.mask_h.clear();
   c->ws.warmup = warmup_steps;
   c->ws.net.warmup = warmup_steps;
-  HIP_TRY(c, gnn::net_set_mask(c->ws.net, mask ? c->ws.mask_h.data() : nullptr, c->stream));
+  RWR_TRY(warm_set_mask(c, mask ? c->ws.mask_h.data() : nullptr));
   return RWR_OK;
 }
 

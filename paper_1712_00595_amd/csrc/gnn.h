@@ -70,6 +70,7 @@ struct Net {
   float lr = 1e-3f, wd = 1e-4f;
   int64_t warmup = 0;      // steps of linear step-size warm-up
   float *mask = nullptr;   // trainable parameters (1) and held ones (0); null: all train
+  int det = 0;             // 1: each aggregation row summed by one thread in edge order
   // activations
   float *F = nullptr;                 // rows x FEAT
   float *h[LAYERS + 1] = {};          // rows x HID
@@ -90,9 +91,14 @@ hipError_t net_alloc(Net &n, int S, int64_t max_rows);
 void net_free(Net &n);
 // Lay the buffers of a network for up to max_rows rows over caller memory
 // (device address base, `bytes` available) instead of allocating them.
-// Returns the bytes taken, or 0 (and an empty Net) when they do not fit.
-// Such a Net must not be passed to net_free or net_set_mask.
-size_t net_view(Net &n, int S, int64_t max_rows, void *base, size_t bytes);
+// Returns the bytes taken, or 0 (and an empty Net) when they do not fit;
+// base null: the bytes it would take (n left empty).  part_cap: floats of
+// weight-gradient partials (0: one HID x HID block per 128 rows).  Its
+// mask is the caller's to set.  Such a Net must not be passed to net_free or
+// net_set_mask.
+size_t net_view(Net &n, int S, int64_t max_rows, void *base, size_t bytes, int64_t part_cap = 0);
+// weight-gradient partials of an allocated network (floats)
+constexpr int64_t NET_PART_CAP = 512 * HID * HID;
 // copy host parameters (float32, LAYOUT.total) and reset the optimiser
 hipError_t net_set_params(Net &n, const float *host, hipStream_t st);
 hipError_t net_get_params(const Net &n, float *host, hipStream_t st);

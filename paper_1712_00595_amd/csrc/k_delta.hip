@@ -413,7 +413,8 @@ __global__ __launch_bounds__(1024) void k_seed_items_small(const int32_t *__rest
 
 // One wavefront per item, the waves looping over all items.  Lane layout:
 // column j = lane % S, edge slot p = lane / S.  Contributions go to ybuf
-// (FP64, atomically); receiving nodes are stamped.
+// (FP64, atomically); receiving nodes are stamped.  With ybuf null only the
+// stamps (the offset support) and the cost model's sums are produced.
 template <int S>
 __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *__restrict__ seg,
                               const int32_t *__restrict__ row, const int32_t *__restrict__ t_dold,
@@ -453,7 +454,7 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
       const int32_t v = adj[o + i];
       const bool del = seg_find(keys, b, e, u, v, b1) >= 0;  // validated: a hit is a deletion
       const double contrib = del ? -w_old : (w_new - w_old);
-      if (contrib != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], contrib);
+      if (ybuf && contrib != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], contrib);
       if (j == 0 && (del || d_new != d_old)) stamp[v] = st;
     }
     if (k != 0) continue;
@@ -467,16 +468,122 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
       if (d_old > 0 && d_new > 0) du += kept * fabs(1.0 / d_new - 1.0 / d_old);
       if (d_new > 0) du += n_ins / (double)d_new;
       if (d_old > 0) du += n_del / (double)d_old;
-      atomic_add_f64(&ctl->dr_l1[j], du * fabs(ru));
+      // without ybuf (deterministic mode) in fixed point: integer sums do not
+      // depend on the order of the additions
+      if (ybuf)
+        atomic_add_f64(&ctl->dr_l1[j], du * fabs(ru));
+      else
+        atomicAdd((unsigned long long *)&ctl->dr_fix[j], (unsigned long long)llrint(du * fabs(ru) * 0x1p52));
     }
     for (int32_t i = b + p; i < e; i += P) {
       const uint64_t kk = keys[i];
       if (!(kk & 1ull)) continue;
       const int32_t v = key_col(kk, b1);
-      if (w_new != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], w_new);
+      if (ybuf && w_new != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], w_new);
       if (j == 0) stamp[v] = st;
     }
   }
+}
+
+// ------------------------------------------- offset seed in a fixed order
+// The offset seed without floating-point atomics, for runs that must not
+// depend on timing.  After the structural apply, every node v that the
+// support pass stamped gets q(v, j) with a plain store, summed in one fixed
+// order: the in-row of v in the new graph (each in-neighbour u whose row the
+// batch changed contributes (1-c) r(u) / d_new(u), minus (1-c) r(u) /
+// d_old(u) unless the edge (u, v) is inserted), then the edges into v that
+// the batch deletes (-(1-c) r(u) / d_old(u)), in key order; lane parts are
+// added by a fixed shuffle tree.  tmark[u] = 1 + the index of u's segment
+// among the changed rows (out orientation), imark[v] = 1 + the index of v's
+// segment among the changed rows of the pull orientation, 0 elsewhere.
+__global__ void k_mark_segments(const int32_t *__restrict__ row0, const int32_t *__restrict__ rowp, Ctl *ctl,
+                                int po, int32_t *__restrict__ tmark, int32_t *__restrict__ imark, int32_t value) {
+  if (ctl->err) return;
+  const int32_t n0 = ctl->nT[0], np = ctl->nT[po];
+  for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < max(n0, np); t += gridDim.x * blockDim.x) {
+    if (t < n0) tmark[row0[t]] = value ? t + 1 : 0;
+    if (t < np) imark[rowp[t]] = value ? t + 1 : 0;
+  }
+}
+
+template <int S>
+__global__ void k_offset_pull(const int32_t *__restrict__ stamp, const Ctl *ctl, int32_t n, DevGraphView in,
+                              const int32_t *__restrict__ tmark, const int32_t *__restrict__ t_dold,
+                              const int32_t *__restrict__ t_dnew, const int32_t *__restrict__ imark,
+                              const uint64_t *__restrict__ ikeys, const int32_t *__restrict__ iseg, int b1,
+                              const double *__restrict__ r, const double *__restrict__ rsub,
+                              double *__restrict__ ybuf, double c1) {
+  if (ctl->err) return;
+  constexpr int P = RWR_WAVE / S;
+  const int lane = threadIdx.x % RWR_WAVE;
+  const int j = lane % S, p = lane / S;
+  const int32_t st = ctl->stamp;
+  auto score = [&](int u) -> double {
+    const int64_t k = col_index(u, S, j);
+    return rsub ? r[k] - rsub[k] : r[k];
+  };
+  const int nwv = gridDim.x * (blockDim.x / RWR_WAVE);
+  for (int base = ((blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE) * RWR_WAVE; base < n;
+       base += nwv * RWR_WAVE) {
+    // the stamped nodes among 64 consecutive ones, one at a time
+    unsigned long long m = __ballot(base + lane < n && stamp[base + lane] == st);
+    while (m) {
+      const int v = base + __builtin_ctzll(m);
+      m &= m - 1;
+      const int32_t sv = imark[v];
+      const int32_t b = sv ? iseg[sv - 1] : 0, e = sv ? iseg[sv] : 0;
+      const int o = in.off[v], d = in.len[v];
+      double q = 0.0;
+      for (int i = p; i < d; i += P) {
+        const int u = in.adj[o + i];
+        const int32_t tu = tmark[u];
+        if (!tu) continue;
+        const double ru = score(u);
+        const int d_old = t_dold[tu - 1], d_new = t_dnew[tu - 1];
+        const double w_new = d_new ? c1 * ru / (double)d_new : 0.0;
+        const double w_old = d_old ? c1 * ru / (double)d_old : 0.0;
+        const int32_t hit = sv ? seg_find(ikeys, b, e, v, u, b1) : -1;
+        q += (hit >= 0 && (ikeys[hit] & 1ull)) ? w_new : (w_new - w_old);
+      }
+      for (int32_t i = b + p; i < e; i += P) {
+        const uint64_t kk = ikeys[i];
+        if (kk & 1ull) continue;  // an insertion: counted in the in-row
+        const int u = key_col(kk, b1);
+        const int32_t tu = tmark[u];
+        const int d_old = tu ? t_dold[tu - 1] : 0;
+        if (d_old) q -= c1 * score(u) / (double)d_old;
+      }
+      for (int off = S; off < RWR_WAVE; off <<= 1) q += __shfl_xor(q, off, RWR_WAVE);
+      if (p == 0) ybuf[col_index(v, S, j)] = q;
+    }
+  }
+}
+
+hipError_t launch_offset_pull(int S, const OrientPair &P, int po, const DevGraphView &in, const int32_t *stamp,
+                              const Ctl *ctl, int32_t n, int32_t *tmark, int32_t *imark, int b1, const double *r,
+                              const double *rsub, double *ybuf, double c1, int32_t max_rows, int grid,
+                              hipStream_t st) {
+  const int mg = std::max(1, std::min(1024, (max_rows + 255) / 256));
+  hipLaunchKernelGGL(k_mark_segments, dim3(mg), dim3(256), 0, st, P.o[0].row, P.o[po].row, (Ctl *)ctl, po, tmark,
+                     imark, 1);
+#define RWR_PULL_CASE(SS)                                                                                        \
+  case SS:                                                                                                       \
+    hipLaunchKernelGGL(k_offset_pull<SS>, dim3(grid), dim3(256), 0, st, stamp, ctl, n, in, tmark, P.o[0].t_dold, \
+                       P.o[0].t_dnew, imark, P.o[po].keys, P.o[po].seg, b1, r, rsub, ybuf, c1);                   \
+    break;
+  switch (S) {
+    RWR_PULL_CASE(1)
+    RWR_PULL_CASE(2)
+    RWR_PULL_CASE(4)
+    RWR_PULL_CASE(8)
+    RWR_PULL_CASE(16)
+    RWR_PULL_CASE(32)
+    RWR_PULL_CASE(64)
+  }
+#undef RWR_PULL_CASE
+  hipLaunchKernelGGL(k_mark_segments, dim3(mg), dim3(256), 0, st, P.o[0].row, P.o[po].row, (Ctl *)ctl, po, tmark,
+                     imark, 0);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------- structural apply
@@ -559,7 +666,10 @@ __global__ void k_reset_batch(Ctl *ctl, int demand_only) {
   ctl->heavy_stale = 0;
   if (!demand_only) {
     ctl->node_dels = 0;
-    for (int j = 0; j < RWR_MAX_COLS; ++j) ctl->dr_l1[j] = 0.0;
+    for (int j = 0; j < RWR_MAX_COLS; ++j) {
+      ctl->dr_l1[j] = 0.0;
+      ctl->dr_fix[j] = 0;
+    }
   }
 }
 

@@ -245,9 +245,10 @@ __global__ void k_reduce_part(const float *__restrict__ part, int nb, int count,
 // backward (IN = false):
 //   Y[i*S+j][.] = dinv[i] sum over out-edges i -> v of M[v*S+j][.]
 // Four gathers in flight per thread.  A row of several chunks is zeroed
-// beforehand and its chunks accumulate with float atomics.
+// beforehand and its chunks accumulate with float atomics; with `det` the
+// first chunk's thread sums the whole row in edge order instead.
 template <bool IN>
-__global__ void k_agg(RegionView g, int S, const float *__restrict__ Min, float *__restrict__ Y) {
+__global__ void k_agg(RegionView g, int S, const float *__restrict__ Min, float *__restrict__ Y, int det) {
   const int32_t *items = IN ? g.in_items : g.out_items;
   const int32_t n_items = IN ? g.n_in_items : g.n_out_items;
   const int32_t *roff = IN ? g.in_off : g.out_off;
@@ -268,8 +269,9 @@ __global__ void k_agg(RegionView g, int S, const float *__restrict__ Min, float 
     const int i = lo;
     const int k = it - items[i];
     const int nch = items[i + 1] - items[i];
+    if (det && k != 0) continue;
     const int o = roff[i], d = rlen[i];
-    const int e0 = k * AGG_CHUNK, e1 = min(d, e0 + AGG_CHUNK);
+    const int e0 = k * AGG_CHUNK, e1 = det ? d : min(d, e0 + AGG_CHUNK);
     float4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int e = e0; e < e1; e += 4) {
       int uu[4];
@@ -294,7 +296,7 @@ __global__ void k_agg(RegionView g, int S, const float *__restrict__ Min, float 
       acc.w *= s;
     }
     float *dst = Y + ((int64_t)i * S + j) * MSG + 4 * q;
-    if (nch == 1) {
+    if (nch == 1 || det) {
       *reinterpret_cast<float4 *>(dst) = acc;
     } else {
       atomicAdd(dst, acc.x);
@@ -445,7 +447,7 @@ hipError_t net_alloc(Net &n, int S, int64_t max_rows) {
   GNN_TRY(dalloc(&n.da, max_rows * MSG));
   GNN_TRY(dalloc(&n.dm, max_rows * MSG));
   GNN_TRY(dalloc(&n.dout, max_rows));
-  n.part_cap = 512 * HID * HID;
+  n.part_cap = NET_PART_CAP;
   GNN_TRY(dalloc(&n.part, n.part_cap));
   GNN_TRY(dalloc(&n.loss_part, 4096));
   GNN_TRY(dalloc(&n.loss, 1));
@@ -453,7 +455,7 @@ hipError_t net_alloc(Net &n, int S, int64_t max_rows) {
   return hipSuccess;
 }
 
-size_t net_view(Net &n, int S, int64_t max_rows, void *base, size_t bytes) {
+size_t net_view(Net &n, int S, int64_t max_rows, void *base, size_t bytes, int64_t part_cap) {
   n = Net{};
   n.S = S;
   n.max_rows = max_rows;
@@ -463,6 +465,11 @@ size_t net_view(Net &n, int S, int64_t max_rows, void *base, size_t bytes) {
   auto take = [&](auto **dst, int64_t count) {
     using T = std::remove_reference_t<decltype(**dst)>;
     const size_t b = ((size_t)count * sizeof(T) + 255) / 256 * 256;
+    if (!p) {  // size query
+      *dst = nullptr;
+      used += b;
+      return;
+    }
     if (used + b > bytes) {
       fit = false;
       *dst = nullptr;
@@ -495,9 +502,9 @@ size_t net_view(Net &n, int S, int64_t max_rows, void *base, size_t bytes) {
   take(&n.da, max_rows * MSG);
   take(&n.dm, max_rows * MSG);
   take(&n.dout, max_rows);
-  // weight-gradient partials: one block of HID x HID per 128 rows (the
-  // same partition as an allocated network uses for these rows)
-  n.part_cap = std::max<int64_t>(1, (max_rows + 127) / 128) * HID * HID;
+  // weight-gradient partials: by default one block of HID x HID per 128
+  // rows (the same partition as an allocated network uses for these rows)
+  n.part_cap = part_cap > 0 ? part_cap : std::max<int64_t>(1, (max_rows + 127) / 128) * HID * HID;
   take(&n.part, n.part_cap);
   take(&n.loss_part, 4096);
   take(&n.loss, 1);
@@ -506,6 +513,7 @@ size_t net_view(Net &n, int S, int64_t max_rows, void *base, size_t bytes) {
     n = Net{};
     return 0;
   }
+  if (!p) n = Net{};
   return used;
 }
 
@@ -547,10 +555,11 @@ static const __bf16 *bwd_w(const Net &n, int i) { return n.wb.bwd + mat_table().
 static int gemm_grid(int64_t rows) { return grid_for((rows + 15) / 16, GB / WAVE, 8192); }
 
 template <bool IN>
-static void agg(const RegionView &g, int S, int64_t rows, const float *Min, float *Y, hipStream_t st) {
+static void agg(const RegionView &g, int S, int64_t rows, const float *Min, float *Y, int det, hipStream_t st) {
   hipLaunchKernelGGL(k_agg_zero<IN>, dim3(grid_for(rows * MSG, GB)), dim3(GB), 0, st, g, S, Y);
   const int64_t work = (int64_t)(IN ? g.n_in_items : g.n_out_items) * 4 * S;
-  if (work > 0) hipLaunchKernelGGL(k_agg<IN>, dim3(grid_for(work, GB, 8192)), dim3(GB), 0, st, g, S, Min, Y);
+  if (work > 0)
+    hipLaunchKernelGGL(k_agg<IN>, dim3(grid_for(work, GB, 8192)), dim3(GB), 0, st, g, S, Min, Y, det);
 }
 
 void net_forward(Net &n, const RegionView &g, int64_t rows, hipStream_t st) {
@@ -561,7 +570,7 @@ void net_forward(Net &n, const RegionView &g, int64_t rows, hipStream_t st) {
   for (int l = 0; l < LAYERS; ++l) {
     hipLaunchKernelGGL((k_gemm<HID, 0, MSG, EPI_NONE>), dim3(gg), dim3(GB), 0, st, rows, n.h[l], nullptr,
                        fwd_w(n, 1 + 3 * l), nullptr, nullptr, nullptr, n.m);
-    agg<true>(g, n.S, rows, n.m, n.a[l], st);
+    agg<true>(g, n.S, rows, n.m, n.a[l], n.det, st);
     hipLaunchKernelGGL((k_gemm<HID, MSG, HID, EPI_BIAS_RELU>), dim3(gg), dim3(GB), 0, st, rows, n.h[l], n.a[l],
                        fwd_w(n, 2 + 3 * l), fwd_w(n, 3 + 3 * l), th + LAYOUT.b[l], nullptr, n.h[l + 1]);
   }
@@ -608,7 +617,7 @@ void net_backward(Net &n, const RegionView &g, int64_t rows, hipStream_t st) {
     // da = dz Wm^T ; dm = aggregation transpose of da
     hipLaunchKernelGGL((k_gemm<HID, 0, MSG, EPI_NONE>), dim3(gg), dim3(GB), 0, st, rows, n.dz, nullptr,
                        bwd_w(n, 3 + 3 * l), nullptr, nullptr, nullptr, n.da);
-    agg<false>(g, n.S, rows, n.da, n.dm, st);
+    agg<false>(g, n.S, rows, n.da, n.dm, n.det, st);
     wgrad<HID, MSG>(n, rows, n.h[l], n.dm, G + LAYOUT.Wp[l], st);
     // dz of layer l = (dz Ws^T + dm Wp^T) masked by h_l > 0
     hipLaunchKernelGGL((k_gemm<HID, MSG, HID, EPI_RELU_MASK>), dim3(gg), dim3(GB), 0, st, rows, n.dz, n.dm,

@@ -73,6 +73,7 @@ struct Ctl {
   int32_t last_it[RWR_MAX_COLS];  // iteration of last_norm
   double dr_l1[RWR_MAX_COLS];     // ||D r_old||_1 of the batch (D: row L1 norms of B~ - A~)
   int32_t inj[RWR_MAX_COLS];      // the column's pending carried vector joined this run
+  uint64_t dr_fix[RWR_MAX_COLS];  // dr_l1 in fixed point (2^-52 units), summed in deterministic mode
 };
 
 // history of per-iteration norms: hist[i * S + j] = ||x^(i)[:, j]||_1

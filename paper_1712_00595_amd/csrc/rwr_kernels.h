@@ -127,6 +127,14 @@ hipError_t launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, c
                               int grid, hipStream_t st);
 size_t seed_scan_temp_bytes(int32_t max_rows);
 void launch_apply(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st);
+// the offset seed summed in a fixed order (no atomics), after the structural
+// apply and a support-only launch_offset_seed (ybuf null): ybuf of every
+// stamped node; tmark/imark are zero node arrays, left zero; po = pull
+// orientation (its keys hold each node's inserted and deleted in-edges)
+hipError_t launch_offset_pull(int S, const OrientPair &P, int po, const DevGraphView &in, const int32_t *stamp,
+                              const Ctl *ctl, int32_t n, int32_t *tmark, int32_t *imark, int b1, const double *r,
+                              const double *rsub, double *ybuf, double c1, int32_t max_rows, int grid,
+                              hipStream_t st);
 
 // ---- propagation (k_prop.hip); fp64 selects the propagation type
 // hist_base: first row of the norm history this run writes (0 for update

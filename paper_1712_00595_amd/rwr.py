@@ -28,6 +28,7 @@ STATUS = {
     -6: "RWR_ENOCONV",
     -7: "RWR_ENUMERIC",
     -8: "RWR_ESTATE",
+    -9: "RWR_EIO",
 }
 
 EXPORTED = [
@@ -54,6 +55,9 @@ EXPORTED = [
     "rwr_model_trainable",
     "rwr_gnn_eval_noalloc",
     "rwr_scores_set",
+    "rwr_save",
+    "rwr_load",
+    "rwr_context_info",
 ]
 
 
@@ -172,12 +176,55 @@ def load_library(path: str = LIB_PATH):
     L.rwr_model_trainable.argtypes = [p, p, i64, i32]
     L.rwr_scores_set.argtypes = [p, i32, p, i64, i32]
     L.rwr_gnn_eval_noalloc.argtypes = [p, i32, i32, p, p, p, i64, p, p, p, i64, p, p, p, p, p, p, p, p, p]
+    L.rwr_save.argtypes = [p, ctypes.c_char_p]
+    L.rwr_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(Config), ctypes.POINTER(p)]
+    L.rwr_context_info.argtypes = [p, ctypes.POINTER(Config), ctypes.POINTER(i32), p]
     for name in EXPORTED:
         f = getattr(L, name)
         if name not in ("rwr_destroy", "rwr_last_error", "rwr_gnn_num_params"):
             f.restype = ctypes.c_int
     _lib = L
     return L
+
+
+# allocator hooks of rwr_config (dev_alloc / dev_free)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """Device memory of a context from torch's caching allocator, on the
+    context's own stream.  Keeps the callbacks alive while a context uses
+    them; ``live`` counts the blocks the context holds."""
+
+    def __init__(self):
+        import torch
+
+        self._torch = torch
+        self.device = torch.cuda.current_device()
+        self.live = 0
+        self.allocs = 0
+        self.alloc_fn = ALLOC_FN(self._alloc)
+        self.free_fn = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, stream, user):
+        try:
+            ptr = self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0) or None)
+        except Exception:  # out of memory: the library reports RWR_ENOMEM
+            return None
+        self.live += 1
+        self.allocs += 1
+        return ptr
+
+    def _free(self, ptr, stream, user):
+        if ptr:
+            self._torch.cuda.caching_allocator_delete(int(ptr))
+            self.live -= 1
+
+    def install(self, cfg: "Config") -> None:
+        cfg.dev_alloc = ctypes.cast(self.alloc_fn, ctypes.c_void_p)
+        cfg.dev_free = ctypes.cast(self.free_fn, ctypes.c_void_p)
+        cfg.alloc_user = None
 
 
 def _is_torch(a) -> bool:
@@ -211,6 +258,14 @@ def _check(lib, ctx, code: int):
     if code != 0:
         msg = lib.rwr_last_error(ctx)
         raise RwrError(code, msg.decode() if msg else "")
+
+
+def _make_allocator(kind: Optional[str]):
+    if kind is None:
+        return None
+    if kind == "torch":
+        return TorchAllocator()
+    raise ValueError(f"unknown allocator {kind!r} (None or 'torch')")
 
 
 @dataclasses.dataclass
@@ -247,9 +302,11 @@ class Context:
         deterministic: bool = False,
         node_deletion: str = "incident",
         phase_timing: bool = False,
+        allocator: Optional[str] = None,
     ):
         self._lib = load_library()
         self._ctx = ctypes.c_void_p(None)
+        self.allocator = _make_allocator(allocator)
         cfg = Config()
         self._lib.rwr_config_default(ctypes.byref(cfg))
         cfg.c = c
@@ -266,6 +323,8 @@ class Context:
         cfg.deterministic = 1 if deterministic else 0
         cfg.node_deletion = {"incident": 0, "row": 1}[node_deletion]
         cfg.phase_timing = 1 if phase_timing else 0
+        if self.allocator is not None:
+            self.allocator.install(cfg)
         on_dev = _is_torch(src)
         s = _Arr(src, on_dev)
         d = _Arr(dst, on_dev)
@@ -293,6 +352,45 @@ class Context:
         self.seeds = sd.copy()
         self.c = c
         self.eps = eps
+
+    # -- checkpoint
+    def save(self, path: str) -> None:
+        """Write the context's state to ``path`` (rwr_save)."""
+        _check(self._lib, self._ctx, self._lib.rwr_save(self._ctx, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path: str, *, stream: Optional[int] = None, allocator: Optional[str] = None,
+             phase_timing: bool = False) -> "Context":
+        """A context continuing from a checkpoint (rwr_load); the configuration
+        comes from the file, except the runtime fields given here."""
+        self = cls.__new__(cls)
+        self._lib = load_library()
+        self._ctx = ctypes.c_void_p(None)
+        self.allocator = _make_allocator(allocator)
+        rt = Config()
+        self._lib.rwr_config_default(ctypes.byref(rt))
+        rt.stream = stream
+        rt.phase_timing = 1 if phase_timing else 0
+        if self.allocator is not None:
+            self.allocator.install(rt)
+        out = ctypes.c_void_p(None)
+        _check(self._lib, None, self._lib.rwr_load(os.fsencode(path), ctypes.byref(rt), ctypes.byref(out)))
+        self._ctx = out
+        cfg = Config()
+        ns = ctypes.c_int32(0)
+        sd = np.zeros(64, np.int32)
+        _check(self._lib, self._ctx, self._lib.rwr_context_info(self._ctx, ctypes.byref(cfg), ctypes.byref(ns),
+                                                                sd.ctypes.data))
+        self.n_seeds = int(ns.value)
+        self.seeds = sd[: self.n_seeds].copy()
+        self.c = cfg.c
+        self.eps = cfg.eps
+        return self
+
+    def config(self) -> dict:
+        cfg = Config()
+        _check(self._lib, self._ctx, self._lib.rwr_context_info(self._ctx, ctypes.byref(cfg), None, None))
+        return {f: getattr(cfg, f) for f, _ in Config._fields_}
 
     # -- lifetime
     def close(self):

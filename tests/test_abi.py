@@ -77,6 +77,32 @@ def test_config_default_and_host_side_rejection():
     L.rwr_destroy(None)
 
 
+def test_checkpoint_and_hook_rejection_on_the_host(tmp_path):
+    """rwr_load refuses a file that is not a checkpoint, and builds refuse an
+    allocator hook given without its partner, before any device call."""
+    L = pkg.load_library()
+    out = ctypes.c_void_p(None)
+    assert L.rwr_load(str(tmp_path / "absent.ckpt").encode(), None, ctypes.byref(out)) == -9
+    junk = tmp_path / "junk.ckpt"
+    junk.write_bytes(b"RWRCKPT0" + bytes(4096))
+    assert L.rwr_load(str(junk).encode(), None, ctypes.byref(out)) == -9
+    assert b"not a checkpoint" in L.rwr_last_error(None)
+    short = tmp_path / "short.ckpt"
+    short.write_bytes(b"RWRCKPT1")
+    assert L.rwr_load(str(short).encode(), None, ctypes.byref(out)) == -9
+    assert not out.value
+    assert L.rwr_save(None, b"x") == -1
+    cfg = rwr.Config()
+    L.rwr_config_default(ctypes.byref(cfg))
+    keep = rwr.ALLOC_FN(lambda n, s, u: None)
+    cfg.dev_alloc = ctypes.cast(keep, ctypes.c_void_p)
+    seeds = (ctypes.c_int32 * 1)(0)
+    src = (ctypes.c_int32 * 1)(0)
+    assert L.rwr_build(ctypes.byref(cfg), 4, 1, src, src, 1, seeds, 0, ctypes.byref(out)) == -1
+    assert b"together" in L.rwr_last_error(None)
+    assert L.rwr_load(str(junk).encode(), ctypes.byref(cfg), ctypes.byref(out)) == -1
+
+
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(ImportError):
         rwr.load_library.__wrapped__ if hasattr(rwr.load_library, "__wrapped__") else None
