@@ -17,8 +17,13 @@
  *   - Every call returns rwr_status (0 = RWR_OK, negative = error); no C++
  *     exception crosses this boundary.  A text for the last error of a
  *     context is returned by rwr_last_error().
- *   - Calls are synchronous with respect to the host on return.  One context
- *     uses one HIP stream; a context is not thread-safe.
+ *   - Calls are synchronous with respect to the host on return: every output
+ *     (scores, statistics, exported arrays) is final and no array the caller
+ *     passed is read any more.  rwr_update may leave work queued on the
+ *     context's stream that only prepares the next update from the context's
+ *     own buffers; every later call on the context, rwr_destroy included, is
+ *     ordered after it.  One context uses one HIP stream; a context is not
+ *     thread-safe.
  *   - The caller owns every array it passes; the library copies what it
  *     keeps.  A pointer flagged "on device" must be device memory of the
  *     context's GPU, readable for the duration of the call.

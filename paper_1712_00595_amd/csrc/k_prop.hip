@@ -1111,6 +1111,12 @@ __global__ __launch_bounds__(BLOCK) void k_heavy_epi(SlotArgs a, int k, int entr
   block_publish<S>(nrm, sm, 0, 0, a.part, a.part_i, entry_base + blockIdx.x, sh);
 }
 
+// V values of T in one aligned access
+template <typename T, int V>
+struct alignas(sizeof(T) * V) VecT {
+  T v[V];
+};
+
 // Carried vectors (one column per seed, FP64 in gbuf).  A pending vector p is
 // part of r, and r - p has residual p in the graph before the batch (Section
 // 3.1's expansion).  Two kinds: the last iterate x^(k) of a run that ended in
@@ -1120,26 +1126,48 @@ __global__ __launch_bounds__(BLOCK) void k_heavy_epi(SlotArgs a, int k, int entr
 //
 // Before an update: gbuf = d_out * x[last] for the columns in tail_mask (with
 // the degrees before the batch), the pending vector for the columns in
-// keep_mask, 0 elsewhere; both x buffers are cleared for the run.
-template <typename XT>
-__global__ __launch_bounds__(BLOCK) void k_carry_prepare(SlotArgs a, int S, int last, uint64_t tail_mask,
+// keep_mask, 0 elsewhere; both x buffers are cleared for the run.  Each
+// thread takes V consecutive columns (16-byte accesses of x where S allows);
+// S is a compile-time power of two, so the node and column of an element
+// are a shift and a mask
+template <typename XT, int S>
+__global__ __launch_bounds__(BLOCK) void k_carry_prepare(SlotArgs a, int last, uint64_t tail_mask,
                                                          uint64_t keep_mask) {
+  constexpr int V = S >= 4 && sizeof(XT) == 4 ? 4 : (S >= 2 ? 2 : 1);
+  using XV = VecT<XT, V>;
+  using DV = VecT<double, V>;
   XT *__restrict__ x0 = (XT *)a.x[0];
   XT *__restrict__ x1 = (XT *)a.x[1];
   const XT *__restrict__ xl = (last == 1) ? x1 : x0;
-  const int64_t total = (int64_t)a.n * S;
-  for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < total; i += (int64_t)gridDim.x * BLOCK) {
-    const int j = (int)(i % S);
-    double p = 0.0;
-    if (last >= 0 && ((tail_mask >> j) & 1ull)) {
-      const int d = a.out.len[i / S];
-      p = d ? (double)xl[i] * (double)d : 0.0;
-    } else if ((keep_mask >> j) & 1ull) {
-      p = a.gbuf[i];
+  const int64_t groups = (int64_t)a.n * (S / V);
+  XV zx;
+#pragma unroll
+  for (int q = 0; q < V; ++q) zx.v[q] = (XT)0;
+  for (int64_t t = blockIdx.x * (int64_t)BLOCK + threadIdx.x; t < groups; t += (int64_t)gridDim.x * BLOCK) {
+    const int64_t i = t * V;
+    const int v = (int)(i / S), j0 = (int)(i % S);
+    const uint64_t tails = last >= 0 ? (tail_mask >> j0) & ((1ull << V) - 1) : 0ull;
+    const uint64_t keeps = (keep_mask >> j0) & ((1ull << V) - 1);
+    DV p;
+    XV xv = zx;
+    DV g;
+#pragma unroll
+    for (int q = 0; q < V; ++q) g.v[q] = 0.0;
+    if (tails) xv = *reinterpret_cast<const XV *>(xl + i);
+    if (keeps & ~tails) g = *reinterpret_cast<const DV *>(a.gbuf + i);
+    const int d = tails ? a.out.len[v] : 0;
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      if ((tails >> q) & 1ull)
+        p.v[q] = d ? (double)xv.v[q] * (double)d : 0.0;
+      else if ((keeps >> q) & 1ull)
+        p.v[q] = g.v[q];
+      else
+        p.v[q] = 0.0;
     }
-    a.gbuf[i] = p;
-    x0[i] = (XT)0;
-    x1[i] = (XT)0;
+    *reinterpret_cast<DV *>(a.gbuf + i) = p;
+    *reinterpret_cast<XV *>(x0 + i) = zx;
+    *reinterpret_cast<XV *>(x1 + i) = zx;
   }
 }
 
@@ -1428,12 +1456,13 @@ void launch_slot0_epilogue(const SlotArgs &a, int S, bool fp64, hipStream_t st) 
 
 void launch_carry_prepare(const SlotArgs &a, int S, bool fp64, int last, uint64_t tail_mask, uint64_t keep_mask,
                           hipStream_t st) {
-  if (fp64)
-    hipLaunchKernelGGL((k_carry_prepare<double>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, S, last, tail_mask,
-                       keep_mask);
-  else
-    hipLaunchKernelGGL((k_carry_prepare<float>), dim3(a.grid_light), dim3(BLOCK), 0, st, a, S, last, tail_mask,
-                       keep_mask);
+  if (fp64) {
+    RWR_DISPATCH_S(S, hipLaunchKernelGGL((k_carry_prepare<double, SS>), dim3(a.grid_light), dim3(BLOCK), 0, st, a,
+                                         last, tail_mask, keep_mask));
+  } else {
+    RWR_DISPATCH_S(S, hipLaunchKernelGGL((k_carry_prepare<float, SS>), dim3(a.grid_light), dim3(BLOCK), 0, st, a,
+                                         last, tail_mask, keep_mask));
+  }
 }
 
 // dense sweep (or residual) + heavy rows + decision; the heavy-row kernel
