@@ -191,6 +191,14 @@ struct rwr_ctx {
     int32_t n_in_items = 0, n_out_items = 0;
     double *gpart = nullptr;  // gradient item partials (one per item and column)
     int64_t gpart_cap = 0;
+    int32_t *grow = nullptr;  // row of each gradient item (gpart_cap / S entries)
+    int32_t *lin_item_row = nullptr, *lout_item_row = nullptr;  // row of each aggregation item
+    int64_t item_row_cap = 0;
+    // row items of the region search and of the local rows (two sets: in- and
+    // out-rows); lv: the region's level table (see ws_region)
+    int32_t *it_tmp[2] = {}, *it_rit[2] = {}, *it_irow[2] = {}, *it_icnt[2] = {}, *it_ioff[2] = {};
+    int64_t items_cap = 0;
+    int32_t *lv = nullptr;
     double *kpart = nullptr;  // per-workgroup partials of the correction's K
     double *fa = nullptr;     // f(|xhat|) per column
     int64_t ladj_cap = 0;
@@ -198,6 +206,7 @@ struct rwr_ctx {
     size_t scan_bytes = 0;
     float *dinv = nullptr;
     double *xhat = nullptr, *wbuf = nullptr, *qn = nullptr, *part = nullptr, *sums = nullptr;
+    int8_t *sg = nullptr;  // signs of the residual (n_cap * S)
     void *temp = nullptr;
     size_t temp_bytes = 0;
     // this update
@@ -610,6 +619,7 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
     RWR_TRY(regrow((void **)&c->ws.wlist, 4, 1));
     RWR_TRY(regrow((void **)&c->ws.flags, 4, 1));
     RWR_TRY(regrow((void **)&c->ws.wbuf, 8, c->S));
+    RWR_TRY(regrow((void **)&c->ws.sg, 1, c->S));
     const size_t tb = ws_select_temp_bytes(new_cap);
     if (tb > c->ws.temp_bytes) {
       dev_free(c, c->ws.temp);
@@ -1089,7 +1099,20 @@ static void warm_free(rwr_ctx *c) {
   dev_free(c, w.lin_items);
   dev_free(c, w.lout_items);
   dev_free(c, w.gpart);
+  dev_free(c, w.grow);
   w.gpart_cap = 0;
+  dev_free(c, w.lin_item_row);
+  dev_free(c, w.lout_item_row);
+  w.item_row_cap = 0;
+  for (int k = 0; k < 2; ++k) {
+    dev_free(c, w.it_tmp[k]);
+    dev_free(c, w.it_rit[k]);
+    dev_free(c, w.it_irow[k]);
+    dev_free(c, w.it_icnt[k]);
+    dev_free(c, w.it_ioff[k]);
+  }
+  w.items_cap = 0;
+  dev_free(c, w.lv);
   dev_free(c, w.kpart);
   dev_free(c, w.fa);
   w.ladj_cap = 0;
@@ -1099,6 +1122,7 @@ static void warm_free(rwr_ctx *c) {
   dev_free(c, w.dinv);
   dev_free(c, w.xhat);
   dev_free(c, w.wbuf);
+  dev_free(c, w.sg);
   dev_free(c, w.qn);
   dev_free(c, w.part);
   dev_free(c, w.sums);
@@ -1142,6 +1166,7 @@ static rwr_status warm_alloc(rwr_ctx *c, int64_t max_rows) {
   RWR_TRY(alloc_zero(c, &w.wlist, c->n_cap));
   RWR_TRY(alloc_zero(c, &w.flags, c->n_cap));
   RWR_TRY(alloc_zero(c, &w.wbuf, (size_t)c->n_cap * c->S));
+  RWR_TRY(alloc_zero(c, &w.sg, (size_t)c->n_cap * c->S));
   RWR_TRY(alloc_zero(c, &w.R, w.max_nodes));
   RWR_TRY(alloc_zero(c, &w.lin_cnt, w.max_nodes + 1));
   RWR_TRY(alloc_zero(c, &w.lin_off, w.max_nodes + 1));
@@ -1153,13 +1178,18 @@ static rwr_status warm_alloc(rwr_ctx *c, int64_t max_rows) {
   RWR_TRY(alloc_zero(c, &w.item_off, w.max_nodes + 1));
   RWR_TRY(alloc_zero(c, &w.kpart, (size_t)WS_KPART_BLOCKS * RWR_MAX_COLS));
   RWR_TRY(alloc_zero(c, &w.fa, RWR_MAX_COLS));
+  for (int k = 0; k < 2; ++k) {
+    RWR_TRY(alloc_zero(c, &w.it_tmp[k], w.max_nodes + 1));
+    RWR_TRY(alloc_zero(c, &w.it_rit[k], w.max_nodes + 1));
+  }
+  RWR_TRY(alloc_zero(c, &w.lv, 3 + WS_MAX_HOPS));
   w.scan_bytes = ws_scan_temp_bytes((int32_t)w.max_nodes);
   RWR_TRY(dev_alloc(c, &w.scan_temp, w.scan_bytes));
   RWR_TRY(alloc_zero(c, &w.dinv, w.max_nodes));
   RWR_TRY(alloc_zero(c, &w.xhat, w.max_rows));
   RWR_TRY(alloc_zero(c, &w.cnt, 4));
   RWR_TRY(alloc_zero(c, &w.qn, 2 * RWR_MAX_COLS));
-  RWR_TRY(alloc_zero(c, &w.sums, 3 * RWR_MAX_COLS));
+  RWR_TRY(alloc_zero(c, &w.sums, 4 * RWR_MAX_COLS));
   RWR_TRY(alloc_zero(c, &w.part, (size_t)1024 * 2 * RWR_MAX_COLS));
   w.temp_bytes = ws_select_temp_bytes(c->n_cap);
   RWR_TRY(dev_alloc(c, &w.temp, w.temp_bytes));
@@ -1182,6 +1212,8 @@ static gnn::RegionView warm_view(rwr_ctx *c) {
   g.out_items = w.lout_items;
   g.n_in_items = w.n_in_items;
   g.n_out_items = w.n_out_items;
+  g.in_item_row = w.lin_item_row;
+  g.out_item_row = w.lout_item_row;
   g.loc = nullptr;
   g.nodes = nullptr;
   g.dinv = w.dinv;
@@ -1189,16 +1221,73 @@ static gnn::RegionView warm_view(rwr_ctx *c) {
   return g;
 }
 
-// local in- and out-rows of the region (after ws_loc)
+// row-item buffers for rows of up to max_nodes region nodes in the current
+// graph (they grow with its edge count)
+static rwr_status warm_items(rwr_ctx *c) {
+  rwr_ctx::Warm &w = c->ws;
+  const int64_t mi = ws_max_items((int32_t)w.max_nodes, c->m);
+  if (mi <= w.items_cap) return RWR_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int64_t cap = std::max<int64_t>(mi, w.items_cap + w.items_cap / 2);
+  if (cap >= INT32_MAX) {
+    c->err = "warm-start row items exceed 2^31";
+    return RWR_ENOMEM;
+  }
+  for (int k = 0; k < 2; ++k) {
+    dev_free(c, w.it_irow[k]);
+    dev_free(c, w.it_icnt[k]);
+    dev_free(c, w.it_ioff[k]);
+    RWR_TRY(alloc_zero(c, &w.it_irow[k], cap + 1));
+    RWR_TRY(alloc_zero(c, &w.it_icnt[k], cap + 1));
+    RWR_TRY(alloc_zero(c, &w.it_ioff[k], cap + 1));
+  }
+  w.items_cap = cap;
+  const size_t sb = ws_scan_temp_bytes((int32_t)std::max<int64_t>(cap, w.max_nodes));
+  if (sb > w.scan_bytes) {
+    dev_free(c, w.scan_temp);
+    w.scan_bytes = 0;
+    RWR_TRY(dev_alloc(c, &w.scan_temp, sb));
+    w.scan_bytes = sb;
+  }
+  return RWR_OK;
+}
+
+static WsItems items_set(rwr_ctx *c, int k) {
+  rwr_ctx::Warm &w = c->ws;
+  WsItems it{};
+  it.tmp = w.it_tmp[k];
+  it.rit = w.it_rit[k];
+  it.irow = w.it_irow[k];
+  it.icnt = w.it_icnt[k];
+  it.ioff = w.it_ioff[k];
+  it.max_items = (int32_t)w.items_cap;
+  it.scan_temp = w.scan_temp;
+  it.scan_bytes = w.scan_bytes;
+  return it;
+}
+
+// local in- and out-rows of the region (after ws_loc): offsets and item
+// counts of both orientations, one read of their totals, then the rows
 static rwr_status warm_local_graph(rwr_ctx *c) {
   rwr_ctx::Warm &w = c->ws;
   const DevGraphView &in = c->g[pull_orient(c)].v;
   const DevGraphView &out = c->g[0].v;
-  HIP_TRY(c, ws_local_rows(w.R, w.nR, in, w.loc1, w.lin_cnt, w.lin_off, w.scan_temp, w.scan_bytes, c->stream));
-  HIP_TRY(c, ws_local_rows(w.R, w.nR, out, w.loc1, w.lout_cnt, w.lout_off, w.scan_temp, w.scan_bytes, c->stream));
-  int32_t tin = 0, tout = 0;
-  D2H(c, &tin, w.lin_off + w.nR, sizeof(int32_t));
-  D2H(c, &tout, w.lout_off + w.nR, sizeof(int32_t));
+  const WsItems A = items_set(c, 0), B = items_set(c, 1);
+  HIP_TRY(c, ws_local_rows(w.R, w.lv, w.nR, in, w.loc1, A, w.lin_cnt, w.lin_off, c->stream));
+  HIP_TRY(c, ws_local_rows(w.R, w.lv, w.nR, out, w.loc1, B, w.lout_cnt, w.lout_off, c->stream));
+  HIP_TRY(c, ws_chunk_items(w.lin_cnt, w.nR, gnn::AGG_CHUNK, w.items, w.lin_items, w.scan_temp, w.scan_bytes,
+                            c->stream));
+  HIP_TRY(c, ws_chunk_items(w.lout_cnt, w.nR, gnn::AGG_CHUNK, w.items, w.lout_items, w.scan_temp, w.scan_bytes,
+                            c->stream));
+  int32_t tot[4] = {0, 0, 0, 0};
+  HIP_TRY(c, hipMemcpyAsync(&tot[0], w.lin_off + w.nR, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&tot[1], w.lout_off + w.nR, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&tot[2], w.lin_items + w.nR, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&tot[3], w.lout_items + w.nR, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int32_t tin = tot[0], tout = tot[1];
+  w.n_in_items = tot[2];
+  w.n_out_items = tot[3];
   const int64_t need = std::max<int64_t>(std::max(tin, tout), 1);
   if (need > w.ladj_cap) {
     dev_free(c, w.lin_adj);
@@ -1208,14 +1297,19 @@ static rwr_status warm_local_graph(rwr_ctx *c) {
     RWR_TRY(dev_alloc(c, (void **)&w.lout_adj, sizeof(int32_t) * cap));
     w.ladj_cap = cap;
   }
-  ws_local_fill(w.R, w.nR, in, w.loc1, w.lin_off, w.lin_adj, c->stream);
-  ws_local_fill(w.R, w.nR, out, w.loc1, w.lout_off, w.lout_adj, c->stream);
-  HIP_TRY(c, ws_chunk_items(w.lin_cnt, w.nR, gnn::AGG_CHUNK, w.items, w.lin_items, w.scan_temp, w.scan_bytes,
-                            c->stream));
-  HIP_TRY(c, ws_chunk_items(w.lout_cnt, w.nR, gnn::AGG_CHUNK, w.items, w.lout_items, w.scan_temp, w.scan_bytes,
-                            c->stream));
-  D2H(c, &w.n_in_items, w.lin_items + w.nR, sizeof(int32_t));
-  D2H(c, &w.n_out_items, w.lout_items + w.nR, sizeof(int32_t));
+  ws_local_fill(w.R, w.lv, in, w.loc1, A, w.lin_adj, c->stream);
+  ws_local_fill(w.R, w.lv, out, w.loc1, B, w.lout_adj, c->stream);
+  const int64_t ni = std::max<int64_t>({w.n_in_items, w.n_out_items, 1});
+  if (ni > w.item_row_cap) {
+    dev_free(c, w.lin_item_row);
+    dev_free(c, w.lout_item_row);
+    const int64_t cap = std::max<int64_t>(ni, 2 * w.item_row_cap);
+    RWR_TRY(dev_alloc(c, (void **)&w.lin_item_row, sizeof(int32_t) * cap));
+    RWR_TRY(dev_alloc(c, (void **)&w.lout_item_row, sizeof(int32_t) * cap));
+    w.item_row_cap = cap;
+  }
+  gnn::region_item_rows(w.lin_items, w.nR, w.lin_item_row, c->stream);
+  gnn::region_item_rows(w.lout_items, w.nR, w.lout_item_row, c->stream);
   return RWR_OK;
 }
 
@@ -1241,25 +1335,14 @@ static rwr_status warm_prepare(rwr_ctx *c) {
   const DevGraphView &in = c->g[pull_orient(c)].v;
   const DevGraphView &out = c->g[0].v;
   const int32_t st0 = c->ctl_h->stamp;
-  int32_t nR = 0, lvl_start = 0, n0 = 0;
-  for (int h = 0; h <= w.hops; ++h) {
-    if (h > 0) ws_expand(w.R + lvl_start, nR - lvl_start, out, h, w.hop1, c->stream);
-    ws_level_flags(c->stamp, st0, c->n, h, w.hop1, w.flags, c->stream);
-    HIP_TRY(c, ws_select(w.flags, c->n, w.wlist, w.cnt, w.temp, w.temp_bytes, c->stream));
-    int32_t k = 0;
-    D2H(c, &k, w.cnt, sizeof(int32_t));
-    if (nR + (int64_t)k > w.max_nodes) {
-      ws_unmark(w.wlist, k, w.hop1, c->stream);
-      break;
-    }
-    if (k > 0)
-      HIP_TRY(c, hipMemcpyAsync(w.R + nR, w.wlist, sizeof(int32_t) * k, hipMemcpyDeviceToDevice, c->stream));
-    if (h == 0) n0 = k;
-    lvl_start = nR;
-    nR += k;
-    if (k == 0) break;
-    w.level_end.push_back(nR);
-  }
+  RWR_TRY(warm_items(c));
+  HIP_TRY(c, ws_region(c->stamp, st0, c->n, w.hops, (int32_t)w.max_nodes, out, w.hop1, w.flags, w.wlist, w.cnt,
+                       w.R, w.lv, items_set(c, 0), w.temp, w.temp_bytes, c->stream));
+  int32_t lvh[3 + WS_MAX_HOPS];
+  D2H(c, lvh, w.lv, sizeof(int32_t) * (3 + w.hops));
+  const int32_t nR = lvh[0];
+  for (int h = 0; h <= w.hops && lvh[2 + h] >= 0; ++h) w.level_end.push_back(lvh[2 + h]);
+  const int32_t n0 = w.level_end.empty() ? 0 : w.level_end[0];
   w.nR = nR;
   if (nR == 0 || n0 == 0) {
     ws_clear(w.R, nR, w.hop1, w.loc1, c->stream);
@@ -1283,7 +1366,7 @@ static rwr_status warm_prepare(rwr_ctx *c) {
     a.zero_seed_rows = 0;
     launch_apply_p(a, S, c->stream);
   }
-  ws_rho(c->n, S, c->ybuf, c->gbuf, w.wbuf, w.part, w.sums, c->stream);
+  ws_rho(c->n, S, c->ybuf, c->gbuf, w.wbuf, w.sg, w.part, w.sums, c->stream);
   std::vector<double> sums(2 * S);
   D2H(c, sums.data(), w.sums, sizeof(double) * 2 * S);
   w.qn_h.assign(S, 0.0);
@@ -1316,12 +1399,15 @@ static rwr_status warm_prepare(rwr_ctx *c) {
     if (need > w.gpart_cap) {
       HIP_TRY(c, hipStreamSynchronize(c->stream));
       dev_free(c, w.gpart);
+      dev_free(c, w.grow);
       w.gpart_cap = 0;
       RWR_TRY(dev_alloc(c, (void **)&w.gpart, sizeof(double) * need));
+      RWR_TRY(dev_alloc(c, (void **)&w.grow, sizeof(int32_t) * (need / S)));
       w.gpart_cap = need;
     }
-    HIP_TRY(c, ws_resid_grad(w.R, nR, S, out, c1, c->gbuf, w.gpart, w.items, w.item_off, w.scan_temp, w.scan_bytes,
-                             w.net.active, den, w.net.o, w.qn, beta, w.fa, w.kpart, w.net.dout, c->stream));
+    HIP_TRY(c, ws_resid_grad(w.R, nR, S, out, c1, c->gbuf, w.sg, w.gpart, w.items, w.item_off, w.grow, w.scan_temp,
+                             w.scan_bytes, w.net.active, den, w.net.o, w.qn, beta, w.fa, w.kpart,
+                             w.sums + 3 * RWR_MAX_COLS, w.net.dout, c->stream));
     gnn::net_backward(w.net, warm_view(c), rows, c->stream);
     gnn::net_adamw(w.net, c->stream);
     w.trained = true;

@@ -54,6 +54,8 @@ struct RegionView {
   // chunks accumulated.
   const int32_t *in_items, *out_items;
   int32_t n_in_items, n_out_items;
+  // row of each item (n_*_items entries; null: found by binary search)
+  const int32_t *in_item_row, *out_item_row;
   const int32_t *loc;
   const int32_t *nodes;
   const float *dinv;  // 1/d_out of each local node (0 for dead ends)
@@ -82,12 +84,15 @@ struct Net {
   float *dout = nullptr;              // rows
   float *part = nullptr;              // partial sums of weight gradients
   int64_t part_cap = 0;
+  float *part2 = nullptr;             // first-stage sums of those (part_cap / 32 + HID * HID)
   double *loss_part = nullptr;        // per-workgroup loss partials
   double *loss = nullptr;             // device scalar
   int32_t *active = nullptr;          // per column: 1 when it counts in the loss
 };
 
 hipError_t net_alloc(Net &n, int S, int64_t max_rows);
+// item_row[it] = row of chunk it, from the chunk offsets items[0..nR]
+void region_item_rows(const int32_t *items, int32_t nR, int32_t *item_row, hipStream_t st);
 void net_free(Net &n);
 // Lay the buffers of a network for up to max_rows rows over caller memory
 // (device address base, `bytes` available) instead of allocating them.
@@ -98,7 +103,7 @@ void net_free(Net &n);
 // net_set_mask.
 size_t net_view(Net &n, int S, int64_t max_rows, void *base, size_t bytes, int64_t part_cap = 0);
 // weight-gradient partials of an allocated network (floats)
-constexpr int64_t NET_PART_CAP = 512 * HID * HID;
+constexpr int64_t NET_PART_CAP = 4096 * HID * HID;
 // copy host parameters (float32, LAYOUT.total) and reset the optimiser
 hipError_t net_set_params(Net &n, const float *host, hipStream_t st);
 hipError_t net_get_params(const Net &n, float *host, hipStream_t st);

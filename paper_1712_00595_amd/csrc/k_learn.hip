@@ -156,14 +156,14 @@ __global__ __launch_bounds__(GB) void k_gemm(int64_t M, const float *__restrict_
   }
 }
 
-// Partial weight gradient of one workgroup: G[k][n] = sum over its rows of
+// Partial weight gradient of one wavefront: G[k][n] = sum over its rows of
 // X[m][k] D[m][n] (both rounded to bfloat16), on the matrix cores with the
-// rows as the reduction index.
+// rows as the reduction index; part row = the wavefront's global index.  No
+// LDS, so that many wavefronts stay resident.
 template <int K, int N>
 __global__ __launch_bounds__(GB) void k_wgrad(int64_t M, const float *__restrict__ X, const float *__restrict__ D,
                                               float *__restrict__ part) {
   constexpr int KT = K / 16, NT = N / 16;
-  __shared__ float red[GB / WAVE][K * N];
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   const int r = lane % 16, g = lane / 16;
   f32x4 acc[KT][NT];
@@ -189,19 +189,13 @@ __global__ __launch_bounds__(GB) void k_wgrad(int64_t M, const float *__restrict
 #pragma unroll
       for (int b = 0; b < NT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
   }
+  float *__restrict__ dst = part + wave * (K * N);
 #pragma unroll
   for (int a = 0; a < KT; ++a)
 #pragma unroll
     for (int b = 0; b < NT; ++b)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) red[w][(a * 16 + 4 * g + i) * N + b * 16 + r] = acc[a][b][i];
-  __syncthreads();
-  for (int e = threadIdx.x; e < K * N; e += GB) {
-    float s = 0.0f;
-#pragma unroll
-    for (int ww = 0; ww < GB / WAVE; ++ww) s += red[ww][e];
-    part[(int64_t)blockIdx.x * K * N + e] = s;
-  }
+      for (int i = 0; i < 4; ++i) dst[(a * 16 + 4 * g + i) * N + b * 16 + r] = acc[a][b][i];
 }
 
 // Column sums over rows (per workgroup): MODE 0: sum A[m][n]; MODE 1: sum
@@ -229,13 +223,29 @@ __global__ __launch_bounds__(GB) void k_colsum(int64_t M, const float *__restric
   }
 }
 
-// out[i] = sum over b of part[b * count + i] (fixed order)
-__global__ void k_reduce_part(const float *__restrict__ part, int nb, int count, float *__restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// out[i] = sum over b of part[b * count + i], in two fixed-order stages:
+// group y of RED_GROUP consecutive partials is summed in order into
+// tmp[y * count + i], then the group sums in order into out[i].
+#define RED_GROUP 32
+__global__ __launch_bounds__(GB) void k_reduce_stage(const float *__restrict__ part, int nb, int count,
+                                                     float *__restrict__ out) {
+  const int i = blockIdx.x * GB + threadIdx.x;
   if (i >= count) return;
+  const int b0 = blockIdx.y * RED_GROUP, b1 = min(nb, b0 + RED_GROUP);
   float s = 0.0f;
-  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * count + i];
-  out[i] = s;
+  for (int b = b0; b < b1; ++b) s += part[(int64_t)b * count + i];
+  out[(int64_t)blockIdx.y * count + i] = s;
+}
+
+static void reduce_part(const Net &n, const float *part, int nb, int count, float *out, hipStream_t st) {
+  const int ng = (nb + RED_GROUP - 1) / RED_GROUP;
+  const int gx = (count + GB - 1) / GB;
+  if (ng == 1) {
+    hipLaunchKernelGGL(k_reduce_stage, dim3(gx, 1), dim3(GB), 0, st, part, nb, count, out);
+    return;
+  }
+  hipLaunchKernelGGL(k_reduce_stage, dim3(gx, ng), dim3(GB), 0, st, part, nb, count, n.part2);
+  hipLaunchKernelGGL(k_reduce_stage, dim3(gx, 1), dim3(GB), 0, st, n.part2, ng, count, out);
 }
 
 // ------------------------------------------------------------ aggregation
@@ -251,6 +261,7 @@ template <bool IN>
 __global__ void k_agg(RegionView g, int S, const float *__restrict__ Min, float *__restrict__ Y, int det) {
   const int32_t *items = IN ? g.in_items : g.out_items;
   const int32_t n_items = IN ? g.n_in_items : g.n_out_items;
+  const int32_t *item_row = IN ? g.in_item_row : g.out_item_row;
   const int32_t *roff = IN ? g.in_off : g.out_off;
   const int32_t *rlen = IN ? g.in_len : g.out_len;
   const int32_t *radj = IN ? g.in_adj : g.out_adj;
@@ -260,13 +271,18 @@ __global__ void k_agg(RegionView g, int S, const float *__restrict__ Min, float 
     const int32_t it = (int32_t)(t / per);
     const int cidx = (int)(t % per);
     const int j = cidx / 4, q = cidx % 4;
-    int32_t lo = 0, hi = g.nR - 1;
-    while (lo < hi) {
-      const int32_t mid = (lo + hi + 1) >> 1;
-      if (items[mid] <= it) lo = mid;
-      else hi = mid - 1;
+    int32_t i;
+    if (item_row) {
+      i = item_row[it];
+    } else {
+      int32_t lo = 0, hi = g.nR - 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (items[mid] <= it) lo = mid;
+        else hi = mid - 1;
+      }
+      i = lo;
     }
-    const int i = lo;
     const int k = it - items[i];
     const int nch = items[i + 1] - items[i];
     if (det && k != 0) continue;
@@ -305,6 +321,12 @@ __global__ void k_agg(RegionView g, int S, const float *__restrict__ Min, float 
       atomicAdd(dst + 3, acc.w);
     }
   }
+}
+
+// item_row[it] = the row whose chunk `it` is (items: nR + 1 chunk offsets)
+__global__ void k_item_rows(const int32_t *__restrict__ items, int32_t nR, int32_t *__restrict__ item_row) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nR; i += gridDim.x * blockDim.x)
+    for (int32_t it = items[i]; it < items[i + 1]; ++it) item_row[it] = i;
 }
 
 // zero the rows of several chunks (and rows without edges) before k_agg
@@ -409,6 +431,10 @@ static int grid_for(int64_t work, int per_block, int cap = 4096) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
 
+void region_item_rows(const int32_t *items, int32_t nR, int32_t *item_row, hipStream_t st) {
+  if (nR > 0) hipLaunchKernelGGL(k_item_rows, dim3(grid_for(nR, GB, 4096)), dim3(GB), 0, st, items, nR, item_row);
+}
+
 #define GNN_TRY(x)                   \
   do {                               \
     hipError_t e_ = (x);             \
@@ -449,6 +475,7 @@ hipError_t net_alloc(Net &n, int S, int64_t max_rows) {
   GNN_TRY(dalloc(&n.dout, max_rows));
   n.part_cap = NET_PART_CAP;
   GNN_TRY(dalloc(&n.part, n.part_cap));
+  GNN_TRY(dalloc(&n.part2, n.part_cap / RED_GROUP + HID * HID));
   GNN_TRY(dalloc(&n.loss_part, 4096));
   GNN_TRY(dalloc(&n.loss, 1));
   GNN_TRY(dalloc(&n.active, 64));
@@ -506,6 +533,7 @@ size_t net_view(Net &n, int S, int64_t max_rows, void *base, size_t bytes, int64
   // rows (the same partition as an allocated network uses for these rows)
   n.part_cap = part_cap > 0 ? part_cap : std::max<int64_t>(1, (max_rows + 127) / 128) * HID * HID;
   take(&n.part, n.part_cap);
+  take(&n.part2, n.part_cap / RED_GROUP + HID * HID);
   take(&n.loss_part, 4096);
   take(&n.loss, 1);
   take(&n.active, 64);
@@ -519,7 +547,7 @@ size_t net_view(Net &n, int S, int64_t max_rows, void *base, size_t bytes, int64
 
 void net_free(Net &n) {
   void *ps[] = {n.theta, n.grad, n.m1, n.m2, n.wb.fwd, n.wb.bwd, n.F, n.m, n.o, n.t, n.dh, n.dz, n.da, n.dm,
-                n.dout, n.part, n.loss_part, n.loss, n.active, n.mask};
+                n.dout, n.part, n.part2, n.loss_part, n.loss, n.active, n.mask};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   for (int l = 0; l <= LAYERS; ++l)
@@ -588,16 +616,19 @@ void net_loss(Net &n, int64_t rows, int n_active, hipStream_t st) {
 
 template <int K, int N>
 static void wgrad(Net &n, int64_t rows, const float *X, const float *D, float *out, hipStream_t st) {
-  const int nb = (int)std::min<int64_t>(std::max<int64_t>(1, (rows + 127) / 128), n.part_cap / (K * N));
+  // one partial per wavefront, GB / WAVE wavefronts per workgroup
+  constexpr int WPB = GB / WAVE;
+  const int64_t waves = std::min<int64_t>(std::max<int64_t>(1, (rows + 127) / 128), n.part_cap / (K * N));
+  const int nb = (int)std::max<int64_t>(1, waves / WPB);
   hipLaunchKernelGGL((k_wgrad<K, N>), dim3(nb), dim3(GB), 0, st, rows, X, D, n.part);
-  hipLaunchKernelGGL(k_reduce_part, dim3((K * N + GB - 1) / GB), dim3(GB), 0, st, n.part, nb, K * N, out);
+  reduce_part(n, n.part, nb * WPB, K * N, out, st);
 }
 
 template <int N, int MODE>
 static void colsum(Net &n, int64_t rows, const float *A, const float *wv, float *out, hipStream_t st) {
   const int nb = (int)std::min<int64_t>(std::max<int64_t>(1, (rows + 255) / 256), 1024);
   hipLaunchKernelGGL((k_colsum<N, MODE>), dim3(nb), dim3(GB), 0, st, rows, A, wv, n.part);
-  hipLaunchKernelGGL(k_reduce_part, dim3((N + GB - 1) / GB), dim3(GB), 0, st, n.part, nb, N, out);
+  reduce_part(n, n.part, nb, N, out, st);
 }
 
 void net_backward(Net &n, const RegionView &g, int64_t rows, hipStream_t st) {

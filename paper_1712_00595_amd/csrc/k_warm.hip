@@ -10,6 +10,7 @@
 // update and is zero otherwise.
 #include <hipcub/hipcub.hpp>
 
+#include "gnn.h"
 #include "rwr_common.h"
 #include "rwr_kernels.h"
 #include "warm.h"
@@ -37,22 +38,88 @@ __global__ void k_ws_level_flags(const int32_t *__restrict__ stamp, int32_t st, 
   }
 }
 
-// one wavefront per node of level h - 1: mark unvisited out-neighbours h + 1
-__global__ void k_ws_expand(const int32_t *__restrict__ list, int32_t cnt, DevGraphView out, int32_t h,
-                            int32_t *__restrict__ hop1) {
+// Region levels on the device.  lv[0] = region nodes so far (nR), lv[1] = 1
+// once the search has stopped (a level came out empty or would pass the
+// capacity), lv[2 + h] = end of level h in R (-1 while not accepted).  The
+// rows of a list (a level, or the whole region) are cut into WS_ROW_CHUNK-edge
+// items, one wavefront each, so that rows of hubs spread over the chip.
+#define WS_ROW_CHUNK 1024
+
+struct ListRef {
+  const int32_t *R;
+  const int32_t *lv;
+  int level;  // level of R to take; -1: the whole region
+  __device__ __forceinline__ int32_t start() const { return level <= 0 ? 0 : lv[2 + level - 1]; }
+  __device__ __forceinline__ int32_t end() const {
+    if (level < 0) return lv[0];
+    const int32_t e = lv[2 + level];
+    return e < 0 ? start() : e;
+  }
+};
+
+// tmp[i] = items of row i of the list (0 past its end), i <= cap
+__global__ void k_ws_row_chunks(ListRef L, int32_t cap, DevGraphView gv, int32_t *__restrict__ tmp) {
+  const int32_t b = L.start(), k = L.end() - b;
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= cap; i += gridDim.x * blockDim.x)
+    tmp[i] = i < k ? (gv.len[L.R[b + i]] + WS_ROW_CHUNK - 1) / WS_ROW_CHUNK : 0;
+}
+
+__global__ void k_ws_item_rows(ListRef L, const int32_t *__restrict__ rit, int32_t *__restrict__ irow) {
+  const int32_t k = L.end() - L.start();
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x)
+    for (int32_t it = rit[i]; it < rit[i + 1]; ++it) irow[it] = i;
+}
+
+// mark the unvisited out-neighbours of level h - 1 with h + 1
+__global__ void k_ws_expand(ListRef L, const int32_t *__restrict__ rit, const int32_t *__restrict__ irow,
+                            DevGraphView out, int32_t h, int32_t *__restrict__ hop1) {
+  if (L.lv[1]) return;
+  const int32_t b = L.start(), k = L.end() - b;
+  const int32_t total = rit[k];
   const int lane = threadIdx.x % RWR_WAVE;
-  for (int w = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; w < cnt; w += gridDim.x * blockDim.x / RWR_WAVE) {
-    const int u = list[w];
+  for (int32_t it = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; it < total;
+       it += gridDim.x * blockDim.x / RWR_WAVE) {
+    const int32_t i = irow[it];
+    const int u = L.R[b + i];
     const int o = out.off[u], d = out.len[u];
-    for (int e = lane; e < d; e += RWR_WAVE) {
+    const int e1 = min(d, (it - rit[i] + 1) * WS_ROW_CHUNK);
+    for (int e = (it - rit[i]) * WS_ROW_CHUNK + lane; e < e1; e += RWR_WAVE) {
       const int v = out.adj[o + e];
       if (hop1[v] == 0) hop1[v] = h + 1;  // every writer stores the same value
     }
   }
 }
 
-__global__ void k_ws_unmark(const int32_t *__restrict__ list, int32_t cnt, int32_t *__restrict__ hop1) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) hop1[list[i]] = 0;
+// level h (k = *kcnt nodes in wlist) joins the region unless the search has
+// stopped or it would pass the capacity (then its marks are removed)
+__global__ void k_ws_append(const int32_t *__restrict__ wlist, const int32_t *__restrict__ kcnt,
+                            int32_t *__restrict__ R, const int32_t *__restrict__ lv, int32_t max_nodes,
+                            int32_t *__restrict__ hop1) {
+  if (lv[1]) return;
+  const int32_t k = *kcnt, nR = lv[0];
+  const bool fits = (int64_t)nR + k <= max_nodes;
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    if (fits)
+      R[nR + i] = wlist[i];
+    else
+      hop1[wlist[i]] = 0;
+  }
+}
+
+__global__ void k_ws_append_fin(const int32_t *__restrict__ kcnt, int32_t *__restrict__ lv, int32_t h,
+                                int32_t max_nodes) {
+  if (lv[1]) return;
+  const int32_t k = *kcnt, nR = lv[0];
+  if (k == 0 || (int64_t)nR + k > max_nodes) {
+    lv[1] = 1;
+    return;
+  }
+  lv[0] = nR + k;
+  lv[2 + h] = nR + k;
+}
+
+__global__ void k_ws_lv_init(int32_t *__restrict__ lv, int32_t n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lv[i] = i < 2 ? 0 : -1;
 }
 
 __global__ void k_ws_loc(const int32_t *__restrict__ R, int32_t nR, const DevGraphView out,
@@ -76,32 +143,56 @@ __global__ void k_ws_clear(const int32_t *__restrict__ R, int32_t nR, int32_t *_
 // ------------------------------------------------------------ local region graph
 // The region's own edges in local ids, so that the network's aggregations
 // touch only them: rows of the region nodes in one orientation of the device
-// graph, filtered to neighbours inside the region, in row order.
-// One wavefront per region node.
-__global__ void k_ws_count_local(const int32_t *__restrict__ R, int32_t nR, DevGraphView gv,
-                                 const int32_t *__restrict__ loc1, int32_t *__restrict__ cnt) {
+// graph, filtered to neighbours inside the region, in row order.  Row items
+// (see ListRef) count their neighbours inside the region; the exclusive sum
+// of the item counts places each item's entries, so a row's entries follow
+// its edge order.
+__global__ void k_ws_count_items(ListRef L, const int32_t *__restrict__ rit, const int32_t *__restrict__ irow,
+                                 int32_t max_items, DevGraphView gv, const int32_t *__restrict__ loc1,
+                                 int32_t *__restrict__ icnt) {
+  const int32_t b = L.start(), k = L.end() - b;
+  const int32_t total = rit[k];
   const int lane = threadIdx.x % RWR_WAVE;
-  for (int w = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; w < nR; w += gridDim.x * blockDim.x / RWR_WAVE) {
-    const int v = R[w];
-    const int o = gv.off[v], d = gv.len[v];
+  for (int32_t it = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; it <= max_items;
+       it += gridDim.x * blockDim.x / RWR_WAVE) {
     int c = 0;
-    for (int e = lane; e < d; e += RWR_WAVE) c += loc1[gv.adj[o + e]] > 0;
-    for (int off = 1; off < RWR_WAVE; off <<= 1) c += __shfl_xor(c, off, RWR_WAVE);
-    if (lane == 0) cnt[w] = c;
+    if (it < total) {
+      const int32_t i = irow[it];
+      const int v = L.R[b + i];
+      const int o = gv.off[v], d = gv.len[v];
+      const int e1 = min(d, (it - rit[i] + 1) * WS_ROW_CHUNK);
+      for (int e = (it - rit[i]) * WS_ROW_CHUNK + lane; e < e1; e += RWR_WAVE) c += loc1[gv.adj[o + e]] > 0;
+      for (int off = 1; off < RWR_WAVE; off <<= 1) c += __shfl_xor(c, off, RWR_WAVE);
+    }
+    if (lane == 0) icnt[it] = c;
   }
 }
 
-__global__ void k_ws_fill_local(const int32_t *__restrict__ R, int32_t nR, DevGraphView gv,
-                                const int32_t *__restrict__ loc1, const int32_t *__restrict__ off,
+// off[i] (nR + 1 entries) and cnt[i] of each row from the item offsets
+__global__ void k_ws_row_off(const int32_t *__restrict__ rit, const int32_t *__restrict__ ioff, int32_t nR,
+                             int32_t *__restrict__ off, int32_t *__restrict__ cnt) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= nR; i += gridDim.x * blockDim.x) {
+    off[i] = ioff[rit[i]];
+    if (i < nR) cnt[i] = ioff[rit[i + 1]] - ioff[rit[i]];
+  }
+}
+
+__global__ void k_ws_fill_items(ListRef L, const int32_t *__restrict__ rit, const int32_t *__restrict__ irow,
+                                DevGraphView gv, const int32_t *__restrict__ loc1, const int32_t *__restrict__ ioff,
                                 int32_t *__restrict__ adj) {
+  const int32_t b = L.start(), k = L.end() - b;
+  const int32_t total = rit[k];
   const int lane = threadIdx.x % RWR_WAVE;
-  for (int w = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; w < nR; w += gridDim.x * blockDim.x / RWR_WAVE) {
-    const int v = R[w];
+  for (int32_t it = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; it < total;
+       it += gridDim.x * blockDim.x / RWR_WAVE) {
+    const int32_t i = irow[it];
+    const int v = L.R[b + i];
     const int o = gv.off[v], d = gv.len[v];
-    int base = off[w];
-    for (int e0 = 0; e0 < d; e0 += RWR_WAVE) {
-      const int e = e0 + lane;
-      const int l = e < d ? loc1[gv.adj[o + e]] : 0;
+    const int e0 = (it - rit[i]) * WS_ROW_CHUNK, e1 = min(d, e0 + WS_ROW_CHUNK);
+    int base = ioff[it];
+    for (int eb = e0; eb < e1; eb += RWR_WAVE) {
+      const int e = eb + lane;
+      const int l = e < e1 ? loc1[gv.adj[o + e]] : 0;
       const uint64_t m = __ballot(l > 0);
       if (l > 0) adj[base + __popcll(m & lanemask_below(lane))] = l - 1;
       base += __popcll(m);
@@ -133,13 +224,22 @@ __global__ __launch_bounds__(WB) void k_ws_qnorm(const int32_t *__restrict__ R, 
   }
 }
 
-// out[j] = sum over b of part[b * S + j]
-__global__ void k_ws_sum_parts(const double *__restrict__ part, int nb, int S, double *__restrict__ out) {
-  const int j = threadIdx.x;
-  if (j >= S) return;
+// out[j] = sum over b of part[b * S + j] (S entries per partial), one
+// workgroup per entry: thread t sums partials t, t + WB, ..., then the thread
+// sums are added in thread order
+__global__ __launch_bounds__(WB) void k_ws_sum_parts(const double *__restrict__ part, int nb, int S,
+                                                     double *__restrict__ out) {
+  __shared__ double red[WB];
+  const int j = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * S + j];
-  out[j] = s;
+  for (int b = threadIdx.x; b < nb; b += WB) s += part[(int64_t)b * S + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < WB; ++q) t += red[q];
+    out[j] = t;
+  }
 }
 
 // The sixteen inputs of a (node, column) row; see warm.h for the list.
@@ -235,23 +335,40 @@ __global__ __launch_bounds__(WB) void k_ws_mass(const int32_t *__restrict__ R, i
   }
 }
 
-// beta[j] from the partials (fixed order) and sum(q) = qn[S + j]; fa[j] =
-// f(|xhat_j|), which the gradient through the correction needs
-__global__ void k_ws_beta(const double *__restrict__ part, int nb, int S, double c1, const double *__restrict__ qn,
-                          double *__restrict__ beta, double *__restrict__ fabs_out) {
-  const int j = threadIdx.x;
-  if (j >= S) return;
+// beta[j] from the partials and sum(q) = qn[S + j]; fa[j] = f(|xhat_j|),
+// which the gradient through the correction needs.  One workgroup per
+// column; fixed order (thread t takes partials t, t + WB, ..., then the
+// thread sums in thread order).
+__global__ __launch_bounds__(WB) void k_ws_beta(const double *__restrict__ part, int nb, int S, double c1,
+                                                const double *__restrict__ qn, double *__restrict__ beta,
+                                                double *__restrict__ fabs_out) {
+  __shared__ double red[4][WB];
+  const int j = blockIdx.x;
   double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
-  for (int k = 0; k < nb; ++k) {
+  for (int k = threadIdx.x; k < nb; k += WB) {
     const double *p = part + (int64_t)k * 4 * S;
     a += p[j];
     b += p[S + j];
     c += p[2 * S + j];
     d += p[3 * S + j];
   }
-  const double fx = a - c1 * b, fa = c - c1 * d;
-  beta[j] = fa > 0.0 ? (fx - qn[S + j]) / fa : 0.0;
-  fabs_out[j] = fa;
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  red[2][threadIdx.x] = c;
+  red[3][threadIdx.x] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = b = c = d = 0.0;
+    for (int q = 0; q < WB; ++q) {
+      a += red[0][q];
+      b += red[1][q];
+      c += red[2][q];
+      d += red[3][q];
+    }
+    const double fx = a - c1 * b, fa = c - c1 * d;
+    beta[j] = fa > 0.0 ? (fx - qn[S + j]) / fa : 0.0;
+    fabs_out[j] = fa;
+  }
 }
 
 // xhat' = xhat - beta |xhat|, scattered into the dense vector w (rows R)
@@ -276,11 +393,12 @@ __global__ void k_ws_unscatter(const int32_t *__restrict__ R, int32_t nR, int S,
 }
 
 // rho = q + g over every node, where g = (1-c) B~^T xhat - xhat (gbuf):
-// rho replaces g in gbuf; partials of ||rho_j||_1 (entries j) and of the
-// sum of xhat_j (entries S + j)
+// rho replaces g in gbuf and its sign goes to sg (one byte per entry, what
+// the gradient gathers); partials of ||rho_j||_1 (entries j) and of the sum
+// of xhat_j (entries S + j)
 __global__ __launch_bounds__(WB) void k_ws_rho(int32_t n, int S, const double *__restrict__ ybuf,
                                                double *__restrict__ gbuf, const double *__restrict__ w,
-                                               double *__restrict__ part) {
+                                               int8_t *__restrict__ sg, double *__restrict__ part) {
   __shared__ double rn[WB], xs[WB];
   const int j = threadIdx.x % S, rl = threadIdx.x / S, RPB = WB / S;
   double a = 0.0, b = 0.0;
@@ -288,6 +406,7 @@ __global__ __launch_bounds__(WB) void k_ws_rho(int32_t n, int S, const double *_
     const int64_t kk = col_index(v, S, j);
     const double rho = ybuf[kk] + gbuf[kk];
     gbuf[kk] = rho;
+    sg[kk] = (int8_t)(rho > 0.0 ? 1 : (rho < 0.0 ? -1 : 0));
     a += fabs(rho);
     b += w[kk];
   }
@@ -353,31 +472,27 @@ __global__ void k_ws_grad_items(const int32_t *__restrict__ R, int32_t nR, DevGr
     items[i] = i < nR ? (out.len[R[i]] + GRAD_CHUNK - 1) / GRAD_CHUNK : 0;
 }
 
-// gpart[it * S + j] = sum of sign(rho(v, j)) over the out-edges u -> v of item it
+// gpart[it * S + j] = sum of sign(rho(v, j)) over the out-edges u -> v of
+// item it (sg: the signs, one byte each; the sums are integers, exact in
+// any order)
 template <int S>
 __global__ void k_ws_grad_sum(const int32_t *__restrict__ R, int32_t nR, DevGraphView out,
-                              const int32_t *__restrict__ item_off, const double *__restrict__ rho,
-                              double *__restrict__ gpart) {
+                              const int32_t *__restrict__ item_off, const int32_t *__restrict__ item_row,
+                              const int8_t *__restrict__ sg, double *__restrict__ gpart) {
   constexpr int PER = RWR_WAVE / S;
   const int lane = threadIdx.x % RWR_WAVE;
   const int j = lane % S, p = lane / S;
   const int32_t total = item_off[nR];
   for (int32_t it = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; it < total;
        it += gridDim.x * blockDim.x / RWR_WAVE) {
-    int32_t lo = 0, hi = nR - 1;
-    while (lo < hi) {
-      const int32_t mid = (lo + hi + 1) >> 1;
-      if (item_off[mid] <= it) lo = mid;
-      else hi = mid - 1;
-    }
-    const int32_t i = lo, k = it - item_off[i];
+    const int32_t i = item_row[it], k = it - item_off[i];
     const int u = R[i];
     const int o = out.off[u], d = out.len[u];
     const int e1 = min(d, (k + 1) * GRAD_CHUNK);
-    double t = 0.0;
-    for (int e = k * GRAD_CHUNK + p; e < e1; e += PER) t += sgn(rho[col_index(out.adj[o + e], S, j)]);
+    int t = 0;
+    for (int e = k * GRAD_CHUNK + p; e < e1; e += PER) t += sg[col_index(out.adj[o + e], S, j)];
     for (int off = S; off < RWR_WAVE; off <<= 1) t += __shfl_xor(t, off, RWR_WAVE);
-    if (p == 0) gpart[(int64_t)it * S + j] = t;
+    if (p == 0) gpart[(int64_t)it * S + j] = (double)t;
   }
 }
 
@@ -416,19 +531,29 @@ __global__ __launch_bounds__(WB) void k_ws_grad_fixed(const int32_t *__restrict_
   }
 }
 
-// dL/do through the correction: dout = (1 - beta s)(d - w ||q|| K / f)
-__global__ void k_ws_grad_corr(const int32_t *__restrict__ R, int32_t nR, int S, DevGraphView out, double c1,
-                               const double *__restrict__ kpart, int nb, const double *__restrict__ qn,
-                               const double *__restrict__ beta, const double *__restrict__ fa,
-                               const float *__restrict__ o, float *__restrict__ dout) {
-  __shared__ double corr[RWR_MAX_COLS];
-  if (threadIdx.x < S) {
-    const int j = threadIdx.x;
+// corr[j] = ||q_j|| K_j / f_j, K_j from its partials (one workgroup per column,
+// fixed order as in k_ws_sum_parts)
+__global__ __launch_bounds__(WB) void k_ws_corr(const double *__restrict__ kpart, int nb, int S,
+                                                const double *__restrict__ qn, const double *__restrict__ fa,
+                                                double *__restrict__ corr) {
+  __shared__ double red[WB];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += WB) s += kpart[(int64_t)b * S + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
     double K = 0.0;
-    for (int b = 0; b < nb; ++b) K += kpart[(int64_t)b * S + j];
+    for (int q = 0; q < WB; ++q) K += red[q];
     corr[j] = fa[j] > 0.0 ? qn[j] * K / fa[j] : 0.0;
   }
-  __syncthreads();
+}
+
+// dL/do through the correction: dout = (1 - beta s)(d - w ||q|| K / f)
+__global__ void k_ws_grad_corr(const int32_t *__restrict__ R, int32_t nR, int S, DevGraphView out, double c1,
+                               const double *__restrict__ corr, const double *__restrict__ beta,
+                               const double *__restrict__ fa, const float *__restrict__ o,
+                               float *__restrict__ dout) {
   const int64_t rows = (int64_t)nR * S;
   for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < rows;
        row += (int64_t)gridDim.x * blockDim.x) {
@@ -445,11 +570,6 @@ static int wgrid(int64_t work, int cap = 4096) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((work + WB - 1) / WB, cap));
 }
 
-void ws_level_flags(const int32_t *stamp, int32_t st, int32_t n, int32_t h, int32_t *hop1, int32_t *flags,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(k_ws_level_flags, dim3(wgrid(n)), dim3(WB), 0, s, stamp, st, n, h, hop1, flags);
-}
-
 size_t ws_select_temp_bytes(int32_t n) {
   size_t bytes = 0;
   (void)hipcub::DeviceSelect::Flagged(nullptr, bytes, hipcub::CountingInputIterator<int32_t>(0), (const int32_t *)nullptr,
@@ -463,14 +583,56 @@ hipError_t ws_select(const int32_t *flags, int32_t n, int32_t *out, int32_t *cou
                                        n, s);
 }
 
-void ws_expand(const int32_t *list, int32_t cnt, const DevGraphView &out, int32_t h, int32_t *hop1, hipStream_t s) {
-  if (cnt <= 0) return;
-  hipLaunchKernelGGL(k_ws_expand, dim3(wgrid((int64_t)cnt * RWR_WAVE)), dim3(WB), 0, s, list, cnt, out, h, hop1);
+
+int64_t ws_max_items(int32_t max_nodes, int64_t m) { return (int64_t)max_nodes + m / WS_ROW_CHUNK + 2; }
+
+static hipError_t row_items(const ListRef &L, int32_t cap, const DevGraphView &gv, int32_t *tmp, int32_t *rit,
+                            int32_t *irow, void *temp, size_t temp_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_row_chunks, dim3(wgrid((int64_t)cap + 1)), dim3(WB), 0, s, L, cap, gv, tmp);
+  hipError_t e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, tmp, rit, cap + 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ws_item_rows, dim3(wgrid(cap)), dim3(WB), 0, s, L, rit, irow);
+  return hipSuccess;
 }
 
-void ws_unmark(const int32_t *list, int32_t cnt, int32_t *hop1, hipStream_t s) {
-  if (cnt <= 0) return;
-  hipLaunchKernelGGL(k_ws_unmark, dim3(wgrid(cnt)), dim3(WB), 0, s, list, cnt, hop1);
+hipError_t ws_region(const int32_t *stamp, int32_t st, int32_t n, int32_t hops, int32_t max_nodes,
+                     const DevGraphView &out, int32_t *hop1, int32_t *flags, int32_t *wlist, int32_t *kcnt,
+                     int32_t *R, int32_t *lv, const WsItems &it, void *sel_temp, size_t sel_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_lv_init, dim3(1), dim3(64), 0, s, lv, 2 + WS_MAX_HOPS + 1);
+  for (int h = 0; h <= hops; ++h) {
+    if (h > 0) {
+      const ListRef L{R, lv, h - 1};
+      hipError_t e = row_items(L, max_nodes, out, it.tmp, it.rit, it.irow, it.scan_temp, it.scan_bytes, s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_ws_expand, dim3(1024), dim3(WB), 0, s, L, it.rit, it.irow, out, h, hop1);
+    }
+    hipLaunchKernelGGL(k_ws_level_flags, dim3(wgrid(n)), dim3(WB), 0, s, stamp, st, n, h, hop1, flags);
+    hipError_t e = ws_select(flags, n, wlist, kcnt, sel_temp, sel_bytes, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ws_append, dim3(wgrid(max_nodes)), dim3(WB), 0, s, wlist, kcnt, R, lv, max_nodes, hop1);
+    hipLaunchKernelGGL(k_ws_append_fin, dim3(1), dim3(1), 0, s, kcnt, lv, h, max_nodes);
+  }
+  return hipSuccess;
+}
+
+hipError_t ws_local_rows(const int32_t *R, const int32_t *lv, int32_t nR, const DevGraphView &gv,
+                         const int32_t *loc1, const WsItems &it, int32_t *cnt, int32_t *off, hipStream_t s) {
+  const ListRef L{R, lv, -1};
+  hipError_t e = row_items(L, nR, gv, it.tmp, it.rit, it.irow, it.scan_temp, it.scan_bytes, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ws_count_items, dim3(1024), dim3(WB), 0, s, L, it.rit, it.irow, it.max_items, gv, loc1,
+                     it.icnt);
+  size_t bytes = it.scan_bytes;
+  e = hipcub::DeviceScan::ExclusiveSum(it.scan_temp, bytes, it.icnt, it.ioff, it.max_items + 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ws_row_off, dim3(wgrid((int64_t)nR + 1)), dim3(WB), 0, s, it.rit, it.ioff, nR, off, cnt);
+  return hipSuccess;
+}
+
+void ws_local_fill(const int32_t *R, const int32_t *lv, const DevGraphView &gv, const int32_t *loc1,
+                   const WsItems &it, int32_t *adj, hipStream_t s) {
+  const ListRef L{R, lv, -1};
+  hipLaunchKernelGGL(k_ws_fill_items, dim3(1024), dim3(WB), 0, s, L, it.rit, it.irow, gv, loc1, it.ioff, adj);
 }
 
 size_t ws_scan_temp_bytes(int32_t n) {
@@ -479,14 +641,6 @@ size_t ws_scan_temp_bytes(int32_t n) {
   return bytes;
 }
 
-hipError_t ws_local_rows(const int32_t *R, int32_t nR, const DevGraphView &gv, const int32_t *loc1, int32_t *cnt,
-                         int32_t *off, void *temp, size_t temp_bytes, hipStream_t s) {
-  hipLaunchKernelGGL(k_ws_count_local, dim3(wgrid((int64_t)nR * RWR_WAVE)), dim3(WB), 0, s, R, nR, gv, loc1, cnt);
-  // cnt[nR] is 0, so off[nR] is the total
-  hipError_t e = hipMemsetAsync(cnt + nR, 0, sizeof(int32_t), s);
-  if (e != hipSuccess) return e;
-  return hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, cnt, off, nR + 1, s);
-}
 
 __global__ void k_ws_chunks(const int32_t *__restrict__ cnt, int32_t nR, int32_t chunk, int32_t *__restrict__ items) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= nR; i += gridDim.x * blockDim.x)
@@ -499,10 +653,6 @@ hipError_t ws_chunk_items(const int32_t *cnt, int32_t nR, int32_t chunk, int32_t
   return hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, tmp, items, nR + 1, s);
 }
 
-void ws_local_fill(const int32_t *R, int32_t nR, const DevGraphView &gv, const int32_t *loc1, const int32_t *off,
-                   int32_t *adj, hipStream_t s) {
-  hipLaunchKernelGGL(k_ws_fill_local, dim3(wgrid((int64_t)nR * RWR_WAVE)), dim3(WB), 0, s, R, nR, gv, loc1, off, adj);
-}
 
 void ws_loc(const int32_t *R, int32_t nR, const DevGraphView &out, int32_t *loc1, float *dinv, hipStream_t s) {
   hipLaunchKernelGGL(k_ws_loc, dim3(wgrid(nR)), dim3(WB), 0, s, R, nR, out, loc1, dinv);
@@ -516,7 +666,7 @@ void ws_clear(const int32_t *R, int32_t nR, int32_t *hop1, int32_t *loc1, hipStr
 void ws_qnorm(const int32_t *R, int32_t n0, int S, const double *ybuf, double *part, double *qn, hipStream_t s) {
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)n0 * S + WB - 1) / WB, 1024));
   hipLaunchKernelGGL(k_ws_qnorm, dim3(nb), dim3(WB), 0, s, R, n0, S, ybuf, part);
-  hipLaunchKernelGGL(k_ws_sum_parts, dim3(1), dim3(128), 0, s, part, nb, 2 * S, qn);
+  hipLaunchKernelGGL(k_ws_sum_parts, dim3(2 * S), dim3(WB), 0, s, part, nb, 2 * S, qn);
 }
 
 void ws_features(const int32_t *R, int32_t nR, int S, const int32_t *hop1, const DevGraphView &in,
@@ -532,7 +682,7 @@ void ws_predict(const int32_t *R, int32_t nR, int S, const DevGraphView &out, co
   hipLaunchKernelGGL(k_ws_predict, dim3(g), dim3(WB), 0, s, nR, S, o, qn, xhat);
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)nR * S + WB - 1) / WB, 512));
   hipLaunchKernelGGL(k_ws_mass, dim3(nb), dim3(WB), 0, s, R, nR, S, out, xhat, part);
-  hipLaunchKernelGGL(k_ws_beta, dim3(1), dim3(64), 0, s, part, nb, S, c1, qn, beta, fa);
+  hipLaunchKernelGGL(k_ws_beta, dim3(S), dim3(WB), 0, s, part, nb, S, c1, qn, beta, fa);
   hipLaunchKernelGGL(k_ws_adjust_scatter, dim3(g), dim3(WB), 0, s, R, nR, S, beta, xhat, w);
 }
 
@@ -541,11 +691,11 @@ void ws_unscatter(const int32_t *R, int32_t nR, int S, double *w, hipStream_t s)
   hipLaunchKernelGGL(k_ws_unscatter, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, R, nR, S, w);
 }
 
-void ws_rho(int32_t n, int S, const double *ybuf, double *gbuf, const double *w, double *part, double *sums,
-            hipStream_t s) {
+void ws_rho(int32_t n, int S, const double *ybuf, double *gbuf, const double *w, int8_t *sg, double *part,
+            double *sums, hipStream_t s) {
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)n * S + WB - 1) / WB, 1024));
-  hipLaunchKernelGGL(k_ws_rho, dim3(nb), dim3(WB), 0, s, n, S, ybuf, gbuf, w, part);
-  hipLaunchKernelGGL(k_ws_sum_parts, dim3(1), dim3(128), 0, s, part, nb, 2 * S, sums);
+  hipLaunchKernelGGL(k_ws_rho, dim3(nb), dim3(WB), 0, s, n, S, ybuf, gbuf, w, sg, part);
+  hipLaunchKernelGGL(k_ws_sum_parts, dim3(2 * S), dim3(WB), 0, s, part, nb, 2 * S, sums);
 }
 
 void ws_apply(int32_t n, int S, uint64_t accept, double *ybuf, const double *gbuf, double *r, const double *w,
@@ -558,16 +708,19 @@ void ws_apply(int32_t n, int S, uint64_t accept, double *ybuf, const double *gbu
 }
 
 hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *rho,
-                         double *gpart, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
-                         const int32_t *active, double q_active, const float *o, const double *qn,
-                         const double *beta, const double *fa, double *kpart, float *dout, hipStream_t s) {
+                         const int8_t *sg, double *gpart, int32_t *items, int32_t *item_off, int32_t *item_row,
+                         void *temp,
+                         size_t temp_bytes, const int32_t *active, double q_active, const float *o, const double *qn,
+                         const double *beta, const double *fa, double *kpart, double *corr, float *dout,
+                         hipStream_t s) {
   hipLaunchKernelGGL(k_ws_grad_items, dim3(wgrid((int64_t)nR + 1)), dim3(WB), 0, s, R, nR, out, items);
   hipError_t e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, items, item_off, nR + 1, s);
   if (e != hipSuccess) return e;
+  gnn::region_item_rows(item_off, nR, item_row, s);
   switch (S) {
 #define WS_GRAD(SS)                                                                                              \
   case SS:                                                                                                       \
-    hipLaunchKernelGGL(k_ws_grad_sum<SS>, dim3(1024), dim3(WB), 0, s, R, nR, out, item_off, rho, gpart);         \
+    hipLaunchKernelGGL(k_ws_grad_sum<SS>, dim3(1024), dim3(WB), 0, s, R, nR, out, item_off, item_row, sg, gpart); \
     break;
     WS_GRAD(1)
     WS_GRAD(2)
@@ -584,7 +737,8 @@ hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)nR * S + WB - 1) / WB, WS_KPART_BLOCKS));
   hipLaunchKernelGGL(k_ws_grad_fixed, dim3(nb), dim3(WB), 0, s, R, nR, S, out, c1, rho, gpart, item_off, active, qn,
                      inv, o, dout, kpart);
-  hipLaunchKernelGGL(k_ws_grad_corr, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, R, nR, S, out, c1, kpart, nb, qn,
-                     beta, fa, o, dout);
+  hipLaunchKernelGGL(k_ws_corr, dim3(S), dim3(WB), 0, s, kpart, nb, S, qn, fa, corr);
+  hipLaunchKernelGGL(k_ws_grad_corr, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, R, nR, S, out, c1, corr, beta, fa,
+                     o, dout);
   return hipSuccess;
 }

@@ -17,23 +17,42 @@
 #include "rwr_common.h"
 #include "rwr_kernels.h"
 
-void ws_level_flags(const int32_t *stamp, int32_t st, int32_t n, int32_t h, int32_t *hop1, int32_t *flags,
-                    hipStream_t s);
 size_t ws_select_temp_bytes(int32_t n);
 // out = indices v < n with flags[v] != 0, in increasing order; *count (device) their number
 hipError_t ws_select(const int32_t *flags, int32_t n, int32_t *out, int32_t *count, void *temp, size_t temp_bytes,
                      hipStream_t s);
-void ws_expand(const int32_t *list, int32_t cnt, const DevGraphView &out, int32_t h, int32_t *hop1, hipStream_t s);
-void ws_unmark(const int32_t *list, int32_t cnt, int32_t *hop1, hipStream_t s);
 void ws_loc(const int32_t *R, int32_t nR, const DevGraphView &out, int32_t *loc1, float *dinv, hipStream_t s);
-// Local rows of the region in orientation gv: cnt[i] = neighbours of R[i]
-// inside the region (cnt has nR + 1 entries), off = exclusive prefix sum
-// (off[nR] = total); then the rows themselves in local ids.
 size_t ws_scan_temp_bytes(int32_t n);
-hipError_t ws_local_rows(const int32_t *R, int32_t nR, const DevGraphView &gv, const int32_t *loc1, int32_t *cnt,
-                         int32_t *off, void *temp, size_t temp_bytes, hipStream_t s);
-void ws_local_fill(const int32_t *R, int32_t nR, const DevGraphView &gv, const int32_t *loc1, const int32_t *off,
-                   int32_t *adj, hipStream_t s);
+
+// Rows of a node list cut into fixed-size edge items (one wavefront each):
+// tmp and rit hold max_nodes + 1 ints, irow, icnt and ioff max_items + 1;
+// scan_temp covers an exclusive sum of max(max_nodes, max_items) + 1 ints.
+#define WS_MAX_HOPS 8
+struct WsItems {
+  int32_t *tmp, *rit, *irow, *icnt, *ioff;
+  int32_t max_items;
+  void *scan_temp;
+  size_t scan_bytes;
+};
+// items needed for rows of up to max_nodes nodes in a graph of m stored edges
+int64_t ws_max_items(int32_t max_nodes, int64_t m);
+// The region on the device: level 0 = the stamped offset support, level h =
+// unvisited out-neighbours of level h - 1 (h <= hops), each level in
+// increasing node order, a level that would pass max_nodes left out and the
+// search stopped there.  R holds the nodes level by level; lv (2 + hops + 1
+// ints) receives lv[0] = |R|, lv[1] = 1 once stopped, lv[2 + h] = end of level
+// h in R (-1 for levels not taken).  hop1 marks the nodes taken.
+hipError_t ws_region(const int32_t *stamp, int32_t st, int32_t n, int32_t hops, int32_t max_nodes,
+                     const DevGraphView &out, int32_t *hop1, int32_t *flags, int32_t *wlist, int32_t *kcnt,
+                     int32_t *R, int32_t *lv, const WsItems &it, void *sel_temp, size_t sel_bytes, hipStream_t s);
+// Local rows of the region (nR = lv[0] nodes, known to the caller) in
+// orientation gv: cnt[i] = neighbours of R[i] inside the region, off =
+// exclusive prefix (nR + 1 entries, off[nR] = total); then (ws_local_fill,
+// with the same items, before they are reused) the rows in local ids.
+hipError_t ws_local_rows(const int32_t *R, const int32_t *lv, int32_t nR, const DevGraphView &gv,
+                         const int32_t *loc1, const WsItems &it, int32_t *cnt, int32_t *off, hipStream_t s);
+void ws_local_fill(const int32_t *R, const int32_t *lv, const DevGraphView &gv, const int32_t *loc1,
+                   const WsItems &it, int32_t *adj, hipStream_t s);
 // items = exclusive prefix of ceil(cnt[i] / chunk) (nR + 1 entries; tmp is
 // scratch of nR + 1 ints)
 hipError_t ws_chunk_items(const int32_t *cnt, int32_t nR, int32_t chunk, int32_t *tmp, int32_t *items, void *temp,
@@ -52,19 +71,22 @@ void ws_predict(const int32_t *R, int32_t nR, int S, const DevGraphView &out, co
                 double c1, double *xhat, double *w, double *part, double *beta, double *fa, hipStream_t s);
 void ws_unscatter(const int32_t *R, int32_t nR, int S, double *w, hipStream_t s);
 // gbuf holds g = (1-c) B~^T xhat - xhat on every node; rho = q + g replaces
-// it; sums[j] = ||rho_j||_1, sums[S + j] = sum of xhat_j
-void ws_rho(int32_t n, int S, const double *ybuf, double *gbuf, const double *w, double *part, double *sums,
-            hipStream_t s);
+// it and its signs go to sg (n * S bytes); sums[j] = ||rho_j||_1, sums[S + j]
+// = sum of xhat_j
+void ws_rho(int32_t n, int S, const double *ybuf, double *gbuf, const double *w, int8_t *sg, double *part,
+            double *sums, hipStream_t s);
 // accepted columns: ybuf = rho, r += xhat, sigma += sum xhat, stamps
 void ws_apply(int32_t n, int S, uint64_t accept, double *ybuf, const double *gbuf, double *r, const double *w,
               int32_t *stamp, Ctl *ctl, const double *xsum, hipStream_t s);
 // dL/do of the residual loss through the mass correction (see
 // k_ws_grad_fixed / k_ws_grad_corr) into dout (rows nR * S); gpart holds one
 // double per (gradient item, column): at least (nR + edges of the region's
-// out-rows / 1024 + 1) * S; kpart WS_KPART_BLOCKS * S doubles.  Fixed-order
-// sums only.
+// out-rows / 1024 + 1) * S, item_row as many ints as gpart has items;
+// kpart WS_KPART_BLOCKS * S doubles, corr S doubles.  Fixed-order sums only.
 #define WS_KPART_BLOCKS 1024
 hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *rho,
-                         double *gpart, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
-                         const int32_t *active, double q_active, const float *o, const double *qn,
-                         const double *beta, const double *fa, double *kpart, float *dout, hipStream_t s);
+                         const int8_t *sg, double *gpart, int32_t *items, int32_t *item_off, int32_t *item_row,
+                         void *temp,
+                         size_t temp_bytes, const int32_t *active, double q_active, const float *o, const double *qn,
+                         const double *beta, const double *fa, double *kpart, double *corr, float *dout,
+                         hipStream_t s);
