@@ -206,7 +206,10 @@ struct rwr_ctx {
     size_t scan_bytes = 0;
     float *dinv = nullptr;
     double *xhat = nullptr, *wbuf = nullptr, *qn = nullptr, *part = nullptr, *sums = nullptr;
-    int8_t *sg = nullptr;  // signs of the residual (n_cap * S)
+    int8_t *sg = nullptr;     // signs of the residual (n_cap * S)
+    double *pbuf = nullptr;   // the residual rho while it is formed (n_cap * S, zero at rest)
+    int32_t out_items = 0;    // 1024-edge items of the region's out-rows (last update)
+    bool pushed = false;      // the last update formed rho from the region alone
     void *temp = nullptr;
     size_t temp_bytes = 0;
     // this update
@@ -218,6 +221,7 @@ struct rwr_ctx {
     std::vector<double> qn_h;
     int32_t accepted = 0, fallback = 0;
     double ratio = 0.0, loss = 0.0, ms = 0.0;
+    int push_mode = -1;  // RWR_WS_PUSH: 0 pull, 1 push, unset: by the region's out-edges
   } ws;
 };
 
@@ -430,6 +434,7 @@ static void tune_defaults(rwr_ctx *c) {
   if (const char *e = getenv("RWR_HEAVY_FOLD")) c->fold_max = atoi(e);
   if (const char *e = getenv("RWR_CARRY")) c->carry_level = std::max(0, std::min(2, atoi(e)));
   if (const char *e = getenv("RWR_LOCKSTEP")) c->lockstep = atoi(e) != 0;
+  if (const char *e = getenv("RWR_WS_PUSH")) c->ws.push_mode = atoi(e) != 0 ? 1 : 0;
   if (const char *e = getenv("RWR_REFINE_TARGET")) {
     const double t = atof(e);
     if (t > 0.0 && t < 1.0) c->refine_target = t;
@@ -620,6 +625,7 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
     RWR_TRY(regrow((void **)&c->ws.flags, 4, 1));
     RWR_TRY(regrow((void **)&c->ws.wbuf, 8, c->S));
     RWR_TRY(regrow((void **)&c->ws.sg, 1, c->S));
+    RWR_TRY(regrow((void **)&c->ws.pbuf, 8, c->S));
     const size_t tb = ws_select_temp_bytes(new_cap);
     if (tb > c->ws.temp_bytes) {
       dev_free(c, c->ws.temp);
@@ -997,10 +1003,9 @@ static rwr_status check_and_refine(rwr_ctx *c, bool force, rwr_stats *st, double
     // a carried vector's bound is replaced by the next run's
     next = std::max(next, c->err_bound[j] - c->pend_b[j]);
   }
-  // the residual carry (updates only, not with the learned warm start, which
-  // uses the residual buffer itself): check now when the next update would
+  // the residual carry (updates only): check now when the next update would
   // likely pass the budget, and carry the residual into it
-  const bool carry = !force && c->carry_level >= 1 && !(c->ws.alloc && c->ws.mode != 0);
+  const bool carry = !force && c->carry_level >= 1;
   if (!force && worst <= c->budget && !(carry && c->tail_ema > 0.0 && next + c->tail_ema > c->budget))
     return RWR_OK;
   drop_carry(c);  // the residual supersedes the carried vectors
@@ -1123,6 +1128,7 @@ static void warm_free(rwr_ctx *c) {
   dev_free(c, w.xhat);
   dev_free(c, w.wbuf);
   dev_free(c, w.sg);
+  dev_free(c, w.pbuf);
   dev_free(c, w.qn);
   dev_free(c, w.part);
   dev_free(c, w.sums);
@@ -1167,6 +1173,7 @@ static rwr_status warm_alloc(rwr_ctx *c, int64_t max_rows) {
   RWR_TRY(alloc_zero(c, &w.flags, c->n_cap));
   RWR_TRY(alloc_zero(c, &w.wbuf, (size_t)c->n_cap * c->S));
   RWR_TRY(alloc_zero(c, &w.sg, (size_t)c->n_cap * c->S));
+  RWR_TRY(alloc_zero(c, &w.pbuf, (size_t)c->n_cap * c->S));
   RWR_TRY(alloc_zero(c, &w.R, w.max_nodes));
   RWR_TRY(alloc_zero(c, &w.lin_cnt, w.max_nodes + 1));
   RWR_TRY(alloc_zero(c, &w.lin_off, w.max_nodes + 1));
@@ -1279,15 +1286,17 @@ static rwr_status warm_local_graph(rwr_ctx *c) {
                             c->stream));
   HIP_TRY(c, ws_chunk_items(w.lout_cnt, w.nR, gnn::AGG_CHUNK, w.items, w.lout_items, w.scan_temp, w.scan_bytes,
                             c->stream));
-  int32_t tot[4] = {0, 0, 0, 0};
+  int32_t tot[5] = {0, 0, 0, 0, 0};
   HIP_TRY(c, hipMemcpyAsync(&tot[0], w.lin_off + w.nR, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(&tot[1], w.lout_off + w.nR, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(&tot[2], w.lin_items + w.nR, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(&tot[3], w.lout_items + w.nR, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&tot[4], B.rit + w.nR, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   const int32_t tin = tot[0], tout = tot[1];
   w.n_in_items = tot[2];
   w.n_out_items = tot[3];
+  w.out_items = tot[4];
   const int64_t need = std::max<int64_t>(std::max(tin, tout), 1);
   if (need > w.ladj_cap) {
     dev_free(c, w.lin_adj);
@@ -1357,16 +1366,38 @@ static rwr_status warm_prepare(rwr_ctx *c) {
   ws_qnorm(w.R, n0, S, c->ybuf, w.part, w.qn, c->stream);
   ws_features(w.R, nR, S, w.hop1, in, out, c->ybuf, c->r, c->ctl, c->seeds_d, w.qn, c->n, w.net.F, c->stream);
   gnn::net_forward(w.net, warm_view(c), rows, c->stream);
-  // prediction in wbuf (dense), (1-c) B~^T xhat - xhat in gbuf, rho = q + that
+  // prediction in wbuf (dense) and xhat (region rows)
   double *beta = w.sums + 2 * RWR_MAX_COLS;
   ws_predict(w.R, nR, S, out, w.net.o, w.qn, c1, w.xhat, w.wbuf, w.part, beta, w.fa, c->stream);
-  {
+  // work items over the region's out-rows (the push and the gradient)
+  const int64_t need = ((int64_t)nR + c->m / 1024 + 2) * S;
+  if (need > w.gpart_cap) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dev_free(c, w.gpart);
+    dev_free(c, w.grow);
+    w.gpart_cap = 0;
+    RWR_TRY(dev_alloc(c, (void **)&w.gpart, sizeof(double) * need));
+    RWR_TRY(dev_alloc(c, (void **)&w.grow, sizeof(int32_t) * (need / S)));
+    w.gpart_cap = need;
+  }
+  HIP_TRY(c, ws_out_items(w.R, nR, out, w.items, w.item_off, w.grow, w.scan_temp, w.scan_bytes, c->stream));
+  // rho = q - (I - (1-c) B~^T) xhat': from the region alone (a push over its
+  // out-rows) when those rows hold less than a quarter of the graph's edges,
+  // else by a pull over every in-row; the push adds with FP64 atomics, so
+  // deterministic mode always pulls
+  w.pushed = !c->det && (w.push_mode == 1 || (w.push_mode < 0 && (int64_t)w.out_items * 1024 * 4 < c->m));
+  // (rho lives in pbuf, so that carried vectors in gbuf stay untouched)
+  if (w.pushed) {
+    ws_rho_push(w.R, nR, S, out, w.item_off, w.grow, w.xhat, c1, w.pbuf, w.hop1, c->n, c->ybuf, w.wbuf, w.sg,
+                w.part, w.sums, c->stream);
+  } else {
     SlotArgs a = slot_args(c);
     a.r = w.wbuf;
+    a.gbuf = w.pbuf;
     a.zero_seed_rows = 0;
     launch_apply_p(a, S, c->stream);
+    ws_rho(c->n, S, c->ybuf, w.pbuf, w.wbuf, w.sg, w.part, w.sums, c->stream);
   }
-  ws_rho(c->n, S, c->ybuf, c->gbuf, w.wbuf, w.sg, w.part, w.sums, c->stream);
   std::vector<double> sums(2 * S);
   D2H(c, sums.data(), w.sums, sizeof(double) * 2 * S);
   w.qn_h.assign(S, 0.0);
@@ -1393,26 +1424,20 @@ static rwr_status warm_prepare(rwr_ctx *c) {
   if ((w.mode & 2) && n_act > 0) {
     w.loss = num / den;
     H2D(c, w.net.active, act.data(), sizeof(int32_t) * RWR_MAX_COLS);
-    // item partials of the gradient: at most one item per region row plus
-    // one per GRAD_CHUNK out-edges
-    const int64_t need = ((int64_t)nR + c->m / 1024 + 2) * S;
-    if (need > w.gpart_cap) {
-      HIP_TRY(c, hipStreamSynchronize(c->stream));
-      dev_free(c, w.gpart);
-      dev_free(c, w.grow);
-      w.gpart_cap = 0;
-      RWR_TRY(dev_alloc(c, (void **)&w.gpart, sizeof(double) * need));
-      RWR_TRY(dev_alloc(c, (void **)&w.grow, sizeof(int32_t) * (need / S)));
-      w.gpart_cap = need;
-    }
-    HIP_TRY(c, ws_resid_grad(w.R, nR, S, out, c1, c->gbuf, w.sg, w.gpart, w.items, w.item_off, w.grow, w.scan_temp,
+    HIP_TRY(c, ws_resid_grad(w.R, nR, S, out, c1, w.pbuf, w.sg, w.gpart, w.items, w.item_off, w.grow, w.scan_temp,
                              w.scan_bytes, w.net.active, den, w.net.o, w.qn, beta, w.fa, w.kpart,
                              w.sums + 3 * RWR_MAX_COLS, w.net.dout, c->stream));
     gnn::net_backward(w.net, warm_view(c), rows, c->stream);
     gnn::net_adamw(w.net, c->stream);
     w.trained = true;
   }
-  ws_apply(c->n, S, accept, c->ybuf, c->gbuf, c->r, w.wbuf, c->stamp, c->ctl, w.sums + S, c->stream);
+  if (w.pushed) {
+    ws_apply_sparse(c->n, S, accept, w.hop1, c->ybuf, w.pbuf, c->r, w.wbuf, c->stamp, c->ctl, w.sums + S,
+                    c->stream);
+    ws_unmark_boundary(c->n, w.hop1, c->stream);
+  } else {
+    ws_apply(c->n, S, accept, c->ybuf, w.pbuf, c->r, w.wbuf, c->stamp, c->ctl, w.sums + S, c->stream);
+  }
   ws_unscatter(w.R, nR, S, w.wbuf, c->stream);
   ws_clear(w.R, nR, w.hop1, w.loc1, c->stream);
   w.ms = now_ms() - t0;
@@ -2079,10 +2104,9 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   // a run that may leave its last iterate for the next update: its columns
   // retire together, so that every column leaves one (a column that stopped
   // earlier would otherwise spend its truncation bound)
-  const bool keep = c->carry_level >= 2 && !(c->ws.alloc && c->ws.mode != 0);
+  const bool keep = c->carry_level >= 2;
   launch_reset_run(c->ctl, c->S, all_cols_mask(c->n_seeds), c->cfg.eps, c->max_iters, dense_thresh(c),
                    c->n / 16 + 1, c->stream, 0, keep && c->lockstep ? 1 : 0);
-  if (warm) drop_carry(c);
   // carried vectors into gbuf (deferred last iterates unscaled with the
   // degrees before the batch; normally done at the end of the previous
   // update); the offset seed is that of r - p

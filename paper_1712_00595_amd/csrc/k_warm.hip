@@ -16,6 +16,8 @@
 #include "warm.h"
 
 #define WB 256
+// edges per work item over the region's out-rows (push and gradient)
+#define GRAD_CHUNK 1024
 
 __device__ __forceinline__ uint64_t lanemask_below(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
 
@@ -392,20 +394,20 @@ __global__ void k_ws_unscatter(const int32_t *__restrict__ R, int32_t nR, int S,
     w[col_index(R[row / S], S, (int)(row % S))] = 0.0;
 }
 
-// rho = q + g over every node, where g = (1-c) B~^T xhat - xhat (gbuf):
-// rho replaces g in gbuf and its sign goes to sg (one byte per entry, what
+// rho = q + g over every node, where g = (1-c) B~^T xhat - xhat (in pbuf):
+// rho replaces g in pbuf and its sign goes to sg (one byte per entry, what
 // the gradient gathers); partials of ||rho_j||_1 (entries j) and of the sum
 // of xhat_j (entries S + j)
 __global__ __launch_bounds__(WB) void k_ws_rho(int32_t n, int S, const double *__restrict__ ybuf,
-                                               double *__restrict__ gbuf, const double *__restrict__ w,
+                                               double *__restrict__ pbuf, const double *__restrict__ w,
                                                int8_t *__restrict__ sg, double *__restrict__ part) {
   __shared__ double rn[WB], xs[WB];
   const int j = threadIdx.x % S, rl = threadIdx.x / S, RPB = WB / S;
   double a = 0.0, b = 0.0;
   for (int v = blockIdx.x * RPB + rl; v < n; v += gridDim.x * RPB) {
     const int64_t kk = col_index(v, S, j);
-    const double rho = ybuf[kk] + gbuf[kk];
-    gbuf[kk] = rho;
+    const double rho = ybuf[kk] + pbuf[kk];
+    pbuf[kk] = rho;
     sg[kk] = (int8_t)(rho > 0.0 ? 1 : (rho < 0.0 ? -1 : 0));
     a += fabs(rho);
     b += w[kk];
@@ -423,16 +425,18 @@ __global__ __launch_bounds__(WB) void k_ws_rho(int32_t n, int S, const double *_
 
 // Accepted columns: the offset seed becomes rho and the scores take xhat;
 // nodes where an accepted rho is non-zero are stamped so that the first
-// propagation slot reads them (stamps are never removed here).
-__global__ void k_ws_apply(int32_t n, int S, uint64_t accept, double *__restrict__ ybuf,
-                           const double *__restrict__ gbuf, double *__restrict__ r, const double *__restrict__ w,
-                           int32_t *__restrict__ stamp, const Ctl *__restrict__ ctl) {
+// propagation slot reads them (stamps are never removed here).  pbuf (rho)
+// is cleared everywhere.
+__global__ void k_ws_apply(int32_t n, int S, uint64_t accept, double *__restrict__ ybuf, double *__restrict__ pbuf,
+                           double *__restrict__ r, const double *__restrict__ w, int32_t *__restrict__ stamp,
+                           const Ctl *__restrict__ ctl) {
   const int32_t st = ctl->stamp;
   const int64_t total = (int64_t)n * S;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int j = (int)(e % S);
+    const double rho = pbuf[e];
+    pbuf[e] = 0.0;
     if (!((accept >> j) & 1ull)) continue;
-    const double rho = gbuf[e];
     ybuf[e] = rho;
     r[e] += w[e];
     if (rho != 0.0) stamp[e / S] = st;  // every writer stores the same value
@@ -443,6 +447,96 @@ __global__ void k_ws_sigma(Ctl *ctl, int S, uint64_t accept, const double *__res
   const int j = threadIdx.x;
   if (j < S && ((accept >> j) & 1ull)) ctl->sigma[j] += xsum[j];
 }
+
+// ------------------------------------------------------------ sparse residual
+// For a region whose out-rows are a small part of the graph, rho is formed
+// from the region alone: pbuf = (1-c) B~^T xhat' by a push over the region's
+// out-rows (FP64 atomics into pbuf, which is zero at rest), and rho = q -
+// xhat' + pbuf on U = region + its out-neighbours, the only nodes where it
+// can be non-zero.  Out-neighbours outside the region are marked in hop1
+// with WS_BOUNDARY until the apply pass.
+#define WS_BOUNDARY (1 << 30)
+
+template <int S>
+__global__ void k_ws_push(const int32_t *__restrict__ R, DevGraphView out, const int32_t *__restrict__ item_off,
+                          const int32_t *__restrict__ item_row, const int32_t *__restrict__ nitems_p,
+                          const double *__restrict__ xhat, double c1, double *__restrict__ pbuf,
+                          int32_t *__restrict__ hop1) {
+  constexpr int PER = RWR_WAVE / S;
+  const int lane = threadIdx.x % RWR_WAVE;
+  const int j = lane % S, p = lane / S;
+  const int32_t total = *nitems_p;
+  for (int32_t it = (blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE; it < total;
+       it += gridDim.x * blockDim.x / RWR_WAVE) {
+    const int32_t i = item_row[it], k = it - item_off[i];
+    const int u = R[i];
+    const int o = out.off[u], d = out.len[u];
+    const double val = d ? c1 * xhat[(int64_t)i * S + j] / (double)d : 0.0;
+    if (__ballot(val != 0.0) == 0ull) continue;
+    const int e1 = min(d, (k + 1) * GRAD_CHUNK);
+    for (int e = k * GRAD_CHUNK + p; e < e1; e += PER) {
+      const int v = out.adj[o + e];
+      if (val != 0.0) atomic_add_f64(&pbuf[col_index(v, S, j)], val);
+      if (j == 0 && hop1[v] == 0) hop1[v] = WS_BOUNDARY;  // every writer stores the same value
+    }
+  }
+}
+
+// rho on U (see above), in place of the push sums in pbuf, and its signs in
+// sg; partials as k_ws_rho
+__global__ __launch_bounds__(WB) void k_ws_rho_sparse(int32_t n, int S, const int32_t *__restrict__ hop1,
+                                                      const double *__restrict__ ybuf, double *__restrict__ pbuf,
+                                                      const double *__restrict__ w, int8_t *__restrict__ sg,
+                                                      double *__restrict__ part) {
+  __shared__ double rn[WB], xs[WB];
+  const int j = threadIdx.x % S, rl = threadIdx.x / S, RPB = WB / S;
+  double a = 0.0, b = 0.0;
+  for (int v = blockIdx.x * RPB + rl; v < n; v += gridDim.x * RPB) {
+    if (hop1[v] == 0) continue;
+    const int64_t kk = col_index(v, S, j);
+    const double xw = w[kk];
+    const double rho = ybuf[kk] + pbuf[kk] - xw;
+    pbuf[kk] = rho;
+    sg[kk] = (int8_t)(rho > 0.0 ? 1 : (rho < 0.0 ? -1 : 0));
+    a += fabs(rho);
+    b += xw;
+  }
+  rn[threadIdx.x] = a;
+  xs[threadIdx.x] = b;
+  __syncthreads();
+  if (threadIdx.x < S) {
+    double t = 0.0, u = 0.0;
+    for (int q = 0; q < RPB; ++q) t += rn[q * S + threadIdx.x], u += xs[q * S + threadIdx.x];
+    part[(int64_t)blockIdx.x * 2 * S + threadIdx.x] = t;
+    part[(int64_t)blockIdx.x * 2 * S + S + threadIdx.x] = u;
+  }
+}
+
+// accepted columns on U: the seed becomes rho, the scores take xhat'; pbuf
+// (rho) back to zero on U
+__global__ void k_ws_apply_sparse(int32_t n, int S, uint64_t accept, const int32_t *__restrict__ hop1,
+                                  double *__restrict__ ybuf, double *__restrict__ pbuf, double *__restrict__ r,
+                                  const double *__restrict__ w, int32_t *__restrict__ stamp,
+                                  const Ctl *__restrict__ ctl) {
+  const int32_t st = ctl->stamp;
+  const int64_t total = (int64_t)n * S;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e % S);
+    if (hop1[e / S] == 0) continue;
+    const double rho = pbuf[e];
+    pbuf[e] = 0.0;
+    if (!((accept >> j) & 1ull)) continue;
+    ybuf[e] = rho;
+    r[e] += w[e];
+    if (rho != 0.0) stamp[e / S] = st;  // every writer stores the same value
+  }
+}
+
+__global__ void k_ws_unmark_boundary(int32_t n, int32_t *__restrict__ hop1) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    if (hop1[v] == WS_BOUNDARY) hop1[v] = 0;
+}
+
 
 // ------------------------------------------------------------ training
 // Gradient of the training loss L = sum_j ||rho_j||_1 / sum_j ||q_j||_1 over
@@ -462,8 +556,6 @@ __global__ void k_ws_sigma(Ctl *ctl, int S, uint64_t accept, const double *__res
 // GRAD_CHUNK edges (one wavefront each); every sum runs in a fixed order
 // (item partials, then each row's items in order, then per-workgroup column
 // partials and their sum), so the gradient does not depend on timing.
-#define GRAD_CHUNK 1024
-
 __device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
 __global__ void k_ws_grad_items(const int32_t *__restrict__ R, int32_t nR, DevGraphView out,
@@ -691,20 +783,18 @@ void ws_unscatter(const int32_t *R, int32_t nR, int S, double *w, hipStream_t s)
   hipLaunchKernelGGL(k_ws_unscatter, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, R, nR, S, w);
 }
 
-void ws_rho(int32_t n, int S, const double *ybuf, double *gbuf, const double *w, int8_t *sg, double *part,
+void ws_rho(int32_t n, int S, const double *ybuf, double *pbuf, const double *w, int8_t *sg, double *part,
             double *sums, hipStream_t s) {
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)n * S + WB - 1) / WB, 1024));
-  hipLaunchKernelGGL(k_ws_rho, dim3(nb), dim3(WB), 0, s, n, S, ybuf, gbuf, w, sg, part);
+  hipLaunchKernelGGL(k_ws_rho, dim3(nb), dim3(WB), 0, s, n, S, ybuf, pbuf, w, sg, part);
   hipLaunchKernelGGL(k_ws_sum_parts, dim3(2 * S), dim3(WB), 0, s, part, nb, 2 * S, sums);
 }
 
-void ws_apply(int32_t n, int S, uint64_t accept, double *ybuf, const double *gbuf, double *r, const double *w,
+void ws_apply(int32_t n, int S, uint64_t accept, double *ybuf, double *pbuf, double *r, const double *w,
               int32_t *stamp, Ctl *ctl, const double *xsum, hipStream_t s) {
-  if (accept) {
-    hipLaunchKernelGGL(k_ws_apply, dim3(wgrid((int64_t)n * S)), dim3(WB), 0, s, n, S, accept, ybuf, gbuf, r, w, stamp,
-                       ctl);
-    hipLaunchKernelGGL(k_ws_sigma, dim3(1), dim3(64), 0, s, ctl, S, accept, xsum);
-  }
+  hipLaunchKernelGGL(k_ws_apply, dim3(wgrid((int64_t)n * S)), dim3(WB), 0, s, n, S, accept, ybuf, pbuf, r, w, stamp,
+                     ctl);
+  if (accept) hipLaunchKernelGGL(k_ws_sigma, dim3(1), dim3(64), 0, s, ctl, S, accept, xsum);
 }
 
 hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *rho,
@@ -713,10 +803,9 @@ hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView
                          size_t temp_bytes, const int32_t *active, double q_active, const float *o, const double *qn,
                          const double *beta, const double *fa, double *kpart, double *corr, float *dout,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_ws_grad_items, dim3(wgrid((int64_t)nR + 1)), dim3(WB), 0, s, R, nR, out, items);
-  hipError_t e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, items, item_off, nR + 1, s);
-  if (e != hipSuccess) return e;
-  gnn::region_item_rows(item_off, nR, item_row, s);
+  (void)items;
+  (void)temp;
+  (void)temp_bytes;
   switch (S) {
 #define WS_GRAD(SS)                                                                                              \
   case SS:                                                                                                       \
@@ -741,4 +830,49 @@ hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView
   hipLaunchKernelGGL(k_ws_grad_corr, dim3(wgrid((int64_t)nR * S)), dim3(WB), 0, s, R, nR, S, out, c1, corr, beta, fa,
                      o, dout);
   return hipSuccess;
+}
+
+hipError_t ws_out_items(const int32_t *R, int32_t nR, const DevGraphView &out, int32_t *items, int32_t *item_off,
+                        int32_t *item_row, void *temp, size_t temp_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_grad_items, dim3(wgrid((int64_t)nR + 1)), dim3(WB), 0, s, R, nR, out, items);
+  hipError_t e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, items, item_off, nR + 1, s);
+  if (e != hipSuccess) return e;
+  gnn::region_item_rows(item_off, nR, item_row, s);
+  return hipSuccess;
+}
+
+void ws_rho_push(const int32_t *R, int32_t nR, int S, const DevGraphView &out, const int32_t *item_off,
+                 const int32_t *item_row, const double *xhat, double c1, double *pbuf, int32_t *hop1, int32_t n,
+                 const double *ybuf, const double *w, int8_t *sg, double *part, double *sums, hipStream_t s) {
+  switch (S) {
+#define WS_PUSH(SS)                                                                                              \
+  case SS:                                                                                                       \
+    hipLaunchKernelGGL(k_ws_push<SS>, dim3(2048), dim3(WB), 0, s, R, out, item_off, item_row, item_off + nR, xhat, \
+                       c1, pbuf, hop1);                                                                          \
+    break;
+    WS_PUSH(1)
+    WS_PUSH(2)
+    WS_PUSH(4)
+    WS_PUSH(8)
+    WS_PUSH(16)
+    WS_PUSH(32)
+    WS_PUSH(64)
+#undef WS_PUSH
+    default:
+      break;
+  }
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)n * S + WB - 1) / WB, 1024));
+  hipLaunchKernelGGL(k_ws_rho_sparse, dim3(nb), dim3(WB), 0, s, n, S, hop1, ybuf, pbuf, w, sg, part);
+  hipLaunchKernelGGL(k_ws_sum_parts, dim3(2 * S), dim3(WB), 0, s, part, nb, 2 * S, sums);
+}
+
+void ws_apply_sparse(int32_t n, int S, uint64_t accept, const int32_t *hop1, double *ybuf, double *pbuf, double *r,
+                     const double *w, int32_t *stamp, Ctl *ctl, const double *xsum, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_apply_sparse, dim3(wgrid((int64_t)n * S)), dim3(WB), 0, s, n, S, accept, hop1, ybuf, pbuf, r,
+                     w, stamp, ctl);
+  if (accept) hipLaunchKernelGGL(k_ws_sigma, dim3(1), dim3(64), 0, s, ctl, S, accept, xsum);
+}
+
+void ws_unmark_boundary(int32_t n, int32_t *hop1, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_unmark_boundary, dim3(wgrid(n)), dim3(WB), 0, s, n, hop1);
 }

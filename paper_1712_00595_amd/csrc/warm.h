@@ -70,18 +70,38 @@ void ws_qnorm(const int32_t *R, int32_t n0, int S, const double *ybuf, double *p
 void ws_predict(const int32_t *R, int32_t nR, int S, const DevGraphView &out, const float *o, const double *qn,
                 double c1, double *xhat, double *w, double *part, double *beta, double *fa, hipStream_t s);
 void ws_unscatter(const int32_t *R, int32_t nR, int S, double *w, hipStream_t s);
-// gbuf holds g = (1-c) B~^T xhat - xhat on every node; rho = q + g replaces
+// pbuf holds g = (1-c) B~^T xhat - xhat on every node; rho = q + g replaces
 // it and its signs go to sg (n * S bytes); sums[j] = ||rho_j||_1, sums[S + j]
 // = sum of xhat_j
-void ws_rho(int32_t n, int S, const double *ybuf, double *gbuf, const double *w, int8_t *sg, double *part,
+void ws_rho(int32_t n, int S, const double *ybuf, double *pbuf, const double *w, int8_t *sg, double *part,
             double *sums, hipStream_t s);
-// accepted columns: ybuf = rho, r += xhat, sigma += sum xhat, stamps
-void ws_apply(int32_t n, int S, uint64_t accept, double *ybuf, const double *gbuf, double *r, const double *w,
+// accepted columns: ybuf = rho, r += xhat, sigma += sum xhat, stamps; pbuf
+// (rho) cleared
+void ws_apply(int32_t n, int S, uint64_t accept, double *ybuf, double *pbuf, double *r, const double *w,
               int32_t *stamp, Ctl *ctl, const double *xsum, hipStream_t s);
+// Work items over the region's out-rows (GRAD_CHUNK = 1024 edges each):
+// items is scratch of nR + 1 ints, item_off[i] = first item of row i (nR + 1
+// entries, item_off[nR] = their number), item_row the row of each item.
+hipError_t ws_out_items(const int32_t *R, int32_t nR, const DevGraphView &out, int32_t *items, int32_t *item_off,
+                        int32_t *item_row, void *temp, size_t temp_bytes, hipStream_t s);
+// The residual from the region alone (for regions whose out-rows are a small
+// part of the graph): rho = q - xhat' + (1-c) B~^T xhat' on the region and its
+// out-neighbours (marked in hop1 until ws_unmark_boundary), by a push of the
+// rows of xhat (region-row order) into pbuf (FP64, zero at rest and left
+// zero at rest).  Outputs as ws_rho (rho in pbuf and its signs in sg only on
+// those nodes).
+void ws_rho_push(const int32_t *R, int32_t nR, int S, const DevGraphView &out, const int32_t *item_off,
+                 const int32_t *item_row, const double *xhat, double c1, double *pbuf, int32_t *hop1, int32_t n,
+                 const double *ybuf, const double *w, int8_t *sg, double *part, double *sums, hipStream_t s);
+// ws_apply for the residual of ws_rho_push (only the marked nodes; pbuf back
+// to zero there)
+void ws_apply_sparse(int32_t n, int S, uint64_t accept, const int32_t *hop1, double *ybuf, double *pbuf, double *r,
+                     const double *w, int32_t *stamp, Ctl *ctl, const double *xsum, hipStream_t s);
+void ws_unmark_boundary(int32_t n, int32_t *hop1, hipStream_t s);
 // dL/do of the residual loss through the mass correction (see
 // k_ws_grad_fixed / k_ws_grad_corr) into dout (rows nR * S); gpart holds one
 // double per (gradient item, column): at least (nR + edges of the region's
-// out-rows / 1024 + 1) * S, item_row as many ints as gpart has items;
+// out-rows / 1024 + 1) * S; item_off and item_row from ws_out_items;
 // kpart WS_KPART_BLOCKS * S doubles, corr S doubles.  Fixed-order sums only.
 #define WS_KPART_BLOCKS 1024
 hipError_t ws_resid_grad(const int32_t *R, int32_t nR, int S, const DevGraphView &out, double c1, const double *rho,

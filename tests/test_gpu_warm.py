@@ -37,9 +37,14 @@ def _l1(a, b):
     return float(np.abs(np.asarray(a) - np.asarray(b)).sum())
 
 
-@pytest.mark.parametrize("n_seeds,undirected", [(1, False), (3, False), (2, True)])
-def test_prediction_path_is_exact(n_seeds, undirected):
-    print(f"[warm exact] seeds={n_seeds} undirected={undirected}", flush=True)
+@pytest.mark.parametrize("n_seeds,undirected,push", [(1, False, None), (3, False, None), (2, True, None),
+                                                     (3, False, "1"), (2, True, "1")])
+def test_prediction_path_is_exact(n_seeds, undirected, push, monkeypatch):
+    """push "1": the residual formed from the region alone (RWR_WS_PUSH=1),
+    None: the library's choice (a pull over every in-row at these sizes)."""
+    print(f"[warm exact] seeds={n_seeds} undirected={undirected} push={push}", flush=True)
+    if push is not None:
+        monkeypatch.setenv("RWR_WS_PUSH", push)
     g = rmat_graph(11, 20000, dead_end_self_loops=not undirected, undirected=undirected)
     seeds = sample_seeds(g, n_seeds, seed=3)
     es, ed = (g.pair_u, g.pair_v) if undirected else (g.src, g.dst)

@@ -37,9 +37,14 @@ def _params(seed):
     return th.astype(np.float32)
 
 
-@pytest.mark.parametrize("undirected,n_seeds,hops", [(False, 3, 2), (True, 2, 2), (False, 5, 3)])
-def test_in_update_training_step_matches_oracle(undirected, n_seeds, hops):
-    print(f"[warm grad] undirected={undirected} seeds={n_seeds} hops={hops}", flush=True)
+@pytest.mark.parametrize("undirected,n_seeds,hops,push", [(False, 3, 2, None), (True, 2, 2, None),
+                                                          (False, 5, 3, None), (False, 3, 2, "1"),
+                                                          (True, 2, 2, "1")])
+def test_in_update_training_step_matches_oracle(undirected, n_seeds, hops, push, monkeypatch):
+    """push "1": the residual formed from the region alone (RWR_WS_PUSH=1)."""
+    print(f"[warm grad] undirected={undirected} seeds={n_seeds} hops={hops} push={push}", flush=True)
+    if push is not None:
+        monkeypatch.setenv("RWR_WS_PUSH", push)
     g = rmat_graph(10, 6000, dead_end_self_loops=not undirected, undirected=undirected)
     seeds = sample_seeds(g, n_seeds, seed=3)
     es, ed = (g.pair_u, g.pair_v) if undirected else (g.src, g.dst)
