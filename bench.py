@@ -269,15 +269,19 @@ def run_batched_seeds(K: int, W: int, check: bool = True, cpu_baseline: bool = T
     return res
 
 
-def run_learned(n_train: int, n_eval: int, check: bool = True) -> dict:
+def run_learned(n_train: int, n_eval: int, check: bool = True, max_rows: int = 0) -> dict:
     """R-MAT scale 21, 16 uniform seeds, 100-edge batches (50/50), eps = 1e-6:
-    online training of the warm-start network on n_train updates, then the
-    same n_eval held-out updates timed with the plain method and with the
-    trained prediction."""
+    online training of the warm-start network on n_train updates (from the
+    copy prior, the positively homogeneous parameters only, step-size
+    warm-up), a checkpoint of the trained context, then the same n_eval
+    held-out updates timed from that checkpoint with the plain method, the
+    trained network, and the untrained copy and propagation priors."""
+    import tempfile
+
     import torch
 
     from paper_1712_00595_amd import rwr
-    from paper_1712_00595_amd.warm import init_params
+    from paper_1712_00595_amd.warm import init_params, trainable_mask
     from synth.configs import RMAT21_LEARNED, stream_for
 
     w = RMAT21_LEARNED
@@ -289,56 +293,71 @@ def run_learned(n_train: int, n_eval: int, check: bool = True) -> dict:
     log(f"[{w.name}] graph n={g.n} m={g.m}, {n_train} train + {n_eval} held-out batches ({time.time() - t:.1f}s)")
     eps = w.eps[0]
     kw = dict(c=w.c, eps=eps, precision="fp32")
-    th0 = init_params(5)
-    res = {"train_updates": n_train, "eval_updates": n_eval, "gate": 2 * eps / w.c}
-    t = time.time()
-    with rwr.Context(g.n, g.src, g.dst, seeds, **kw) as tr:
-        tr.model_set(th0)
-        tr.warm_start("predict+train", hops=3, lr=1e-5)
-        st = [tr.update_batch(b) for b in train]
-        th = tr.model_get()
-    res["train_s"] = time.time() - t
-    res["train_loss_first_last"] = [float(np.mean([s["ws_loss"] for s in st[:50]])),
-                                    float(np.mean([s["ws_loss"] for s in st[-50:]]))]
-    log(f"[{w.name}] trained in {res['train_s']:.1f}s, loss {res['train_loss_first_last']}")
-    for name, params in (("plain", None), ("learned", th), ("prior", th0)):
-        with rwr.Context(g.n, g.src, g.dst, seeds, **kw) as ctx:
-            for b in train:
-                ctx.update_batch(b)
-            if params is not None:
-                ctx.model_set(params)
-                ctx.warm_start("predict", hops=3)
+    th_copy = init_params(5, prior="copy")
+    th_prop = init_params(5, prior="propagation", c=w.c)
+    res = {"train_updates": n_train, "eval_updates": n_eval, "gate": 2 * eps / w.c, "max_rows": max_rows,
+           "hops": 3, "lr": 3e-4, "init": "copy prior", "warmup_steps": 10}
+    fd, ckpt = tempfile.mkstemp(suffix=".ckpt")
+    os.close(fd)
+    try:
+        t = time.time()
+        with rwr.Context(g.n, g.src, g.dst, seeds, **kw) as tr:
+            tr.model_set(th_copy)
+            tr.model_trainable(trainable_mask(), warmup=10)
+            tr.warm_start("predict+train", hops=3, lr=3e-4, max_rows=max_rows)
+            st = [tr.update_batch(b) for b in train]
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st = [ctx.update_batch(b) for b in held]
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            mods = sum(b.size for b in held)
-            r = {"updates_per_s": n_eval / el, "modifications_per_s": mods / el,
-                 "mean_iters": float(np.mean([s["iters"] for s in st])),
-                 "mean_dense_sweeps": float(np.mean([s["dense_iters"] for s in st])),
-                 "max_err_bound": float(max(s["err_bound"] for s in st))}
-            if params is not None:
-                r["mean_resid_ratio"] = float(np.mean([s["ws_resid_ratio"] for s in st]))
-                r["mean_accepted_columns"] = float(np.mean([s["ws_accepted"] for s in st]))
-                r["mean_region_nodes"] = float(np.mean([s["ws_region"] for s in st]))
-                r["mean_warm_ms"] = float(np.mean([s["ms_warm"] for s in st]))
-            if name == "learned" and check:
-                import oracle
+            res["train_s"] = time.time() - t
+            th = tr.model_get()
+            tr.save(ckpt)
+        k = min(100, max(1, n_train // 10))
+        res["train_loss_first_last"] = [float(np.mean([s["ws_loss"] for s in st[:k]])),
+                                        float(np.mean([s["ws_loss"] for s in st[-k:]]))]
+        res["train_ms_per_update"] = 1e3 * res["train_s"] / max(1, n_train)
+        log(f"[{w.name}] trained in {res['train_s']:.1f}s, loss (first/last {k}) {res['train_loss_first_last']}")
+        for name, params in (("plain", None), ("trained", th), ("copy_prior", th_copy),
+                             ("propagation_prior", th_prop)):
+            with rwr.Context.load(ckpt) as ctx:
+                if params is None:
+                    ctx.warm_start("off")
+                else:
+                    ctx.model_set(params)
+                    ctx.warm_start("predict", hops=3, max_rows=max_rows)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = [ctx.update_batch(b) for b in held]
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                mods = sum(b.size for b in held)
+                r = {"updates_per_s": n_eval / el, "modifications_per_s": mods / el, "ms_per_update": 1e3 * el / n_eval,
+                     "mean_iters": float(np.mean([s["iters"] for s in st])),
+                     "mean_dense_sweeps": float(np.mean([s["dense_iters"] for s in st])),
+                     "residual_checks": int(sum(s["checked"] for s in st)),
+                     "max_err_bound": float(max(s["err_bound"] for s in st))}
+                if params is not None:
+                    r["mean_resid_ratio"] = float(np.mean([s["ws_resid_ratio"] for s in st]))
+                    r["mean_accepted_columns"] = float(np.mean([s["ws_accepted"] for s in st]))
+                    r["mean_region_nodes"] = float(np.mean([s["ws_region"] for s in st]))
+                    r["mean_warm_ms"] = float(np.mean([s["ms_warm"] for s in st]))
+                if name == "trained" and check:
+                    import oracle
 
-                from paper_1712_00595_amd import accuracy
+                    from paper_1712_00595_amd import accuracy
 
-                n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream)
-                errs, ranks = [], []
-                for j in (0, 15):
-                    ref = oracle.rwr_static(n2, s2, d2, int(seeds[j]), w.c)
-                    got = ctx.scores(j)
-                    errs.append(float(np.abs(got - ref).sum()))
-                    ranks.append(rank_accuracy(accuracy, got, ref))
-                r["parity"] = {"columns": [0, 15], "l1_vs_oracle": errs, "rank_accuracy": ranks,
-                               "ok": max(errs) <= res["gate"]}
-            res[name] = r
-            log(f"[{w.name}] {name}: {r['updates_per_s']:.1f} updates/s, iters {r['mean_iters']:.2f}")
+                    n2, s2, d2 = oracle.apply_stream(g.n, g.src, g.dst, stream)
+                    errs, ranks = [], []
+                    for j in (0, 15):
+                        ref = oracle.rwr_static(n2, s2, d2, int(seeds[j]), w.c)
+                        got = ctx.scores(j)
+                        errs.append(float(np.abs(got - ref).sum()))
+                        ranks.append(rank_accuracy(accuracy, got, ref))
+                    r["parity"] = {"columns": [0, 15], "l1_vs_oracle": errs, "rank_accuracy": ranks,
+                                   "ok": max(errs) <= res["gate"]}
+                res[name] = r
+                log(f"[{w.name}] {name}: {r['updates_per_s']:.1f} updates/s, iters {r['mean_iters']:.2f}"
+                    + (f", resid ratio {r['mean_resid_ratio']:.3f}" if params is not None else ""))
+    finally:
+        os.remove(ckpt)
     return res
 
 
@@ -735,8 +754,10 @@ def main() -> int:
                          "rmat21_learned_warm_start, rmat23_undirected_churn, rmat20_delta_study")
     ap.add_argument("--churn-batches", type=int, default=10, help="batches of the undirected churn workload")
     ap.add_argument("--churn-check", action="store_true", help="check one column of the churn workload (slow)")
-    ap.add_argument("--learned-train", type=int, default=500, help="training updates of the learned workload")
-    ap.add_argument("--learned-eval", type=int, default=100, help="held-out updates of the learned workload")
+    ap.add_argument("--learned-train", type=int, default=5000, help="training updates of the learned workload")
+    ap.add_argument("--learned-eval", type=int, default=500, help="held-out updates of the learned workload")
+    ap.add_argument("--learned-max-rows", type=int, default=0,
+                    help="region capacity of the learned warm start in (node, column) rows (0: the default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one elementwise copy of MIB MiB (calibrates the traffic counters) and exit")
     args = ap.parse_args()
@@ -782,7 +803,7 @@ def main() -> int:
     extra = {}
     for wname in [x for x in args.workloads.split(",") if x]:
         if wname == "rmat21_learned_warm_start":
-            extra[wname] = run_learned(args.learned_train, args.learned_eval, check)
+            extra[wname] = run_learned(args.learned_train, args.learned_eval, check, args.learned_max_rows)
         elif wname == "rmat23_undirected_churn":
             extra[wname] = run_churn(args.churn_batches, args.churn_check)
         elif wname == "rmat20_delta_study":
