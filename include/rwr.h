@@ -74,7 +74,10 @@ typedef struct rwr_config {
                         this interface are unchanged); 0: keep the caller's order      */
   int32_t autotune;  /* 1: the build's static solve times candidate shapes of the dense
                         sweep (lanes per row, workgroups) on its first sweeps and keeps
-                        the fastest; 0: the fixed defaults                               */
+                        the fastest; 0: the fixed defaults.  Environment RWR_TUNE_CACHE
+                        = a text file: a build whose workload (device, n, m, S,
+                        precision, in-degree histogram) is listed there takes the
+                        listed shape without timing; a tuned build appends its line   */
   void *stream;      /* hipStream_t to run on; NULL: the library creates its own        */
   int32_t deterministic; /* 1: results do not depend on timing -- no floating-point atomics
                             on the score path: the offset seed is summed per node in a
@@ -243,7 +246,8 @@ rwr_status rwr_graph_export(rwr_ctx *ctx, int32_t *src, int32_t *dst, int64_t ca
 
 /* Shape of the dense sweep in use: lanes per in-row (multi-column sweep)
  * and workgroups, and the median time of one sweep at that shape measured
- * while tuning (0 when the shape was not tuned).  Any pointer may be NULL. */
+ * while tuning, or read from the tuning cache (0 when the shape was not
+ * tuned).  Any pointer may be NULL. */
 rwr_status rwr_sweep_shape(const rwr_ctx *ctx, int32_t *lanes_per_row, int32_t *workgroups, double *tuned_ms);
 
 /* Per-iteration ||x^(i)||_1 of seed column j during the last update (i = 0 is

@@ -164,6 +164,9 @@ struct rwr_ctx {
     std::vector<hipEvent_t> ev;
     std::vector<int> pending;  // candidate of each launch of the current chunk
     double best_ms = 0.0;
+    bool cached = false;     // the shape came from the tuning cache
+    std::string cache_path;  // where a finished tuning appends its line (empty: nowhere)
+    std::string cache_key;
   } tune;
   // HIP graph of two consecutive dense iteration slots (an even and an odd
   // one: the kernels depend on the slot index only through its parity),
@@ -734,6 +737,62 @@ static void tune_begin(rwr_ctx *c) {
   t.on = true;
 }
 
+// Tuning cache (environment RWR_TUNE_CACHE = a text file): one line per
+// tuned workload, "key lanes workgroups ms", the key naming the device
+// (architecture and compute units), n, m, S, the propagation precision and
+// a hash of the pull orientation's degree histogram (log2 buckets).  A build
+// whose key is listed takes the listed shape instead of tuning.
+static rwr_status tune_key(rwr_ctx *c, std::string *key) {
+  hipDeviceProp_t prop{};
+  HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
+  std::vector<int32_t> len(c->n);
+  D2H(c, len.data(), c->g[pull_orient(c)].v.len, sizeof(int32_t) * c->n);
+  uint64_t hist[33] = {};
+  for (int32_t d : len) {
+    int b = 0;
+    while (b < 32 && (1ll << b) <= d) ++b;
+    ++hist[b];
+  }
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the histogram counts
+  for (uint64_t x : hist)
+    for (int k = 0; k < 8; ++k) {
+      h ^= (x >> (8 * k)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s/cu%d/n%d/m%lld/S%d/fp%d/deg%016llx", prop.gcnArchName, c->n_cu, c->n,
+                (long long)c->m, c->S, c->fp64 ? 64 : 32, (unsigned long long)h);
+  for (char *p = buf; *p; ++p)
+    if (*p == ' ') *p = '_';
+  *key = buf;
+  return RWR_OK;
+}
+
+static bool tune_cache_find(const char *path, const std::string &key, int32_t *lanes, int32_t *grid, double *ms) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char k[256];
+  int l = 0, g = 0;
+  double t = 0.0;
+  bool found = false;
+  while (std::fscanf(f, "%255s %d %d %lf", k, &l, &g, &t) == 4)
+    if (key == k && l > 0 && g > 0) {
+      *lanes = l;
+      *grid = g;
+      *ms = t;
+      found = true;  // the last entry for the key wins
+    }
+  std::fclose(f);
+  return found;
+}
+
+static void tune_cache_store(const char *path, const std::string &key, int32_t lanes, int32_t grid, double ms) {
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;  // the cache is an optimisation: a read-only location only costs the tuning
+  std::fprintf(f, "%s %d %d %.6f\n", key.c_str(), lanes, grid, ms);
+  std::fclose(f);
+}
+
 static bool tune_done(const rwr_ctx::Tune &t) {
   for (const auto &v : t.ms)
     if ((int)v.size() < t.reps) return false;
@@ -756,7 +815,9 @@ static void tune_finish(rwr_ctx *c) {
     c->pull_lanes = t.cand[best].first;
     c->grid_pull = t.cand[best].second;
     t.best_ms = bms;
+    if (!t.cache_path.empty()) tune_cache_store(t.cache_path.c_str(), t.cache_key, c->pull_lanes, c->grid_pull, bms);
   }
+  t.cache_path.clear();
 }
 
 static void pair_graph_drop(rwr_ctx *c) {
@@ -1749,8 +1810,28 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   // Its first dense sweeps also choose the sweep shape (unless fixed by the
   // caller's configuration or the environment).
   // (not in deterministic mode: the shape sets each row's summation order)
-  if (c->cfg.autotune && !c->det && !getenv("RWR_PULL_LANES") && !getenv("RWR_GRID_PULL")) {
+  const char *cache = getenv("RWR_TUNE_CACHE");
+  std::string tkey;
+  bool cached = false;
+  if (c->cfg.autotune && !c->det && !getenv("RWR_PULL_LANES") && !getenv("RWR_GRID_PULL") && cache && *cache) {
+    RWR_TRY(tune_key(c, &tkey));
+    int32_t l = 0, g = 0;
+    double ms = 0.0;
+    if (tune_cache_find(cache, tkey, &l, &g, &ms)) {
+      c->pull_lanes = l;
+      c->grid_pull = g;
+      c->tune.best_ms = ms;
+      c->tune.cached = true;
+      cached = true;
+      RWR_TRY(ensure_partials(c));
+    }
+  }
+  if (c->cfg.autotune && !c->det && !cached && !getenv("RWR_PULL_LANES") && !getenv("RWR_GRID_PULL")) {
     tune_begin(c);
+    if (!tkey.empty()) {
+      c->tune.cache_path = cache;
+      c->tune.cache_key = tkey;
+    }
     int32_t gmax = 0;
     for (const auto &cd : c->tune.cand) gmax = std::max(gmax, cd.second);
     const int32_t keep = c->grid_pull;

@@ -540,6 +540,37 @@ def test_sweep_shape_tuning(monkeypatch, n_seeds):
             assert _l1(fixed.scores(j), ref) < 1e-11
 
 
+def test_tuning_cache(monkeypatch, tmp_path):
+    # RWR_TUNE_CACHE: the first build tunes and appends its shape; a build of
+    # the same workload takes it from the file without timing; another
+    # workload (more columns) gets a line of its own
+    print("[tuning cache]", flush=True)
+    monkeypatch.delenv("RWR_PULL_LANES", raising=False)
+    monkeypatch.delenv("RWR_GRID_PULL", raising=False)
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("RWR_TUNE_CACHE", str(path))
+    from synth.rmat import sample_seeds
+
+    g = rmat_graph(13, 120000, dead_end_self_loops=True)
+    seeds = sample_seeds(g, 8, seed=3)
+    kw = dict(eps=1e-12, precision="fp64", build_tol=1e-11)
+    with _ctx(g, seeds, autotune=True, **kw) as a:
+        sa = a.sweep_shape()
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[1:3] == [str(sa["lanes_per_row"]), str(sa["workgroups"])]
+    assert "/S8/" in lines[0] and f"/n{g.n}/" in lines[0]
+    with _ctx(g, seeds, autotune=True, **kw) as b:
+        sb = b.sweep_shape()
+        assert (sb["lanes_per_row"], sb["workgroups"]) == (sa["lanes_per_row"], sa["workgroups"])
+        assert abs(sb["tuned_ms"] - sa["tuned_ms"]) <= 1e-6 * max(1.0, sa["tuned_ms"])
+        ref = oracle.rwr_static(g.n, g.src, g.dst, int(seeds[0]), 0.15)
+        assert _l1(b.scores(0), ref) < 1e-11
+    assert len(path.read_text().splitlines()) == 1
+    with _ctx(g, sample_seeds(g, 16, seed=3), autotune=True, **kw):
+        pass
+    assert len(path.read_text().splitlines()) == 2
+
+
 def test_graph_replay_matches_eager(monkeypatch):
     # dense iteration pairs replayed from a captured HIP graph give the same
     # propagation as eager launches, update after update (each update replays
