@@ -468,8 +468,12 @@ def run_churn(n_batches: int, check: bool) -> dict:
     g = w.graph()
     seeds = w.seeds(g)
     pool = PairPool(g.n, g.pair_u, g.pair_v)
-    stream = list(churn_stream(pool, n_batches, 0.01, 1000, seed=4))
-    log(f"[{w.name}] graph n={g.n} pairs={g.pair_u.shape[0]}, {len(stream)} batches ({time.time() - t:.1f}s)")
+    log(f"[{w.name}] graph n={g.n} pairs={g.pair_u.shape[0]} ({time.time() - t:.1f}s)")
+    stream = []
+    for b in churn_stream(pool, n_batches, 0.01, 1000, seed=4):
+        stream.append(b)
+        if len(stream) % 10 == 0:
+            log(f"[{w.name}] {len(stream)} of {n_batches} batches drawn ({time.time() - t:.1f}s)")
     eps = w.eps[0]
     t = time.time()
     ctx = rwr.Context(g.n, g.pair_u, g.pair_v, seeds, c=w.c, eps=eps, precision="fp32", undirected=True)
@@ -480,7 +484,11 @@ def run_churn(n_batches: int, check: bool) -> dict:
     ctx.profile_read(reset=True)
     mods = sum(b.size for b in stream)
     t0 = time.perf_counter()
-    stats = [ctx.update_batch(b) for b in stream]
+    stats = []
+    for i, b in enumerate(stream):
+        stats.append(ctx.update_batch(b))
+        if (i + 1) % 25 == 0:
+            log(f"[{w.name}] {i + 1} batches")  # a line per 25 batches (each takes about a second)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     P = ctx.profile_read(reset=True)
@@ -752,7 +760,7 @@ def main() -> int:
     ap.add_argument("--workloads", default="",
                     help="extra workloads run after the headline, comma list of: "
                          "rmat21_learned_warm_start, rmat23_undirected_churn, rmat20_delta_study")
-    ap.add_argument("--churn-batches", type=int, default=10, help="batches of the undirected churn workload")
+    ap.add_argument("--churn-batches", type=int, default=100, help="batches of the undirected churn workload")
     ap.add_argument("--churn-check", action="store_true", help="check one column of the churn workload (slow)")
     ap.add_argument("--learned-train", type=int, default=5000, help="training updates of the learned workload")
     ap.add_argument("--learned-eval", type=int, default=500, help="held-out updates of the learned workload")

@@ -397,7 +397,7 @@ static rwr_status read_ctl(rwr_ctx *c) {
 // partial-sum buffers sized for the largest grid in use
 static rwr_status ensure_partials(rwr_ctx *c) {
   // entries: the largest grid plus the heavy-row kernel's workgroups
-  const int64_t blocks = std::max<int64_t>({c->grid_light, c->grid_sparse, c->grid_pull}) + 320;
+  const int64_t blocks = std::max<int64_t>({c->grid_light, c->grid_sparse, c->grid_pull}) + HEAVY_EPI_MAX_GRID + 64;
   if (blocks <= c->part_blocks) return RWR_OK;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   dev_free(c, c->part);

@@ -1513,7 +1513,7 @@ static void pull_impl(const SlotArgs &a, int k, hipStream_t st, hipEvent_t ev0 =
   const bool fold = decide && (int64_t)a.heavy.n_rows * S <= std::min(a.fold_max, 2 * DECIDE_BLOCK);
   int hgrid = 0;
   if (a.heavy.n_rows > 0 && !fold) {
-    hgrid = std::max(1, std::min((a.heavy.n_rows * S + BLOCK - 1) / BLOCK, 256));
+    hgrid = std::max(1, std::min((a.heavy.n_rows * S + BLOCK - 1) / BLOCK, HEAVY_EPI_MAX_GRID));
     hipLaunchKernelGGL((k_heavy_epi<XT, S, KIND>), dim3(hgrid), dim3(BLOCK), 0, st, a, k, grid);
   }
   if (decide) decide_impl<S, XT>(a, KIND, grid + hgrid, k & 1, st, fold ? 1 : 0);

@@ -126,6 +126,9 @@ hipError_t launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, c
                               int32_t max_rows, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
                               int grid, hipStream_t st);
 size_t seed_scan_temp_bytes(int32_t max_rows);
+// workgroups of the heavy-row epilogue (one (row, column) pair per thread);
+// its partials follow the sweep's, so partial buffers hold this many more
+constexpr int HEAVY_EPI_MAX_GRID = 2048;
 void launch_apply(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st);
 // the offset seed summed in a fixed order (no atomics), after the structural
 // apply and a support-only launch_offset_seed (ybuf null): ybuf of every
