@@ -166,10 +166,29 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
       hv[u] = a.heavy.rows[h];
     }
   }
-  double A = 0.0, B = 0.0;
-  for (int e = q; e < count; e += TPC) {
-    A += a.part[e * entry_stride<S>() + 2 * j];
-    B += a.part[e * entry_stride<S>() + 2 * j + 1];
+  // four partials per step in flight, into four sums added in a fixed order
+  double A, B;
+  {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    const double *__restrict__ pp = a.part + 2 * j;
+    const int64_t ES = entry_stride<S>();
+    int e = q;
+    for (; e + 3 * TPC < count; e += 4 * TPC) {
+      a0 += pp[(int64_t)e * ES];
+      b0 += pp[(int64_t)e * ES + 1];
+      a1 += pp[(int64_t)(e + TPC) * ES];
+      b1 += pp[(int64_t)(e + TPC) * ES + 1];
+      a2 += pp[(int64_t)(e + 2 * TPC) * ES];
+      b2 += pp[(int64_t)(e + 2 * TPC) * ES + 1];
+      a3 += pp[(int64_t)(e + 3 * TPC) * ES];
+      b3 += pp[(int64_t)(e + 3 * TPC) * ES + 1];
+    }
+    for (; e < count; e += TPC) {
+      a0 += pp[(int64_t)e * ES];
+      b0 += pp[(int64_t)e * ES + 1];
+    }
+    A = (a0 + a1) + (a2 + a3);
+    B = (b0 + b1) + (b2 + b3);
   }
   // a slot enqueued past the end of the run, or of the other phase
   const bool live_par = ((it ^ new_list) & 1) == 0;
