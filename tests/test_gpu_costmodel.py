@@ -69,4 +69,12 @@ def test_delta_weight_matches_oracle(n_seeds, undirected):
                 # so Theorem 2 bounds the dense sweeps by ||q||_1 + ||p||_1
                 assert st["dense_iters"] <= costmodel.iterations_bound(st["q_off_l1"] + g, EPS, C)
                 assert st["dense_iters"] <= costmodel.iterations_bound((1 - C) * st["dr_l1"] + g, EPS, C)
+                # the sparse slots before it propagate q alone: a run whose
+                # ||P^i q||_1 passed the stop test there would have ended (p
+                # then stays pending), so they are bounded by ||q||_1, and the
+                # whole run by the sum of both bounds
+                sparse = st["iters"] - st["dense_iters"]
+                assert sparse <= costmodel.iterations_bound(st["q_off_l1"], EPS, C), st
+                assert st["iters"] <= (costmodel.iterations_bound(st["q_off_l1"], EPS, C)
+                                       + costmodel.iterations_bound(st["q_off_l1"] + g, EPS, C)), st
             n, s, d = n2, s2, d2
