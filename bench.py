@@ -65,14 +65,21 @@ SWEEP_SOURCE = os.path.join(ROOT, "paper_1712_00595_amd", "csrc", "k_prop.hip")
 
 
 def host_cpu_model() -> str:
-    """The host CPU's model name (as lscpu prints it)."""
+    """The host CPU's model name as lscpu prints it, with its family, model
+    and stepping numbers (a virtualised host may report a short name)."""
+    fields = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields.setdefault(k.strip(), v.strip())
+            if not line.strip() and fields:
+                break
     except OSError:
         pass
-    return platform.processor() or platform.machine()
+    name = fields.get("model name") or platform.processor() or platform.machine()
+    ids = [f"{k} {fields[k]}" for k in ("cpu family", "model", "stepping") if k in fields]
+    return f"{name} ({', '.join(ids)})" if ids else name
 
 
 def measured_traffic(sweep_bytes: int, summary: str = TRAFFIC_C2):
