@@ -40,6 +40,10 @@ int next_pow2_cols(int n) {
   return s;
 }
 
+// terms of the offset seed (old degrees of the touched rows plus the batch's
+// keys) from which it is sorted and reduced instead of scattered atomically
+constexpr int64_t SEED_SORT_MIN = 1 << 16;
+
 int bits_for(int64_t v) {
   int b = 1;
   while ((1ll << b) <= v) ++b;
@@ -82,7 +86,14 @@ struct rwr_ctx {
   int32_t solve_iters = 10000; // of a build or refinement run (at least Theorem 2's bound)
   bool rows_only = false;      // node deletion removes the row only
   bool det = false;            // no floating-point atomics on the score path
-  int32_t *tmark = nullptr;    // 2 n_cap: changed-row marks of the fixed-order offset seed (det)
+  // the offset seed's records (sort-and-reduce form): two key buffers of
+  // srec_cap, the chunk partials, per-row old degrees and their prefix sum
+  uint64_t *srec[2] = {nullptr, nullptr};
+  double *spart = nullptr;
+  int32_t *sdcnt = nullptr, *sroff = nullptr;
+  int64_t srec_cap = 0;
+  int seed_sort_mode = -1;   // RWR_SEED_SORT: 1 always sort and reduce, 0 atomics (outside deterministic mode)
+  bool seed_sorted = false;  // the last update's offset seed was sorted and reduced
   hipEvent_t ph_ev[7] = {};    // phase-timing events (created on first use)
   double *part = nullptr;
   int64_t *part_i = nullptr;
@@ -438,6 +449,7 @@ static void tune_defaults(rwr_ctx *c) {
   if (const char *e = getenv("RWR_CARRY")) c->carry_level = std::max(0, std::min(2, atoi(e)));
   if (const char *e = getenv("RWR_LOCKSTEP")) c->lockstep = atoi(e) != 0;
   if (const char *e = getenv("RWR_WS_PUSH")) c->ws.push_mode = atoi(e) != 0 ? 1 : 0;
+  if (const char *e = getenv("RWR_SEED_SORT")) c->seed_sort_mode = atoi(e) != 0 ? 1 : 0;
   if (const char *e = getenv("RWR_REFINE_TARGET")) {
     const double t = atof(e);
     if (t > 0.0 && t < 1.0) c->refine_target = t;
@@ -614,7 +626,6 @@ static rwr_status grow_nodes(rwr_ctx *c, int32_t need) {
   RWR_TRY(regrow((void **)&c->stamp, 4, 1));
   RWR_TRY(regrow((void **)&c->fstamp, 4, 1));
   RWR_TRY(regrow((void **)&c->nmark, 4, 1));
-  if (c->det) RWR_TRY(regrow((void **)&c->tmark, 4, 2));
   RWR_TRY(regrow((void **)&c->hfront, 4, 1));
   RWR_TRY(regrow((void **)&c->hbase, 4, 1));
   RWR_TRY(regrow((void **)&c->sel, 4, 2));
@@ -1521,7 +1532,8 @@ static void fill_stats(rwr_ctx *c, rwr_stats *st) {
   st->last_x_l1 = lx;
   st->carry_l1 = c->last_carry_l1;
   double dr = 0.0;
-  for (int j = 0; j < c->n_seeds; ++j) dr = std::max(dr, c->det ? std::ldexp((double)h.dr_fix[j], -52) : h.dr_l1[j]);
+  for (int j = 0; j < c->n_seeds; ++j)
+    dr = std::max(dr, c->seed_sorted ? std::ldexp((double)h.dr_fix[j], -52) : h.dr_l1[j]);
   st->dr_l1 = dr;
 }
 
@@ -1795,7 +1807,6 @@ static rwr_status build_impl(rwr_ctx *c, int32_t n, int64_t m, const int32_t *sr
   RWR_TRY(alloc_zero(c, &c->stamp, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->fstamp, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->nmark, c->n_cap));
-  if (c->det) RWR_TRY(alloc_zero(c, &c->tmark, (size_t)c->n_cap * 2));
   RWR_TRY(alloc_zero(c, &c->hfront, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->hbase, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->sel, (size_t)c->n_cap * 2));
@@ -1974,9 +1985,13 @@ static rwr_status ensure_batch(rwr_ctx *c, int64_t nkeys, int64_t nints) {
     dev_free(c, c->keys_alt);
     dev_free(c, c->flags);
     dev_free(c, c->pos);
+    dev_free(c, c->sdcnt);
+    dev_free(c, c->sroff);
     RWR_TRY(alloc_zero(c, &c->keys_alt, cap));
     RWR_TRY(alloc_zero(c, &c->flags, cap + 1));
     RWR_TRY(alloc_zero(c, &c->pos, cap + 1));
+    RWR_TRY(alloc_zero(c, &c->sdcnt, cap + 1));
+    RWR_TRY(alloc_zero(c, &c->sroff, cap + 1));
     RWR_TRY(ensure_temp(c, std::max(sort_temp_bytes((int32_t)cap), seed_scan_temp_bytes((int32_t)cap))));
     c->bcap = cap;
   }
@@ -1990,6 +2005,25 @@ static rwr_status ensure_batch(rwr_ctx *c, int64_t nkeys, int64_t nints) {
     c->b_host_cap = cap;
   }
   return RWR_OK;
+}
+
+// record buffers of the sorted offset seed for n_rec records
+static rwr_status ensure_seed_recs(rwr_ctx *c, int64_t n_rec) {
+  if (n_rec > c->srec_cap) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int64_t cap = std::min<int64_t>(INT32_MAX, std::max<int64_t>(n_rec, 2 * c->srec_cap));
+    for (int i = 0; i < 2; ++i) {
+      dev_free(c, c->srec[i]);
+      c->srec[i] = nullptr;
+    }
+    dev_free(c, c->spart);
+    c->spart = nullptr;
+    c->srec_cap = 0;
+    for (int i = 0; i < 2; ++i) RWR_TRY(dev_alloc(c, (void **)&c->srec[i], sizeof(uint64_t) * cap));
+    RWR_TRY(dev_alloc(c, (void **)&c->spart, sizeof(double) * 2 * seed_part_len(cap, c->S)));
+    c->srec_cap = cap;
+  }
+  return ensure_temp(c, seed_sort_temp_bytes(c->srec_cap));
 }
 
 // per-orientation arguments of the batch kernels (check: the out orientation
@@ -2177,6 +2211,19 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     launch_validate_plan(orient_pair(c, false), norient, b1, c->ctl, (int32_t)nkeys, c->stream);
     RWR_TRY(read_ctl(c));
   }
+  // the offset seed: scattered with FP64 atomics, or written as records that
+  // are sorted and summed per node in a fixed order (deterministic mode, and
+  // batches with many terms, where it is also faster)
+  const int64_t n_rec = nkeys > 0 ? c->ctl_h->seed_recs + nkeys : 0;
+  c->seed_sorted = nkeys > 0 && (c->det || c->seed_sort_mode == 1 || (c->seed_sort_mode < 0 && n_rec >= SEED_SORT_MIN));
+  if (c->seed_sorted && n_rec >= INT32_MAX) {
+    if (c->det) {
+      c->err = "batch too large for the deterministic offset seed (2^31 terms)";
+      return RWR_EINVAL;
+    }
+    c->seed_sorted = false;
+  }
+  if (c->seed_sorted) RWR_TRY(ensure_seed_recs(c, n_rec));
   // the batch is valid: commit the node count and apply
   RWR_TRY(phase_mark(c, 1));
   c->n = n_new;
@@ -2198,21 +2245,23 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     c->tail_slot = -1;
     c->tail_cols = 0;
   }
-  // the offset seed of r - p; deterministic: only its support here, its
-  // values summed in a fixed order once the batch is applied
+  // the offset seed of r - p
   const double *rsub = c->pend ? c->gbuf : nullptr;
   if (nkeys > 0)
     HIP_TRY(c, launch_offset_seed(c->S, c->keys[0], c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->g[0].v,
-                                  c->r, rsub, c->det ? nullptr : c->ybuf, c->stamp, c->ctl, b1, 1.0 - c->cfg.c,
-                                  (int32_t)nkeys, c->flags, c->pos, c->temp, c->temp_bytes, 4 * c->n_cu, c->stream));
+                                  c->r, rsub, c->seed_sorted ? nullptr : c->ybuf, c->stamp, c->ctl, b1,
+                                  1.0 - c->cfg.c, (int32_t)nkeys, c->flags, c->pos,
+                                  c->seed_sorted ? c->srec[0] : nullptr, c->sdcnt, c->sroff, c->temp,
+                                  c->temp_bytes, 4 * c->n_cu, c->stream));
+  if (c->seed_sorted) {
+    const int64_t pl = seed_part_len(n_rec, c->S);
+    HIP_TRY(c, launch_seed_sort_reduce(c->S, c->srec[0], c->srec[1], (int32_t)n_rec, (int32_t)nkeys, c->n, c->sroff,
+                                       c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->r, rsub, 1.0 - c->cfg.c,
+                                       c->ybuf, c->spart, c->spart + pl, c->temp, c->temp_bytes, c->ctl,
+                                       8 * c->n_cu, c->stream));
+  }
   RWR_TRY(phase_mark(c, 2));
   if (nkeys > 0) launch_apply(orient_pair(c, false), norient, b1, c->ctl, (int32_t)nkeys, c->stream);
-  if (nkeys > 0 && c->det) {
-    const int po = pull_orient(c);
-    HIP_TRY(c, launch_offset_pull(c->S, orient_pair(c, false), po, c->g[po].v, c->stamp, c->ctl, c->n, c->tmark,
-                                  c->tmark + c->n_cap, b1, c->r, rsub, c->ybuf, 1.0 - c->cfg.c, (int32_t)nkeys,
-                                  8 * c->n_cu, c->stream));
-  }
   RWR_TRY(phase_mark(c, 3));
   // stored edge count (an undirected self-loop is stored once; the count only
   // steers the sparse/dense switch and the visited-edge statistic)
@@ -2409,7 +2458,11 @@ void rwr_destroy(rwr_ctx *c) {
   dev_free(c, c->stamp);
   dev_free(c, c->fstamp);
   dev_free(c, c->nmark);
-  dev_free(c, c->tmark);
+  dev_free(c, c->srec[0]);
+  dev_free(c, c->srec[1]);
+  dev_free(c, c->spart);
+  dev_free(c, c->sdcnt);
+  dev_free(c, c->sroff);
   dev_free(c, c->ndel);
   dev_free(c, c->row_order);
   dev_free(c, c->hfront);
@@ -2836,7 +2889,6 @@ static rwr_status load_impl(rwr_ctx *c, FILE *f, const CkptHead &h) {
   RWR_TRY(alloc_zero(c, &c->stamp, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->fstamp, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->nmark, c->n_cap));
-  if (c->det) RWR_TRY(alloc_zero(c, &c->tmark, (size_t)c->n_cap * 2));
   RWR_TRY(alloc_zero(c, &c->hfront, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->hbase, c->n_cap));
   RWR_TRY(alloc_zero(c, &c->sel, (size_t)c->n_cap * 2));

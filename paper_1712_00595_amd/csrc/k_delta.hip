@@ -357,6 +357,7 @@ __global__ void k_validate_plan(OrientPair P, int b1, Ctl *ctl) {
     t_dold[t] = d_old;
     t_dnew[t] = d_new;
     if (d_new > cap[u]) atomicAdd((unsigned long long *)&ctl->demand[orient], (unsigned long long)grown_cap(d_new));
+    if (orient == 0) atomicAdd((unsigned long long *)&ctl->seed_recs, (unsigned long long)d_old);
     if (heavy_limit > 0 && d_old <= heavy_limit && d_new > heavy_limit) atomicAdd(&ctl->heavy_stale, 1);
   }
 }
@@ -366,34 +367,40 @@ __global__ void k_validate_plan(OrientPair P, int b1, Ctl *ctl) {
 // chunks of SEED_CHUNK old neighbours; item 0 of a row also takes the row's
 // inserted neighbours.  k_seed_items counts the items of each touched row
 // (0 past the touched rows); an exclusive prefix sum gives each row's first
-// item, and the total is the entry at index max_rows.
+// item, and the total is the entry at index max_rows.  When the seed is
+// written as records (sort and reduce, below), a second prefix sum over the
+// old degrees gives each row's first record slot: row t owns d_old(t) slots
+// for its old neighbours followed by one per key of its batch segment, from
+// rec_off[t] + seg[t].
 #define SEED_CHUNK 1024
 
+// A record of the seed's sort-and-reduce form: receiving node v above rsh
+// bits, touched row t above 2 bits, the term's kind in the low 2 bits.  The
+// pad key (kind 3) sorts after every record.
+#define SEED_KEPT 0ull  // kept edge: (1-c) r(u) (1/d_new - 1/d_old)
+#define SEED_DEL 1ull   // deleted edge: -(1-c) r(u) / d_old
+#define SEED_INS 2ull   // inserted edge: (1-c) r(u) / d_new
+#define SEED_PAD (~0ull)
+__device__ __forceinline__ uint64_t seed_rec_key(int32_t v, int32_t t, uint64_t kind, int rsh) {
+  return ((uint64_t)v << rsh) | ((uint64_t)t << 2) | kind;
+}
+
 __global__ void k_seed_items(const int32_t *__restrict__ t_dold, const Ctl *__restrict__ ctl, int32_t max_rows,
-                             int32_t *__restrict__ items) {
+                             int32_t *__restrict__ items, int32_t *__restrict__ dcnt) {
   const int32_t nT = ctl->err ? 0 : ctl->nT[0];
-  for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t <= max_rows; t += gridDim.x * blockDim.x)
+  for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t <= max_rows; t += gridDim.x * blockDim.x) {
     items[t] = t < nT ? max(1, (t_dold[t] + SEED_CHUNK - 1) / SEED_CHUNK) : 0;
+    if (dcnt) dcnt[t] = t < nT ? t_dold[t] : 0;
+  }
 }
 
 // Small batches (max_rows < SEED_SMALL): counts and the exclusive prefix sum
 // in one workgroup of 1024 threads, four consecutive rows per thread (no
 // library scan, one launch less).
 #define SEED_SMALL 4096
-__global__ __launch_bounds__(1024) void k_seed_items_small(const int32_t *__restrict__ t_dold,
-                                                           const Ctl *__restrict__ ctl, int32_t max_rows,
-                                                           int32_t *__restrict__ item_off) {
-  __shared__ int32_t wsum[1024 / RWR_WAVE];
-  const int32_t nT = ctl->err ? 0 : ctl->nT[0];
+__device__ __forceinline__ int32_t block_exclusive_scan4(const int32_t (&v)[4], int32_t *wsum) {
   const int t = threadIdx.x, lane = t % RWR_WAVE, w = t / RWR_WAVE;
-  int32_t v[4];
-  int32_t s = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int32_t i = 4 * t + q;
-    v[q] = i < nT ? max(1, (t_dold[i] + SEED_CHUNK - 1) / SEED_CHUNK) : 0;
-    s += v[q];
-  }
+  const int32_t s = v[0] + v[1] + v[2] + v[3];
   int32_t incl = s;
   for (int off = 1; off < RWR_WAVE; off <<= 1) {
     const int32_t y = __shfl_up(incl, off, RWR_WAVE);
@@ -403,18 +410,43 @@ __global__ __launch_bounds__(1024) void k_seed_items_small(const int32_t *__rest
   __syncthreads();
   int32_t base = incl - s;
   for (int ww = 0; ww < w; ++ww) base += wsum[ww];
+  return base;
+}
+
+__global__ __launch_bounds__(1024) void k_seed_items_small(const int32_t *__restrict__ t_dold,
+                                                           const Ctl *__restrict__ ctl, int32_t max_rows,
+                                                           int32_t *__restrict__ item_off,
+                                                           int32_t *__restrict__ rec_off) {
+  __shared__ int32_t wsum[2][1024 / RWR_WAVE];
+  const int32_t nT = ctl->err ? 0 : ctl->nT[0];
+  const int t = threadIdx.x;
+  int32_t v[4], d[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int32_t i = 4 * t + q;
-    if (i <= max_rows) item_off[i] = base;
+    v[q] = i < nT ? max(1, (t_dold[i] + SEED_CHUNK - 1) / SEED_CHUNK) : 0;
+    d[q] = i < nT ? t_dold[i] : 0;
+  }
+  int32_t base = block_exclusive_scan4(v, wsum[0]);
+  int32_t dbase = rec_off ? block_exclusive_scan4(d, wsum[1]) : 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int32_t i = 4 * t + q;
+    if (i <= max_rows) {
+      item_off[i] = base;
+      if (rec_off) rec_off[i] = dbase;
+    }
     base += v[q];
+    dbase += d[q];
   }
 }
 
 // One wavefront per item, the waves looping over all items.  Lane layout:
 // column j = lane % S, edge slot p = lane / S.  Contributions go to ybuf
 // (FP64, atomically); receiving nodes are stamped.  With ybuf null only the
-// stamps (the offset support) and the cost model's sums are produced.
+// stamps (the offset support) and the cost model's sums are produced, and
+// with rec set every slot of the item gets its record (a structurally
+// nonzero term) or the pad key.
 template <int S>
 __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *__restrict__ seg,
                               const int32_t *__restrict__ row, const int32_t *__restrict__ t_dold,
@@ -422,7 +454,8 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
                               const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
                               const double *__restrict__ r, const double *__restrict__ rsub,
                               double *__restrict__ ybuf, int32_t *__restrict__ stamp, Ctl *ctl, int b1, double c1,
-                              int32_t max_rows) {
+                              int32_t max_rows, uint64_t *__restrict__ rec, const int32_t *__restrict__ rec_off,
+                              int rsh) {
   if (ctl->err) return;
   constexpr int P = RWR_WAVE / S;
   const int lane = threadIdx.x % RWR_WAVE;
@@ -445,17 +478,29 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
     const int32_t d_old = t_dold[t], d_new = t_dnew[t];
     // the scores without a deferred last iterate (rsub) when one is carried
     const double ru = rsub ? r[col_index(u, S, j)] - rsub[col_index(u, S, j)] : r[col_index(u, S, j)];
-    if (__ballot(ru != 0.0) == 0ull) continue;
+    const int32_t i1 = min(d_old, (k + 1) * SEED_CHUNK);
+    // this item's record slots: old neighbours k*SEED_CHUNK .. i1, and (item
+    // 0) the segment's keys
+    const int64_t rb = rec ? (int64_t)rec_off[t] + b : 0;
+    if (__ballot(ru != 0.0) == 0ull) {
+      if (rec && j == 0) {
+        for (int32_t i = k * SEED_CHUNK + p; i < i1; i += P) rec[rb + i] = SEED_PAD;
+        if (k == 0)
+          for (int32_t i = b + p; i < e; i += P) rec[rb + d_old + (i - b)] = SEED_PAD;
+      }
+      continue;
+    }
     const double w_old = d_old ? c1 * ru / (double)d_old : 0.0;
     const double w_new = d_new ? c1 * ru / (double)d_new : 0.0;
     const int32_t o = off[u];
-    const int32_t i1 = min(d_old, (k + 1) * SEED_CHUNK);
     for (int32_t i = k * SEED_CHUNK + p; i < i1; i += P) {
       const int32_t v = adj[o + i];
       const bool del = seg_find(keys, b, e, u, v, b1) >= 0;  // validated: a hit is a deletion
+      const bool nz = del || d_new != d_old;
       const double contrib = del ? -w_old : (w_new - w_old);
       if (ybuf && contrib != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], contrib);
-      if (j == 0 && (del || d_new != d_old)) stamp[v] = st;
+      if (j == 0 && nz) stamp[v] = st;
+      if (rec && j == 0) rec[rb + i] = nz ? seed_rec_key(v, t, del ? SEED_DEL : SEED_KEPT, rsh) : SEED_PAD;
     }
     if (k != 0) continue;
     if (p == 0) {
@@ -477,8 +522,9 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
     }
     for (int32_t i = b + p; i < e; i += P) {
       const uint64_t kk = keys[i];
-      if (!(kk & 1ull)) continue;
       const int32_t v = key_col(kk, b1);
+      if (rec && j == 0) rec[rb + d_old + (i - b)] = (kk & 1ull) ? seed_rec_key(v, t, SEED_INS, rsh) : SEED_PAD;
+      if (!(kk & 1ull)) continue;
       if (ybuf && w_new != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], w_new);
       if (j == 0) stamp[v] = st;
     }
@@ -487,102 +533,183 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
 
 // ------------------------------------------- offset seed in a fixed order
 // The offset seed without floating-point atomics, for runs that must not
-// depend on timing.  After the structural apply, every node v that the
-// support pass stamped gets q(v, j) with a plain store, summed in one fixed
-// order: the in-row of v in the new graph (each in-neighbour u whose row the
-// batch changed contributes (1-c) r(u) / d_new(u), minus (1-c) r(u) /
-// d_old(u) unless the edge (u, v) is inserted), then the edges into v that
-// the batch deletes (-(1-c) r(u) / d_old(u)), in key order; lane parts are
-// added by a fixed shuffle tree.  tmark[u] = 1 + the index of u's segment
-// among the changed rows (out orientation), imark[v] = 1 + the index of v's
-// segment among the changed rows of the pull orientation, 0 elsewhere.
-__global__ void k_mark_segments(const int32_t *__restrict__ row0, const int32_t *__restrict__ rowp, Ctl *ctl,
-                                int po, int32_t *__restrict__ tmark, int32_t *__restrict__ imark, int32_t value) {
-  if (ctl->err) return;
-  const int32_t n0 = ctl->nT[0], np = ctl->nT[po];
-  for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < max(n0, np); t += gridDim.x * blockDim.x) {
-    if (t < n0) tmark[row0[t]] = value ? t + 1 : 0;
-    if (t < np) imark[rowp[t]] = value ? t + 1 : 0;
-  }
-}
+// depend on timing (and for large batches, where it is also faster): the
+// support pass writes one record per structurally nonzero term of
+// (1-c)(B~^T - A~^T) r_old, the records are radix-sorted, and each node's
+// terms are summed in sorted order.  Keys are unique (one term per edge of a
+// touched row), so the sorted order, and with it every sum, does not depend
+// on the order the records were written in.
+//
+// The sorted records are cut into chunks of SEED_RED_CH; one group of S lanes
+// (lane = column) walks a chunk.  A node whose terms lie inside one chunk is
+// stored from there; a node whose terms cross chunk boundaries leaves its
+// first chunk's sum in tpart and each later chunk's sum in hpart, and
+// k_seed_fixup adds them in chunk order.
+#define SEED_RED_CH 128
+#define SEED_RED_U 8
 
 template <int S>
-__global__ void k_offset_pull(const int32_t *__restrict__ stamp, const Ctl *ctl, int32_t n, DevGraphView in,
-                              const int32_t *__restrict__ tmark, const int32_t *__restrict__ t_dold,
-                              const int32_t *__restrict__ t_dnew, const int32_t *__restrict__ imark,
-                              const uint64_t *__restrict__ ikeys, const int32_t *__restrict__ iseg, int b1,
-                              const double *__restrict__ r, const double *__restrict__ rsub,
-                              double *__restrict__ ybuf, double c1) {
+__global__ __launch_bounds__(256) void k_seed_reduce(const uint64_t *__restrict__ rec, int32_t n_rec, int rsh,
+                                                     uint64_t tmask, const int32_t *__restrict__ row,
+                                                     const int32_t *__restrict__ t_dold,
+                                                     const int32_t *__restrict__ t_dnew,
+                                                     const double *__restrict__ r, const double *__restrict__ rsub,
+                                                     double c1, double *__restrict__ ybuf,
+                                                     double *__restrict__ hpart, double *__restrict__ tpart,
+                                                     const Ctl *ctl) {
   if (ctl->err) return;
-  constexpr int P = RWR_WAVE / S;
-  const int lane = threadIdx.x % RWR_WAVE;
-  const int j = lane % S, p = lane / S;
-  const int32_t st = ctl->stamp;
-  auto score = [&](int u) -> double {
-    const int64_t k = col_index(u, S, j);
-    return rsub ? r[k] - rsub[k] : r[k];
-  };
-  const int nwv = gridDim.x * (blockDim.x / RWR_WAVE);
-  for (int base = ((blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE) * RWR_WAVE; base < n;
-       base += nwv * RWR_WAVE) {
-    // the stamped nodes among 64 consecutive ones, one at a time
-    unsigned long long m = __ballot(base + lane < n && stamp[base + lane] == st);
-    while (m) {
-      const int v = base + __builtin_ctzll(m);
-      m &= m - 1;
-      const int32_t sv = imark[v];
-      const int32_t b = sv ? iseg[sv - 1] : 0, e = sv ? iseg[sv] : 0;
-      const int o = in.off[v], d = in.len[v];
-      double q = 0.0;
-      for (int i = p; i < d; i += P) {
-        const int u = in.adj[o + i];
-        const int32_t tu = tmark[u];
-        if (!tu) continue;
-        const double ru = score(u);
-        const int d_old = t_dold[tu - 1], d_new = t_dnew[tu - 1];
-        const double w_new = d_new ? c1 * ru / (double)d_new : 0.0;
-        const double w_old = d_old ? c1 * ru / (double)d_old : 0.0;
-        const int32_t hit = sv ? seg_find(ikeys, b, e, v, u, b1) : -1;
-        q += (hit >= 0 && (ikeys[hit] & 1ull)) ? w_new : (w_new - w_old);
+  constexpr int G = RWR_WAVE / S;
+  const int lane = threadIdx.x % RWR_WAVE, j = lane % S, g = lane / S;
+  const int32_t nch = (n_rec + SEED_RED_CH - 1) / SEED_RED_CH;
+  const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / RWR_WAVE) * G;
+  for (int64_t c = (int64_t)((blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE) * G + g; c < nch; c += ngroups) {
+    const int32_t b = (int32_t)c * SEED_RED_CH, e = min(n_rec, b + SEED_RED_CH);
+    if ((rec[b] & 3ull) == 3ull) continue;  // pads only
+    int32_t cur = (int32_t)(rec[b] >> rsh);
+    const bool open_l = b > 0 && (int32_t)(rec[b - 1] >> rsh) == cur;
+    bool first_seg = true, done = false;
+    double acc = 0.0;
+    for (int32_t i0 = b; i0 < e && !done; i0 += SEED_RED_U) {
+      uint64_t kk[SEED_RED_U];
+      double a[SEED_RED_U], x[SEED_RED_U];
+#pragma unroll
+      for (int q = 0; q < SEED_RED_U; ++q) kk[q] = i0 + q < e ? rec[i0 + q] : SEED_PAD;
+#pragma unroll
+      for (int q = 0; q < SEED_RED_U; ++q) {
+        const uint64_t kind = kk[q] & 3ull;
+        a[q] = 0.0;
+        x[q] = 0.0;
+        if (kind == 3ull) continue;
+        const int32_t t = (int32_t)((kk[q] >> 2) & tmask);
+        const int32_t u = row[t], d_old = t_dold[t], d_new = t_dnew[t];
+        const double wo = d_old ? c1 / (double)d_old : 0.0, wn = d_new ? c1 / (double)d_new : 0.0;
+        a[q] = kind == SEED_KEPT ? wn - wo : (kind == SEED_DEL ? -wo : wn);
+        const int64_t k = col_index(u, S, j);
+        x[q] = rsub ? r[k] - rsub[k] : r[k];
       }
-      for (int32_t i = b + p; i < e; i += P) {
-        const uint64_t kk = ikeys[i];
-        if (kk & 1ull) continue;  // an insertion: counted in the in-row
-        const int u = key_col(kk, b1);
-        const int32_t tu = tmark[u];
-        const int d_old = tu ? t_dold[tu - 1] : 0;
-        if (d_old) q -= c1 * score(u) / (double)d_old;
+#pragma unroll
+      for (int q = 0; q < SEED_RED_U; ++q) {
+        if ((kk[q] & 3ull) == 3ull) {
+          done = true;
+          break;
+        }
+        const int32_t v = (int32_t)(kk[q] >> rsh);
+        if (v != cur) {
+          if (first_seg && open_l)
+            hpart[c * S + j] = acc;
+          else
+            ybuf[col_index(cur, S, j)] = acc;
+          first_seg = false;
+          cur = v;
+          acc = 0.0;
+        }
+        acc = fma(a[q], x[q], acc);
       }
-      for (int off = S; off < RWR_WAVE; off <<= 1) q += __shfl_xor(q, off, RWR_WAVE);
-      if (p == 0) ybuf[col_index(v, S, j)] = q;
     }
+    const bool open_r = e < n_rec && (rec[e] & 3ull) != 3ull && (int32_t)(rec[e] >> rsh) == cur;
+    if (first_seg && open_l)
+      hpart[c * S + j] = acc;
+    else if (open_r)
+      tpart[c * S + j] = acc;
+    else
+      ybuf[col_index(cur, S, j)] = acc;
   }
 }
 
-hipError_t launch_offset_pull(int S, const OrientPair &P, int po, const DevGraphView &in, const int32_t *stamp,
-                              const Ctl *ctl, int32_t n, int32_t *tmark, int32_t *imark, int b1, const double *r,
-                              const double *rsub, double *ybuf, double c1, int32_t max_rows, int grid,
-                              hipStream_t st) {
-  const int mg = std::max(1, std::min(1024, (max_rows + 255) / 256));
-  hipLaunchKernelGGL(k_mark_segments, dim3(mg), dim3(256), 0, st, P.o[0].row, P.o[po].row, (Ctl *)ctl, po, tmark,
-                     imark, 1);
-#define RWR_PULL_CASE(SS)                                                                                        \
+// Slots past the last touched row's: the batch's padding keys (entries a
+// node deletion skips, an undirected self-loop's second direction) own none,
+// so the count read back after validation can exceed the slots written.
+__global__ void k_seed_pad_tail(uint64_t *__restrict__ rec, const int32_t *__restrict__ rec_off,
+                                const int32_t *__restrict__ seg, const Ctl *ctl, int32_t n_rec) {
+  if (ctl->err) return;
+  const int32_t nT = ctl->nT[0];
+  const int64_t start = (int64_t)rec_off[nT] + seg[nT];
+  for (int64_t i = start + blockIdx.x * blockDim.x + threadIdx.x; i < n_rec; i += (int64_t)gridDim.x * blockDim.x)
+    rec[i] = SEED_PAD;
+}
+
+// One group per chunk whose last node continues into the next chunk and
+// began in this one: that node's sum, chunk by chunk in order.
+template <int S>
+__global__ __launch_bounds__(256) void k_seed_fixup(const uint64_t *__restrict__ rec, int32_t n_rec, int rsh,
+                                                    const double *__restrict__ hpart,
+                                                    const double *__restrict__ tpart, double *__restrict__ ybuf,
+                                                    const Ctl *ctl) {
+  if (ctl->err) return;
+  constexpr int G = RWR_WAVE / S;
+  const int lane = threadIdx.x % RWR_WAVE, j = lane % S, g = lane / S;
+  const int32_t nch = (n_rec + SEED_RED_CH - 1) / SEED_RED_CH;
+  const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / RWR_WAVE) * G;
+  auto node = [&](int32_t i) -> int64_t {  // -1 for a pad
+    const uint64_t k = rec[i];
+    return (k & 3ull) == 3ull ? -1 : (int64_t)(k >> rsh);
+  };
+  for (int64_t c = (int64_t)((blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE) * G + g; c < nch; c += ngroups) {
+    const int32_t b = (int32_t)c * SEED_RED_CH, e = min(n_rec, b + SEED_RED_CH);
+    if (e >= n_rec) continue;
+    const int64_t v = node(e - 1);
+    if (v < 0 || node(e) != v) continue;                        // the last node ends here
+    if (node(b) == v && b > 0 && node(b - 1) == v) continue;  // it began in an earlier chunk
+    double s = tpart[c * S + j];
+    for (int32_t cc = (int32_t)c + 1; cc < nch; ++cc) {
+      s += hpart[(int64_t)cc * S + j];
+      const int32_t ee = min(n_rec, (cc + 1) * SEED_RED_CH);
+      if (ee >= n_rec || node(ee - 1) != v || node(ee) != v) break;
+    }
+    ybuf[col_index(v, S, j)] = s;
+  }
+}
+
+// bits that hold every value in [0, v]
+static int width_of(int64_t v) {
+  int b = 1;
+  while ((1ll << b) <= v) ++b;
+  return b;
+}
+
+int seed_rec_shift(int32_t max_rows) { return 2 + width_of(std::max(1, max_rows)); }
+
+int64_t seed_part_len(int64_t n_rec, int S) { return (n_rec + SEED_RED_CH - 1) / SEED_RED_CH * S; }
+
+size_t seed_sort_temp_bytes(int64_t n_rec) {
+  size_t a = 0;
+  (void)hipcub::DeviceRadixSort::SortKeys((void *)nullptr, a, (uint64_t *)nullptr, (uint64_t *)nullptr,
+                                          (int)std::min<int64_t>(n_rec, INT32_MAX), 0, 64);
+  return a;
+}
+
+hipError_t launch_seed_sort_reduce(int S, uint64_t *rec, uint64_t *rec_alt, int32_t n_rec, int32_t max_rows,
+                                   int32_t n_nodes, const int32_t *rec_off, const int32_t *seg,
+                                   const int32_t *row, const int32_t *t_dold, const int32_t *t_dnew,
+                                   const double *r, const double *rsub, double c1, double *ybuf, double *hpart,
+                                   double *tpart, void *temp, size_t temp_bytes, const Ctl *ctl, int grid,
+                                   hipStream_t st) {
+  if (n_rec <= 0) return hipSuccess;
+  const int rsh = seed_rec_shift(max_rows);
+  const int end_bit = rsh + width_of(std::max(1, n_nodes - 1));
+  if (end_bit > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_seed_pad_tail, dim3(64), dim3(256), 0, st, rec, rec_off, seg, ctl, n_rec);
+  size_t bytes = temp_bytes;
+  hipError_t err = hipcub::DeviceRadixSort::SortKeys(temp, bytes, rec, rec_alt, n_rec, 0, end_bit, st);
+  if (err != hipSuccess) return err;
+  const uint64_t tmask = (1ull << (rsh - 2)) - 1;
+#define RWR_RED_CASE(SS)                                                                                         \
   case SS:                                                                                                       \
-    hipLaunchKernelGGL(k_offset_pull<SS>, dim3(grid), dim3(256), 0, st, stamp, ctl, n, in, tmark, P.o[0].t_dold, \
-                       P.o[0].t_dnew, imark, P.o[po].keys, P.o[po].seg, b1, r, rsub, ybuf, c1);                   \
+    hipLaunchKernelGGL(k_seed_reduce<SS>, dim3(grid), dim3(256), 0, st, rec_alt, n_rec, rsh, tmask, row, t_dold, \
+                       t_dnew, r, rsub, c1, ybuf, hpart, tpart, ctl);                                            \
+    hipLaunchKernelGGL(k_seed_fixup<SS>, dim3(grid), dim3(256), 0, st, rec_alt, n_rec, rsh, hpart, tpart, ybuf,  \
+                       ctl);                                                                                     \
     break;
   switch (S) {
-    RWR_PULL_CASE(1)
-    RWR_PULL_CASE(2)
-    RWR_PULL_CASE(4)
-    RWR_PULL_CASE(8)
-    RWR_PULL_CASE(16)
-    RWR_PULL_CASE(32)
-    RWR_PULL_CASE(64)
+    RWR_RED_CASE(1)
+    RWR_RED_CASE(2)
+    RWR_RED_CASE(4)
+    RWR_RED_CASE(8)
+    RWR_RED_CASE(16)
+    RWR_RED_CASE(32)
+    RWR_RED_CASE(64)
   }
-#undef RWR_PULL_CASE
-  hipLaunchKernelGGL(k_mark_segments, dim3(mg), dim3(256), 0, st, P.o[0].row, P.o[po].row, (Ctl *)ctl, po, tmark,
-                     imark, 0);
+#undef RWR_RED_CASE
   return hipGetLastError();
 }
 
@@ -663,6 +790,7 @@ __global__ void k_reset_batch(Ctl *ctl, int demand_only) {
   }
   ctl->demand[0] = 0;
   ctl->demand[1] = 0;
+  ctl->seed_recs = 0;
   ctl->heavy_stale = 0;
   if (!demand_only) {
     ctl->node_dels = 0;
@@ -753,29 +881,38 @@ template <int S>
 static void offset_seed_s(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
                           const int32_t *t_dnew, const int32_t *item_off, const DevGraphView &g, const double *r,
                           const double *rsub, double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1,
-                          int32_t max_rows, int grid, hipStream_t st) {
+                          int32_t max_rows, uint64_t *rec, const int32_t *rec_off, int rsh, int grid,
+                          hipStream_t st) {
   hipLaunchKernelGGL(k_offset_seed<S>, dim3(grid), dim3(256), 0, st, keys, seg, row, t_dold, t_dnew, item_off, g.off,
-                     g.adj, r, rsub, ybuf, stamp, ctl, b1, c1, max_rows);
+                     g.adj, r, rsub, ybuf, stamp, ctl, b1, c1, max_rows, rec, rec_off, rsh);
 }
 
 hipError_t launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row,
                               const int32_t *t_dold, const int32_t *t_dnew, const DevGraphView &g, const double *r,
                               const double *rsub, double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1,
-                              int32_t max_rows, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
-                              int grid, hipStream_t st) {
+                              int32_t max_rows, int32_t *items, int32_t *item_off, uint64_t *rec, int32_t *dcnt,
+                              int32_t *rec_off, void *temp, size_t temp_bytes, int grid, hipStream_t st) {
   if (max_rows <= 0) return hipSuccess;
   if (max_rows < SEED_SMALL) {
-    hipLaunchKernelGGL(k_seed_items_small, dim3(1), dim3(1024), 0, st, t_dold, ctl, max_rows, item_off);
+    hipLaunchKernelGGL(k_seed_items_small, dim3(1), dim3(1024), 0, st, t_dold, ctl, max_rows, item_off,
+                       rec ? rec_off : nullptr);
   } else {
     hipLaunchKernelGGL(k_seed_items, dim3(std::min(4096, (max_rows + 256) / 256)), dim3(256), 0, st, t_dold, ctl,
-                       max_rows, items);
-    hipError_t e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, items, item_off, max_rows + 1, st);
+                       max_rows, items, rec ? dcnt : nullptr);
+    size_t bytes = temp_bytes;
+    hipError_t e = hipcub::DeviceScan::ExclusiveSum(temp, bytes, items, item_off, max_rows + 1, st);
     if (e != hipSuccess) return e;
+    if (rec) {
+      bytes = temp_bytes;
+      e = hipcub::DeviceScan::ExclusiveSum(temp, bytes, dcnt, rec_off, max_rows + 1, st);
+      if (e != hipSuccess) return e;
+    }
   }
+  const int rsh = seed_rec_shift(max_rows);
 #define RWR_SEED_CASE(SS)                                                                                        \
   case SS:                                                                                                       \
     offset_seed_s<SS>(keys, seg, row, t_dold, t_dnew, item_off, g, r, rsub, ybuf, stamp, ctl, b1, c1, max_rows, \
-                      grid, st);                                                                                 \
+                      rec, rec_off, rsh, grid, st);                                                              \
     break;
   switch (S) {
     RWR_SEED_CASE(1)

@@ -117,27 +117,36 @@ struct OrientPair {
   OrientArgs o[2];
 };
 void launch_validate_plan(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st);
-// q_offset of r - rsub (rsub may be null) into ybuf; touched rows cut into
-// chunks (items: max_rows + 1 ints, item_off: max_rows + 1 ints, temp:
-// seed_scan_temp_bytes(max_rows))
+// q_offset of r - rsub (rsub may be null) into ybuf (atomically; ybuf null:
+// the support stamps and cost-model sums only); touched rows cut into chunks
+// (items, item_off: max_rows + 1 ints, temp: seed_scan_temp_bytes(max_rows)).
+// rec (optional): the seed's records for launch_seed_sort_reduce, one slot per
+// old neighbour and batch key of each touched row (ctl->seed_recs + the number
+// of keys, read back after validation), with dcnt, rec_off: max_rows + 1 ints
 hipError_t launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row,
                               const int32_t *t_dold, const int32_t *t_dnew, const DevGraphView &g, const double *r,
                               const double *rsub, double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1,
-                              int32_t max_rows, int32_t *items, int32_t *item_off, void *temp, size_t temp_bytes,
-                              int grid, hipStream_t st);
+                              int32_t max_rows, int32_t *items, int32_t *item_off, uint64_t *rec, int32_t *dcnt,
+                              int32_t *rec_off, void *temp, size_t temp_bytes, int grid, hipStream_t st);
 size_t seed_scan_temp_bytes(int32_t max_rows);
 // workgroups of the heavy-row epilogue (one (row, column) pair per thread);
 // its partials follow the sweep's, so partial buffers hold this many more
 constexpr int HEAVY_EPI_MAX_GRID = 2048;
 void launch_apply(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st);
-// the offset seed summed in a fixed order (no atomics), after the structural
-// apply and a support-only launch_offset_seed (ybuf null): ybuf of every
-// stamped node; tmark/imark are zero node arrays, left zero; po = pull
-// orientation (its keys hold each node's inserted and deleted in-edges)
-hipError_t launch_offset_pull(int S, const OrientPair &P, int po, const DevGraphView &in, const int32_t *stamp,
-                              const Ctl *ctl, int32_t n, int32_t *tmark, int32_t *imark, int b1, const double *r,
-                              const double *rsub, double *ybuf, double c1, int32_t max_rows, int grid,
-                              hipStream_t st);
+// the offset seed summed in a fixed order (no atomics) from the records that
+// launch_offset_seed wrote into rec (n_rec slots; those past the last touched
+// row's, located by rec_off and seg, become pads): sorted into
+// rec_alt, each node's terms added in sorted order and stored into ybuf
+// (plain stores; zero elsewhere).  hpart, tpart: seed_part_len(n_rec, S)
+// doubles each; temp: seed_sort_temp_bytes(n_rec)
+hipError_t launch_seed_sort_reduce(int S, uint64_t *rec, uint64_t *rec_alt, int32_t n_rec, int32_t max_rows,
+                                   int32_t n_nodes, const int32_t *rec_off, const int32_t *seg,
+                                   const int32_t *row, const int32_t *t_dold, const int32_t *t_dnew,
+                                   const double *r, const double *rsub, double c1, double *ybuf, double *hpart,
+                                   double *tpart, void *temp, size_t temp_bytes, const Ctl *ctl, int grid,
+                                   hipStream_t st);
+int64_t seed_part_len(int64_t n_rec, int S);
+size_t seed_sort_temp_bytes(int64_t n_rec);
 
 // ---- propagation (k_prop.hip); fp64 selects the propagation type
 // hist_base: first row of the norm history this run writes (0 for update
