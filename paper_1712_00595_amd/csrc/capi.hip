@@ -150,7 +150,9 @@ struct rwr_ctx {
   // columns of a run that may leave its last iterate retire together
   // (RWR_LOCKSTEP = 0: each at its own stop test)
   bool lockstep = true;
-  uint64_t pend = 0;         // columns with a pending vector in gbuf
+  // columns with a pending vector in gbuf; gbuf's other columns hold stale
+  // values, and every reader takes gbuf only in the columns of pend
+  uint64_t pend = 0;
   int tail_slot = -1;        // x buffer holding deferred last iterates (-1: none)
   uint64_t tail_cols = 0;    // their columns
   double pend_b[RWR_MAX_COLS] = {};   // error bound each pending (or deferred) vector carries
@@ -2249,14 +2251,15 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   const double *rsub = c->pend ? c->gbuf : nullptr;
   if (nkeys > 0)
     HIP_TRY(c, launch_offset_seed(c->S, c->keys[0], c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->g[0].v,
-                                  c->r, rsub, c->seed_sorted ? nullptr : c->ybuf, c->stamp, c->ctl, b1,
+                                  c->r, rsub, c->pend, c->seed_sorted ? nullptr : c->ybuf, c->stamp, c->ctl, b1,
                                   1.0 - c->cfg.c, (int32_t)nkeys, c->flags, c->pos,
                                   c->seed_sorted ? c->srec[0] : nullptr, c->sdcnt, c->sroff, c->temp,
                                   c->temp_bytes, 4 * c->n_cu, c->stream));
   if (c->seed_sorted) {
     const int64_t pl = seed_part_len(n_rec, c->S);
     HIP_TRY(c, launch_seed_sort_reduce(c->S, c->srec[0], c->srec[1], (int32_t)n_rec, (int32_t)nkeys, c->n, c->sroff,
-                                       c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->r, rsub, 1.0 - c->cfg.c,
+                                       c->seg[0], c->row[0], c->t_dold[0], c->t_dnew[0], c->r, rsub, c->pend,
+                                       1.0 - c->cfg.c,
                                        c->ybuf, c->spart, c->spart + pl, c->temp, c->temp_bytes, c->ctl,
                                        8 * c->n_cu, c->stream));
   }

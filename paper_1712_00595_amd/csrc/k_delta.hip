@@ -300,6 +300,35 @@ __device__ __forceinline__ int32_t seg_find(const uint64_t *__restrict__ keys, i
   return (lo < e && (keys[lo] >> 1) == (target >> 1)) ? lo : -1;
 }
 
+// seg_find for SEG_W columns at once (a negative column is skipped: -1): the
+// searches halve the same range in lockstep, so their loads are in flight
+// together
+#define SEG_W 4
+__device__ __forceinline__ void seg_find_w(const uint64_t *__restrict__ keys, int32_t b, int32_t e, int32_t r,
+                                           const int32_t (&col)[SEG_W], int b1, int32_t (&pos)[SEG_W]) {
+  uint64_t tg[SEG_W];
+  int32_t base[SEG_W];
+#pragma unroll
+  for (int q = 0; q < SEG_W; ++q) {
+    tg[q] = ((uint64_t)r << b1) | ((uint64_t)max(col[q], 0) << 1);
+    base[q] = b;
+    pos[q] = -1;
+  }
+  if (e <= b) return;
+  for (int32_t n = e - b; n > 1;) {
+    const int32_t half = n >> 1;
+#pragma unroll
+    for (int q = 0; q < SEG_W; ++q) base[q] = keys[base[q] + half] < tg[q] ? base[q] + half : base[q];
+    n -= half;
+  }
+#pragma unroll
+  for (int q = 0; q < SEG_W; ++q) {
+    const uint64_t k = keys[base[q]];
+    const int32_t at = k < tg[q] ? base[q] + 1 : base[q];
+    if (col[q] >= 0 && at < e && (keys[at] >> 1) == (tg[q] >> 1)) pos[q] = at;
+  }
+}
+
 __device__ __forceinline__ int32_t grown_cap(int32_t d) { return d + max(4, d >> 2); }
 
 // ------------------------------------------------- validation and planning
@@ -332,16 +361,24 @@ __global__ void k_validate_plan(OrientPair P, int b1, Ctl *ctl) {
   int found = 0;
   int exists = 0;
   if (check) {
+    // SEG_W x 64 neighbours per step: their loads and searches in flight together
     const int32_t o = off[u];
-    for (int32_t i = lane; i < d_old; i += RWR_WAVE) {
-      const int32_t v = adj[o + i];
-      const int32_t p = seg_find(keys, b, e, u, v, b1);
-      if (p >= 0) {
-        if (keys[p] & 1ull)
-          exists = 1;
-        else
-          ++found;
+    for (int32_t i0 = 0; i0 < d_old; i0 += SEG_W * RWR_WAVE) {
+      int32_t v[SEG_W], p[SEG_W];
+#pragma unroll
+      for (int q = 0; q < SEG_W; ++q) {
+        const int32_t i = i0 + q * RWR_WAVE + lane;
+        v[q] = i < d_old ? adj[o + i] : -1;
       }
+      seg_find_w(keys, b, e, u, v, b1, p);
+#pragma unroll
+      for (int q = 0; q < SEG_W; ++q)
+        if (p[q] >= 0) {
+          if (keys[p[q]] & 1ull)
+            exists = 1;
+          else
+            ++found;
+        }
     }
     found = wave_xor_sum(found, 1, RWR_WAVE);
     exists = wave_xor_sum(exists, 1, RWR_WAVE);
@@ -441,12 +478,14 @@ __global__ __launch_bounds__(1024) void k_seed_items_small(const int32_t *__rest
   }
 }
 
-// One wavefront per item, the waves looping over all items.  Lane layout:
-// column j = lane % S, edge slot p = lane / S.  Contributions go to ybuf
-// (FP64, atomically); receiving nodes are stamped.  With ybuf null only the
-// stamps (the offset support) and the cost model's sums are produced, and
-// with rec set every slot of the item gets its record (a structurally
-// nonzero term) or the pad key.
+// One wavefront per item, the waves looping over all items.  The item's old
+// neighbours are tested 64 at a time, one per lane (is the edge deleted?);
+// each lane stamps its receiving node and writes its record slot.  The
+// contributions to ybuf (FP64, atomically) then take the lane layout column
+// j = lane % S, edge slot p = lane / S, P entries per step.  With ybuf null
+// only the stamps (the offset support), the records (rec set: every slot of
+// the item gets its record, a structurally nonzero term, or the pad key) and
+// the cost model's sums are produced.
 template <int S>
 __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *__restrict__ seg,
                               const int32_t *__restrict__ row, const int32_t *__restrict__ t_dold,
@@ -455,7 +494,7 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
                               const double *__restrict__ r, const double *__restrict__ rsub,
                               double *__restrict__ ybuf, int32_t *__restrict__ stamp, Ctl *ctl, int b1, double c1,
                               int32_t max_rows, uint64_t *__restrict__ rec, const int32_t *__restrict__ rec_off,
-                              int rsh) {
+                              int rsh, uint64_t rmask) {
   if (ctl->err) return;
   constexpr int P = RWR_WAVE / S;
   const int lane = threadIdx.x % RWR_WAVE;
@@ -476,31 +515,44 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
     const int32_t k = it - item_off[t];
     const int32_t u = row[t], b = seg[t], e = seg[t + 1];
     const int32_t d_old = t_dold[t], d_new = t_dnew[t];
-    // the scores without a deferred last iterate (rsub) when one is carried
-    const double ru = rsub ? r[col_index(u, S, j)] - rsub[col_index(u, S, j)] : r[col_index(u, S, j)];
+    // the scores without a carried vector (rsub, in the columns of rmask)
+    const double ru = rsub && ((rmask >> j) & 1ull) ? r[col_index(u, S, j)] - rsub[col_index(u, S, j)]
+                                                    : r[col_index(u, S, j)];
     const int32_t i1 = min(d_old, (k + 1) * SEED_CHUNK);
     // this item's record slots: old neighbours k*SEED_CHUNK .. i1, and (item
     // 0) the segment's keys
     const int64_t rb = rec ? (int64_t)rec_off[t] + b : 0;
     if (__ballot(ru != 0.0) == 0ull) {
-      if (rec && j == 0) {
-        for (int32_t i = k * SEED_CHUNK + p; i < i1; i += P) rec[rb + i] = SEED_PAD;
+      if (rec) {
+        for (int32_t i = k * SEED_CHUNK + lane; i < i1; i += RWR_WAVE) rec[rb + i] = SEED_PAD;
         if (k == 0)
-          for (int32_t i = b + p; i < e; i += P) rec[rb + d_old + (i - b)] = SEED_PAD;
+          for (int32_t i = b + lane; i < e; i += RWR_WAVE) rec[rb + d_old + (i - b)] = SEED_PAD;
       }
       continue;
     }
     const double w_old = d_old ? c1 * ru / (double)d_old : 0.0;
     const double w_new = d_new ? c1 * ru / (double)d_new : 0.0;
     const int32_t o = off[u];
-    for (int32_t i = k * SEED_CHUNK + p; i < i1; i += P) {
-      const int32_t v = adj[o + i];
-      const bool del = seg_find(keys, b, e, u, v, b1) >= 0;  // validated: a hit is a deletion
-      const bool nz = del || d_new != d_old;
-      const double contrib = del ? -w_old : (w_new - w_old);
-      if (ybuf && contrib != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], contrib);
-      if (j == 0 && nz) stamp[v] = st;
-      if (rec && j == 0) rec[rb + i] = nz ? seed_rec_key(v, t, del ? SEED_DEL : SEED_KEPT, rsh) : SEED_PAD;
+    for (int32_t i0 = k * SEED_CHUNK; i0 < i1; i0 += RWR_WAVE) {
+      const int32_t il = i0 + lane;
+      int32_t vl = 0;
+      int dl = 0;
+      if (il < i1) {
+        vl = adj[o + il];
+        dl = seg_find(keys, b, e, u, vl, b1) >= 0;  // validated: a hit is a deletion
+        const bool nz = dl || d_new != d_old;
+        if (nz) stamp[vl] = st;
+        if (rec) rec[rb + il] = nz ? seed_rec_key(vl, t, dl ? SEED_DEL : SEED_KEPT, rsh) : SEED_PAD;
+      }
+      if (!ybuf) continue;
+      const int cnt = min(RWR_WAVE, i1 - i0);
+      for (int s0 = 0; s0 < cnt; s0 += P) {
+        const int src = s0 + p;
+        const int32_t v = __shfl(vl, src, RWR_WAVE);
+        const int del = __shfl(dl, src, RWR_WAVE);
+        const double contrib = del ? -w_old : (w_new - w_old);
+        if (src < cnt && contrib != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], contrib);
+      }
     }
     if (k != 0) continue;
     if (p == 0) {
@@ -520,14 +572,17 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
       else
         atomicAdd((unsigned long long *)&ctl->dr_fix[j], (unsigned long long)llrint(du * fabs(ru) * 0x1p52));
     }
-    for (int32_t i = b + p; i < e; i += P) {
+    for (int32_t i = b + lane; i < e; i += RWR_WAVE) {
       const uint64_t kk = keys[i];
       const int32_t v = key_col(kk, b1);
-      if (rec && j == 0) rec[rb + d_old + (i - b)] = (kk & 1ull) ? seed_rec_key(v, t, SEED_INS, rsh) : SEED_PAD;
-      if (!(kk & 1ull)) continue;
-      if (ybuf && w_new != 0.0) atomic_add_f64(&ybuf[col_index(v, S, j)], w_new);
-      if (j == 0) stamp[v] = st;
+      if (rec) rec[rb + d_old + (i - b)] = (kk & 1ull) ? seed_rec_key(v, t, SEED_INS, rsh) : SEED_PAD;
+      if (kk & 1ull) stamp[v] = st;
     }
+    if (ybuf && w_new != 0.0)
+      for (int32_t i = b + p; i < e; i += P) {
+        const uint64_t kk = keys[i];
+        if (kk & 1ull) atomic_add_f64(&ybuf[col_index(key_col(kk, b1), S, j)], w_new);
+      }
   }
 }
 
@@ -546,7 +601,7 @@ __global__ void k_offset_seed(const uint64_t *__restrict__ keys, const int32_t *
 // first chunk's sum in tpart and each later chunk's sum in hpart, and
 // k_seed_fixup adds them in chunk order.
 #define SEED_RED_CH 128
-#define SEED_RED_U 8
+#define SEED_RED_U 16
 
 template <int S>
 __global__ __launch_bounds__(256) void k_seed_reduce(const uint64_t *__restrict__ rec, int32_t n_rec, int rsh,
@@ -554,12 +609,14 @@ __global__ __launch_bounds__(256) void k_seed_reduce(const uint64_t *__restrict_
                                                      const int32_t *__restrict__ t_dold,
                                                      const int32_t *__restrict__ t_dnew,
                                                      const double *__restrict__ r, const double *__restrict__ rsub,
-                                                     double c1, double *__restrict__ ybuf,
+                                                     uint64_t rmask, double c1, double *__restrict__ ybuf,
                                                      double *__restrict__ hpart, double *__restrict__ tpart,
                                                      const Ctl *ctl) {
   if (ctl->err) return;
   constexpr int G = RWR_WAVE / S;
+  constexpr int U = S < SEED_RED_U ? S : SEED_RED_U;
   const int lane = threadIdx.x % RWR_WAVE, j = lane % S, g = lane / S;
+  const double *__restrict__ sub = (rmask >> j) & 1ull ? rsub : nullptr;
   const int32_t nch = (n_rec + SEED_RED_CH - 1) / SEED_RED_CH;
   const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / RWR_WAVE) * G;
   for (int64_t c = (int64_t)((blockIdx.x * blockDim.x + threadIdx.x) / RWR_WAVE) * G + g; c < nch; c += ngroups) {
@@ -569,41 +626,52 @@ __global__ __launch_bounds__(256) void k_seed_reduce(const uint64_t *__restrict_
     const bool open_l = b > 0 && (int32_t)(rec[b - 1] >> rsh) == cur;
     bool first_seg = true, done = false;
     double acc = 0.0;
-    for (int32_t i0 = b; i0 < e && !done; i0 += SEED_RED_U) {
-      uint64_t kk[SEED_RED_U];
-      double a[SEED_RED_U], x[SEED_RED_U];
-#pragma unroll
-      for (int q = 0; q < SEED_RED_U; ++q) kk[q] = i0 + q < e ? rec[i0 + q] : SEED_PAD;
-#pragma unroll
-      for (int q = 0; q < SEED_RED_U; ++q) {
-        const uint64_t kind = kk[q] & 3ull;
-        a[q] = 0.0;
-        x[q] = 0.0;
-        if (kind == 3ull) continue;
-        const int32_t t = (int32_t)((kk[q] >> 2) & tmask);
-        const int32_t u = row[t], d_old = t_dold[t], d_new = t_dnew[t];
+    for (int32_t i0 = b; i0 < e && !done; i0 += S) {
+      // decode S records, one per lane of the group: receiving node (-1 for
+      // a pad), source node, coefficient of its score
+      const int32_t ir = i0 + j;
+      const uint64_t kk = ir < e ? rec[ir] : SEED_PAD;
+      int32_t vv = -1, uu = 0;
+      double aa = 0.0;
+      if ((kk & 3ull) != 3ull) {
+        const int32_t t = (int32_t)((kk >> 2) & tmask);
+        const uint64_t kind = kk & 3ull;
+        vv = (int32_t)(kk >> rsh);
+        uu = row[t];
+        const int32_t d_old = t_dold[t], d_new = t_dnew[t];
         const double wo = d_old ? c1 / (double)d_old : 0.0, wn = d_new ? c1 / (double)d_new : 0.0;
-        a[q] = kind == SEED_KEPT ? wn - wo : (kind == SEED_DEL ? -wo : wn);
-        const int64_t k = col_index(u, S, j);
-        x[q] = rsub ? r[k] - rsub[k] : r[k];
+        aa = kind == SEED_KEPT ? wn - wo : (kind == SEED_DEL ? -wo : wn);
       }
+      // then the group's lanes are columns: U records' scores in flight, summed in order
+      for (int k0 = 0; k0 < S && !done; k0 += U) {
+        int32_t vk[U];
+        double ak[U], x[U];
 #pragma unroll
-      for (int q = 0; q < SEED_RED_U; ++q) {
-        if ((kk[q] & 3ull) == 3ull) {
-          done = true;
-          break;
+        for (int q = 0; q < U; ++q) {
+          const int src = g * S + k0 + q;
+          vk[q] = __shfl(vv, src, RWR_WAVE);
+          const int32_t uk = __shfl(uu, src, RWR_WAVE);
+          ak[q] = __shfl(aa, src, RWR_WAVE);
+          const int64_t kx = col_index(uk, S, j);
+          x[q] = vk[q] < 0 ? 0.0 : (sub ? r[kx] - sub[kx] : r[kx]);
         }
-        const int32_t v = (int32_t)(kk[q] >> rsh);
-        if (v != cur) {
-          if (first_seg && open_l)
-            hpart[c * S + j] = acc;
-          else
-            ybuf[col_index(cur, S, j)] = acc;
-          first_seg = false;
-          cur = v;
-          acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          if (done || vk[q] < 0) {
+            done = true;
+            continue;
+          }
+          if (vk[q] != cur) {
+            if (first_seg && open_l)
+              hpart[c * S + j] = acc;
+            else
+              ybuf[col_index(cur, S, j)] = acc;
+            first_seg = false;
+            cur = vk[q];
+            acc = 0.0;
+          }
+          acc = fma(ak[q], x[q], acc);
         }
-        acc = fma(a[q], x[q], acc);
       }
     }
     const bool open_r = e < n_rec && (rec[e] & 3ull) != 3ull && (int32_t)(rec[e] >> rsh) == cur;
@@ -681,9 +749,9 @@ size_t seed_sort_temp_bytes(int64_t n_rec) {
 hipError_t launch_seed_sort_reduce(int S, uint64_t *rec, uint64_t *rec_alt, int32_t n_rec, int32_t max_rows,
                                    int32_t n_nodes, const int32_t *rec_off, const int32_t *seg,
                                    const int32_t *row, const int32_t *t_dold, const int32_t *t_dnew,
-                                   const double *r, const double *rsub, double c1, double *ybuf, double *hpart,
-                                   double *tpart, void *temp, size_t temp_bytes, const Ctl *ctl, int grid,
-                                   hipStream_t st) {
+                                   const double *r, const double *rsub, uint64_t rmask, double c1, double *ybuf,
+                                   double *hpart, double *tpart, void *temp, size_t temp_bytes, const Ctl *ctl,
+                                   int grid, hipStream_t st) {
   if (n_rec <= 0) return hipSuccess;
   const int rsh = seed_rec_shift(max_rows);
   const int end_bit = rsh + width_of(std::max(1, n_nodes - 1));
@@ -696,7 +764,7 @@ hipError_t launch_seed_sort_reduce(int S, uint64_t *rec, uint64_t *rec_alt, int3
 #define RWR_RED_CASE(SS)                                                                                         \
   case SS:                                                                                                       \
     hipLaunchKernelGGL(k_seed_reduce<SS>, dim3(grid), dim3(256), 0, st, rec_alt, n_rec, rsh, tmask, row, t_dold, \
-                       t_dnew, r, rsub, c1, ybuf, hpart, tpart, ctl);                                            \
+                       t_dnew, r, rsub, rmask, c1, ybuf, hpart, tpart, ctl);                                     \
     hipLaunchKernelGGL(k_seed_fixup<SS>, dim3(grid), dim3(256), 0, st, rec_alt, n_rec, rsh, hpart, tpart, ybuf,  \
                        ctl);                                                                                     \
     break;
@@ -753,18 +821,27 @@ __global__ void k_apply(OrientPair P, int b1, Ctl *ctl) {
     base = (int32_t)pos;
   }
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (RWR_WAVE - lane));
-  int32_t w = 0;
-  for (int32_t i0 = 0; i0 < d_old; i0 += RWR_WAVE) {
-    const int32_t i = i0 + lane;
-    int32_t v = -1;
-    bool keep = false;
-    if (i < d_old) {
-      v = adj[o + i];
-      keep = seg_find(keys, b, e, u, v, b1) < 0;
+  // a row that keeps every entry in place only appends
+  const int32_t n_del = ((e - b) - (d_new - d_old)) / 2;
+  const bool scan = move || n_del != 0;
+  int32_t w = scan ? 0 : d_old;
+  for (int32_t i0 = 0; scan && i0 < d_old; i0 += SEG_W * RWR_WAVE) {
+    // SEG_W x 64 entries read before any is written: a kept entry moves to a
+    // position at or below its own, which this or an earlier step has read
+    int32_t v[SEG_W], p[SEG_W];
+#pragma unroll
+    for (int q = 0; q < SEG_W; ++q) {
+      const int32_t i = i0 + q * RWR_WAVE + lane;
+      v[q] = i < d_old ? adj[o + i] : -1;
     }
-    const uint64_t m = __ballot(keep);
-    if (keep) adj[base + w + __popcll(m & lt_mask)] = v;
-    w += __popcll(m);
+    seg_find_w(keys, b, e, u, v, b1, p);
+#pragma unroll
+    for (int q = 0; q < SEG_W; ++q) {
+      const bool keep = v[q] >= 0 && p[q] < 0;
+      const uint64_t m = __ballot(keep);
+      if (keep) adj[base + w + __popcll(m & lt_mask)] = v[q];
+      w += __popcll(m);
+    }
   }
   for (int32_t i0 = b; i0 < e; i0 += RWR_WAVE) {
     const int32_t i = i0 + lane;
@@ -881,17 +958,18 @@ template <int S>
 static void offset_seed_s(const uint64_t *keys, const int32_t *seg, const int32_t *row, const int32_t *t_dold,
                           const int32_t *t_dnew, const int32_t *item_off, const DevGraphView &g, const double *r,
                           const double *rsub, double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1,
-                          int32_t max_rows, uint64_t *rec, const int32_t *rec_off, int rsh, int grid,
-                          hipStream_t st) {
+                          int32_t max_rows, uint64_t *rec, const int32_t *rec_off, int rsh, uint64_t rmask,
+                          int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_offset_seed<S>, dim3(grid), dim3(256), 0, st, keys, seg, row, t_dold, t_dnew, item_off, g.off,
-                     g.adj, r, rsub, ybuf, stamp, ctl, b1, c1, max_rows, rec, rec_off, rsh);
+                     g.adj, r, rsub, ybuf, stamp, ctl, b1, c1, max_rows, rec, rec_off, rsh, rmask);
 }
 
 hipError_t launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row,
                               const int32_t *t_dold, const int32_t *t_dnew, const DevGraphView &g, const double *r,
-                              const double *rsub, double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1,
-                              int32_t max_rows, int32_t *items, int32_t *item_off, uint64_t *rec, int32_t *dcnt,
-                              int32_t *rec_off, void *temp, size_t temp_bytes, int grid, hipStream_t st) {
+                              const double *rsub, uint64_t rmask, double *ybuf, int32_t *stamp, Ctl *ctl, int b1,
+                              double c1, int32_t max_rows, int32_t *items, int32_t *item_off, uint64_t *rec,
+                              int32_t *dcnt, int32_t *rec_off, void *temp, size_t temp_bytes, int grid,
+                              hipStream_t st) {
   if (max_rows <= 0) return hipSuccess;
   if (max_rows < SEED_SMALL) {
     hipLaunchKernelGGL(k_seed_items_small, dim3(1), dim3(1024), 0, st, t_dold, ctl, max_rows, item_off,
@@ -912,7 +990,7 @@ hipError_t launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, c
 #define RWR_SEED_CASE(SS)                                                                                        \
   case SS:                                                                                                       \
     offset_seed_s<SS>(keys, seg, row, t_dold, t_dnew, item_off, g, r, rsub, ybuf, stamp, ctl, b1, c1, max_rows, \
-                      rec, rec_off, rsh, grid, st);                                                              \
+                      rec, rec_off, rsh, rmask, grid, st);                                                       \
     break;
   switch (S) {
     RWR_SEED_CASE(1)

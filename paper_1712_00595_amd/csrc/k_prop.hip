@@ -1194,27 +1194,36 @@ __global__ __launch_bounds__(BLOCK) void k_carry_prepare(SlotArgs a, int last, u
 // added to that sweep's input, x^(k-1) += p (pre-scaled by the new 1/d_out),
 // so that every later iterate carries their propagation.  r already holds p.
 // Columns that stopped before the dense phase keep theirs pending; ctl->inj
-// records which columns took it.
+// records which columns took it.  A column that takes its vector leaves the
+// pending set, and readers of gbuf skip such columns, so gbuf is only read.
 template <typename XT, int S>
 __global__ __launch_bounds__(BLOCK) void k_inject(SlotArgs a, int k, uint64_t mask) {
   Ctl *ctl = a.ctl;
   if (!slot_live(ctl, MODE_DENSE, k)) return;
+  // V consecutive columns per thread, as in k_carry_prepare
+  constexpr int V = S >= 4 && sizeof(XT) == 4 ? 4 : (S >= 2 ? 2 : 1);
+  using XV = VecT<XT, V>;
+  using DV = VecT<double, V>;
   XT *__restrict__ xin = (XT *)a.x[(k - 1) & 1];
-  const int j = threadIdx.x % S;
-  constexpr int NPB = BLOCK / S;
-  const bool take = ((mask >> j) & 1ull) && ctl->active[j] != 0;
-  if (blockIdx.x == 0 && threadIdx.x < S) ctl->inj[threadIdx.x] = take ? 1 : 0;
+  uint64_t take = 0;  // pending columns still propagating
+  for (int j = 0; j < S; ++j)
+    if (((mask >> j) & 1ull) && ctl->active[j] != 0) take |= 1ull << j;
+  if (blockIdx.x == 0 && threadIdx.x < S) ctl->inj[threadIdx.x] = (int32_t)((take >> threadIdx.x) & 1ull);
   if (!take) return;
-  for (int v = blockIdx.x * NPB + threadIdx.x / S; v < a.n; v += gridDim.x * NPB) {
-    const int64_t kk = col_index(v, S, j);
-    const double p = a.gbuf[kk];
+  const int64_t groups = (int64_t)a.n * (S / V);
+  for (int64_t t = blockIdx.x * (int64_t)BLOCK + threadIdx.x; t < groups; t += (int64_t)gridDim.x * BLOCK) {
+    const int64_t i = t * V;
+    const int v = (int)(i / S), j0 = (int)(i % S);
+    const uint64_t tk = (take >> j0) & ((1ull << V) - 1);
+    if (!tk) continue;
     const int d = a.out.len[v];
-    if (p != 0.0) {
-      if (d) xin[kk] = (XT)((double)xin[kk] + p / (double)d);
-      // the column leaves the pending set: its entries of gbuf must read 0,
-      // since the next offset seed takes r - gbuf in every column
-      a.gbuf[kk] = 0.0;
-    }
+    if (!d) continue;
+    const DV g = *reinterpret_cast<const DV *>(a.gbuf + i);
+    XV xv = *reinterpret_cast<const XV *>(xin + i);
+#pragma unroll
+    for (int q = 0; q < V; ++q)
+      if (((tk >> q) & 1ull) && g.v[q] != 0.0) xv.v[q] = (XT)((double)xv.v[q] + g.v[q] / (double)d);
+    *reinterpret_cast<XV *>(xin + i) = xv;
   }
 }
 

@@ -117,7 +117,8 @@ struct OrientPair {
   OrientArgs o[2];
 };
 void launch_validate_plan(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st);
-// q_offset of r - rsub (rsub may be null) into ybuf (atomically; ybuf null:
+// q_offset of r - rsub (rsub may be null; subtracted in the columns of
+// rmask only) into ybuf (atomically; ybuf null:
 // the support stamps and cost-model sums only); touched rows cut into chunks
 // (items, item_off: max_rows + 1 ints, temp: seed_scan_temp_bytes(max_rows)).
 // rec (optional): the seed's records for launch_seed_sort_reduce, one slot per
@@ -125,9 +126,10 @@ void launch_validate_plan(const OrientPair &P, int norient, int b1, Ctl *ctl, in
 // of keys, read back after validation), with dcnt, rec_off: max_rows + 1 ints
 hipError_t launch_offset_seed(int S, const uint64_t *keys, const int32_t *seg, const int32_t *row,
                               const int32_t *t_dold, const int32_t *t_dnew, const DevGraphView &g, const double *r,
-                              const double *rsub, double *ybuf, int32_t *stamp, Ctl *ctl, int b1, double c1,
-                              int32_t max_rows, int32_t *items, int32_t *item_off, uint64_t *rec, int32_t *dcnt,
-                              int32_t *rec_off, void *temp, size_t temp_bytes, int grid, hipStream_t st);
+                              const double *rsub, uint64_t rmask, double *ybuf, int32_t *stamp, Ctl *ctl, int b1,
+                              double c1, int32_t max_rows, int32_t *items, int32_t *item_off, uint64_t *rec,
+                              int32_t *dcnt, int32_t *rec_off, void *temp, size_t temp_bytes, int grid,
+                              hipStream_t st);
 size_t seed_scan_temp_bytes(int32_t max_rows);
 // workgroups of the heavy-row epilogue (one (row, column) pair per thread);
 // its partials follow the sweep's, so partial buffers hold this many more
@@ -142,9 +144,9 @@ void launch_apply(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t ma
 hipError_t launch_seed_sort_reduce(int S, uint64_t *rec, uint64_t *rec_alt, int32_t n_rec, int32_t max_rows,
                                    int32_t n_nodes, const int32_t *rec_off, const int32_t *seg,
                                    const int32_t *row, const int32_t *t_dold, const int32_t *t_dnew,
-                                   const double *r, const double *rsub, double c1, double *ybuf, double *hpart,
-                                   double *tpart, void *temp, size_t temp_bytes, const Ctl *ctl, int grid,
-                                   hipStream_t st);
+                                   const double *r, const double *rsub, uint64_t rmask, double c1, double *ybuf,
+                                   double *hpart, double *tpart, void *temp, size_t temp_bytes, const Ctl *ctl,
+                                   int grid, hipStream_t st);
 int64_t seed_part_len(int64_t n_rec, int S);
 size_t seed_sort_temp_bytes(int64_t n_rec);
 
