@@ -108,25 +108,35 @@ struct DecideShared {
   int s_active;  // columns still above eps
   int s_nact;    // columns active in this iteration
   int s_bad;  // a column's norm or sum is not finite
+  int s_last;    // this workgroup arrived last
 };
+
+// workgroups of the decision kernel: each reduces a slice of the entries,
+// the last to arrive adds their totals in workgroup order and decides
+#define DECIDE_GRID 16
 
 template <typename XT, int S, int KIND>
 __device__ __forceinline__ void pull_epilogue(const SlotArgs &a, XT *__restrict__ xnext, int v, int j, double y,
                                               bool act, double &nrm, double &sm);
 
-// One workgroup: totals of entries 0..count-1, then the decision of the
-// iteration (kind SPARSE/DENSE/REFINE), or the residual / column-sum results.
-// With `fold` (after a dense or residual sweep with few heavy rows) it first
-// finishes the heavy rows itself: chunk sums added in order, row epilogue.
-// Every sum runs in a fixed order: strided per thread, then a shuffle tree in
-// each wave, then the waves in index order.
+// Totals of entries 0..count-1, then the decision of the iteration (kind
+// SPARSE/DENSE/REFINE), or the residual / column-sum results.  With `fold`
+// (after a dense or residual sweep with few heavy rows) the heavy rows are
+// finished here first: chunk sums added in order, row epilogue.  Every sum
+// runs in a fixed order: strided per thread, then a shuffle tree in each
+// wave, then the waves in index order, then (several workgroups) the
+// workgroups' totals in workgroup order, added by the workgroup that arrives
+// last (it publishes through entries count .. count + gridDim.x - 1, which
+// the partial buffers hold beyond every sweep's entries).
 template <typename XT, int S>
 __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, int count, int new_list, int fold) {
   __shared__ DecideShared sh;
   constexpr int NW = DECIDE_BLOCK / RWR_WAVE;
   Ctl *ctl = a.ctl;
   constexpr int TPC = DECIDE_BLOCK / S;
-  const int t = threadIdx.x, j = t % S, q = t / S;
+  const int t = threadIdx.x, j = t % S;
+  const int nb = gridDim.x, TPCG = TPC * nb;
+  const int q = blockIdx.x * TPC + t / S;  // this thread's place among the column's threads of all workgroups
   const int lane = t % RWR_WAVE, w = t / RWR_WAVE;
   // The control values this kernel reads are loaded up front, together with
   // the partials below, so that their latencies overlap (the slot test would
@@ -159,36 +169,36 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
   int hf[2] = {0, 0}, hc[2] = {0, 0}, hv[2] = {0, 0};
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    const int h = q + u * TPC;
+    const int h = q + u * TPCG;
     if (h < nh) {
       hf[u] = a.heavy.first[h];
       hc[u] = a.heavy.nchunks[h];
       hv[u] = a.heavy.rows[h];
     }
   }
-  // four partials per step in flight, into four sums added in a fixed order
+  // eight partials per step in flight, into eight sums added in a fixed order
   double A, B;
   {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    constexpr int R = 8;
+    double av[R], bv[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) av[u] = bv[u] = 0.0;
     const double *__restrict__ pp = a.part + 2 * j;
     const int64_t ES = entry_stride<S>();
     int e = q;
-    for (; e + 3 * TPC < count; e += 4 * TPC) {
-      a0 += pp[(int64_t)e * ES];
-      b0 += pp[(int64_t)e * ES + 1];
-      a1 += pp[(int64_t)(e + TPC) * ES];
-      b1 += pp[(int64_t)(e + TPC) * ES + 1];
-      a2 += pp[(int64_t)(e + 2 * TPC) * ES];
-      b2 += pp[(int64_t)(e + 2 * TPC) * ES + 1];
-      a3 += pp[(int64_t)(e + 3 * TPC) * ES];
-      b3 += pp[(int64_t)(e + 3 * TPC) * ES + 1];
+    for (; e + (R - 1) * TPCG < count; e += R * TPCG) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        av[u] += pp[(int64_t)(e + u * TPCG) * ES];
+        bv[u] += pp[(int64_t)(e + u * TPCG) * ES + 1];
+      }
     }
-    for (; e < count; e += TPC) {
-      a0 += pp[(int64_t)e * ES];
-      b0 += pp[(int64_t)e * ES + 1];
+    for (; e < count; e += TPCG) {
+      av[0] += pp[(int64_t)e * ES];
+      bv[0] += pp[(int64_t)e * ES + 1];
     }
-    A = (a0 + a1) + (a2 + a3);
-    B = (b0 + b1) + (b2 + b3);
+    A = ((av[0] + av[1]) + (av[2] + av[3])) + ((av[4] + av[5]) + (av[6] + av[7]));
+    B = ((bv[0] + bv[1]) + (bv[2] + bv[3])) + ((bv[4] + bv[5]) + (bv[6] + bv[7]));
   }
   // a slot enqueued past the end of the run, or of the other phase
   const bool live_par = ((it ^ new_list) & 1) == 0;
@@ -201,7 +211,7 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
     double hn = 0.0, hs = 0.0;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      if (q + u * TPC >= nh) break;
+      if (q + u * TPCG >= nh) break;
       double y = 0.0;
       for (int qq = 0; qq < hc[u]; ++qq) y += a.heavy.part[(int64_t)(hf[u] + qq) * S + j];
       if (kind == KIND_RESID)
@@ -215,7 +225,7 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
   // frontier counters: only a sparse slot publishes them
   int64_t ia = 0, ib = 0;
   if (kind == KIND_SPARSE) {
-    for (int e = t; e < count; e += DECIDE_BLOCK) {
+    for (int e = blockIdx.x * DECIDE_BLOCK + t; e < count; e += nb * DECIDE_BLOCK) {
       ia += a.part_i[(int64_t)e * 16];
       ib += a.part_i[(int64_t)e * 16 + 1];
     }
@@ -251,6 +261,46 @@ __global__ __launch_bounds__(DECIDE_BLOCK) void k_decide(SlotArgs a, int kind, i
     sh.s_i[1] = Y;
   }
   __syncthreads();
+  if (nb > 1) {
+    const int64_t ES = entry_stride<S>();
+    const int64_t se = (int64_t)count + blockIdx.x;
+    if (t < S) {
+      a.part[se * ES + 2 * t] = sh.s_norm[t];
+      a.part[se * ES + 2 * t + 1] = sh.s_sum[t];
+    }
+    if (t == 0) {
+      a.part_i[se * 16] = sh.s_i[0];
+      a.part_i[se * 16 + 1] = sh.s_i[1];
+    }
+    // release this workgroup's totals, then count the arrival
+    __threadfence();
+    __syncthreads();
+    if (t == 0) sh.s_last = atomicAdd(&ctl->done_blocks, 1u) == (unsigned)(nb - 1);
+    __syncthreads();
+    if (!sh.s_last) return;
+    // acquire the other workgroups' totals
+    __threadfence();
+    if (t < S) {
+      double X = 0.0, Y = 0.0;
+      for (int bb = 0; bb < nb; ++bb) {
+        X += a.part[((int64_t)count + bb) * ES + 2 * t];
+        Y += a.part[((int64_t)count + bb) * ES + 2 * t + 1];
+      }
+      sh.s_norm[t] = X;
+      sh.s_sum[t] = Y;
+    }
+    if (t == 0) {
+      ctl->done_blocks = 0;
+      int64_t X = 0, Y = 0;
+      for (int bb = 0; bb < nb; ++bb) {
+        X += a.part_i[((int64_t)count + bb) * 16];
+        Y += a.part_i[((int64_t)count + bb) * 16 + 1];
+      }
+      sh.s_i[0] = X;
+      sh.s_i[1] = Y;
+    }
+    __syncthreads();
+  }
   if (kind == KIND_RESID || kind == KIND_SIGMA) {
     if (t < S) {
       ctl->red_norm[t] = sh.s_norm[t];
@@ -1121,11 +1171,22 @@ __global__ __launch_bounds__(BLOCK) void k_heavy_epi(SlotArgs a, int k, int entr
   constexpr int NPB = BLOCK / S;
   const bool act = ctl->active[j] != 0;
   double nrm = 0.0, sm = 0.0;
-  for (int h = blockIdx.x * NPB + threadIdx.x / S; h < a.heavy.n_rows; h += gridDim.x * NPB) {
-    const int f = a.heavy.first[h], nch = a.heavy.nchunks[h];
-    double s = 0.0;
-    for (int q = 0; q < nch; ++q) s += a.heavy.part[(int64_t)(f + q) * S + j];
-    pull_epilogue<XT, S, KIND>(a, xnext, a.heavy.rows[h], j, c1 * s, act, nrm, sm);
+  // two rows per step (h and h + stride), their row data and chunk sums in
+  // flight together; each row's chunks are added in order
+  const int stride = gridDim.x * NPB;
+  for (int h = blockIdx.x * NPB + threadIdx.x / S; h < a.heavy.n_rows; h += 2 * stride) {
+    const int h2 = h + stride;
+    const bool two = h2 < a.heavy.n_rows;
+    const int f = a.heavy.first[h], nch = a.heavy.nchunks[h], v = a.heavy.rows[h];
+    const int f2 = two ? a.heavy.first[h2] : 0, nch2 = two ? a.heavy.nchunks[h2] : 0;
+    const int v2 = two ? a.heavy.rows[h2] : 0;
+    double s = 0.0, s2 = 0.0;
+    for (int q = 0; q < max(nch, nch2); ++q) {
+      if (q < nch) s += a.heavy.part[(int64_t)(f + q) * S + j];
+      if (q < nch2) s2 += a.heavy.part[(int64_t)(f2 + q) * S + j];
+    }
+    pull_epilogue<XT, S, KIND>(a, xnext, v, j, c1 * s, act, nrm, sm);
+    if (two) pull_epilogue<XT, S, KIND>(a, xnext, v2, j, c1 * s2, act, nrm, sm);
   }
   block_publish<S>(nrm, sm, 0, 0, a.part, a.part_i, entry_base + blockIdx.x, sh);
 }
@@ -1431,7 +1492,8 @@ void launch_reset_run(Ctl *ctl, int32_t S, uint64_t mask, double eps, int32_t ma
 
 template <int S, typename XT = float>
 static void decide_impl(const SlotArgs &a, int kind, int count, int new_list, hipStream_t st, int fold = 0) {
-  hipLaunchKernelGGL((k_decide<XT, S>), dim3(1), dim3(DECIDE_BLOCK), 0, st, a, kind, count, new_list, fold);
+  const int nb = std::max(1, std::min(DECIDE_GRID, count / 128));
+  hipLaunchKernelGGL((k_decide<XT, S>), dim3(nb), dim3(DECIDE_BLOCK), 0, st, a, kind, count, new_list, fold);
 }
 
 void launch_seed_init(const SlotArgs &a, int S, hipStream_t st) {
