@@ -43,6 +43,7 @@ int next_pow2_cols(int n) {
 // terms of the offset seed (old degrees of the touched rows plus the batch's
 // keys) from which it is sorted and reduced instead of scattered atomically
 constexpr int64_t SEED_SORT_MIN = 1 << 16;
+constexpr int SEED_SORT_MIN_S = 32;
 
 int bits_for(int64_t v) {
   int b = 1;
@@ -2215,9 +2216,11 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   }
   // the offset seed: scattered with FP64 atomics, or written as records that
   // are sorted and summed per node in a fixed order (deterministic mode, and
-  // batches with many terms, where it is also faster)
+  // batches with many terms of many columns, where it is also faster: the
+  // scatter issues S atomics per term, the sort moves one key)
   const int64_t n_rec = nkeys > 0 ? c->ctl_h->seed_recs + nkeys : 0;
-  c->seed_sorted = nkeys > 0 && (c->det || c->seed_sort_mode == 1 || (c->seed_sort_mode < 0 && n_rec >= SEED_SORT_MIN));
+  c->seed_sorted = nkeys > 0 && (c->det || c->seed_sort_mode == 1 ||
+                                 (c->seed_sort_mode < 0 && n_rec >= SEED_SORT_MIN && c->S >= SEED_SORT_MIN_S));
   if (c->seed_sorted && n_rec >= INT32_MAX) {
     if (c->det) {
       c->err = "batch too large for the deterministic offset seed (2^31 terms)";
