@@ -44,6 +44,9 @@ int next_pow2_cols(int n) {
 // keys) from which it is sorted and reduced instead of scattered atomically
 constexpr int64_t SEED_SORT_MIN = 1 << 16;
 constexpr int SEED_SORT_MIN_S = 32;
+// batch keys from which rows above BIG_ROW entries get a workgroup each in
+// the batch check and apply (smaller batches keep one launch per step)
+constexpr int64_t BIG_BATCH = 256;
 
 int bits_for(int64_t v) {
   int b = 1;
@@ -93,6 +96,10 @@ struct rwr_ctx {
   double *spart = nullptr;
   int32_t *sdcnt = nullptr, *sroff = nullptr;
   int64_t srec_cap = 0;
+  // rows above BIG_ROW entries handled by a workgroup each (batches of
+  // BIG_BATCH keys or more): their lists
+  int32_t *bigv = nullptr, *biga = nullptr;
+  bool big_batch = false;
   int seed_sort_mode = -1;   // RWR_SEED_SORT: 1 always sort and reduce, 0 atomics (outside deterministic mode)
   bool seed_sorted = false;  // the last update's offset seed was sorted and reduced
   hipEvent_t ph_ev[7] = {};    // phase-timing events (created on first use)
@@ -1990,7 +1997,11 @@ static rwr_status ensure_batch(rwr_ctx *c, int64_t nkeys, int64_t nints) {
     dev_free(c, c->pos);
     dev_free(c, c->sdcnt);
     dev_free(c, c->sroff);
+    dev_free(c, c->bigv);
+    dev_free(c, c->biga);
     RWR_TRY(alloc_zero(c, &c->keys_alt, cap));
+    RWR_TRY(alloc_zero(c, &c->bigv, 2 * (cap + 1)));
+    RWR_TRY(alloc_zero(c, &c->biga, 2 * (cap + 1)));
     RWR_TRY(alloc_zero(c, &c->flags, cap + 1));
     RWR_TRY(alloc_zero(c, &c->pos, cap + 1));
     RWR_TRY(alloc_zero(c, &c->sdcnt, cap + 1));
@@ -2047,6 +2058,9 @@ static OrientPair orient_pair(const rwr_ctx *c, bool check) {
     q.heavy_limit = o == po ? c->heavy_limit : 0;
     q.e_cap = c->g[o].e_cap;
   }
+  P.bigv = c->bigv;
+  P.biga = c->biga;
+  P.big = c->big_batch ? 1 : 0;
   return P;
 }
 
@@ -2165,6 +2179,7 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
     return RWR_EINVAL;
   }
   RWR_TRY(ensure_batch(c, std::max<int64_t>(nkeys, 1), std::max<int64_t>(nints, 1)));
+  c->big_batch = nkeys >= BIG_BATCH;
   const int b1 = bits_for(std::max(1, n_new - 1)) + 1;
   launch_reset_batch(c->ctl, 0, c->stream);
 
@@ -2267,7 +2282,8 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
                                        8 * c->n_cu, c->stream));
   }
   RWR_TRY(phase_mark(c, 2));
-  if (nkeys > 0) launch_apply(orient_pair(c, false), norient, b1, c->ctl, (int32_t)nkeys, c->stream);
+  if (nkeys > 0)
+    launch_apply(orient_pair(c, false), norient, b1, c->ctl, (int32_t)nkeys, c->ctl_h->nbig_a, c->stream);
   RWR_TRY(phase_mark(c, 3));
   // stored edge count (an undirected self-loop is stored once; the count only
   // steers the sparse/dense switch and the visited-edge statistic)
@@ -2469,6 +2485,8 @@ void rwr_destroy(rwr_ctx *c) {
   dev_free(c, c->spart);
   dev_free(c, c->sdcnt);
   dev_free(c, c->sroff);
+  dev_free(c, c->bigv);
+  dev_free(c, c->biga);
   dev_free(c, c->ndel);
   dev_free(c, c->row_order);
   dev_free(c, c->hfront);

@@ -336,7 +336,9 @@ __device__ __forceinline__ int32_t grown_cap(int32_t d) { return d + max(4, d >>
 // checks the batch against the graph: an inserted edge must be absent
 // (EEXIST), a deleted edge present (ENOENT).  Records old/new degree of each
 // touched row and the arena demand of rows that outgrow their capacity.
-// Both orientations in one launch (blockIdx.y selects one).
+// Both orientations in one launch (blockIdx.y selects one).  With P.big, a
+// row above BIG_ROW entries is listed instead for k_validate_big (its check)
+// and, when its entries must be compacted or moved, for k_apply_big.
 __global__ void k_validate_plan(OrientPair P, int b1, Ctl *ctl) {
   const OrientArgs &q = P.o[blockIdx.y];
   const uint64_t *__restrict__ keys = q.keys;
@@ -358,9 +360,10 @@ __global__ void k_validate_plan(OrientPair P, int b1, Ctl *ctl) {
   n_ins = wave_xor_sum(n_ins, 1, RWR_WAVE);
   const int n_del = (e - b) - n_ins;
   const int32_t d_old = len[u];
+  const bool big = P.big && d_old > BIG_ROW;
   int found = 0;
   int exists = 0;
-  if (check) {
+  if (check && !big) {
     // SEG_W x 64 neighbours per step: their loads and searches in flight together
     const int32_t o = off[u];
     for (int32_t i0 = 0; i0 < d_old; i0 += SEG_W * RWR_WAVE) {
@@ -384,13 +387,15 @@ __global__ void k_validate_plan(OrientPair P, int b1, Ctl *ctl) {
     exists = wave_xor_sum(exists, 1, RWR_WAVE);
   }
   if (lane == 0) {
-    if (check) {
+    if (check && !big) {
       if (exists)
         set_error(ctl, ERR_EEXIST);
       else if (found != n_del)
         set_error(ctl, ERR_ENOENT);
     }
     const int32_t d_new = d_old - n_del + n_ins;
+    if (big && check) P.bigv[atomicAdd(&ctl->nbig_v, 1)] = t;
+    if (big && (n_del > 0 || d_new > cap[u])) P.biga[atomicAdd(&ctl->nbig_a, 1)] = (int32_t)((unsigned)orient << 31) | t;
     t_dold[t] = d_old;
     t_dnew[t] = d_new;
     if (d_new > cap[u]) atomicAdd((unsigned long long *)&ctl->demand[orient], (unsigned long long)grown_cap(d_new));
@@ -808,6 +813,8 @@ __global__ void k_apply(OrientPair P, int b1, Ctl *ctl) {
   int32_t base = o;
   int32_t ncap = cap[u];
   const bool move = d_new > ncap;
+  const int32_t n_del = ((e - b) - (d_new - d_old)) / 2;
+  if (P.big && d_old > BIG_ROW && (n_del > 0 || move)) return;  // k_apply_big's row
   if (move) {
     ncap = grown_cap(d_new);
     unsigned long long pos = 0;
@@ -822,7 +829,6 @@ __global__ void k_apply(OrientPair P, int b1, Ctl *ctl) {
   }
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (RWR_WAVE - lane));
   // a row that keeps every entry in place only appends
-  const int32_t n_del = ((e - b) - (d_new - d_old)) / 2;
   const bool scan = move || n_del != 0;
   int32_t w = scan ? 0 : d_old;
   for (int32_t i0 = 0; scan && i0 < d_old; i0 += SEG_W * RWR_WAVE) {
@@ -859,6 +865,162 @@ __global__ void k_apply(OrientPair P, int b1, Ctl *ctl) {
   }
 }
 
+// ------------------------------------------------- rows above BIG_ROW
+#define BIG_BLOCK 1024
+#define BIG_WAVES (BIG_BLOCK / RWR_WAVE)
+
+// exclusive prefix of a per-wavefront count over the workgroup's wavefronts
+// (cnt: the counts in LDS), and the workgroup's total
+__device__ __forceinline__ int32_t big_prefix(const int32_t *cnt, int wid, int32_t &total) {
+  int32_t pre = 0, tot = 0;
+  for (int ww = 0; ww < BIG_WAVES; ++ww) {
+    pre += ww < wid ? cnt[ww] : 0;
+    tot += cnt[ww];
+  }
+  total = tot;
+  return pre;
+}
+
+// The batch check of listed rows, one workgroup per row.
+__global__ __launch_bounds__(BIG_BLOCK) void k_validate_big(OrientPair P, int b1, Ctl *ctl) {
+  __shared__ int32_t s_red[3][BIG_WAVES];
+  if (ctl->err) return;
+  const OrientArgs &q = P.o[0];
+  const int tid = threadIdx.x, lane = tid % RWR_WAVE, wid = tid / RWR_WAVE;
+  const int32_t nb = ctl->nbig_v;
+  for (int32_t i = blockIdx.x; i < nb; i += gridDim.x) {
+    const int32_t t = P.bigv[i];
+    const int32_t u = q.row[t], b = q.seg[t], e = q.seg[t + 1];
+    const int32_t d_old = q.g.len[u], o = q.g.off[u];
+    int found = 0, exists = 0, dels = 0;
+    for (int32_t k = b + tid; k < e; k += BIG_BLOCK) dels += (int)!(q.keys[k] & 1ull);
+    for (int32_t i0 = 0; i0 < d_old; i0 += SEG_W * BIG_BLOCK) {
+      int32_t v[SEG_W], p[SEG_W];
+#pragma unroll
+      for (int w = 0; w < SEG_W; ++w) {
+        const int32_t k = i0 + w * BIG_BLOCK + tid;
+        v[w] = k < d_old ? q.g.adj[o + k] : -1;
+      }
+      seg_find_w(q.keys, b, e, u, v, b1, p);
+#pragma unroll
+      for (int w = 0; w < SEG_W; ++w)
+        if (p[w] >= 0) {
+          if (q.keys[p[w]] & 1ull)
+            exists = 1;
+          else
+            ++found;
+        }
+    }
+    found = wave_xor_sum(found, 1, RWR_WAVE);
+    exists = wave_xor_sum(exists, 1, RWR_WAVE);
+    dels = wave_xor_sum(dels, 1, RWR_WAVE);
+    if (lane == 0) {
+      s_red[0][wid] = found;
+      s_red[1][wid] = exists;
+      s_red[2][wid] = dels;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int F = 0, X = 0, D = 0;
+      for (int ww = 0; ww < BIG_WAVES; ++ww) F += s_red[0][ww], X += s_red[1][ww], D += s_red[2][ww];
+      if (X)
+        set_error(ctl, ERR_EEXIST);
+      else if (F != D)
+        set_error(ctl, ERR_ENOENT);
+    }
+    __syncthreads();
+  }
+}
+
+// The structural apply of listed rows, one workgroup per row: the kept
+// entries compacted in order (in place, or into a fresh arena slot), then the
+// inserted ones appended, as k_apply does with one wavefront.
+__global__ __launch_bounds__(BIG_BLOCK) void k_apply_big(OrientPair P, int b1, Ctl *ctl) {
+  __shared__ int32_t s_cnt[SEG_W][BIG_WAVES];
+  __shared__ long long s_pos;
+  if (ctl->err) return;
+  const int tid = threadIdx.x, lane = tid % RWR_WAVE, wid = tid / RWR_WAVE;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (RWR_WAVE - lane));
+  const int32_t nb = ctl->nbig_a;
+  for (int32_t i = blockIdx.x; i < nb; i += gridDim.x) {
+    const uint32_t ent = (uint32_t)P.biga[i];
+    const int orient = (int)(ent >> 31);
+    const int32_t t = (int32_t)(ent & 0x7fffffffu);
+    const OrientArgs &q = P.o[orient];
+    const int32_t u = q.row[t], b = q.seg[t], e = q.seg[t + 1];
+    const int32_t d_old = q.t_dold[t], d_new = q.t_dnew[t];
+    const int32_t o = q.g.off[u];
+    int32_t ncap = q.g.cap[u];
+    const bool move = d_new > ncap;
+    if (move) ncap = grown_cap(d_new);
+    if (tid == 0) {
+      long long pos = o;
+      if (move) {
+        pos = (long long)atomicAdd((unsigned long long *)&ctl->tail[orient], (unsigned long long)ncap);
+        // the host sizes the arena from the validated demand; never write past it
+        if (pos + ncap > q.e_cap) {
+          atomicCAS(&ctl->prop_err, 0, ERR_ENOMEM);
+          pos = -1;
+        }
+      }
+      s_pos = pos;
+    }
+    __syncthreads();
+    const long long sp = s_pos;
+    if (sp < 0) {
+      __syncthreads();
+      continue;
+    }
+    const int32_t base = (int32_t)sp;
+    int32_t w = 0;
+    for (int32_t i0 = 0; i0 < d_old; i0 += SEG_W * BIG_BLOCK) {
+      int32_t v[SEG_W], p[SEG_W];
+#pragma unroll
+      for (int x = 0; x < SEG_W; ++x) {
+        const int32_t k = i0 + x * BIG_BLOCK + tid;
+        v[x] = k < d_old ? q.g.adj[o + k] : -1;
+      }
+      seg_find_w(q.keys, b, e, u, v, b1, p);
+      uint64_t m[SEG_W];
+#pragma unroll
+      for (int x = 0; x < SEG_W; ++x) {
+        m[x] = __ballot(v[x] >= 0 && p[x] < 0);
+        if (lane == 0) s_cnt[x][wid] = __popcll(m[x]);
+      }
+      // every read of this step is done before any write: a kept entry
+      // moves to a position at or below its own
+      __syncthreads();
+#pragma unroll
+      for (int x = 0; x < SEG_W; ++x) {
+        int32_t tot;
+        const int32_t pre = big_prefix(s_cnt[x], wid, tot);
+        if ((m[x] >> lane) & 1ull) q.g.adj[base + w + pre + __popcll(m[x] & lt_mask)] = v[x];
+        w += tot;
+      }
+      __syncthreads();
+    }
+    for (int32_t k0 = b; k0 < e; k0 += BIG_BLOCK) {
+      const int32_t k = k0 + tid;
+      const bool ins = k < e && (q.keys[k] & 1ull);
+      const uint64_t mi = __ballot(ins);
+      if (lane == 0) s_cnt[0][wid] = __popcll(mi);
+      __syncthreads();
+      int32_t tot;
+      const int32_t pre = big_prefix(s_cnt[0], wid, tot);
+      if (ins) q.g.adj[base + w + pre + __popcll(mi & lt_mask)] = key_col(q.keys[k], b1);
+      w += tot;
+      __syncthreads();
+    }
+    if (tid == 0) {
+      q.g.len[u] = d_new;
+      if (move) {
+        q.g.off[u] = base;
+        q.g.cap[u] = ncap;
+      }
+    }
+  }
+}
+
 __global__ void k_reset_batch(Ctl *ctl, int demand_only) {
   if (!demand_only) {
     ctl->err = 0;
@@ -868,6 +1030,8 @@ __global__ void k_reset_batch(Ctl *ctl, int demand_only) {
   ctl->demand[0] = 0;
   ctl->demand[1] = 0;
   ctl->seed_recs = 0;
+  ctl->nbig_v = 0;
+  ctl->nbig_a = 0;
   ctl->heavy_stale = 0;
   if (!demand_only) {
     ctl->node_dels = 0;
@@ -952,6 +1116,7 @@ void launch_validate_plan(const OrientPair &P, int norient, int b1, Ctl *ctl, in
   const int waves_per_block = 4;
   const int grid = (max_rows + waves_per_block - 1) / waves_per_block;
   hipLaunchKernelGGL(k_validate_plan, dim3(grid, norient), dim3(waves_per_block * RWR_WAVE), 0, st, P, b1, ctl);
+  if (P.big && P.o[0].check) hipLaunchKernelGGL(k_validate_big, dim3(128), dim3(BIG_BLOCK), 0, st, P, b1, ctl);
 }
 
 template <int S>
@@ -1011,9 +1176,12 @@ size_t seed_scan_temp_bytes(int32_t max_rows) {
   return bytes;
 }
 
-void launch_apply(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st) {
+void launch_apply(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, int32_t big_rows,
+                  hipStream_t st) {
   if (max_rows <= 0) return;
   const int waves_per_block = 4;
   const int grid = (max_rows + waves_per_block - 1) / waves_per_block;
   hipLaunchKernelGGL(k_apply, dim3(grid, norient), dim3(waves_per_block * RWR_WAVE), 0, st, P, b1, ctl);
+  if (P.big && big_rows > 0)
+    hipLaunchKernelGGL(k_apply_big, dim3(std::min(big_rows, 1024)), dim3(BIG_BLOCK), 0, st, P, b1, ctl);
 }

@@ -1492,7 +1492,11 @@ void launch_reset_run(Ctl *ctl, int32_t S, uint64_t mask, double eps, int32_t ma
 
 template <int S, typename XT = float>
 static void decide_impl(const SlotArgs &a, int kind, int count, int new_list, hipStream_t st, int fold = 0) {
-  const int nb = std::max(1, std::min(DECIDE_GRID, count / 128));
+  // several workgroups once the entries are large (many columns): one
+  // workgroup streams them at a fraction of the chip's rate, while the
+  // arrival count and fences cost a few microseconds
+  const int64_t bytes = (int64_t)count * std::max(16, 2 * S) * 8;
+  const int nb = bytes >= (512 << 10) ? std::max(1, std::min(DECIDE_GRID, count / 128)) : 1;
   hipLaunchKernelGGL((k_decide<XT, S>), dim3(nb), dim3(DECIDE_BLOCK), 0, st, a, kind, count, new_list, fold);
 }
 

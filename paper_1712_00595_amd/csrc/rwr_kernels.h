@@ -113,8 +113,16 @@ struct OrientArgs {
   int32_t heavy_limit;  // count rows that become heavy (pull orientation)
   int64_t e_cap;        // arena capacity
 };
+// Rows above BIG_ROW entries are checked and rewritten by a whole workgroup
+// when `big` is set (lists bigv: checked rows of the out orientation, biga:
+// orient << 31 | t of rows to compact or move; 2 (max_rows + 1) ints each);
+// otherwise every row takes one wavefront.
+constexpr int32_t BIG_ROW = 4096;
 struct OrientPair {
   OrientArgs o[2];
+  int32_t *bigv;
+  int32_t *biga;
+  int32_t big;
 };
 void launch_validate_plan(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st);
 // q_offset of r - rsub (rsub may be null; subtracted in the columns of
@@ -134,7 +142,9 @@ size_t seed_scan_temp_bytes(int32_t max_rows);
 // workgroups of the heavy-row epilogue (one (row, column) pair per thread);
 // its partials follow the sweep's, so partial buffers hold this many more
 constexpr int HEAVY_EPI_MAX_GRID = 2048;
-void launch_apply(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st);
+// big_rows: the count of biga read back after validation (0: no launch)
+void launch_apply(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, int32_t big_rows,
+                  hipStream_t st);
 // the offset seed summed in a fixed order (no atomics) from the records that
 // launch_offset_seed wrote into rec (n_rec slots; those past the last touched
 // row's, located by rec_off and seg, become pads): sorted into

@@ -385,6 +385,97 @@ def test_relayout_when_arena_fills():
         assert _l1(ctx.scores(0), ref) < 1e-10
 
 
+@pytest.mark.parametrize("undirected", [False, True])
+def test_hub_rows_batch_check_and_apply(undirected):
+    """Rows above 4096 entries in batches of 256 keys or more are checked and
+    rewritten by a workgroup each: deletions compact the hub's row (in both
+    orientations when directed), a large insertion moves it to the arena, and
+    a missing or an existing hub edge among many valid keys is rejected with
+    the state kept."""
+    print(f"[hub rows] undirected={undirected}", flush=True)
+    rng = np.random.default_rng(31)
+    base = rmat_graph(13, 30000, dead_end_self_loops=not undirected, undirected=undirected)
+    n, hub = base.n, 5
+    others = np.setdiff1d(np.arange(n), [hub])
+    outs = rng.choice(others, 4500, replace=False)
+    ins = rng.choice(others, 4500, replace=False)
+    if undirected:
+        pu = np.concatenate([base.pair_u, np.full(4500, hub)]).astype(np.int64)
+        pv = np.concatenate([base.pair_v, outs]).astype(np.int64)
+        key = np.unique(np.minimum(pu, pv) * n + np.maximum(pu, pv))
+        eu, ev = (key // n).astype(np.int32), (key % n).astype(np.int32)
+        loop = eu == ev
+        src = np.concatenate([eu, ev[~loop]]).astype(np.int32)
+        dst = np.concatenate([ev, eu[~loop]]).astype(np.int32)
+    else:
+        s0 = np.concatenate([base.src, np.full(4500, hub), ins]).astype(np.int64)
+        d0 = np.concatenate([base.dst, outs, np.full(4500, hub)]).astype(np.int64)
+        key = np.unique(s0 * n + d0)
+        eu, ev = (key // n).astype(np.int32), (key % n).astype(np.int32)
+        src, dst = eu, ev
+    seeds = [hub, int(outs[0]), int(outs[1])]
+    kw = dict(c=0.15, eps=1e-12, precision="fp64", build_tol=1e-12, err_budget=1e-10, undirected=undirected)
+    E = np.zeros(0, np.int32)
+
+    def edges():
+        return set(zip(src.tolist(), dst.tolist()))
+
+    def absent_from_hub(model, k, skip=()):
+        out = []
+        for v in rng.permutation(others).tolist():
+            if not model.has(hub, v) and v not in skip:
+                out.append(v)
+                if len(out) == k:
+                    break
+        return out
+
+    with rwr.Context(n, eu, ev, seeds, **kw) as ctx:
+        model = EdgeSetModel(n, eu, ev, undirected=undirected)
+        # 1: 500 hub out-edge (and, directed, 300 hub in-edge) deletions, 300
+        #    new hub out-edges, 200 new edges away from the hub
+        hub_out = [int(v) for v in outs if model.has(hub, int(v))][:500]
+        d_s, d_d = [hub] * 500, hub_out
+        if not undirected:
+            hub_in = [int(u) for u in ins if model.has(int(u), hub) and int(u) not in set(hub_out)][:300]
+            d_s, d_d = d_s + hub_in, d_d + [hub] * 300
+        new_out = absent_from_hub(model, 300)
+        far = set()
+        while len(far) < 200:
+            u, v = (int(x) for x in rng.integers(0, n, 2))
+            if hub in (u, v) or u == v or model.has(u, v) or (v, u) in far or (u, v) in far:
+                continue
+            far.add((u, v))
+        i_s = [hub] * 300 + [u for u, _ in far]
+        i_d = new_out + [v for _, v in far]
+        b1 = Batch(np.array(i_s, np.int32), np.array(i_d, np.int32), np.array(d_s, np.int32), np.array(d_d, np.int32))
+        ctx.update_batch(b1)
+        n, src, dst = oracle.apply_batch(n, src, dst, b1, undirected=undirected)
+        assert set(zip(*[x.tolist() for x in ctx.export()[:2]])) == edges()
+        # 2: 1500 more hub out-edges: the row outgrows its slack and moves
+        model = EdgeSetModel(n, src, dst)
+        b2 = Batch(np.full(1500, hub, np.int32), np.array(absent_from_hub(model, 1500), np.int32), E, E)
+        ctx.update_batch(b2)
+        n, src, dst = oracle.apply_batch(n, src, dst, b2, undirected=undirected)
+        assert set(zip(*[x.tolist() for x in ctx.export()[:2]])) == edges()
+        before = ctx.scores(0)
+        model = EdgeSetModel(n, src, dst)
+        fresh = absent_from_hub(model, 301)
+        assert len(fresh) == 301
+        gone, fresh = fresh[0], fresh[1:]
+        present = next(v for v in rng.permutation(others).tolist() if model.has(hub, v))
+        for name, extra in (("RWR_ENOENT", dict(del_src=[hub], del_dst=[gone])),
+                            ("RWR_EEXIST", dict(ins_src=[hub] * 301, ins_dst=fresh + [present]))):
+            kwb = dict(ins_src=[hub] * 300, ins_dst=fresh)
+            kwb.update(extra)
+            with pytest.raises(rwr.RwrError) as ei:
+                ctx.update(**kwb)
+            assert ei.value.name == name
+        assert np.array_equal(ctx.scores(0), before)
+        assert set(zip(*[x.tolist() for x in ctx.export()[:2]])) == edges()
+        for j, sd in enumerate(seeds):
+            assert _l1(ctx.scores(j), oracle.rwr_static(n, src, dst, sd, 0.15)) < 1e-9, j
+
+
 # ------------------------------------------------------------- node deletion
 
 @pytest.mark.parametrize("undirected", [False, True])
