@@ -80,8 +80,11 @@ typedef struct rwr_config {
                         listed shape without timing; a tuned build appends its line   */
   void *stream;      /* hipStream_t to run on; NULL: the library creates its own        */
   int32_t deterministic; /* 1: results do not depend on timing -- no floating-point atomics
-                            on the score path: the offset seed is summed per node in a
-                            fixed order after the structural apply, propagation runs dense
+                            on the score path: the offset seed's terms are written as
+                            keyed records, radix-sorted and summed per node in sorted
+                            order (the default mode does this too for large batches at
+                            32 or more columns, and scatters with atomics otherwise),
+                            propagation runs dense
                             pull sweeps only (no sparse push phase), the sweep shape is not
                             tuned by timing (autotune ignored), and the warm-start
                             network's aggregations sum each row in edge order; two runs of
