@@ -2040,6 +2040,12 @@ static rwr_status ensure_seed_recs(rwr_ctx *c, int64_t n_rec) {
   return ensure_temp(c, seed_sort_temp_bytes(c->srec_cap));
 }
 
+// whether an update may take the sorted offset seed (it then needs the
+// record count that validation sums)
+static bool seed_sort_possible(const rwr_ctx *c) {
+  return c->det || c->seed_sort_mode == 1 || (c->seed_sort_mode < 0 && c->S >= SEED_SORT_MIN_S);
+}
+
 // per-orientation arguments of the batch kernels (check: the out orientation
 // tests the batch against the graph)
 static OrientPair orient_pair(const rwr_ctx *c, bool check) {
@@ -2061,6 +2067,7 @@ static OrientPair orient_pair(const rwr_ctx *c, bool check) {
   P.bigv = c->bigv;
   P.biga = c->biga;
   P.big = c->big_batch ? 1 : 0;
+  P.recs = seed_sort_possible(c) ? 1 : 0;
   return P;
 }
 
@@ -2233,9 +2240,12 @@ rwr_status rwr_update(rwr_ctx *c, const rwr_batch *b, rwr_stats *st) {
   // are sorted and summed per node in a fixed order (deterministic mode, and
   // batches with many terms of many columns, where it is also faster: the
   // scatter issues S atomics per term, the sort moves one key)
-  const int64_t n_rec = nkeys > 0 ? c->ctl_h->seed_recs + nkeys : 0;
-  c->seed_sorted = nkeys > 0 && (c->det || c->seed_sort_mode == 1 ||
-                                 (c->seed_sort_mode < 0 && n_rec >= SEED_SORT_MIN && c->S >= SEED_SORT_MIN_S));
+  int64_t n_rec = 0;
+  if (nkeys > 0 && seed_sort_possible(c)) {
+    n_rec = nkeys;
+    for (int i = 0; i < 32; ++i) n_rec += c->ctl_h->seed_recs[i];
+  }
+  c->seed_sorted = n_rec > 0 && (c->det || c->seed_sort_mode == 1 || n_rec >= SEED_SORT_MIN);
   if (c->seed_sorted && n_rec >= INT32_MAX) {
     if (c->det) {
       c->err = "batch too large for the deterministic offset seed (2^31 terms)";

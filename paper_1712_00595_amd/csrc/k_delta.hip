@@ -302,10 +302,12 @@ __device__ __forceinline__ int32_t seg_find(const uint64_t *__restrict__ keys, i
 
 // seg_find for SEG_W columns at once (a negative column is skipped: -1): the
 // searches halve the same range in lockstep, so their loads are in flight
-// together
+// together.  nq (the same in every lane of a wavefront): only columns
+// 0 .. nq-1 are searched, so a short row costs no more than one search.
 #define SEG_W 4
 __device__ __forceinline__ void seg_find_w(const uint64_t *__restrict__ keys, int32_t b, int32_t e, int32_t r,
-                                           const int32_t (&col)[SEG_W], int b1, int32_t (&pos)[SEG_W]) {
+                                           const int32_t (&col)[SEG_W], int b1, int32_t (&pos)[SEG_W],
+                                           int nq = SEG_W) {
   uint64_t tg[SEG_W];
   int32_t base[SEG_W];
 #pragma unroll
@@ -318,11 +320,13 @@ __device__ __forceinline__ void seg_find_w(const uint64_t *__restrict__ keys, in
   for (int32_t n = e - b; n > 1;) {
     const int32_t half = n >> 1;
 #pragma unroll
-    for (int q = 0; q < SEG_W; ++q) base[q] = keys[base[q] + half] < tg[q] ? base[q] + half : base[q];
+    for (int q = 0; q < SEG_W; ++q)
+      if (q < nq) base[q] = keys[base[q] + half] < tg[q] ? base[q] + half : base[q];
     n -= half;
   }
 #pragma unroll
   for (int q = 0; q < SEG_W; ++q) {
+    if (q >= nq) break;
     const uint64_t k = keys[base[q]];
     const int32_t at = k < tg[q] ? base[q] + 1 : base[q];
     if (col[q] >= 0 && at < e && (keys[at] >> 1) == (tg[q] >> 1)) pos[q] = at;
@@ -373,7 +377,7 @@ __global__ void k_validate_plan(OrientPair P, int b1, Ctl *ctl) {
         const int32_t i = i0 + q * RWR_WAVE + lane;
         v[q] = i < d_old ? adj[o + i] : -1;
       }
-      seg_find_w(keys, b, e, u, v, b1, p);
+      seg_find_w(keys, b, e, u, v, b1, p, (d_old - i0 + RWR_WAVE - 1) / RWR_WAVE);
 #pragma unroll
       for (int q = 0; q < SEG_W; ++q)
         if (p[q] >= 0) {
@@ -399,7 +403,8 @@ __global__ void k_validate_plan(OrientPair P, int b1, Ctl *ctl) {
     t_dold[t] = d_old;
     t_dnew[t] = d_new;
     if (d_new > cap[u]) atomicAdd((unsigned long long *)&ctl->demand[orient], (unsigned long long)grown_cap(d_new));
-    if (orient == 0) atomicAdd((unsigned long long *)&ctl->seed_recs, (unsigned long long)d_old);
+    if (orient == 0 && P.recs)
+      atomicAdd((unsigned long long *)&ctl->seed_recs[blockIdx.x % 32], (unsigned long long)d_old);
     if (heavy_limit > 0 && d_old <= heavy_limit && d_new > heavy_limit) atomicAdd(&ctl->heavy_stale, 1);
   }
 }
@@ -840,7 +845,7 @@ __global__ void k_apply(OrientPair P, int b1, Ctl *ctl) {
       const int32_t i = i0 + q * RWR_WAVE + lane;
       v[q] = i < d_old ? adj[o + i] : -1;
     }
-    seg_find_w(keys, b, e, u, v, b1, p);
+    seg_find_w(keys, b, e, u, v, b1, p, (d_old - i0 + RWR_WAVE - 1) / RWR_WAVE);
 #pragma unroll
     for (int q = 0; q < SEG_W; ++q) {
       const bool keep = v[q] >= 0 && p[q] < 0;
@@ -901,7 +906,7 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_validate_big(OrientPair P, int b1
         const int32_t k = i0 + w * BIG_BLOCK + tid;
         v[w] = k < d_old ? q.g.adj[o + k] : -1;
       }
-      seg_find_w(q.keys, b, e, u, v, b1, p);
+      seg_find_w(q.keys, b, e, u, v, b1, p, (d_old - i0 + BIG_BLOCK - 1) / BIG_BLOCK);
 #pragma unroll
       for (int w = 0; w < SEG_W; ++w)
         if (p[w] >= 0) {
@@ -980,7 +985,7 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_apply_big(OrientPair P, int b1, C
         const int32_t k = i0 + x * BIG_BLOCK + tid;
         v[x] = k < d_old ? q.g.adj[o + k] : -1;
       }
-      seg_find_w(q.keys, b, e, u, v, b1, p);
+      seg_find_w(q.keys, b, e, u, v, b1, p, (d_old - i0 + BIG_BLOCK - 1) / BIG_BLOCK);
       uint64_t m[SEG_W];
 #pragma unroll
       for (int x = 0; x < SEG_W; ++x) {
@@ -1029,7 +1034,7 @@ __global__ void k_reset_batch(Ctl *ctl, int demand_only) {
   }
   ctl->demand[0] = 0;
   ctl->demand[1] = 0;
-  ctl->seed_recs = 0;
+  for (int i = 0; i < 32; ++i) ctl->seed_recs[i] = 0;
   ctl->nbig_v = 0;
   ctl->nbig_a = 0;
   ctl->heavy_stale = 0;
@@ -1116,7 +1121,8 @@ void launch_validate_plan(const OrientPair &P, int norient, int b1, Ctl *ctl, in
   const int waves_per_block = 4;
   const int grid = (max_rows + waves_per_block - 1) / waves_per_block;
   hipLaunchKernelGGL(k_validate_plan, dim3(grid, norient), dim3(waves_per_block * RWR_WAVE), 0, st, P, b1, ctl);
-  if (P.big && P.o[0].check) hipLaunchKernelGGL(k_validate_big, dim3(128), dim3(BIG_BLOCK), 0, st, P, b1, ctl);
+  // the listed rows' count is on the device: a grid for many (idle workgroups return at once)
+  if (P.big && P.o[0].check) hipLaunchKernelGGL(k_validate_big, dim3(1024), dim3(BIG_BLOCK), 0, st, P, b1, ctl);
 }
 
 template <int S>

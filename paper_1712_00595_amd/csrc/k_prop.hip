@@ -1171,22 +1171,11 @@ __global__ __launch_bounds__(BLOCK) void k_heavy_epi(SlotArgs a, int k, int entr
   constexpr int NPB = BLOCK / S;
   const bool act = ctl->active[j] != 0;
   double nrm = 0.0, sm = 0.0;
-  // two rows per step (h and h + stride), their row data and chunk sums in
-  // flight together; each row's chunks are added in order
-  const int stride = gridDim.x * NPB;
-  for (int h = blockIdx.x * NPB + threadIdx.x / S; h < a.heavy.n_rows; h += 2 * stride) {
-    const int h2 = h + stride;
-    const bool two = h2 < a.heavy.n_rows;
-    const int f = a.heavy.first[h], nch = a.heavy.nchunks[h], v = a.heavy.rows[h];
-    const int f2 = two ? a.heavy.first[h2] : 0, nch2 = two ? a.heavy.nchunks[h2] : 0;
-    const int v2 = two ? a.heavy.rows[h2] : 0;
-    double s = 0.0, s2 = 0.0;
-    for (int q = 0; q < max(nch, nch2); ++q) {
-      if (q < nch) s += a.heavy.part[(int64_t)(f + q) * S + j];
-      if (q < nch2) s2 += a.heavy.part[(int64_t)(f2 + q) * S + j];
-    }
-    pull_epilogue<XT, S, KIND>(a, xnext, v, j, c1 * s, act, nrm, sm);
-    if (two) pull_epilogue<XT, S, KIND>(a, xnext, v2, j, c1 * s2, act, nrm, sm);
+  for (int h = blockIdx.x * NPB + threadIdx.x / S; h < a.heavy.n_rows; h += gridDim.x * NPB) {
+    const int f = a.heavy.first[h], nch = a.heavy.nchunks[h];
+    double s = 0.0;
+    for (int q = 0; q < nch; ++q) s += a.heavy.part[(int64_t)(f + q) * S + j];
+    pull_epilogue<XT, S, KIND>(a, xnext, a.heavy.rows[h], j, c1 * s, act, nrm, sm);
   }
   block_publish<S>(nrm, sm, 0, 0, a.part, a.part_i, entry_base + blockIdx.x, sh);
 }
@@ -1496,7 +1485,7 @@ static void decide_impl(const SlotArgs &a, int kind, int count, int new_list, hi
   // workgroup streams them at a fraction of the chip's rate, while the
   // arrival count and fences cost a few microseconds
   const int64_t bytes = (int64_t)count * std::max(16, 2 * S) * 8;
-  const int nb = bytes >= (512 << 10) ? std::max(1, std::min(DECIDE_GRID, count / 128)) : 1;
+  const int nb = bytes >= (2 << 20) ? std::max(1, std::min(DECIDE_GRID, count / 128)) : 1;
   hipLaunchKernelGGL((k_decide<XT, S>), dim3(nb), dim3(DECIDE_BLOCK), 0, st, a, kind, count, new_list, fold);
 }
 

@@ -61,7 +61,7 @@ struct Ctl {
   int64_t dense_thresh; // switch to dense once fedges exceeds this
   int64_t dense_nodes;  // ... or once the frontier holds more nodes than this
   int64_t node_dels;    // stored adjacency entries removed by this batch's node deletions
-  int64_t seed_recs;    // old degrees summed over the touched rows (out orientation)
+  int64_t seed_recs[32]; // old degrees summed over the touched rows (out orientation), in 32 parts
   int32_t nbig_v;       // rows above BIG_ROW left to the workgroup check
   int32_t nbig_a;       // rows above BIG_ROW left to the workgroup apply
   double eps;           // stop tolerance of this run

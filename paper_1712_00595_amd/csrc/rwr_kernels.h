@@ -123,6 +123,7 @@ struct OrientPair {
   int32_t *bigv;
   int32_t *biga;
   int32_t big;
+  int32_t recs;  // sum the touched rows' old degrees (Ctl::seed_recs) for the sorted offset seed
 };
 void launch_validate_plan(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st);
 // q_offset of r - rsub (rsub may be null; subtracted in the columns of
