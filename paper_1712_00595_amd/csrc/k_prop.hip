@@ -480,17 +480,18 @@ __global__ __launch_bounds__(BLOCK) void k_epi(SlotArgs a, int k, double scale, 
   XT *__restrict__ xnew = (XT *)a.x[nw];
   XT *__restrict__ xold = (XT *)a.x[old];
   const int32_t st = ctl->stamp;
-  const int j = threadIdx.x % S;
-  constexpr int NPB = BLOCK / S;
+  // each wavefront tests the stamps of 64 consecutive nodes with one load per
+  // array, then its groups of S lanes (one lane per column) take the marked
+  // nodes, P at a time
+  constexpr int P = RWR_WAVE / S;
+  const int lane = threadIdx.x % RWR_WAVE, j = lane % S, g = lane / S;
   const bool act = ctl->active[j] != 0;
   double nrm = 0.0, sm = 0.0;
   int64_t fe = 0, fn = 0;
-  for (int v = blockIdx.x * NPB + threadIdx.x / S; v < a.n; v += gridDim.x * NPB) {
-    const int32_t fs = a.fstamp[v];
-    const int32_t ts = a.stamp[v];
-    if (!first && fs == st - 1) xold[col_index(v, S, j)] = (XT)0;
-    if (ts != st) continue;
+  auto node = [&](int v, bool clear, bool work) {
     const int64_t kk = col_index(v, S, j);
+    if (clear) xold[kk] = (XT)0;
+    if (!work) return;
     const double y = a.ybuf[kk] * scale;
     a.ybuf[kk] = 0.0;
     const int d = a.out.len[v];
@@ -506,6 +507,36 @@ __global__ __launch_bounds__(BLOCK) void k_epi(SlotArgs a, int k, double scale, 
       a.fstamp[v] = st;
       fe += d;
       fn += 1;
+    }
+  };
+  const int nwv = gridDim.x * (BLOCK / RWR_WAVE);
+  for (int base = (blockIdx.x * (BLOCK / RWR_WAVE) + threadIdx.x / RWR_WAVE) * RWR_WAVE; base < a.n;
+       base += nwv * RWR_WAVE) {
+    const int ul = base + lane;
+    const bool in = ul < a.n;
+    const int32_t fs = in ? a.fstamp[ul] : 0, ts = in ? a.stamp[ul] : 0;
+    const unsigned long long mc = __ballot(in && !first && fs == st - 1);  // the previous frontier
+    const unsigned long long mw = __ballot(in && ts == st);                 // this slot's nodes
+    if constexpr (P <= 8) {
+      // few nodes per step: group g takes the g-th lowest marked node left
+      unsigned long long m = mc | mw;
+      while (m) {
+        unsigned long long mm = m;
+        for (int q = 0; q < g; ++q) mm &= mm - 1;
+#pragma unroll
+        for (int q = 0; q < P; ++q) m &= m - 1;
+        if (!mm) continue;
+        const int bit = __builtin_ctzll(mm);
+        node(base + bit, (mc >> bit) & 1ull, (mw >> bit) & 1ull);
+      }
+    } else {
+      // many: group g takes positions g, g + P, ...
+#pragma unroll
+      for (int c0 = 0; c0 < RWR_WAVE; c0 += P) {
+        const int bit = c0 + g;
+        const bool cl = (mc >> bit) & 1ull, wk = (mw >> bit) & 1ull;
+        if (cl || wk) node(base + bit, cl, wk);
+      }
     }
   }
   block_publish<S>(nrm, sm, fe, fn, a.part, a.part_i, blockIdx.x, sh);
