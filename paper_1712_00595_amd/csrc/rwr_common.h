@@ -16,6 +16,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #define RWR_MAX_COLS 64
@@ -78,6 +79,11 @@ struct Ctl {
   int32_t inj[RWR_MAX_COLS];      // the column's pending carried vector joined this run
   uint64_t dr_fix[RWR_MAX_COLS];  // dr_l1 in fixed point (2^-52 units), summed in deterministic mode
 };
+// the host copies the block whole: host and device compilations must agree
+// on its layout
+static_assert(sizeof(Ctl) == 5800 && offsetof(Ctl, seed_recs) == 152 && offsetof(Ctl, nbig_a) == 412 &&
+                  offsetof(Ctl, dr_fix) == 5288,
+              "control block layout");
 
 // history of per-iteration norms: hist[i * S + j] = ||x^(i)[:, j]||_1
 

@@ -71,6 +71,17 @@ struct SlotArgs {
   int32_t n_mp;            // items of that partition
 };
 
+// The host fills these structures and the kernels read them as by-value
+// arguments: their layout is pinned here, so that the host and the device
+// compilation of every source agree on it (plain pointers and 32/64-bit
+// scalars only).
+static_assert(sizeof(DevGraphView) == 40 && sizeof(HeavyView) == 64, "view layout");
+static_assert(sizeof(SlotArgs) == 352 && offsetof(SlotArgs, r) == 144 && offsetof(SlotArgs, x) == 176 &&
+                  offsetof(SlotArgs, ctl) == 232 && offsetof(SlotArgs, n) == 264 && offsetof(SlotArgs, c) == 272 &&
+                  offsetof(SlotArgs, zero_seed_rows) == 304 && offsetof(SlotArgs, qvec) == 312 &&
+                  offsetof(SlotArgs, n_mp) == 344,
+              "slot argument layout");
+
 #define WV_ROWS 64      // rows per wave item of the wave-granular single-column sweep
 #define WV_EDGES 512    // light in-edges per wave item (one round of the wavefront)
 
@@ -125,6 +136,8 @@ struct OrientPair {
   int32_t big;
   int32_t recs;  // sum the touched rows' old degrees (Ctl::seed_recs) for the sorted offset seed
 };
+static_assert(sizeof(OrientArgs) == 104 && sizeof(OrientPair) == 232 && offsetof(OrientPair, recs) == 228,
+              "batch argument layout");
 void launch_validate_plan(const OrientPair &P, int norient, int b1, Ctl *ctl, int32_t max_rows, hipStream_t st);
 // q_offset of r - rsub (rsub may be null; subtracted in the columns of
 // rmask only) into ybuf (atomically; ybuf null:
